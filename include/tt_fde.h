@@ -1,0 +1,231 @@
+/*
+ * tt_fde.h - C ABI of the MI355X tensor-train solver for the Burgers-Hopf
+ * characteristic-function PDE.
+ *
+ * The method (Rodgers & Venturi, "Tensor approximation of functional
+ * differential equations"):
+ *   - Sec. 3, eq. (hyper1): projecting the Hopf FDE of Burgers' equation
+ *     (Sec. 5, eq. (eqn:BHfde), no reaction term) onto d Fourier modes gives
+ *     the linear PDE
+ *         dphi/dt = sum_k a_k [ (i/2) sum_jl B_kjl d2phi/da_j da_l
+ *                               + nu sum_j D_kj dphi/da_j ].
+ *   - Sec. 4, eq. (tt)/(eqn:ode): phi is held on an n^d tensor-product grid
+ *     (second-order finite differences) as a tensor train.
+ *   - Sec. 4.1, eq. (eqn:discrete-flow-trunc-intro): step-truncation; an
+ *     explicit Runge-Kutta step off the TT manifold followed by truncation.
+ *   - App. A.1: TT format, sum by concatenation, scaling, orthogonalisation
+ *     (Alg. 1, mirrored) and truncation by rounding (Alg. 2, mirrored).
+ *
+ * Conventions shared by every entry point
+ *   - All floating-point data are complex double, stored interleaved
+ *     (re, im) as pairs of doubles.
+ *   - A TT core C_k has shape r_{k-1} x n x r_k and is stored column major
+ *     with the left rank index fastest: C[a, i, b] at a + r_{k-1}(i + n b)
+ *     (the vertical / horizontal flattenings of App. A.1 are then zero-copy).
+ *   - Every call is enqueued asynchronously on the context's HIP stream
+ *     unless stated otherwise.  Device pointers passed in must stay valid
+ *     until the enqueued work completes.
+ *   - Every call returns TT_OK (0) or a negative TT_E* code; no exception
+ *     crosses the ABI.  tt_last_error() gives a text for the last failure on
+ *     that context.  After TT_EHIP the context should be destroyed.
+ *   - Tensors own cap-sized device buffers allocated at creation; no call in
+ *     the stepping path allocates tensor storage.  Contexts own workspaces,
+ *     grown on first use to the largest size a call needs.
+ */
+#ifndef TT_FDE_H
+#define TT_FDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TT_MAX_D 128
+
+enum {
+  TT_OK = 0,
+  TT_EINVAL = -1,      /* invalid argument (null pointer, bad option)         */
+  TT_ESHAPE = -2,      /* d / n / rank mismatch between arguments             */
+  TT_ECAPACITY = -3,   /* a result rank exceeds the output tensor's capacity  */
+  TT_ENOMEM = -4,      /* device or host allocation failed                    */
+  TT_EHIP = -5,        /* a HIP runtime call failed                           */
+  TT_ENOCONV = -6,     /* Jacobi SVD did not converge within its sweep limit  */
+  TT_ENONFINITE = -7   /* a non-finite value was detected                     */
+};
+
+/* Orthogonality state of a tensor (App. A.1 definitions). */
+enum { TT_ORTH_NONE = 0, TT_ORTH_RIGHT = 1, TT_ORTH_LEFT = 2 };
+
+/* Operator application modes. */
+enum {
+  TT_APPLY_EXACT = 0,  /* operator in TT-matrix form times x: ranks multiply   */
+  TT_APPLY_SKETCH = 1  /* fused apply + randomised range compression           */
+};
+
+typedef struct tt_ctx tt_ctx;
+typedef struct tt_tensor tt_tensor;
+typedef struct tt_op tt_op;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  hip_stream is a hipStream_t or
+ * NULL (the context then creates its own default-priority stream). */
+int tt_ctx_create(int device, void* hip_stream, tt_ctx** out);
+int tt_ctx_destroy(tt_ctx* ctx);
+/* Wait for all work enqueued on the context's stream. */
+int tt_ctx_sync(tt_ctx* ctx);
+const char* tt_last_error(const tt_ctx* ctx);
+/* The hipStream_t all work is enqueued on. */
+void* tt_ctx_stream(const tt_ctx* ctx);
+
+/* Per-kernel timing with HIP events on the context stream (off by default).
+ * Named kernel classes: "zgemm", "gather", "cholqr", "jacobi", "apply_exact",
+ * "concat", "eval".  flops / bytes are the algorithmic counts of the launches
+ * recorded (see the design notes); times are summed event durations. */
+int tt_ctx_set_profiling(tt_ctx* ctx, int on);
+int tt_ctx_reset_stats(tt_ctx* ctx);
+int tt_ctx_get_stats(tt_ctx* ctx, const char* kernel, double* total_ms,
+                     double* flops, double* bytes, long long* launches);
+
+/* ---------------------------------------------------------------- tensors */
+
+/* Tensor with d modes of size n and rank capacities rank_cap[0..d]
+ * (rank_cap[0] and rank_cap[d] must be 1).  Cores are allocated at capacity.
+ * Initial ranks are all 1 with zero cores. */
+int tt_tensor_create(tt_ctx* ctx, int d, int n, const int* rank_cap, tt_tensor** out);
+int tt_tensor_destroy(tt_tensor* t);
+/* Copy host cores in (synchronous).  ranks[0..d]; cores[k] points to
+ * 2*ranks[k]*n*ranks[k+1] doubles in the layout above. */
+int tt_tensor_set_cores(tt_tensor* t, const int* ranks, const double* const* cores);
+/* Current ranks (host copy; reflects all completed work - call after
+ * tt_ctx_sync for work still in flight). */
+int tt_tensor_get_ranks(const tt_tensor* t, int* ranks);
+/* Copy cores out to host buffers sized by the current ranks (synchronous). */
+int tt_tensor_get_cores(const tt_tensor* t, double* const* cores);
+int tt_tensor_get_orth(const tt_tensor* t);
+/* dst <- src (same d, n; dst capacities must hold src's ranks). */
+int tt_tensor_copy(tt_ctx* ctx, const tt_tensor* src, tt_tensor* dst);
+/* Rank-one Gaussian characteristic function on the grid a_i = -L + 2Li/(n-1):
+ * phi0(a) = prod_k exp(i mu_k a_k - sigma_k^2 a_k^2 / 2)
+ * (characteristic function of independent N(mu_k, sigma_k^2) amplitudes). */
+int tt_tensor_set_gaussian(tt_ctx* ctx, tt_tensor* t, const double* mu,
+                           const double* sigma, double L);
+
+/* -------------------------------------------------------------- operator */
+
+/* Build the Burgers-Hopf operator for d Fourier modes (mode k = 1..d has
+ * wavenumber ceil(k/2), cosine for odd k, sine for even k) on n grid points
+ * per axis over [-L, L] with viscosity nu.  Finite differences: centred
+ * second order, one-sided second-order boundary rows.  The operator is held
+ * as a TT-matrix (finite-state automaton over the local operators I, X, G,
+ * L2, XG) whose bond dimension is at most 2d + 2.  ctx may be NULL: the
+ * operator is then host-only (usable with the export calls below). */
+int tt_op_create_burgers_hopf(tt_ctx* ctx, int d, int n, double L, double nu, tt_op** out);
+int tt_op_destroy(tt_op* op);
+/* Bond dimensions R[0..d] of the operator's TT-matrix form. */
+int tt_op_get_ranks(const tt_op* op, int* R);
+/* Host-side export for inspection and tests (no device work):
+ *   coefficients: B (d*d*d, index (k*d + j)*d + l) and D (d*d, k*d + j);
+ *   local operators: nops*n*n doubles, op-major, row-major n x n matrices,
+ *     in the order I, X, G, L2, XG, XL2 (returns nops via *nops);
+ *   site entries: for site m (0-based) the transitions
+ *     (alpha, beta, local op, coefficient re/im) of the automaton.
+ *     Call with NULL arrays to query the count. */
+int tt_op_export_coefficients(const tt_op* op, double* B, double* D);
+int tt_op_export_local_ops(const tt_op* op, int* nops, double* mats);
+int tt_op_export_site(const tt_op* op, int site, int* count, int* alpha, int* beta,
+                      int* lop, double* coef);
+
+/* ----------------------------------------------------------- arithmetic */
+
+typedef struct {
+  int size;              /* sizeof(tt_apply_opts) */
+  int mode;              /* TT_APPLY_EXACT or TT_APPLY_SKETCH */
+  int sketch_rank;       /* sketch width l for TT_APPLY_SKETCH (>= 1) */
+  int pad;
+  uint64_t seed;         /* counter-based RNG key for the Gaussian sketch */
+} tt_apply_opts;
+
+/* y <- L x.  EXACT: the TT-matrix product (Sec. 3 operator applied core by
+ * core; ranks R_k r_k; y needs that capacity).  SKETCH: y is the projection
+ * of L x onto a right-orthonormal basis found by a Gaussian TT sketch of
+ * width l (randomised range finder, left sketches then a right-to-left
+ * sweep); ranks <= l; exact whenever l >= the ranks of L x. */
+int tt_apply(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y,
+             const tt_apply_opts* opts);
+
+/* z <- alpha x + beta y by concatenation (App. A.1).  Scalars are complex
+ * (re, im).  z must not alias x or y. */
+int tt_axpy(tt_ctx* ctx, double alpha_re, double alpha_im, const tt_tensor* x,
+            double beta_re, double beta_im, const tt_tensor* y, tt_tensor* z);
+/* z <- sum_t coef[t] x_t (coef: 2*nterms doubles), one concatenation. */
+int tt_sum(tt_ctx* ctx, int nterms, const double* coef, const tt_tensor* const* xs,
+           tt_tensor* z);
+
+typedef struct {
+  int d;
+  int ranks[TT_MAX_D + 1];     /* output ranks */
+  double tail[TT_MAX_D];       /* discarded Frobenius tail per bond */
+  double sigma_min_kept[TT_MAX_D];
+  double norm;                 /* ||x|| before truncation */
+  int jacobi_sweeps_max;
+} tt_round_report;
+
+/* TT rounding (App. A.1, Alg. 2 mirrored): right-to-left orthogonalisation
+ * (skipped when x is already right-orthogonal), then a left-to-right sweep
+ * of truncated SVDs.  Per bond the smallest rank k >= 1 whose discarded tail
+ * is <= eps_rel * ||x|| / sqrt(d - 1) is kept, then k <= rmax (rmax <= 0:
+ * no cap) and k <= the capacity of x.  Output cores 1..d-1 are
+ * left-orthonormal.  rep may be NULL; when given it is filled on return
+ * (the call then synchronises). */
+int tt_round(tt_ctx* ctx, tt_tensor* x, double eps_rel, int rmax, tt_round_report* rep);
+
+typedef struct {
+  int size;              /* sizeof(tt_step_opts) */
+  int rmax;              /* rank cap of every truncation */
+  double eps;            /* relative tolerance of every truncation */
+  int apply_mode;        /* TT_APPLY_EXACT or TT_APPLY_SKETCH */
+  int sketch_rank;
+  uint64_t seed;
+} tt_step_opts;
+
+typedef struct {
+  int stages;
+  int max_rank;          /* largest rank of any truncated tensor in the step */
+  int ranks[TT_MAX_D + 1];
+} tt_step_report;
+
+/* One classical RK4 step-truncation step of df/dt = L f, in place:
+ *   k1 = T[L f],  y2 = T[f + dt/2 k1],  k2 = T[L y2],  y3 = T[f + dt/2 k2],
+ *   k3 = T[L y3], y4 = T[f + dt k3],    k4 = T[L y4],
+ *   f <- T[f + dt/6 (k1 + 2 k2 + 2 k3 + k4)]
+ * with T = tt_round(eps, rmax).  Each of the four stages is one operator
+ * application, its truncation, one combination and its truncation
+ * (the last stage's combination is the final one). */
+int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt,
+            const tt_step_opts* opts, tt_step_report* rep);
+
+/* out[p] = x[idx[p, 0], ..., idx[p, d-1]] (iterated matrix product,
+ * App. A.1).  idx: device int32 array npts x d (row p contiguous);
+ * out: device array of npts complex values. */
+int tt_eval(tt_ctx* ctx, const tt_tensor* x, const int32_t* idx, int64_t npts, double* out);
+
+/* Building block exposed for testing and benchmarking: complex double GEMM
+ * on the context stream, C = alpha op(A) op(B) + beta C, column major, with
+ * op 0 = none, 1 = transpose, 2 = conjugate transpose, and `batch` strided
+ * batches.  A, B, C are device pointers to interleaved complex doubles;
+ * leading dimensions and strides count complex elements. */
+int tt_zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, double alpha_re, double alpha_im,
+             const double* A, int64_t lda, int64_t strideA, const double* B, int64_t ldb,
+             int64_t strideB, double beta_re, double beta_im, double* C, int64_t ldc,
+             int64_t strideC, int batch);
+
+/* Frobenius norm of x (synchronous; computed by orthogonalisation). */
+int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TT_FDE_H */

@@ -1,0 +1,1028 @@
+// C ABI and host orchestration: tensors, operator upload, TT rounding
+// sweeps, exact and sketched operator application, RK4 step-truncation.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <tuple>
+
+#include "common.hpp"
+
+namespace ttf {
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(TT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+KTimer::KTimer(tt_ctx* c, const char* nm, double fl, double by) : ctx(c), name(nm), flops(fl), bytes(by) {
+  if (!ctx || !ctx->profiling) return;
+  auto take = [&]() {
+    hipEvent_t e;
+    if (!ctx->free_events.empty()) {
+      e = ctx->free_events.back();
+      ctx->free_events.pop_back();
+    } else {
+      TTF_HIP(hipEventCreate(&e));
+    }
+    return e;
+  };
+  a = take();
+  b = take();
+  TTF_HIP(hipEventRecord(a, ctx->stream));
+}
+
+KTimer::~KTimer() {
+  if (!a) return;
+  (void)hipEventRecord(b, ctx->stream);
+  ctx->pending.push_back({name, a, b, flops, bytes});
+}
+
+}  // namespace ttf
+
+using namespace ttf;
+
+void* tt_ctx::get_ws(const std::string& name, size_t bytes) {
+  Buf& b = ws[name];
+  if (b.bytes >= bytes && b.p) return b.p;
+  if (b.p) {
+    TTF_HIP(hipStreamSynchronize(stream));
+    TTF_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  const size_t want = std::max<size_t>(bytes + bytes / 8, 4096);
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    fail(TT_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed (" + name + ")");
+  }
+  b.bytes = want;
+  return b.p;
+}
+
+void* tt_ctx::host_scratch(size_t bytes) {
+  if (pinned_bytes >= bytes) return pinned;
+  if (pinned) {
+    TTF_HIP(hipStreamSynchronize(stream));
+    TTF_HIP(hipHostFree(pinned));
+    pinned = nullptr;
+    pinned_bytes = 0;
+  }
+  const size_t want = std::max<size_t>(bytes, 1 << 16);
+  TTF_HIP(hipHostMalloc(&pinned, want, hipHostMallocDefault));
+  pinned_bytes = want;
+  return pinned;
+}
+
+void tt_ctx::resolve_stats() {
+  for (auto& p : pending) {
+    float ms = 0;
+    TTF_HIP(hipEventSynchronize(p.b));
+    TTF_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    Stat& s = stats[p.name];
+    s.ms += ms;
+    s.flops += p.flops;
+    s.bytes += p.bytes;
+    s.n += 1;
+    free_events.push_back(p.a);
+    free_events.push_back(p.b);
+  }
+  pending.clear();
+}
+
+void tt_ctx::sync() {
+  TTF_HIP(hipStreamSynchronize(stream));
+  resolve_stats();
+}
+
+namespace {
+
+#define ABI_TRY try {
+#define ABI_CATCH(ctxp)                                   \
+  }                                                       \
+  catch (const ttf::Error& e) {                           \
+    if (ctxp) (ctxp)->last_error = e.msg;                 \
+    return e.code;                                        \
+  }                                                       \
+  catch (const std::bad_alloc&) {                         \
+    if (ctxp) (ctxp)->last_error = "host allocation failed"; \
+    return TT_ENOMEM;                                     \
+  }                                                       \
+  catch (const std::exception& e) {                       \
+    if (ctxp) (ctxp)->last_error = e.what();              \
+    return TT_EINVAL;                                     \
+  }                                                       \
+  catch (...) {                                           \
+    if (ctxp) (ctxp)->last_error = "unknown error";       \
+    return TT_EINVAL;                                     \
+  }
+
+inline zc Z(double re, double im = 0.0) { return make_double2(re, im); }
+constexpr double U_ROUND = 1.1102230246251565e-16;  // 2^-53
+
+void require(bool c, int code, const char* msg) {
+  if (!c) fail(code, msg);
+}
+
+void copy_d2d(tt_ctx* ctx, zc* dst, const zc* src, size_t elems) {
+  if (elems == 0 || dst == src) return;
+  TTF_HIP(hipMemcpyAsync(dst, src, elems * sizeof(zc), hipMemcpyDeviceToDevice, ctx->stream));
+}
+
+// ------------------------------------------------ shifted CholeskyQR3
+// QR form.  The logical input is A (m x k) stored at `a` with leading
+// dimension lda, or, when `ct` is set, A = S^H for S (k x m) stored at `a`.
+// On exit q (m x k, ld m) has orthonormal columns (up to null directions of
+// A, which come out with negligible weight) and r (k x k, ld k) is upper
+// triangular with A = q r.
+void cholqr3(tt_ctx* ctx, int m, int k, const zc* a, long lda, bool ct, zc* q, zc* r) {
+  zc* G = (zc*)ctx->get_ws("cq_g", sizeof(zc) * k * k);
+  zc* Rp = (zc*)ctx->get_ws("cq_r", sizeof(zc) * k * k);
+  zc* Ri = (zc*)ctx->get_ws("cq_ri", sizeof(zc) * k * k);
+  zc* Rt = (zc*)ctx->get_ws("cq_rt", sizeof(zc) * k * k);
+  zc* Qt = (zc*)ctx->get_ws("cq_qt", sizeof(zc) * (size_t)m * k);
+  const double s1 = 11.0 * ((double)m * k + (double)k * (k + 1)) * U_ROUND;
+  const double fl = (double)k * U_ROUND;
+  // pass 1 on the input
+  if (!ct)
+    zgemm(ctx, OPC, OPN, k, k, m, Z(1), a, lda, 0, a, lda, 0, Z(0), G, k, 0);
+  else  // A^H A = S S^H
+    zgemm(ctx, OPN, OPC, k, k, m, Z(1), a, lda, 0, a, lda, 0, Z(0), G, k, 0);
+  chol_inv(ctx, k, G, r, Ri, s1, 0.0);
+  // Q1 = A R^{-1}; pass 1 writes Qt when three passes follow so the last
+  // pass lands in q
+  if (!ct)
+    zgemm(ctx, OPN, OPN, m, k, k, Z(1), a, lda, 0, Ri, k, 0, Z(0), Qt, m, 0);
+  else
+    zgemm(ctx, OPC, OPN, m, k, k, Z(1), a, lda, 0, Ri, k, 0, Z(0), Qt, m, 0);
+  const zc* src = Qt;
+  for (int pass = 2; pass <= 3; ++pass) {
+    zc* dst = (pass == 2) ? q : Qt;  // pass 2 writes q, pass 3 writes Qt
+    zgemm(ctx, OPC, OPN, k, k, m, Z(1), src, m, 0, src, m, 0, Z(0), G, k, 0);
+    chol_inv(ctx, k, G, Rp, Ri, 0.0, fl);
+    zgemm(ctx, OPN, OPN, m, k, k, Z(1), src, m, 0, Ri, k, 0, Z(0), dst, m, 0);
+    // r <- Rp r
+    zgemm(ctx, OPN, OPN, k, k, k, Z(1), Rp, k, 0, r, k, 0, Z(0), Rt, k, 0);
+    copy_d2d(ctx, r, Rt, (size_t)k * k);
+    src = dst;
+  }
+  copy_d2d(ctx, q, Qt, (size_t)m * k);
+}
+
+// LQ form: A (k x m, ld lda) = L Q with Q (k x m, ld k) row-orthonormal and
+// returned R (k x k upper) such that L = R^H.
+void cholqr3_lq(tt_ctx* ctx, int k, int m, const zc* a, long lda, zc* q, zc* r) {
+  // A^H = Q' R  =>  A = R^H Q'^H ; run the QR form on S = A via ct
+  zc* qt = (zc*)ctx->get_ws("lq_qt", sizeof(zc) * (size_t)m * k);
+  cholqr3(ctx, m, k, a, lda, true, qt, r);
+  // q = qt^H (k x m): conjugate transpose via GEMM with the identity
+  zc* I = (zc*)ctx->get_ws("lq_eye", sizeof(zc) * (size_t)k * k);
+  set_identity(ctx, I, k, k, k);
+  zgemm(ctx, OPN, OPC, k, m, k, Z(1), I, k, 0, qt, m, 0, Z(0), q, k, 0);
+}
+
+int bounded_pow(int n, int e, int cap) {
+  long v = 1;
+  for (int i = 0; i < e && v < cap; ++i) v *= n;
+  return (int)std::min<long>(v, cap);
+}
+
+// ------------------------------------------------------- TT rounding
+void phase1_right_orth(tt_ctx* ctx, tt_tensor* x) {
+  const int d = x->d, n = x->n;
+  auto& r = x->rank;
+  for (int c = d - 1; c >= 1; --c) {
+    const int p0 = r[c], p1 = r[c + 1];
+    const int N = n * p1;
+    const int rl = r[c - 1];
+    zc* tmp = (zc*)ctx->get_ws("ph1_tmp", sizeof(zc) * (size_t)rl * n * std::max(p0, N));
+    if (p0 > N) {
+      // H(C_c) is taller than wide: C_c <- I, C_{c-1} <- C_{c-1} H(C_c)
+      zgemm(ctx, OPN, OPN, rl * n, N, p0, Z(1), x->core[c - 1], (long)rl * n, 0, x->core[c], p0, 0, Z(0), tmp,
+            (long)rl * n, 0);
+      copy_d2d(ctx, x->core[c - 1], tmp, (size_t)rl * n * N);
+      identity_core(ctx, x->core[c], n, p1);
+      r[c] = N;
+    } else {
+      zc* q = (zc*)ctx->get_ws("ph1_q", sizeof(zc) * (size_t)p0 * N);
+      zc* R = (zc*)ctx->get_ws("ph1_r", sizeof(zc) * (size_t)p0 * p0);
+      cholqr3_lq(ctx, p0, N, x->core[c], p0, q, R);
+      copy_d2d(ctx, x->core[c], q, (size_t)p0 * N);
+      // C_{c-1} <- C_{c-1} L, L = R^H
+      zgemm(ctx, OPN, OPC, rl * n, p0, p0, Z(1), x->core[c - 1], (long)rl * n, 0, R, p0, 0, Z(0), tmp,
+            (long)rl * n, 0);
+      copy_d2d(ctx, x->core[c - 1], tmp, (size_t)rl * n * p0);
+    }
+  }
+  x->orth = TT_ORTH_RIGHT;
+}
+
+double core_norm(tt_ctx* ctx, const tt_tensor* x, int k) {
+  double* dv = (double*)ctx->get_ws("norm_out", 64);
+  frob_norm2(ctx, x->core[k], (long)x->elems(k), dv);
+  double* h = (double*)ctx->host_scratch(64);
+  TTF_HIP(hipMemcpyAsync(h, dv, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  TTF_HIP(hipStreamSynchronize(ctx->stream));
+  return std::sqrt(std::max(0.0, h[0]));
+}
+
+int truncation_rank(const std::vector<double>& s, double delta, int cap, double* tail_out) {
+  const int k = (int)s.size();
+  std::vector<double> tail(k + 1, 0.0);
+  for (int i = k - 1; i >= 0; --i) tail[i] = tail[i + 1] + s[i] * s[i];
+  int kk = k;
+  for (int j = 1; j <= k; ++j)
+    if (std::sqrt(tail[j]) <= delta) {
+      kk = j;
+      break;
+    }
+  if (cap > 0) kk = std::min(kk, cap);
+  kk = std::max(kk, 1);
+  if (tail_out) *tail_out = std::sqrt(tail[kk]);
+  return kk;
+}
+
+void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_report* rep) {
+  const int d = x->d, n = x->n;
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->d = d;
+  }
+  if (d == 1) {
+    if (rep) {
+      rep->ranks[0] = rep->ranks[1] = 1;
+      rep->norm = core_norm(ctx, x, 0);
+    }
+    return;
+  }
+  if (x->orth != TT_ORTH_RIGHT) phase1_right_orth(ctx, x);
+  auto& r = x->rank;
+  const double norm = core_norm(ctx, x, 0);
+  const double delta = eps * norm / std::sqrt((double)(d - 1));
+  int sweeps_max = 0;
+  for (int c = 0; c < d - 1; ++c) {
+    const int m = r[c] * n, k = r[c + 1];
+    const int rr = r[c + 2];
+    const int sq = std::min(m, k);  // size of the square factor
+    zc* Q = (zc*)ctx->get_ws("p2_q", sizeof(zc) * (size_t)m * k);
+    zc* R = (zc*)ctx->get_ws("p2_r", sizeof(zc) * (size_t)sq * sq);
+    zc* B = (zc*)ctx->get_ws("p2_b", sizeof(zc) * (size_t)sq * sq);
+    zc* U = (zc*)ctx->get_ws("p2_u", sizeof(zc) * (size_t)sq * sq);
+    double* sig = (double*)ctx->get_ws("p2_sig", sizeof(double) * (sq + 8));
+    int* sw = (int*)(sig + sq + 2);
+    zc* carry = (zc*)ctx->get_ws("p2_carry", sizeof(zc) * (size_t)sq * k);
+    zc* tmp = (zc*)ctx->get_ws("p2_tmp", sizeof(zc) * (size_t)sq * n * rr);
+    const zc* V = x->core[c];
+    if (m >= k) {
+      cholqr3(ctx, m, k, V, m, false, Q, R);
+      copy_d2d(ctx, B, R, (size_t)k * k);
+    } else {
+      // V^H (k x m) = Q' R' ; SVD of R'^H gives the left vectors of V
+      cholqr3(ctx, k, m, V, m, true, Q, R);
+      zc* I = (zc*)ctx->get_ws("p2_eye", sizeof(zc) * (size_t)m * m);
+      set_identity(ctx, I, m, m, m);
+      zgemm(ctx, OPN, OPC, m, m, m, Z(1), I, m, 0, R, m, 0, Z(0), B, m, 0);  // B = R'^H
+    }
+    jacobi_svd(ctx, sq, sq, B, U, sig, sw);
+    double* h = (double*)ctx->host_scratch(sizeof(double) * (sq + 8));
+    TTF_HIP(hipMemcpyAsync(h, sig, sizeof(double) * (sq + 8), hipMemcpyDeviceToHost, ctx->stream));
+    TTF_HIP(hipStreamSynchronize(ctx->stream));
+    std::vector<double> s(h, h + sq);
+    for (double v : s)
+      if (!std::isfinite(v)) fail(TT_ENONFINITE, "non-finite singular value in tt_round");
+    int swp = 0;
+    std::memcpy(&swp, (char*)(h + sq + 2), sizeof(int));
+    sweeps_max = std::max(sweeps_max, swp);
+    int capk = x->cap[c + 1];
+    if (rmax > 0) capk = std::min(capk, rmax);
+    double tail = 0;
+    const int kk = truncation_rank(s, delta, capk, &tail);
+    if (m >= k) {
+      // C_c <- Q U_k ; carry = U_k^H R
+      zgemm(ctx, OPN, OPN, m, kk, k, Z(1), Q, m, 0, U, k, 0, Z(0), x->core[c], m, 0);
+      zgemm(ctx, OPC, OPN, kk, k, k, Z(1), U, k, 0, R, k, 0, Z(0), carry, kk, 0);
+    } else {
+      // C_c <- U_k ; carry = U_k^H V
+      zgemm(ctx, OPC, OPN, kk, k, m, Z(1), U, m, 0, V, m, 0, Z(0), carry, kk, 0);
+      copy_d2d(ctx, x->core[c], U, (size_t)m * kk);
+    }
+    // C_{c+1} <- carry H(C_{c+1})
+    zgemm(ctx, OPN, OPN, kk, n * rr, k, Z(1), carry, kk, 0, x->core[c + 1], k, 0, Z(0), tmp, kk, 0);
+    copy_d2d(ctx, x->core[c + 1], tmp, (size_t)kk * n * rr);
+    r[c + 1] = kk;
+    if (rep) {
+      rep->tail[c] = tail;
+      rep->sigma_min_kept[c] = s[kk - 1];
+    }
+  }
+  x->orth = TT_ORTH_LEFT;
+  if (rep) {
+    for (int c = 0; c <= d; ++c) rep->ranks[c] = r[c];
+    rep->norm = norm;
+    rep->jacobi_sweeps_max = sweeps_max;
+  }
+}
+
+// --------------------------------------------------------- operator apply
+void check_same_shape(const tt_op* op, const tt_tensor* x) {
+  require(op->d == x->d && op->n == x->n, TT_ESHAPE, "operator and tensor shapes differ");
+}
+
+void apply_exact(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y) {
+  const int d = x->d;
+  for (int k = 0; k <= d; ++k)
+    require((long)op->R[k] * x->rank[k] <= y->cap[k], TT_ECAPACITY, "tt_apply: output capacity too small");
+  for (int k = 0; k < d; ++k) apply_exact_core(ctx, op, k, x->core[k], x->rank[k], x->rank[k + 1], y->core[k]);
+  for (int k = 0; k <= d; ++k) y->rank[k] = op->R[k] * x->rank[k];
+  y->orth = TT_ORTH_NONE;
+}
+
+void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int l, uint64_t seed) {
+  const int d = x->d, n = x->n;
+  const auto& r = x->rank;
+  const auto& R = op->R;
+  require(l >= 1, TT_EINVAL, "tt_apply: sketch rank must be >= 1");
+  std::vector<int> ll(d + 1);
+  for (int m = 0; m <= d; ++m) ll[m] = std::min(bounded_pow(n, m, l), bounded_pow(n, d - m, l));
+  for (int m = 0; m <= d; ++m) require(ll[m] <= y->cap[m], TT_ECAPACITY, "tt_apply: output capacity below sketch rank");
+  if (d == 1) {
+    apply_exact_core(ctx, op, 0, x->core[0], 1, 1, y->core[0]);
+    y->rank[0] = y->rank[1] = 1;
+    y->orth = TT_ORTH_NONE;
+    return;
+  }
+  // workspace sizes
+  size_t big0 = 0, big1 = 0, sk_total = 0, om = 0;
+  std::vector<size_t> sk_off(d + 1, 0);
+  for (int m = 0; m < d; ++m) {
+    big0 = std::max(big0, (size_t)ll[m] * R[m] * n * r[m + 1]);          // V
+    big1 = std::max(big1, (size_t)ll[m] * n * r[m + 1] * R[m + 1]);      // W
+    big0 = std::max(big0, (size_t)r[m] * n * R[m + 1] * ll[m + 1]);      // V2
+    big1 = std::max(big1, (size_t)r[m] * R[m] * n * ll[m + 1]);          // Z
+    om = std::max(om, (size_t)ll[m] * n * ll[m + 1]);
+  }
+  for (int m = 0; m <= d; ++m) {
+    sk_off[m] = sk_total;
+    sk_total += (size_t)ll[m] * r[m] * R[m];
+  }
+  zc* V = (zc*)ctx->get_ws("sk_big0", sizeof(zc) * big0);
+  zc* W = (zc*)ctx->get_ws("sk_big1", sizeof(zc) * big1);
+  zc* S = (zc*)ctx->get_ws("sk_S", sizeof(zc) * sk_total);
+  zc* omega = (zc*)ctx->get_ws("sk_omega", sizeof(zc) * om);
+  size_t pmax = 0, mmax = 0;
+  for (int m = 0; m <= d; ++m) pmax = std::max(pmax, (size_t)r[m] * R[m] * ll[m]);
+  for (int m = 1; m < d; ++m) mmax = std::max(mmax, (size_t)ll[m] * n * ll[m + 1]);
+  zc* P = (zc*)ctx->get_ws("sk_P", sizeof(zc) * pmax);
+  zc* P2 = (zc*)ctx->get_ws("sk_P2", sizeof(zc) * pmax);
+  zc* M = (zc*)ctx->get_ws("sk_M", sizeof(zc) * std::max<size_t>(mmax, 1));
+  zc* Qm = (zc*)ctx->get_ws("sk_Q", sizeof(zc) * std::max<size_t>(mmax, 1));
+  zc* Rm = (zc*)ctx->get_ws("sk_R", sizeof(zc) * (size_t)l * l);
+  // S_0 = 1
+  {
+    const zc one = Z(1);
+    TTF_HIP(hipMemcpyAsync(S + sk_off[0], &one, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
+  }
+  // ---- left sketches S_{m+1} = omega_m^T (Y_m contracted with S_m)
+  for (int m = 0; m + 1 < d; ++m) {
+    const int lm = ll[m], lp = ll[m + 1], r0 = r[m], r1 = r[m + 1], R0 = R[m], R1 = R[m + 1];
+    const zc* Sm = S + sk_off[m];
+    // V[j, alpha, i', b] = sum_a S_m[j, a, alpha] C_m[a, i', b]  (batched over alpha)
+    zgemm(ctx, OPN, OPN, lm, n * r1, r0, Z(1), Sm, lm, (long)lm * r0, x->core[m], r0, 0, Z(0), V, (long)lm * R0,
+          lm, R0);
+    gather_left(ctx, op, m, V, W, lm, r1);
+    sketch_core(ctx, omega, (long)lm * n * lp, seed, m, 1.0 / std::sqrt((double)lp));
+    zgemm(ctx, OPT, OPN, lp, r1 * R1, lm * n, Z(1), omega, (long)lm * n, 0, W, (long)lm * n, 0, Z(0),
+          S + sk_off[m + 1], lp, 0);
+  }
+  // ---- right-to-left compression
+  std::vector<int> s(d + 1, 1);
+  // P_d = 1 (r_d = R_d = s_d = 1)
+  {
+    const zc one = Z(1);
+    TTF_HIP(hipMemcpyAsync(P, &one, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
+  }
+  for (int m = d - 1; m >= 0; --m) {
+    const int r0 = r[m], r1 = r[m + 1], R0 = R[m], R1 = R[m + 1], sp = s[m + 1];
+    // V2[a, i', beta, q] = V(C_m) P_{m+1}
+    zgemm(ctx, OPN, OPN, r0 * n, R1 * sp, r1, Z(1), x->core[m], (long)r0 * n, 0, P, r1, 0, Z(0), V,
+          (long)r0 * n, 0);
+    if (m == 0) {
+      gather_right(ctx, op, 0, V, y->core[0], 1, sp);
+      break;
+    }
+    gather_right(ctx, op, m, V, W, r0, sp);  // Z in W
+    const int lm = ll[m];
+    const int N = n * sp;
+    // M = S_m Z  (l_m x n s_{m+1})
+    zgemm(ctx, OPN, OPN, lm, N, r0 * R0, Z(1), S + sk_off[m], lm, 0, W, (long)r0 * R0, 0, Z(0), M, lm, 0);
+    cholqr3_lq(ctx, lm, N, M, lm, Qm, Rm);
+    copy_d2d(ctx, y->core[m], Qm, (size_t)lm * N);
+    s[m] = lm;
+    // P_m = Z Q^H  ((r0 R0) x l_m), layout [a, alpha, q]
+    zgemm(ctx, OPN, OPC, r0 * R0, lm, N, Z(1), W, (long)r0 * R0, 0, Qm, lm, 0, Z(0), P2, (long)r0 * R0, 0);
+    std::swap(P, P2);
+  }
+  for (int m = 0; m <= d; ++m) y->rank[m] = s[m];
+  y->rank[0] = 1;
+  y->orth = TT_ORTH_RIGHT;
+}
+
+void apply_any(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int mode, int l, uint64_t seed) {
+  check_same_shape(op, x);
+  require(x->d == y->d && x->n == y->n, TT_ESHAPE, "tt_apply: x and y shapes differ");
+  require(x != y, TT_EINVAL, "tt_apply: y must not alias x");
+  require(op->ctx == ctx, TT_EINVAL, "tt_apply: operator was created on another context");
+  if (mode == TT_APPLY_EXACT)
+    apply_exact(ctx, op, x, y);
+  else if (mode == TT_APPLY_SKETCH)
+    apply_sketch(ctx, op, x, y, l, seed);
+  else
+    fail(TT_EINVAL, "tt_apply: unknown mode");
+}
+
+// ------------------------------------------------------------------ sums
+void sum_tensors(tt_ctx* ctx, int nterms, const zc* coef, const tt_tensor* const* xs, tt_tensor* z) {
+  require(nterms >= 1 && nterms <= 8, TT_EINVAL, "tt_sum: 1..8 terms supported");
+  const int d = z->d, n = z->n;
+  std::vector<int> rk(d + 1, 0);
+  for (int t = 0; t < nterms; ++t) {
+    require(xs[t] && xs[t]->d == d && xs[t]->n == n, TT_ESHAPE, "tt_sum: shape mismatch");
+    require(xs[t] != z, TT_EINVAL, "tt_sum: output aliases an input");
+  }
+  rk[0] = rk[d] = 1;
+  for (int k = 1; k < d; ++k) {
+    for (int t = 0; t < nterms; ++t) rk[k] += xs[t]->rank[k];
+    require(rk[k] <= z->cap[k], TT_ECAPACITY, "tt_sum: output capacity too small");
+  }
+  std::vector<const zc*> src(nterms);
+  std::vector<int> r0s(nterms), r1s(nterms);
+  for (int k = 0; k < d; ++k) {
+    for (int t = 0; t < nterms; ++t) {
+      src[t] = xs[t]->core[k];
+      r0s[t] = xs[t]->rank[k];
+      r1s[t] = xs[t]->rank[k + 1];
+    }
+    const int kind = (d == 1) ? 3 : (k == 0 ? 0 : (k == d - 1 ? 2 : 1));
+    concat_core(ctx, nterms, src.data(), r0s.data(), r1s.data(), coef, kind, n, z->core[k], rk[k], rk[k + 1]);
+  }
+  z->rank = rk;
+  z->orth = TT_ORTH_NONE;
+}
+
+tt_tensor* make_tensor(tt_ctx* ctx, int d, int n, const std::vector<int>& cap) {
+  require(d >= 1 && d <= TT_MAX_D, TT_EINVAL, "tensor dimension must be in 1..128");
+  require(n >= 4, TT_EINVAL, "mode size must be at least 4");
+  require((int)cap.size() == d + 1 && cap[0] == 1 && cap[d] == 1, TT_EINVAL, "rank capacities must start and end with 1");
+  for (int c : cap) require(c >= 1, TT_EINVAL, "rank capacities must be positive");
+  tt_tensor* t = new tt_tensor;
+  t->ctx = ctx;
+  t->d = d;
+  t->n = n;
+  t->cap = cap;
+  t->rank.assign(d + 1, 1);
+  t->core.assign(d, nullptr);
+  for (int k = 0; k < d; ++k) {
+    const size_t bytes = sizeof(zc) * t->cap_elems(k);
+    if (hipMalloc(&t->core[k], bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      for (int j = 0; j < k; ++j) (void)hipFree(t->core[j]);
+      delete t;
+      fail(TT_ENOMEM, "tensor core allocation failed");
+    }
+    TTF_HIP(hipMemsetAsync(t->core[k], 0, bytes, ctx->stream));
+  }
+  return t;
+}
+
+void free_tensor(tt_tensor* t) {
+  if (!t) return;
+  for (auto p : t->core)
+    if (p) (void)hipFree(p);
+  delete t;
+}
+
+void copy_tensor(tt_ctx* ctx, const tt_tensor* src, tt_tensor* dst) {
+  require(src->d == dst->d && src->n == dst->n, TT_ESHAPE, "tt_tensor_copy: shape mismatch");
+  for (int k = 0; k <= src->d; ++k) require(src->rank[k] <= dst->cap[k], TT_ECAPACITY, "tt_tensor_copy: capacity too small");
+  if (src == dst) return;
+  for (int k = 0; k < src->d; ++k) copy_d2d(ctx, dst->core[k], src->core[k], src->elems(k));
+  dst->rank = src->rank;
+  dst->orth = src->orth;
+}
+
+// temporaries used by tt_step / tt_norm, cached per context and shape
+struct StepTemps {
+  tt_tensor* k[4] = {nullptr, nullptr, nullptr, nullptr};
+  tt_tensor* ysum = nullptr;
+  tt_tensor* y = nullptr;
+  tt_tensor* fsum = nullptr;
+};
+std::map<std::pair<tt_ctx*, std::string>, StepTemps>& step_cache() {
+  static std::map<std::pair<tt_ctx*, std::string>, StepTemps> c;
+  return c;
+}
+std::map<std::pair<tt_ctx*, std::string>, tt_tensor*>& norm_cache() {
+  static std::map<std::pair<tt_ctx*, std::string>, tt_tensor*> c;
+  return c;
+}
+
+std::string shape_key(int d, int n, const std::vector<int>& cap, int extra) {
+  std::string s = std::to_string(d) + ":" + std::to_string(n) + ":" + std::to_string(extra);
+  for (int c : cap) s += "," + std::to_string(c);
+  return s;
+}
+
+void drop_ctx_caches(tt_ctx* ctx) {
+  auto& sc = step_cache();
+  for (auto it = sc.begin(); it != sc.end();) {
+    if (it->first.first == ctx) {
+      for (auto* t : it->second.k) free_tensor(t);
+      free_tensor(it->second.ysum);
+      free_tensor(it->second.y);
+      free_tensor(it->second.fsum);
+      it = sc.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  auto& nc = norm_cache();
+  for (auto it = nc.begin(); it != nc.end();) {
+    if (it->first.first == ctx) {
+      free_tensor(it->second);
+      it = nc.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+void upload_op(tt_ctx* ctx, tt_op* op) {
+  const int d = op->d, n = op->n;
+  op->ctx = ctx;
+  TTF_HIP(hipMalloc(&op->d_tap_col, sizeof(int) * op->tap_col.size()));
+  TTF_HIP(hipMalloc(&op->d_tap_w, sizeof(double) * op->tap_w.size()));
+  TTF_HIP(hipMemcpy(op->d_tap_col, op->tap_col.data(), sizeof(int) * op->tap_col.size(), hipMemcpyHostToDevice));
+  TTF_HIP(hipMemcpy(op->d_tap_w, op->tap_w.data(), sizeof(double) * op->tap_w.size(), hipMemcpyHostToDevice));
+  (void)n;
+  op->dev.assign(d, {});
+  for (int s = 0; s < d; ++s) {
+    const auto& ent = op->site[s];
+    const int R0 = op->R[s], R1 = op->R[s + 1];
+    // CSR by beta (incoming) and by alpha (outgoing)
+    std::vector<int> inp(R1 + 1, 0), outp(R0 + 1, 0);
+    for (const Entry& e : ent) {
+      inp[e.beta + 1]++;
+      outp[e.alpha + 1]++;
+    }
+    for (int i = 0; i < R1; ++i) inp[i + 1] += inp[i];
+    for (int i = 0; i < R0; ++i) outp[i + 1] += outp[i];
+    std::vector<DevEntry> ine(ent.size()), oute(ent.size());
+    std::vector<int> fi(inp.begin(), inp.end() - 1), fo(outp.begin(), outp.end() - 1);
+    for (const Entry& e : ent) {
+      ine[fi[e.beta]++] = DevEntry{e.alpha, e.lop, e.cre, e.cim};
+      oute[fo[e.alpha]++] = DevEntry{e.beta, e.lop, e.cre, e.cim};
+    }
+    // exact-apply blocks
+    std::map<std::pair<int, int>, std::vector<DevBlockOp>> blk;
+    for (const Entry& e : ent) blk[{e.alpha, e.beta}].push_back(DevBlockOp{e.lop, 0, e.cre, e.cim});
+    std::vector<DevBlock> blocks;
+    std::vector<DevBlockOp> bops;
+    for (auto& kv : blk) {
+      blocks.push_back(DevBlock{kv.first.first, kv.first.second, (int)bops.size(), (int)kv.second.size()});
+      for (auto& b : kv.second) bops.push_back(b);
+    }
+    auto& sd = op->dev[s];
+    sd.nblocks = (int)blocks.size();
+    auto up = [&](void** dst, const void* src, size_t bytes) {
+      TTF_HIP(hipMalloc(dst, std::max<size_t>(bytes, 16)));
+      if (bytes) TTF_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    };
+    up((void**)&sd.in_ptr, inp.data(), sizeof(int) * inp.size());
+    up((void**)&sd.out_ptr, outp.data(), sizeof(int) * outp.size());
+    up((void**)&sd.in_ent, ine.data(), sizeof(DevEntry) * ine.size());
+    up((void**)&sd.out_ent, oute.data(), sizeof(DevEntry) * oute.size());
+    up((void**)&sd.blocks, blocks.data(), sizeof(DevBlock) * blocks.size());
+    up((void**)&sd.bops, bops.data(), sizeof(DevBlockOp) * bops.size());
+  }
+}
+
+void free_op(tt_op* op) {
+  if (!op) return;
+  if (op->ctx) {
+    (void)hipFree(op->d_tap_col);
+    (void)hipFree(op->d_tap_w);
+    for (auto& sd : op->dev) {
+      (void)hipFree(sd.in_ptr);
+      (void)hipFree(sd.out_ptr);
+      (void)hipFree(sd.in_ent);
+      (void)hipFree(sd.out_ent);
+      (void)hipFree(sd.blocks);
+      (void)hipFree(sd.bops);
+    }
+  }
+  delete op;
+}
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+int tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
+  tt_ctx* ctx = nullptr;
+  ABI_TRY
+  require(out != nullptr, TT_EINVAL, "tt_ctx_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  TTF_HIP(hipGetDeviceCount(&ndev));
+  require(device >= 0 && device < ndev, TT_EINVAL, "tt_ctx_create: no such device");
+  TTF_HIP(hipSetDevice(device));
+  ctx = new tt_ctx;
+  ctx->device = device;
+  if (hip_stream) {
+    ctx->stream = (hipStream_t)hip_stream;
+  } else {
+    TTF_HIP(hipStreamCreate(&ctx->stream));
+    ctx->own_stream = true;
+  }
+  *out = ctx;
+  return TT_OK;
+  }
+  catch (const ttf::Error& e) {
+    delete ctx;
+    return e.code;
+  }
+  catch (...) {
+    delete ctx;
+    return TT_EINVAL;
+  }
+}
+
+int tt_ctx_destroy(tt_ctx* ctx) {
+  if (!ctx) return TT_EINVAL;
+  (void)hipStreamSynchronize(ctx->stream);
+  drop_ctx_caches(ctx);
+  for (auto& kv : ctx->ws)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  for (auto& p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : ctx->free_events) (void)hipEventDestroy(e);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return TT_OK;
+}
+
+int tt_ctx_sync(tt_ctx* ctx) {
+  if (!ctx) return TT_EINVAL;
+  ABI_TRY
+  ctx->sync();
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+const char* tt_last_error(const tt_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+void* tt_ctx_stream(const tt_ctx* ctx) { return ctx ? (void*)ctx->stream : nullptr; }
+
+int tt_ctx_set_profiling(tt_ctx* ctx, int on) {
+  if (!ctx) return TT_EINVAL;
+  ABI_TRY
+  ctx->sync();
+  ctx->profiling = on != 0;
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_ctx_reset_stats(tt_ctx* ctx) {
+  if (!ctx) return TT_EINVAL;
+  ABI_TRY
+  ctx->sync();
+  ctx->stats.clear();
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_ctx_get_stats(tt_ctx* ctx, const char* kernel, double* total_ms, double* flops, double* bytes,
+                     long long* launches) {
+  if (!ctx || !kernel) return TT_EINVAL;
+  ABI_TRY
+  ctx->sync();
+  auto it = ctx->stats.find(kernel);
+  tt_ctx::Stat s;
+  if (it != ctx->stats.end()) s = it->second;
+  if (total_ms) *total_ms = s.ms;
+  if (flops) *flops = s.flops;
+  if (bytes) *bytes = s.bytes;
+  if (launches) *launches = s.n;
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_tensor_create(tt_ctx* ctx, int d, int n, const int* rank_cap, tt_tensor** out) {
+  if (!ctx || !rank_cap || !out) return TT_EINVAL;
+  ABI_TRY
+  *out = make_tensor(ctx, d, n, std::vector<int>(rank_cap, rank_cap + d + 1));
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_tensor_destroy(tt_tensor* t) {
+  if (!t) return TT_EINVAL;
+  (void)hipStreamSynchronize(t->ctx->stream);
+  free_tensor(t);
+  return TT_OK;
+}
+
+int tt_tensor_set_cores(tt_tensor* t, const int* ranks, const double* const* cores) {
+  if (!t || !ranks || !cores) return TT_EINVAL;
+  tt_ctx* ctx = t->ctx;
+  ABI_TRY
+  require(ranks[0] == 1 && ranks[t->d] == 1, TT_EINVAL, "boundary ranks must be 1");
+  for (int k = 0; k <= t->d; ++k) require(ranks[k] >= 1 && ranks[k] <= t->cap[k], TT_ECAPACITY, "rank exceeds capacity");
+  TTF_HIP(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < t->d; ++k) {
+    require(cores[k] != nullptr, TT_EINVAL, "null core pointer");
+    const size_t bytes = sizeof(zc) * (size_t)ranks[k] * t->n * ranks[k + 1];
+    TTF_HIP(hipMemcpy(t->core[k], cores[k], bytes, hipMemcpyHostToDevice));
+  }
+  t->rank.assign(ranks, ranks + t->d + 1);
+  t->orth = TT_ORTH_NONE;
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_tensor_get_ranks(const tt_tensor* t, int* ranks) {
+  if (!t || !ranks) return TT_EINVAL;
+  for (int k = 0; k <= t->d; ++k) ranks[k] = t->rank[k];
+  return TT_OK;
+}
+
+int tt_tensor_get_cores(const tt_tensor* t, double* const* cores) {
+  if (!t || !cores) return TT_EINVAL;
+  tt_ctx* ctx = t->ctx;
+  ABI_TRY
+  TTF_HIP(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < t->d; ++k) {
+    require(cores[k] != nullptr, TT_EINVAL, "null core pointer");
+    TTF_HIP(hipMemcpy(cores[k], t->core[k], sizeof(zc) * t->elems(k), hipMemcpyDeviceToHost));
+  }
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_tensor_get_orth(const tt_tensor* t) { return t ? t->orth : TT_EINVAL; }
+
+int tt_tensor_copy(tt_ctx* ctx, const tt_tensor* src, tt_tensor* dst) {
+  if (!ctx || !src || !dst) return TT_EINVAL;
+  ABI_TRY
+  copy_tensor(ctx, src, dst);
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_tensor_set_gaussian(tt_ctx* ctx, tt_tensor* t, const double* mu, const double* sigma, double L) {
+  if (!ctx || !t || !mu || !sigma) return TT_EINVAL;
+  ABI_TRY
+  require(L > 0, TT_EINVAL, "L must be positive");
+  for (int k = 0; k < t->d; ++k) gaussian_factor(ctx, t->core[k], t->n, L, mu[k], sigma[k]);
+  t->rank.assign(t->d + 1, 1);
+  t->orth = TT_ORTH_NONE;
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_op_create_burgers_hopf(tt_ctx* ctx, int d, int n, double L, double nu, tt_op** out) {
+  if (!out) return TT_EINVAL;
+  tt_op* op = nullptr;
+  ABI_TRY
+  *out = nullptr;
+  require(d >= 1 && d <= TT_MAX_D, TT_EINVAL, "d must be in 1..128");
+  require(n >= 4, TT_EINVAL, "n must be at least 4");
+  require(L > 0 && nu >= 0, TT_EINVAL, "need L > 0 and nu >= 0");
+  op = new tt_op;
+  op->d = d;
+  op->n = n;
+  op->L = L;
+  op->nu = nu;
+  build_burgers_hopf(op);
+  if (ctx) upload_op(ctx, op);
+  *out = op;
+  return TT_OK;
+  }
+  catch (const ttf::Error& e) {
+    if (ctx) ctx->last_error = e.msg;
+    free_op(op);
+    return e.code;
+  }
+  catch (...) {
+    free_op(op);
+    return TT_EINVAL;
+  }
+}
+
+int tt_op_destroy(tt_op* op) {
+  if (!op) return TT_EINVAL;
+  if (op->ctx) (void)hipStreamSynchronize(op->ctx->stream);
+  free_op(op);
+  return TT_OK;
+}
+
+int tt_op_get_ranks(const tt_op* op, int* R) {
+  if (!op || !R) return TT_EINVAL;
+  for (int k = 0; k <= op->d; ++k) R[k] = op->R[k];
+  return TT_OK;
+}
+
+int tt_op_export_coefficients(const tt_op* op, double* B, double* D) {
+  if (!op) return TT_EINVAL;
+  if (B) std::memcpy(B, op->B.data(), sizeof(double) * op->B.size());
+  if (D) std::memcpy(D, op->D.data(), sizeof(double) * op->D.size());
+  return TT_OK;
+}
+
+int tt_op_export_local_ops(const tt_op* op, int* nops, double* mats) {
+  if (!op) return TT_EINVAL;
+  const int n = op->n;
+  if (nops) *nops = NOPS;
+  if (mats) {
+    std::memset(mats, 0, sizeof(double) * NOPS * n * n);
+    for (int o = 0; o < NOPS; ++o)
+      for (int i = 0; i < n; ++i)
+        for (int t = 0; t < NTAPS; ++t) {
+          const size_t ti = ((size_t)o * n + i) * NTAPS + t;
+          mats[((size_t)o * n + i) * n + op->tap_col[ti]] += op->tap_w[ti];
+        }
+  }
+  return TT_OK;
+}
+
+int tt_op_export_site(const tt_op* op, int site, int* count, int* alpha, int* beta, int* lop, double* coef) {
+  if (!op || !count || site < 0 || site >= op->d) return TT_EINVAL;
+  const auto& ent = op->site[site];
+  *count = (int)ent.size();
+  if (alpha && beta && lop && coef) {
+    for (size_t i = 0; i < ent.size(); ++i) {
+      alpha[i] = ent[i].alpha;
+      beta[i] = ent[i].beta;
+      lop[i] = ent[i].lop;
+      coef[2 * i] = ent[i].cre;
+      coef[2 * i + 1] = ent[i].cim;
+    }
+  }
+  return TT_OK;
+}
+
+int tt_apply(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, const tt_apply_opts* opts) {
+  if (!ctx || !op || !x || !y || !opts) return TT_EINVAL;
+  ABI_TRY
+  require(opts->size == (int)sizeof(tt_apply_opts), TT_EINVAL, "tt_apply_opts.size mismatch");
+  apply_any(ctx, op, x, y, opts->mode, opts->sketch_rank, opts->seed);
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_axpy(tt_ctx* ctx, double ar, double ai, const tt_tensor* x, double br, double bi, const tt_tensor* y,
+            tt_tensor* z) {
+  if (!ctx || !x || !y || !z) return TT_EINVAL;
+  ABI_TRY
+  const tt_tensor* xs[2] = {x, y};
+  const zc coef[2] = {Z(ar, ai), Z(br, bi)};
+  sum_tensors(ctx, 2, coef, xs, z);
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_sum(tt_ctx* ctx, int nterms, const double* coef, const tt_tensor* const* xs, tt_tensor* z) {
+  if (!ctx || !coef || !xs || !z) return TT_EINVAL;
+  ABI_TRY
+  require(nterms >= 1 && nterms <= 8, TT_EINVAL, "tt_sum: 1..8 terms");
+  std::vector<zc> c(nterms);
+  for (int t = 0; t < nterms; ++t) c[t] = Z(coef[2 * t], coef[2 * t + 1]);
+  sum_tensors(ctx, nterms, c.data(), xs, z);
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_round(tt_ctx* ctx, tt_tensor* x, double eps_rel, int rmax, tt_round_report* rep) {
+  if (!ctx || !x) return TT_EINVAL;
+  ABI_TRY
+  require(eps_rel >= 0, TT_EINVAL, "tt_round: eps must be >= 0");
+  round_tensor(ctx, x, eps_rel, rmax, rep);
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step_opts* opts, tt_step_report* rep) {
+  if (!ctx || !op || !f || !opts) return TT_EINVAL;
+  ABI_TRY
+  require(opts->size == (int)sizeof(tt_step_opts), TT_EINVAL, "tt_step_opts.size mismatch");
+  require(opts->rmax >= 1, TT_EINVAL, "tt_step: rmax must be >= 1");
+  check_same_shape(op, f);
+  const int d = f->d, n = f->n, rmax = opts->rmax;
+  // capacities of the temporaries
+  std::vector<int> capk(d + 1), capy(d + 1), capf(d + 1);
+  for (int k = 0; k <= d; ++k) {
+    const int rk = (k == 0 || k == d) ? 1 : std::max(rmax, f->cap[k]);
+    const int base = (k == 0 || k == d) ? 1 : rmax;
+    if (opts->apply_mode == TT_APPLY_EXACT)
+      capk[k] = op->R[k] * rk;
+    else
+      capk[k] = (k == 0 || k == d) ? 1 : std::max(opts->sketch_rank, rmax);
+    capy[k] = (k == 0 || k == d) ? 1 : rk + base;
+    capf[k] = (k == 0 || k == d) ? 1 : rk + 4 * base;
+  }
+  const std::string key = shape_key(d, n, f->cap, opts->apply_mode * 100000 + opts->sketch_rank * 100 + rmax);
+  StepTemps& T = step_cache()[{ctx, key}];
+  if (!T.ysum) {
+    for (int s = 0; s < 4; ++s) T.k[s] = make_tensor(ctx, d, n, capk);
+    T.ysum = make_tensor(ctx, d, n, capy);
+    T.fsum = make_tensor(ctx, d, n, capf);
+  }
+  const double eps = opts->eps;
+  const int mode = opts->apply_mode, l = opts->sketch_rank;
+  int maxr = 0;
+  auto track = [&](const tt_tensor* t) {
+    for (int k = 0; k <= d; ++k) maxr = std::max(maxr, t->rank[k]);
+  };
+  const tt_tensor* stage_in = f;
+  const double cst[3] = {0.5 * dt, 0.5 * dt, dt};
+  for (int s = 0; s < 4; ++s) {
+    apply_any(ctx, op, stage_in, T.k[s], mode, l, opts->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(s + 1));
+    round_tensor(ctx, T.k[s], eps, rmax, nullptr);
+    track(T.k[s]);
+    if (s < 3) {
+      const tt_tensor* xs[2] = {f, T.k[s]};
+      const zc coef[2] = {Z(1), Z(cst[s])};
+      sum_tensors(ctx, 2, coef, xs, T.ysum);
+      round_tensor(ctx, T.ysum, eps, rmax, nullptr);
+      track(T.ysum);
+      stage_in = T.ysum;
+    }
+  }
+  const tt_tensor* xs[5] = {f, T.k[0], T.k[1], T.k[2], T.k[3]};
+  const zc coef[5] = {Z(1), Z(dt / 6), Z(dt / 3), Z(dt / 3), Z(dt / 6)};
+  sum_tensors(ctx, 5, coef, xs, T.fsum);
+  round_tensor(ctx, T.fsum, eps, rmax, nullptr);
+  track(T.fsum);
+  copy_tensor(ctx, T.fsum, f);
+  if (rep) {
+    rep->stages = 4;
+    rep->max_rank = maxr;
+    for (int k = 0; k <= d; ++k) rep->ranks[k] = f->rank[k];
+  }
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_eval(tt_ctx* ctx, const tt_tensor* x, const int32_t* idx, int64_t npts, double* out) {
+  if (!ctx || !x || (npts > 0 && (!idx || !out))) return TT_EINVAL;
+  ABI_TRY
+  for (int k = 0; k <= x->d; ++k) require(x->rank[k] <= 512, TT_EINVAL, "tt_eval: ranks above 512 unsupported");
+  const int d = x->d;
+  std::vector<const zc*> ptrs(x->core.begin(), x->core.end());
+  std::vector<int> ranks(x->rank.begin(), x->rank.end());
+  char* meta = (char*)ctx->get_ws("eval_meta", sizeof(void*) * d + sizeof(int) * (d + 1) + 64);
+  TTF_HIP(hipMemcpyAsync(meta, ptrs.data(), sizeof(void*) * d, hipMemcpyHostToDevice, ctx->stream));
+  TTF_HIP(hipMemcpyAsync(meta + sizeof(void*) * d, ranks.data(), sizeof(int) * (d + 1), hipMemcpyHostToDevice,
+                         ctx->stream));
+  // pageable sources: wait so the host vectors may go out of scope
+  TTF_HIP(hipStreamSynchronize(ctx->stream));
+  tt_eval_kernel(ctx, d, x->n, (const zc* const*)meta, (const int*)(meta + sizeof(void*) * d), idx, npts, (zc*)out);
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, double alpha_re, double alpha_im, const double* A,
+             int64_t lda, int64_t strideA, const double* B, int64_t ldb, int64_t strideB, double beta_re,
+             double beta_im, double* C, int64_t ldc, int64_t strideC, int batch) {
+  if (!ctx) return TT_EINVAL;
+  ABI_TRY
+  require(opA >= 0 && opA <= 2 && opB >= 0 && opB <= 2, TT_EINVAL, "tt_zgemm: op must be 0, 1 or 2");
+  require(M >= 0 && N >= 0 && K >= 0 && batch >= 1, TT_EINVAL, "tt_zgemm: negative size");
+  require(C && ((A && B) || K == 0), TT_EINVAL, "tt_zgemm: null pointer");
+  require(lda >= std::max(1, opA == OPN ? M : K) && ldb >= std::max(1, opB == OPN ? K : N) && ldc >= std::max(1, M),
+          TT_EINVAL, "tt_zgemm: leading dimension too small");
+  zgemm(ctx, opA, opB, M, N, K, Z(alpha_re, alpha_im), (const zc*)A, lda, strideA, (const zc*)B, ldb, strideB,
+        Z(beta_re, beta_im), (zc*)C, ldc, strideC, batch);
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out) {
+  if (!ctx || !x || !out) return TT_EINVAL;
+  ABI_TRY
+  tt_tensor*& tmp = norm_cache()[{ctx, shape_key(x->d, x->n, x->cap, -1)}];
+  if (!tmp) tmp = make_tensor(ctx, x->d, x->n, x->cap);
+  copy_tensor(ctx, x, tmp);
+  if (tmp->orth != TT_ORTH_RIGHT && x->d > 1) phase1_right_orth(ctx, tmp);
+  *out = core_norm(ctx, tmp, 0);
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+}  // extern "C"

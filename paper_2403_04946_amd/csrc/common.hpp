@@ -1,0 +1,179 @@
+// Internal declarations of the tensor-train solver library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tt_fde.h"
+
+namespace ttf {
+
+using zc = double2;  // complex double, interleaved (re, im)
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  int code;
+  std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define TTF_HIP(call) ::ttf::hip_check((call), #call)
+
+// Local (one-axis) operators of the grid discretisation.  Every row has at
+// most four non-zeros; they are stored as taps (column, weight).
+enum LocalOp { OP_I = 0, OP_X = 1, OP_G = 2, OP_L2 = 3, OP_XG = 4, OP_XL2 = 5, NOPS = 6 };
+constexpr int NTAPS = 4;
+
+// Automaton transition (TT-matrix entry) at one site.
+struct Entry {
+  int alpha, beta, lop;
+  double cre, cim;
+};
+
+// Packed device form of a transition list grouped by one channel index.
+struct DevEntry {
+  int other;  // the channel on the other side of the site
+  int lop;
+  double cre, cim;
+};
+
+struct DevBlock {  // exact apply: one (alpha, beta) block and its op list
+  int alpha, beta, first, count;
+};
+struct DevBlockOp {
+  int lop, pad;
+  double cre, cim;
+};
+
+}  // namespace ttf
+
+// ------------------------------------------------------------ opaque types
+struct tt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string last_error;
+  struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<std::string, Buf> ws;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  // profiling
+  bool profiling = false;
+  struct Stat {
+    double ms = 0, flops = 0, bytes = 0;
+    long long n = 0;
+  };
+  std::map<std::string, Stat> stats;
+  struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
+
+  void* get_ws(const std::string& name, size_t bytes);
+  void* host_scratch(size_t bytes);
+  void sync();
+  void resolve_stats();
+};
+
+struct tt_tensor {
+  tt_ctx* ctx = nullptr;
+  int d = 0, n = 0;
+  std::vector<int> cap, rank;
+  std::vector<ttf::zc*> core;
+  int orth = TT_ORTH_NONE;
+  size_t cap_elems(int k) const { return (size_t)cap[k] * n * cap[k + 1]; }
+  size_t elems(int k) const { return (size_t)rank[k] * n * rank[k + 1]; }
+};
+
+struct tt_op {
+  int d = 0, n = 0;
+  double L = 0, nu = 0;
+  std::vector<double> B, D;           // host coefficients
+  std::vector<double> grid;           // a_i
+  std::vector<int> tap_col;           // [NOPS][n][NTAPS]
+  std::vector<double> tap_w;          // [NOPS][n][NTAPS]
+  std::vector<int> R;                 // bond dimensions, d+1
+  std::vector<std::vector<ttf::Entry>> site;
+  // device copies (when created with a context)
+  tt_ctx* ctx = nullptr;
+  int* d_tap_col = nullptr;
+  double* d_tap_w = nullptr;
+  struct SiteDev {
+    int* in_ptr = nullptr;   // CSR over beta: incoming (alpha, op, coef)
+    ttf::DevEntry* in_ent = nullptr;
+    int* out_ptr = nullptr;  // CSR over alpha: outgoing (beta, op, coef)
+    ttf::DevEntry* out_ent = nullptr;
+    ttf::DevBlock* blocks = nullptr;
+    ttf::DevBlockOp* bops = nullptr;
+    int nblocks = 0;
+  };
+  std::vector<SiteDev> dev;
+};
+
+namespace ttf {
+
+// ---------------------------------------------------------- host builder
+void build_burgers_hopf(tt_op* op);  // fills everything but device data
+
+// --------------------------------------------------------------- profiling
+struct KTimer {
+  tt_ctx* ctx;
+  const char* name;
+  double flops, bytes;
+  hipEvent_t a = nullptr, b = nullptr;
+  KTimer(tt_ctx* c, const char* nm, double fl, double by);
+  ~KTimer();
+};
+
+// ------------------------------------------------------- kernel launchers
+// op codes for GEMM operands
+enum { OPN = 0, OPT = 1, OPC = 2 };
+
+// C[M x N] = alpha op(A) op(B) + beta C, column major, batched with strides.
+void zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const zc* A,
+           long lda, long strideA, const zc* B, long ldb, long strideB, zc beta, zc* C,
+           long ldc, long strideC, int batch = 1);
+
+// Dense kernels (single workgroup per problem).
+// Cholesky of G (k x k, ld k) with diagonal shift and pivot floor, returning
+// upper R (G + shift I = R^H R) and R^{-1}.  Both k x k, ld k.
+void chol_inv(tt_ctx* ctx, int k, const zc* G, zc* R, zc* Rinv, double shift_rel, double floor_rel);
+// One-sided Jacobi SVD of B (m x k, ld m) in place: on exit the columns of B
+// are U * Sigma, sorted by decreasing norm; sigma[k] holds the norms and B
+// is scratch; U (m x k, ld m) receives the normalised columns (zero where
+// sigma = 0).  Writes the
+// number of sweeps used to *sweeps (device int).
+void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps);
+
+// Elementwise / small helpers.
+void set_identity(tt_ctx* ctx, zc* A, int m, int k, long lda);  // A = I (m x k)
+void copy_matrix(tt_ctx* ctx, const zc* src, long lds, zc* dst, long ldd, int m, int k);
+void frob_norm2(tt_ctx* ctx, const zc* x, long n, double* out_dev);  // single value
+
+// TT kernels
+void concat_core(tt_ctx* ctx, int nterms, const zc* const* src, const int* r0s, const int* r1s,
+                 const zc* coefs, int kind, int n, zc* dst, int R0, int R1);
+void tt_eval_kernel(tt_ctx* ctx, int d, int n, const zc* const* cores, const int* ranks,
+                    const int32_t* idx, int64_t npts, zc* out);
+void gaussian_factor(tt_ctx* ctx, zc* core, int n, double L, double mu, double sigma);
+void identity_core(tt_ctx* ctx, zc* core, int n, int r1);  // (n r1) x n x r1, I
+void apply_exact_core(tt_ctx* ctx, const tt_op* op, int site, const zc* x, int r0, int r1,
+                      zc* y);
+// left-sketch gather:  W[j,i,b,beta] = sum_in(beta) c * (O V[j,alpha,:,b])[i]
+void gather_left(tt_ctx* ctx, const tt_op* op, int site, const zc* V, zc* W, int l, int r1);
+// right gather: Z[a,alpha,i,q] = sum_out(alpha) c * (O V2[a,:,beta,q])[i]
+void gather_right(tt_ctx* ctx, const tt_op* op, int site, const zc* V2, zc* Z, int r0, int s);
+// Gaussian sketch core (counter-based Philox4x32-10 + Box-Muller)
+void sketch_core(tt_ctx* ctx, zc* w, long count, uint64_t seed, int site, double scale);
+
+}  // namespace ttf

@@ -1,0 +1,332 @@
+// Small dense factorisations used once per TT bond, one workgroup each.
+//
+// * chol_inv: Cholesky factor R (upper, G + s I = R^H R) of a Hermitian
+//   Gram matrix and its inverse.  Together with the GEMMs G = A^H A and
+//   Q = A R^{-1} this is one pass of CholeskyQR; three passes with a shift
+//   on the first (shifted CholeskyQR3) give a QR factorisation whose R has
+//   the singular values of A to working accuracy, also for ill-conditioned
+//   or rank-deficient A, while keeping all O(m k^2) work on matrix cores.
+//   It replaces the Householder QR / LQ of the paper's orthogonalisation
+//   and truncation sweeps (App. A.1, Alg. 1 and Alg. 2; App. A.3 TSQR).
+// * jacobi_svd: one-sided (Hestenes) Jacobi SVD of the small square factor
+//   R (the "SVD of the R factor" of App. A.4): columns are rotated pairwise
+//   until orthogonal; their norms are the singular values and the
+//   normalised columns the left singular vectors.  Parallel round-robin
+//   ordering, one wavefront per column pair, matrix in LDS when it fits.
+#include "common.hpp"
+
+namespace ttf {
+
+constexpr int CHOL_THREADS = 512;
+constexpr int CHOL_KMAX = 512;
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+// R (k x k, ld k) <- chol(G + shift*tr(G)/k... ) see launcher; Rinv <- R^{-1}
+__global__ __launch_bounds__(CHOL_THREADS) void chol_inv_kernel(int k, const zc* __restrict__ G,
+                                                                zc* __restrict__ R, zc* __restrict__ Rinv,
+                                                                double shift_rel, double floor_rel) {
+  __shared__ double red[CHOL_THREADS / 64];
+  __shared__ double s_inv;
+  __shared__ double dinv[CHOL_KMAX];
+  const int t = threadIdx.x, nt = blockDim.x;
+  // trace
+  double tr = 0;
+  for (int j = t; j < k; j += nt) tr += G[j + (long)k * j].x;
+  tr = block_sum(tr, red);
+  const double shift = shift_rel * tr, floor_v = floor_rel * tr;
+  const double tiny = 1e-300;
+  // copy upper triangle (+ shift on the diagonal), zero the lower one
+  for (long e = t; e < (long)k * k; e += nt) {
+    const int r = (int)(e % k), c = (int)(e / k);
+    zc v = make_double2(0.0, 0.0);
+    if (r <= c) {
+      v = G[e];
+      if (r == c) {
+        v.x += shift;
+        v.y = 0.0;
+      }
+    }
+    R[e] = v;
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (t == 0) {
+      double dj = R[j + (long)k * j].x;
+      if (!(dj > floor_v)) dj = floor_v;  // also catches NaN
+      if (!(dj > tiny)) dj = tiny;
+      const double rjj = sqrt(dj);
+      R[j + (long)k * j] = make_double2(rjj, 0.0);
+      s_inv = 1.0 / rjj;
+      dinv[j] = s_inv;
+    }
+    __syncthreads();
+    const double inv = s_inv;
+    for (int c = j + 1 + t; c < k; c += nt) {
+      zc v = R[j + (long)k * c];
+      R[j + (long)k * c] = make_double2(v.x * inv, v.y * inv);
+    }
+    __syncthreads();
+    const int m = k - j - 1;
+    for (long e = t; e < (long)m * m; e += nt) {
+      const int r = j + 1 + (int)(e % m), c = j + 1 + (int)(e / m);
+      if (r > c) continue;
+      const zc a = R[j + (long)k * r];  // R[j][r]
+      const zc b = R[j + (long)k * c];  // R[j][c]
+      // R[r][c] -= conj(a) * b
+      zc v = R[r + (long)k * c];
+      v.x -= a.x * b.x + a.y * b.y;
+      v.y -= a.x * b.y - a.y * b.x;
+      R[r + (long)k * c] = v;
+    }
+    __syncthreads();
+  }
+  // inverse of the upper-triangular R, one column per wavefront, column
+  // held across lanes (element r in lane r % 64, slot r / 64)
+  const int wave = t >> 6, lane = t & 63, nw = nt >> 6;
+  constexpr int SLOTS = CHOL_KMAX / 64;
+  for (int c = wave; c < k; c += nw) {
+    double xr[SLOTS], xi[SLOTS];
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+      const int r = lane + 64 * q;
+      xr[q] = (r == c) ? 1.0 : 0.0;
+      xi[q] = 0.0;
+    }
+    for (int p = c; p >= 0; --p) {
+      const int ql = p >> 6, lp = p & 63;
+      double vr = 0, vi = 0;
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q)
+        if (q == ql) {
+          vr = xr[q];
+          vi = xi[q];
+        }
+      vr = __shfl(vr, lp, 64);
+      vi = __shfl(vi, lp, 64);
+      const double di = dinv[p];
+      vr *= di;
+      vi *= di;
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q) {
+        const int r = lane + 64 * q;
+        if (r == p) {
+          xr[q] = vr;
+          xi[q] = vi;
+        } else if (r < p) {
+          const zc a = R[r + (long)k * p];
+          xr[q] -= a.x * vr - a.y * vi;
+          xi[q] -= a.x * vi + a.y * vr;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+      const int r = lane + 64 * q;
+      if (r < k) Rinv[r + (long)k * c] = (r <= c) ? make_double2(xr[q], xi[q]) : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+void chol_inv(tt_ctx* ctx, int k, const zc* G, zc* R, zc* Rinv, double shift_rel, double floor_rel) {
+  if (k <= 0) return;
+  if (k > CHOL_KMAX) fail(TT_EINVAL, "chol_inv: rank above the supported maximum of 512");
+  KTimer kt(ctx, "cholqr", 8.0 * k * (double)k * k / 3.0 + 8.0 * k * (double)k * k / 6.0, 48.0 * k * k);
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CHOL_THREADS), 0, ctx->stream, k, G, R, Rinv,
+                     shift_rel, floor_rel);
+  TTF_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ Jacobi SVD
+constexpr int JAC_THREADS = 1024;
+constexpr int JAC_LDS_ELEMS = 9216;  // 144 KiB of complex doubles
+constexpr int JAC_MAX_SWEEPS = 60;
+
+// round-robin pairing of players 0..P-1 (P even) in round r
+__device__ inline void rr_pair(int P, int r, int i, int& a, int& b) {
+  const int M = P - 1;
+  if (i == 0) {
+    a = 0;
+    b = 1 + (r % M);
+  } else {
+    a = 1 + ((r + i) % M);
+    b = 1 + ((r - i + M) % M);
+  }
+}
+
+template <bool IN_LDS>
+__global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, int k, zc* __restrict__ Bg,
+                                                             zc* __restrict__ U, double* __restrict__ sigma,
+                                                             int* __restrict__ sweeps_out) {
+  extern __shared__ double2 lds[];
+  __shared__ int rotated;
+  __shared__ double norms[CHOL_KMAX];
+  zc* B = IN_LDS ? lds : Bg;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
+  if (IN_LDS)
+    for (long e = t; e < (long)m * k; e += blockDim.x) B[e] = Bg[e];
+  __syncthreads();
+  const int P = (k + 1) & ~1;
+  const double tol = 1e-15 * sqrt((double)m);
+  int sweep = 0;
+  for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
+    if (t == 0) rotated = 0;
+    __syncthreads();
+    int any = 0;
+    for (int r = 0; r < P - 1; ++r) {
+      for (int i = wave; i < P / 2; i += nw) {
+        int p, q;
+        rr_pair(P, r, i, p, q);
+        if (p >= k || q >= k) continue;
+        double al = 0, be = 0, gr = 0, gi = 0;
+        for (int row = lane; row < m; row += 64) {
+          const zc x = B[row + (long)m * p], y = B[row + (long)m * q];
+          al += x.x * x.x + x.y * x.y;
+          be += y.x * y.x + y.y * y.y;
+          gr += x.x * y.x + x.y * y.y;  // conj(x) * y
+          gi += x.x * y.y - x.y * y.x;
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        gr = wave_sum(gr);
+        gi = wave_sum(gi);
+        const double g = sqrt(gr * gr + gi * gi);
+        if (g <= tol * sqrt(al * be) || g == 0.0) continue;
+        any = 1;
+        // complex Jacobi rotation orthogonalising columns p and q
+        const double zeta = (be - al) / (2.0 * g);
+        const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+        const double er = gr / g, ei = gi / g;  // e^{i phi}
+        for (int row = lane; row < m; row += 64) {
+          const zc x = B[row + (long)m * p], y = B[row + (long)m * q];
+          // x' = c x - s e^{-i phi} y ; y' = s e^{i phi} x + c y
+          zc xn, yn;
+          xn.x = c * x.x - s * (er * y.x + ei * y.y);
+          xn.y = c * x.y - s * (er * y.y - ei * y.x);
+          yn.x = s * (er * x.x - ei * x.y) + c * y.x;
+          yn.y = s * (er * x.y + ei * x.x) + c * y.y;
+          B[row + (long)m * p] = xn;
+          B[row + (long)m * q] = yn;
+        }
+      }
+      __syncthreads();
+    }
+    if (any && lane == 0) atomicOr(&rotated, 1);
+    __syncthreads();
+    if (!rotated) break;
+  }
+  // singular values = column norms
+  for (int c = wave; c < k; c += nw) {
+    double s = 0;
+    for (int row = lane; row < m; row += 64) {
+      const zc x = B[row + (long)m * c];
+      s += x.x * x.x + x.y * x.y;
+    }
+    s = wave_sum(s);
+    if (lane == 0) norms[c] = sqrt(s);
+  }
+  __syncthreads();
+  // sort by decreasing norm (ties by index) and normalise into U
+  for (int c = wave; c < k; c += nw) {
+    const double v = norms[c];
+    int pos = 0;
+    for (int o = 0; o < k; ++o) {
+      const double w = norms[o];
+      pos += (w > v) || (w == v && o < c);
+    }
+    const double inv = v > 0 ? 1.0 / v : 0.0;
+    for (int row = lane; row < m; row += 64) {
+      const zc x = B[row + (long)m * c];
+      U[row + (long)m * pos] = make_double2(x.x * inv, x.y * inv);
+    }
+    if (lane == 0) sigma[pos] = v;
+  }
+  if (t == 0) *sweeps_out = sweep + 1;
+}
+
+void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
+  if (k <= 0) return;
+  if (k > CHOL_KMAX) fail(TT_EINVAL, "jacobi_svd: rank above the supported maximum of 512");
+  static int lds_limit = -1;
+  if (lds_limit < 0) {
+    int dev = 0, v = 0;
+    TTF_HIP(hipGetDevice(&dev));
+    TTF_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    lds_limit = v;
+  }
+  KTimer kt(ctx, "jacobi", 0.0, 0.0);
+  const long need = (long)sizeof(zc) * m * k + 8 * CHOL_KMAX + 64;
+  if ((long)m * k <= JAC_LDS_ELEMS && need <= lds_limit) {
+    const size_t lds = sizeof(zc) * (size_t)m * k;
+    hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(JAC_THREADS), lds, ctx->stream, m, k, B, U,
+                       sigma, sweeps);
+  } else {
+    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(JAC_THREADS), 0, ctx->stream, m, k, B, U,
+                       sigma, sweeps);
+  }
+  TTF_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------- helpers
+__global__ void set_identity_kernel(zc* A, int m, int k, long lda) {
+  const long total = (long)m * k;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(e % m), c = (int)(e / m);
+    A[r + lda * c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+}
+
+void set_identity(tt_ctx* ctx, zc* A, int m, int k, long lda) {
+  const long total = (long)m * k;
+  if (total <= 0) return;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(set_identity_kernel, dim3(blocks), dim3(256), 0, ctx->stream, A, m, k, lda);
+  TTF_HIP(hipGetLastError());
+}
+
+__global__ void copy_matrix_kernel(const zc* src, long lds_, zc* dst, long ldd, int m, int k) {
+  const long total = (long)m * k;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(e % m), c = (int)(e / m);
+    dst[r + ldd * c] = src[r + lds_ * c];
+  }
+}
+
+void copy_matrix(tt_ctx* ctx, const zc* src, long lds_, zc* dst, long ldd, int m, int k) {
+  const long total = (long)m * k;
+  if (total <= 0) return;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(copy_matrix_kernel, dim3(blocks), dim3(256), 0, ctx->stream, src, lds_, dst, ldd, m, k);
+  TTF_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(1024) void frob_norm2_kernel(const zc* x, long n, double* out) {
+  __shared__ double red[16];
+  double s = 0;
+  for (long e = threadIdx.x; e < n; e += blockDim.x) s += x[e].x * x[e].x + x[e].y * x[e].y;
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) *out = s;
+}
+
+void frob_norm2(tt_ctx* ctx, const zc* x, long n, double* out_dev) {
+  hipLaunchKernelGGL(frob_norm2_kernel, dim3(1), dim3(1024), 0, ctx->stream, x, n, out_dev);
+  TTF_HIP(hipGetLastError());
+}
+
+}  // namespace ttf

@@ -1,0 +1,370 @@
+// TT-format kernels: concatenation (sums), pointwise evaluation, initial
+// condition, exact operator application, the MPO gathers of the sketched
+// application, and the Gaussian sketch generator.
+#include "common.hpp"
+
+namespace ttf {
+
+// ---------------------------------------------------------------- concat
+// Sum by concatenation (App. A.1): first cores side by side (scaled by the
+// term coefficients), middle cores block diagonal, last cores stacked.
+constexpr int MAX_TERMS = 8;
+struct ConcatArgs {
+  const zc* src[MAX_TERMS];
+  int r0[MAX_TERMS], r1[MAX_TERMS];
+  int off0[MAX_TERMS + 1], off1[MAX_TERMS + 1];
+  zc coef[MAX_TERMS];
+  int nterms, kind, n, R0, R1;
+};
+
+__global__ void concat_kernel(ConcatArgs a, zc* dst) {
+  const long total = (long)a.R0 * a.n * a.R1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int p = (int)(e % a.R0);
+    const long rest = e / a.R0;
+    const int i = (int)(rest % a.n), q = (int)(rest / a.n);
+    int tp = 0, tq = 0;
+    while (tp + 1 < a.nterms && p >= a.off0[tp + 1]) ++tp;
+    while (tq + 1 < a.nterms && q >= a.off1[tq + 1]) ++tq;
+    zc v = make_double2(0.0, 0.0);
+    int t = -1;
+    if (a.kind == 0) t = tq;            // first core: 1 x n x sum r1
+    else if (a.kind == 2) t = tp;       // last core: sum r0 x n x 1
+    else if (a.kind == 1) t = (tp == tq) ? tp : -1;  // block diagonal
+    else t = -2;                        // d == 1: plain weighted sum
+    if (t >= 0) {
+      const int pa = (a.kind == 0) ? 0 : p - a.off0[t];
+      const int qb = (a.kind == 2) ? 0 : q - a.off1[t];
+      const zc x = a.src[t][pa + (long)a.r0[t] * (i + (long)a.n * qb)];
+      if (a.kind == 0) {
+        const zc c = a.coef[t];
+        v = make_double2(c.x * x.x - c.y * x.y, c.x * x.y + c.y * x.x);
+      } else {
+        v = x;
+      }
+    } else if (t == -2) {
+      for (int s = 0; s < a.nterms; ++s) {
+        const zc x = a.src[s][i];
+        const zc c = a.coef[s];
+        v.x += c.x * x.x - c.y * x.y;
+        v.y += c.x * x.y + c.y * x.x;
+      }
+    }
+    dst[e] = v;
+  }
+}
+
+void concat_core(tt_ctx* ctx, int nterms, const zc* const* src, const int* r0s, const int* r1s,
+                 const zc* coefs, int kind, int n, zc* dst, int R0, int R1) {
+  if (nterms > MAX_TERMS) fail(TT_EINVAL, "concat: too many terms");
+  ConcatArgs a;
+  a.nterms = nterms;
+  a.kind = kind;
+  a.n = n;
+  a.R0 = R0;
+  a.R1 = R1;
+  a.off0[0] = a.off1[0] = 0;
+  for (int t = 0; t < nterms; ++t) {
+    a.src[t] = src[t];
+    a.r0[t] = r0s[t];
+    a.r1[t] = r1s[t];
+    a.coef[t] = coefs[t];
+    a.off0[t + 1] = a.off0[t] + ((kind == 0 || kind == 3) ? 0 : r0s[t]);
+    a.off1[t + 1] = a.off1[t] + ((kind == 2 || kind == 3) ? 0 : r1s[t]);
+  }
+  if (kind == 0 || kind == 3)
+    for (int t = 0; t <= nterms; ++t) a.off0[t] = 0;
+  if (kind == 2 || kind == 3)
+    for (int t = 0; t <= nterms; ++t) a.off1[t] = 0;
+  const long total = (long)R0 * n * R1;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 16384);
+  KTimer kt(ctx, "concat", 0.0, 32.0 * total);
+  hipLaunchKernelGGL(concat_kernel, dim3(blocks), dim3(256), 0, ctx->stream, a, dst);
+  TTF_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ eval
+// f[i_1..i_d] = C_1[0,i_1,:] C_2[:,i_2,:] ... C_d[:,i_d,0] (App. A.1), one
+// wavefront per point, the running row vector in LDS.
+constexpr int EVAL_RMAX = 512;
+struct EvalArgs {
+  const zc* const* cores;
+  const int* ranks;
+  const int32_t* idx;
+  long npts;
+  int d, n;
+  zc* out;
+};
+
+__global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
+  __shared__ zc buf[4][2][EVAL_RMAX];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (long pt = blockIdx.x * 4L + wave; pt < a.npts; pt += gridDim.x * 4L) {
+    zc* cur = buf[wave][0];
+    zc* nxt = buf[wave][1];
+    if (lane == 0) cur[0] = make_double2(1.0, 0.0);
+    __builtin_amdgcn_wave_barrier();
+    bool bad = false;
+    for (int k = 0; k < a.d; ++k) {
+      const int r0 = a.ranks[k], r1 = a.ranks[k + 1];
+      int i = a.idx[pt * a.d + k];
+      if (i < 0 || i >= a.n) {  // out-of-range index: result is NaN
+        bad = true;
+        i = 0;
+      }
+      const zc* C = a.cores[k] + (long)r0 * i;
+      for (int b = lane; b < r1; b += 64) {
+        double sr = 0, si = 0;
+        const zc* col = C + (long)r0 * a.n * b;
+        for (int q = 0; q < r0; ++q) {
+          const zc v = cur[q], c = col[q];
+          sr += v.x * c.x - v.y * c.y;
+          si += v.x * c.y + v.y * c.x;
+        }
+        nxt[b] = make_double2(sr, si);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      zc* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+    }
+    if (lane == 0) a.out[pt] = bad ? make_double2(__builtin_nan(""), __builtin_nan("")) : cur[0];
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+void tt_eval_kernel(tt_ctx* ctx, int d, int n, const zc* const* cores, const int* ranks,
+                    const int32_t* idx, int64_t npts, zc* out) {
+  if (npts <= 0) return;
+  EvalArgs a{cores, ranks, idx, (long)npts, d, n, out};
+  const int blocks = (int)std::min<long>((npts + 3) / 4, 65536);
+  KTimer kt(ctx, "eval", 0.0, 0.0);
+  hipLaunchKernelGGL(eval_kernel, dim3(blocks), dim3(256), 0, ctx->stream, a);
+  TTF_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------- init helpers
+__global__ void gaussian_factor_kernel(zc* core, int n, double L, double mu, double sigma) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = -L + 2.0 * L * i / (n - 1);
+  const double mag = exp(-0.5 * sigma * sigma * a * a);
+  double s, c;
+  sincos(mu * a, &s, &c);
+  core[i] = make_double2(mag * c, mag * s);
+}
+
+void gaussian_factor(tt_ctx* ctx, zc* core, int n, double L, double mu, double sigma) {
+  hipLaunchKernelGGL(gaussian_factor_kernel, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, core, n, L, mu,
+                     sigma);
+  TTF_HIP(hipGetLastError());
+}
+
+__global__ void identity_core_kernel(zc* core, int n, int r1) {
+  const long R0 = (long)n * r1;
+  const long total = R0 * n * r1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long p = e % R0;
+    const long rest = e / R0;
+    const int i = (int)(rest % n), b = (int)(rest / n);
+    core[e] = make_double2(p == i + (long)n * b ? 1.0 : 0.0, 0.0);
+  }
+}
+
+void identity_core(tt_ctx* ctx, zc* core, int n, int r1) {
+  const long total = (long)n * r1 * n * r1;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(identity_core_kernel, dim3(blocks), dim3(256), 0, ctx->stream, core, n, r1);
+  TTF_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------- exact apply
+// Y[(a + r0 alpha), i, (b + r1 beta)] = sum_{ops of block} c (O C[a,:,b])[i]
+__global__ void zero_kernel(zc* y, long total) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
+    y[e] = make_double2(0.0, 0.0);
+}
+
+__global__ void apply_exact_kernel(const DevBlock* __restrict__ blocks, const DevBlockOp* __restrict__ bops,
+                                   int nblocks, const int* __restrict__ tcol, const double* __restrict__ tw,
+                                   const zc* __restrict__ x, int n, int r0, int r1, int R0, int R1,
+                                   zc* __restrict__ y) {
+  const long per = (long)r0 * n * r1;
+  const long total = per * nblocks;
+  const long ld0 = (long)R0 * r0;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int bk = (int)(e / per);
+    const long loc = e - bk * per;
+    const int a = (int)(loc % r0);
+    const long rest = loc / r0;
+    const int i = (int)(rest % n), b = (int)(rest / n);
+    const DevBlock blk = blocks[bk];
+    double sr = 0, si = 0;
+    for (int o = 0; o < blk.count; ++o) {
+      const DevBlockOp bo = bops[blk.first + o];
+      double vr = 0, vi = 0;
+      for (int t = 0; t < NTAPS; ++t) {
+        const long ti = ((long)bo.lop * n + i) * NTAPS + t;
+        const double w = tw[ti];
+        if (w == 0.0) continue;
+        const zc xv = x[a + (long)r0 * (tcol[ti] + (long)n * b)];
+        vr += w * xv.x;
+        vi += w * xv.y;
+      }
+      sr += bo.cre * vr - bo.cim * vi;
+      si += bo.cre * vi + bo.cim * vr;
+    }
+    const long p = a + (long)r0 * blk.alpha;
+    const long q = b + (long)r1 * blk.beta;
+    y[p + ld0 * (i + (long)n * q)] = make_double2(sr, si);
+  }
+}
+
+void apply_exact_core(tt_ctx* ctx, const tt_op* op, int site, const zc* x, int r0, int r1, zc* y) {
+  const int n = op->n, R0 = op->R[site], R1 = op->R[site + 1];
+  const auto& sd = op->dev[site];
+  const long total_out = (long)R0 * r0 * n * R1 * r1;
+  int blocks = (int)std::min<long>((total_out + 255) / 256, 16384);
+  KTimer kt(ctx, "apply_exact", 0.0, 16.0 * total_out);
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, ctx->stream, y, total_out);
+  const long total = (long)r0 * n * r1 * sd.nblocks;
+  blocks = (int)std::min<long>((total + 255) / 256, 16384);
+  if (total > 0)
+    hipLaunchKernelGGL(apply_exact_kernel, dim3(blocks), dim3(256), 0, ctx->stream, sd.blocks, sd.bops, sd.nblocks,
+                       op->d_tap_col, op->d_tap_w, x, n, r0, r1, R0, R1, y);
+  TTF_HIP(hipGetLastError());
+}
+
+// --------------------------------------------------- sketched-apply gathers
+// Left:  W[j, i, b, beta] = sum_{(alpha, o, c) -> beta} c * sum_t w_t V[j, alpha, col_t, b]
+//        V layout j + l (alpha + R0 (i' + n b)); W layout j + l (i + n (b + r1 beta)).
+__global__ void gather_left_kernel(const int* __restrict__ ptr, const DevEntry* __restrict__ ent,
+                                   const int* __restrict__ tcol, const double* __restrict__ tw,
+                                   const zc* __restrict__ V, zc* __restrict__ W, int l, int n, int r1, int R0,
+                                   int R1) {
+  const long total = (long)l * n * r1 * R1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e % l);
+    long rest = e / l;
+    const int i = (int)(rest % n);
+    rest /= n;
+    const int b = (int)(rest % r1), beta = (int)(rest / r1);
+    double sr = 0, si = 0;
+    for (int q = ptr[beta]; q < ptr[beta + 1]; ++q) {
+      const DevEntry en = ent[q];
+      double vr = 0, vi = 0;
+      for (int t = 0; t < NTAPS; ++t) {
+        const long ti = ((long)en.lop * n + i) * NTAPS + t;
+        const double w = tw[ti];
+        if (w == 0.0) continue;
+        const zc v = V[j + (long)l * (en.other + (long)R0 * (tcol[ti] + (long)n * b))];
+        vr += w * v.x;
+        vi += w * v.y;
+      }
+      sr += en.cre * vr - en.cim * vi;
+      si += en.cre * vi + en.cim * vr;
+    }
+    W[e] = make_double2(sr, si);
+  }
+}
+
+void gather_left(tt_ctx* ctx, const tt_op* op, int site, const zc* V, zc* W, int l, int r1) {
+  const int n = op->n, R0 = op->R[site], R1 = op->R[site + 1];
+  const long total = (long)l * n * r1 * R1;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
+  KTimer kt(ctx, "gather", 0.0, 32.0 * total);
+  hipLaunchKernelGGL(gather_left_kernel, dim3(blocks), dim3(256), 0, ctx->stream, op->dev[site].in_ptr,
+                     op->dev[site].in_ent, op->d_tap_col, op->d_tap_w, V, W, l, n, r1, R0, R1);
+  TTF_HIP(hipGetLastError());
+}
+
+// Right: Z[a, alpha, i, q] = sum_{alpha -> (beta, o, c)} c * sum_t w_t V2[a, col_t, beta, q]
+//        V2 layout a + r0 (i' + n (beta + R1 q)); Z layout a + r0 (alpha + R0 (i + n q)).
+__global__ void gather_right_kernel(const int* __restrict__ ptr, const DevEntry* __restrict__ ent,
+                                    const int* __restrict__ tcol, const double* __restrict__ tw,
+                                    const zc* __restrict__ V2, zc* __restrict__ Z, int r0, int n, int s, int R0,
+                                    int R1) {
+  const long total = (long)r0 * R0 * n * s;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int a = (int)(e % r0);
+    long rest = e / r0;
+    const int alpha = (int)(rest % R0);
+    rest /= R0;
+    const int i = (int)(rest % n), q = (int)(rest / n);
+    double sr = 0, si = 0;
+    for (int p = ptr[alpha]; p < ptr[alpha + 1]; ++p) {
+      const DevEntry en = ent[p];
+      double vr = 0, vi = 0;
+      for (int t = 0; t < NTAPS; ++t) {
+        const long ti = ((long)en.lop * n + i) * NTAPS + t;
+        const double w = tw[ti];
+        if (w == 0.0) continue;
+        const zc v = V2[a + (long)r0 * (tcol[ti] + (long)n * (en.other + (long)R1 * q))];
+        vr += w * v.x;
+        vi += w * v.y;
+      }
+      sr += en.cre * vr - en.cim * vi;
+      si += en.cre * vi + en.cim * vr;
+    }
+    Z[e] = make_double2(sr, si);
+  }
+}
+
+void gather_right(tt_ctx* ctx, const tt_op* op, int site, const zc* V2, zc* Z, int r0, int s) {
+  const int n = op->n, R0 = op->R[site], R1 = op->R[site + 1];
+  const long total = (long)r0 * R0 * n * s;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
+  KTimer kt(ctx, "gather", 0.0, 32.0 * total);
+  hipLaunchKernelGGL(gather_right_kernel, dim3(blocks), dim3(256), 0, ctx->stream, op->dev[site].out_ptr,
+                     op->dev[site].out_ent, op->d_tap_col, op->d_tap_w, V2, Z, r0, n, s, R0, R1);
+  TTF_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------ Gaussian sketch
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): a counter-based
+// generator; ten rounds of two 32x32->64-bit multiplies and xors with a
+// Weyl-sequence key schedule.  Box-Muller turns two uniforms into a pair of
+// independent normals, used as the real and imaginary part of a sketch entry.
+__device__ inline void philox_round(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+  const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+  const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+  const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+  c[0] = n0;
+  c[1] = lo1;
+  c[2] = n2;
+  c[3] = lo0;
+}
+
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    philox_round(c, k0, k1);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__global__ void sketch_kernel(zc* w, long count, uint32_t k0, uint32_t k1, uint32_t site, double scale) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x) {
+    uint32_t c[4] = {(uint32_t)e, (uint32_t)((uint64_t)e >> 32), site, 0x5EEDu};
+    philox4x32_10(c, k0, k1);
+    const double u1 = ((double)c[0] + 1.0) / 4294967297.0;  // (0, 1)
+    const double u2 = (double)c[1] / 4294967296.0;          // [0, 1)
+    const double r = sqrt(-2.0 * log(u1)) * scale;
+    double s, cs;
+    sincospi(2.0 * u2, &s, &cs);
+    w[e] = make_double2(r * cs, r * s);
+  }
+}
+
+void sketch_core(tt_ctx* ctx, zc* w, long count, uint64_t seed, int site, double scale) {
+  const int blocks = (int)std::min<long>((count + 255) / 256, 8192);
+  hipLaunchKernelGGL(sketch_kernel, dim3(blocks), dim3(256), 0, ctx->stream, w, count, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), (uint32_t)site, scale);
+  TTF_HIP(hipGetLastError());
+}
+
+}  // namespace ttf

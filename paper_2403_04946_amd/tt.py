@@ -1,0 +1,340 @@
+"""Thin ctypes binding of the C ABI in include/tt_fde.h (argument marshalling
+only; every step of the method runs in the HIP library).
+
+Cores cross the boundary as numpy complex128 arrays of shape (r0, n, r1)
+and are stored on the device column major (left rank index fastest), as the
+header specifies.  Device buffers for tt_eval are torch tensors; the
+context runs on torch's current stream unless another stream is given.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libttfde.so")
+MAX_D = 128
+
+TT_APPLY_EXACT = 0
+TT_APPLY_SKETCH = 1
+ORTH = {0: "none", 1: "right", 2: "left"}
+ERRORS = {
+    -1: "TT_EINVAL",
+    -2: "TT_ESHAPE",
+    -3: "TT_ECAPACITY",
+    -4: "TT_ENOMEM",
+    -5: "TT_EHIP",
+    -6: "TT_ENOCONV",
+    -7: "TT_ENONFINITE",
+}
+_LIB = None
+
+
+class TTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class RoundReport(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int),
+        ("ranks", ctypes.c_int * (MAX_D + 1)),
+        ("tail", ctypes.c_double * MAX_D),
+        ("sigma_min_kept", ctypes.c_double * MAX_D),
+        ("norm", ctypes.c_double),
+        ("jacobi_sweeps_max", ctypes.c_int),
+    ]
+
+
+class ApplyOpts(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_int),
+        ("mode", ctypes.c_int),
+        ("sketch_rank", ctypes.c_int),
+        ("pad", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class StepOpts(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_int),
+        ("rmax", ctypes.c_int),
+        ("eps", ctypes.c_double),
+        ("apply_mode", ctypes.c_int),
+        ("sketch_rank", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class StepReport(ctypes.Structure):
+    _fields_ = [
+        ("stages", ctypes.c_int),
+        ("max_rank", ctypes.c_int),
+        ("ranks", ctypes.c_int * (MAX_D + 1)),
+    ]
+
+
+P = ctypes.c_void_p
+I = ctypes.c_int
+D = ctypes.c_double
+PI = ctypes.POINTER(ctypes.c_int)
+PD = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "tt_ctx_create": (I, [I, P, ctypes.POINTER(P)]),
+    "tt_ctx_destroy": (I, [P]),
+    "tt_ctx_sync": (I, [P]),
+    "tt_last_error": (ctypes.c_char_p, [P]),
+    "tt_ctx_stream": (P, [P]),
+    "tt_ctx_set_profiling": (I, [P, I]),
+    "tt_ctx_reset_stats": (I, [P]),
+    "tt_ctx_get_stats": (I, [P, ctypes.c_char_p, PD, PD, PD, ctypes.POINTER(ctypes.c_longlong)]),
+    "tt_tensor_create": (I, [P, I, I, PI, ctypes.POINTER(P)]),
+    "tt_tensor_destroy": (I, [P]),
+    "tt_tensor_set_cores": (I, [P, PI, ctypes.POINTER(P)]),
+    "tt_tensor_get_ranks": (I, [P, PI]),
+    "tt_tensor_get_cores": (I, [P, ctypes.POINTER(P)]),
+    "tt_tensor_get_orth": (I, [P]),
+    "tt_tensor_copy": (I, [P, P, P]),
+    "tt_tensor_set_gaussian": (I, [P, P, PD, PD, D]),
+    "tt_op_create_burgers_hopf": (I, [P, I, I, D, D, ctypes.POINTER(P)]),
+    "tt_op_destroy": (I, [P]),
+    "tt_op_get_ranks": (I, [P, PI]),
+    "tt_op_export_coefficients": (I, [P, PD, PD]),
+    "tt_op_export_local_ops": (I, [P, PI, PD]),
+    "tt_op_export_site": (I, [P, I, PI, PI, PI, PI, PD]),
+    "tt_apply": (I, [P, P, P, P, ctypes.POINTER(ApplyOpts)]),
+    "tt_axpy": (I, [P, D, D, P, D, D, P, P]),
+    "tt_sum": (I, [P, I, PD, ctypes.POINTER(P), P]),
+    "tt_round": (I, [P, P, D, I, ctypes.POINTER(RoundReport)]),
+    "tt_step": (I, [P, P, P, D, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport)]),
+    "tt_eval": (I, [P, P, P, ctypes.c_int64, P]),
+    "tt_norm": (I, [P, P, PD]),
+    "tt_zgemm": (I, [P, I, I, I, I, I, D, D, P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64,
+                     ctypes.c_int64, D, D, P, ctypes.c_int64, ctypes.c_int64, I]),
+}
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(
+                f"{LIBPATH} is missing: build it with `python -m paper_2403_04946_amd.build`"
+            )
+        h = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = h
+    return _LIB
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _ip(a):
+    return a.ctypes.data_as(PI)
+
+
+def _dp(a):
+    return a.ctypes.data_as(PD)
+
+
+class Context:
+    """A device context; work runs on ``stream`` (a torch stream, a raw
+    hipStream_t integer, or None for torch's current stream)."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self._torch_stream = stream
+        h = P()
+        rc = lib().tt_ctx_create(device, P(handle), ctypes.byref(h))
+        if rc != 0:
+            raise TTError(rc, "tt_ctx_create failed")
+        self.h = h
+
+    def check(self, rc):
+        if rc != 0:
+            raise TTError(rc, lib().tt_last_error(self.h).decode())
+
+    def sync(self):
+        self.check(lib().tt_ctx_sync(self.h))
+
+    def set_profiling(self, on):
+        self.check(lib().tt_ctx_set_profiling(self.h, int(bool(on))))
+
+    def reset_stats(self):
+        self.check(lib().tt_ctx_reset_stats(self.h))
+
+    def stats(self, kernel):
+        ms, fl, by, n = D(), D(), D(), ctypes.c_longlong()
+        self.check(
+            lib().tt_ctx_get_stats(self.h, kernel.encode(), ctypes.byref(ms), ctypes.byref(fl),
+                                   ctypes.byref(by), ctypes.byref(n))
+        )
+        return {"ms": ms.value, "flops": fl.value, "bytes": by.value, "launches": n.value}
+
+    def close(self):
+        if self.h:
+            lib().tt_ctx_destroy(self.h)
+            self.h = None
+
+
+class Tensor:
+    def __init__(self, ctx, d, n, caps):
+        caps = np.ascontiguousarray(caps, dtype=np.int32)
+        if caps.size == 1 and d > 1:
+            c = int(caps.ravel()[0])
+            caps = np.array([1] + [c] * (d - 1) + [1], dtype=np.int32)
+        self.ctx, self.d, self.n = ctx, d, n
+        self.caps = caps
+        h = P()
+        ctx.check(lib().tt_tensor_create(ctx.h, d, n, _ip(caps), ctypes.byref(h)))
+        self.h = h
+
+    def ranks(self):
+        r = np.zeros(self.d + 1, dtype=np.int32)
+        self.ctx.check(lib().tt_tensor_get_ranks(self.h, _ip(r)))
+        return [int(v) for v in r]
+
+    def orth(self):
+        return ORTH[lib().tt_tensor_get_orth(self.h)]
+
+    def set_cores(self, cores):
+        ranks = np.array([1] + [c.shape[2] for c in cores], dtype=np.int32)
+        bufs = [np.ascontiguousarray(np.asarray(c, dtype=np.complex128).ravel(order="F")) for c in cores]
+        ptrs = (P * self.d)(*[b.ctypes.data for b in bufs])
+        self.ctx.check(lib().tt_tensor_set_cores(self.h, _ip(ranks), ptrs))
+
+    def get_cores(self):
+        r = self.ranks()
+        bufs = [np.empty(r[k] * self.n * r[k + 1], dtype=np.complex128) for k in range(self.d)]
+        ptrs = (P * self.d)(*[b.ctypes.data for b in bufs])
+        self.ctx.check(lib().tt_tensor_get_cores(self.h, ptrs))
+        return [b.reshape((r[k], self.n, r[k + 1]), order="F") for k, b in enumerate(bufs)]
+
+    def set_gaussian(self, mu, sigma, length):
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+        self.ctx.check(lib().tt_tensor_set_gaussian(self.ctx.h, self.h, _dp(mu), _dp(sigma), float(length)))
+
+    def copy_from(self, other):
+        self.ctx.check(lib().tt_tensor_copy(self.ctx.h, other.h, self.h))
+
+    def close(self):
+        if self.h:
+            lib().tt_tensor_destroy(self.h)
+            self.h = None
+
+
+class Operator:
+    """Burgers-Hopf operator; ctx=None builds a host-only operator."""
+
+    def __init__(self, ctx, d, n, length, nu):
+        self.ctx, self.d, self.n = ctx, d, n
+        h = P()
+        rc = lib().tt_op_create_burgers_hopf(ctx.h if ctx else None, d, n, float(length), float(nu),
+                                             ctypes.byref(h))
+        if rc != 0:
+            raise TTError(rc, "tt_op_create_burgers_hopf failed")
+        self.h = h
+
+    def ranks(self):
+        r = np.zeros(self.d + 1, dtype=np.int32)
+        lib().tt_op_get_ranks(self.h, _ip(r))
+        return [int(v) for v in r]
+
+    def coefficients(self):
+        b = np.zeros(self.d**3)
+        dm = np.zeros(self.d**2)
+        lib().tt_op_export_coefficients(self.h, _dp(b), _dp(dm))
+        return b.reshape(self.d, self.d, self.d), dm.reshape(self.d, self.d)
+
+    def local_ops(self):
+        nops = ctypes.c_int()
+        lib().tt_op_export_local_ops(self.h, ctypes.byref(nops), None)
+        m = np.zeros(nops.value * self.n * self.n)
+        lib().tt_op_export_local_ops(self.h, ctypes.byref(nops), _dp(m))
+        return m.reshape(nops.value, self.n, self.n)
+
+    def site(self, m):
+        cnt = ctypes.c_int()
+        lib().tt_op_export_site(self.h, m, ctypes.byref(cnt), None, None, None, None)
+        k = cnt.value
+        a, b, o = (np.zeros(k, dtype=np.int32) for _ in range(3))
+        c = np.zeros(2 * k)
+        lib().tt_op_export_site(self.h, m, ctypes.byref(cnt), _ip(a), _ip(b), _ip(o), _dp(c))
+        return a, b, o, c[0::2] + 1j * c[1::2]
+
+    def close(self):
+        if self.h:
+            lib().tt_op_destroy(self.h)
+            self.h = None
+
+
+def tt_apply(ctx, op, x, y, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0):
+    o = ApplyOpts(ctypes.sizeof(ApplyOpts), mode, sketch_rank, 0, seed)
+    ctx.check(lib().tt_apply(ctx.h, op.h, x.h, y.h, ctypes.byref(o)))
+
+
+def tt_axpy(ctx, alpha, x, beta, y, z):
+    a, b = complex(alpha), complex(beta)
+    ctx.check(lib().tt_axpy(ctx.h, a.real, a.imag, x.h, b.real, b.imag, y.h, z.h))
+
+
+def tt_sum(ctx, coefs, xs, z):
+    c = np.zeros(2 * len(xs))
+    for t, v in enumerate(coefs):
+        c[2 * t], c[2 * t + 1] = complex(v).real, complex(v).imag
+    ptrs = (P * len(xs))(*[x.h.value for x in xs])
+    ctx.check(lib().tt_sum(ctx.h, len(xs), _dp(c), ptrs, z.h))
+
+
+def tt_round(ctx, x, eps, rmax=0, report=True):
+    rep = RoundReport()
+    ctx.check(lib().tt_round(ctx.h, x.h, float(eps), int(rmax), ctypes.byref(rep) if report else None))
+    if not report:
+        return None
+    d = rep.d
+    return {
+        "ranks": list(rep.ranks[: d + 1]),
+        "tail": list(rep.tail[: max(d - 1, 0)]),
+        "sigma_min_kept": list(rep.sigma_min_kept[: max(d - 1, 0)]),
+        "norm": rep.norm,
+        "jacobi_sweeps_max": rep.jacobi_sweeps_max,
+    }
+
+
+def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0):
+    o = StepOpts(ctypes.sizeof(StepOpts), int(rmax), float(eps), int(mode), int(sketch_rank), int(seed))
+    rep = StepReport()
+    ctx.check(lib().tt_step(ctx.h, op.h, f.h, float(dt), ctypes.byref(o), ctypes.byref(rep)))
+    return {"stages": rep.stages, "max_rank": rep.max_rank, "ranks": list(rep.ranks[: f.d + 1])}
+
+
+def tt_eval(ctx, x, idx, out):
+    """idx: torch int32 (npts, d) on the device; out: torch complex128 (npts,)."""
+    ctx.check(lib().tt_eval(ctx.h, x.h, P(idx.data_ptr()), int(idx.shape[0]), P(out.data_ptr())))
+
+
+def tt_zgemm(ctx, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch=1):
+    """Device GEMM on torch complex128 buffers A, B, C (column-major views)."""
+    a, b = complex(alpha), complex(beta)
+    ctx.check(lib().tt_zgemm(ctx.h, opA, opB, M, N, K, a.real, a.imag, P(A.data_ptr()), lda, sA,
+                             P(B.data_ptr()), ldb, sB, b.real, b.imag, P(C.data_ptr()), ldc, sC, batch))
+
+
+def tt_norm(ctx, x):
+    v = D()
+    ctx.check(lib().tt_norm(ctx.h, x.h, ctypes.byref(v)))
+    return v.value

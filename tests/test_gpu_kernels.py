@@ -1,0 +1,179 @@
+"""GPU unit checks of the library's building blocks against numpy / the
+oracle (all through the C ABI)."""
+import numpy as np
+import pytest
+
+from gpu_util import full, make_ctx, rel, upload
+from oracle import fullgrid, galerkin, tt_ref
+from paper_2403_04946_amd import inputs, tt
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = make_ctx()
+    yield c
+    c.sync()
+    c.close()
+
+
+def _mat(rng, rows, cols):
+    return rng.standard_normal((rows, cols)) + 1j * rng.standard_normal((rows, cols))
+
+
+def _op(x, o):
+    return x if o == 0 else (x.T if o == 1 else x.conj().T)
+
+
+@pytest.mark.parametrize(
+    "M,N,K,batch",
+    [(1, 1, 1, 1), (17, 33, 5, 1), (64, 64, 16, 1), (65, 130, 47, 3), (20, 30, 5000, 1), (130, 7, 900, 2),
+     (8, 200, 0, 1)],
+)
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (2, 0), (0, 1), (0, 2), (2, 2)])
+def test_zgemm_against_numpy(ctx, M, N, K, batch, opa, opb):
+    import torch
+
+    rng = np.random.default_rng(M * 1000 + N * 10 + K + opa * 7 + opb)
+    As, Bs, Cs = [], [], []
+    for _ in range(batch):
+        As.append(_mat(rng, M, K) if opa == 0 else _mat(rng, K, M))
+        Bs.append(_mat(rng, K, N) if opb == 0 else _mat(rng, N, K))
+        Cs.append(_mat(rng, M, N))
+    alpha, beta = 0.7 - 0.3j, -0.4 + 0.2j
+    ref = [alpha * _op(a, opa) @ _op(b, opb) + beta * c for a, b, c in zip(As, Bs, Cs)]
+    dev = lambda arrs: torch.from_numpy(np.concatenate([a.ravel(order="F") for a in arrs])).cuda()
+    A, B, C = dev(As), dev(Bs), dev(Cs)
+    lda, ldb = As[0].shape[0], Bs[0].shape[0]
+    tt.tt_zgemm(ctx, opa, opb, M, N, K, alpha, A, max(lda, 1), As[0].size, B, max(ldb, 1), Bs[0].size, beta, C, M,
+                M * N, batch)
+    got = C.cpu().numpy()
+    for b in range(batch):
+        g = got[b * M * N:(b + 1) * M * N].reshape((M, N), order="F")
+        assert np.abs(g - ref[b]).max() <= 1e-13 * max(1.0, np.sqrt(K)) * (np.abs(ref[b]).max() + 1)
+
+
+def test_set_get_roundtrip_and_eval(ctx):
+    import torch
+
+    x = inputs.random_tt(4, 8, [1, 3, 5, 2, 1], 0)
+    t = upload(ctx, x, caps=6)
+    back = t.get_cores()
+    for a, b in zip(x, back):
+        assert np.array_equal(a, b)
+    idx = inputs.random_points(4, 8, 300, 1)
+    out = torch.zeros(300, dtype=torch.complex128, device="cuda")
+    tt.tt_eval(ctx, t, torch.from_numpy(idx).cuda(), out)
+    ref = tt_ref.tt_eval(x, idx)
+    assert np.abs(out.cpu().numpy() - ref).max() < 1e-14 * np.abs(ref).max() * 10
+
+
+def test_gaussian_initial_condition(ctx):
+    d, n, length = 4, 16, 4.0
+    mu, sig = inputs.ic_params(d, 0)
+    t = tt.Tensor(ctx, d, n, 2)
+    t.set_gaussian(mu, sig, length)
+    assert rel(full(t), fullgrid.gaussian_ic(mu, sig, n, length)) < 1e-15
+
+
+def test_axpy_and_sum(ctx):
+    x = inputs.random_tt(4, 6, 3, 2)
+    y = inputs.random_tt(4, 6, [1, 2, 4, 1, 1], 3)
+    w = inputs.random_tt(4, 6, 2, 4)
+    tx, ty, tw = upload(ctx, x), upload(ctx, y), upload(ctx, w)
+    z = tt.Tensor(ctx, 4, 6, 12)
+    tt.tt_axpy(ctx, 0.5 - 1j, tx, 2.0, ty, z)
+    assert z.ranks() == [1, 5, 7, 4, 1]
+    assert rel(full(z), (0.5 - 1j) * full(tx) + 2.0 * full(ty)) < 1e-14
+    tt.tt_sum(ctx, [1.0, -0.5, 0.25j], [tx, ty, tw], z)
+    assert rel(full(z), full(tx) - 0.5 * full(ty) + 0.25j * full(tw)) < 1e-14
+
+
+@pytest.mark.parametrize("eps,cap", [(0.0, 0), (1e-12, 0), (1e-3, 0), (0.0, 3)])
+def test_round_matches_oracle(ctx, eps, cap):
+    x = tt_ref.tt_add(inputs.random_tt(5, 6, 3, 5), inputs.random_tt(5, 6, 4, 6), 1.0, 0.01)
+    t = upload(ctx, x, caps=8)
+    rep = tt.tt_round(ctx, t, eps, cap)
+    ref, info = tt_ref.tt_round(x, eps, cap if cap > 0 else None)
+    assert t.ranks() == tt_ref.tt_ranks(ref)
+    assert rel(full(t), fullgrid.tt_to_full(ref)) < 1e-11
+    # left-orthonormal output cores
+    for c in t.get_cores()[:-1]:
+        v = c.reshape(-1, c.shape[2], order="F")
+        assert np.abs(v.conj().T @ v - np.eye(v.shape[1])).max() < 1e-12
+    assert abs(rep["norm"] - info["norm"]) < 1e-12 * info["norm"]
+
+
+def test_round_rank_deficient_inputs(ctx):
+    x = inputs.random_tt(5, 6, 3, 7)
+    tx = upload(ctx, x, caps=8)
+    z = tt.Tensor(ctx, 5, 6, 8)
+    tt.tt_axpy(ctx, 1.0, tx, 1.0, tx, z)  # 2x at double rank: exactly rank-deficient
+    tt.tt_round(ctx, z, 1e-12, 0)
+    assert max(z.ranks()) <= 3
+    assert rel(full(z), 2 * fullgrid.tt_to_full(x)) < 1e-12
+    # exact cancellation: x - x rounds to (numerically) zero
+    tt.tt_axpy(ctx, 1.0, tx, -1.0, tx, z)
+    tt.tt_round(ctx, z, 1e-12, 0)
+    assert np.abs(full(z)).max() < 1e-12 * np.abs(fullgrid.tt_to_full(x)).max()
+
+
+def test_round_wide_first_core(ctx):
+    # first-core rank above n: the phase-2 factor is wide
+    x = tt_ref.tt_add(inputs.random_tt(3, 4, 5, 8), inputs.random_tt(3, 4, 5, 9))
+    t = upload(ctx, x, caps=12)
+    tt.tt_round(ctx, t, 1e-13, 0)
+    assert t.ranks()[1] <= 4
+    assert rel(full(t), fullgrid.tt_to_full(x)) < 1e-12
+
+
+@pytest.mark.parametrize("d,n,ranks", [(4, 8, [1, 2, 3, 2, 1]), (3, 6, [1, 1, 1, 1]), (5, 5, [1, 2, 2, 2, 2, 1])])
+def test_apply_exact_matches_oracle_operator(ctx, d, n, ranks):
+    length, nu = 4.0, 0.05
+    op = tt.Operator(ctx, d, n, length, nu)
+    R = op.ranks()
+    x = inputs.random_tt(d, n, ranks, 10)
+    tx = upload(ctx, x)
+    ty = tt.Tensor(ctx, d, n, [R[k] * ranks[k] for k in range(d + 1)])
+    tt.tt_apply(ctx, op, tx, ty, tt.TT_APPLY_EXACT)
+    prob = fullgrid.Problem(galerkin.coefficient_B(d), galerkin.coefficient_D(d), nu, n, length)
+    assert rel(full(ty), prob.apply(fullgrid.tt_to_full(x))) < 1e-13
+    op.close()
+
+
+@pytest.mark.parametrize("d,n,ranks,ell", [(4, 8, [1, 2, 3, 2, 1], 40), (5, 6, [1, 2, 2, 2, 2, 1], 30)])
+def test_apply_sketch_is_exact_when_wide_enough(ctx, d, n, ranks, ell):
+    length, nu = 4.0, 0.05
+    op = tt.Operator(ctx, d, n, length, nu)
+    x = inputs.random_tt(d, n, ranks, 11)
+    tx = upload(ctx, x)
+    ty = tt.Tensor(ctx, d, n, ell)
+    tt.tt_apply(ctx, op, tx, ty, tt.TT_APPLY_SKETCH, sketch_rank=ell, seed=5)
+    assert ty.orth() == "right"
+    prob = fullgrid.Problem(galerkin.coefficient_B(d), galerkin.coefficient_D(d), nu, n, length)
+    assert rel(full(ty), prob.apply(fullgrid.tt_to_full(x))) < 1e-11
+    # right-orthonormal cores 2..d
+    for c in ty.get_cores()[1:]:
+        h = c.reshape(c.shape[0], -1, order="F")
+        assert np.abs(h @ h.conj().T - np.eye(h.shape[0])).max() < 1e-10
+    op.close()
+
+
+def test_norm(ctx):
+    x = inputs.random_tt(5, 6, 4, 12)
+    t = upload(ctx, x)
+    assert abs(tt.tt_norm(ctx, t) - np.linalg.norm(fullgrid.tt_to_full(x))) < 1e-13 * np.linalg.norm(
+        fullgrid.tt_to_full(x))
+
+
+def test_errors_are_reported(ctx):
+    x = upload(ctx, inputs.random_tt(4, 6, 3, 13))
+    small = tt.Tensor(ctx, 4, 6, 2)
+    with pytest.raises(tt.TTError) as e:
+        tt.tt_axpy(ctx, 1.0, x, 1.0, x, small)
+    assert e.value.code == -3
+    other = tt.Tensor(ctx, 3, 6, 4)
+    with pytest.raises(tt.TTError) as e:
+        tt.tt_axpy(ctx, 1.0, x, 1.0, other, small)
+    assert e.value.code == -2

@@ -1,0 +1,99 @@
+"""Host-side checks of the HIP library (no GPU needed): the shared library
+loads, exports every entry point of include/tt_fde.h, and its operator
+builder agrees with the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import fd, fullgrid, galerkin
+from paper_2403_04946_amd import tt
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "tt_fde.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void\*|void|const char\*)\s+(tt_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 25
+    h = tt.lib()
+    missing = [n for n in names if not hasattr(h, n)]
+    assert not missing, missing
+    assert set(names) == set(tt.exported_symbols())
+
+
+@pytest.mark.parametrize("d", [4, 7, 20])
+def test_coefficients_match_oracle(d):
+    op = tt.Operator(None, d, 8, 4.0, 0.05)
+    b, dm = op.coefficients()
+    assert np.abs(b - galerkin.coefficient_B(d)).max() < 1e-14 * d
+    assert np.abs(dm - galerkin.coefficient_D(d)).max() < 1e-14 * np.abs(dm).max()
+    op.close()
+
+
+def test_local_operators_match_oracle():
+    n, length = 9, 3.0
+    op = tt.Operator(None, 3, n, length, 0.1)
+    mats = op.local_ops()
+    x = fd.position(n, length)
+    g = fd.first_derivative(n, length)
+    l2 = fd.second_derivative(n, length)
+    ref = [np.eye(n), x, g, l2, x @ g, x @ l2]
+    for o in range(6):
+        assert np.abs(mats[o] - ref[o]).max() < 1e-12, o
+    op.close()
+
+
+def mpo_dense(op, n):
+    """Contract the exported automaton into the dense n^d x n^d matrix."""
+    d = op.d
+    mats = op.local_ops()
+    R = op.ranks()
+    full = np.ones((1, 1, 1), dtype=np.complex128)  # (rows, cols, bond)
+    for m in range(d):
+        a, b, o, c = op.site(m)
+        w = np.zeros((R[m], R[m + 1], n, n), dtype=np.complex128)
+        for ai, bi, oi, ci in zip(a, b, o, c):
+            w[ai, bi] += ci * mats[oi]
+        full = np.einsum("xya,abij->xiyjb", full, w).reshape(full.shape[0] * n, full.shape[1] * n, R[m + 1])
+    return full[:, :, 0]
+
+
+@pytest.mark.parametrize("d,n,nu", [(4, 5, 0.05), (5, 4, 0.0), (3, 6, 0.3)])
+def test_operator_automaton_matches_oracle_operator(d, n, nu):
+    length = 4.0
+    op = tt.Operator(None, d, n, length, nu)
+    R = op.ranks()
+    assert R[0] == 1 and R[d] == 1 and max(R) <= 2 * d + 2
+    dense = mpo_dense(op, n)
+    prob = fullgrid.Problem(galerkin.coefficient_B(d), galerkin.coefficient_D(d), nu, n, length)
+    rng = np.random.default_rng(0)
+    f = rng.standard_normal((n,) * d) + 1j * rng.standard_normal((n,) * d)
+    ref = prob.apply(f).ravel()
+    got = dense @ f.ravel()
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    op.close()
+
+
+def test_operator_ranks_at_benchmark_size():
+    op = tt.Operator(None, 50, 128, 8.0, 0.01)
+    R = op.ranks()
+    assert R[0] == R[50] == 1 and max(R) <= 102
+    op.close()
+
+
+def test_invalid_arguments_are_rejected_without_a_device():
+    h = tt.lib()
+    out = ctypes.c_void_p()
+    assert h.tt_op_create_burgers_hopf(None, 0, 8, 4.0, 0.1, ctypes.byref(out)) == -1
+    assert h.tt_op_create_burgers_hopf(None, 4, 2, 4.0, 0.1, ctypes.byref(out)) == -1
+    assert h.tt_op_create_burgers_hopf(None, 4, 8, -1.0, 0.1, ctypes.byref(out)) == -1
+    assert h.tt_tensor_create(None, 4, 8, None, ctypes.byref(out)) == -1
+    assert h.tt_round(None, None, 0.0, 0, None) == -1
+    assert h.tt_ctx_sync(None) == -1
