@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""RK4 stages/s of the TT step-truncation solver for the Burgers-Hopf
+characteristic-function PDE on one MI355X.
+
+Workload (the metric's configuration): d = 50 Fourier modes, n = 128 grid
+points per mode on [-8, 8], nu = 0.01, rank cap 64, relative truncation
+tolerance 1e-6, dt = 2e-4, plain complex FP64 arithmetic.  Timing uses the
+saturated regime: the input is a seeded random TT with every interior rank
+at the cap (64), so every stage runs at the worst-case shapes of the
+configuration.  One step = one RK4 step-truncation step (4 stages: four
+sketched operator applications, their truncations, the stage combinations
+and their truncations) followed by a pointwise read-out of 1024 entries.
+
+Prints one JSON line.  `value` is stages per second (4 per step) over the
+timed steps, with the input resident in device memory.  `roofline` reports
+the dominant kernel class, its algorithmic FLOP count divided by its
+HIP-event-timed duration, against the FP64 matrix peak.  `cpu_baseline` is
+the CPU oracle (full-grid RK4 step-truncation) on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+D, N, LEN, NU, CAP, EPS, DT = 50, 128, 8.0, 0.01, 64, 1e-6, 2e-4
+PEAK_F64_MFMA_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def cpu_baseline(seconds_target=20.0):
+    """The CPU oracle timed on this host: full-grid truncation-aware RK4 at
+    d = 4, n = 32 (the d = 50 grid has 128^50 points and cannot be formed)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import fullgrid, galerkin
+    from paper_2403_04946_amd import inputs
+
+    d, n, length, nu = 4, 32, 4.0, 0.05
+    prob = fullgrid.Problem(galerkin.coefficient_B(d), galerkin.coefficient_D(d), nu, n, length)
+    mu, sig = inputs.ic_params(d, 0)
+    f = fullgrid.gaussian_ic(mu, sig, n, length)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        f = fullgrid.truncated_rk4_step(f, 1e-3, prob.apply, 1e-12, 8)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds_target or steps >= 50:
+            break
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    assert np.isfinite(f).all()
+    return {
+        "value": 4.0 * steps / el,
+        "unit": "RK stages/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"{steps} full-grid RK4 step-truncation steps (cap 8, eps 1e-12) at d=4, n=32 "
+                   f"({el:.1f} s); the d=50, n=128 grid (128^50 points) cannot be formed on a CPU"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sketch-rank", type=int, default=80)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2403_04946_amd import inputs, tt
+
+    torch.cuda.init()
+    ctx = tt.Context(0)
+    op = tt.Operator(ctx, D, N, LEN, NU)
+    f = tt.Tensor(ctx, D, N, CAP)
+    f.set_cores(inputs.random_tt(D, N, CAP, 0))
+    idx = torch.from_numpy(inputs.random_points(D, N, 1024, 1)).cuda()
+    out = torch.empty(1024, dtype=torch.complex128, device="cuda")
+    ell = args.sketch_rank
+    seed = 12345
+
+    def step():
+        rep = tt.tt_step(ctx, op, f, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, seed)
+        tt.tt_eval(ctx, f, idx, out)
+        return rep
+
+    for _ in range(args.warmup):
+        step()
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ctx.set_profiling(True)
+    stream = ctx.torch_stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    rep = None
+    for _ in range(args.steps):
+        rep = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = e0.elapsed_time(e1)
+    ctx.set_profiling(False)
+    kernels = {k: ctx.stats(k) for k in ("zgemm", "gather", "cholqr", "jacobi", "concat", "eval", "apply_exact")}
+    assert torch.isfinite(out.real).all() and torch.isfinite(out.imag).all()
+
+    stages = 4 * args.steps
+    value = stages / (ms / 1e3)
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    g = kernels["zgemm"]
+    roof = {
+        "kernel": "zgemm",
+        "bound": "mfma",
+        "achieved": g["flops"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0,
+        "peak": PEAK_F64_MFMA_TFLOPS,
+        "unit": "TFLOP/s",
+        "traffic": None,
+    }
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    result = {
+        "metric": "RK stages/sec at d=50,n=128,r<=64 vs plain FP64 at rel-L2 err <=1e-5",
+        "value": value,
+        "unit": "RK stages/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "Burgers-Hopf TT RK4 step-truncation, plain complex FP64, saturated ranks",
+            "d": D, "n": N, "L": LEN, "nu": NU, "rank_cap": CAP, "eps": EPS, "dt": DT,
+            "apply": f"sketched (width {ell})", "input": "seeded random TT, all interior ranks 64",
+        },
+        "roofline": roof,
+        "kernels_ms": {k: round(v["ms"], 3) for k, v in kernels.items()},
+        "dominant_kernel": dom,
+        "wall_s": wall,
+        "final_ranks_max": max(f.ranks()),
+        "step_max_rank": rep["max_rank"] if rep else None,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

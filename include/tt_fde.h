@@ -123,6 +123,11 @@ int tt_tensor_set_gaussian(tt_ctx* ctx, tt_tensor* t, const double* mu,
  * L2, XG) whose bond dimension is at most 2d + 2.  ctx may be NULL: the
  * operator is then host-only (usable with the export calls below). */
 int tt_op_create_burgers_hopf(tt_ctx* ctx, int d, int n, double L, double nu, tt_op** out);
+/* Same with the advective (B) term multiplied by `advection` (1 gives the
+ * Burgers-Hopf operator, 0 the viscous-only operator whose exact
+ * semi-discrete solution is known in closed form). */
+int tt_op_create_burgers_hopf_scaled(tt_ctx* ctx, int d, int n, double L, double nu,
+                                     double advection, tt_op** out);
 int tt_op_destroy(tt_op* op);
 /* Bond dimensions R[0..d] of the operator's TT-matrix form. */
 int tt_op_get_ranks(const tt_op* op, int* R);

@@ -131,56 +131,57 @@ void copy_d2d(tt_ctx* ctx, zc* dst, const zc* src, size_t elems) {
   TTF_HIP(hipMemcpyAsync(dst, src, elems * sizeof(zc), hipMemcpyDeviceToDevice, ctx->stream));
 }
 
-// ------------------------------------------------ shifted CholeskyQR3
-// QR form.  The logical input is A (m x k) stored at `a` with leading
-// dimension lda, or, when `ct` is set, A = S^H for S (k x m) stored at `a`.
-// On exit q (m x k, ld m) has orthonormal columns (up to null directions of
-// A, which come out with negligible weight) and r (k x k, ld k) is upper
-// triangular with A = q r.
-void cholqr3(tt_ctx* ctx, int m, int k, const zc* a, long lda, bool ct, zc* q, zc* r) {
-  zc* G = (zc*)ctx->get_ws("cq_g", sizeof(zc) * k * k);
-  zc* Rp = (zc*)ctx->get_ws("cq_r", sizeof(zc) * k * k);
-  zc* Ri = (zc*)ctx->get_ws("cq_ri", sizeof(zc) * k * k);
-  zc* Rt = (zc*)ctx->get_ws("cq_rt", sizeof(zc) * k * k);
-  zc* Qt = (zc*)ctx->get_ws("cq_qt", sizeof(zc) * (size_t)m * k);
-  const double s1 = 11.0 * ((double)m * k + (double)k * (k + 1)) * U_ROUND;
-  const double fl = (double)k * U_ROUND;
-  // pass 1 on the input
-  if (!ct)
-    zgemm(ctx, OPC, OPN, k, k, m, Z(1), a, lda, 0, a, lda, 0, Z(0), G, k, 0);
-  else  // A^H A = S S^H
-    zgemm(ctx, OPN, OPC, k, k, m, Z(1), a, lda, 0, a, lda, 0, Z(0), G, k, 0);
-  chol_inv(ctx, k, G, r, Ri, s1, 0.0);
-  // Q1 = A R^{-1}; pass 1 writes Qt when three passes follow so the last
-  // pass lands in q
-  if (!ct)
-    zgemm(ctx, OPN, OPN, m, k, k, Z(1), a, lda, 0, Ri, k, 0, Z(0), Qt, m, 0);
-  else
-    zgemm(ctx, OPC, OPN, m, k, k, Z(1), a, lda, 0, Ri, k, 0, Z(0), Qt, m, 0);
-  const zc* src = Qt;
-  for (int pass = 2; pass <= 3; ++pass) {
-    zc* dst = (pass == 2) ? q : Qt;  // pass 2 writes q, pass 3 writes Qt
-    zgemm(ctx, OPC, OPN, k, k, m, Z(1), src, m, 0, src, m, 0, Z(0), G, k, 0);
-    chol_inv(ctx, k, G, Rp, Ri, 0.0, fl);
-    zgemm(ctx, OPN, OPN, m, k, k, Z(1), src, m, 0, Ri, k, 0, Z(0), dst, m, 0);
-    // r <- Rp r
-    zgemm(ctx, OPN, OPN, k, k, k, Z(1), Rp, k, 0, r, k, 0, Z(0), Rt, k, 0);
-    copy_d2d(ctx, r, Rt, (size_t)k * k);
-    src = dst;
+// ------------------------------------------------------------- TSQR
+// Householder TSQR of the m x k matrix held in q (ld m, m >= k), in place:
+// q becomes the explicit Q factor and r (k x k, ld k) the R factor.  Row
+// blocks of bl rows are factored by separate workgroups; their stacked R
+// factors (P k x k) are factored recursively; each block's Q is then
+// multiplied by its k x k block of the stacked factor's Q (batched GEMM).
+void tsqr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level) {
+  require(m >= k && k >= 1, TT_EINVAL, "tsqr: need m >= k >= 1");
+  const int bmax = hh_max_rows();
+  if (m <= bmax && (m <= 2 * k || m <= 256)) {
+    hh_leaves(ctx, q, m, m, 1, m, k, r, k, 0);
+    return;
   }
-  copy_d2d(ctx, q, Qt, (size_t)m * k);
+  int bl = std::min(std::max(2 * k, 128), bmax - k);
+  require(bl >= k, TT_EINVAL, "tsqr: rank too large for the leaf size");
+  int P = m / bl;  // the last leaf takes bl + (m mod bl) < bl + bl rows
+  if (m - (P - 1) * bl > bmax) P += 1;  // then the last leaf is short but >= k? ensured below
+  int last = m - (P - 1) * bl;
+  if (last < k) {
+    P -= 1;
+    last += bl;
+  }
+  require(P >= 1 && last >= k && last <= bmax, TT_EINVAL, "tsqr: cannot partition rows");
+  if (P == 1) {
+    hh_leaves(ctx, q, m, m, 1, m, k, r, k, 0);
+    return;
+  }
+  const long Sm = (long)P * k;
+  zc* S = (zc*)ctx->get_ws("tsqr_S" + std::to_string(level), sizeof(zc) * Sm * k);
+  zc* T = (zc*)ctx->get_ws("tsqr_T" + std::to_string(level), sizeof(zc) * (size_t)m * k);
+  hh_leaves(ctx, q, m, bl, P, m, k, S, Sm, k);
+  tsqr_inplace(ctx, (int)Sm, k, S, r, level + 1);
+  // block i of Q <- Q_i * S[i k : (i+1) k, :]
+  if (P > 1)
+    zgemm(ctx, OPN, OPN, bl, k, k, Z(1), q, m, bl, S, Sm, k, Z(0), T, m, bl, P - 1);
+  zgemm(ctx, OPN, OPN, last, k, k, Z(1), q + (long)(P - 1) * bl, m, 0, S + (long)(P - 1) * k, Sm, 0, Z(0),
+        T + (long)(P - 1) * bl, m, 0);
+  copy_d2d(ctx, q, T, (size_t)m * k);
 }
 
-// LQ form: A (k x m, ld lda) = L Q with Q (k x m, ld k) row-orthonormal and
-// returned R (k x k upper) such that L = R^H.
-void cholqr3_lq(tt_ctx* ctx, int k, int m, const zc* a, long lda, zc* q, zc* r) {
-  // A^H = Q' R  =>  A = R^H Q'^H ; run the QR form on S = A via ct
-  zc* qt = (zc*)ctx->get_ws("lq_qt", sizeof(zc) * (size_t)m * k);
-  cholqr3(ctx, m, k, a, lda, true, qt, r);
-  // q = qt^H (k x m): conjugate transpose via GEMM with the identity
-  zc* I = (zc*)ctx->get_ws("lq_eye", sizeof(zc) * (size_t)k * k);
-  set_identity(ctx, I, k, k, k);
-  zgemm(ctx, OPN, OPC, k, m, k, Z(1), I, k, 0, qt, m, 0, Z(0), q, k, 0);
+// QR of A (m x k, ld lda, m >= k): Q (m x k, ld m), R (k x k, ld k).
+void tsqr(tt_ctx* ctx, int m, int k, const zc* a, long lda, zc* q, zc* r) {
+  copy_matrix(ctx, a, lda, q, m, m, k);
+  tsqr_inplace(ctx, m, k, q, r, 0);
+}
+
+// LQ of A (k x m, ld lda, k <= m): A = R^H Qt^H with Qt (m x k, ld m) having
+// orthonormal columns; returns Qt and R (k x k upper).
+void tsqr_lq(tt_ctx* ctx, int k, int m, const zc* a, long lda, zc* qt, zc* r) {
+  conj_transpose(ctx, a, lda, qt, m, k, m);
+  tsqr_inplace(ctx, m, k, qt, r, 0);
 }
 
 int bounded_pow(int n, int e, int cap) {
@@ -206,10 +207,10 @@ void phase1_right_orth(tt_ctx* ctx, tt_tensor* x) {
       identity_core(ctx, x->core[c], n, p1);
       r[c] = N;
     } else {
-      zc* q = (zc*)ctx->get_ws("ph1_q", sizeof(zc) * (size_t)p0 * N);
+      zc* qt = (zc*)ctx->get_ws("ph1_q", sizeof(zc) * (size_t)p0 * N);
       zc* R = (zc*)ctx->get_ws("ph1_r", sizeof(zc) * (size_t)p0 * p0);
-      cholqr3_lq(ctx, p0, N, x->core[c], p0, q, R);
-      copy_d2d(ctx, x->core[c], q, (size_t)p0 * N);
+      tsqr_lq(ctx, p0, N, x->core[c], p0, qt, R);
+      conj_transpose(ctx, qt, N, x->core[c], p0, N, p0);  // C_c <- Qt^H
       // C_{c-1} <- C_{c-1} L, L = R^H
       zgemm(ctx, OPN, OPC, rl * n, p0, p0, Z(1), x->core[c - 1], (long)rl * n, 0, R, p0, 0, Z(0), tmp,
             (long)rl * n, 0);
@@ -276,14 +277,12 @@ void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_repo
     zc* tmp = (zc*)ctx->get_ws("p2_tmp", sizeof(zc) * (size_t)sq * n * rr);
     const zc* V = x->core[c];
     if (m >= k) {
-      cholqr3(ctx, m, k, V, m, false, Q, R);
+      tsqr(ctx, m, k, V, m, Q, R);
       copy_d2d(ctx, B, R, (size_t)k * k);
     } else {
       // V^H (k x m) = Q' R' ; SVD of R'^H gives the left vectors of V
-      cholqr3(ctx, k, m, V, m, true, Q, R);
-      zc* I = (zc*)ctx->get_ws("p2_eye", sizeof(zc) * (size_t)m * m);
-      set_identity(ctx, I, m, m, m);
-      zgemm(ctx, OPN, OPC, m, m, m, Z(1), I, m, 0, R, m, 0, Z(0), B, m, 0);  // B = R'^H
+      tsqr_lq(ctx, m, k, V, m, Q, R);
+      conj_transpose(ctx, R, m, B, m, m, m);  // B = R'^H
     }
     jacobi_svd(ctx, sq, sq, B, U, sig, sw);
     double* h = (double*)ctx->host_scratch(sizeof(double) * (sq + 8));
@@ -417,11 +416,12 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
     const int N = n * sp;
     // M = S_m Z  (l_m x n s_{m+1})
     zgemm(ctx, OPN, OPN, lm, N, r0 * R0, Z(1), S + sk_off[m], lm, 0, W, (long)r0 * R0, 0, Z(0), M, lm, 0);
-    cholqr3_lq(ctx, lm, N, M, lm, Qm, Rm);
-    copy_d2d(ctx, y->core[m], Qm, (size_t)lm * N);
+    // M = R^H Qt^H: the new core is Qt^H (right-orthonormal rows)
+    tsqr_lq(ctx, lm, N, M, lm, Qm, Rm);
+    conj_transpose(ctx, Qm, N, y->core[m], lm, N, lm);
     s[m] = lm;
-    // P_m = Z Q^H  ((r0 R0) x l_m), layout [a, alpha, q]
-    zgemm(ctx, OPN, OPC, r0 * R0, lm, N, Z(1), W, (long)r0 * R0, 0, Qm, lm, 0, Z(0), P2, (long)r0 * R0, 0);
+    // P_m = Z Q^H = Z Qt  ((r0 R0) x l_m), layout [a, alpha, q]
+    zgemm(ctx, OPN, OPN, r0 * R0, lm, N, Z(1), W, (long)r0 * R0, 0, Qm, N, 0, Z(0), P2, (long)r0 * R0, 0);
     std::swap(P, P2);
   }
   for (int m = 0; m <= d; ++m) y->rank[m] = s[m];
@@ -797,6 +797,11 @@ int tt_tensor_set_gaussian(tt_ctx* ctx, tt_tensor* t, const double* mu, const do
 }
 
 int tt_op_create_burgers_hopf(tt_ctx* ctx, int d, int n, double L, double nu, tt_op** out) {
+  return tt_op_create_burgers_hopf_scaled(ctx, d, n, L, nu, 1.0, out);
+}
+
+int tt_op_create_burgers_hopf_scaled(tt_ctx* ctx, int d, int n, double L, double nu, double advection,
+                                     tt_op** out) {
   if (!out) return TT_EINVAL;
   tt_op* op = nullptr;
   ABI_TRY
@@ -809,6 +814,7 @@ int tt_op_create_burgers_hopf(tt_ctx* ctx, int d, int n, double L, double nu, tt
   op->n = n;
   op->L = L;
   op->nu = nu;
+  op->adv = advection;
   build_burgers_hopf(op);
   if (ctx) upload_op(ctx, op);
   *out = op;

@@ -97,7 +97,7 @@ struct tt_tensor {
 
 struct tt_op {
   int d = 0, n = 0;
-  double L = 0, nu = 0;
+  double L = 0, nu = 0, adv = 1.0;
   std::vector<double> B, D;           // host coefficients
   std::vector<double> grid;           // a_i
   std::vector<int> tap_col;           // [NOPS][n][NTAPS]
@@ -144,10 +144,13 @@ void zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const z
            long lda, long strideA, const zc* B, long ldb, long strideB, zc beta, zc* C,
            long ldc, long strideC, int batch = 1);
 
-// Dense kernels (single workgroup per problem).
-// Cholesky of G (k x k, ld k) with diagonal shift and pivot floor, returning
-// upper R (G + shift I = R^H R) and R^{-1}.  Both k x k, ld k.
-void chol_inv(tt_ctx* ctx, int k, const zc* G, zc* R, zc* Rinv, double shift_rel, double floor_rel);
+// Householder QR of nleaves row blocks of an m x k matrix (ld ldq), in
+// place: each block becomes its explicit Q factor and its R factor (k x k)
+// is written at R + i*strideR with leading dimension ldr.
+void hh_leaves(tt_ctx* ctx, zc* Q, long ldq, int bl, int nleaves, int m, int k, zc* R, long ldr, long strideR);
+int hh_max_rows();
+// dst (k x m, ld ldd) = src (m x k, ld lds)^H
+void conj_transpose(tt_ctx* ctx, const zc* src, long lds, zc* dst, long ldd, int m, int k);
 // One-sided Jacobi SVD of B (m x k, ld m) in place: on exit the columns of B
 // are U * Sigma, sorted by decreasing norm; sigma[k] holds the norms and B
 // is scratch; U (m x k, ld m) receives the normalised columns (zero where

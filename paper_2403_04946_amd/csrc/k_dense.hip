@@ -1,13 +1,5 @@
-// Small dense factorisations used once per TT bond, one workgroup each.
+// Small dense factorisation used once per TT bond, one workgroup each.
 //
-// * chol_inv: Cholesky factor R (upper, G + s I = R^H R) of a Hermitian
-//   Gram matrix and its inverse.  Together with the GEMMs G = A^H A and
-//   Q = A R^{-1} this is one pass of CholeskyQR; three passes with a shift
-//   on the first (shifted CholeskyQR3) give a QR factorisation whose R has
-//   the singular values of A to working accuracy, also for ill-conditioned
-//   or rank-deficient A, while keeping all O(m k^2) work on matrix cores.
-//   It replaces the Householder QR / LQ of the paper's orthogonalisation
-//   and truncation sweeps (App. A.1, Alg. 1 and Alg. 2; App. A.3 TSQR).
 // * jacobi_svd: one-sided (Hestenes) Jacobi SVD of the small square factor
 //   R (the "SVD of the R factor" of App. A.4): columns are rotated pairwise
 //   until orthogonal; their norms are the singular values and the
@@ -17,7 +9,6 @@
 
 namespace ttf {
 
-constexpr int CHOL_THREADS = 512;
 constexpr int CHOL_KMAX = 512;
 
 __device__ inline double wave_sum(double v) {
@@ -35,121 +26,6 @@ __device__ inline double block_sum(double v, double* red) {
   const int nw = blockDim.x >> 6;
   for (int w = 0; w < nw; ++w) s += red[w];
   return s;
-}
-
-// R (k x k, ld k) <- chol(G + shift*tr(G)/k... ) see launcher; Rinv <- R^{-1}
-__global__ __launch_bounds__(CHOL_THREADS) void chol_inv_kernel(int k, const zc* __restrict__ G,
-                                                                zc* __restrict__ R, zc* __restrict__ Rinv,
-                                                                double shift_rel, double floor_rel) {
-  __shared__ double red[CHOL_THREADS / 64];
-  __shared__ double s_inv;
-  __shared__ double dinv[CHOL_KMAX];
-  const int t = threadIdx.x, nt = blockDim.x;
-  // trace
-  double tr = 0;
-  for (int j = t; j < k; j += nt) tr += G[j + (long)k * j].x;
-  tr = block_sum(tr, red);
-  const double shift = shift_rel * tr, floor_v = floor_rel * tr;
-  const double tiny = 1e-300;
-  // copy upper triangle (+ shift on the diagonal), zero the lower one
-  for (long e = t; e < (long)k * k; e += nt) {
-    const int r = (int)(e % k), c = (int)(e / k);
-    zc v = make_double2(0.0, 0.0);
-    if (r <= c) {
-      v = G[e];
-      if (r == c) {
-        v.x += shift;
-        v.y = 0.0;
-      }
-    }
-    R[e] = v;
-  }
-  __syncthreads();
-  for (int j = 0; j < k; ++j) {
-    if (t == 0) {
-      double dj = R[j + (long)k * j].x;
-      if (!(dj > floor_v)) dj = floor_v;  // also catches NaN
-      if (!(dj > tiny)) dj = tiny;
-      const double rjj = sqrt(dj);
-      R[j + (long)k * j] = make_double2(rjj, 0.0);
-      s_inv = 1.0 / rjj;
-      dinv[j] = s_inv;
-    }
-    __syncthreads();
-    const double inv = s_inv;
-    for (int c = j + 1 + t; c < k; c += nt) {
-      zc v = R[j + (long)k * c];
-      R[j + (long)k * c] = make_double2(v.x * inv, v.y * inv);
-    }
-    __syncthreads();
-    const int m = k - j - 1;
-    for (long e = t; e < (long)m * m; e += nt) {
-      const int r = j + 1 + (int)(e % m), c = j + 1 + (int)(e / m);
-      if (r > c) continue;
-      const zc a = R[j + (long)k * r];  // R[j][r]
-      const zc b = R[j + (long)k * c];  // R[j][c]
-      // R[r][c] -= conj(a) * b
-      zc v = R[r + (long)k * c];
-      v.x -= a.x * b.x + a.y * b.y;
-      v.y -= a.x * b.y - a.y * b.x;
-      R[r + (long)k * c] = v;
-    }
-    __syncthreads();
-  }
-  // inverse of the upper-triangular R, one column per wavefront, column
-  // held across lanes (element r in lane r % 64, slot r / 64)
-  const int wave = t >> 6, lane = t & 63, nw = nt >> 6;
-  constexpr int SLOTS = CHOL_KMAX / 64;
-  for (int c = wave; c < k; c += nw) {
-    double xr[SLOTS], xi[SLOTS];
-#pragma unroll
-    for (int q = 0; q < SLOTS; ++q) {
-      const int r = lane + 64 * q;
-      xr[q] = (r == c) ? 1.0 : 0.0;
-      xi[q] = 0.0;
-    }
-    for (int p = c; p >= 0; --p) {
-      const int ql = p >> 6, lp = p & 63;
-      double vr = 0, vi = 0;
-#pragma unroll
-      for (int q = 0; q < SLOTS; ++q)
-        if (q == ql) {
-          vr = xr[q];
-          vi = xi[q];
-        }
-      vr = __shfl(vr, lp, 64);
-      vi = __shfl(vi, lp, 64);
-      const double di = dinv[p];
-      vr *= di;
-      vi *= di;
-#pragma unroll
-      for (int q = 0; q < SLOTS; ++q) {
-        const int r = lane + 64 * q;
-        if (r == p) {
-          xr[q] = vr;
-          xi[q] = vi;
-        } else if (r < p) {
-          const zc a = R[r + (long)k * p];
-          xr[q] -= a.x * vr - a.y * vi;
-          xi[q] -= a.x * vi + a.y * vr;
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < SLOTS; ++q) {
-      const int r = lane + 64 * q;
-      if (r < k) Rinv[r + (long)k * c] = (r <= c) ? make_double2(xr[q], xi[q]) : make_double2(0.0, 0.0);
-    }
-  }
-}
-
-void chol_inv(tt_ctx* ctx, int k, const zc* G, zc* R, zc* Rinv, double shift_rel, double floor_rel) {
-  if (k <= 0) return;
-  if (k > CHOL_KMAX) fail(TT_EINVAL, "chol_inv: rank above the supported maximum of 512");
-  KTimer kt(ctx, "cholqr", 8.0 * k * (double)k * k / 3.0 + 8.0 * k * (double)k * k / 6.0, 48.0 * k * k);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CHOL_THREADS), 0, ctx->stream, k, G, R, Rinv,
-                     shift_rel, floor_rel);
-  TTF_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------ Jacobi SVD

@@ -184,7 +184,7 @@ void build_burgers_hopf(tt_op* op) {
   for (int k = 0; k < d; ++k)
     for (int j = 0; j < d; ++j)
       for (int l = j; l < d; ++l) {
-        const double bjl = op->B[((size_t)k * d + j) * d + l];
+        const double bjl = op->adv * op->B[((size_t)k * d + j) * d + l];
         if (bjl == 0.0) continue;
         // sum over ordered (j,l) of B_kjl d_j d_l = B_kjj d_j^2 + 2 B_kjl d_j d_l (j<l)
         const cplx c = half_i * (j == l ? bjl : 2.0 * bjl);

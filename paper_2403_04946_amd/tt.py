@@ -100,6 +100,7 @@ _SIGS = {
     "tt_tensor_copy": (I, [P, P, P]),
     "tt_tensor_set_gaussian": (I, [P, P, PD, PD, D]),
     "tt_op_create_burgers_hopf": (I, [P, I, I, D, D, ctypes.POINTER(P)]),
+    "tt_op_create_burgers_hopf_scaled": (I, [P, I, I, D, D, D, ctypes.POINTER(P)]),
     "tt_op_destroy": (I, [P]),
     "tt_op_get_ranks": (I, [P, PI]),
     "tt_op_export_coefficients": (I, [P, PD, PD]),
@@ -147,16 +148,17 @@ def _dp(a):
 
 
 class Context:
-    """A device context; work runs on ``stream`` (a torch stream, a raw
-    hipStream_t integer, or None for torch's current stream)."""
+    """A device context.  All library work runs on one HIP stream: ``stream``
+    (a torch stream or a raw hipStream_t integer) or, by default, a dedicated
+    default-priority torch stream (``self.torch_stream``)."""
 
     def __init__(self, device=0, stream=None):
         import torch
 
         if stream is None:
-            stream = torch.cuda.current_stream(device)
+            stream = torch.cuda.Stream(device=device)
+        self.torch_stream = stream if hasattr(stream, "cuda_stream") else None
         handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
-        self._torch_stream = stream
         h = P()
         rc = lib().tt_ctx_create(device, P(handle), ctypes.byref(h))
         if rc != 0:
@@ -169,6 +171,9 @@ class Context:
 
     def sync(self):
         self.check(lib().tt_ctx_sync(self.h))
+
+    def stream_handle(self):
+        return lib().tt_ctx_stream(self.h)
 
     def set_profiling(self, on):
         self.check(lib().tt_ctx_set_profiling(self.h, int(bool(on))))
@@ -240,11 +245,11 @@ class Tensor:
 class Operator:
     """Burgers-Hopf operator; ctx=None builds a host-only operator."""
 
-    def __init__(self, ctx, d, n, length, nu):
+    def __init__(self, ctx, d, n, length, nu, advection=1.0):
         self.ctx, self.d, self.n = ctx, d, n
         h = P()
-        rc = lib().tt_op_create_burgers_hopf(ctx.h if ctx else None, d, n, float(length), float(nu),
-                                             ctypes.byref(h))
+        rc = lib().tt_op_create_burgers_hopf_scaled(ctx.h if ctx else None, d, n, float(length), float(nu),
+                                                    float(advection), ctypes.byref(h))
         if rc != 0:
             raise TTError(rc, "tt_op_create_burgers_hopf failed")
         self.h = h
@@ -323,15 +328,32 @@ def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=
 
 
 def tt_eval(ctx, x, idx, out):
-    """idx: torch int32 (npts, d) on the device; out: torch complex128 (npts,)."""
+    """idx: torch int32 (npts, d) on the device; out: torch complex128 (npts,).
+    Ordered after torch's current stream (which wrote idx) and before it
+    (which reads out)."""
+    import torch
+
+    cur = torch.cuda.current_stream()
+    if ctx.torch_stream is not None:
+        ctx.torch_stream.wait_stream(cur)
     ctx.check(lib().tt_eval(ctx.h, x.h, P(idx.data_ptr()), int(idx.shape[0]), P(out.data_ptr())))
+    if ctx.torch_stream is not None:
+        cur.wait_stream(ctx.torch_stream)
 
 
 def tt_zgemm(ctx, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch=1):
-    """Device GEMM on torch complex128 buffers A, B, C (column-major views)."""
+    """Device GEMM on torch complex128 buffers A, B, C (column-major views),
+    ordered against torch's current stream like tt_eval."""
+    import torch
+
+    cur = torch.cuda.current_stream()
+    if ctx.torch_stream is not None:
+        ctx.torch_stream.wait_stream(cur)
     a, b = complex(alpha), complex(beta)
     ctx.check(lib().tt_zgemm(ctx.h, opA, opB, M, N, K, a.real, a.imag, P(A.data_ptr()), lda, sA,
                              P(B.data_ptr()), ldb, sB, b.real, b.imag, P(C.data_ptr()), ldc, sC, batch))
+    if ctx.torch_stream is not None:
+        cur.wait_stream(ctx.torch_stream)
 
 
 def tt_norm(ctx, x):

@@ -97,3 +97,16 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert h.tt_tensor_create(None, 4, 8, None, ctypes.byref(out)) == -1
     assert h.tt_round(None, None, 0.0, 0, None) == -1
     assert h.tt_ctx_sync(None) == -1
+
+
+def test_viscous_only_operator():
+    d, n, length, nu = 4, 5, 4.0, 0.2
+    op = tt.Operator(None, d, n, length, nu, advection=0.0)
+    assert max(op.ranks()) == 2
+    dense = mpo_dense(op, n)
+    prob = fullgrid.Problem(np.zeros((d, d, d)), galerkin.coefficient_D(d), nu, n, length)
+    rng = np.random.default_rng(1)
+    f = rng.standard_normal((n,) * d) + 1j * rng.standard_normal((n,) * d)
+    ref = prob.apply(f).ravel()
+    assert np.linalg.norm(dense @ f.ravel() - ref) <= 1e-12 * np.linalg.norm(ref)
+    op.close()
