@@ -131,57 +131,86 @@ void copy_d2d(tt_ctx* ctx, zc* dst, const zc* src, size_t elems) {
   TTF_HIP(hipMemcpyAsync(dst, src, elems * sizeof(zc), hipMemcpyDeviceToDevice, ctx->stream));
 }
 
-// ------------------------------------------------------------- TSQR
-// Householder TSQR of the m x k matrix held in q (ld m, m >= k), in place:
-// q becomes the explicit Q factor and r (k x k, ld k) the R factor.  Row
-// blocks of bl rows are factored by separate workgroups; their stacked R
-// factors (P k x k) are factored recursively; each block's Q is then
-// multiplied by its k x k block of the stacked factor's Q (batched GEMM).
-void tsqr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level) {
-  require(m >= k && k >= 1, TT_EINVAL, "tsqr: need m >= k >= 1");
-  const int bmax = hh_max_rows();
-  if (m <= bmax && (m <= 2 * k || m <= 256)) {
-    hh_leaves(ctx, q, m, m, 1, m, k, r, k, 0);
+// ------------------------------------------------------------- QR
+// Householder TSQR of a panel of k <= 32 columns held in q (m x k, ld ldq),
+// in place: q becomes Q, r (ld ldr) the k x k R factor.  P balanced row
+// blocks of at most 256 rows are factored in LDS; their stacked R factors
+// (P k x k, ld P k) are factored recursively and each block of Q is then
+// multiplied by its k x k block of the stacked Q.
+void ptsqr_inplace(tt_ctx* ctx, int m, int k, zc* q, long ldq, zc* r, long ldr, int level) {
+  require(m >= k && k >= 1 && k <= pt_max_cols(), TT_EINVAL, "panel tsqr: bad shape");
+  const int bmax = pt_max_rows();
+  if (m <= bmax) {
+    pt_leaves(ctx, q, ldq, 1, m, k, r, ldr, 0);
     return;
   }
-  int bl = std::min(std::max(2 * k, 128), bmax - k);
-  require(bl >= k, TT_EINVAL, "tsqr: rank too large for the leaf size");
-  int P = m / bl;  // the last leaf takes bl + (m mod bl) < bl + bl rows
-  if (m - (P - 1) * bl > bmax) P += 1;  // then the last leaf is short but >= k? ensured below
-  int last = m - (P - 1) * bl;
-  if (last < k) {
-    P -= 1;
-    last += bl;
-  }
-  require(P >= 1 && last >= k && last <= bmax, TT_EINVAL, "tsqr: cannot partition rows");
-  if (P == 1) {
-    hh_leaves(ctx, q, m, m, 1, m, k, r, k, 0);
-    return;
-  }
+  const int P = (m + bmax - 1) / bmax;  // every block has floor(m / P) > bmax / 2 >= k rows
   const long Sm = (long)P * k;
-  zc* S = (zc*)ctx->get_ws("tsqr_S" + std::to_string(level), sizeof(zc) * Sm * k);
-  zc* T = (zc*)ctx->get_ws("tsqr_T" + std::to_string(level), sizeof(zc) * (size_t)m * k);
-  hh_leaves(ctx, q, m, bl, P, m, k, S, Sm, k);
-  tsqr_inplace(ctx, (int)Sm, k, S, r, level + 1);
-  // block i of Q <- Q_i * S[i k : (i+1) k, :]
-  if (P > 1)
-    zgemm(ctx, OPN, OPN, bl, k, k, Z(1), q, m, bl, S, Sm, k, Z(0), T, m, bl, P - 1);
-  zgemm(ctx, OPN, OPN, last, k, k, Z(1), q + (long)(P - 1) * bl, m, 0, S + (long)(P - 1) * k, Sm, 0, Z(0),
-        T + (long)(P - 1) * bl, m, 0);
-  copy_d2d(ctx, q, T, (size_t)m * k);
+  zc* S = (zc*)ctx->get_ws("ptsqr_S" + std::to_string(level), sizeof(zc) * Sm * k);
+  pt_leaves(ctx, q, ldq, P, m, k, S, Sm, k);
+  ptsqr_inplace(ctx, (int)Sm, k, S, Sm, r, ldr, level + 1);
+  pt_assemble(ctx, q, ldq, m, k, P, S, Sm);
+}
+
+// QR of A (m x k, ld lda, m >= k) by block classical Gram-Schmidt with
+// reorthogonalisation (two projection passes per 32-column panel, each
+// followed by a panel TSQR): Q (m x k, ld m) orthonormal, R (k x k, ld k)
+// upper triangular, A = Q R.  A panel column whose residual after the first
+// projection is below 1e-13 of its norm (a column dependent on the earlier
+// ones, or zero) is replaced by a Gaussian vector before the panel is
+// factored and its R entries below the projection coefficients are zeroed,
+// so Q stays orthonormal for rank-deficient A.
+// The matrix is factored in place: q holds A on entry and Q on exit.
+void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r) {
+  require(m >= k && k >= 1, TT_EINVAL, "qr: need m >= k >= 1");
+  const int NB = pt_max_cols();
+  fill_zero(ctx, r, (long)k * k);
+  // small work: W2, T (k x NB), R1, R2, Rpp, G (NB x NB), flags
+  const size_t kb = (size_t)k * NB, bb = (size_t)NB * NB;
+  zc* W2 = (zc*)ctx->get_ws("bcgs_small", sizeof(zc) * (2 * kb + 4 * bb) + sizeof(int) * NB);
+  zc* T = W2 + kb;
+  zc* R1 = T + kb;
+  zc* R2 = R1 + bb;
+  zc* Rpp = R2 + bb;
+  zc* G = Rpp + bb;
+  int* flags = (int*)(G + bb);
+  for (int p0 = 0; p0 < k; p0 += NB) {
+    const int nb = std::min(NB, k - p0);
+    zc* Ap = q + (long)m * p0;
+    zc* Rp = r + (long)k * p0;  // R[0:p0, p0:p0+nb]
+    if (p0 > 0) {
+      zgemm(ctx, OPC, OPN, p0, nb, m, Z(1), q, m, 0, Ap, m, 0, Z(0), Rp, k, 0);
+      zgemm(ctx, OPN, OPN, m, nb, p0, Z(-1), q, m, 0, Rp, k, 0, Z(1), Ap, m, 0);
+    }
+    zgemm(ctx, OPC, OPN, nb, nb, m, Z(1), Ap, m, 0, Ap, m, 0, Z(0), G, nb, 0);
+    bcgs_flag(ctx, G, nb, Rp, k, p0, flags);
+    bcgs_random(ctx, Ap, m, m, nb, flags, 0x243F6A8885A308D3ull, p0);
+    ptsqr_inplace(ctx, m, nb, Ap, m, R1, nb, 0);
+    if (p0 > 0) {
+      zgemm(ctx, OPC, OPN, p0, nb, m, Z(1), q, m, 0, Ap, m, 0, Z(0), W2, p0, 0);
+      zgemm(ctx, OPN, OPN, m, nb, p0, Z(-1), q, m, 0, W2, p0, 0, Z(1), Ap, m, 0);
+      ptsqr_inplace(ctx, m, nb, Ap, m, R2, nb, 0);
+      zgemm(ctx, OPN, OPN, nb, nb, nb, Z(1), R2, nb, 0, R1, nb, 0, Z(0), Rpp, nb, 0);
+      zgemm(ctx, OPN, OPN, p0, nb, nb, Z(1), W2, p0, 0, R1, nb, 0, Z(0), T, p0, 0);
+      bcgs_masked_add(ctx, Rp, k, T, p0, p0, nb, flags);
+      bcgs_put_diag(ctx, r + (long)k * p0 + p0, k, Rpp, nb, flags);
+    } else {
+      bcgs_put_diag(ctx, r, k, R1, nb, flags);
+    }
+  }
 }
 
 // QR of A (m x k, ld lda, m >= k): Q (m x k, ld m), R (k x k, ld k).
 void tsqr(tt_ctx* ctx, int m, int k, const zc* a, long lda, zc* q, zc* r) {
   copy_matrix(ctx, a, lda, q, m, m, k);
-  tsqr_inplace(ctx, m, k, q, r, 0);
+  bcgs_qr_inplace(ctx, m, k, q, r);
 }
 
 // LQ of A (k x m, ld lda, k <= m): A = R^H Qt^H with Qt (m x k, ld m) having
 // orthonormal columns; returns Qt and R (k x k upper).
 void tsqr_lq(tt_ctx* ctx, int k, int m, const zc* a, long lda, zc* qt, zc* r) {
   conj_transpose(ctx, a, lda, qt, m, k, m);
-  tsqr_inplace(ctx, m, k, qt, r, 0);
+  bcgs_qr_inplace(ctx, m, k, qt, r);
 }
 
 int bounded_pow(int n, int e, int cap) {

@@ -149,6 +149,18 @@ void zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const z
 // is written at R + i*strideR with leading dimension ldr.
 void hh_leaves(tt_ctx* ctx, zc* Q, long ldq, int bl, int nleaves, int m, int k, zc* R, long ldr, long strideR);
 int hh_max_rows();
+// LDS Householder leaves for panels of at most 32 columns: P balanced row
+// blocks of 32..256 rows, see k_qr.hip
+void pt_leaves(tt_ctx* ctx, zc* Q, long ldq, int nleaves, int m, int k, zc* R, long ldr, long strideR);
+void pt_assemble(tt_ctx* ctx, zc* Q, long ldq, int m, int k, int nleaves, const zc* S, long lds);
+int pt_max_rows();
+int pt_max_cols();
+// block Gram-Schmidt helpers (k_qr.hip)
+void bcgs_flag(tt_ctx* ctx, const zc* G, int nb, const zc* W, long ldw, int p0, int* flags);
+void bcgs_random(tt_ctx* ctx, zc* Qp, long ldq, int m, int nb, const int* flags, uint64_t seed, int tag);
+void bcgs_masked_add(tt_ctx* ctx, zc* Rd, long ldr, const zc* W, long ldw, int rows, int nb, const int* flags);
+void bcgs_put_diag(tt_ctx* ctx, zc* Rd, long ldr, const zc* Rp, int nb, const int* flags);
+void fill_zero(tt_ctx* ctx, zc* x, long n);
 // dst (k x m, ld ldd) = src (m x k, ld lds)^H
 void conj_transpose(tt_ctx* ctx, const zc* src, long lds, zc* dst, long ldd, int m, int k);
 // One-sided Jacobi SVD of B (m x k, ld m) in place: on exit the columns of B

@@ -6,6 +6,7 @@
 //   normalised columns the left singular vectors.  Parallel round-robin
 //   ordering, one wavefront per column pair, matrix in LDS when it fits.
 #include "common.hpp"
+#include "dpp.hpp"
 
 namespace ttf {
 
@@ -30,6 +31,7 @@ __device__ inline double block_sum(double v, double* red) {
 
 // ------------------------------------------------------------ Jacobi SVD
 constexpr int JAC_THREADS = 1024;
+constexpr int JAC_GROUPS = JAC_THREADS / 16;
 constexpr int JAC_LDS_ELEMS = 9216;  // 144 KiB of complex doubles
 constexpr int JAC_MAX_SWEEPS = 60;
 
@@ -45,6 +47,9 @@ __device__ inline void rr_pair(int P, int r, int i, int& a, int& b) {
   }
 }
 
+// One-sided Jacobi: one 16-lane group per column pair (64 pairs in flight),
+// 16-lane DPP reductions; the pairs of a round are disjoint, rounds are
+// separated by a barrier.
 template <bool IN_LDS>
 __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, int k, zc* __restrict__ Bg,
                                                              zc* __restrict__ U, double* __restrict__ sigma,
@@ -53,7 +58,7 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, int k, zc* _
   __shared__ int rotated;
   __shared__ double norms[CHOL_KMAX];
   zc* B = IN_LDS ? lds : Bg;
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
+  const int t = threadIdx.x, g = t >> 4, l16 = t & 15;
   if (IN_LDS)
     for (long e = t; e < (long)m * k; e += blockDim.x) B[e] = Bg[e];
   __syncthreads();
@@ -65,61 +70,63 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, int k, zc* _
     __syncthreads();
     int any = 0;
     for (int r = 0; r < P - 1; ++r) {
-      for (int i = wave; i < P / 2; i += nw) {
+      for (int i = g; i < P / 2; i += JAC_GROUPS) {
         int p, q;
         rr_pair(P, r, i, p, q);
         if (p >= k || q >= k) continue;
+        zc* x = B + (long)m * p;
+        zc* y = B + (long)m * q;
         double al = 0, be = 0, gr = 0, gi = 0;
-        for (int row = lane; row < m; row += 64) {
-          const zc x = B[row + (long)m * p], y = B[row + (long)m * q];
-          al += x.x * x.x + x.y * x.y;
-          be += y.x * y.x + y.y * y.y;
-          gr += x.x * y.x + x.y * y.y;  // conj(x) * y
-          gi += x.x * y.y - x.y * y.x;
+        for (int row = l16; row < m; row += 16) {
+          const zc a = x[row], c = y[row];
+          al += a.x * a.x + a.y * a.y;
+          be += c.x * c.x + c.y * c.y;
+          gr += a.x * c.x + a.y * c.y;  // conj(x) * y
+          gi += a.x * c.y - a.y * c.x;
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        gr = wave_sum(gr);
-        gi = wave_sum(gi);
-        const double g = sqrt(gr * gr + gi * gi);
-        if (g <= tol * sqrt(al * be) || g == 0.0) continue;
+        al = row16_sum(al);
+        be = row16_sum(be);
+        gr = row16_sum(gr);
+        gi = row16_sum(gi);
+        const double gg = sqrt(gr * gr + gi * gi);
+        if (gg <= tol * sqrt(al * be) || gg == 0.0) continue;
         any = 1;
-        // complex Jacobi rotation orthogonalising columns p and q
-        const double zeta = (be - al) / (2.0 * g);
+        // complex rotation orthogonalising columns p and q
+        const double zeta = (be - al) / (2.0 * gg);
         const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-        const double er = gr / g, ei = gi / g;  // e^{i phi}
-        for (int row = lane; row < m; row += 64) {
-          const zc x = B[row + (long)m * p], y = B[row + (long)m * q];
-          // x' = c x - s e^{-i phi} y ; y' = s e^{i phi} x + c y
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        const double er = gr / gg, ei = gi / gg;  // e^{i phi}
+        for (int row = l16; row < m; row += 16) {
+          const zc a = x[row], c = y[row];
+          // x' = cs x - sn e^{-i phi} y ; y' = sn e^{i phi} x + cs y
           zc xn, yn;
-          xn.x = c * x.x - s * (er * y.x + ei * y.y);
-          xn.y = c * x.y - s * (er * y.y - ei * y.x);
-          yn.x = s * (er * x.x - ei * x.y) + c * y.x;
-          yn.y = s * (er * x.y + ei * x.x) + c * y.y;
-          B[row + (long)m * p] = xn;
-          B[row + (long)m * q] = yn;
+          xn.x = cs * a.x - sn * (er * c.x + ei * c.y);
+          xn.y = cs * a.y - sn * (er * c.y - ei * c.x);
+          yn.x = sn * (er * a.x - ei * a.y) + cs * c.x;
+          yn.y = sn * (er * a.y + ei * a.x) + cs * c.y;
+          x[row] = xn;
+          y[row] = yn;
         }
       }
       __syncthreads();
     }
-    if (any && lane == 0) atomicOr(&rotated, 1);
+    if (any) atomicOr(&rotated, 1);
     __syncthreads();
     if (!rotated) break;
   }
   // singular values = column norms
-  for (int c = wave; c < k; c += nw) {
-    double s = 0;
-    for (int row = lane; row < m; row += 64) {
-      const zc x = B[row + (long)m * c];
-      s += x.x * x.x + x.y * x.y;
+  for (int c = g; c < k; c += JAC_GROUPS) {
+    double sq = 0;
+    for (int row = l16; row < m; row += 16) {
+      const zc a = B[row + (long)m * c];
+      sq += a.x * a.x + a.y * a.y;
     }
-    s = wave_sum(s);
-    if (lane == 0) norms[c] = sqrt(s);
+    sq = row16_sum(sq);
+    if (l16 == 0) norms[c] = sqrt(sq);
   }
   __syncthreads();
   // sort by decreasing norm (ties by index) and normalise into U
-  for (int c = wave; c < k; c += nw) {
+  for (int c = g; c < k; c += JAC_GROUPS) {
     const double v = norms[c];
     int pos = 0;
     for (int o = 0; o < k; ++o) {
@@ -127,11 +134,11 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, int k, zc* _
       pos += (w > v) || (w == v && o < c);
     }
     const double inv = v > 0 ? 1.0 / v : 0.0;
-    for (int row = lane; row < m; row += 64) {
-      const zc x = B[row + (long)m * c];
-      U[row + (long)m * pos] = make_double2(x.x * inv, x.y * inv);
+    for (int row = l16; row < m; row += 16) {
+      const zc a = B[row + (long)m * c];
+      U[row + (long)m * pos] = make_double2(a.x * inv, a.y * inv);
     }
-    if (lane == 0) sigma[pos] = v;
+    if (l16 == 0) sigma[pos] = v;
   }
   if (t == 0) *sweeps_out = sweep + 1;
 }
@@ -146,15 +153,16 @@ void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* swe
     TTF_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     lds_limit = v;
   }
+  // per sweep: k(k-1)/2 pairs x (16 m for the inner products + 28 m for the rotation)
   KTimer kt(ctx, "jacobi", 0.0, 0.0);
   const long need = (long)sizeof(zc) * m * k + 8 * CHOL_KMAX + 64;
   if ((long)m * k <= JAC_LDS_ELEMS && need <= lds_limit) {
     const size_t lds = sizeof(zc) * (size_t)m * k;
-    hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(JAC_THREADS), lds, ctx->stream, m, k, B, U,
-                       sigma, sweeps);
+    hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(JAC_THREADS), lds, ctx->stream, m, k, B, U, sigma,
+                       sweeps);
   } else {
-    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(JAC_THREADS), 0, ctx->stream, m, k, B, U,
-                       sigma, sweeps);
+    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(JAC_THREADS), 0, ctx->stream, m, k, B, U, sigma,
+                       sweeps);
   }
   TTF_HIP(hipGetLastError());
 }
