@@ -81,13 +81,23 @@ const char* tt_last_error(const tt_ctx* ctx);
 void* tt_ctx_stream(const tt_ctx* ctx);
 
 /* Per-kernel timing with HIP events on the context stream (off by default).
- * Named kernel classes: "zgemm", "gather", "cholqr", "jacobi", "apply_exact",
- * "concat", "eval".  flops / bytes are the algorithmic counts of the launches
- * recorded (see the design notes); times are summed event durations. */
+ * on = 0 off, 1 on, 2 on and every GEMM also recorded under the key
+ * "zgemm:<opA><opB>:MxNxKxbatch".  Named kernel classes: "zgemm", "gather",
+ * "hhqr" (panel Householder QR and its assembly), "jacobi", "apply_exact",
+ * "concat", "eval".  flops / bytes are the algorithmic counts of the
+ * launches recorded; times are summed event durations.  Every call syncs
+ * the context stream. */
 int tt_ctx_set_profiling(tt_ctx* ctx, int on);
 int tt_ctx_reset_stats(tt_ctx* ctx);
 int tt_ctx_get_stats(tt_ctx* ctx, const char* kernel, double* total_ms,
                      double* flops, double* bytes, long long* launches);
+/* All recorded keys as text, one line each: "key launches total_ms flops
+ * bytes", NUL-terminated in buf (cap bytes, caller-owned); the first line,
+ * "qr_fallbacks N 0 0 0", counts the QR factorisations since the last reset
+ * whose fast second pass was unsafe and that were redone in the robust form
+ * (counted whether or not profiling is on).  Returns TT_ECAPACITY when the
+ * text was cut. */
+int tt_ctx_dump_stats(tt_ctx* ctx, char* buf, long cap);
 
 /* ---------------------------------------------------------------- tensors */
 

@@ -152,28 +152,32 @@ void ptsqr_inplace(tt_ctx* ctx, int m, int k, zc* q, long ldq, zc* r, long ldr, 
   pt_assemble(ctx, q, ldq, m, k, P, S, Sm);
 }
 
-// QR of A (m x k, ld lda, m >= k) by block classical Gram-Schmidt with
-// reorthogonalisation (two projection passes per 32-column panel, each
-// followed by a panel TSQR): Q (m x k, ld m) orthonormal, R (k x k, ld k)
-// upper triangular, A = Q R.  A panel column whose residual after the first
-// projection is below 1e-13 of its norm (a column dependent on the earlier
-// ones, or zero) is replaced by a Gaussian vector before the panel is
-// factored and its R entries below the projection coefficients are zeroed,
-// so Q stays orthonormal for rank-deficient A.
-// The matrix is factored in place: q holds A on entry and Q on exit.
-void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r) {
+// QR of A (m x k, m >= k) by block classical Gram-Schmidt with
+// reorthogonalisation over panels of 32 columns: Q (m x k, ld m)
+// orthonormal, R (k x k, ld k) upper triangular, A = Q R.  The matrix is
+// factored in place: q holds A on entry and Q on exit.
+// Per panel: project out the earlier columns (W = Q^H A_p, A_p -= Q W);
+// replace every column whose residual is below 1e-13 of its norm (a column
+// dependent on the earlier ones, or zero) by a Gaussian vector, to be
+// left out of R; factor the panel with the Householder TSQR (Q1 R1); then
+// project once more.  robust = false finishes with the Pythagorean
+// shortcut (Cholesky of I - W2^H W2, see bcgs_pip) and raises *bad when it
+// is not safe; robust = true factors the reprojected panel again with the
+// Householder TSQR.
+void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, bool robust, int* bad) {
   require(m >= k && k >= 1, TT_EINVAL, "qr: need m >= k >= 1");
   const int NB = pt_max_cols();
   fill_zero(ctx, r, (long)k * k);
-  // small work: W2, T (k x NB), R1, R2, Rpp, G (NB x NB), flags
+  // small work: W2, T (k x NB), R1, R2, Rpp (NB x NB), flags, norm partials
   const size_t kb = (size_t)k * NB, bb = (size_t)NB * NB;
-  zc* W2 = (zc*)ctx->get_ws("bcgs_small", sizeof(zc) * (2 * kb + 4 * bb) + sizeof(int) * NB);
+  const int G = bcgs_flag_groups(m);
+  zc* W2 = (zc*)ctx->get_ws("bcgs_small", sizeof(zc) * (2 * kb + 3 * bb) + sizeof(double) * ((size_t)(G + 1) * NB));
   zc* T = W2 + kb;
   zc* R1 = T + kb;
   zc* R2 = R1 + bb;
   zc* Rpp = R2 + bb;
-  zc* G = Rpp + bb;
-  int* flags = (int*)(G + bb);
+  int* flags = (int*)(Rpp + bb);
+  double* part = (double*)(Rpp + bb) + NB;  // NB ints fit in NB doubles
   for (int p0 = 0; p0 < k; p0 += NB) {
     const int nb = std::min(NB, k - p0);
     zc* Ap = q + (long)m * p0;
@@ -182,35 +186,55 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r) {
       zgemm(ctx, OPC, OPN, p0, nb, m, Z(1), q, m, 0, Ap, m, 0, Z(0), Rp, k, 0);
       zgemm(ctx, OPN, OPN, m, nb, p0, Z(-1), q, m, 0, Rp, k, 0, Z(1), Ap, m, 0);
     }
-    zgemm(ctx, OPC, OPN, nb, nb, m, Z(1), Ap, m, 0, Ap, m, 0, Z(0), G, nb, 0);
-    bcgs_flag(ctx, G, nb, Rp, k, p0, flags);
+    bcgs_flag(ctx, Ap, m, m, nb, Rp, k, p0, flags, part);
     bcgs_random(ctx, Ap, m, m, nb, flags, 0x243F6A8885A308D3ull, p0);
     ptsqr_inplace(ctx, m, nb, Ap, m, R1, nb, 0);
-    if (p0 > 0) {
-      zgemm(ctx, OPC, OPN, p0, nb, m, Z(1), q, m, 0, Ap, m, 0, Z(0), W2, p0, 0);
-      zgemm(ctx, OPN, OPN, m, nb, p0, Z(-1), q, m, 0, W2, p0, 0, Z(1), Ap, m, 0);
+    if (p0 == 0) {
+      bcgs_put_diag(ctx, r, k, R1, nb, flags);
+      continue;
+    }
+    zgemm(ctx, OPC, OPN, p0, nb, m, Z(1), q, m, 0, Ap, m, 0, Z(0), W2, p0, 0);
+    zgemm(ctx, OPN, OPN, m, nb, p0, Z(-1), q, m, 0, W2, p0, 0, Z(1), Ap, m, 0);
+    if (robust) {
       ptsqr_inplace(ctx, m, nb, Ap, m, R2, nb, 0);
       zgemm(ctx, OPN, OPN, nb, nb, nb, Z(1), R2, nb, 0, R1, nb, 0, Z(0), Rpp, nb, 0);
       zgemm(ctx, OPN, OPN, p0, nb, nb, Z(1), W2, p0, 0, R1, nb, 0, Z(0), T, p0, 0);
       bcgs_masked_add(ctx, Rp, k, T, p0, p0, nb, flags);
       bcgs_put_diag(ctx, r + (long)k * p0 + p0, k, Rpp, nb, flags);
     } else {
-      bcgs_put_diag(ctx, r, k, R1, nb, flags);
+      bcgs_pip(ctx, W2, p0, nb, R1, Rp, r + (long)k * p0 + p0, k, flags, R2, bad);
+      panel_trmm(ctx, Ap, m, m, nb, R2);
     }
   }
 }
 
+// Runs the fast form and checks its flag (one host synchronisation); when
+// the shortcut was unsafe for some panel, `load` refills q and the robust
+// form runs.
+template <class Load>
+void qr_checked(tt_ctx* ctx, int m, int k, zc* q, zc* r, Load load) {
+  int* bad = (int*)ctx->get_ws("qr_bad", 64);
+  zero_ints(ctx, bad, 1);
+  load();
+  bcgs_qr_inplace(ctx, m, k, q, r, false, bad);
+  int* h = (int*)ctx->host_scratch(64);
+  TTF_HIP(hipMemcpyAsync(h, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  TTF_HIP(hipStreamSynchronize(ctx->stream));
+  if (h[0] == 0) return;
+  ctx->qr_fallbacks += 1;
+  load();
+  bcgs_qr_inplace(ctx, m, k, q, r, true, nullptr);
+}
+
 // QR of A (m x k, ld lda, m >= k): Q (m x k, ld m), R (k x k, ld k).
 void tsqr(tt_ctx* ctx, int m, int k, const zc* a, long lda, zc* q, zc* r) {
-  copy_matrix(ctx, a, lda, q, m, m, k);
-  bcgs_qr_inplace(ctx, m, k, q, r);
+  qr_checked(ctx, m, k, q, r, [&]() { copy_matrix(ctx, a, lda, q, m, m, k); });
 }
 
 // LQ of A (k x m, ld lda, k <= m): A = R^H Qt^H with Qt (m x k, ld m) having
 // orthonormal columns; returns Qt and R (k x k upper).
 void tsqr_lq(tt_ctx* ctx, int k, int m, const zc* a, long lda, zc* qt, zc* r) {
-  conj_transpose(ctx, a, lda, qt, m, k, m);
-  bcgs_qr_inplace(ctx, m, k, qt, r);
+  qr_checked(ctx, m, k, qt, r, [&]() { conj_transpose(ctx, a, lda, qt, m, k, m); });
 }
 
 int bounded_pow(int n, int e, int cap) {
@@ -306,8 +330,14 @@ void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_repo
     zc* tmp = (zc*)ctx->get_ws("p2_tmp", sizeof(zc) * (size_t)sq * n * rr);
     const zc* V = x->core[c];
     if (m >= k) {
+      // V = Q R and R = R2^H Q2^H: R and B = R2^H share their left singular
+      // vectors; one-sided Jacobi converges in far fewer sweeps on the
+      // lower-triangular B than on R itself
       tsqr(ctx, m, k, V, m, Q, R);
-      copy_d2d(ctx, B, R, (size_t)k * k);
+      zc* Q2 = (zc*)ctx->get_ws("p2_q2", sizeof(zc) * (size_t)k * k);
+      zc* R2 = (zc*)ctx->get_ws("p2_r2", sizeof(zc) * (size_t)k * k);
+      tsqr_lq(ctx, k, k, R, k, Q2, R2);
+      conj_transpose(ctx, R2, k, B, k, k, k);
     } else {
       // V^H (k x m) = Q' R' ; SVD of R'^H gives the left vectors of V
       tsqr_lq(ctx, m, k, V, m, Q, R);
@@ -723,6 +753,7 @@ int tt_ctx_set_profiling(tt_ctx* ctx, int on) {
   ABI_TRY
   ctx->sync();
   ctx->profiling = on != 0;
+  ctx->profile_shapes = on == 2;
   return TT_OK;
   ABI_CATCH(ctx)
 }
@@ -732,6 +763,7 @@ int tt_ctx_reset_stats(tt_ctx* ctx) {
   ABI_TRY
   ctx->sync();
   ctx->stats.clear();
+  ctx->qr_fallbacks = 0;
   return TT_OK;
   ABI_CATCH(ctx)
 }
@@ -749,6 +781,26 @@ int tt_ctx_get_stats(tt_ctx* ctx, const char* kernel, double* total_ms, double* 
   if (bytes) *bytes = s.bytes;
   if (launches) *launches = s.n;
   return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_ctx_dump_stats(tt_ctx* ctx, char* buf, long cap) {
+  if (!ctx || !buf || cap <= 0) return TT_EINVAL;
+  ABI_TRY
+  ctx->sync();
+  std::string out;
+  char line[512];
+  std::snprintf(line, sizeof(line), "qr_fallbacks %lld 0 0 0\n", ctx->qr_fallbacks);
+  out += line;
+  for (const auto& kv : ctx->stats) {
+    std::snprintf(line, sizeof(line), "%s %lld %.6f %.6g %.6g\n", kv.first.c_str(), kv.second.n, kv.second.ms,
+                  kv.second.flops, kv.second.bytes);
+    out += line;
+  }
+  const long n = std::min<long>((long)out.size(), cap - 1);
+  std::memcpy(buf, out.data(), (size_t)n);
+  buf[n] = 0;
+  return (long)out.size() < cap ? TT_OK : TT_ECAPACITY;
   ABI_CATCH(ctx)
 }
 

@@ -66,6 +66,8 @@ struct tt_ctx {
   size_t pinned_bytes = 0;
   // profiling
   bool profiling = false;
+  bool profile_shapes = false;  // also key GEMM timings by shape
+  long long qr_fallbacks = 0;   // QRs redone in the robust form
   struct Stat {
     double ms = 0, flops = 0, bytes = 0;
     long long n = 0;
@@ -144,11 +146,6 @@ void zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const z
            long lda, long strideA, const zc* B, long ldb, long strideB, zc beta, zc* C,
            long ldc, long strideC, int batch = 1);
 
-// Householder QR of nleaves row blocks of an m x k matrix (ld ldq), in
-// place: each block becomes its explicit Q factor and its R factor (k x k)
-// is written at R + i*strideR with leading dimension ldr.
-void hh_leaves(tt_ctx* ctx, zc* Q, long ldq, int bl, int nleaves, int m, int k, zc* R, long ldr, long strideR);
-int hh_max_rows();
 // LDS Householder leaves for panels of at most 32 columns: P balanced row
 // blocks of 32..256 rows, see k_qr.hip
 void pt_leaves(tt_ctx* ctx, zc* Q, long ldq, int nleaves, int m, int k, zc* R, long ldr, long strideR);
@@ -156,7 +153,13 @@ void pt_assemble(tt_ctx* ctx, zc* Q, long ldq, int m, int k, int nleaves, const 
 int pt_max_rows();
 int pt_max_cols();
 // block Gram-Schmidt helpers (k_qr.hip)
-void bcgs_flag(tt_ctx* ctx, const zc* G, int nb, const zc* W, long ldw, int p0, int* flags);
+void bcgs_flag(tt_ctx* ctx, const zc* Y, long ldy, int m, int nb, const zc* W, long ldw, int p0, int* flags,
+               double* part);
+int bcgs_flag_groups(int m);  // partial sums used by bcgs_flag (part holds groups * nb)
+void bcgs_pip(tt_ctx* ctx, const zc* W2, int p0, int nb, const zc* R1, zc* Ro, zc* Rd, long ldr, const int* flags,
+              zc* R2inv, int* bad);
+void panel_trmm(tt_ctx* ctx, zc* Z, long ldz, int m, int nb, const zc* Rinv);
+void zero_ints(tt_ctx* ctx, int* x, int n);
 void bcgs_random(tt_ctx* ctx, zc* Qp, long ldq, int m, int nb, const int* flags, uint64_t seed, int tag);
 void bcgs_masked_add(tt_ctx* ctx, zc* Rd, long ldr, const zc* W, long ldw, int rows, int nb, const int* flags);
 void bcgs_put_diag(tt_ctx* ctx, zc* Rd, long ldr, const zc* Rp, int nb, const int* flags);

@@ -1,10 +1,18 @@
-// Small dense factorisation used once per TT bond, one workgroup each.
+// Small dense factorisation used once per TT bond.
 //
 // * jacobi_svd: one-sided (Hestenes) Jacobi SVD of the small square factor
 //   R (the "SVD of the R factor" of App. A.4): columns are rotated pairwise
 //   until orthogonal; their norms are the singular values and the
-//   normalised columns the left singular vectors.  Parallel round-robin
-//   ordering, one wavefront per column pair, matrix in LDS when it fits.
+//   normalised columns the left singular vectors.
+//   Block-parallel form (m <= 512 rows): the columns are cut into blocks of
+//   16; each launch is one round of a round-robin tournament over the
+//   blocks, one workgroup per block pair.  A workgroup keeps its 32 columns
+//   in registers, two per wavefront, and runs one cyclic sweep over all 496
+//   column pairs of the block pair (31 rounds of 16 disjoint pairs; between
+//   rounds columns move to the neighbouring wavefront through LDS).  Each
+//   column pair of the matrix meets at least once per outer sweep, so the
+//   iteration is a cyclic Jacobi method with a block ordering.  Sweeps stop
+//   after the first outer sweep without a rotation.
 #include "common.hpp"
 #include "dpp.hpp"
 
@@ -34,6 +42,9 @@ constexpr int JAC_THREADS = 1024;
 constexpr int JAC_GROUPS = JAC_THREADS / 16;
 constexpr int JAC_LDS_ELEMS = 9216;  // 144 KiB of complex doubles
 constexpr int JAC_MAX_SWEEPS = 60;
+constexpr int JB_COLS = 16;    // columns per block
+constexpr int JB_MAXM = 512;   // rows supported by the register-resident form
+constexpr int JB_MAXS = 64;    // sweep counters
 
 // round-robin pairing of players 0..P-1 (P even) in round r
 __device__ inline void rr_pair(int P, int r, int i, int& a, int& b) {
@@ -143,6 +154,8 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, int k, zc* _
   if (t == 0) *sweeps_out = sweep + 1;
 }
 
+void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps);
+
 void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
   if (k <= 0) return;
   if (k > CHOL_KMAX) fail(TT_EINVAL, "jacobi_svd: rank above the supported maximum of 512");
@@ -155,6 +168,10 @@ void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* swe
   }
   // per sweep: k(k-1)/2 pairs x (16 m for the inner products + 28 m for the rotation)
   KTimer kt(ctx, "jacobi", 0.0, 0.0);
+  if (m <= JB_MAXM && JB_MAXS >= JAC_MAX_SWEEPS) {
+    jacobi_blocked(ctx, m, k, B, U, sigma, sweeps);
+    return;
+  }
   const long need = (long)sizeof(zc) * m * k + 8 * CHOL_KMAX + 64;
   if ((long)m * k <= JAC_LDS_ELEMS && need <= lds_limit) {
     const size_t lds = sizeof(zc) * (size_t)m * k;
@@ -164,6 +181,296 @@ void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* swe
     hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(JAC_THREADS), 0, ctx->stream, m, k, B, U, sigma,
                        sweeps);
   }
+  TTF_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------ block-parallel Jacobi
+__device__ inline double wave64_sum(double x) {
+  x = row16_sum(x);
+  x += __shfl_xor(x, 16, 64);
+  x += __shfl_xor(x, 32, 64);
+  return x;
+}
+
+// Rotate the column pair (x, y) held by one wavefront (rows lane + 64 j)
+// so that x^H y = 0; returns 1 when a rotation was applied.
+template <int RPL>
+__device__ inline int jacobi_rotate(zc (&x)[RPL], zc (&y)[RPL], double tol) {
+  double al = 0, be = 0, gr = 0, gi = 0;
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    const zc a = x[j], c = y[j];
+    al += a.x * a.x + a.y * a.y;
+    be += c.x * c.x + c.y * c.y;
+    gr += a.x * c.x + a.y * c.y;  // conj(x) * y
+    gi += a.x * c.y - a.y * c.x;
+  }
+  al = wave64_sum(al);
+  be = wave64_sum(be);
+  gr = wave64_sum(gr);
+  gi = wave64_sum(gi);
+  const double gg = sqrt(gr * gr + gi * gi);
+  if (!(gg > tol * sqrt(al * be)) || gg == 0.0) return 0;
+  const double zeta = (be - al) / (2.0 * gg);
+  const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+  const double er = gr / gg, ei = gi / gg;  // e^{i phi}
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    const zc a = x[j], c = y[j];
+    // x' = cs x - sn e^{-i phi} y ; y' = sn e^{i phi} x + cs y
+    x[j] = make_double2(cs * a.x - sn * (er * c.x + ei * c.y), cs * a.y - sn * (er * c.y - ei * c.x));
+    y[j] = make_double2(sn * (er * a.x - ei * a.y) + cs * c.x, sn * (er * a.y + ei * a.x) + cs * c.y);
+  }
+  return 1;
+}
+
+// add the workgroup's rotation count to rot[idx]; returns it to every thread
+__device__ inline int jacobi_count(int nrot, int* wg_rot, int* rot, int idx) {
+  __syncthreads();
+  if (threadIdx.x == 0) *wg_rot = 0;
+  __syncthreads();
+  if (nrot && (threadIdx.x & 63) == 0) atomicAdd(wg_rot, nrot);
+  __syncthreads();
+  const int tot = *wg_rot;
+  if (threadIdx.x == 0 && tot) atomicAdd(&rot[idx], tot);
+  return tot;
+}
+
+// Cyclic one-sided Jacobi over the 2W columns c0 .. c0 + 2W - 1 (those >= k
+// are absent) with W wavefronts.  Circle ordering: wavefront w holds
+// positions w and 2W-1-w; after each of the 2W-1 rounds positions
+// 1..2W-1 shift by one, so every pair meets once per sweep and after the
+// sweep every column is back in place.  Workgroup g handles the columns
+// starting at 2W g.  Up to inner_max sweeps (sweep counts in rot[sweep ..]);
+// a launch of sweep > 0 returns at once when sweep - 1 rotated nothing.
+template <int RPL, int W>
+__global__ __launch_bounds__(64 * W) void jacobi_circle_kernel(zc* __restrict__ B, int m, int k, int inner_max,
+                                                               int sweep, int* __restrict__ rot, double tol) {
+  extern __shared__ double2 xch[];  // W slots of 64 RPL rows
+  __shared__ int wg_rot;
+  if (sweep > 0 && rot[sweep - 1] == 0) return;
+  constexpr int NP = 2 * W - 1;
+  constexpr int LD = 64 * RPL;
+  const int c0 = blockIdx.x * 2 * W;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  zc xt[RPL], xb[RPL];
+  {
+    const int ct = c0 + w, cb = c0 + 2 * W - 1 - w;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      const int row = lane + 64 * j;
+      xt[j] = (ct < k && row < m) ? B[row + (long)m * ct] : make_double2(0.0, 0.0);
+      xb[j] = (cb < k && row < m) ? B[row + (long)m * cb] : make_double2(0.0, 0.0);
+    }
+  }
+  zc* mine = xch + (long)LD * w;
+  for (int it = 0; it < inner_max; ++it) {
+    int nrot = 0;
+    for (int r = 0; r < NP; ++r) {
+      // positions w and 2W-1-w after r shifts
+      const int pt = (w == 0) ? 0 : ((w - 1 - r) % NP + NP) % NP + 1;
+      const int pb = ((2 * W - 2 - w - r) % NP + NP) % NP + 1;
+      if (c0 + pt < k && c0 + pb < k) nrot += jacobi_rotate<RPL>(xt, xb, tol);
+      // shift: bottoms move to the previous wavefront (the last one takes
+      // its own top), then tops to the next one (wavefront 1 takes
+      // wavefront 0's old bottom, left in slot 0 by the first phase)
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) mine[lane + 64 * j] = xb[j];
+      __syncthreads();
+      if (w <= W - 2) {
+        const zc* src = mine + LD;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) xb[j] = src[lane + 64 * j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) xb[j] = xt[j];
+      }
+      __syncthreads();
+      if (w >= 1 && w <= W - 2) {
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) mine[lane + 64 * j] = xt[j];
+      }
+      __syncthreads();
+      if (w >= 1) {
+        const zc* src = mine - LD;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) xt[j] = src[lane + 64 * j];
+      }
+    }
+    const int tot = jacobi_count(nrot, &wg_rot, rot, sweep + it);
+    if (tot == 0) break;
+  }
+  const int ct = c0 + w, cb = c0 + 2 * W - 1 - w;
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    const int row = lane + 64 * j;
+    if (row < m) {
+      if (ct < k) B[row + (long)m * ct] = xt[j];
+      if (cb < k) B[row + (long)m * cb] = xb[j];
+    }
+  }
+}
+
+// All 16 x 16 column pairs between blocks a and b (16 columns each; the
+// pair of workgroup g in round `round` of a round-robin over P blocks):
+// wavefront w keeps column 16a + w and meets column 16b + (w + s) mod 16 in
+// step s; between steps the b columns move to the previous wavefront.
+template <int RPL>
+__global__ __launch_bounds__(1024) void jacobi_cross_kernel(zc* __restrict__ B, int m, int k, int P, int round,
+                                                            int sweep, int* __restrict__ rot, double tol) {
+  extern __shared__ double2 xch[];  // 16 slots of 64 RPL rows
+  __shared__ int wg_rot;
+  if (sweep > 0 && rot[sweep - 1] == 0) return;
+  constexpr int LD = 64 * RPL;
+  int ba, bb;
+  rr_pair(P, round, blockIdx.x, ba, bb);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ca = ba * JB_COLS + w;
+  zc xa[RPL], xb[RPL];
+  {
+    const int cb = bb * JB_COLS + w;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      const int row = lane + 64 * j;
+      xa[j] = (ca < k && row < m) ? B[row + (long)m * ca] : make_double2(0.0, 0.0);
+      xb[j] = (cb < k && row < m) ? B[row + (long)m * cb] : make_double2(0.0, 0.0);
+    }
+  }
+  zc* mine = xch + (long)LD * w;
+  const zc* next = xch + (long)LD * ((w + 1) & 15);
+  int nrot = 0;
+  for (int st = 0; st < JB_COLS; ++st) {
+    const int cb = bb * JB_COLS + ((w + st) & 15);
+    if (ca < k && cb < k) nrot += jacobi_rotate<RPL>(xa, xb, tol);
+    if (st == JB_COLS - 1) break;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) mine[lane + 64 * j] = xb[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) xb[j] = next[lane + 64 * j];
+  }
+  jacobi_count(nrot, &wg_rot, rot, sweep);
+  const int cb = bb * JB_COLS + ((w + JB_COLS - 1) & 15);
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    const int row = lane + 64 * j;
+    if (row < m) {
+      if (ca < k) B[row + (long)m * ca] = xa[j];
+      if (cb < k) B[row + (long)m * cb] = xb[j];
+    }
+  }
+}
+
+__global__ void zero_ints_kernel(int* x, int n) {
+  for (int e = threadIdx.x; e < n; e += blockDim.x) x[e] = 0;
+}
+
+void zero_ints(tt_ctx* ctx, int* x, int n) {
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(256), 0, ctx->stream, x, n);
+  TTF_HIP(hipGetLastError());
+}
+
+// singular values (column norms) sorted decreasingly, ties by index; U =
+// normalised columns in that order; sweeps = first sweep without rotation + 1
+__global__ __launch_bounds__(1024) void jacobi_finish_kernel(int m, int k, const zc* __restrict__ B,
+                                                             zc* __restrict__ U, double* __restrict__ sigma,
+                                                             const int* __restrict__ rot, int nsweeps,
+                                                             int* __restrict__ sweeps_out) {
+  __shared__ double norms[CHOL_KMAX];
+  const int t = threadIdx.x, g = t >> 4, l16 = t & 15;
+  for (int c = g; c < k; c += JAC_GROUPS) {
+    double sq = 0;
+    for (int row = l16; row < m; row += 16) {
+      const zc a = B[row + (long)m * c];
+      sq += a.x * a.x + a.y * a.y;
+    }
+    sq = row16_sum(sq);
+    if (l16 == 0) norms[c] = sqrt(sq);
+  }
+  __syncthreads();
+  for (int c = g; c < k; c += JAC_GROUPS) {
+    const double v = norms[c];
+    int pos = 0;
+    for (int o = 0; o < k; ++o) {
+      const double w = norms[o];
+      pos += (w > v) || (w == v && o < c);
+    }
+    const double inv = v > 0 ? 1.0 / v : 0.0;
+    for (int row = l16; row < m; row += 16) {
+      const zc a = B[row + (long)m * c];
+      U[row + (long)m * pos] = make_double2(a.x * inv, a.y * inv);
+    }
+    if (l16 == 0) sigma[pos] = v;
+  }
+  if (t == 0) {
+    int s = 0;
+    while (s < nsweeps && rot[s] != 0) ++s;
+    *sweeps_out = s < nsweeps ? s + 1 : nsweeps;
+  }
+}
+
+template <int RPL>
+void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int round, int inner_max, int sweep,
+                       int* rot, double tol) {
+  const size_t slot = sizeof(zc) * 64 * RPL;
+  if (kind == 0)  // whole matrix (k <= 32) in one workgroup
+    hipLaunchKernelGGL((jacobi_circle_kernel<RPL, 16>), dim3(1), dim3(1024), 16 * slot, ctx->stream, B, m, k,
+                       inner_max, sweep, rot, tol);
+  else if (kind == 1)  // every block of 16 columns on its own
+    hipLaunchKernelGGL((jacobi_circle_kernel<RPL, 8>), dim3((k + 15) / 16), dim3(512), 8 * slot, ctx->stream, B, m,
+                       k, 1, sweep, rot, tol);
+  else
+    hipLaunchKernelGGL(jacobi_cross_kernel<RPL>, dim3(P / 2), dim3(1024), 16 * slot, ctx->stream, B, m, k, P, round,
+                       sweep, rot, tol);
+  TTF_HIP(hipGetLastError());
+}
+
+// Blocks of 16 columns; one sweep = every block on its own (all pairs
+// inside a block) followed by the P - 1 rounds of a round-robin over the
+// blocks (all pairs between two blocks), so each column pair meets once.
+void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
+  const int rpl = (m + 63) / 64;
+  auto launch = [&](int kind, int P, int round, int inner_max, int sweep, int* rot, double tol) {
+    if (rpl <= 2)
+      jacobi_launch_rpl<2>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+    else if (rpl <= 4)
+      jacobi_launch_rpl<4>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+    else if (rpl <= 5)
+      jacobi_launch_rpl<5>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+    else
+      jacobi_launch_rpl<8>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+  };
+  const double tol = 1e-15 * sqrt((double)m);
+  const int nblk = (k + JB_COLS - 1) / JB_COLS;
+  const int P = nblk + (nblk & 1);
+  int* rot = (int*)ctx->get_ws("jac_rot", sizeof(int) * JB_MAXS);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, ctx->stream, rot, JB_MAXS);
+  TTF_HIP(hipGetLastError());
+  int nsweeps = 0;
+  if (k <= 2 * JB_COLS) {
+    launch(0, 2, 0, JAC_MAX_SWEEPS, 0, rot, tol);
+    nsweeps = JAC_MAX_SWEEPS;
+  } else {
+    int* h = (int*)ctx->host_scratch(sizeof(int) * JB_MAXS);
+    int batch = 6;
+    bool done = false;
+    while (!done && nsweeps < JAC_MAX_SWEEPS) {
+      for (int b = 0; b < batch && nsweeps < JAC_MAX_SWEEPS; ++b, ++nsweeps) {
+        launch(1, P, 0, 1, nsweeps, rot, tol);
+        for (int r = 0; r < P - 1; ++r) launch(2, P, r, 1, nsweeps, rot, tol);
+      }
+      TTF_HIP(hipMemcpyAsync(h, rot, sizeof(int) * nsweeps, hipMemcpyDeviceToHost, ctx->stream));
+      TTF_HIP(hipStreamSynchronize(ctx->stream));
+      for (int s = 0; s < nsweeps; ++s)
+        if (h[s] == 0) done = true;
+      batch = 2;
+    }
+  }
+  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(1024), 0, ctx->stream, m, k, B, U, sigma, rot, nsweeps,
+                     sweeps);
   TTF_HIP(hipGetLastError());
 }
 

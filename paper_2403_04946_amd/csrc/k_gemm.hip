@@ -13,6 +13,8 @@
 // and imaginary planes so every MFMA operand is one 8-byte LDS read per lane.
 // Large K with a small output grid is split over workgroups (split-K) into a
 // workspace and reduced deterministically by a second kernel.
+#include <string>
+
 #include "common.hpp"
 
 namespace ttf {
@@ -233,6 +235,14 @@ void zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const z
   }
   if ((long)batch * nsplit > 65535) fail(TT_EINVAL, "zgemm: batch * split too large for the grid");
   {
+    // with shape profiling on, the launch is also recorded under its shape
+    std::string shape;
+    if (ctx->profile_shapes) {
+      const char ops[3] = {'N', 'T', 'C'};
+      shape = std::string("zgemm:") + ops[opA] + ops[opB] + ":" + std::to_string(M) + "x" + std::to_string(N) + "x" +
+              std::to_string(K) + "x" + std::to_string(batch);
+    }
+    KTimer kt2(ctx->profile_shapes ? ctx : nullptr, shape.c_str(), flops, bytes);
     KTimer kt(ctx, "zgemm", flops, bytes);
     hipLaunchKernelGGL(zgemm_kernel, dim3(gx, gy, batch * nsplit), dim3(256), 0, ctx->stream, p);
     if (nsplit > 1) {

@@ -1,316 +1,156 @@
-// Householder QR of tall blocks, one workgroup per block, explicit Q.
+// QR factorisations for the orthogonalisations of the TT sweeps: the QR of
+// V(C) and the LQ of H(C) (App. A.1, Alg. 1 and Alg. 2).
 //
-// This is the leaf factorisation of the tall-skinny QR (TSQR) used by every
-// orthogonalisation of the TT sweeps: the QR of V(C) and the LQ of H(C)
-// (App. A.1, Alg. 1 and Alg. 2), tree-reduced as in the paper's TSQR
-// (App. A.3, Fig. tsqr-tree) but inside one GPU: leaves are row blocks
-// factored by separate workgroups, their stacked R factors are factored
-// again, and Q is assembled top-down with batched matrix-core GEMMs.
-// Householder reflections keep Q orthonormal to working precision whatever
-// the rank of the input, which matters here because MPO products and sums
-// of TTs are routinely exactly rank-deficient.
-//
-// Per block (b x k, b >= k, in place): for j = 0..k-1 a reflector
-// H_j = I - tau_j v_j v_j^H annihilates column j below the diagonal
-// (v_j(0) = 1, beta real) and H_j^H is applied to the trailing columns;
-// then R is copied out and Q = H_0 ... H_{k-1} [I; 0] is formed backwards
-// in place of the block.
+// * Panel Householder QR (pt_leaves / pt_assemble): tall blocks of at most
+//   32 columns, tree-reduced as in the paper's TSQR (App. A.3) but inside
+//   one GPU: leaves of at most 256 rows are factored by separate
+//   workgroups, their stacked R factors are factored again, and Q is
+//   assembled top-down.  Householder reflections keep Q orthonormal to
+//   working precision whatever the rank of the panel.
+// * Helpers of the block Gram-Schmidt QR that orthogonalises wide matrices
+//   panel by panel (the driver is in capi.cpp).
 #include "common.hpp"
 #include "dpp.hpp"
 #include "rng.hpp"
 
 namespace ttf {
 
-constexpr int HH_THREADS = 1024;
-constexpr int HH_KMAX = 512;
-constexpr int HH_BMAX = 2048;
-constexpr int HH_GROUPS = HH_THREADS / 16;
-
-// Householder reflector for column j of the block (rows j..b-1), computed by
-// one 16-lane group: v(j) = 1, the entries below the diagonal are scaled in
-// place and copied to vb, A(j,j) becomes beta, tau goes to *tau_out.
-__device__ inline void hh_reflector(zc* A, long ldq, int b, int j, int l16, zc* vb, zc* tau_out) {
-  double xs = 0;
-  for (int r = j + 1 + l16; r < b; r += 16) {
-    const zc a = A[r + ldq * j];
-    xs += a.x * a.x + a.y * a.y;
-  }
-  xs = row16_sum(xs);
-  const zc al = A[j + ldq * j];
-  zc tj, sc;
-  double be;
-  if (xs == 0.0 && al.y == 0.0) {
-    tj = make_double2(0.0, 0.0);
-    be = al.x;
-    sc = make_double2(0.0, 0.0);
-  } else {
-    const double nrm = sqrt(al.x * al.x + al.y * al.y + xs);
-    be = (al.x >= 0.0) ? -nrm : nrm;
-    tj = make_double2((be - al.x) / be, -al.y / be);
-    const double dr = al.x - be, di = al.y;
-    const double den = dr * dr + di * di;
-    sc = make_double2(dr / den, -di / den);  // 1 / (alpha - beta)
-  }
-  for (int r = j + 1 + l16; r < b; r += 16) {
-    const zc a = A[r + ldq * j];
-    const zc vr = make_double2(a.x * sc.x - a.y * sc.y, a.x * sc.y + a.y * sc.x);
-    A[r + ldq * j] = vr;
-    vb[r] = vr;
-  }
-  if (l16 == 0) {
-    vb[j] = make_double2(1.0, 0.0);
-    A[j + ldq * j] = make_double2(be, 0.0);
-    *tau_out = tj;
-  }
-}
-
-// A(j:b, c) -= s * v(j:b), s = t * (v^H A(j:b, c)); one 16-lane group.
-__device__ inline void hh_apply_column(zc* A, long ldq, int b, int j, int c, int l16, const zc* v, zc t) {
-  constexpr int RPL = 8;
-  double dr = 0, di = 0;
-  for (int r0 = j; r0 < b; r0 += 16 * RPL) {
-    zc a[RPL], w[RPL];
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-      const int r = r0 + l16 + 16 * s;
-      a[s] = (r < b) ? A[r + ldq * c] : make_double2(0.0, 0.0);
-      w[s] = (r < b) ? v[r] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-      dr += w[s].x * a[s].x + w[s].y * a[s].y;  // conj(v) a
-      di += w[s].x * a[s].y - w[s].y * a[s].x;
-    }
-  }
-  dr = row16_sum(dr);
-  di = row16_sum(di);
-  const double sr = t.x * dr - t.y * di, si = t.x * di + t.y * dr;
-  for (int r0 = j; r0 < b; r0 += 16 * RPL) {
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-      const int r = r0 + l16 + 16 * s;
-      if (r < b) {
-        const zc w = v[r];
-        zc a = A[r + ldq * c];
-        a.x -= w.x * sr - w.y * si;
-        a.y -= w.x * si + w.y * sr;
-        A[r + ldq * c] = a;
-      }
-    }
-  }
-}
-
-// Leaf i holds rows [i*bl, i*bl + rows) of the m-row matrix, rows = bl for
-// every leaf but the last, which takes the remainder (arranged by the host
-// so that k <= rows <= HH_BMAX).  1024 threads = 64 groups of 16 lanes; each
-// group updates one column at a time with 16-lane DPP reductions, and the
-// group that updates column j+1 forms the next reflector right away
-// (look-ahead), so each column step needs one barrier.
-__global__ __launch_bounds__(HH_THREADS) void hh_leaf_kernel(zc* __restrict__ Qbase, long ldq, int bl, int nleaves,
-                                                             int m, int k, zc* __restrict__ Rbase, long ldr,
-                                                             long strideR) {
-  __shared__ zc vbuf[2][HH_BMAX];
-  __shared__ zc tau[HH_KMAX];
-  const int leaf = blockIdx.x;
-  zc* A = Qbase + (long)leaf * bl;
-  const int b = (leaf == nleaves - 1) ? m - leaf * bl : bl;
-  zc* R = Rbase + strideR * leaf;
-  const int t = threadIdx.x, nt = blockDim.x, g = t >> 4, l16 = t & 15;
-
-  // ---- factorisation
-  if (g == 0) hh_reflector(A, ldq, b, 0, l16, vbuf[0], &tau[0]);
-  __syncthreads();
-  for (int j = 0; j < k; ++j) {
-    const zc* v = vbuf[j & 1];
-    const zc tc = make_double2(tau[j].x, -tau[j].y);  // apply H_j^H
-    const bool active = (tc.x != 0.0 || tc.y != 0.0);
-    for (int c = j + 1 + g; c < k; c += HH_GROUPS) {
-      if (active) hh_apply_column(A, ldq, b, j, c, l16, v, tc);
-      if (c == j + 1) hh_reflector(A, ldq, b, j + 1, l16, vbuf[(j + 1) & 1], &tau[j + 1]);
-    }
-    __syncthreads();
-  }
-  // ---- R (upper triangle)
-  for (long e = t; e < (long)k * k; e += nt) {
-    const int p = (int)(e % k), c = (int)(e / k);
-    R[p + ldr * c] = (p <= c) ? A[p + ldq * c] : make_double2(0.0, 0.0);
-  }
-  // ---- Q = H_0 ... H_{k-1} [I; 0], backwards and in place; the reflector
-  // of the next (lower) column is prefetched into the other buffer
-  for (int r = k + t; r < b; r += nt) vbuf[(k - 1) & 1][r] = A[r + ldq * (k - 1)];
-  if (t == 0) vbuf[(k - 1) & 1][k - 1] = make_double2(1.0, 0.0);
-  __syncthreads();
-  for (int j = k - 1; j >= 0; --j) {
-    const zc* v = vbuf[j & 1];
-    const zc tj = tau[j];
-    if (j > 0) {
-      zc* vn = vbuf[(j - 1) & 1];
-      for (int r = j + t; r < b; r += nt) vn[r] = A[r + ldq * (j - 1)];
-      if (t == 0) vn[j - 1] = make_double2(1.0, 0.0);
-    }
-    if (tj.x != 0.0 || tj.y != 0.0)
-      for (int c = j + 1 + g; c < k; c += HH_GROUPS) hh_apply_column(A, ldq, b, j, c, l16, v, tj);
-    for (int r = t; r < b; r += nt) {
-      zc q;
-      if (r < j)
-        q = make_double2(0.0, 0.0);
-      else if (r == j)
-        q = make_double2(1.0 - tj.x, -tj.y);
-      else {
-        const zc vr = v[r];
-        q = make_double2(-(tj.x * vr.x - tj.y * vr.y), -(tj.x * vr.y + tj.y * vr.x));
-      }
-      A[r + ldq * j] = q;
-    }
-    __syncthreads();
-  }
-}
-
-void hh_leaves(tt_ctx* ctx, zc* Q, long ldq, int bl, int nleaves, int m, int k, zc* R, long ldr, long strideR) {
-  if (k > HH_KMAX) fail(TT_EINVAL, "Householder QR: rank above the supported maximum of 512");
-  const int last = m - (nleaves - 1) * bl;
-  if (bl < k || last < k || last > HH_BMAX || bl > HH_BMAX) fail(TT_EINVAL, "Householder QR: bad leaf shape");
-  // factor (4 b k^2 - 4/3 k^3 complex) and forming Q (same), real flops
-  const double flops = 8.0 * (8.0 * (double)m * k * k - 8.0 / 3.0 * (double)k * k * k * nleaves);
-  KTimer kt(ctx, "hhqr", flops, 32.0 * (double)m * k);
-  hipLaunchKernelGGL(hh_leaf_kernel, dim3(nleaves), dim3(HH_THREADS), 0, ctx->stream, Q, ldq, bl, nleaves, m, k, R,
-                     ldr, strideR);
-  TTF_HIP(hipGetLastError());
-}
-
-int hh_max_rows() { return HH_BMAX; }
-
-// ----------------------------------------------- LDS panel Householder QR
-// Blocks of at most 256 rows x 32 columns held in LDS for the whole
-// factorisation (Householder factor, R copy-out, explicit Q), one workgroup
-// per block.  Used for the panels of the block Gram-Schmidt QR below and for
-// the R-stack merges of its TSQR tree (eight 32 x 32 factors per block).
 constexpr int PT_ROWS = 256;
 constexpr int PT_COLS = 32;
 
-__device__ inline void pt_reflector(zc (*A)[PT_ROWS + 1], int b, int j, int l16, zc* tau_out) {
-  double xs = 0;
-  for (int r = j + 1 + l16; r < b; r += 16) {
-    const zc a = A[j][r];
-    xs += a.x * a.x + a.y * a.y;
-  }
-  xs = row16_sum(xs);
-  const zc al = A[j][j];
-  zc tj, sc;
-  double be;
-  if (xs == 0.0 && al.y == 0.0) {
-    tj = make_double2(0.0, 0.0);
-    be = al.x;
-    sc = make_double2(0.0, 0.0);
-  } else {
-    const double nrm = sqrt(al.x * al.x + al.y * al.y + xs);
-    be = (al.x >= 0.0) ? -nrm : nrm;
-    tj = make_double2((be - al.x) / be, -al.y / be);
-    const double dr = al.x - be, di = al.y;
-    const double den = dr * dr + di * di;
-    sc = make_double2(dr / den, -di / den);
-  }
-  for (int r = j + 1 + l16; r < b; r += 16) {
-    const zc a = A[j][r];
-    A[j][r] = make_double2(a.x * sc.x - a.y * sc.y, a.x * sc.y + a.y * sc.x);
-  }
-  if (l16 == 0) {
-    A[j][j] = make_double2(be, 0.0);
-    *tau_out = tj;
-  }
+// sum over a 32-lane half of a wavefront, bitwise identical in every lane
+__device__ inline double hw_sum(double x) {
+  x = row16_sum(x);
+  x += __shfl_xor(x, 16, 64);
+  return x;
 }
 
-// column c (rows j..b-1) <- (I - t v v^H) column c, v = [1; A[j][j+1..b-1]]
-// when vsrc == nullptr, else v from vsrc (with vsrc[j] = 1)
-__device__ inline void pt_apply(zc (*A)[PT_ROWS + 1], int b, int j, int c, int l16, const zc* vsrc, zc t) {
-  double dr = 0, di = 0;
-  for (int r = j + l16; r < b; r += 16) {
-    const zc w = vsrc ? vsrc[r] : (r == j ? make_double2(1.0, 0.0) : A[j][r]);
-    const zc a = A[c][r];
-    dr += w.x * a.x + w.y * a.y;
-    di += w.x * a.y - w.y * a.x;
-  }
-  dr = row16_sum(dr);
-  di = row16_sum(di);
-  const double sr = t.x * dr - t.y * di, si = t.x * di + t.y * dr;
-  for (int r = j + l16; r < b; r += 16) {
-    const zc w = vsrc ? vsrc[r] : (r == j ? make_double2(1.0, 0.0) : A[j][r]);
-    zc a = A[c][r];
-    a.x -= w.x * sr - w.y * si;
-    a.y -= w.x * si + w.y * sr;
-    A[c][r] = a;
-  }
-}
-
-// Householder QR of one row block per workgroup, entirely in LDS.  Leaf i
-// owns rows [i m / P, (i+1) m / P) of the m x k matrix at Qbase (ld ldq),
-// k <= 32 and every leaf 32..256 rows; it leaves the explicit Q factor in
-// place and writes R_i (k x k upper) at Rbase + i strideR (ld ldr).
+// Householder QR of one row block per workgroup.  Leaf i owns rows
+// [i m / P, (i+1) m / P) of the m x k matrix at Qbase (ld ldq), k <= 32 and
+// every leaf 32..256 rows; it leaves the explicit Q factor in place and
+// writes R_i (k x k upper) at Rbase + i strideR (ld ldr).
+// Column c lives in the registers of half-wavefront c (8 rows per lane).
+// Step j: the owner of column j forms reflector j (LAPACK zlarfg
+// convention, H = I - tau v v^H with v_j = 1) and publishes v and tau in
+// LDS; after one barrier every later column applies H^H.  The explicit Q
+// is then built column by column, q_c = H_0 ... H_c e_c, with no further
+// synchronisation.
 __global__ __launch_bounds__(1024) void pt_leaf_kernel(zc* __restrict__ Qbase, long ldq, int nleaves, int m, int k,
                                                        zc* __restrict__ Rbase, long ldr, long strideR) {
-  __shared__ zc A[PT_COLS][PT_ROWS + 1];
-  __shared__ zc vb[2][PT_ROWS];
+  constexpr int RPL = PT_ROWS / 32;
+  __shared__ zc V[PT_COLS][PT_ROWS];
   __shared__ zc tau[PT_COLS];
   const int leaf = blockIdx.x;
   const long r0 = (long)leaf * m / nleaves, r1 = (long)(leaf + 1) * m / nleaves;
-  zc* G = Qbase + r0;
   const int b = (int)(r1 - r0);
+  zc* G = Qbase + r0;
   zc* R = Rbase + strideR * leaf;
-  const int t = threadIdx.x, g = t >> 4, l16 = t & 15;
-  for (int e = t; e < b * k; e += 1024) {
-    const int r = e % b, c = e / b;
-    A[c][r] = G[r + ldq * c];
+  const int h = threadIdx.x >> 5, l = threadIdx.x & 31;
+  const bool active = h < k;
+  zc x[RPL];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int row = l + 32 * i;
+    x[i] = (active && row < b) ? G[row + ldq * h] : make_double2(0.0, 0.0);
   }
-  __syncthreads();
-  // factor: the group that updates column j+1 forms reflector j+1 next
-  if (g == 0) pt_reflector(A, b, 0, l16, &tau[0]);
-  __syncthreads();
   for (int j = 0; j < k; ++j) {
-    const zc tc = make_double2(tau[j].x, -tau[j].y);
-    const int c = j + 1 + g;
-    if (c < k) {
-      if (tc.x != 0.0 || tc.y != 0.0) pt_apply(A, b, j, c, l16, nullptr, tc);
-      if (c == j + 1) pt_reflector(A, b, j + 1, l16, &tau[j + 1]);
+    if (h == j) {
+      double xs = 0, ar = 0, ai = 0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = l + 32 * i;
+        if (row > j) xs += x[i].x * x[i].x + x[i].y * x[i].y;
+        if (row == j) {
+          ar = x[i].x;
+          ai = x[i].y;
+        }
+      }
+      xs = hw_sum(xs);
+      ar = hw_sum(ar);
+      ai = hw_sum(ai);
+      zc tj, sc;
+      double be;
+      if (xs == 0.0 && ai == 0.0) {
+        tj = make_double2(0.0, 0.0);
+        be = ar;
+        sc = make_double2(0.0, 0.0);
+      } else {
+        const double nrm = sqrt(ar * ar + ai * ai + xs);
+        be = (ar >= 0.0) ? -nrm : nrm;
+        tj = make_double2((be - ar) / be, -ai / be);
+        const double dr = ar - be, di = ai;
+        const double den = dr * dr + di * di;
+        sc = make_double2(dr / den, -di / den);
+      }
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = l + 32 * i;
+        zc v;
+        if (row < j) {
+          v = make_double2(0.0, 0.0);
+        } else if (row == j) {
+          v = make_double2(1.0, 0.0);
+          x[i] = make_double2(be, 0.0);
+        } else {
+          v = make_double2(x[i].x * sc.x - x[i].y * sc.y, x[i].x * sc.y + x[i].y * sc.x);
+        }
+        V[j][row] = v;
+      }
+      if (l == 0) tau[j] = tj;
     }
     __syncthreads();
-  }
-  for (int e = t; e < k * k; e += 1024) {
-    const int p = e % k, c = e / k;
-    R[p + ldr * c] = (p <= c) ? A[c][p] : make_double2(0.0, 0.0);
-  }
-  // Q backwards; v_j staged in vb[j & 1], v_{j-1} prefetched meanwhile
-  for (int r = k + t; r < b; r += 1024) vb[(k - 1) & 1][r] = A[k - 1][r];
-  if (t == 0) vb[(k - 1) & 1][k - 1] = make_double2(1.0, 0.0);
-  __syncthreads();
-  for (int j = k - 1; j >= 0; --j) {
-    const zc* v = vb[j & 1];
-    const zc tj = tau[j];
-    if (j > 0) {
-      for (int r = j + t; r < b; r += 1024) vb[(j - 1) & 1][r] = A[j - 1][r];
-      if (t == 0) vb[(j - 1) & 1][j - 1] = make_double2(1.0, 0.0);
-    }
-    const int c = j + 1 + g;
-    if (c < k && (tj.x != 0.0 || tj.y != 0.0)) pt_apply(A, b, j, c, l16, v, tj);
-    if (g == k - j - 1) {
-      // the first idle group (k <= 32 < 64 groups) rewrites column j
-      for (int r = l16; r < b; r += 16) {
-        zc q;
-        if (r < j)
-          q = make_double2(0.0, 0.0);
-        else if (r == j)
-          q = make_double2(1.0 - tj.x, -tj.y);
-        else {
-          const zc vr = v[r];
-          q = make_double2(-(tj.x * vr.x - tj.y * vr.y), -(tj.x * vr.y + tj.y * vr.x));
+    if (h > j && active) {
+      const zc t = make_double2(tau[j].x, -tau[j].y);
+      if (t.x != 0.0 || t.y != 0.0) {
+        double dr = 0, di = 0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const zc w = V[j][l + 32 * i];
+          dr += w.x * x[i].x + w.y * x[i].y;
+          di += w.x * x[i].y - w.y * x[i].x;
         }
-        A[j][r] = q;
+        dr = hw_sum(dr);
+        di = hw_sum(di);
+        const double sr = t.x * dr - t.y * di, si = t.x * di + t.y * dr;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const zc w = V[j][l + 32 * i];
+          x[i].x -= w.x * sr - w.y * si;
+          x[i].y -= w.x * si + w.y * sr;
+        }
       }
     }
-    __syncthreads();
   }
-  for (int e = t; e < b * k; e += 1024) {
-    const int r = e % b, c = e / b;
-    G[r + ldq * c] = A[c][r];
+  if (!active) return;
+  // R: rows 0..h of column h (k <= 32, so row l sits in x[0])
+  if (l < k) R[l + ldr * h] = (l <= h) ? x[0] : make_double2(0.0, 0.0);
+  // q_h = H_0 ... H_h e_h
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) x[i] = make_double2((l + 32 * i == h) ? 1.0 : 0.0, 0.0);
+  for (int j = h; j >= 0; --j) {
+    const zc t = tau[j];
+    if (t.x == 0.0 && t.y == 0.0) continue;
+    double dr = 0, di = 0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const zc w = V[j][l + 32 * i];
+      dr += w.x * x[i].x + w.y * x[i].y;
+      di += w.x * x[i].y - w.y * x[i].x;
+    }
+    dr = hw_sum(dr);
+    di = hw_sum(di);
+    const double sr = t.x * dr - t.y * di, si = t.x * di + t.y * dr;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const zc w = V[j][l + 32 * i];
+      x[i].x -= w.x * sr - w.y * si;
+      x[i].y -= w.x * si + w.y * sr;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int row = l + 32 * i;
+    if (row < b) G[row + ldq * h] = x[i];
   }
 }
 
@@ -395,14 +235,39 @@ void conj_transpose(tt_ctx* ctx, const zc* src, long lds_, zc* dst, long ldd, in
 
 
 // ------------------------------------------ block Gram-Schmidt helpers
+__device__ inline double wave_sum64(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// part[g nb + c] = squared norm of rows [g m / G, (g+1) m / G) of column c
+// of Y (m x nb, ld ldy); one wavefront per column, G workgroups
+__global__ __launch_bounds__(256) void colnorm_partial_kernel(const zc* __restrict__ Y, long ldy, int m, int nb,
+                                                              double* __restrict__ part) {
+  const int g = blockIdx.x, G = gridDim.x;
+  const long r0 = (long)g * m / G, r1 = (long)(g + 1) * m / G;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c = w; c < nb; c += 4) {
+    double s = 0;
+    for (long r = r0 + lane; r < r1; r += 64) {
+      const zc v = Y[r + ldy * c];
+      s += v.x * v.x + v.y * v.y;
+    }
+    s = wave_sum64(s);
+    if (lane == 0) part[(long)g * nb + c] = s;
+  }
+}
+
 // flag[c] = 1 when the residual of panel column c after projection is below
-// 1e-13 of the column's norm (residual^2 from the Gram G, projected part from
-// the coefficients W, p0 rows, leading dimension ldw).
-__global__ void bcgs_flag_kernel(const zc* __restrict__ G, int nb, const zc* __restrict__ W, long ldw, int p0,
-                                 int* __restrict__ flags) {
+// 1e-13 of the column's norm: the squared residual is the sum of the G
+// partial norms (fixed order), the projected part the squared norm of the
+// coefficients W (p0 rows, leading dimension ldw)
+__global__ void bcgs_flag_kernel(const double* __restrict__ part, int G, int nb, const zc* __restrict__ W, long ldw,
+                                 int p0, int* __restrict__ flags) {
   const int c = threadIdx.x;
   if (c >= nb) return;
-  const double res2 = G[c + (long)nb * c].x;
+  double res2 = 0;
+  for (int g = 0; g < G; ++g) res2 += part[(long)g * nb + c];
   double w2 = 0;
   for (int i = 0; i < p0; ++i) {
     const zc w = W[i + ldw * c];
@@ -446,10 +311,15 @@ __global__ void bcgs_put_diag_kernel(zc* __restrict__ Rd, long ldr, const zc* __
   }
 }
 
-void bcgs_flag(tt_ctx* ctx, const zc* G, int nb, const zc* W, long ldw, int p0, int* flags) {
-  hipLaunchKernelGGL(bcgs_flag_kernel, dim3(1), dim3(64), 0, ctx->stream, G, nb, W, ldw, p0, flags);
+void bcgs_flag(tt_ctx* ctx, const zc* Y, long ldy, int m, int nb, const zc* W, long ldw, int p0, int* flags,
+               double* part) {
+  const int G = bcgs_flag_groups(m);
+  hipLaunchKernelGGL(colnorm_partial_kernel, dim3(G), dim3(256), 0, ctx->stream, Y, ldy, m, nb, part);
+  hipLaunchKernelGGL(bcgs_flag_kernel, dim3(1), dim3(64), 0, ctx->stream, part, G, nb, W, ldw, p0, flags);
   TTF_HIP(hipGetLastError());
 }
+
+int bcgs_flag_groups(int m) { return std::max(1, std::min(512, m / 256)); }
 
 void bcgs_random(tt_ctx* ctx, zc* Qp, long ldq, int m, int nb, const int* flags, uint64_t seed, int tag) {
   const long total = (long)m * nb;
@@ -469,6 +339,147 @@ void bcgs_masked_add(tt_ctx* ctx, zc* Rd, long ldr, const zc* W, long ldw, int r
 
 void bcgs_put_diag(tt_ctx* ctx, zc* Rd, long ldr, const zc* Rp, int nb, const int* flags) {
   hipLaunchKernelGGL(bcgs_put_diag_kernel, dim3(1), dim3(256), 0, ctx->stream, Rd, ldr, Rp, nb, flags);
+  TTF_HIP(hipGetLastError());
+}
+
+// Second pass of the block Gram-Schmidt step for one panel (one workgroup,
+// nb <= 32): with Q1 orthonormal and W2 = Q^H Q1 (p0 x nb, ld p0), the
+// reorthogonalised panel Z = Q1 - Q W2 has Gram matrix I - W2^H W2, so its
+// Cholesky factor R2 comes without another pass over the panel.  Outputs:
+// R2^{-1} (nb x nb, ld nb) for Q2 = Z R2^{-1}; the diagonal block R2 R1 of R
+// at Rd (ld ldr) and W2 R1 added to the off-diagonal block Ro (p0 x nb, ld
+// ldr), both with flagged columns left out; *bad = 1 when a pivot of the
+// Cholesky factorisation falls below 0.1 (Z too far from orthonormal for
+// this shortcut), in which case the caller redoes the factorisation.
+__global__ __launch_bounds__(1024) void bcgs_pip_kernel(const zc* __restrict__ W2, int p0, int nb,
+                                                        const zc* __restrict__ R1, zc* __restrict__ Ro,
+                                                        zc* __restrict__ Rd, long ldr, const int* __restrict__ flags,
+                                                        zc* __restrict__ R2inv, int* __restrict__ bad) {
+  __shared__ zc Gs[PT_COLS][PT_COLS + 1];
+  __shared__ zc R1s[PT_COLS][PT_COLS + 1];
+  __shared__ zc Ri[PT_COLS][PT_COLS + 1];
+  __shared__ int fl[PT_COLS];
+  const int t = threadIdx.x;
+  const int i = t & 31, j = t >> 5;
+  if (i < nb && j < nb) {
+    double gr = (i == j) ? 1.0 : 0.0, gi = 0.0;
+    for (int q = 0; q < p0; ++q) {
+      const zc a = W2[q + (long)p0 * i], b = W2[q + (long)p0 * j];
+      gr -= a.x * b.x + a.y * b.y;  // conj(a) b
+      gi -= a.x * b.y - a.y * b.x;
+    }
+    Gs[i][j] = make_double2(gr, gi);
+    R1s[i][j] = R1[i + (long)nb * j];
+  }
+  if (t < nb) fl[t] = flags[t];
+  __syncthreads();
+  // upper Cholesky factor in place: G = R2^H R2, row by row
+  for (int r = 0; r < nb; ++r) {
+    if (t == 0) {
+      const double d = Gs[r][r].x;
+      const bool ok = d > 1e-2;
+      if (!ok) *bad = 1;
+      Gs[r][r] = make_double2(ok ? sqrt(d) : 1.0, 0.0);
+    }
+    __syncthreads();
+    const double inv = 1.0 / Gs[r][r].x;
+    if (t > r && t < nb) Gs[r][t] = make_double2(Gs[r][t].x * inv, Gs[r][t].y * inv);
+    __syncthreads();
+    // trailing update G[a][b] -= conj(R[r][a]) R[r][b] for r < a <= b
+    if (i > r && j >= i && j < nb) {
+      const zc a = Gs[r][i], b = Gs[r][j];
+      zc g = Gs[i][j];
+      g.x -= a.x * b.x + a.y * b.y;
+      g.y -= a.x * b.y - a.y * b.x;
+      Gs[i][j] = g;
+    }
+    __syncthreads();
+  }
+  // inverse of the upper factor, one column per thread
+  if (t < nb) {
+    const int c = t;
+    for (int r = 0; r < nb; ++r) Ri[r][c] = make_double2(0.0, 0.0);
+    const double dc = 1.0 / Gs[c][c].x;
+    Ri[c][c] = make_double2(dc, 0.0);
+    for (int r = c - 1; r >= 0; --r) {
+      double sr = 0, si = 0;
+      for (int q = r + 1; q <= c; ++q) {
+        const zc a = Gs[r][q], b = Ri[q][c];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+      const double dr = 1.0 / Gs[r][r].x;
+      Ri[r][c] = make_double2(-sr * dr, -si * dr);
+    }
+  }
+  __syncthreads();
+  if (i < nb && j < nb) {
+    R2inv[i + (long)nb * j] = Ri[i][j];
+    // (R2 R1)[i][j], both upper
+    double sr = 0, si = 0;
+    for (int q = i; q <= j; ++q) {
+      const zc a = Gs[i][q], b = R1s[q][j];
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
+    }
+    Rd[i + ldr * j] = (i <= j && !fl[j]) ? make_double2(sr, si) : make_double2(0.0, 0.0);
+  }
+  // Ro += W2 R1 for unflagged columns
+  for (int e = t; e < p0 * nb; e += 1024) {
+    const int r = e % p0, c = e / p0;
+    if (fl[c]) continue;
+    double sr = 0, si = 0;
+    for (int q = 0; q <= c; ++q) {
+      const zc a = W2[r + (long)p0 * q], b = R1s[q][c];
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
+    }
+    zc v = Ro[r + ldr * c];
+    v.x += sr;
+    v.y += si;
+    Ro[r + ldr * c] = v;
+  }
+}
+
+// Z <- Z Rinv for the m x nb panel Z (ld ldz), Rinv upper nb x nb (ld nb);
+// one row per thread
+__global__ __launch_bounds__(256) void panel_trmm_kernel(zc* __restrict__ Z, long ldz, int m, int nb,
+                                                         const zc* __restrict__ Rinv) {
+  __shared__ zc Rs[PT_COLS][PT_COLS];
+  for (int e = threadIdx.x; e < nb * nb; e += 256) Rs[e % nb][e / nb] = Rinv[e];
+  __syncthreads();
+  const long r = (long)blockIdx.x * 256 + threadIdx.x;
+  if (r >= m) return;
+  zc x[PT_COLS];
+#pragma unroll
+  for (int q = 0; q < PT_COLS; ++q) x[q] = (q < nb) ? Z[r + ldz * q] : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int c = 0; c < PT_COLS; ++c) {
+    if (c >= nb) break;
+    double sr = 0, si = 0;
+#pragma unroll
+    for (int q = 0; q <= c; ++q) {
+      const zc b = Rs[q][c];
+      sr += x[q].x * b.x - x[q].y * b.y;
+      si += x[q].x * b.y + x[q].y * b.x;
+    }
+    Z[r + ldz * c] = make_double2(sr, si);
+  }
+}
+
+void bcgs_pip(tt_ctx* ctx, const zc* W2, int p0, int nb, const zc* R1, zc* Ro, zc* Rd, long ldr, const int* flags,
+              zc* R2inv, int* bad) {
+  if (nb > PT_COLS) fail(TT_EINVAL, "bcgs_pip: panel too wide");
+  KTimer kt(ctx, "hhqr", 8.0 * ((double)p0 * nb * nb * 1.5), 16.0 * (double)p0 * nb);
+  hipLaunchKernelGGL(bcgs_pip_kernel, dim3(1), dim3(1024), 0, ctx->stream, W2, p0, nb, R1, Ro, Rd, ldr, flags, R2inv,
+                     bad);
+  TTF_HIP(hipGetLastError());
+}
+
+void panel_trmm(tt_ctx* ctx, zc* Z, long ldz, int m, int nb, const zc* Rinv) {
+  if (nb > PT_COLS) fail(TT_EINVAL, "panel_trmm: panel too wide");
+  KTimer kt(ctx, "hhqr", 4.0 * (double)m * nb * nb, 32.0 * (double)m * nb);
+  hipLaunchKernelGGL(panel_trmm_kernel, dim3((m + 255) / 256), dim3(256), 0, ctx->stream, Z, ldz, m, nb, Rinv);
   TTF_HIP(hipGetLastError());
 }
 

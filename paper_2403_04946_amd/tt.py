@@ -17,6 +17,7 @@ MAX_D = 128
 
 TT_APPLY_EXACT = 0
 TT_APPLY_SKETCH = 1
+TT_ECAPACITY = -3
 ORTH = {0: "none", 1: "right", 2: "left"}
 ERRORS = {
     -1: "TT_EINVAL",
@@ -102,6 +103,7 @@ _SIGS = {
     "tt_op_create_burgers_hopf": (I, [P, I, I, D, D, ctypes.POINTER(P)]),
     "tt_op_create_burgers_hopf_scaled": (I, [P, I, I, D, D, D, ctypes.POINTER(P)]),
     "tt_op_destroy": (I, [P]),
+    "tt_ctx_dump_stats": (I, [P, ctypes.c_char_p, ctypes.c_long]),
     "tt_op_get_ranks": (I, [P, PI]),
     "tt_op_export_coefficients": (I, [P, PD, PD]),
     "tt_op_export_local_ops": (I, [P, PI, PD]),
@@ -175,8 +177,26 @@ class Context:
     def stream_handle(self):
         return lib().tt_ctx_stream(self.h)
 
-    def set_profiling(self, on):
-        self.check(lib().tt_ctx_set_profiling(self.h, int(bool(on))))
+    def set_profiling(self, on, shapes=False):
+        """Event timing per kernel class; with shapes=True every GEMM is also
+        recorded under "zgemm:<ops>:MxNxKxbatch"."""
+        self.check(lib().tt_ctx_set_profiling(self.h, (2 if shapes else 1) if on else 0))
+
+    def dump_stats(self):
+        """All recorded keys: {key: {"launches", "ms", "flops", "bytes"}}."""
+        cap = 1 << 16
+        while True:
+            buf = ctypes.create_string_buffer(cap)
+            rc = lib().tt_ctx_dump_stats(self.h, buf, cap)
+            if rc != TT_ECAPACITY:
+                self.check(rc)
+                break
+            cap *= 4
+        out = {}
+        for line in buf.value.decode().splitlines():
+            key, n, ms, fl, by = line.rsplit(" ", 4)
+            out[key] = {"launches": int(n), "ms": float(ms), "flops": float(fl), "bytes": float(by)}
+        return out
 
     def reset_stats(self):
         self.check(lib().tt_ctx_reset_stats(self.h))
