@@ -185,16 +185,21 @@ void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* swe
 }
 
 // ------------------------------------------------ block-parallel Jacobi
-__device__ inline double wave64_sum(double x) {
+// A column pair is held by a group of GS lanes (16: one DPP row, 64: a whole
+// wavefront), lane l owning rows l + GS j, j < RPL.
+template <int GS>
+__device__ inline double group_sum(double x) {
   x = row16_sum(x);
-  x += __shfl_xor(x, 16, 64);
-  x += __shfl_xor(x, 32, 64);
+  if (GS == 64) {
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+  }
   return x;
 }
 
-// Rotate the column pair (x, y) held by one wavefront (rows lane + 64 j)
-// so that x^H y = 0; returns 1 when a rotation was applied.
-template <int RPL>
+// Rotate the column pair (x, y) so that x^H y = 0; returns 1 when a
+// rotation was applied.
+template <int RPL, int GS>
 __device__ inline int jacobi_rotate(zc (&x)[RPL], zc (&y)[RPL], double tol) {
   double al = 0, be = 0, gr = 0, gi = 0;
 #pragma unroll
@@ -205,22 +210,25 @@ __device__ inline int jacobi_rotate(zc (&x)[RPL], zc (&y)[RPL], double tol) {
     gr += a.x * c.x + a.y * c.y;  // conj(x) * y
     gi += a.x * c.y - a.y * c.x;
   }
-  al = wave64_sum(al);
-  be = wave64_sum(be);
-  gr = wave64_sum(gr);
-  gi = wave64_sum(gi);
-  const double gg = sqrt(gr * gr + gi * gi);
-  if (!(gg > tol * sqrt(al * be)) || gg == 0.0) return 0;
-  const double zeta = (be - al) / (2.0 * gg);
+  al = group_sum<GS>(al);
+  be = group_sum<GS>(be);
+  gr = group_sum<GS>(gr);
+  gi = group_sum<GS>(gi);
+  const double g2 = gr * gr + gi * gi;
+  if (!(g2 > tol * tol * al * be) || g2 == 0.0) return 0;
+  const double gg = sqrt(g2);
+  const double ig = 1.0 / gg;
+  const double zeta = (be - al) * (0.5 * ig);
   const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-  const double er = gr / gg, ei = gi / gg;  // e^{i phi}
+  const double er = gr * ig, ei = gi * ig;  // e^{i phi}
+  const double ser = sn * er, sei = sn * ei;
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
     const zc a = x[j], c = y[j];
     // x' = cs x - sn e^{-i phi} y ; y' = sn e^{i phi} x + cs y
-    x[j] = make_double2(cs * a.x - sn * (er * c.x + ei * c.y), cs * a.y - sn * (er * c.y - ei * c.x));
-    y[j] = make_double2(sn * (er * a.x - ei * a.y) + cs * c.x, sn * (er * a.y + ei * a.x) + cs * c.y);
+    x[j] = make_double2(cs * a.x - (ser * c.x + sei * c.y), cs * a.y - (ser * c.y - sei * c.x));
+    y[j] = make_double2((ser * a.x - sei * a.y) + cs * c.x, (ser * a.y + sei * a.x) + cs * c.y);
   }
   return 1;
 }
@@ -230,7 +238,7 @@ __device__ inline int jacobi_count(int nrot, int* wg_rot, int* rot, int idx) {
   __syncthreads();
   if (threadIdx.x == 0) *wg_rot = 0;
   __syncthreads();
-  if (nrot && (threadIdx.x & 63) == 0) atomicAdd(wg_rot, nrot);
+  if (nrot && (threadIdx.x & 15) == 0) atomicAdd(wg_rot, nrot);
   __syncthreads();
   const int tot = *wg_rot;
   if (threadIdx.x == 0 && tot) atomicAdd(&rot[idx], tot);
@@ -238,28 +246,28 @@ __device__ inline int jacobi_count(int nrot, int* wg_rot, int* rot, int idx) {
 }
 
 // Cyclic one-sided Jacobi over the 2W columns c0 .. c0 + 2W - 1 (those >= k
-// are absent) with W wavefronts.  Circle ordering: wavefront w holds
-// positions w and 2W-1-w; after each of the 2W-1 rounds positions
-// 1..2W-1 shift by one, so every pair meets once per sweep and after the
-// sweep every column is back in place.  Workgroup g handles the columns
-// starting at 2W g.  Up to inner_max sweeps (sweep counts in rot[sweep ..]);
-// a launch of sweep > 0 returns at once when sweep - 1 rotated nothing.
-template <int RPL, int W>
-__global__ __launch_bounds__(64 * W) void jacobi_circle_kernel(zc* __restrict__ B, int m, int k, int inner_max,
+// are absent) with W lane groups.  Circle ordering: group w holds positions
+// w and 2W-1-w; after each of the 2W-1 rounds positions 1..2W-1 shift by
+// one, so every pair meets once per sweep and after the sweep every column
+// is back in place.  Workgroup g handles the columns starting at 2W g.  Up
+// to inner_max sweeps (counts in rot[sweep ..]); a launch of sweep > 0
+// returns at once when sweep - 1 rotated nothing.
+template <int RPL, int W, int GS>
+__global__ __launch_bounds__(GS * W) void jacobi_circle_kernel(zc* __restrict__ B, int m, int k, int inner_max,
                                                                int sweep, int* __restrict__ rot, double tol) {
-  extern __shared__ double2 xch[];  // W slots of 64 RPL rows
+  extern __shared__ double2 xch[];  // W slots of GS RPL rows
   __shared__ int wg_rot;
   if (sweep > 0 && rot[sweep - 1] == 0) return;
   constexpr int NP = 2 * W - 1;
-  constexpr int LD = 64 * RPL;
+  constexpr int LD = GS * RPL;
   const int c0 = blockIdx.x * 2 * W;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = threadIdx.x / GS, lane = threadIdx.x % GS;
   zc xt[RPL], xb[RPL];
   {
     const int ct = c0 + w, cb = c0 + 2 * W - 1 - w;
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
-      const int row = lane + 64 * j;
+      const int row = lane + GS * j;
       xt[j] = (ct < k && row < m) ? B[row + (long)m * ct] : make_double2(0.0, 0.0);
       xb[j] = (cb < k && row < m) ? B[row + (long)m * cb] : make_double2(0.0, 0.0);
     }
@@ -271,18 +279,18 @@ __global__ __launch_bounds__(64 * W) void jacobi_circle_kernel(zc* __restrict__ 
       // positions w and 2W-1-w after r shifts
       const int pt = (w == 0) ? 0 : ((w - 1 - r) % NP + NP) % NP + 1;
       const int pb = ((2 * W - 2 - w - r) % NP + NP) % NP + 1;
-      if (c0 + pt < k && c0 + pb < k) nrot += jacobi_rotate<RPL>(xt, xb, tol);
-      // shift: bottoms move to the previous wavefront (the last one takes
-      // its own top), then tops to the next one (wavefront 1 takes
-      // wavefront 0's old bottom, left in slot 0 by the first phase)
+      if (c0 + pt < k && c0 + pb < k) nrot += jacobi_rotate<RPL, GS>(xt, xb, tol);
+      // shift: bottoms move to the previous group (the last one takes its
+      // own top), then tops to the next one (group 1 takes group 0's old
+      // bottom, left in slot 0 by the first phase)
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < RPL; ++j) mine[lane + 64 * j] = xb[j];
+      for (int j = 0; j < RPL; ++j) mine[lane + GS * j] = xb[j];
       __syncthreads();
       if (w <= W - 2) {
         const zc* src = mine + LD;
 #pragma unroll
-        for (int j = 0; j < RPL; ++j) xb[j] = src[lane + 64 * j];
+        for (int j = 0; j < RPL; ++j) xb[j] = src[lane + GS * j];
       } else {
 #pragma unroll
         for (int j = 0; j < RPL; ++j) xb[j] = xt[j];
@@ -290,13 +298,13 @@ __global__ __launch_bounds__(64 * W) void jacobi_circle_kernel(zc* __restrict__ 
       __syncthreads();
       if (w >= 1 && w <= W - 2) {
 #pragma unroll
-        for (int j = 0; j < RPL; ++j) mine[lane + 64 * j] = xt[j];
+        for (int j = 0; j < RPL; ++j) mine[lane + GS * j] = xt[j];
       }
       __syncthreads();
       if (w >= 1) {
         const zc* src = mine - LD;
 #pragma unroll
-        for (int j = 0; j < RPL; ++j) xt[j] = src[lane + 64 * j];
+        for (int j = 0; j < RPL; ++j) xt[j] = src[lane + GS * j];
       }
     }
     const int tot = jacobi_count(nrot, &wg_rot, rot, sweep + it);
@@ -305,7 +313,7 @@ __global__ __launch_bounds__(64 * W) void jacobi_circle_kernel(zc* __restrict__ 
   const int ct = c0 + w, cb = c0 + 2 * W - 1 - w;
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
-    const int row = lane + 64 * j;
+    const int row = lane + GS * j;
     if (row < m) {
       if (ct < k) B[row + (long)m * ct] = xt[j];
       if (cb < k) B[row + (long)m * cb] = xb[j];
@@ -315,25 +323,25 @@ __global__ __launch_bounds__(64 * W) void jacobi_circle_kernel(zc* __restrict__ 
 
 // All 16 x 16 column pairs between blocks a and b (16 columns each; the
 // pair of workgroup g in round `round` of a round-robin over P blocks):
-// wavefront w keeps column 16a + w and meets column 16b + (w + s) mod 16 in
-// step s; between steps the b columns move to the previous wavefront.
-template <int RPL>
-__global__ __launch_bounds__(1024) void jacobi_cross_kernel(zc* __restrict__ B, int m, int k, int P, int round,
-                                                            int sweep, int* __restrict__ rot, double tol) {
-  extern __shared__ double2 xch[];  // 16 slots of 64 RPL rows
+// group w keeps column 16a + w and meets column 16b + (w + s) mod 16 in
+// step s; between steps the b columns move to the previous group.
+template <int RPL, int GS>
+__global__ __launch_bounds__(16 * GS) void jacobi_cross_kernel(zc* __restrict__ B, int m, int k, int P, int round,
+                                                               int sweep, int* __restrict__ rot, double tol) {
+  extern __shared__ double2 xch[];  // 16 slots of GS RPL rows
   __shared__ int wg_rot;
   if (sweep > 0 && rot[sweep - 1] == 0) return;
-  constexpr int LD = 64 * RPL;
+  constexpr int LD = GS * RPL;
   int ba, bb;
   rr_pair(P, round, blockIdx.x, ba, bb);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = threadIdx.x / GS, lane = threadIdx.x % GS;
   const int ca = ba * JB_COLS + w;
   zc xa[RPL], xb[RPL];
   {
     const int cb = bb * JB_COLS + w;
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
-      const int row = lane + 64 * j;
+      const int row = lane + GS * j;
       xa[j] = (ca < k && row < m) ? B[row + (long)m * ca] : make_double2(0.0, 0.0);
       xb[j] = (cb < k && row < m) ? B[row + (long)m * cb] : make_double2(0.0, 0.0);
     }
@@ -343,20 +351,20 @@ __global__ __launch_bounds__(1024) void jacobi_cross_kernel(zc* __restrict__ B, 
   int nrot = 0;
   for (int st = 0; st < JB_COLS; ++st) {
     const int cb = bb * JB_COLS + ((w + st) & 15);
-    if (ca < k && cb < k) nrot += jacobi_rotate<RPL>(xa, xb, tol);
+    if (ca < k && cb < k) nrot += jacobi_rotate<RPL, GS>(xa, xb, tol);
     if (st == JB_COLS - 1) break;
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) mine[lane + 64 * j] = xb[j];
+    for (int j = 0; j < RPL; ++j) mine[lane + GS * j] = xb[j];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) xb[j] = next[lane + 64 * j];
+    for (int j = 0; j < RPL; ++j) xb[j] = next[lane + GS * j];
   }
   jacobi_count(nrot, &wg_rot, rot, sweep);
   const int cb = bb * JB_COLS + ((w + JB_COLS - 1) & 15);
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
-    const int row = lane + 64 * j;
+    const int row = lane + GS * j;
     if (row < m) {
       if (ca < k) B[row + (long)m * ca] = xa[j];
       if (cb < k) B[row + (long)m * cb] = xb[j];
@@ -412,19 +420,19 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(int m, int k, const
   }
 }
 
-template <int RPL>
+template <int RPL, int GS>
 void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int round, int inner_max, int sweep,
                        int* rot, double tol) {
-  const size_t slot = sizeof(zc) * 64 * RPL;
+  const size_t slot = sizeof(zc) * GS * RPL;
   if (kind == 0)  // whole matrix (k <= 32) in one workgroup
-    hipLaunchKernelGGL((jacobi_circle_kernel<RPL, 16>), dim3(1), dim3(1024), 16 * slot, ctx->stream, B, m, k,
+    hipLaunchKernelGGL((jacobi_circle_kernel<RPL, 16, GS>), dim3(1), dim3(16 * GS), 16 * slot, ctx->stream, B, m, k,
                        inner_max, sweep, rot, tol);
   else if (kind == 1)  // every block of 16 columns on its own
-    hipLaunchKernelGGL((jacobi_circle_kernel<RPL, 8>), dim3((k + 15) / 16), dim3(512), 8 * slot, ctx->stream, B, m,
-                       k, 1, sweep, rot, tol);
+    hipLaunchKernelGGL((jacobi_circle_kernel<RPL, 8, GS>), dim3((k + 15) / 16), dim3(8 * GS), 8 * slot, ctx->stream,
+                       B, m, k, 1, sweep, rot, tol);
   else
-    hipLaunchKernelGGL(jacobi_cross_kernel<RPL>, dim3(P / 2), dim3(1024), 16 * slot, ctx->stream, B, m, k, P, round,
-                       sweep, rot, tol);
+    hipLaunchKernelGGL((jacobi_cross_kernel<RPL, GS>), dim3(P / 2), dim3(16 * GS), 16 * slot, ctx->stream, B, m, k,
+                       P, round, sweep, rot, tol);
   TTF_HIP(hipGetLastError());
 }
 
@@ -432,16 +440,21 @@ void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int ro
 // inside a block) followed by the P - 1 rounds of a round-robin over the
 // blocks (all pairs between two blocks), so each column pair meets once.
 void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
-  const int rpl = (m + 63) / 64;
+  // a 16-lane group per column pair up to 320 rows (at most 20 rows per
+  // lane), a whole wavefront beyond
   auto launch = [&](int kind, int P, int round, int inner_max, int sweep, int* rot, double tol) {
-    if (rpl <= 2)
-      jacobi_launch_rpl<2>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
-    else if (rpl <= 4)
-      jacobi_launch_rpl<4>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
-    else if (rpl <= 5)
-      jacobi_launch_rpl<5>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+    if (m <= 64)
+      jacobi_launch_rpl<4, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+    else if (m <= 128)
+      jacobi_launch_rpl<8, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+    else if (m <= 192)
+      jacobi_launch_rpl<12, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+    else if (m <= 256)
+      jacobi_launch_rpl<16, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+    else if (m <= 320)
+      jacobi_launch_rpl<20, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
     else
-      jacobi_launch_rpl<8>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+      jacobi_launch_rpl<8, 64>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
   };
   const double tol = 1e-15 * sqrt((double)m);
   const int nblk = (k + JB_COLS - 1) / JB_COLS;
