@@ -82,12 +82,18 @@ void* tt_ctx_stream(const tt_ctx* ctx);
 
 /* Per-kernel timing with HIP events on the context stream (off by default).
  * on = 0 off, 1 on, 2 on and every GEMM also recorded under the key
- * "zgemm:<opA><opB>:MxNxKxbatch".  Named kernel classes: "zgemm", "gather",
- * "hhqr" (panel Householder QR and its assembly), "jacobi", "apply_exact",
- * "concat", "eval".  flops / bytes are the algorithmic counts of the
- * launches recorded; times are summed event durations.  Every call syncs
- * the context stream. */
+ * "zgemm:<opA><opB>:MxNxKxbatch".  Kernel classes (one kernel each unless
+ * noted): "zgemm" (the GEMM proper), "zgemm_reduce" (its split-K
+ * reduction), "pt_leaf" (LDS panel Householder QR leaves), "pt_assemble",
+ * "bcgs_pip", "panel_trmm", "jacobi_svd" (a whole small SVD: several
+ * kernels and one host synchronisation), "gather_left", "gather_right",
+ * "apply_exact", "concat", "eval".  flops / bytes are the algorithmic counts
+ * of the launches recorded; times are summed event durations.  Every call
+ * syncs the context stream. */
 int tt_ctx_set_profiling(tt_ctx* ctx, int on);
+/* Restrict event timing to one kernel class (NULL or "" = all classes), so
+ * that a timed run pays the event overhead of that class only. */
+int tt_ctx_set_profile_filter(tt_ctx* ctx, const char* kernel);
 int tt_ctx_reset_stats(tt_ctx* ctx);
 int tt_ctx_get_stats(tt_ctx* ctx, const char* kernel, double* total_ms,
                      double* flops, double* bytes, long long* launches);

@@ -18,6 +18,7 @@ void hip_check(hipError_t e, const char* what) {
 
 KTimer::KTimer(tt_ctx* c, const char* nm, double fl, double by) : ctx(c), name(nm), flops(fl), bytes(by) {
   if (!ctx || !ctx->profiling) return;
+  if (!ctx->profile_only.empty() && ctx->profile_only != nm) return;
   auto take = [&]() {
     hipEvent_t e;
     if (!ctx->free_events.empty()) {
@@ -159,25 +160,29 @@ void ptsqr_inplace(tt_ctx* ctx, int m, int k, zc* q, long ldq, zc* r, long ldr, 
 // Per panel: project out the earlier columns (W = Q^H A_p, A_p -= Q W);
 // replace every column whose residual is below 1e-13 of its norm (a column
 // dependent on the earlier ones, or zero) by a Gaussian vector, to be
-// left out of R; factor the panel with the Householder TSQR (Q1 R1); then
-// project once more.  robust = false finishes with the Pythagorean
-// shortcut (Cholesky of I - W2^H W2, see bcgs_pip) and raises *bad when it
-// is not safe; robust = true factors the reprojected panel again with the
-// Householder TSQR.
-void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, bool robust, int* bad) {
+// left out of R; factor the panel (Q1 R1); then project once more.
+// level 0 factors the panel by Cholesky QR twice, levels 1 and 2 by the
+// Householder TSQR; levels 0 and 1 finish with the Pythagorean shortcut
+// (Cholesky of I - W2^H W2, see bcgs_pip), level 2 factors the reprojected
+// panel again with the TSQR.  Shortcuts raise *bad when they are not safe
+// for the data (bad may be null at level 2).
+void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* bad) {
   require(m >= k && k >= 1, TT_EINVAL, "qr: need m >= k >= 1");
   const int NB = pt_max_cols();
   fill_zero(ctx, r, (long)k * k);
   // small work: W2, T (k x NB), R1, R2, Rpp (NB x NB), flags, norm partials
   const size_t kb = (size_t)k * NB, bb = (size_t)NB * NB;
   const int G = bcgs_flag_groups(m);
-  zc* W2 = (zc*)ctx->get_ws("bcgs_small", sizeof(zc) * (2 * kb + 3 * bb) + sizeof(double) * ((size_t)(G + 1) * NB));
+  zc* W2 = (zc*)ctx->get_ws("bcgs_small", sizeof(zc) * (2 * kb + 6 * bb) + sizeof(double) * ((size_t)(G + 1) * NB));
   zc* T = W2 + kb;
   zc* R1 = T + kb;
   zc* R2 = R1 + bb;
   zc* Rpp = R2 + bb;
-  int* flags = (int*)(Rpp + bb);
-  double* part = (double*)(Rpp + bb) + NB;  // NB ints fit in NB doubles
+  zc* Gm = Rpp + bb;
+  zc* Ra = Gm + bb;
+  zc* Rinv = Ra + bb;
+  int* flags = (int*)(Rinv + bb);
+  double* part = (double*)(Rinv + bb) + NB;  // NB ints fit in NB doubles
   for (int p0 = 0; p0 < k; p0 += NB) {
     const int nb = std::min(NB, k - p0);
     zc* Ap = q + (long)m * p0;
@@ -188,14 +193,22 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, bool robust, int* 
     }
     bcgs_flag(ctx, Ap, m, m, nb, Rp, k, p0, flags, part);
     bcgs_random(ctx, Ap, m, m, nb, flags, 0x243F6A8885A308D3ull, p0);
-    ptsqr_inplace(ctx, m, nb, Ap, m, R1, nb, 0);
+    if (level == 0) {
+      // Cholesky QR twice: Y = Y Ra^{-1}, then again with Rb; R1 = Rb Ra
+      zgemm(ctx, OPC, OPN, nb, nb, m, Z(1), Ap, m, 0, Ap, m, 0, Z(0), Gm, nb, 0);
+      chol_solve(ctx, Ap, m, m, nb, Gm, 1e-12, nullptr, Ra, bad);
+      zgemm(ctx, OPC, OPN, nb, nb, m, Z(1), Ap, m, 0, Ap, m, 0, Z(0), Gm, nb, 0);
+      chol_solve(ctx, Ap, m, m, nb, Gm, 0.5, Ra, R1, bad);
+    } else {
+      ptsqr_inplace(ctx, m, nb, Ap, m, R1, nb, 0);
+    }
     if (p0 == 0) {
       bcgs_put_diag(ctx, r, k, R1, nb, flags);
       continue;
     }
     zgemm(ctx, OPC, OPN, p0, nb, m, Z(1), q, m, 0, Ap, m, 0, Z(0), W2, p0, 0);
     zgemm(ctx, OPN, OPN, m, nb, p0, Z(-1), q, m, 0, W2, p0, 0, Z(1), Ap, m, 0);
-    if (robust) {
+    if (level == 2) {
       ptsqr_inplace(ctx, m, nb, Ap, m, R2, nb, 0);
       zgemm(ctx, OPN, OPN, nb, nb, nb, Z(1), R2, nb, 0, R1, nb, 0, Z(0), Rpp, nb, 0);
       zgemm(ctx, OPN, OPN, p0, nb, nb, Z(1), W2, p0, 0, R1, nb, 0, Z(0), T, p0, 0);
@@ -208,22 +221,27 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, bool robust, int* 
   }
 }
 
-// Runs the fast form and checks its flag (one host synchronisation); when
-// the shortcut was unsafe for some panel, `load` refills q and the robust
-// form runs.
+// Runs the fastest form and checks its flag (one host synchronisation per
+// attempt); when a shortcut was unsafe for some panel, `load` refills q and
+// the next, more robust form runs: level 0 factors each projected panel by
+// Cholesky QR twice, level 1 by the Householder TSQR, both finishing with
+// the Pythagorean second pass; level 2 uses the Householder TSQR for both
+// passes and cannot fail.
 template <class Load>
 void qr_checked(tt_ctx* ctx, int m, int k, zc* q, zc* r, Load load) {
   int* bad = (int*)ctx->get_ws("qr_bad", 64);
-  zero_ints(ctx, bad, 1);
-  load();
-  bcgs_qr_inplace(ctx, m, k, q, r, false, bad);
   int* h = (int*)ctx->host_scratch(64);
-  TTF_HIP(hipMemcpyAsync(h, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  TTF_HIP(hipStreamSynchronize(ctx->stream));
-  if (h[0] == 0) return;
-  ctx->qr_fallbacks += 1;
+  for (int level = 0; level < 2; ++level) {
+    zero_ints(ctx, bad, 1);
+    load();
+    bcgs_qr_inplace(ctx, m, k, q, r, level, bad);
+    TTF_HIP(hipMemcpyAsync(h, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    TTF_HIP(hipStreamSynchronize(ctx->stream));
+    if (h[0] == 0) return;
+    ctx->qr_fallbacks += 1;
+  }
   load();
-  bcgs_qr_inplace(ctx, m, k, q, r, true, nullptr);
+  bcgs_qr_inplace(ctx, m, k, q, r, 2, nullptr);
 }
 
 // QR of A (m x k, ld lda, m >= k): Q (m x k, ld m), R (k x k, ld k).
@@ -754,6 +772,15 @@ int tt_ctx_set_profiling(tt_ctx* ctx, int on) {
   ctx->sync();
   ctx->profiling = on != 0;
   ctx->profile_shapes = on == 2;
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_ctx_set_profile_filter(tt_ctx* ctx, const char* kernel) {
+  if (!ctx) return TT_EINVAL;
+  ABI_TRY
+  ctx->sync();
+  ctx->profile_only = kernel ? kernel : "";
   return TT_OK;
   ABI_CATCH(ctx)
 }

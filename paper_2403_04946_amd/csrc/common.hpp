@@ -68,6 +68,7 @@ struct tt_ctx {
   bool profiling = false;
   bool profile_shapes = false;  // also key GEMM timings by shape
   long long qr_fallbacks = 0;   // QRs redone in the robust form
+  std::string profile_only;     // when set, only this kernel class is timed
   struct Stat {
     double ms = 0, flops = 0, bytes = 0;
     long long n = 0;
@@ -158,7 +159,10 @@ void bcgs_flag(tt_ctx* ctx, const zc* Y, long ldy, int m, int nb, const zc* W, l
 int bcgs_flag_groups(int m);  // partial sums used by bcgs_flag (part holds groups * nb)
 void bcgs_pip(tt_ctx* ctx, const zc* W2, int p0, int nb, const zc* R1, zc* Ro, zc* Rd, long ldr, const int* flags,
               zc* R2inv, int* bad);
+void chol_solve(tt_ctx* ctx, zc* Y, long ldy, int m, int nb, const zc* G, double tau, const zc* Rprev, zc* Rout,
+                int* bad);
 void panel_trmm(tt_ctx* ctx, zc* Z, long ldz, int m, int nb, const zc* Rinv);
+void chol_inv(tt_ctx* ctx, const zc* G, int nb, double tau, const zc* Rprev, zc* Rout, zc* Rinv, int* bad);
 void zero_ints(tt_ctx* ctx, int* x, int n);
 void bcgs_random(tt_ctx* ctx, zc* Qp, long ldq, int m, int nb, const int* flags, uint64_t seed, int tag);
 void bcgs_masked_add(tt_ctx* ctx, zc* Rd, long ldr, const zc* W, long ldw, int rows, int nb, const int* flags);

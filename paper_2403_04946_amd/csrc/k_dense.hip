@@ -167,7 +167,7 @@ void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* swe
     lds_limit = v;
   }
   // per sweep: k(k-1)/2 pairs x (16 m for the inner products + 28 m for the rotation)
-  KTimer kt(ctx, "jacobi", 0.0, 0.0);
+  KTimer kt(ctx, "jacobi_svd", 0.0, 0.0);
   if (m <= JB_MAXM && JB_MAXS >= JAC_MAX_SWEEPS) {
     jacobi_blocked(ctx, m, k, B, U, sigma, sweeps);
     return;

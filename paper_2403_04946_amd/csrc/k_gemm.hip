@@ -5,8 +5,9 @@
 // TT arithmetic (orthogonalisation factors pushed into neighbour cores,
 // Gram matrices, sketch contractions, Q * U products) is one of these.
 //
-// Workgroup tile 64 x 64, K step 16, 256 threads = 4 wavefronts of 64 lanes;
-// each wavefront owns a 32 x 32 sub-tile = 2 x 2 MFMA tiles of 16 x 16.
+// Workgroup tiles 64 x 64, 128 x 32, 64 x 32, 32 x 32 or 32 x 64 (chosen by
+// the output shape), K step 16, 256 threads = 4 wavefronts of 64 lanes in a
+// 2 x 2 arrangement; operand ops are template parameters.
 // A complex product is four real MFMAs: Re += Ar Br - Ai Bi,
 // Im += Ar Bi + Ai Br (the imaginary part of A is negated once in LDS for
 // the subtraction).  Operand tiles are staged through LDS as separate real
@@ -21,10 +22,10 @@ namespace ttf {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
+constexpr int BK = 16, PAD = 1;
 
 struct GemmParams {
-  int M, N, K, opA, opB, kchunk;
+  int M, N, K, kchunk;
   const zc* A;
   long lda, sA;
   const zc* B;
@@ -36,81 +37,98 @@ struct GemmParams {
   zc* ws;  // split-K partials: [split][batch][N][M] (column major M x N)
 };
 
-__device__ inline zc load_a(const GemmParams& p, const zc* A, int m, int k) {
-  if (m >= p.M || k >= p.K) return make_double2(0.0, 0.0);
-  if (p.opA == OPN) return A[m + p.lda * (long)k];
-  zc v = A[k + p.lda * (long)m];
-  if (p.opA == OPC) v.y = -v.y;
+template <int OP>
+__device__ inline zc load_op(const zc* X, long ld, int r, int c, int R, int Ccount) {
+  // element (r, c) of op(X), R x Ccount, zero outside
+  if (r >= R || c >= Ccount) return make_double2(0.0, 0.0);
+  if (OP == OPN) return X[r + ld * (long)c];
+  zc v = X[c + ld * (long)r];
+  if (OP == OPC) v.y = -v.y;
   return v;
 }
 
-__device__ inline zc load_b(const GemmParams& p, const zc* B, int k, int n) {
-  if (k >= p.K || n >= p.N) return make_double2(0.0, 0.0);
-  if (p.opB == OPN) return B[k + p.ldb * (long)n];
-  zc v = B[n + p.ldb * (long)k];
-  if (p.opB == OPC) v.y = -v.y;
-  return v;
-}
-
+// Workgroup tile BM x BN, 256 threads = 2 x 2 wavefronts, each owning a
+// (BM/2) x (BN/2) block of (BM/32) x (BN/32) MFMA tiles of 16 x 16.
+// blockIdx.x runs over N tiles (fastest), so consecutive workgroups share
+// the A tile through L2.
+template <int OPA, int OPB, int BM, int BN>
 __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
+  constexpr int TI = BM / 32, TJ = BN / 32;
+  constexpr int RA = BM * BK / 256, RB = BN * BK / 256;  // elements per thread
   __shared__ double Ar[BK][BM + PAD], Ai[BK][BM + PAD];  // Ai holds -Im(A)
-  __shared__ double Br[BK][BN + PAD], Bi[BK][BN + PAD];
   __shared__ double Ap[BK][BM + PAD];                    // +Im(A)
+  __shared__ double Br[BK][BN + PAD], Bi[BK][BN + PAD];
 
   const int nsplit = gridDim.z / p.batch;
   const int bz = blockIdx.z % p.batch;
   const int split = blockIdx.z / p.batch;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
   const int kbeg = split * p.kchunk;
   const int kend = min(p.K, kbeg + p.kchunk);
   const zc* A = p.A + p.sA * (long)bz;
   const zc* B = p.B + p.sB * (long)bz;
 
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
   const int lr = lane & 15, lk = lane >> 4;
 
-  dbl4 accR[2][2], accI[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
+  dbl4 accR[TI][TJ], accI[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
       accR[i][j] = dbl4{0, 0, 0, 0};
       accI[i][j] = dbl4{0, 0, 0, 0};
     }
 
-  zc ra[4], rb[4];
+  // thread -> (row, k) of the A tile and (k, col) of the B tile, following
+  // the memory order of each operand so that global loads coalesce
+  auto a_idx = [&](int r, int& mm, int& kk) {
+    if (OPA == OPN) {
+      mm = t % BM;
+      kk = t / BM + (256 / BM) * r;
+    } else {
+      kk = t % BK;
+      mm = t / BK + (256 / BK) * r;
+    }
+  };
+  auto b_idx = [&](int r, int& kk, int& nn) {
+    if (OPB == OPN) {
+      kk = t % BK;
+      nn = t / BK + (256 / BK) * r;
+    } else {
+      nn = t % BN;
+      kk = t / BN + (256 / BN) * r;
+    }
+  };
+  zc ra[RA], rb[RB];
   auto gload = [&](int k0) {
-    for (int r = 0; r < 4; ++r) {
-      if (p.opA == OPN)
-        ra[r] = load_a(p, A, m0 + (t & 63), k0 + (t >> 6) + 4 * r);
-      else
-        ra[r] = load_a(p, A, m0 + (t >> 4) + 16 * r, k0 + (t & 15));
-      if (p.opB == OPN)
-        rb[r] = load_b(p, B, k0 + (t & 15), n0 + (t >> 4) + 16 * r);
-      else
-        rb[r] = load_b(p, B, k0 + (t >> 6) + 4 * r, n0 + (t & 63));
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      int mm, kk;
+      a_idx(r, mm, kk);
+      ra[r] = load_op<OPA>(A, p.lda, m0 + mm, k0 + kk, p.M, kend);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      int kk, nn;
+      b_idx(r, kk, nn);
+      rb[r] = load_op<OPB>(B, p.ldb, k0 + kk, n0 + nn, kend, p.N);
     }
   };
   auto sstore = [&]() {
-    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
       int mm, kk;
-      if (p.opA == OPN) {
-        mm = t & 63;
-        kk = (t >> 6) + 4 * r;
-      } else {
-        mm = (t >> 4) + 16 * r;
-        kk = t & 15;
-      }
+      a_idx(r, mm, kk);
       Ar[kk][mm] = ra[r].x;
       Ai[kk][mm] = -ra[r].y;
       Ap[kk][mm] = ra[r].y;
-      int nn;
-      if (p.opB == OPN) {
-        kk = t & 15;
-        nn = (t >> 4) + 16 * r;
-      } else {
-        kk = (t >> 6) + 4 * r;
-        nn = t & 63;
-      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      int kk, nn;
+      b_idx(r, kk, nn);
       Br[kk][nn] = rb[r].x;
       Bi[kk][nn] = rb[r].y;
     }
@@ -126,18 +144,22 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
     if (more) gload(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      double ar[2], an[2], ap[2], br[2], bi[2];
-      for (int i = 0; i < 2; ++i) {
+      double ar[TI], an[TI], ap[TI], br[TJ], bi[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
         ar[i] = Ar[ks + lk][wm + 16 * i + lr];
         an[i] = Ai[ks + lk][wm + 16 * i + lr];
         ap[i] = Ap[ks + lk][wm + 16 * i + lr];
       }
-      for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
         br[j] = Br[ks + lk][wn + 16 * j + lr];
         bi[j] = Bi[ks + lk][wn + 16 * j + lr];
       }
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
           accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
           accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[i], bi[j], accR[i][j], 0, 0, 0);
           accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
@@ -153,8 +175,11 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
 
   // v_mfma_f64_16x16x4f64 result layout: register v of lane l holds
   // D[4 v + l/16][l % 16] of each 16 x 16 tile
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + wm + 16 * i + 4 * v + lk;
         const int n = n0 + wn + 16 * j + lr;
@@ -183,12 +208,27 @@ __global__ void splitk_reduce(GemmParams p, int nsplit) {
     const int bz = (int)(e / ((long)p.M * p.N));
     const long mn = e - (long)bz * p.M * p.N;
     const int n = (int)(mn / p.M), m = (int)(mn - (long)n * p.M);
-    double re = 0, im = 0;
-    for (int s = 0; s < nsplit; ++s) {
-      const zc v = p.ws[((long)s * p.batch + bz) * (long)p.M * p.N + mn];
-      re += v.x;
-      im += v.y;
+    // eight independent partial sums keep eight loads in flight; they are
+    // combined in a fixed order, so the result does not depend on timing
+    const long stride = (long)p.batch * p.M * p.N;
+    const zc* src = p.ws + (long)bz * p.M * p.N + mn;
+    double pr[8] = {0, 0, 0, 0, 0, 0, 0, 0}, pi[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int s = 0;
+    for (; s + 8 <= nsplit; s += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const zc v = src[stride * (s + u)];
+        pr[u] += v.x;
+        pi[u] += v.y;
+      }
     }
+    for (int u = 0; s < nsplit; ++s, ++u) {
+      const zc v = src[stride * s];
+      pr[u] += v.x;
+      pi[u] += v.y;
+    }
+    const double re = ((pr[0] + pr[1]) + (pr[2] + pr[3])) + ((pr[4] + pr[5]) + (pr[6] + pr[7]));
+    const double im = ((pi[0] + pi[1]) + (pi[2] + pi[3])) + ((pi[4] + pi[5]) + (pi[6] + pi[7]));
     zc* C = p.C + p.sC * (long)bz;
     zc out = make_double2(p.alpha.x * re - p.alpha.y * im, p.alpha.x * im + p.alpha.y * re);
     const long off = m + p.ldc * (long)n;
@@ -201,6 +241,26 @@ __global__ void splitk_reduce(GemmParams p, int nsplit) {
   }
 }
 
+template <int BM, int BN>
+void launch_tile(int opA, int opB, dim3 grid, hipStream_t st, const GemmParams& p) {
+#define TTF_GEMM_CASE(OA, OB)                                                             \
+  if (opA == OA && opB == OB) {                                                           \
+    hipLaunchKernelGGL((zgemm_kernel<OA, OB, BM, BN>), grid, dim3(256), 0, st, p);        \
+    return;                                                                               \
+  }
+  TTF_GEMM_CASE(OPN, OPN)
+  TTF_GEMM_CASE(OPN, OPT)
+  TTF_GEMM_CASE(OPN, OPC)
+  TTF_GEMM_CASE(OPT, OPN)
+  TTF_GEMM_CASE(OPT, OPT)
+  TTF_GEMM_CASE(OPT, OPC)
+  TTF_GEMM_CASE(OPC, OPN)
+  TTF_GEMM_CASE(OPC, OPT)
+  TTF_GEMM_CASE(OPC, OPC)
+#undef TTF_GEMM_CASE
+  fail(TT_EINVAL, "zgemm: bad op");
+}
+
 void zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const zc* A, long lda,
            long strideA, const zc* B, long ldb, long strideB, zc beta, zc* C, long ldc, long strideC,
            int batch) {
@@ -210,30 +270,42 @@ void zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const z
     K = 0;
   }
   GemmParams p;
-  p.M = M; p.N = N; p.K = K; p.opA = opA; p.opB = opB;
+  p.M = M; p.N = N; p.K = K;
   p.A = A; p.lda = lda; p.sA = strideA;
   p.B = B; p.ldb = ldb; p.sB = strideB;
   p.C = C; p.ldc = ldc; p.sC = strideC;
   p.alpha = alpha; p.beta = beta; p.batch = batch; p.ws = nullptr;
-  const int gx = (M + BM - 1) / BM, gy = (N + BN - 1) / BN;
+  // tile shape: narrow outputs take 32-wide tiles, tall ones 128 rows
+  int bm = 64, bn = 64;
+  if (N <= 32) {
+    bn = 32;
+    bm = (M <= 32) ? 32 : (M >= 4096 ? 128 : 64);
+  } else if (M <= 32) {
+    bm = 32;
+    bn = 64;
+  }
+  const int gx = (N + bn - 1) / bn, gy = (M + bm - 1) / bm;
   const long tiles = (long)gx * gy * batch;
-  // split K when the output grid alone cannot occupy the chip
+  // split K when the output grid alone cannot occupy the chip (about two
+  // workgroups per compute unit), keeping at least two K steps per split
   int nsplit = 1;
   const int kblocks = (K + BK - 1) / BK;
-  if (tiles < 512 && kblocks >= 8) {
-    nsplit = (int)std::min<long>((1024 + tiles - 1) / tiles, kblocks / 4);
-    nsplit = std::max(1, std::min(nsplit, 64));
+  if (tiles < 512 && kblocks >= 4) {
+    nsplit = (int)std::min<long>((512 + tiles - 1) / tiles, kblocks / 2);
+    nsplit = std::max(1, std::min(nsplit, 128));
   }
   int kchunk = ((kblocks + nsplit - 1) / nsplit) * BK;
   if (K == 0) kchunk = 0;
   nsplit = (K == 0) ? 1 : (K + kchunk - 1) / kchunk;
   p.kchunk = kchunk;
   const double flops = 8.0 * M * N * (double)K * batch;
-  const double bytes = 16.0 * ((double)M * K + (double)K * N + 2.0 * M * N) * batch;
+  // algorithmic bytes of the product: operands read once, C written once
+  // (and read once when beta != 0); split-K partials are the reduce's
+  const double bytes = 16.0 * ((double)M * K + (double)K * N + (1.0 + (beta.x != 0.0 || beta.y != 0.0)) * M * N) * batch;
   if (nsplit > 1) {
     p.ws = (zc*)ctx->get_ws("gemm_splitk", sizeof(zc) * (size_t)nsplit * batch * M * N);
   }
-  if ((long)batch * nsplit > 65535) fail(TT_EINVAL, "zgemm: batch * split too large for the grid");
+  if ((long)batch * nsplit > 65535 || gy > 65535) fail(TT_EINVAL, "zgemm: grid too large");
   {
     // with shape profiling on, the launch is also recorded under its shape
     std::string shape;
@@ -243,11 +315,24 @@ void zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const z
               std::to_string(K) + "x" + std::to_string(batch);
     }
     KTimer kt2(ctx->profile_shapes ? ctx : nullptr, shape.c_str(), flops, bytes);
-    KTimer kt(ctx, "zgemm", flops, bytes);
-    hipLaunchKernelGGL(zgemm_kernel, dim3(gx, gy, batch * nsplit), dim3(256), 0, ctx->stream, p);
+    {
+      KTimer kt(ctx, "zgemm", flops, bytes);
+      const dim3 grid(gx, gy, batch * nsplit);
+      if (bm == 64 && bn == 64)
+        launch_tile<64, 64>(opA, opB, grid, ctx->stream, p);
+      else if (bm == 128)
+        launch_tile<128, 32>(opA, opB, grid, ctx->stream, p);
+      else if (bm == 64)
+        launch_tile<64, 32>(opA, opB, grid, ctx->stream, p);
+      else if (bn == 32)
+        launch_tile<32, 32>(opA, opB, grid, ctx->stream, p);
+      else
+        launch_tile<32, 64>(opA, opB, grid, ctx->stream, p);
+    }
     if (nsplit > 1) {
       const long total = (long)M * N * batch;
       const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+      KTimer kt(ctx, "zgemm_reduce", 0.0, 16.0 * (double)total * (nsplit + 1 + (p.beta.x != 0.0 || p.beta.y != 0.0)));
       hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, ctx->stream, p, nsplit);
     }
   }

@@ -158,8 +158,10 @@ void pt_leaves(tt_ctx* ctx, zc* Q, long ldq, int nleaves, int m, int k, zc* R, l
   // leaf sizes are floor(m / P) or ceil(m / P)
   if (k < 1 || k > PT_COLS || nleaves < 1 || m / nleaves < k || (m + nleaves - 1) / nleaves > PT_ROWS)
     fail(TT_EINVAL, "panel QR: bad block shape");
-  const double flops = 8.0 * (8.0 * (double)m * k * k - 8.0 / 3.0 * (double)k * k * k * nleaves);
-  KTimer kt(ctx, "hhqr", flops, 32.0 * (double)m * k);
+  // Householder factorisation and explicit Q of each leaf (b x k):
+  // 2 x (8 b k^2 - 8 k^3 / 3) real flops; the block is read and written once
+  const double flops = 16.0 * (double)m * k * k - 16.0 / 3.0 * (double)k * k * k * nleaves;
+  KTimer kt(ctx, "pt_leaf", flops, 32.0 * (double)m * k);
   hipLaunchKernelGGL(pt_leaf_kernel, dim3(nleaves), dim3(1024), 0, ctx->stream, Q, ldq, nleaves, m, k, R, ldr,
                      strideR);
   TTF_HIP(hipGetLastError());
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256) void pt_assemble_kernel(zc* __restrict__ Q, lo
 
 void pt_assemble(tt_ctx* ctx, zc* Q, long ldq, int m, int k, int nleaves, const zc* S, long lds_) {
   if (k < 1 || k > PT_COLS) fail(TT_EINVAL, "panel QR: bad assembly shape");
-  KTimer kt(ctx, "hhqr", 8.0 * (double)m * k * k, 48.0 * (double)m * k);
+  KTimer kt(ctx, "pt_assemble", 8.0 * (double)m * k * k, 32.0 * (double)m * k);
   hipLaunchKernelGGL(pt_assemble_kernel, dim3((m + 63) / 64), dim3(256), 0, ctx->stream, Q, ldq, m, k, nleaves, S,
                      lds_);
   TTF_HIP(hipGetLastError());
@@ -262,19 +264,24 @@ __global__ __launch_bounds__(256) void colnorm_partial_kernel(const zc* __restri
 // 1e-13 of the column's norm: the squared residual is the sum of the G
 // partial norms (fixed order), the projected part the squared norm of the
 // coefficients W (p0 rows, leading dimension ldw)
-__global__ void bcgs_flag_kernel(const double* __restrict__ part, int G, int nb, const zc* __restrict__ W, long ldw,
-                                 int p0, int* __restrict__ flags) {
-  const int c = threadIdx.x;
+__global__ __launch_bounds__(1024) void bcgs_flag_kernel(const double* __restrict__ part, int G, int nb,
+                                                         const zc* __restrict__ W, long ldw, int p0,
+                                                         int* __restrict__ flags) {
+  // 32 lanes per column (two DPP rows), fixed summation order
+  const int c = threadIdx.x >> 5, l = threadIdx.x & 31;
   if (c >= nb) return;
-  double res2 = 0;
-  for (int g = 0; g < G; ++g) res2 += part[(long)g * nb + c];
-  double w2 = 0;
-  for (int i = 0; i < p0; ++i) {
+  double res2 = 0, w2 = 0;
+  for (int g = l; g < G; g += 32) res2 += part[(long)g * nb + c];
+  for (int i = l; i < p0; i += 32) {
     const zc w = W[i + ldw * c];
     w2 += w.x * w.x + w.y * w.y;
   }
+  res2 = row16_sum(res2);
+  w2 = row16_sum(w2);
+  res2 += __shfl_xor(res2, 16, 64);
+  w2 += __shfl_xor(w2, 16, 64);
   const double tot = res2 + w2;
-  flags[c] = (!(res2 > 1e-26 * tot) || !(res2 > 0.0)) ? 1 : 0;
+  if (l == 0) flags[c] = (!(res2 > 1e-26 * tot) || !(res2 > 0.0)) ? 1 : 0;
 }
 
 // flagged columns are replaced by standard complex Gaussian vectors
@@ -315,7 +322,7 @@ void bcgs_flag(tt_ctx* ctx, const zc* Y, long ldy, int m, int nb, const zc* W, l
                double* part) {
   const int G = bcgs_flag_groups(m);
   hipLaunchKernelGGL(colnorm_partial_kernel, dim3(G), dim3(256), 0, ctx->stream, Y, ldy, m, nb, part);
-  hipLaunchKernelGGL(bcgs_flag_kernel, dim3(1), dim3(64), 0, ctx->stream, part, G, nb, W, ldw, p0, flags);
+  hipLaunchKernelGGL(bcgs_flag_kernel, dim3(1), dim3(1024), 0, ctx->stream, part, G, nb, W, ldw, p0, flags);
   TTF_HIP(hipGetLastError());
 }
 
@@ -342,6 +349,58 @@ void bcgs_put_diag(tt_ctx* ctx, zc* Rd, long ldr, const zc* Rp, int nb, const in
   TTF_HIP(hipGetLastError());
 }
 
+// Cholesky factor of the nb x nb Hermitian matrix in Gs (LDS), G = R^H R,
+// by a workgroup of 1024 threads (thread (i, j) = (t % 32, t / 32) owns
+// entry (i, j)): Gs becomes R (upper triangle), dinv the reciprocals of its
+// diagonal and, when Ri is given, Ri its inverse (one column per thread,
+// back substitution).  dg holds the original diagonal; *bad = 1 when a
+// pivot falls below tau times it (bad may be null).
+__device__ void block_chol_inv(zc (*Gs)[PT_COLS + 1], const double* dg, zc (*Ri)[PT_COLS + 1], int nb, double tau,
+                               int* bad, double* dinv) {
+  const int t = threadIdx.x, i = t & 31, j = t >> 5;
+  for (int r = 0; r < nb; ++r) {
+    if (t == 0) {
+      const double d = Gs[r][r].x;
+      const bool ok = d > tau * dg[r] && d > 0.0;
+      if (!ok && bad) *bad = 1;
+      const double sd = ok ? sqrt(d) : 1.0;
+      Gs[r][r] = make_double2(sd, 0.0);
+      dinv[r] = 1.0 / sd;
+    }
+    __syncthreads();
+    if (t > r && t < nb) {
+      const double inv = dinv[r];
+      Gs[r][t] = make_double2(Gs[r][t].x * inv, Gs[r][t].y * inv);
+    }
+    __syncthreads();
+    if (i > r && j >= i && j < nb) {
+      const zc x = Gs[r][i], y = Gs[r][j];
+      zc g = Gs[i][j];
+      g.x -= x.x * y.x + x.y * y.y;
+      g.y -= x.x * y.y - x.y * y.x;
+      Gs[i][j] = g;
+    }
+    __syncthreads();
+  }
+  if (!Ri) return;
+  if (t < nb) {
+    const int c = t;
+    for (int q = 0; q < nb; ++q) Ri[q][c] = make_double2(0.0, 0.0);
+    Ri[c][c] = make_double2(dinv[c], 0.0);
+    for (int q = c - 1; q >= 0; --q) {
+      double sr = 0, si = 0;
+      for (int u = q + 1; u <= c; ++u) {
+        const zc a = Gs[q][u], b = Ri[u][c];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+      const double dq = dinv[q];
+      Ri[q][c] = make_double2(-sr * dq, -si * dq);
+    }
+  }
+  __syncthreads();
+}
+
 // Second pass of the block Gram-Schmidt step for one panel (one workgroup,
 // nb <= 32): with Q1 orthonormal and W2 = Q^H Q1 (p0 x nb, ld p0), the
 // reorthogonalised panel Z = Q1 - Q W2 has Gram matrix I - W2^H W2, so its
@@ -359,60 +418,47 @@ __global__ __launch_bounds__(1024) void bcgs_pip_kernel(const zc* __restrict__ W
   __shared__ zc R1s[PT_COLS][PT_COLS + 1];
   __shared__ zc Ri[PT_COLS][PT_COLS + 1];
   __shared__ int fl[PT_COLS];
+  __shared__ double dg[PT_COLS], dinv[PT_COLS];
+  __shared__ zc Wc[PT_COLS][65];  // 64-row chunks of W2
   const int t = threadIdx.x;
   const int i = t & 31, j = t >> 5;
-  if (i < nb && j < nb) {
-    double gr = (i == j) ? 1.0 : 0.0, gi = 0.0;
-    for (int q = 0; q < p0; ++q) {
-      const zc a = W2[q + (long)p0 * i], b = W2[q + (long)p0 * j];
-      gr -= a.x * b.x + a.y * b.y;  // conj(a) b
-      gi -= a.x * b.y - a.y * b.x;
-    }
-    Gs[i][j] = make_double2(gr, gi);
-    R1s[i][j] = R1[i + (long)nb * j];
-  }
+  if (i < nb && j < nb) R1s[i][j] = R1[i + (long)nb * j];
   if (t < nb) fl[t] = flags[t];
-  __syncthreads();
-  // upper Cholesky factor in place: G = R2^H R2, row by row
-  for (int r = 0; r < nb; ++r) {
-    if (t == 0) {
-      const double d = Gs[r][r].x;
-      const bool ok = d > 1e-2;
-      if (!ok) *bad = 1;
-      Gs[r][r] = make_double2(ok ? sqrt(d) : 1.0, 0.0);
+  double gr = (i == j) ? 1.0 : 0.0, gi = 0.0;
+  for (int q0 = 0; q0 < p0; q0 += 64) {
+    const int rows = min(64, p0 - q0);
+    __syncthreads();
+    for (int e = t; e < rows * nb; e += 1024) {
+      const int r = e % rows, c = e / rows;
+      Wc[c][r] = W2[q0 + r + (long)p0 * c];
     }
     __syncthreads();
-    const double inv = 1.0 / Gs[r][r].x;
-    if (t > r && t < nb) Gs[r][t] = make_double2(Gs[r][t].x * inv, Gs[r][t].y * inv);
-    __syncthreads();
-    // trailing update G[a][b] -= conj(R[r][a]) R[r][b] for r < a <= b
-    if (i > r && j >= i && j < nb) {
-      const zc a = Gs[r][i], b = Gs[r][j];
-      zc g = Gs[i][j];
-      g.x -= a.x * b.x + a.y * b.y;
-      g.y -= a.x * b.y - a.y * b.x;
-      Gs[i][j] = g;
-    }
-    __syncthreads();
-  }
-  // inverse of the upper factor, one column per thread
-  if (t < nb) {
-    const int c = t;
-    for (int r = 0; r < nb; ++r) Ri[r][c] = make_double2(0.0, 0.0);
-    const double dc = 1.0 / Gs[c][c].x;
-    Ri[c][c] = make_double2(dc, 0.0);
-    for (int r = c - 1; r >= 0; --r) {
+    if (i < nb && j < nb)
+      for (int r = 0; r < rows; ++r) {
+        const zc a = Wc[i][r], b = Wc[j][r];
+        gr -= a.x * b.x + a.y * b.y;  // conj(a) b
+        gi -= a.x * b.y - a.y * b.x;
+      }
+    // Ro += W2 R1 on these rows, unflagged columns
+    for (int e = t; e < rows * nb; e += 1024) {
+      const int r = e % rows, c = e / rows;
+      if (fl[c]) continue;
       double sr = 0, si = 0;
-      for (int q = r + 1; q <= c; ++q) {
-        const zc a = Gs[r][q], b = Ri[q][c];
+      for (int q = 0; q <= c; ++q) {
+        const zc a = Wc[q][r], b = R1s[q][c];
         sr += a.x * b.x - a.y * b.y;
         si += a.x * b.y + a.y * b.x;
       }
-      const double dr = 1.0 / Gs[r][r].x;
-      Ri[r][c] = make_double2(-sr * dr, -si * dr);
+      zc v = Ro[q0 + r + ldr * c];
+      v.x += sr;
+      v.y += si;
+      Ro[q0 + r + ldr * c] = v;
     }
   }
+  if (i < nb && j < nb) Gs[i][j] = make_double2(gr, gi);
+  if (t < PT_COLS) dg[t] = 1.0;  // absolute pivot test: Z is near orthonormal
   __syncthreads();
+  block_chol_inv(Gs, dg, Ri, nb, 1e-2, bad, dinv);
   if (i < nb && j < nb) {
     R2inv[i + (long)nb * j] = Ri[i][j];
     // (R2 R1)[i][j], both upper
@@ -424,53 +470,167 @@ __global__ __launch_bounds__(1024) void bcgs_pip_kernel(const zc* __restrict__ W
     }
     Rd[i + ldr * j] = (i <= j && !fl[j]) ? make_double2(sr, si) : make_double2(0.0, 0.0);
   }
-  // Ro += W2 R1 for unflagged columns
-  for (int e = t; e < p0 * nb; e += 1024) {
-    const int r = e % p0, c = e / p0;
-    if (fl[c]) continue;
-    double sr = 0, si = 0;
-    for (int q = 0; q <= c; ++q) {
-      const zc a = W2[r + (long)p0 * q], b = R1s[q][c];
-      sr += a.x * b.x - a.y * b.y;
-      si += a.x * b.y + a.y * b.x;
+}
+
+// Cholesky factor of a Hermitian nb x nb Gram matrix G (ld nb, nb <= 32),
+// G = R^H R with R upper triangular, and R^{-1}; one workgroup.  *bad = 1
+// when a pivot falls below tau times its original diagonal entry (the
+// columns behind G too close to dependent for Cholesky QR).  With Rprev
+// given, Rout = R Rprev (the accumulated factor of repeated passes), else
+// Rout = R.
+__global__ __launch_bounds__(1024) void chol_inv_kernel(const zc* __restrict__ G, int nb, double tau,
+                                                       const zc* __restrict__ Rprev, zc* __restrict__ Rout,
+                                                       zc* __restrict__ Rinv, int* __restrict__ bad) {
+  __shared__ zc Gs[PT_COLS][PT_COLS + 1];
+  __shared__ zc Ri[PT_COLS][PT_COLS + 1];
+  __shared__ zc Rp[PT_COLS][PT_COLS + 1];
+  __shared__ double dg[PT_COLS], dinv[PT_COLS];
+  const int t = threadIdx.x;
+  const int i = t & 31, j = t >> 5;
+  if (i < nb && j < nb) {
+    Gs[i][j] = G[i + (long)nb * j];
+    if (Rprev) Rp[i][j] = Rprev[i + (long)nb * j];
+  }
+  if (t < nb) dg[t] = G[t + (long)nb * t].x;
+  __syncthreads();
+  block_chol_inv(Gs, dg, Ri, nb, tau, bad, dinv);
+  if (i < nb && j < nb) {
+    Rinv[i + (long)nb * j] = Ri[i][j];
+    zc v = make_double2(0.0, 0.0);
+    if (i <= j) {
+      if (Rprev) {
+        double sr = 0, si = 0;
+        for (int q = i; q <= j; ++q) {
+          const zc a = Gs[i][q], b = Rp[q][j];
+          sr += a.x * b.x - a.y * b.y;
+          si += a.x * b.y + a.y * b.x;
+        }
+        v = make_double2(sr, si);
+      } else {
+        v = Gs[i][j];
+      }
     }
-    zc v = Ro[r + ldr * c];
-    v.x += sr;
-    v.y += si;
-    Ro[r + ldr * c] = v;
+    Rout[i + (long)nb * j] = v;
   }
 }
 
+void chol_inv(tt_ctx* ctx, const zc* G, int nb, double tau, const zc* Rprev, zc* Rout, zc* Rinv, int* bad) {
+  if (nb > PT_COLS) fail(TT_EINVAL, "chol_inv: block too wide");
+  KTimer kt(ctx, "chol_inv", 0.0, 0.0);
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, ctx->stream, G, nb, tau, Rprev, Rout, Rinv, bad);
+  TTF_HIP(hipGetLastError());
+}
+
+// Z <- Z Rinv for rows [row0, row0 + rows) of the panel (ld ldz), Rinv upper
+// nb x nb in LDS; rows staged through the LDS tile, in place
+__device__ inline void tile_trmm(zc* __restrict__ Z, long ldz, long row0, int rows, int nb, zc (*tile)[65],
+                                 const zc (*Rs)[PT_COLS + 1]) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  __syncthreads();
+  for (int e = t; e < rows * nb; e += nt) {
+    const int r = e % rows, c = e / rows;
+    tile[c][r] = Z[row0 + r + ldz * c];
+  }
+  __syncthreads();
+  for (int e = t; e < rows * nb; e += nt) {
+    const int r = e % rows, c = e / rows;
+    double sr = 0, si = 0;
+    for (int q = 0; q <= c; ++q) {
+      const zc a = tile[q][r], b = Rs[q][c];
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
+    }
+    Z[row0 + r + ldz * c] = make_double2(sr, si);
+  }
+}
+
+// One Cholesky QR pass on the m x nb panel Y given its Gram matrix G
+// (ld nb): every workgroup factors G = R^H R and inverts R itself (nb <= 32,
+// cheap) and replaces its 256 rows by Y R^{-1}; workgroup 0 also writes
+// Rout = R Rprev (R without Rprev) and raises *bad when a pivot falls below
+// tau times its diagonal entry.
+__global__ __launch_bounds__(1024) void chol_solve_kernel(zc* __restrict__ Y, long ldy, int m, int nb,
+                                                         const zc* __restrict__ G, double tau,
+                                                         const zc* __restrict__ Rprev, zc* __restrict__ Rout,
+                                                         int* __restrict__ bad) {
+  __shared__ zc Gs[PT_COLS][PT_COLS + 1];
+  __shared__ zc Ri[PT_COLS][PT_COLS + 1];
+  __shared__ zc tile[PT_COLS][65];
+  __shared__ zc Rp[PT_COLS][PT_COLS + 1];
+  __shared__ double dg[PT_COLS], dinv[PT_COLS];
+  const int t = threadIdx.x;
+  const int i = t & 31, j = t >> 5;
+  if (i < nb && j < nb) {
+    Gs[i][j] = G[i + (long)nb * j];
+    if (Rprev && blockIdx.x == 0) Rp[i][j] = Rprev[i + (long)nb * j];
+  }
+  if (t < nb) dg[t] = G[t + (long)nb * t].x;
+  __syncthreads();
+  block_chol_inv(Gs, dg, Ri, nb, tau, blockIdx.x == 0 ? bad : nullptr, dinv);
+  if (blockIdx.x == 0 && i < nb && j < nb) {
+    zc v = make_double2(0.0, 0.0);
+    if (i <= j) {
+      if (Rprev) {
+        double sr = 0, si = 0;
+        for (int q = i; q <= j; ++q) {
+          const zc a = Gs[i][q], b = Rp[q][j];
+          sr += a.x * b.x - a.y * b.y;
+          si += a.x * b.y + a.y * b.x;
+        }
+        v = make_double2(sr, si);
+      } else {
+        v = Gs[i][j];
+      }
+    }
+    Rout[i + (long)nb * j] = v;
+  }
+  const long r0 = (long)blockIdx.x * 256;
+  for (int s0 = 0; s0 < 256 && r0 + s0 < m; s0 += 64) {
+    const long row0 = r0 + s0;
+    tile_trmm(Y, ldy, row0, (m - row0 < 64) ? (int)(m - row0) : 64, nb, tile, Ri);
+  }
+}
+
+void chol_solve(tt_ctx* ctx, zc* Y, long ldy, int m, int nb, const zc* G, double tau, const zc* Rprev, zc* Rout,
+                int* bad) {
+  if (nb > PT_COLS) fail(TT_EINVAL, "chol_solve: panel too wide");
+  KTimer kt(ctx, "chol_solve", 4.0 * (double)m * nb * nb, 32.0 * (double)m * nb);
+  hipLaunchKernelGGL(chol_solve_kernel, dim3((m + 255) / 256), dim3(1024), 0, ctx->stream, Y, ldy, m, nb, G, tau,
+                     Rprev, Rout, bad);
+  TTF_HIP(hipGetLastError());
+}
+
 // Z <- Z Rinv for the m x nb panel Z (ld ldz), Rinv upper nb x nb (ld nb);
-// one row per thread
+// 64 rows per workgroup staged in LDS, in place
 __global__ __launch_bounds__(256) void panel_trmm_kernel(zc* __restrict__ Z, long ldz, int m, int nb,
                                                          const zc* __restrict__ Rinv) {
-  __shared__ zc Rs[PT_COLS][PT_COLS];
-  for (int e = threadIdx.x; e < nb * nb; e += 256) Rs[e % nb][e / nb] = Rinv[e];
+  __shared__ zc tile[PT_COLS][65];
+  __shared__ zc Rs[PT_COLS][PT_COLS + 1];
+  const long row0 = (long)blockIdx.x * 64;
+  const int t = threadIdx.x;
+  const int rows = (m - row0 < 64) ? (int)(m - row0) : 64;
+  for (int e = t; e < nb * nb; e += 256) Rs[e % nb][e / nb] = Rinv[e];
+  for (int e = t; e < rows * nb; e += 256) {
+    const int r = e % rows, c = e / rows;
+    tile[c][r] = Z[row0 + r + ldz * c];
+  }
   __syncthreads();
-  const long r = (long)blockIdx.x * 256 + threadIdx.x;
-  if (r >= m) return;
-  zc x[PT_COLS];
-#pragma unroll
-  for (int q = 0; q < PT_COLS; ++q) x[q] = (q < nb) ? Z[r + ldz * q] : make_double2(0.0, 0.0);
-#pragma unroll
-  for (int c = 0; c < PT_COLS; ++c) {
-    if (c >= nb) break;
+  for (int e = t; e < rows * nb; e += 256) {
+    const int r = e % rows, c = e / rows;
     double sr = 0, si = 0;
-#pragma unroll
     for (int q = 0; q <= c; ++q) {
-      const zc b = Rs[q][c];
-      sr += x[q].x * b.x - x[q].y * b.y;
-      si += x[q].x * b.y + x[q].y * b.x;
+      const zc a = tile[q][r], b = Rs[q][c];
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
     }
-    Z[r + ldz * c] = make_double2(sr, si);
+    Z[row0 + r + ldz * c] = make_double2(sr, si);
   }
 }
 
 void bcgs_pip(tt_ctx* ctx, const zc* W2, int p0, int nb, const zc* R1, zc* Ro, zc* Rd, long ldr, const int* flags,
               zc* R2inv, int* bad) {
   if (nb > PT_COLS) fail(TT_EINVAL, "bcgs_pip: panel too wide");
-  KTimer kt(ctx, "hhqr", 8.0 * ((double)p0 * nb * nb * 1.5), 16.0 * (double)p0 * nb);
+  KTimer kt(ctx, "bcgs_pip", 8.0 * ((double)p0 * nb * nb * 1.5), 16.0 * (double)p0 * nb);
   hipLaunchKernelGGL(bcgs_pip_kernel, dim3(1), dim3(1024), 0, ctx->stream, W2, p0, nb, R1, Ro, Rd, ldr, flags, R2inv,
                      bad);
   TTF_HIP(hipGetLastError());
@@ -478,8 +638,8 @@ void bcgs_pip(tt_ctx* ctx, const zc* W2, int p0, int nb, const zc* R1, zc* Ro, z
 
 void panel_trmm(tt_ctx* ctx, zc* Z, long ldz, int m, int nb, const zc* Rinv) {
   if (nb > PT_COLS) fail(TT_EINVAL, "panel_trmm: panel too wide");
-  KTimer kt(ctx, "hhqr", 4.0 * (double)m * nb * nb, 32.0 * (double)m * nb);
-  hipLaunchKernelGGL(panel_trmm_kernel, dim3((m + 255) / 256), dim3(256), 0, ctx->stream, Z, ldz, m, nb, Rinv);
+  KTimer kt(ctx, "panel_trmm", 4.0 * (double)m * nb * nb, 32.0 * (double)m * nb);
+  hipLaunchKernelGGL(panel_trmm_kernel, dim3((m + 63) / 64), dim3(256), 0, ctx->stream, Z, ldz, m, nb, Rinv);
   TTF_HIP(hipGetLastError());
 }
 

@@ -275,7 +275,7 @@ void gather_left(tt_ctx* ctx, const tt_op* op, int site, const zc* V, zc* W, int
   const int n = op->n, R0 = op->R[site], R1 = op->R[site + 1];
   const long total = (long)l * n * r1 * R1;
   const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
-  KTimer kt(ctx, "gather", 0.0, 32.0 * total);
+  KTimer kt(ctx, "gather_left", 0.0, 32.0 * total);
   hipLaunchKernelGGL(gather_left_kernel, dim3(blocks), dim3(256), 0, ctx->stream, op->dev[site].in_ptr,
                      op->dev[site].in_ent, op->d_tap_col, op->d_tap_w, V, W, l, n, r1, R0, R1);
   TTF_HIP(hipGetLastError());
@@ -317,7 +317,7 @@ void gather_right(tt_ctx* ctx, const tt_op* op, int site, const zc* V2, zc* Z, i
   const int n = op->n, R0 = op->R[site], R1 = op->R[site + 1];
   const long total = (long)r0 * R0 * n * s;
   const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
-  KTimer kt(ctx, "gather", 0.0, 32.0 * total);
+  KTimer kt(ctx, "gather_right", 0.0, 32.0 * total);
   hipLaunchKernelGGL(gather_right_kernel, dim3(blocks), dim3(256), 0, ctx->stream, op->dev[site].out_ptr,
                      op->dev[site].out_ent, op->d_tap_col, op->d_tap_w, V2, Z, r0, n, s, R0, R1);
   TTF_HIP(hipGetLastError());

@@ -104,6 +104,7 @@ _SIGS = {
     "tt_op_create_burgers_hopf_scaled": (I, [P, I, I, D, D, D, ctypes.POINTER(P)]),
     "tt_op_destroy": (I, [P]),
     "tt_ctx_dump_stats": (I, [P, ctypes.c_char_p, ctypes.c_long]),
+    "tt_ctx_set_profile_filter": (I, [P, ctypes.c_char_p]),
     "tt_op_get_ranks": (I, [P, PI]),
     "tt_op_export_coefficients": (I, [P, PD, PD]),
     "tt_op_export_local_ops": (I, [P, PI, PD]),
@@ -181,6 +182,10 @@ class Context:
         """Event timing per kernel class; with shapes=True every GEMM is also
         recorded under "zgemm:<ops>:MxNxKxbatch"."""
         self.check(lib().tt_ctx_set_profiling(self.h, (2 if shapes else 1) if on else 0))
+
+    def set_profile_filter(self, kernel=None):
+        """Time only the given kernel class (None: all classes)."""
+        self.check(lib().tt_ctx_set_profile_filter(self.h, kernel.encode() if kernel else None))
 
     def dump_stats(self):
         """All recorded keys: {key: {"launches", "ms", "flops", "bytes"}}."""

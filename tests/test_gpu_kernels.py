@@ -29,9 +29,9 @@ def _op(x, o):
 @pytest.mark.parametrize(
     "M,N,K,batch",
     [(1, 1, 1, 1), (17, 33, 5, 1), (64, 64, 16, 1), (65, 130, 47, 3), (20, 30, 5000, 1), (130, 7, 900, 2),
-     (8, 200, 0, 1)],
+     (8, 200, 0, 1), (4100, 20, 37, 1), (300, 32, 3000, 1), (33, 96, 700, 2)],
 )
-@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (2, 0), (0, 1), (0, 2), (2, 2)])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (2, 0), (0, 1), (0, 2), (2, 2), (1, 2), (2, 1)])
 def test_zgemm_against_numpy(ctx, M, N, K, batch, opa, opb):
     import torch
 
