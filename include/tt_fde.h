@@ -246,6 +246,25 @@ int tt_zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, double alpha_re
 /* Frobenius norm of x (synchronous; computed by orthogonalisation). */
 int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out);
 
+/* Building block exposed for testing: the QR factorisation used by every
+ * orthogonalisation of the TT sweeps (the QR of V(C) and the LQ of H(C),
+ * App. A.1, Alg. 1-2).  A (m x k, ld lda >= m, m >= k >= 1) = Q R with Q
+ * (m x k, ld m) orthonormal and R (k x k, ld k) upper triangular, also for
+ * rank-deficient A (columns dependent on earlier ones get R columns that
+ * are zero below the projection coefficients).  Device pointers to
+ * interleaved complex doubles; A is not modified; synchronous (one host
+ * synchronisation per attempt of the checked fast path). */
+int tt_qr(tt_ctx* ctx, int m, int k, const double* A, int64_t lda, double* Q, double* R);
+
+/* Building block exposed for testing: one-sided Jacobi SVD of the small
+ * factor of a TT truncation (App. A.4): B (m x k, ld m, m <= 512 and
+ * k <= 512, overwritten) has left singular vectors U (m x k, ld m; columns
+ * in order of decreasing singular value, a zero column for a zero singular
+ * value) and singular values sigma (k doubles, decreasing).  sweeps
+ * (host int, may be null) receives the number of sweeps.  Device pointers;
+ * synchronous.  TT_ENOCONV when 60 sweeps did not converge. */
+int tt_svd_small(tt_ctx* ctx, int m, int k, double* B, double* U, double* sigma, int* sweeps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1139,4 +1139,32 @@ int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out) {
   ABI_CATCH(ctx)
 }
 
+int tt_qr(tt_ctx* ctx, int m, int k, const double* A, int64_t lda, double* Q, double* R) {
+  if (!ctx) return TT_EINVAL;
+  ABI_TRY
+  require(m >= k && k >= 1, TT_EINVAL, "tt_qr: need m >= k >= 1");
+  require(A && Q && R, TT_EINVAL, "tt_qr: null pointer");
+  require(lda >= m, TT_EINVAL, "tt_qr: leading dimension too small");
+  tsqr(ctx, m, k, (const zc*)A, lda, (zc*)Q, (zc*)R);
+  ctx->sync();
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_svd_small(tt_ctx* ctx, int m, int k, double* B, double* U, double* sigma, int* sweeps) {
+  if (!ctx) return TT_EINVAL;
+  ABI_TRY
+  require(m >= 1 && k >= 1 && m <= 512 && k <= 512, TT_EINVAL, "tt_svd_small: need 1 <= m, k <= 512");
+  require(B && U && sigma, TT_EINVAL, "tt_svd_small: null pointer");
+  int* sw = (int*)ctx->get_ws("svd_small_sweeps", 64);
+  jacobi_svd(ctx, m, k, (zc*)B, (zc*)U, sigma, sw);
+  int* h = (int*)ctx->host_scratch(64);
+  TTF_HIP(hipMemcpyAsync(h, sw, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  ctx->sync();
+  if (sweeps) *sweeps = h[0];
+  require(h[0] < 60, TT_ENOCONV, "tt_svd_small: Jacobi did not converge in 60 sweeps");
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
 }  // extern "C"

@@ -162,7 +162,6 @@ void bcgs_pip(tt_ctx* ctx, const zc* W2, int p0, int nb, const zc* R1, zc* Ro, z
 void chol_solve(tt_ctx* ctx, zc* Y, long ldy, int m, int nb, const zc* G, double tau, const zc* Rprev, zc* Rout,
                 int* bad);
 void panel_trmm(tt_ctx* ctx, zc* Z, long ldz, int m, int nb, const zc* Rinv);
-void chol_inv(tt_ctx* ctx, const zc* G, int nb, double tau, const zc* Rprev, zc* Rout, zc* Rinv, int* bad);
 void zero_ints(tt_ctx* ctx, int* x, int n);
 void bcgs_random(tt_ctx* ctx, zc* Qp, long ldq, int m, int nb, const int* flags, uint64_t seed, int tag);
 void bcgs_masked_add(tt_ctx* ctx, zc* Rd, long ldr, const zc* W, long ldw, int rows, int nb, const int* flags);

@@ -1,24 +1,23 @@
 // Small dense factorisation used once per TT bond.
 //
-// * jacobi_svd: one-sided (Hestenes) Jacobi SVD of the small square factor
-//   R (the "SVD of the R factor" of App. A.4): columns are rotated pairwise
-//   until orthogonal; their norms are the singular values and the
-//   normalised columns the left singular vectors.
-//   Block-parallel form (m <= 512 rows): the columns are cut into blocks of
-//   16; each launch is one round of a round-robin tournament over the
-//   blocks, one workgroup per block pair.  A workgroup keeps its 32 columns
-//   in registers, two per wavefront, and runs one cyclic sweep over all 496
-//   column pairs of the block pair (31 rounds of 16 disjoint pairs; between
-//   rounds columns move to the neighbouring wavefront through LDS).  Each
-//   column pair of the matrix meets at least once per outer sweep, so the
-//   iteration is a cyclic Jacobi method with a block ordering.  Sweeps stop
-//   after the first outer sweep without a rotation.
+// jacobi_svd: one-sided (Hestenes) Jacobi SVD of the small square factor of
+// a truncation step (the "SVD of the R factor" of App. A.4): columns are
+// rotated pairwise until orthogonal; their norms are the singular values
+// and the normalised columns the left singular vectors.  The columns are
+// cut into blocks of 16.  One sweep runs every block on its own (all pairs
+// inside a block, circle ordering) and then the rounds of a round-robin
+// tournament over the blocks, one workgroup per block pair meeting all 256
+// pairs between the two blocks.  A column pair is held in registers by a
+// group of 16 lanes (a whole wavefront beyond 320 rows); columns move
+// between groups through LDS.  Every column pair meets once per sweep, so
+// this is a cyclic Jacobi method with a block ordering; sweeps stop after
+// the first one without a rotation.
 #include "common.hpp"
 #include "dpp.hpp"
 
 namespace ttf {
 
-constexpr int CHOL_KMAX = 512;
+constexpr int JB_NORMS = 512;  // columns of the finishing kernel
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -40,10 +39,10 @@ __device__ inline double block_sum(double v, double* red) {
 // ------------------------------------------------------------ Jacobi SVD
 constexpr int JAC_THREADS = 1024;
 constexpr int JAC_GROUPS = JAC_THREADS / 16;
-constexpr int JAC_LDS_ELEMS = 9216;  // 144 KiB of complex doubles
 constexpr int JAC_MAX_SWEEPS = 60;
 constexpr int JB_COLS = 16;    // columns per block
 constexpr int JB_MAXM = 512;   // rows supported by the register-resident form
+constexpr int JB_MAXK = 512;   // columns
 constexpr int JB_MAXS = 64;    // sweep counters
 
 // round-robin pairing of players 0..P-1 (P even) in round r
@@ -58,130 +57,13 @@ __device__ inline void rr_pair(int P, int r, int i, int& a, int& b) {
   }
 }
 
-// One-sided Jacobi: one 16-lane group per column pair (64 pairs in flight),
-// 16-lane DPP reductions; the pairs of a round are disjoint, rounds are
-// separated by a barrier.
-template <bool IN_LDS>
-__global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, int k, zc* __restrict__ Bg,
-                                                             zc* __restrict__ U, double* __restrict__ sigma,
-                                                             int* __restrict__ sweeps_out) {
-  extern __shared__ double2 lds[];
-  __shared__ int rotated;
-  __shared__ double norms[CHOL_KMAX];
-  zc* B = IN_LDS ? lds : Bg;
-  const int t = threadIdx.x, g = t >> 4, l16 = t & 15;
-  if (IN_LDS)
-    for (long e = t; e < (long)m * k; e += blockDim.x) B[e] = Bg[e];
-  __syncthreads();
-  const int P = (k + 1) & ~1;
-  const double tol = 1e-15 * sqrt((double)m);
-  int sweep = 0;
-  for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
-    if (t == 0) rotated = 0;
-    __syncthreads();
-    int any = 0;
-    for (int r = 0; r < P - 1; ++r) {
-      for (int i = g; i < P / 2; i += JAC_GROUPS) {
-        int p, q;
-        rr_pair(P, r, i, p, q);
-        if (p >= k || q >= k) continue;
-        zc* x = B + (long)m * p;
-        zc* y = B + (long)m * q;
-        double al = 0, be = 0, gr = 0, gi = 0;
-        for (int row = l16; row < m; row += 16) {
-          const zc a = x[row], c = y[row];
-          al += a.x * a.x + a.y * a.y;
-          be += c.x * c.x + c.y * c.y;
-          gr += a.x * c.x + a.y * c.y;  // conj(x) * y
-          gi += a.x * c.y - a.y * c.x;
-        }
-        al = row16_sum(al);
-        be = row16_sum(be);
-        gr = row16_sum(gr);
-        gi = row16_sum(gi);
-        const double gg = sqrt(gr * gr + gi * gi);
-        if (gg <= tol * sqrt(al * be) || gg == 0.0) continue;
-        any = 1;
-        // complex rotation orthogonalising columns p and q
-        const double zeta = (be - al) / (2.0 * gg);
-        const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-        const double er = gr / gg, ei = gi / gg;  // e^{i phi}
-        for (int row = l16; row < m; row += 16) {
-          const zc a = x[row], c = y[row];
-          // x' = cs x - sn e^{-i phi} y ; y' = sn e^{i phi} x + cs y
-          zc xn, yn;
-          xn.x = cs * a.x - sn * (er * c.x + ei * c.y);
-          xn.y = cs * a.y - sn * (er * c.y - ei * c.x);
-          yn.x = sn * (er * a.x - ei * a.y) + cs * c.x;
-          yn.y = sn * (er * a.y + ei * a.x) + cs * c.y;
-          x[row] = xn;
-          y[row] = yn;
-        }
-      }
-      __syncthreads();
-    }
-    if (any) atomicOr(&rotated, 1);
-    __syncthreads();
-    if (!rotated) break;
-  }
-  // singular values = column norms
-  for (int c = g; c < k; c += JAC_GROUPS) {
-    double sq = 0;
-    for (int row = l16; row < m; row += 16) {
-      const zc a = B[row + (long)m * c];
-      sq += a.x * a.x + a.y * a.y;
-    }
-    sq = row16_sum(sq);
-    if (l16 == 0) norms[c] = sqrt(sq);
-  }
-  __syncthreads();
-  // sort by decreasing norm (ties by index) and normalise into U
-  for (int c = g; c < k; c += JAC_GROUPS) {
-    const double v = norms[c];
-    int pos = 0;
-    for (int o = 0; o < k; ++o) {
-      const double w = norms[o];
-      pos += (w > v) || (w == v && o < c);
-    }
-    const double inv = v > 0 ? 1.0 / v : 0.0;
-    for (int row = l16; row < m; row += 16) {
-      const zc a = B[row + (long)m * c];
-      U[row + (long)m * pos] = make_double2(a.x * inv, a.y * inv);
-    }
-    if (l16 == 0) sigma[pos] = v;
-  }
-  if (t == 0) *sweeps_out = sweep + 1;
-}
-
 void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps);
 
 void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
   if (k <= 0) return;
-  if (k > CHOL_KMAX) fail(TT_EINVAL, "jacobi_svd: rank above the supported maximum of 512");
-  static int lds_limit = -1;
-  if (lds_limit < 0) {
-    int dev = 0, v = 0;
-    TTF_HIP(hipGetDevice(&dev));
-    TTF_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    lds_limit = v;
-  }
-  // per sweep: k(k-1)/2 pairs x (16 m for the inner products + 28 m for the rotation)
+  if (k > JB_MAXK || m > JB_MAXM || m < 1) fail(TT_EINVAL, "jacobi_svd: sizes above the supported maximum of 512");
   KTimer kt(ctx, "jacobi_svd", 0.0, 0.0);
-  if (m <= JB_MAXM && JB_MAXS >= JAC_MAX_SWEEPS) {
-    jacobi_blocked(ctx, m, k, B, U, sigma, sweeps);
-    return;
-  }
-  const long need = (long)sizeof(zc) * m * k + 8 * CHOL_KMAX + 64;
-  if ((long)m * k <= JAC_LDS_ELEMS && need <= lds_limit) {
-    const size_t lds = sizeof(zc) * (size_t)m * k;
-    hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(JAC_THREADS), lds, ctx->stream, m, k, B, U, sigma,
-                       sweeps);
-  } else {
-    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(JAC_THREADS), 0, ctx->stream, m, k, B, U, sigma,
-                       sweeps);
-  }
-  TTF_HIP(hipGetLastError());
+  jacobi_blocked(ctx, m, k, B, U, sigma, sweeps);
 }
 
 // ------------------------------------------------ block-parallel Jacobi
@@ -197,10 +79,10 @@ __device__ inline double group_sum(double x) {
   return x;
 }
 
-// Rotate the column pair (x, y) so that x^H y = 0; returns 1 when a
-// rotation was applied.
+// Rotate the column pair (x, y) so that x^H y = 0 unless they already are
+// to the tolerance; returns 1 when a rotation was applied.
 template <int RPL, int GS>
-__device__ inline int jacobi_rotate(zc (&x)[RPL], zc (&y)[RPL], double tol) {
+__device__ inline int jacobi_rotate(zc (&x)[RPL], zc (&y)[RPL], double tol, double abs2) {
   double al = 0, be = 0, gr = 0, gi = 0;
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
@@ -215,7 +97,8 @@ __device__ inline int jacobi_rotate(zc (&x)[RPL], zc (&y)[RPL], double tol) {
   gr = group_sum<GS>(gr);
   gi = group_sum<GS>(gi);
   const double g2 = gr * gr + gi * gi;
-  if (!(g2 > tol * tol * al * be) || g2 == 0.0) return 0;
+  // pairs with a negligible column (squared norm below abs2) are left alone
+  if (!(g2 > tol * tol * al * be) || g2 == 0.0 || al < abs2 || be < abs2) return 0;
   const double gg = sqrt(g2);
   const double ig = 1.0 / gg;
   const double zeta = (be - al) * (0.5 * ig);
@@ -254,10 +137,12 @@ __device__ inline int jacobi_count(int nrot, int* wg_rot, int* rot, int idx) {
 // returns at once when sweep - 1 rotated nothing.
 template <int RPL, int W, int GS>
 __global__ __launch_bounds__(GS * W) void jacobi_circle_kernel(zc* __restrict__ B, int m, int k, int inner_max,
-                                                               int sweep, int* __restrict__ rot, double tol) {
+                                                               int sweep, int* __restrict__ rot, double tol,
+                                                               const double* __restrict__ fro2) {
   extern __shared__ double2 xch[];  // W slots of GS RPL rows
   __shared__ int wg_rot;
   if (sweep > 0 && rot[sweep - 1] == 0) return;
+  const double abs2 = 1e-30 * fro2[0];  // (1e-15 |B|_F)^2
   constexpr int NP = 2 * W - 1;
   constexpr int LD = GS * RPL;
   const int c0 = blockIdx.x * 2 * W;
@@ -279,7 +164,7 @@ __global__ __launch_bounds__(GS * W) void jacobi_circle_kernel(zc* __restrict__ 
       // positions w and 2W-1-w after r shifts
       const int pt = (w == 0) ? 0 : ((w - 1 - r) % NP + NP) % NP + 1;
       const int pb = ((2 * W - 2 - w - r) % NP + NP) % NP + 1;
-      if (c0 + pt < k && c0 + pb < k) nrot += jacobi_rotate<RPL, GS>(xt, xb, tol);
+      if (c0 + pt < k && c0 + pb < k) nrot += jacobi_rotate<RPL, GS>(xt, xb, tol, abs2);
       // shift: bottoms move to the previous group (the last one takes its
       // own top), then tops to the next one (group 1 takes group 0's old
       // bottom, left in slot 0 by the first phase)
@@ -327,10 +212,12 @@ __global__ __launch_bounds__(GS * W) void jacobi_circle_kernel(zc* __restrict__ 
 // step s; between steps the b columns move to the previous group.
 template <int RPL, int GS>
 __global__ __launch_bounds__(16 * GS) void jacobi_cross_kernel(zc* __restrict__ B, int m, int k, int P, int round,
-                                                               int sweep, int* __restrict__ rot, double tol) {
+                                                               int sweep, int* __restrict__ rot, double tol,
+                                                               const double* __restrict__ fro2) {
   extern __shared__ double2 xch[];  // 16 slots of GS RPL rows
   __shared__ int wg_rot;
   if (sweep > 0 && rot[sweep - 1] == 0) return;
+  const double abs2 = 1e-30 * fro2[0];  // (1e-15 |B|_F)^2
   constexpr int LD = GS * RPL;
   int ba, bb;
   rr_pair(P, round, blockIdx.x, ba, bb);
@@ -351,7 +238,7 @@ __global__ __launch_bounds__(16 * GS) void jacobi_cross_kernel(zc* __restrict__ 
   int nrot = 0;
   for (int st = 0; st < JB_COLS; ++st) {
     const int cb = bb * JB_COLS + ((w + st) & 15);
-    if (ca < k && cb < k) nrot += jacobi_rotate<RPL, GS>(xa, xb, tol);
+    if (ca < k && cb < k) nrot += jacobi_rotate<RPL, GS>(xa, xb, tol, abs2);
     if (st == JB_COLS - 1) break;
     __syncthreads();
 #pragma unroll
@@ -387,7 +274,7 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(int m, int k, const
                                                              zc* __restrict__ U, double* __restrict__ sigma,
                                                              const int* __restrict__ rot, int nsweeps,
                                                              int* __restrict__ sweeps_out) {
-  __shared__ double norms[CHOL_KMAX];
+  __shared__ double norms[JB_NORMS];
   const int t = threadIdx.x, g = t >> 4, l16 = t & 15;
   for (int c = g; c < k; c += JAC_GROUPS) {
     double sq = 0;
@@ -422,17 +309,17 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(int m, int k, const
 
 template <int RPL, int GS>
 void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int round, int inner_max, int sweep,
-                       int* rot, double tol) {
+                       int* rot, double tol, const double* fro2) {
   const size_t slot = sizeof(zc) * GS * RPL;
   if (kind == 0)  // whole matrix (k <= 32) in one workgroup
     hipLaunchKernelGGL((jacobi_circle_kernel<RPL, 16, GS>), dim3(1), dim3(16 * GS), 16 * slot, ctx->stream, B, m, k,
-                       inner_max, sweep, rot, tol);
+                       inner_max, sweep, rot, tol, fro2);
   else if (kind == 1)  // every block of 16 columns on its own
     hipLaunchKernelGGL((jacobi_circle_kernel<RPL, 8, GS>), dim3((k + 15) / 16), dim3(8 * GS), 8 * slot, ctx->stream,
-                       B, m, k, 1, sweep, rot, tol);
+                       B, m, k, 1, sweep, rot, tol, fro2);
   else
     hipLaunchKernelGGL((jacobi_cross_kernel<RPL, GS>), dim3(P / 2), dim3(16 * GS), 16 * slot, ctx->stream, B, m, k,
-                       P, round, sweep, rot, tol);
+                       P, round, sweep, rot, tol, fro2);
   TTF_HIP(hipGetLastError());
 }
 
@@ -440,26 +327,29 @@ void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int ro
 // inside a block) followed by the P - 1 rounds of a round-robin over the
 // blocks (all pairs between two blocks), so each column pair meets once.
 void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
+  int* rot = (int*)ctx->get_ws("jac_rot", sizeof(int) * JB_MAXS + 64);
+  double* fro2 = (double*)(rot + JB_MAXS);
+  frob_norm2(ctx, B, (long)m * k, fro2);
   // a 16-lane group per column pair up to 320 rows (at most 20 rows per
   // lane), a whole wavefront beyond
   auto launch = [&](int kind, int P, int round, int inner_max, int sweep, int* rot, double tol) {
+    const double* f2 = fro2;
     if (m <= 64)
-      jacobi_launch_rpl<4, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+      jacobi_launch_rpl<4, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else if (m <= 128)
-      jacobi_launch_rpl<8, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+      jacobi_launch_rpl<8, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else if (m <= 192)
-      jacobi_launch_rpl<12, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+      jacobi_launch_rpl<12, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else if (m <= 256)
-      jacobi_launch_rpl<16, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+      jacobi_launch_rpl<16, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else if (m <= 320)
-      jacobi_launch_rpl<20, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+      jacobi_launch_rpl<20, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else
-      jacobi_launch_rpl<8, 64>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol);
+      jacobi_launch_rpl<8, 64>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
   };
   const double tol = 1e-15 * sqrt((double)m);
   const int nblk = (k + JB_COLS - 1) / JB_COLS;
   const int P = nblk + (nblk & 1);
-  int* rot = (int*)ctx->get_ws("jac_rot", sizeof(int) * JB_MAXS);
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, ctx->stream, rot, JB_MAXS);
   TTF_HIP(hipGetLastError());
   int nsweeps = 0;

@@ -472,55 +472,6 @@ __global__ __launch_bounds__(1024) void bcgs_pip_kernel(const zc* __restrict__ W
   }
 }
 
-// Cholesky factor of a Hermitian nb x nb Gram matrix G (ld nb, nb <= 32),
-// G = R^H R with R upper triangular, and R^{-1}; one workgroup.  *bad = 1
-// when a pivot falls below tau times its original diagonal entry (the
-// columns behind G too close to dependent for Cholesky QR).  With Rprev
-// given, Rout = R Rprev (the accumulated factor of repeated passes), else
-// Rout = R.
-__global__ __launch_bounds__(1024) void chol_inv_kernel(const zc* __restrict__ G, int nb, double tau,
-                                                       const zc* __restrict__ Rprev, zc* __restrict__ Rout,
-                                                       zc* __restrict__ Rinv, int* __restrict__ bad) {
-  __shared__ zc Gs[PT_COLS][PT_COLS + 1];
-  __shared__ zc Ri[PT_COLS][PT_COLS + 1];
-  __shared__ zc Rp[PT_COLS][PT_COLS + 1];
-  __shared__ double dg[PT_COLS], dinv[PT_COLS];
-  const int t = threadIdx.x;
-  const int i = t & 31, j = t >> 5;
-  if (i < nb && j < nb) {
-    Gs[i][j] = G[i + (long)nb * j];
-    if (Rprev) Rp[i][j] = Rprev[i + (long)nb * j];
-  }
-  if (t < nb) dg[t] = G[t + (long)nb * t].x;
-  __syncthreads();
-  block_chol_inv(Gs, dg, Ri, nb, tau, bad, dinv);
-  if (i < nb && j < nb) {
-    Rinv[i + (long)nb * j] = Ri[i][j];
-    zc v = make_double2(0.0, 0.0);
-    if (i <= j) {
-      if (Rprev) {
-        double sr = 0, si = 0;
-        for (int q = i; q <= j; ++q) {
-          const zc a = Gs[i][q], b = Rp[q][j];
-          sr += a.x * b.x - a.y * b.y;
-          si += a.x * b.y + a.y * b.x;
-        }
-        v = make_double2(sr, si);
-      } else {
-        v = Gs[i][j];
-      }
-    }
-    Rout[i + (long)nb * j] = v;
-  }
-}
-
-void chol_inv(tt_ctx* ctx, const zc* G, int nb, double tau, const zc* Rprev, zc* Rout, zc* Rinv, int* bad) {
-  if (nb > PT_COLS) fail(TT_EINVAL, "chol_inv: block too wide");
-  KTimer kt(ctx, "chol_inv", 0.0, 0.0);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, ctx->stream, G, nb, tau, Rprev, Rout, Rinv, bad);
-  TTF_HIP(hipGetLastError());
-}
-
 // Z <- Z Rinv for rows [row0, row0 + rows) of the panel (ld ldz), Rinv upper
 // nb x nb in LDS; rows staged through the LDS tile, in place
 __device__ inline void tile_trmm(zc* __restrict__ Z, long ldz, long row0, int rows, int nb, zc (*tile)[65],

@@ -116,6 +116,8 @@ _SIGS = {
     "tt_step": (I, [P, P, P, D, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport)]),
     "tt_eval": (I, [P, P, P, ctypes.c_int64, P]),
     "tt_norm": (I, [P, P, PD]),
+    "tt_qr": (I, [P, I, I, P, ctypes.c_int64, P, P]),
+    "tt_svd_small": (I, [P, I, I, P, P, P, PI]),
     "tt_zgemm": (I, [P, I, I, I, I, I, D, D, P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64,
                      ctypes.c_int64, D, D, P, ctypes.c_int64, ctypes.c_int64, I]),
 }
@@ -385,3 +387,36 @@ def tt_norm(ctx, x):
     v = D()
     ctx.check(lib().tt_norm(ctx.h, x.h, ctypes.byref(v)))
     return v.value
+
+
+def tt_qr(ctx, A, Q, R):
+    """QR of the column-major complex128 device matrix A (m x k, its storage
+    a Fortran-ordered torch tensor or a transposed C-ordered one): Q (m x k)
+    and R (k x k), torch complex128 buffers of m*k and k*k elements."""
+    import torch
+
+    m, k = A.shape[0], A.shape[1]
+    lda = A.stride(1) if k > 1 else m
+    if A.stride(0) != 1 and m > 1:
+        raise ValueError("tt_qr: A must be column-major (stride(0) == 1)")
+    cur = torch.cuda.current_stream()
+    if ctx.torch_stream is not None:
+        ctx.torch_stream.wait_stream(cur)
+    ctx.check(lib().tt_qr(ctx.h, m, k, P(A.data_ptr()), lda, P(Q.data_ptr()), P(R.data_ptr())))
+
+
+def tt_svd_small(ctx, B, U, sigma):
+    """One-sided Jacobi SVD of the column-major complex128 device matrix B
+    (m x k, overwritten): U (m x k) and sigma (k float64); returns sweeps."""
+    import torch
+
+    m, k = B.shape[0], B.shape[1]
+    if (B.stride(0) != 1 and m > 1) or (B.stride(1) != m and k > 1):
+        raise ValueError("tt_svd_small: B must be contiguous column-major")
+    cur = torch.cuda.current_stream()
+    if ctx.torch_stream is not None:
+        ctx.torch_stream.wait_stream(cur)
+    sw = ctypes.c_int()
+    ctx.check(lib().tt_svd_small(ctx.h, m, k, P(B.data_ptr()), P(U.data_ptr()), P(sigma.data_ptr()),
+                                 ctypes.byref(sw)))
+    return sw.value

@@ -1,0 +1,165 @@
+"""GPU checks of the dense building blocks of TT rounding, through the C
+ABI: the QR factorisation behind every orthogonalisation (block
+Gram-Schmidt with Cholesky / Householder panels and its checked fallbacks)
+and the one-sided Jacobi SVD of the small truncation factor, against numpy
+and against the defining identities (A = QR, Q^H Q = I, B = U S V^H)."""
+import numpy as np
+import pytest
+
+from gpu_util import make_ctx
+from paper_2403_04946_amd import tt
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = make_ctx()
+    yield c
+    c.sync()
+    c.close()
+
+
+def _cplx(rng, m, k):
+    return rng.standard_normal((m, k)) + 1j * rng.standard_normal((m, k))
+
+
+def _dev(a):
+    import torch
+
+    # column-major device copy: the transpose of a C-ordered tensor
+    return torch.from_numpy(np.ascontiguousarray(a.T)).cuda().t()
+
+
+def _qr(ctx, a):
+    import torch
+
+    m, k = a.shape
+    A = _dev(a)
+    Q = torch.empty((k, m), dtype=torch.complex128, device="cuda")
+    R = torch.empty((k, k), dtype=torch.complex128, device="cuda")
+    tt.tt_qr(ctx, A, Q, R)
+    torch.cuda.synchronize()
+    return Q.cpu().numpy().T, R.cpu().numpy().T
+
+
+def _fallbacks(ctx):
+    return ctx.dump_stats()["qr_fallbacks"]["launches"]
+
+
+def _check_qr(a, q, r, tol=1e-12):
+    k = a.shape[1]
+    orth = np.linalg.norm(q.conj().T @ q - np.eye(k))
+    res = np.linalg.norm(q @ r - a) / max(np.linalg.norm(a), 1e-300)
+    assert orth < tol * max(1, k) ** 0.5, orth
+    assert res < tol, res
+    assert np.abs(np.tril(r, -1)).max() == 0.0
+
+
+def _cases(rng, m, k):
+    x = _cplx(rng, m, (k + 1) // 2)
+    yield "random", _cplx(rng, m, k)
+    yield "duplicate", np.hstack([x, x])[:, :k]
+    yield "zero half", np.hstack([x, 0 * x])[:, :k]
+    yield "rank 3", (_cplx(rng, m, 3) @ _cplx(rng, 3, k))
+    yield "unit columns", np.eye(m, k, dtype=complex)[:, ::-1].copy()
+    scaled = _cplx(rng, m, k) * np.logspace(0, -14, k)[None, :]
+    yield "graded columns", scaled
+
+
+@pytest.mark.parametrize("m,k", [(1, 1), (5, 3), (64, 64), (300, 32), (1000, 70), (2049, 100), (320, 320),
+                                 (700, 200), (16384, 40)])
+def test_qr_identities(ctx, m, k):
+    rng = np.random.default_rng(m * 1000 + k)
+    for name, a in _cases(rng, m, k):
+        q, r = _qr(ctx, a)
+        try:
+            _check_qr(a, q, r)
+        except AssertionError as e:
+            raise AssertionError(f"{name}: {e}") from None
+
+
+def test_qr_matches_numpy_up_to_phases(ctx):
+    rng = np.random.default_rng(7)
+    a = _cplx(rng, 3000, 96)
+    q, r = _qr(ctx, a)
+    qn, rn = np.linalg.qr(a)
+    # unique up to a unit complex scaling of each column: Q = Qn D, R = D^H Rn
+    dph = np.diag(qn.conj().T @ q)
+    assert np.allclose(np.abs(dph), 1.0, atol=1e-11)
+    assert np.linalg.norm(q - qn * dph[None, :]) < 1e-11
+    assert np.linalg.norm(r - dph.conj()[:, None] * rn) / np.linalg.norm(rn) < 1e-12
+
+
+def test_qr_fast_path_and_fallback(ctx):
+    rng = np.random.default_rng(11)
+    ctx.reset_stats()
+    a = _cplx(rng, 4000, 64)
+    q, r = _qr(ctx, a)
+    _check_qr(a, q, r)
+    assert _fallbacks(ctx) == 0  # well conditioned: Cholesky QR panels suffice
+    # two columns of one panel that differ by 1e-9: the Cholesky pivot test
+    # fails and the factorisation is redone with Householder panels
+    b = _cplx(rng, 4000, 64)
+    b[:, 5] = b[:, 4] + 1e-9 * _cplx(rng, 4000, 1)[:, 0]
+    ctx.reset_stats()
+    q, r = _qr(ctx, b)
+    _check_qr(b, q, r)
+    assert _fallbacks(ctx) >= 1
+
+
+def test_qr_and_svd_reject_bad_shapes(ctx):
+    null = tt.P(0)
+    assert tt.lib().tt_qr(ctx.h, 4, 8, null, 4, null, null) == -1  # m < k
+    assert tt.lib().tt_qr(ctx.h, 8, 0, null, 8, null, null) == -1  # k < 1
+    assert tt.lib().tt_svd_small(ctx.h, 513, 4, null, null, null, None) == -1  # beyond 512 rows
+    ctx.sync()
+
+
+def _svd(ctx, b):
+    import torch
+
+    m, k = b.shape
+    B = torch.from_numpy(np.ascontiguousarray(b.T)).cuda().t()  # column-major m x k
+    U = torch.empty(m * k, dtype=torch.complex128, device="cuda")
+    s = torch.empty(k, dtype=torch.float64, device="cuda")
+    sweeps = tt.tt_svd_small(ctx, B, U, s)
+    torch.cuda.synchronize()
+    return U.cpu().numpy().reshape(k, m).T, s.cpu().numpy(), sweeps
+
+
+@pytest.mark.parametrize("m,k", [(1, 1), (16, 16), (33, 33), (80, 80), (128, 128), (320, 320), (500, 500), (200, 50),
+                                 (64, 100)])
+def test_svd_small_matches_numpy(ctx, m, k):
+    rng = np.random.default_rng(m + 7 * k)
+    b = _cplx(rng, m, k)
+    u, s, sweeps = _svd(ctx, b)
+    sn = np.linalg.svd(b, compute_uv=False)
+    r = min(m, k)
+    assert sweeps < 60
+    assert np.abs(s[:r] - sn).max() < 1e-12 * sn[0]
+    assert np.all(np.diff(s) <= 0)
+    if k > m:  # the extra singular values are zero, their U columns zero
+        assert np.abs(s[r:]).max() < 1e-12 * sn[0]
+    ur = u[:, :r]
+    assert np.linalg.norm(ur.conj().T @ ur - np.eye(r)) < 1e-11
+    # U^H B B^H U = S^2 (B = U S V^H)
+    w = ur.conj().T @ b
+    assert np.linalg.norm(w @ w.conj().T - np.diag(s[:r] ** 2)) < 1e-11 * sn[0] ** 2
+
+
+def test_svd_small_graded_and_rank_deficient(ctx):
+    rng = np.random.default_rng(3)
+    m = 96
+    uq, _ = np.linalg.qr(_cplx(rng, m, m))
+    vq, _ = np.linalg.qr(_cplx(rng, m, m))
+    spec = np.logspace(0, -10, m)
+    spec[60:] = 0.0  # exact rank 60
+    b = (uq * spec) @ vq.conj().T
+    u, s, _ = _svd(ctx, b)
+    assert np.abs(s[:60] - spec[:60]).max() < 1e-13
+    assert np.abs(s[60:]).max() < 1e-13
+    # the leading singular vectors span the constructed subspace: every
+    # principal angle between the two 50-dimensional spaces is tiny
+    cosines = np.linalg.svd(uq[:, :50].conj().T @ u[:, :50], compute_uv=False)
+    assert cosines.min() > 1 - 1e-10
