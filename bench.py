@@ -90,7 +90,9 @@ def roofline(name, kd):
         "bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
         "traffic": traffic_per_launch(name), "kernel": name, "launches": kd["launches"],
         "avg_launch_us": 1e3 * kd["ms"] / max(kd["launches"], 1),
-        f"algorithmic_{work}_per_launch": kd[work] / max(kd["launches"], 1),
+        "algorithmic_flops_per_launch": kd["flops"] / max(kd["launches"], 1),
+        "algorithmic_bytes_per_launch": kd["bytes"] / max(kd["launches"], 1),
+        "work": work,
     }
 
 
@@ -156,6 +158,7 @@ def main():
         if i == args.warmup - 1:
             breakdown = ctx.dump_stats()
             ctx.set_profiling(False)
+        print(f"bench: warm-up step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     ctx.sync()
     torch.cuda.synchronize()
     dom = dominant(breakdown) if breakdown else "zgemm"
@@ -173,6 +176,7 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
+    print(f"bench: {args.steps} timed steps done", file=sys.stderr, flush=True)
     ms = e0.elapsed_time(e1)
     kd = ctx.stats(dom)
     ctx.set_profiling(False)
