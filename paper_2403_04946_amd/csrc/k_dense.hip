@@ -4,11 +4,11 @@
 // a truncation step (the "SVD of the R factor" of App. A.4): columns are
 // rotated pairwise until orthogonal; their norms are the singular values
 // and the normalised columns the left singular vectors.  The columns are
-// cut into blocks of 16.  One sweep runs every block on its own (all pairs
+// cut into blocks of 8.  One sweep runs every block on its own (all pairs
 // inside a block, circle ordering) and then the rounds of a round-robin
-// tournament over the blocks, one workgroup per block pair meeting all 256
+// tournament over the blocks, one workgroup per block pair meeting all 64
 // pairs between the two blocks.  A column pair is held in registers by a
-// group of 16 lanes (a whole wavefront beyond 320 rows); columns move
+// group of 32 lanes (a whole wavefront beyond 320 rows); columns move
 // between groups through LDS.  Every column pair meets once per sweep, so
 // this is a cyclic Jacobi method with a block ordering; sweeps stop after
 // the first one without a rotation.
@@ -40,7 +40,7 @@ __device__ inline double block_sum(double v, double* red) {
 constexpr int JAC_THREADS = 1024;
 constexpr int JAC_GROUPS = JAC_THREADS / 16;
 constexpr int JAC_MAX_SWEEPS = 60;
-constexpr int JB_COLS = 16;    // columns per block
+constexpr int JB_COLS = 8;     // columns per block
 constexpr int JB_MAXM = 512;   // rows supported by the register-resident form
 constexpr int JB_MAXK = 512;   // columns
 constexpr int JB_MAXS = 64;    // sweep counters
@@ -67,15 +67,13 @@ void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* swe
 }
 
 // ------------------------------------------------ block-parallel Jacobi
-// A column pair is held by a group of GS lanes (16: one DPP row, 64: a whole
-// wavefront), lane l owning rows l + GS j, j < RPL.
+// A column pair is held by a group of GS lanes (16: one DPP row, 32: half a
+// wavefront, 64: a whole wavefront), lane l owning rows l + GS j, j < RPL.
 template <int GS>
 __device__ inline double group_sum(double x) {
   x = row16_sum(x);
-  if (GS == 64) {
-    x += __shfl_xor(x, 16, 64);
-    x += __shfl_xor(x, 32, 64);
-  }
+  if (GS >= 32) x += __shfl_xor(x, 16, 64);
+  if (GS == 64) x += __shfl_xor(x, 32, 64);
   return x;
 }
 
@@ -206,15 +204,15 @@ __global__ __launch_bounds__(GS * W) void jacobi_circle_kernel(zc* __restrict__ 
   }
 }
 
-// All 16 x 16 column pairs between blocks a and b (16 columns each; the
+// All BC x BC column pairs between blocks a and b (BC columns each; the
 // pair of workgroup g in round `round` of a round-robin over P blocks):
-// group w keeps column 16a + w and meets column 16b + (w + s) mod 16 in
+// group w keeps column BC a + w and meets column BC b + (w + s) mod BC in
 // step s; between steps the b columns move to the previous group.
-template <int RPL, int GS>
-__global__ __launch_bounds__(16 * GS) void jacobi_cross_kernel(zc* __restrict__ B, int m, int k, int P, int round,
+template <int RPL, int GS, int BC>
+__global__ __launch_bounds__(BC * GS) void jacobi_cross_kernel(zc* __restrict__ B, int m, int k, int P, int round,
                                                                int sweep, int* __restrict__ rot, double tol,
                                                                const double* __restrict__ fro2) {
-  extern __shared__ double2 xch[];  // 16 slots of GS RPL rows
+  extern __shared__ double2 xch[];  // BC slots of GS RPL rows
   __shared__ int wg_rot;
   if (sweep > 0 && rot[sweep - 1] == 0) return;
   const double abs2 = 1e-30 * fro2[0];  // (1e-15 |B|_F)^2
@@ -222,10 +220,10 @@ __global__ __launch_bounds__(16 * GS) void jacobi_cross_kernel(zc* __restrict__ 
   int ba, bb;
   rr_pair(P, round, blockIdx.x, ba, bb);
   const int w = threadIdx.x / GS, lane = threadIdx.x % GS;
-  const int ca = ba * JB_COLS + w;
+  const int ca = ba * BC + w;
   zc xa[RPL], xb[RPL];
   {
-    const int cb = bb * JB_COLS + w;
+    const int cb = bb * BC + w;
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
       const int row = lane + GS * j;
@@ -234,12 +232,12 @@ __global__ __launch_bounds__(16 * GS) void jacobi_cross_kernel(zc* __restrict__ 
     }
   }
   zc* mine = xch + (long)LD * w;
-  const zc* next = xch + (long)LD * ((w + 1) & 15);
+  const zc* next = xch + (long)LD * ((w + 1) % BC);
   int nrot = 0;
-  for (int st = 0; st < JB_COLS; ++st) {
-    const int cb = bb * JB_COLS + ((w + st) & 15);
+  for (int st = 0; st < BC; ++st) {
+    const int cb = bb * BC + (w + st) % BC;
     if (ca < k && cb < k) nrot += jacobi_rotate<RPL, GS>(xa, xb, tol, abs2);
-    if (st == JB_COLS - 1) break;
+    if (st == BC - 1) break;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < RPL; ++j) mine[lane + GS * j] = xb[j];
@@ -248,7 +246,7 @@ __global__ __launch_bounds__(16 * GS) void jacobi_cross_kernel(zc* __restrict__ 
     for (int j = 0; j < RPL; ++j) xb[j] = next[lane + GS * j];
   }
   jacobi_count(nrot, &wg_rot, rot, sweep);
-  const int cb = bb * JB_COLS + ((w + JB_COLS - 1) & 15);
+  const int cb = bb * BC + (w + BC - 1) % BC;
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
     const int row = lane + GS * j;
@@ -314,36 +312,36 @@ void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int ro
   if (kind == 0)  // whole matrix (k <= 32) in one workgroup
     hipLaunchKernelGGL((jacobi_circle_kernel<RPL, 16, GS>), dim3(1), dim3(16 * GS), 16 * slot, ctx->stream, B, m, k,
                        inner_max, sweep, rot, tol, fro2);
-  else if (kind == 1)  // every block of 16 columns on its own
-    hipLaunchKernelGGL((jacobi_circle_kernel<RPL, 8, GS>), dim3((k + 15) / 16), dim3(8 * GS), 8 * slot, ctx->stream,
-                       B, m, k, 1, sweep, rot, tol, fro2);
+  else if (kind == 1)  // every block of JB_COLS columns on its own
+    hipLaunchKernelGGL((jacobi_circle_kernel<RPL, JB_COLS / 2, GS>), dim3((k + JB_COLS - 1) / JB_COLS),
+                       dim3(JB_COLS / 2 * GS), JB_COLS / 2 * slot, ctx->stream, B, m, k, 1, sweep, rot, tol, fro2);
   else
-    hipLaunchKernelGGL((jacobi_cross_kernel<RPL, GS>), dim3(P / 2), dim3(16 * GS), 16 * slot, ctx->stream, B, m, k,
-                       P, round, sweep, rot, tol, fro2);
+    hipLaunchKernelGGL((jacobi_cross_kernel<RPL, GS, JB_COLS>), dim3(P / 2), dim3(JB_COLS * GS), JB_COLS * slot,
+                       ctx->stream, B, m, k, P, round, sweep, rot, tol, fro2);
   TTF_HIP(hipGetLastError());
 }
 
-// Blocks of 16 columns; one sweep = every block on its own (all pairs
+// Blocks of JB_COLS columns; one sweep = every block on its own (all pairs
 // inside a block) followed by the P - 1 rounds of a round-robin over the
 // blocks (all pairs between two blocks), so each column pair meets once.
 void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
   int* rot = (int*)ctx->get_ws("jac_rot", sizeof(int) * JB_MAXS + 64);
   double* fro2 = (double*)(rot + JB_MAXS);
   frob_norm2(ctx, B, (long)m * k, fro2);
-  // a 16-lane group per column pair up to 320 rows (at most 20 rows per
+  // a 32-lane group per column pair up to 320 rows (at most 10 rows per
   // lane), a whole wavefront beyond
   auto launch = [&](int kind, int P, int round, int inner_max, int sweep, int* rot, double tol) {
     const double* f2 = fro2;
     if (m <= 64)
-      jacobi_launch_rpl<4, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
+      jacobi_launch_rpl<2, 32>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else if (m <= 128)
-      jacobi_launch_rpl<8, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
+      jacobi_launch_rpl<4, 32>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else if (m <= 192)
-      jacobi_launch_rpl<12, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
+      jacobi_launch_rpl<6, 32>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else if (m <= 256)
-      jacobi_launch_rpl<16, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
+      jacobi_launch_rpl<8, 32>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else if (m <= 320)
-      jacobi_launch_rpl<20, 16>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
+      jacobi_launch_rpl<10, 32>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else
       jacobi_launch_rpl<8, 64>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
   };
@@ -353,7 +351,7 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, ctx->stream, rot, JB_MAXS);
   TTF_HIP(hipGetLastError());
   int nsweeps = 0;
-  if (k <= 2 * JB_COLS) {
+  if (k <= 32) {
     launch(0, 2, 0, JAC_MAX_SWEEPS, 0, rot, tol);
     nsweeps = JAC_MAX_SWEEPS;
   } else {

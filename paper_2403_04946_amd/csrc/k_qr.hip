@@ -349,56 +349,81 @@ void bcgs_put_diag(tt_ctx* ctx, zc* Rd, long ldr, const zc* Rp, int nb, const in
   TTF_HIP(hipGetLastError());
 }
 
-// Cholesky factor of the nb x nb Hermitian matrix in Gs (LDS), G = R^H R,
-// by a workgroup of 1024 threads (thread (i, j) = (t % 32, t / 32) owns
-// entry (i, j)): Gs becomes R (upper triangle), dinv the reciprocals of its
-// diagonal and, when Ri is given, Ri its inverse (one column per thread,
-// back substitution).  dg holds the original diagonal; *bad = 1 when a
-// pivot falls below tau times it (bad may be null).
-__device__ void block_chol_inv(zc (*Gs)[PT_COLS + 1], const double* dg, zc (*Ri)[PT_COLS + 1], int nb, double tau,
-                               int* bad, double* dinv) {
+// Cholesky factor and inverse of the nb x nb Hermitian matrix in Gs (LDS),
+// G = R^H R with R upper triangular, by a workgroup of 1024 threads (thread
+// (i, j) = (t % 32, t / 32) owns entry (i, j)); nb <= 32.
+// Factor: step r subtracts conj(G[r][a]) G[r][b] / G[r][r] from the
+// trailing entries and stores row r of R, one barrier per step.  Inverse:
+// recursive doubling on diagonal blocks of size h = 1, 2, 4, 8, 16: the
+// off-diagonal block of [A B; 0 C]^{-1} is -A^{-1} (B C^{-1}).
+// On return Rs holds R (zero below the diagonal and beyond nb), Ri its
+// inverse, dinv the reciprocal diagonal; dg holds the original diagonal and
+// *bad = 1 when a pivot falls below tau times it (bad may be null).  Gs and
+// T are overwritten.
+__device__ void block_chol_inv(zc (*Gs)[PT_COLS + 1], zc (*Rs)[PT_COLS + 1], zc (*Ri)[PT_COLS + 1],
+                               zc (*T)[PT_COLS + 1], const double* dg, int nb, double tau, int* bad,
+                               double* dinv) {
+  __shared__ double piv[PT_COLS][2];  // 1 / d and 1 / sqrt(d) of step r
   const int t = threadIdx.x, i = t & 31, j = t >> 5;
+  Rs[i][j] = make_double2(0.0, 0.0);
+  // the pivot of step r is prepared by the thread that last updated it
+  auto pivot = [&](int r, double d) {
+    const bool ok = d > tau * dg[r] && d > 0.0;
+    if (!ok && bad) *bad = 1;
+    const double dd = ok ? d : 1.0;
+    const double is = 1.0 / sqrt(dd);
+    piv[r][0] = is * is;
+    piv[r][1] = is;
+    dinv[r] = is;
+  };
+  if (t == 0 && nb > 0) pivot(0, Gs[0][0].x);
+  __syncthreads();
   for (int r = 0; r < nb; ++r) {
-    if (t == 0) {
-      const double d = Gs[r][r].x;
-      const bool ok = d > tau * dg[r] && d > 0.0;
-      if (!ok && bad) *bad = 1;
-      const double sd = ok ? sqrt(d) : 1.0;
-      Gs[r][r] = make_double2(sd, 0.0);
-      dinv[r] = 1.0 / sd;
+    const double id = piv[r][0], is = piv[r][1];
+    if (i == r && j >= r && j < nb) {
+      const zc g = Gs[r][j];
+      Rs[r][j] = (j == r) ? make_double2(1.0 / is, 0.0) : make_double2(g.x * is, g.y * is);
     }
-    __syncthreads();
-    if (t > r && t < nb) {
-      const double inv = dinv[r];
-      Gs[r][t] = make_double2(Gs[r][t].x * inv, Gs[r][t].y * inv);
-    }
-    __syncthreads();
     if (i > r && j >= i && j < nb) {
       const zc x = Gs[r][i], y = Gs[r][j];
       zc g = Gs[i][j];
-      g.x -= x.x * y.x + x.y * y.y;
-      g.y -= x.x * y.y - x.y * y.x;
+      g.x -= (x.x * y.x + x.y * y.y) * id;  // conj(x) y / d
+      g.y -= (x.x * y.y - x.y * y.x) * id;
       Gs[i][j] = g;
+      if (i == r + 1 && j == r + 1) pivot(r + 1, g.x);
     }
     __syncthreads();
   }
-  if (!Ri) return;
-  if (t < nb) {
-    const int c = t;
-    for (int q = 0; q < nb; ++q) Ri[q][c] = make_double2(0.0, 0.0);
-    Ri[c][c] = make_double2(dinv[c], 0.0);
-    for (int q = c - 1; q >= 0; --q) {
+  // identity beyond nb keeps the padded factor invertible
+  if (i == j && i >= nb) Rs[i][j] = make_double2(1.0, 0.0);
+  if (t >= nb && t < PT_COLS) dinv[t] = 1.0;
+  __syncthreads();
+  Ri[i][j] = (i == j) ? make_double2(dinv[i], 0.0) : make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int h = 1; h < PT_COLS; h *= 2) {
+    const int s0 = (i / (2 * h)) * (2 * h);
+    const bool blk = i < s0 + h && j >= s0 + h && j < s0 + 2 * h;
+    if (blk) {  // T = B C^{-1}
       double sr = 0, si = 0;
-      for (int u = q + 1; u <= c; ++u) {
-        const zc a = Gs[q][u], b = Ri[u][c];
+      for (int u = s0 + h; u <= j; ++u) {
+        const zc a = Rs[i][u], b = Ri[u][j];
         sr += a.x * b.x - a.y * b.y;
         si += a.x * b.y + a.y * b.x;
       }
-      const double dq = dinv[q];
-      Ri[q][c] = make_double2(-sr * dq, -si * dq);
+      T[i][j] = make_double2(sr, si);
     }
+    __syncthreads();
+    if (blk) {  // X = -A^{-1} T
+      double sr = 0, si = 0;
+      for (int u = i; u < s0 + h; ++u) {
+        const zc a = Ri[i][u], b = T[u][j];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+      Ri[i][j] = make_double2(-sr, -si);
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // Second pass of the block Gram-Schmidt step for one panel (one workgroup,
@@ -417,6 +442,8 @@ __global__ __launch_bounds__(1024) void bcgs_pip_kernel(const zc* __restrict__ W
   __shared__ zc Gs[PT_COLS][PT_COLS + 1];
   __shared__ zc R1s[PT_COLS][PT_COLS + 1];
   __shared__ zc Ri[PT_COLS][PT_COLS + 1];
+  __shared__ zc Rs[PT_COLS][PT_COLS + 1];
+  __shared__ zc Tt[PT_COLS][PT_COLS + 1];
   __shared__ int fl[PT_COLS];
   __shared__ double dg[PT_COLS], dinv[PT_COLS];
   __shared__ zc Wc[PT_COLS][65];  // 64-row chunks of W2
@@ -434,6 +461,7 @@ __global__ __launch_bounds__(1024) void bcgs_pip_kernel(const zc* __restrict__ W
     }
     __syncthreads();
     if (i < nb && j < nb)
+#pragma unroll 8
       for (int r = 0; r < rows; ++r) {
         const zc a = Wc[i][r], b = Wc[j][r];
         gr -= a.x * b.x + a.y * b.y;  // conj(a) b
@@ -444,6 +472,7 @@ __global__ __launch_bounds__(1024) void bcgs_pip_kernel(const zc* __restrict__ W
       const int r = e % rows, c = e / rows;
       if (fl[c]) continue;
       double sr = 0, si = 0;
+#pragma unroll 8
       for (int q = 0; q <= c; ++q) {
         const zc a = Wc[q][r], b = R1s[q][c];
         sr += a.x * b.x - a.y * b.y;
@@ -458,13 +487,13 @@ __global__ __launch_bounds__(1024) void bcgs_pip_kernel(const zc* __restrict__ W
   if (i < nb && j < nb) Gs[i][j] = make_double2(gr, gi);
   if (t < PT_COLS) dg[t] = 1.0;  // absolute pivot test: Z is near orthonormal
   __syncthreads();
-  block_chol_inv(Gs, dg, Ri, nb, 1e-2, bad, dinv);
+  block_chol_inv(Gs, Rs, Ri, Tt, dg, nb, 1e-2, bad, dinv);
   if (i < nb && j < nb) {
     R2inv[i + (long)nb * j] = Ri[i][j];
     // (R2 R1)[i][j], both upper
     double sr = 0, si = 0;
     for (int q = i; q <= j; ++q) {
-      const zc a = Gs[i][q], b = R1s[q][j];
+      const zc a = Rs[i][q], b = R1s[q][j];
       sr += a.x * b.x - a.y * b.y;
       si += a.x * b.y + a.y * b.x;
     }
@@ -472,73 +501,79 @@ __global__ __launch_bounds__(1024) void bcgs_pip_kernel(const zc* __restrict__ W
   }
 }
 
-// Z <- Z Rinv for rows [row0, row0 + rows) of the panel (ld ldz), Rinv upper
-// nb x nb in LDS; rows staged through the LDS tile, in place
-__device__ inline void tile_trmm(zc* __restrict__ Z, long ldz, long row0, int rows, int nb, zc (*tile)[65],
-                                 const zc (*Rs)[PT_COLS + 1]) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  __syncthreads();
-  for (int e = t; e < rows * nb; e += nt) {
-    const int r = e % rows, c = e / rows;
-    tile[c][r] = Z[row0 + r + ldz * c];
-  }
-  __syncthreads();
-  for (int e = t; e < rows * nb; e += nt) {
-    const int r = e % rows, c = e / rows;
-    double sr = 0, si = 0;
-    for (int q = 0; q <= c; ++q) {
-      const zc a = tile[q][r], b = Rs[q][c];
-      sr += a.x * b.x - a.y * b.y;
-      si += a.x * b.y + a.y * b.x;
-    }
-    Z[row0 + r + ldz * c] = make_double2(sr, si);
-  }
-}
-
 // One Cholesky QR pass on the m x nb panel Y given its Gram matrix G
 // (ld nb): every workgroup factors G = R^H R and inverts R itself (nb <= 32,
 // cheap) and replaces its 256 rows by Y R^{-1}; workgroup 0 also writes
 // Rout = R Rprev (R without Rprev) and raises *bad when a pivot falls below
-// tau times its diagonal entry.
+// tau times its diagonal entry.  The rows are fetched into registers before
+// the factorisation and multiplied in two 128-row tiles through LDS.
 __global__ __launch_bounds__(1024) void chol_solve_kernel(zc* __restrict__ Y, long ldy, int m, int nb,
                                                          const zc* __restrict__ G, double tau,
                                                          const zc* __restrict__ Rprev, zc* __restrict__ Rout,
                                                          int* __restrict__ bad) {
   __shared__ zc Gs[PT_COLS][PT_COLS + 1];
+  __shared__ zc Rs[PT_COLS][PT_COLS + 1];
   __shared__ zc Ri[PT_COLS][PT_COLS + 1];
-  __shared__ zc tile[PT_COLS][65];
-  __shared__ zc Rp[PT_COLS][PT_COLS + 1];
+  __shared__ zc Tt[PT_COLS][PT_COLS + 1];
+  __shared__ zc tile[PT_COLS][129];
   __shared__ double dg[PT_COLS], dinv[PT_COLS];
   const int t = threadIdx.x;
   const int i = t & 31, j = t >> 5;
-  if (i < nb && j < nb) {
-    Gs[i][j] = G[i + (long)nb * j];
-    if (Rprev && blockIdx.x == 0) Rp[i][j] = Rprev[i + (long)nb * j];
+  const long row0 = (long)blockIdx.x * 256;
+  const int rows = (m - row0 < 256) ? (int)(m - row0) : 256;
+  // thread t holds row t % 256 of the block, columns t / 256 + 4 u
+  const int rr = t & 255, cg = t >> 8;
+  zc y[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int c = cg + 4 * u;
+    y[u] = (rr < rows && c < nb) ? Y[row0 + rr + ldy * c] : make_double2(0.0, 0.0);
   }
+  if (i < nb && j < nb) Gs[i][j] = G[i + (long)nb * j];
   if (t < nb) dg[t] = G[t + (long)nb * t].x;
   __syncthreads();
-  block_chol_inv(Gs, dg, Ri, nb, tau, blockIdx.x == 0 ? bad : nullptr, dinv);
+  block_chol_inv(Gs, Rs, Ri, Tt, dg, nb, tau, blockIdx.x == 0 ? bad : nullptr, dinv);
   if (blockIdx.x == 0 && i < nb && j < nb) {
     zc v = make_double2(0.0, 0.0);
     if (i <= j) {
       if (Rprev) {
         double sr = 0, si = 0;
         for (int q = i; q <= j; ++q) {
-          const zc a = Gs[i][q], b = Rp[q][j];
+          const zc a = Rs[i][q], b = Rprev[q + (long)nb * j];
           sr += a.x * b.x - a.y * b.y;
           si += a.x * b.y + a.y * b.x;
         }
         v = make_double2(sr, si);
       } else {
-        v = Gs[i][j];
+        v = Rs[i][j];
       }
     }
     Rout[i + (long)nb * j] = v;
   }
-  const long r0 = (long)blockIdx.x * 256;
-  for (int s0 = 0; s0 < 256 && r0 + s0 < m; s0 += 64) {
-    const long row0 = r0 + s0;
-    tile_trmm(Y, ldy, row0, (m - row0 < 64) ? (int)(m - row0) : 64, nb, tile, Ri);
+  for (int half = 0; half < 2; ++half) {
+    const int lo = 128 * half;
+    if (lo >= rows) break;
+    __syncthreads();
+    if (rr >= lo && rr < lo + 128) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = cg + 4 * u;
+        if (c < PT_COLS) tile[c][rr - lo] = y[u];
+      }
+    }
+    __syncthreads();
+    const int nrow = (rows - lo < 128) ? rows - lo : 128;
+    for (int e = t; e < nrow * nb; e += 1024) {
+      const int r = e % nrow, c = e / nrow;
+      double sr = 0, si = 0;
+#pragma unroll 8
+      for (int q = 0; q <= c; ++q) {
+        const zc a = tile[q][r], b = Ri[q][c];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+      Y[row0 + lo + r + ldy * c] = make_double2(sr, si);
+    }
   }
 }
 
@@ -569,6 +604,7 @@ __global__ __launch_bounds__(256) void panel_trmm_kernel(zc* __restrict__ Z, lon
   for (int e = t; e < rows * nb; e += 256) {
     const int r = e % rows, c = e / rows;
     double sr = 0, si = 0;
+#pragma unroll 8
     for (int q = 0; q <= c; ++q) {
       const zc a = tile[q][r], b = Rs[q][c];
       sr += a.x * b.x - a.y * b.y;
