@@ -1,26 +1,37 @@
 #!/usr/bin/env python3
 """RK4 stages/s of the TT step-truncation solver for the Burgers-Hopf
-characteristic-function PDE on one MI355X.
+characteristic-function PDE on one MI355X, mixed-precision form against
+plain FP64.
 
-Workload (the metric's configuration): d = 50 Fourier modes, n = 128 grid
-points per mode on [-8, 8], nu = 0.01, rank cap 64, relative truncation
-tolerance 1e-6, dt = 2e-4, plain complex FP64 arithmetic.  Timing uses the
-saturated regime: the input is a seeded random TT with every interior rank
-at the cap (64), so every stage runs at the worst-case shapes of the
+Workload (the metric's configuration, precision form): d = 50 Fourier
+modes, n = 128 grid points per mode on [-8, 8], nu = 0.01, rank cap 64,
+relative truncation tolerance 1e-6, dt = 2e-4.  The operator application's
+sketch contractions run in split-FP16x3 on the fp16 matrix cores (FP32
+accumulation; --precision bf16x3 selects split-BF16x3, fp64 the plain
+form); QR, SVD, the truncation test and all sums stay FP64.  Timing uses
+the saturated regime: the input is a seeded random TT with every interior
+rank at the cap (64), so every stage runs at the worst-case shapes of the
 configuration.  One step = one RK4 step-truncation step (4 stages: four
 sketched operator applications, their truncations, the stage combinations
 and their truncations) followed by a pointwise read-out of 1024 entries.
 
-Prints one JSON line.  `value` is stages per second (4 per step) over the
-timed steps, with the input resident in device memory.  The last warm-up
-step is profiled per kernel class (HIP events around every launch); the
-class with the most time becomes the roofline kernel, and only its launches
-are timed with events inside the timed region.  `roofline` divides its
-algorithmic FLOPs (or bytes, for memory-bound kernels) by its event-timed
-duration and compares with the MI355X peak: FP64 78.6 TFLOP/s for the
-matrix-core GEMM and for the FP64 vector kernels alike, 8 TB/s HBM.
-`cpu_baseline` is the CPU oracle (full-grid RK4 step-truncation) on a
-bounded sample.
+Prints one JSON line.  `value` is stages per second (4 per step) of the
+selected form over the timed steps, with the input resident in device
+memory; `fp64_reference` times the plain FP64 form the same way from the
+same input.  `error_vs_fp64` gives the relative L2 distance to the FP64
+form per stage from identical inputs (the stage derivative k after its
+truncation, and the stage output y = f + c dt k) in the timed regime and
+along a trajectory from the seeded Gaussian initial condition, plus whole
+steps from identical inputs; the gate is 1e-5.  The last warm-up step is
+profiled per kernel class (HIP events around every launch); the class with
+the most time becomes the roofline kernel, and only its launches are timed
+with events inside the timed region.  `roofline` divides its algorithmic
+FLOPs (or bytes, for memory-bound kernels) by its event-timed duration and
+compares with the MI355X peak: FP64 78.6 TFLOP/s for the FP64 matrix-core
+GEMM and the FP64 vector kernels, 2.5 PFLOP/s dense fp16/bf16 for the split
+GEMMs (counting the three 16-bit products per real product they execute),
+8 TB/s HBM.  `cpu_baseline` is the CPU oracle (full-grid RK4
+step-truncation) on a bounded sample.
 """
 import argparse
 import json
@@ -30,7 +41,10 @@ import time
 
 D, N, LEN, NU, CAP, EPS, DT = 50, 128, 8.0, 0.01, 64, 1e-6, 2e-4
 PEAK_F64_TFLOPS = 78.6  # FP64: matrix cores and vector units alike
+PEAK_F16_TFLOPS = 2500.0  # dense fp16 / bf16 matrix cores
 PEAK_HBM_GBS = 8000.0
+GATE = 1e-5
+PRECISIONS = {"fp64": 0, "bf16x3": 1, "fp16x3": 2}
 
 
 def cpu_baseline(seconds_target=20.0):
@@ -68,7 +82,7 @@ def cpu_baseline(seconds_target=20.0):
 
 # kernel classes that are one kernel each, with the resource that bounds them
 KERNEL_BOUND = {
-    "zgemm": "mfma", "pt_leaf": "alu", "pt_assemble": "hbm", "panel_trmm": "hbm", "bcgs_pip": "alu",
+    "zgemm": "mfma", "zgemm_fp16x3": "mfma", "zgemm_bf16x3": "mfma", "chol_solve": "alu", "pt_leaf": "alu", "pt_assemble": "hbm", "panel_trmm": "hbm", "bcgs_pip": "alu",
     "gather_left": "hbm", "gather_right": "hbm", "zgemm_reduce": "hbm", "concat": "hbm",
 }
 
@@ -85,7 +99,8 @@ def roofline(name, kd):
     if bound == "hbm":
         achieved, peak, unit, work = kd["bytes"] / sec / 1e9, PEAK_HBM_GBS, "GB/s", "bytes"
     else:
-        achieved, peak, unit, work = kd["flops"] / sec / 1e12, PEAK_F64_TFLOPS, "TFLOP/s", "flops"
+        peak = PEAK_F16_TFLOPS if name in ("zgemm_fp16x3", "zgemm_bf16x3") else PEAK_F64_TFLOPS
+        achieved, unit, work = kd["flops"] / sec / 1e12, "TFLOP/s", "flops"
     return {
         "bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
         "traffic": traffic_per_launch(name), "kernel": name, "launches": kd["launches"],
@@ -114,12 +129,86 @@ def traffic_per_launch(name):
     return rec["bytes_per_launch"]
 
 
+def rel_tt(ctx, tt, a, b):
+    """||a - b|| / ||b|| of device TTs via the difference TT."""
+    import numpy as np
+
+    caps = np.array(a.ranks()) + np.array(b.ranks())
+    caps[0] = caps[-1] = 1
+    diff = tt.Tensor(ctx, D, N, caps)
+    tt.tt_axpy(ctx, 1.0, a, -1.0, b, diff)
+    r = tt.tt_norm(ctx, diff) / tt.tt_norm(ctx, b)
+    diff.close()
+    return r
+
+
+def stage_errors(ctx, tt, op, f, prec, ell, seed, c=0.5 * DT):
+    """One stage from the identical input f in FP64 and in `prec`: relative
+    L2 of the truncated stage derivative k and of the stage output
+    y = T[f + c k]."""
+    out = {}
+    ks = []
+    for p in (0, prec):
+        k = tt.Tensor(ctx, D, N, max(ell, CAP))
+        tt.tt_apply(ctx, op, f, k, tt.TT_APPLY_SKETCH, ell, seed, precision=p)
+        tt.tt_round(ctx, k, EPS, CAP, report=False)
+        y = tt.Tensor(ctx, D, N, 2 * CAP)
+        tt.tt_axpy(ctx, 1.0, f, c, k, y)
+        tt.tt_round(ctx, y, EPS, CAP, report=False)
+        ks.append((k, y))
+    out["k"] = rel_tt(ctx, tt, ks[1][0], ks[0][0])
+    out["stage_output"] = rel_tt(ctx, tt, ks[1][1], ks[0][1])
+    for k, y in ks:
+        k.close()
+        y.close()
+    return out
+
+
+def error_report(ctx, tt, op, f0, prec, ell, traj_steps):
+    """Errors of the `prec` form against plain FP64 from identical inputs:
+    one stage and one step in the timed (saturated) regime, then along the
+    FP64 trajectory from the seeded Gaussian initial condition every stage
+    (from the FP64 stage input) and every step (from the FP64 step input)."""
+    from paper_2403_04946_amd import inputs
+
+    rep = {"gate": GATE}
+    rep["saturated_stage"] = stage_errors(ctx, tt, op, f0, prec, ell, 99)
+    a, b = tt.Tensor(ctx, D, N, CAP), tt.Tensor(ctx, D, N, CAP)
+    a.copy_from(f0)
+    b.copy_from(f0)
+    tt.tt_step(ctx, op, a, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 7, precision=0)
+    tt.tt_step(ctx, op, b, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 7, precision=prec)
+    rep["saturated_step"] = rel_tt(ctx, tt, b, a)
+    mu, sig = inputs.ic_params(D, 0)
+    a.set_gaussian(mu, sig, LEN)
+    ks, ys, steps = [], [], []
+    for s in range(traj_steps):
+        se = stage_errors(ctx, tt, op, a, prec, ell, 1000 + s)
+        ks.append(se["k"])
+        ys.append(se["stage_output"])
+        b.copy_from(a)
+        tt.tt_step(ctx, op, b, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 500 + s, precision=prec)
+        tt.tt_step(ctx, op, a, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 500 + s, precision=0)
+        steps.append(rel_tt(ctx, tt, b, a))
+    rep["trajectory_from_ic"] = {"stage_k": ks, "stage_output": ys, "step": steps}
+    worst = max([rep["saturated_stage"]["stage_output"], rep["saturated_step"]] + ys + steps)
+    rep["worst_stage_output_or_step"] = worst
+    rep["within_gate"] = bool(worst <= GATE)
+    a.close()
+    b.close()
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sketch-rank", type=int, default=80)
+    ap.add_argument("--precision", choices=sorted(PRECISIONS), default="fp16x3")
+    ap.add_argument("--error-steps", type=int, default=2,
+                    help="trajectory steps from the initial condition in the error report")
+    ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -133,15 +222,18 @@ def main():
     torch.cuda.init()
     ctx = tt.Context(0)
     op = tt.Operator(ctx, D, N, LEN, NU)
+    prec = PRECISIONS[args.precision]
+    f0 = tt.Tensor(ctx, D, N, CAP)
+    f0.set_cores(inputs.random_tt(D, N, CAP, 0))
     f = tt.Tensor(ctx, D, N, CAP)
-    f.set_cores(inputs.random_tt(D, N, CAP, 0))
+    f.copy_from(f0)
     idx = torch.from_numpy(inputs.random_points(D, N, 1024, 1)).cuda()
     out = torch.empty(1024, dtype=torch.complex128, device="cuda")
     ell = args.sketch_rank
     seed = 12345
 
-    def step():
-        rep = tt.tt_step(ctx, op, f, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, seed)
+    def step(p=prec):
+        rep = tt.tt_step(ctx, op, f, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, seed, precision=p)
         tt.tt_eval(ctx, f, idx, out)
         return rep
 
@@ -185,6 +277,31 @@ def main():
 
     stages = 4 * args.steps
     value = stages / (ms / 1e3)
+    final_ranks_max = max(f.ranks())
+
+    fp64_ref = None
+    if prec != 0 and not args.no_fp64_reference:
+        # the plain FP64 form from the same input, timed the same way
+        f.copy_from(f0)
+        step(0)
+        ctx.sync()
+        torch.cuda.synchronize()
+        f.copy_from(f0)
+        torch.cuda.synchronize()
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0.record(stream)
+        for _ in range(args.steps):
+            step(0)
+        r1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = r0.elapsed_time(r1)
+        fp64_ref = {"value": stages / (ms64 / 1e3), "unit": "RK stages/s", "ms_per_step": ms64 / args.steps,
+                    "speedup_of_selected_form": (stages / (ms / 1e3)) / (stages / (ms64 / 1e3))}
+        print(f"bench: FP64 reference, {args.steps} timed steps done", file=sys.stderr, flush=True)
+    errors = None
+    if prec != 0:
+        errors = error_report(ctx, tt, op, f0, prec, ell, args.error_steps)
+        print("bench: error report done", file=sys.stderr, flush=True)
     roof = roofline(dom, kd)
     kernels_ms = {k: round(v["ms"], 3) for k, v in (breakdown or {}).items() if k != "qr_fallbacks"}
     result = {
@@ -198,18 +315,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {0: "f64", 1: "bf16x3+f64", 2: "fp16x3+f64"}[prec],
         "data": "synthetic",
         "config": {
-            "workload": "Burgers-Hopf TT RK4 step-truncation, plain complex FP64, saturated ranks",
+            "workload": ("Burgers-Hopf TT RK4 step-truncation, saturated ranks, "
+                         + {0: "plain complex FP64",
+                            1: "sketch contractions split-BF16x3 (FP32 accumulate), QR/SVD/truncation FP64",
+                            2: "sketch contractions split-FP16x3 (FP32 accumulate), QR/SVD/truncation FP64"}[prec]),
+            "precision": args.precision,
             "d": D, "n": N, "L": LEN, "nu": NU, "rank_cap": CAP, "eps": EPS, "dt": DT,
             "apply": f"sketched (width {ell})", "input": "seeded random TT, all interior ranks 64",
         },
         "roofline": roof,
+        "fp64_reference": fp64_ref,
+        "error_vs_fp64": errors,
         "kernels_ms_profiled_warmup_step": kernels_ms,
         "qr_fallbacks": int((breakdown or {}).get("qr_fallbacks", {"launches": 0})["launches"]),
         "wall_s": wall,
-        "final_ranks_max": max(f.ranks()),
+        "final_ranks_max": final_ranks_max,
         "step_max_rank": rep["max_rank"] if rep else None,
     }
     if not args.no_cpu_baseline:

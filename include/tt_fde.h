@@ -64,6 +64,17 @@ enum {
   TT_APPLY_SKETCH = 1  /* fused apply + randomised range compression           */
 };
 
+/* Arithmetic of the operator application's contractions. */
+enum {
+  TT_PREC_FP64 = 0,    /* plain complex FP64                                   */
+  TT_PREC_BF16X3 = 1,  /* split-BF16x3 on the bf16 matrix cores, FP32
+                          accumulation (about 17 significant bits; see
+                          tt_zgemm_mixed)                                      */
+  TT_PREC_FP16X3 = 2   /* split-FP16x3 on the fp16 matrix cores with a
+                          power-of-two scale per K stage, FP32 accumulation
+                          (about 22 significant bits)                          */
+};
+
 typedef struct tt_ctx tt_ctx;
 typedef struct tt_tensor tt_tensor;
 typedef struct tt_op tt_op;
@@ -165,7 +176,10 @@ typedef struct {
   int size;              /* sizeof(tt_apply_opts) */
   int mode;              /* TT_APPLY_EXACT or TT_APPLY_SKETCH */
   int sketch_rank;       /* sketch width l for TT_APPLY_SKETCH (>= 1) */
-  int pad;
+  int precision;         /* TT_PREC_FP64, or TT_PREC_BF16X3 / TT_PREC_FP16X3:
+                            the sketch contractions in that split 16-bit
+                            form (mixed form; the exact product and
+                            everything else stay FP64) */
   uint64_t seed;         /* counter-based RNG key for the Gaussian sketch */
 } tt_apply_opts;
 
@@ -210,6 +224,10 @@ typedef struct {
   int apply_mode;        /* TT_APPLY_EXACT or TT_APPLY_SKETCH */
   int sketch_rank;
   uint64_t seed;
+  int precision;         /* a TT_PREC_* value (the operator
+                            applications' contractions; QR, SVD, truncation
+                            test and sums always FP64) */
+  int pad;
 } tt_step_opts;
 
 typedef struct {
@@ -242,6 +260,20 @@ int tt_zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, double alpha_re
              const double* A, int64_t lda, int64_t strideA, const double* B, int64_t ldb,
              int64_t strideB, double beta_re, double beta_im, double* C, int64_t ldc,
              int64_t strideC, int batch);
+
+/* The same product in a split 16-bit arithmetic on the matrix cores: the
+ * core contractions of the mixed-precision form.  Every real operand is
+ * split as hi + lo in the 16-bit format and each real product taken as
+ * hi*hi + hi*lo + lo*hi with FP32 accumulation, summed into FP64.
+ * precision TT_PREC_BF16X3: bfloat16 halves, error about 1e-5 of
+ * |op(A)| |op(B)| per entry.  TT_PREC_FP16X3: half-precision halves with a
+ * power-of-two scale per 32-wide K stage of each operand tile, error about
+ * 5e-7 of the same.  Other arguments and layout as tt_zgemm; TT_EINVAL for
+ * any other precision. */
+int tt_zgemm_mixed(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, int K, double alpha_re,
+                   double alpha_im, const double* A, int64_t lda, int64_t strideA, const double* B,
+                   int64_t ldb, int64_t strideB, double beta_re, double beta_im, double* C, int64_t ldc,
+                   int64_t strideC, int batch);
 
 /* Frobenius norm of x (synchronous; computed by orthogonalisation). */
 int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out);

@@ -415,7 +415,14 @@ void apply_exact(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y)
   y->orth = TT_ORTH_NONE;
 }
 
-void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int l, uint64_t seed) {
+void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int l, uint64_t seed,
+                  int precision) {
+  // the sketch contractions in plain FP64 or a split 16-bit form (mixed)
+  auto gemm = [ctx, precision](tt_ctx*, int opA, int opB, int M, int N, int K, zc alpha, const zc* A, long lda,
+                                long sA, const zc* B, long ldb, long sB, zc beta, zc* C, long ldc, long sC,
+                                int batch) {
+    zgemm_prec(precision, ctx, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
+  };
   const int d = x->d, n = x->n;
   const auto& r = x->rank;
   const auto& R = op->R;
@@ -455,6 +462,10 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
   zc* M = (zc*)ctx->get_ws("sk_M", sizeof(zc) * std::max<size_t>(mmax, 1));
   zc* Qm = (zc*)ctx->get_ws("sk_Q", sizeof(zc) * std::max<size_t>(mmax, 1));
   zc* Rm = (zc*)ctx->get_ws("sk_R", sizeof(zc) * (size_t)l * l);
+  // power-of-two scales of the sketch chains: [0] current exponent, [1] the
+  // sum of the exponents taken out of P (restored in the last core)
+  int* pexp = (int*)ctx->get_ws("sk_pow2", 64);
+  zero_ints(ctx, pexp, 2);
   // S_0 = 1
   {
     const zc one = Z(1);
@@ -465,12 +476,14 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
     const int lm = ll[m], lp = ll[m + 1], r0 = r[m], r1 = r[m + 1], R0 = R[m], R1 = R[m + 1];
     const zc* Sm = S + sk_off[m];
     // V[j, alpha, i', b] = sum_a S_m[j, a, alpha] C_m[a, i', b]  (batched over alpha)
-    zgemm(ctx, OPN, OPN, lm, n * r1, r0, Z(1), Sm, lm, (long)lm * r0, x->core[m], r0, 0, Z(0), V, (long)lm * R0,
+    gemm(ctx, OPN, OPN, lm, n * r1, r0, Z(1), Sm, lm, (long)lm * r0, x->core[m], r0, 0, Z(0), V, (long)lm * R0,
           lm, R0);
     gather_left(ctx, op, m, V, W, lm, r1);
     sketch_core(ctx, omega, (long)lm * n * lp, seed, m, 1.0 / std::sqrt((double)lp));
-    zgemm(ctx, OPT, OPN, lp, r1 * R1, lm * n, Z(1), omega, (long)lm * n, 0, W, (long)lm * n, 0, Z(0),
-          S + sk_off[m + 1], lp, 0);
+    gemm(ctx, OPT, OPN, lp, r1 * R1, lm * n, Z(1), omega, (long)lm * n, 0, W, (long)lm * n, 0, Z(0),
+          S + sk_off[m + 1], lp, 0, 1);
+    // the range found does not depend on the scale of S
+    pow2_normalize(ctx, S + sk_off[m + 1], (long)lp * r1 * R1, pexp, false);
   }
   // ---- right-to-left compression
   std::vector<int> s(d + 1, 1);
@@ -482,23 +495,25 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
   for (int m = d - 1; m >= 0; --m) {
     const int r0 = r[m], r1 = r[m + 1], R0 = R[m], R1 = R[m + 1], sp = s[m + 1];
     // V2[a, i', beta, q] = V(C_m) P_{m+1}
-    zgemm(ctx, OPN, OPN, r0 * n, R1 * sp, r1, Z(1), x->core[m], (long)r0 * n, 0, P, r1, 0, Z(0), V,
-          (long)r0 * n, 0);
+    gemm(ctx, OPN, OPN, r0 * n, R1 * sp, r1, Z(1), x->core[m], (long)r0 * n, 0, P, r1, 0, Z(0), V,
+          (long)r0 * n, 0, 1);
     if (m == 0) {
       gather_right(ctx, op, 0, V, y->core[0], 1, sp);
+      pow2_restore(ctx, y->core[0], (long)n * sp, pexp);
       break;
     }
     gather_right(ctx, op, m, V, W, r0, sp);  // Z in W
     const int lm = ll[m];
     const int N = n * sp;
     // M = S_m Z  (l_m x n s_{m+1})
-    zgemm(ctx, OPN, OPN, lm, N, r0 * R0, Z(1), S + sk_off[m], lm, 0, W, (long)r0 * R0, 0, Z(0), M, lm, 0);
+    gemm(ctx, OPN, OPN, lm, N, r0 * R0, Z(1), S + sk_off[m], lm, 0, W, (long)r0 * R0, 0, Z(0), M, lm, 0, 1);
     // M = R^H Qt^H: the new core is Qt^H (right-orthonormal rows)
     tsqr_lq(ctx, lm, N, M, lm, Qm, Rm);
     conj_transpose(ctx, Qm, N, y->core[m], lm, N, lm);
     s[m] = lm;
     // P_m = Z Q^H = Z Qt  ((r0 R0) x l_m), layout [a, alpha, q]
-    zgemm(ctx, OPN, OPN, r0 * R0, lm, N, Z(1), W, (long)r0 * R0, 0, Qm, N, 0, Z(0), P2, (long)r0 * R0, 0);
+    gemm(ctx, OPN, OPN, r0 * R0, lm, N, Z(1), W, (long)r0 * R0, 0, Qm, N, 0, Z(0), P2, (long)r0 * R0, 0, 1);
+    pow2_normalize(ctx, P2, (long)r0 * R0 * lm, pexp, true);
     std::swap(P, P2);
   }
   for (int m = 0; m <= d; ++m) y->rank[m] = s[m];
@@ -506,7 +521,10 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
   y->orth = TT_ORTH_RIGHT;
 }
 
-void apply_any(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int mode, int l, uint64_t seed) {
+void apply_any(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int mode, int l, uint64_t seed,
+               int precision) {
+  require(precision == TT_PREC_FP64 || precision == TT_PREC_BF16X3 || precision == TT_PREC_FP16X3, TT_EINVAL,
+          "tt_apply: unknown precision");
   check_same_shape(op, x);
   require(x->d == y->d && x->n == y->n, TT_ESHAPE, "tt_apply: x and y shapes differ");
   require(x != y, TT_EINVAL, "tt_apply: y must not alias x");
@@ -514,7 +532,7 @@ void apply_any(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, i
   if (mode == TT_APPLY_EXACT)
     apply_exact(ctx, op, x, y);
   else if (mode == TT_APPLY_SKETCH)
-    apply_sketch(ctx, op, x, y, l, seed);
+    apply_sketch(ctx, op, x, y, l, seed, precision);
   else
     fail(TT_EINVAL, "tt_apply: unknown mode");
 }
@@ -995,7 +1013,7 @@ int tt_apply(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, con
   if (!ctx || !op || !x || !y || !opts) return TT_EINVAL;
   ABI_TRY
   require(opts->size == (int)sizeof(tt_apply_opts), TT_EINVAL, "tt_apply_opts.size mismatch");
-  apply_any(ctx, op, x, y, opts->mode, opts->sketch_rank, opts->seed);
+  apply_any(ctx, op, x, y, opts->mode, opts->sketch_rank, opts->seed, opts->precision);
   return TT_OK;
   ABI_CATCH(ctx)
 }
@@ -1051,6 +1069,9 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
     capf[k] = (k == 0 || k == d) ? 1 : rk + 4 * base;
   }
   const std::string key = shape_key(d, n, f->cap, opts->apply_mode * 100000 + opts->sketch_rank * 100 + rmax);
+  require(opts->precision == TT_PREC_FP64 || opts->precision == TT_PREC_BF16X3 || opts->precision == TT_PREC_FP16X3,
+          TT_EINVAL,
+          "tt_step: unknown precision");
   StepTemps& T = step_cache()[{ctx, key}];
   if (!T.ysum) {
     for (int s = 0; s < 4; ++s) T.k[s] = make_tensor(ctx, d, n, capk);
@@ -1066,7 +1087,8 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
   const tt_tensor* stage_in = f;
   const double cst[3] = {0.5 * dt, 0.5 * dt, dt};
   for (int s = 0; s < 4; ++s) {
-    apply_any(ctx, op, stage_in, T.k[s], mode, l, opts->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(s + 1));
+    apply_any(ctx, op, stage_in, T.k[s], mode, l, opts->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(s + 1),
+              opts->precision);
     round_tensor(ctx, T.k[s], eps, rmax, nullptr);
     track(T.k[s]);
     if (s < 3) {
@@ -1123,6 +1145,25 @@ int tt_zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, double alpha_re
           TT_EINVAL, "tt_zgemm: leading dimension too small");
   zgemm(ctx, opA, opB, M, N, K, Z(alpha_re, alpha_im), (const zc*)A, lda, strideA, (const zc*)B, ldb, strideB,
         Z(beta_re, beta_im), (zc*)C, ldc, strideC, batch);
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_zgemm_mixed(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, int K, double alpha_re,
+                   double alpha_im, const double* A, int64_t lda, int64_t strideA, const double* B, int64_t ldb,
+                   int64_t strideB, double beta_re, double beta_im, double* C, int64_t ldc, int64_t strideC,
+                   int batch) {
+  if (!ctx) return TT_EINVAL;
+  ABI_TRY
+  require(precision == TT_PREC_BF16X3 || precision == TT_PREC_FP16X3, TT_EINVAL,
+          "tt_zgemm_mixed: precision must be TT_PREC_BF16X3 or TT_PREC_FP16X3");
+  require(opA >= 0 && opA <= 2 && opB >= 0 && opB <= 2, TT_EINVAL, "tt_zgemm_mixed: op must be 0, 1 or 2");
+  require(M >= 0 && N >= 0 && K >= 0 && batch >= 1, TT_EINVAL, "tt_zgemm_mixed: negative size");
+  require(C && ((A && B) || K == 0), TT_EINVAL, "tt_zgemm_mixed: null pointer");
+  require(lda >= std::max(1, opA == OPN ? M : K) && ldb >= std::max(1, opB == OPN ? K : N) && ldc >= std::max(1, M),
+          TT_EINVAL, "tt_zgemm_mixed: leading dimension too small");
+  zgemm_prec(precision, ctx, opA, opB, M, N, K, Z(alpha_re, alpha_im), (const zc*)A, lda, strideA, (const zc*)B, ldb,
+             strideB, Z(beta_re, beta_im), (zc*)C, ldc, strideC, batch);
   return TT_OK;
   ABI_CATCH(ctx)
 }

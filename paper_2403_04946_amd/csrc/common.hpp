@@ -146,6 +146,12 @@ enum { OPN = 0, OPT = 1, OPC = 2 };
 void zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const zc* A,
            long lda, long strideA, const zc* B, long ldb, long strideB, zc beta, zc* C,
            long ldc, long strideC, int batch = 1);
+// The same product in the arithmetic `fmt` (TT_PREC_*): FP64, or a split
+// 16-bit form on the matrix cores (FP32 accumulation, FP64 operands and
+// result; see k_gemm.hip).
+void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const zc* A,
+                long lda, long strideA, const zc* B, long ldb, long strideB, zc beta, zc* C,
+                long ldc, long strideC, int batch);
 
 // LDS Householder leaves for panels of at most 32 columns: P balanced row
 // blocks of 32..256 rows, see k_qr.hip
@@ -196,5 +202,9 @@ void gather_left(tt_ctx* ctx, const tt_op* op, int site, const zc* V, zc* W, int
 void gather_right(tt_ctx* ctx, const tt_op* op, int site, const zc* V2, zc* Z, int r0, int s);
 // Gaussian sketch core (counter-based Philox4x32-10 + Box-Muller)
 void sketch_core(tt_ctx* ctx, zc* w, long count, uint64_t seed, int site, double scale);
+// x <- 2^-e x with e the largest exponent in x (e[0]); with accumulate,
+// e[1] += e.  pow2_restore: x <- 2^e[1] x.  e: two device ints.
+void pow2_normalize(tt_ctx* ctx, zc* x, long n, int* e, bool accumulate);
+void pow2_restore(tt_ctx* ctx, zc* x, long n, const int* e);
 
 }  // namespace ttf

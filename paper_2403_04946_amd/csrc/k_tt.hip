@@ -338,4 +338,56 @@ void sketch_core(tt_ctx* ctx, zc* w, long count, uint64_t seed, int site, double
   TTF_HIP(hipGetLastError());
 }
 
+// ------------------------------------------- power-of-two normalisation
+// The sketch chains of the sketched apply multiply by operator and core
+// factors site after site; their magnitude drifts geometrically along the
+// train.  Rescaling by a power of two (exact in floating point) keeps them
+// near 1, which the FP32 accumulation of the mixed-precision contractions
+// needs; e[0] receives the exponent and, with accumulate, e[1] sums them.
+__global__ void pow2_init_kernel(int* e) { e[0] = -1100; }
+
+__global__ void pow2_maxexp_kernel(const zc* __restrict__ x, long n, int* __restrict__ e) {
+  int mx = -1100;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double a = fmax(fabs(x[i].x), fabs(x[i].y));
+    if (a > 0.0 && a <= 1.7976931348623157e308) mx = max(mx, ilogb(a));
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(e, mx);
+}
+
+__global__ void pow2_scale_kernel(zc* __restrict__ x, long n, int* __restrict__ e, int accumulate) {
+  const int ex = e[0];
+  if (ex <= -1100) return;  // all zero
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const zc v = x[i];
+    x[i] = make_double2(ldexp(v.x, -ex), ldexp(v.y, -ex));
+  }
+  if (accumulate && blockIdx.x == 0 && threadIdx.x == 0) e[1] += ex;
+}
+
+__global__ void pow2_apply_kernel(zc* __restrict__ x, long n, const int* __restrict__ e) {
+  const int ex = e[1];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const zc v = x[i];
+    x[i] = make_double2(ldexp(v.x, ex), ldexp(v.y, ex));
+  }
+}
+
+void pow2_normalize(tt_ctx* ctx, zc* x, long n, int* e, bool accumulate) {
+  if (n <= 0) return;
+  const int blocks = (int)std::min<long>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(pow2_init_kernel, dim3(1), dim3(1), 0, ctx->stream, e);
+  hipLaunchKernelGGL(pow2_maxexp_kernel, dim3(blocks), dim3(256), 0, ctx->stream, x, n, e);
+  hipLaunchKernelGGL(pow2_scale_kernel, dim3(blocks), dim3(256), 0, ctx->stream, x, n, e, accumulate ? 1 : 0);
+  TTF_HIP(hipGetLastError());
+}
+
+void pow2_restore(tt_ctx* ctx, zc* x, long n, const int* e) {
+  if (n <= 0) return;
+  const int blocks = (int)std::min<long>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(pow2_apply_kernel, dim3(blocks), dim3(256), 0, ctx->stream, x, n, e);
+  TTF_HIP(hipGetLastError());
+}
+
 }  // namespace ttf

@@ -17,6 +17,9 @@ MAX_D = 128
 
 TT_APPLY_EXACT = 0
 TT_APPLY_SKETCH = 1
+TT_PREC_FP64 = 0
+TT_PREC_BF16X3 = 1
+TT_PREC_FP16X3 = 2
 TT_ECAPACITY = -3
 ORTH = {0: "none", 1: "right", 2: "left"}
 ERRORS = {
@@ -53,7 +56,7 @@ class ApplyOpts(ctypes.Structure):
         ("size", ctypes.c_int),
         ("mode", ctypes.c_int),
         ("sketch_rank", ctypes.c_int),
-        ("pad", ctypes.c_int),
+        ("precision", ctypes.c_int),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -66,6 +69,8 @@ class StepOpts(ctypes.Structure):
         ("apply_mode", ctypes.c_int),
         ("sketch_rank", ctypes.c_int),
         ("seed", ctypes.c_uint64),
+        ("precision", ctypes.c_int),
+        ("pad", ctypes.c_int),
     ]
 
 
@@ -117,6 +122,8 @@ _SIGS = {
     "tt_eval": (I, [P, P, P, ctypes.c_int64, P]),
     "tt_norm": (I, [P, P, PD]),
     "tt_qr": (I, [P, I, I, P, ctypes.c_int64, P, P]),
+    "tt_zgemm_mixed": (I, [P, I, I, I, I, I, I, D, D, P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64,
+                           ctypes.c_int64, D, D, P, ctypes.c_int64, ctypes.c_int64, I]),
     "tt_svd_small": (I, [P, I, I, P, P, P, PI]),
     "tt_zgemm": (I, [P, I, I, I, I, I, D, D, P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64,
                      ctypes.c_int64, D, D, P, ctypes.c_int64, ctypes.c_int64, I]),
@@ -314,8 +321,8 @@ class Operator:
             self.h = None
 
 
-def tt_apply(ctx, op, x, y, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0):
-    o = ApplyOpts(ctypes.sizeof(ApplyOpts), mode, sketch_rank, 0, seed)
+def tt_apply(ctx, op, x, y, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0):
+    o = ApplyOpts(ctypes.sizeof(ApplyOpts), mode, sketch_rank, int(precision), seed)
     ctx.check(lib().tt_apply(ctx.h, op.h, x.h, y.h, ctypes.byref(o)))
 
 
@@ -347,8 +354,9 @@ def tt_round(ctx, x, eps, rmax=0, report=True):
     }
 
 
-def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0):
-    o = StepOpts(ctypes.sizeof(StepOpts), int(rmax), float(eps), int(mode), int(sketch_rank), int(seed))
+def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0):
+    o = StepOpts(ctypes.sizeof(StepOpts), int(rmax), float(eps), int(mode), int(sketch_rank), int(seed),
+                 int(precision), 0)
     rep = StepReport()
     ctx.check(lib().tt_step(ctx.h, op.h, f.h, float(dt), ctypes.byref(o), ctypes.byref(rep)))
     return {"stages": rep.stages, "max_rank": rep.max_rank, "ranks": list(rep.ranks[: f.d + 1])}
@@ -368,17 +376,23 @@ def tt_eval(ctx, x, idx, out):
         cur.wait_stream(ctx.torch_stream)
 
 
-def tt_zgemm(ctx, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch=1):
+def tt_zgemm(ctx, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch=1,
+             precision=TT_PREC_FP64):
     """Device GEMM on torch complex128 buffers A, B, C (column-major views),
-    ordered against torch's current stream like tt_eval."""
+    ordered against torch's current stream like tt_eval; precision selects
+    plain FP64 (tt_zgemm) or a split 16-bit matrix-core form (tt_zgemm_mixed)."""
     import torch
 
     cur = torch.cuda.current_stream()
     if ctx.torch_stream is not None:
         ctx.torch_stream.wait_stream(cur)
     a, b = complex(alpha), complex(beta)
-    ctx.check(lib().tt_zgemm(ctx.h, opA, opB, M, N, K, a.real, a.imag, P(A.data_ptr()), lda, sA,
-                             P(B.data_ptr()), ldb, sB, b.real, b.imag, P(C.data_ptr()), ldc, sC, batch))
+    args = (opA, opB, M, N, K, a.real, a.imag, P(A.data_ptr()), lda, sA, P(B.data_ptr()), ldb, sB, b.real, b.imag,
+            P(C.data_ptr()), ldc, sC, batch)
+    if precision == TT_PREC_FP64:
+        ctx.check(lib().tt_zgemm(ctx.h, *args))
+    else:
+        ctx.check(lib().tt_zgemm_mixed(ctx.h, int(precision), *args))
     if ctx.torch_stream is not None:
         cur.wait_stream(ctx.torch_stream)
 

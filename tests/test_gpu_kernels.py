@@ -54,6 +54,73 @@ def test_zgemm_against_numpy(ctx, M, N, K, batch, opa, opb):
         assert np.abs(g - ref[b]).max() <= 1e-13 * max(1.0, np.sqrt(K)) * (np.abs(ref[b]).max() + 1)
 
 
+@pytest.mark.parametrize(
+    "M,N,K,batch",
+    [(1, 1, 1, 1), (17, 33, 5, 1), (64, 64, 16, 1), (65, 130, 47, 3), (20, 30, 5000, 1), (130, 7, 900, 2),
+     (8, 200, 0, 1), (4100, 20, 37, 1), (300, 32, 3000, 1), (33, 96, 700, 2)],
+)
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (2, 0), (0, 1), (0, 2), (2, 2)])
+@pytest.mark.parametrize("prec", [tt.TT_PREC_BF16X3, tt.TT_PREC_FP16X3])
+def test_zgemm_split_error_bound(ctx, M, N, K, batch, opa, opb, prec):
+    """Split 16-bit products.  BF16x3: each real operand is represented to
+    2^-17 relative by hi + lo, so every entry is within a small multiple of
+    2^-16 |alpha| (|op(A)| |op(B)|) of the exact product.  FP16x3: hi + lo
+    keeps 2^-22 relative, FP32 accumulation over a 32-wide K stage adds at
+    most 12 roundings of 2^-24, so 2^-18 (|op(A)| |op(B)|) bounds every
+    entry, plus an absolute term for components far below their stage's
+    largest (those fall into half's subnormal range).  beta C is FP64."""
+    import torch
+
+    rng = np.random.default_rng(M * 1000 + N * 10 + K + opa * 7 + opb + 5)
+    As, Bs, Cs = [], [], []
+    for _ in range(batch):
+        As.append(_mat(rng, M, K) if opa == 0 else _mat(rng, K, M))
+        Bs.append(_mat(rng, K, N) if opb == 0 else _mat(rng, N, K))
+        Cs.append(_mat(rng, M, N))
+    alpha, beta = 0.7 - 0.3j, -0.4 + 0.2j
+    ref = [alpha * _op(a, opa) @ _op(b, opb) + beta * c for a, b, c in zip(As, Bs, Cs)]
+    dev = lambda arrs: torch.from_numpy(np.concatenate([a.ravel(order="F") for a in arrs])).cuda()
+    A, B, C = dev(As), dev(Bs), dev(Cs)
+    lda, ldb = As[0].shape[0], Bs[0].shape[0]
+    tt.tt_zgemm(ctx, opa, opb, M, N, K, alpha, A, max(lda, 1), As[0].size, B, max(ldb, 1), Bs[0].size, beta, C, M,
+                M * N, batch, precision=prec)
+    got = C.cpu().numpy()
+    coef, typical = (4 * 2.0 ** -16, 2e-5) if prec == tt.TT_PREC_BF16X3 else (2.0 ** -18, 1e-6)
+    for b in range(batch):
+        g = got[b * M * N:(b + 1) * M * N].reshape((M, N), order="F")
+        absprod = np.abs(_op(As[b], opa)) @ np.abs(_op(Bs[b], opb))
+        bound = coef * abs(alpha) * absprod + 1e-13 * (np.abs(ref[b]) + 1)
+        if K and prec == tt.TT_PREC_FP16X3:
+            bound += 2.0 ** -30 * abs(alpha) * K * np.abs(As[b]).max() * np.abs(Bs[b]).max()
+        assert np.all(np.abs(g - ref[b]) <= bound)
+        if K > 100:  # typical error far below the bound (independent rounding errors)
+            rel = np.linalg.norm(g - ref[b]) / np.linalg.norm(ref[b] - beta * Cs[b])
+            assert rel < typical, rel
+
+
+@pytest.mark.parametrize("scale_a,scale_b", [(1e30, 1e-25), (1e-200, 1e180), (3e-5, 7e4)])
+def test_zgemm_fp16x3_scaling_range(ctx, scale_a, scale_b):
+    """Half precision spans only about 2^-24..2^16: the per-stage power-of-two
+    scaling must keep the FP16x3 product accurate for operands far outside
+    that range, with magnitudes graded along K (stage scales differ)."""
+    import torch
+
+    rng = np.random.default_rng(17)
+    M, N, K = 96, 80, 640
+    grade = np.logspace(0, -8, K)  # stage maxima fall by 8 decades along K
+    a = _mat(rng, M, K) * grade[None, :] * scale_a
+    b = _mat(rng, K, N) * scale_b
+    ref = a @ b
+    A = torch.from_numpy(a.ravel(order="F")).cuda()
+    B = torch.from_numpy(b.ravel(order="F")).cuda()
+    C = torch.zeros(M * N, dtype=torch.complex128, device="cuda")
+    tt.tt_zgemm(ctx, 0, 0, M, N, K, 1.0, A, M, 0, B, K, 0, 0.0, C, M, 0, 1, precision=tt.TT_PREC_FP16X3)
+    g = C.cpu().numpy().reshape((M, N), order="F")
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    assert rel < 1e-6, rel
+    assert np.all(np.abs(g - ref) <= 2.0 ** -18 * (np.abs(a) @ np.abs(b)) + 1e-300)
+
+
 def test_set_get_roundtrip_and_eval(ctx):
     import torch
 

@@ -1,0 +1,174 @@
+"""GPU checks of the mixed-precision form: the operator application's
+sketch contractions in a split 16-bit form on the matrix cores (FP32
+accumulation), QR, SVD, truncation test and sums in FP64.
+
+The gate is relative L2 <= 1e-5 against the plain FP64 form, per RK4 stage
+from identical inputs: a stage is one operator application, its rounding
+and the stage combination y = f + c dt k (rounded), so every stage below
+starts from the FP64 path's own stage input.  Split-FP16x3 meets it;
+split-BF16x3 (about 17 significant bits) does not, and its larger error is
+pinned separately."""
+import numpy as np
+import pytest
+
+from gpu_util import full, make_ctx, rel, upload
+from oracle import fullgrid, galerkin
+from paper_2403_04946_amd import inputs, tt
+
+pytestmark = pytest.mark.gpu
+
+GATE = 1e-5
+D, N, LENGTH, NU, CAP, ELL, EPS, DT = 50, 128, 8.0, 0.01, 64, 80, 1e-6, 2e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = make_ctx()
+    yield c
+    c.sync()
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def op(ctx):
+    o = tt.Operator(ctx, D, N, LENGTH, NU)
+    yield o
+    o.close()
+
+
+def _rel_tt(ctx, a, b):
+    """||a - b|| / ||b|| for device TTs, via the difference TT."""
+    caps = np.array(a.ranks()) + np.array(b.ranks())
+    caps[0] = caps[-1] = 1
+    diff = tt.Tensor(ctx, a.d, a.n, caps)
+    tt.tt_axpy(ctx, 1.0, a, -1.0, b, diff)
+    num = tt.tt_norm(ctx, diff)
+    den = tt.tt_norm(ctx, b)
+    diff.close()
+    return num / den
+
+
+def _apply_round(ctx, op, x, prec, seed):
+    y = tt.Tensor(ctx, D, N, max(ELL, CAP))
+    tt.tt_apply(ctx, op, x, y, tt.TT_APPLY_SKETCH, ELL, seed, precision=prec)
+    tt.tt_round(ctx, y, EPS, CAP, report=False)
+    return y
+
+
+def _combine(ctx, coefs, xs, caps):
+    z = tt.Tensor(ctx, D, N, caps)
+    tt.tt_sum(ctx, coefs, xs, z)
+    tt.tt_round(ctx, z, EPS, CAP, report=False)
+    return z
+
+
+@pytest.mark.parametrize("prec,bound", [(tt.TT_PREC_FP16X3, GATE), (tt.TT_PREC_BF16X3, 1e-3)])
+def test_mixed_sketched_apply_saturated(ctx, op, prec, bound):
+    """The timed regime: a seeded random TT with every interior rank 64.
+    FP16x3 is within the gate of FP64; BF16x3 within 1e-3."""
+    x = upload(ctx, inputs.random_tt(D, N, CAP, 0), caps=CAP)
+    y64 = tt.Tensor(ctx, D, N, ELL)
+    ymx = tt.Tensor(ctx, D, N, ELL)
+    tt.tt_apply(ctx, op, x, y64, tt.TT_APPLY_SKETCH, ELL, 99, precision=tt.TT_PREC_FP64)
+    tt.tt_apply(ctx, op, x, ymx, tt.TT_APPLY_SKETCH, ELL, 99, precision=prec)
+    err = _rel_tt(ctx, ymx, y64)
+    print(f"precision {prec} vs FP64 sketched apply, d=50 rank 64: rel L2 {err:.2e}")
+    assert 0.0 < err < bound, err  # > 0: the split path really ran
+    for t in (x, y64, ymx):
+        t.close()
+
+
+def test_mixed_stages_from_identical_inputs(ctx, op):
+    """Two RK4 steps from the seeded Gaussian initial condition: every stage
+    of the FP16x3 form, started from the FP64 path's stage input, gives a
+    stage output within the gate of the FP64 one; the stage derivatives k
+    themselves stay within 2e-4 (at sketch width 80 the sketch's own error
+    against the exact product is about 4e-4 here)."""
+    mu, sig = inputs.ic_params(D, 0)
+    f = tt.Tensor(ctx, D, N, CAP)
+    f.set_gaussian(mu, sig, LENGTH)
+    cst = [0.5 * DT, 0.5 * DT, DT]
+    worst = 0.0
+    for step in range(2):
+        y = f
+        k64, kmx = [], []
+        for s in range(4):
+            seed = 1000 * step + s
+            k64.append(_apply_round(ctx, op, y, tt.TT_PREC_FP64, seed))
+            kmx.append(_apply_round(ctx, op, y, tt.TT_PREC_FP16X3, seed))
+            kerr = _rel_tt(ctx, kmx[-1], k64[-1])
+            assert kerr < 2e-4, (step, s, kerr)
+            if s < 3:
+                y64 = _combine(ctx, [1.0, cst[s]], [f, k64[-1]], 2 * CAP)
+                ymx = _combine(ctx, [1.0, cst[s]], [f, kmx[-1]], 2 * CAP)
+            else:
+                w = [1.0, DT / 6, DT / 3, DT / 3, DT / 6]
+                y64 = _combine(ctx, w, [f] + k64, 5 * CAP)
+                ymx = _combine(ctx, w, [f] + kmx, 5 * CAP)
+            err = _rel_tt(ctx, ymx, y64)
+            print(f"step {step} stage {s}: k {kerr:.2e}  stage output {err:.2e}")
+            worst = max(worst, err)
+            assert err < GATE, (step, s, err)
+            ymx.close()
+            if y is not f:
+                y.close()
+            y = y64
+        for t in k64 + kmx:
+            t.close()
+        f.copy_from(y)
+        y.close()
+    assert worst > 0.0
+    f.close()
+
+
+def test_mixed_step_from_identical_input(ctx, op):
+    """Whole RK4 steps through tt_step from the same Gaussian initial state."""
+    mu, sig = inputs.ic_params(D, 1)
+    f64 = tt.Tensor(ctx, D, N, CAP)
+    f64.set_gaussian(mu, sig, LENGTH)
+    fmx = tt.Tensor(ctx, D, N, CAP)
+    fmx.copy_from(f64)
+    tt.tt_step(ctx, op, f64, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ELL, 12345, precision=tt.TT_PREC_FP64)
+    tt.tt_step(ctx, op, fmx, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ELL, 12345, precision=tt.TT_PREC_FP16X3)
+    err = _rel_tt(ctx, fmx, f64)
+    print(f"FP16x3 vs FP64 RK4 step from the initial condition, d=50: rel L2 {err:.2e}")
+    assert err < GATE, err
+    for t in (f64, fmx):
+        t.close()
+
+
+def test_mixed_config1_trajectory_against_oracle(ctx):
+    """d=4, n=32, cap 8 for 20 steps with the sketched apply in the FP16x3
+    form: within the gate of the truncation-aware FP64 oracle."""
+    d, n, length, nu, dt, steps, eps, cap = 4, 32, 4.0, 0.05, 1e-3, 20, 1e-12, 8
+    op = tt.Operator(ctx, d, n, length, nu)
+    f = tt.Tensor(ctx, d, n, cap)
+    mu, sig = inputs.ic_params(d, 0)
+    f.set_gaussian(mu, sig, length)
+    for s in range(steps):
+        tt.tt_step(ctx, op, f, dt, cap, eps, tt.TT_APPLY_SKETCH, 96, 777 + s, precision=tt.TT_PREC_FP16X3)
+    got = full(f)
+    prob = fullgrid.Problem(galerkin.coefficient_B(d), galerkin.coefficient_D(d), nu, n, length)
+    ref = fullgrid.gaussian_ic(mu, sig, n, length)
+    for _ in range(steps):
+        ref = fullgrid.truncated_rk4_step(ref, dt, prob.apply, eps, cap)
+    err = rel(got, ref)
+    print(f"FP16x3 d=4, {steps} steps: rel L2 vs oracle {err:.2e}")
+    assert err < GATE, err
+    f.close()
+    op.close()
+
+
+def test_mixed_precision_is_rejected_when_unknown(ctx):
+    d, n = 3, 8
+    op = tt.Operator(ctx, d, n, 4.0, 0.05)
+    x = upload(ctx, inputs.random_tt(d, n, 2, 0), caps=4)
+    y = tt.Tensor(ctx, d, n, 16)
+    with pytest.raises(tt.TTError):
+        tt.tt_apply(ctx, op, x, y, tt.TT_APPLY_SKETCH, 8, 1, precision=7)
+    f = upload(ctx, inputs.random_tt(d, n, 2, 0), caps=4)
+    with pytest.raises(tt.TTError):
+        tt.tt_step(ctx, op, f, 1e-3, 4, 1e-8, tt.TT_APPLY_SKETCH, 8, 1, precision=3)
+    for t in (x, y, f):
+        t.close()
+    op.close()
