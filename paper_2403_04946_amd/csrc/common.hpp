@@ -148,10 +148,17 @@ void zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const z
            long ldc, long strideC, int batch = 1);
 // The same product in the arithmetic `fmt` (TT_PREC_*): FP64, or a split
 // 16-bit form on the matrix cores (FP32 accumulation, FP64 operands and
-// result; see k_gemm.hip).
+// result; zgemm_split, k_mixed.hip).
 void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const zc* A,
                 long lda, long strideA, const zc* B, long ldb, long strideB, zc beta, zc* C,
                 long ldc, long strideC, int batch);
+void zgemm_split(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const zc* A, long lda,
+                 long strideA, const zc* B, long ldb, long strideB, zc beta, zc* C, long ldc, long strideC,
+                 int batch);
+// C = alpha sum_s ws[s] + beta C over nsplit split-K partials
+// ws[s][batch][N][M] (fixed summation order)
+void splitk_finish(tt_ctx* ctx, int M, int N, int batch, int nsplit, zc* ws, zc alpha, zc beta, zc* C, long ldc,
+                   long strideC);
 
 // LDS Householder leaves for panels of at most 32 columns: P balanced row
 // blocks of 32..256 rows, see k_qr.hip

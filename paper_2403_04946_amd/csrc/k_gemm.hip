@@ -241,310 +241,26 @@ __global__ void splitk_reduce(GemmParams p, int nsplit) {
   }
 }
 
-// ------------------------------------------- split low-precision variants
-// Same contract as zgemm_kernel (FP64 complex operands and result), but the
-// products run on the 16-bit matrix cores: every real operand x is split as
-// x = hi + lo with hi = round(x), lo = round(x - hi) in the 16-bit format,
-// and each real product is hi*hi + hi*lo + lo*hi with FP32 accumulation,
-// i.e. three 16-bit products per real product and twelve per complex one.
-//  - FMT = TT_PREC_BF16X3: bfloat16 halves (8-bit significands, so the
-//    split keeps about 17 bits); no scaling needed, FP32 accumulators added
-//    into FP64 ones every MX_FLUSH K.
-//  - FMT = TT_PREC_FP16X3: IEEE half halves (11-bit significands, about 22
-//    bits kept).  Half has a narrow exponent range, so every K stage of the
-//    A tile and of the B tile is scaled by a power of two that brings its
-//    largest component to [2^14, 2^15) (exact); the FP32 accumulators are
-//    added into FP64 ones, with the inverse scale, at the end of every stage.
-// The 16x16x16 matrix-core layout (bf16_1k and f16 alike): A lane l holds
-// A[l%16][4(l/16)+j], B lane l holds B[4(l/16)+j][l%16], result register v
-// of lane l holds D[4(l/16)+v][l%16].
-typedef short sh4 __attribute__((ext_vector_type(4)));
-typedef _Float16 hf4 __attribute__((ext_vector_type(4)));
-typedef float fl4 __attribute__((ext_vector_type(4)));
-
-constexpr int MX_BK = 32, MX_FLUSH = 128, MX_PAD = 4;
-constexpr int MX_F16_EXP = 14;  // target exponent of a scaled half stage
-constexpr int MX_ZERO_EXP = -1100;
-
-__device__ inline unsigned short bf16_rne(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ inline float bf16_to_float(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
-
-template <int FMT>
-__device__ inline void split16(double x, unsigned short& hi, unsigned short& lo) {
-  if constexpr (FMT == TT_PREC_BF16X3) {
-    hi = bf16_rne((float)x);
-    lo = bf16_rne((float)(x - (double)bf16_to_float(hi)));
-  } else {
-    const _Float16 h = (_Float16)(float)x;
-    const _Float16 l = (_Float16)(float)(x - (double)(float)h);
-    hi = __builtin_bit_cast(unsigned short, h);
-    lo = __builtin_bit_cast(unsigned short, l);
-  }
-}
-
-template <int FMT>
-__device__ inline fl4 mfma16(sh4 a, sh4 b, fl4 c) {
-  if constexpr (FMT == TT_PREC_BF16X3)
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-  else
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(hf4, a), __builtin_bit_cast(hf4, b), c, 0, 0, 0);
-}
-
-template <int FMT, int OPA, int OPB, int BM, int BN>
-__global__ __launch_bounds__(256) void zgemm_split_kernel(GemmParams p) {
-  constexpr bool SCALED = FMT == TT_PREC_FP16X3;
-  constexpr int TI = BM / 32, TJ = BN / 32;
-  constexpr int RA = BM * MX_BK / 256, RB = BN * MX_BK / 256;
-  constexpr int LK = MX_BK + MX_PAD;  // row stride of the k-contiguous planes
-  // planes: 0 Re hi, 1 Re lo, 2 -Im hi, 3 -Im lo, 4 Im hi, 5 Im lo (A);
-  //         0 Re hi, 1 Re lo, 2 Im hi, 3 Im lo (B)
-  __shared__ unsigned short As[6][BM][LK];
-  __shared__ unsigned short Bs[4][BN][LK];
-  __shared__ int ex_s[4][2];  // per-wave largest exponents of the next stage
-
-  const int nsplit = gridDim.z / p.batch;
-  const int bz = blockIdx.z % p.batch;
-  const int split = blockIdx.z / p.batch;
-  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
-  const int kbeg = split * p.kchunk;
-  const int kend = min(p.K, kbeg + p.kchunk);
-  const zc* A = p.A + p.sA * (long)bz;
-  const zc* B = p.B + p.sB * (long)bz;
-
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
-  const int lr = lane & 15, lq = lane >> 4;
-
-  double dR[TI][TJ][4], dI[TI][TJ][4];
-  fl4 fR[TI][TJ], fI[TI][TJ];
-#pragma unroll
-  for (int i = 0; i < TI; ++i)
-#pragma unroll
-    for (int j = 0; j < TJ; ++j) {
-      fR[i][j] = fl4{0, 0, 0, 0};
-      fI[i][j] = fl4{0, 0, 0, 0};
-#pragma unroll
-      for (int v = 0; v < 4; ++v) dR[i][j][v] = dI[i][j][v] = 0.0;
-    }
-
-  auto a_idx = [&](int r, int& mm, int& kk) {
-    if (OPA == OPN) {
-      mm = t % BM;
-      kk = t / BM + (256 / BM) * r;
-    } else {
-      kk = t % MX_BK;
-      mm = t / MX_BK + (256 / MX_BK) * r;
-    }
-  };
-  auto b_idx = [&](int r, int& kk, int& nn) {
-    if (OPB == OPN) {
-      kk = t % MX_BK;
-      nn = t / MX_BK + (256 / MX_BK) * r;
-    } else {
-      nn = t % BN;
-      kk = t / BN + (256 / BN) * r;
-    }
-  };
-  zc ra[RA], rb[RB];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      int mm, kk;
-      a_idx(r, mm, kk);
-      ra[r] = load_op<OPA>(A, p.lda, m0 + mm, k0 + kk, p.M, kend);
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      int kk, nn;
-      b_idx(r, kk, nn);
-      rb[r] = load_op<OPB>(B, p.ldb, k0 + kk, n0 + nn, kend, p.N);
-    }
-  };
-  // largest binary exponents of the loaded A and B stage tiles: per-wave
-  // maxima into ex_s; read_exps combines them after a barrier
-  auto stage_exps = [&]() {
-    double ma = 0.0, mb = 0.0;
-#pragma unroll
-    for (int r = 0; r < RA; ++r) ma = fmax(ma, fmax(fabs(ra[r].x), fabs(ra[r].y)));
-#pragma unroll
-    for (int r = 0; r < RB; ++r) mb = fmax(mb, fmax(fabs(rb[r].x), fabs(rb[r].y)));
-    int ia = ma > 0.0 ? min(ilogb(ma), 1000) : MX_ZERO_EXP;
-    int ib = mb > 0.0 ? min(ilogb(mb), 1000) : MX_ZERO_EXP;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      ia = max(ia, __shfl_xor(ia, off, 64));
-      ib = max(ib, __shfl_xor(ib, off, 64));
-    }
-    if (lane == 0) {
-      ex_s[wave][0] = ia;
-      ex_s[wave][1] = ib;
-    }
-  };
-  int ea = 0, eb = 0;  // exponents of the stage held in LDS (scaled form)
-  auto read_exps = [&]() {
-    ea = max(max(ex_s[0][0], ex_s[1][0]), max(ex_s[2][0], ex_s[3][0]));
-    eb = max(max(ex_s[0][1], ex_s[1][1]), max(ex_s[2][1], ex_s[3][1]));
-    if (ea == MX_ZERO_EXP) ea = 0;  // an all-zero tile: any scale is exact
-    if (eb == MX_ZERO_EXP) eb = 0;
-  };
-  auto sstore = [&]() {
-    const int sa = SCALED ? MX_F16_EXP - ea : 0, sb = SCALED ? MX_F16_EXP - eb : 0;
-#pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      int mm, kk;
-      a_idx(r, mm, kk);
-      unsigned short h, l;
-      split16<FMT>(SCALED ? ldexp(ra[r].x, sa) : ra[r].x, h, l);
-      As[0][mm][kk] = h;
-      As[1][mm][kk] = l;
-      split16<FMT>(SCALED ? ldexp(-ra[r].y, sa) : -ra[r].y, h, l);
-      As[2][mm][kk] = h;
-      As[3][mm][kk] = l;
-      As[4][mm][kk] = h ^ 0x8000u;  // +Im: flip the sign bits
-      As[5][mm][kk] = l ^ 0x8000u;
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      int kk, nn;
-      b_idx(r, kk, nn);
-      unsigned short h, l;
-      split16<FMT>(SCALED ? ldexp(rb[r].x, sb) : rb[r].x, h, l);
-      Bs[0][nn][kk] = h;
-      Bs[1][nn][kk] = l;
-      split16<FMT>(SCALED ? ldexp(rb[r].y, sb) : rb[r].y, h, l);
-      Bs[2][nn][kk] = h;
-      Bs[3][nn][kk] = l;
-    }
-  };
-  // FP32 accumulators -> FP64 ones, undoing the stage scale 2^(2*14 - e)
-  auto flush = [&](int e) {
-    const int un = SCALED ? e - 2 * MX_F16_EXP : 0;
-#pragma unroll
-    for (int i = 0; i < TI; ++i)
-#pragma unroll
-      for (int j = 0; j < TJ; ++j) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          dR[i][j][v] += SCALED ? ldexp((double)fR[i][j][v], un) : (double)fR[i][j][v];
-          dI[i][j][v] += SCALED ? ldexp((double)fI[i][j][v], un) : (double)fI[i][j][v];
-        }
-        fR[i][j] = fl4{0, 0, 0, 0};
-        fI[i][j] = fl4{0, 0, 0, 0};
-      }
-  };
-
-  if (kbeg < kend) {
-    gload(kbeg);
-    if (SCALED) stage_exps();
-  }
-  if (SCALED) {
-    __syncthreads();
-    read_exps();
-  }
-  if (kbeg < kend) sstore();
-  __syncthreads();
-  int ecur = ea + eb, since = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += MX_BK) {
-    const bool more = k0 + MX_BK < kend;
-    if (more) gload(k0 + MX_BK);
-#pragma unroll
-    for (int ks = 0; ks < MX_BK; ks += 16) {
-      sh4 a[TI][6], b[TJ][4];
-#pragma unroll
-      for (int i = 0; i < TI; ++i)
-#pragma unroll
-        for (int pl = 0; pl < 6; ++pl)
-          a[i][pl] = *reinterpret_cast<const sh4*>(&As[pl][wm + 16 * i + lr][ks + 4 * lq]);
-#pragma unroll
-      for (int j = 0; j < TJ; ++j)
-#pragma unroll
-        for (int pl = 0; pl < 4; ++pl)
-          b[j][pl] = *reinterpret_cast<const sh4*>(&Bs[pl][wn + 16 * j + lr][ks + 4 * lq]);
-#pragma unroll
-      for (int i = 0; i < TI; ++i)
-#pragma unroll
-        for (int j = 0; j < TJ; ++j) {
-          fl4 r = fR[i][j], m = fI[i][j];
-          // Re += Re(A) Re(B) + (-Im A) Im(B);  Im += Re(A) Im(B) + Im(A) Re(B)
-          r = mfma16<FMT>(a[i][0], b[j][0], r);
-          r = mfma16<FMT>(a[i][0], b[j][1], r);
-          r = mfma16<FMT>(a[i][1], b[j][0], r);
-          r = mfma16<FMT>(a[i][2], b[j][2], r);
-          r = mfma16<FMT>(a[i][2], b[j][3], r);
-          r = mfma16<FMT>(a[i][3], b[j][2], r);
-          m = mfma16<FMT>(a[i][0], b[j][2], m);
-          m = mfma16<FMT>(a[i][0], b[j][3], m);
-          m = mfma16<FMT>(a[i][1], b[j][2], m);
-          m = mfma16<FMT>(a[i][4], b[j][0], m);
-          m = mfma16<FMT>(a[i][4], b[j][1], m);
-          m = mfma16<FMT>(a[i][5], b[j][0], m);
-          fR[i][j] = r;
-          fI[i][j] = m;
-        }
-    }
-    since += MX_BK;
-    if (SCALED) {
-      // every stage has its own scale: fold it into FP64 now
-      flush(ecur);
-      if (more) stage_exps();
-    } else if (since >= MX_FLUSH) {
-      flush(0);
-      since = 0;
-    }
-    __syncthreads();
-    if (more) {
-      if (SCALED) {
-        read_exps();
-        ecur = ea + eb;
-      }
-      sstore();
-      __syncthreads();
-    }
-  }
-  if (!SCALED) flush(0);
-
-#pragma unroll
-  for (int i = 0; i < TI; ++i)
-#pragma unroll
-    for (int j = 0; j < TJ; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm + 16 * i + 4 * lq + v;
-        const int n = n0 + wn + 16 * j + lr;
-        if (m >= p.M || n >= p.N) continue;
-        const double re = dR[i][j][v], im = dI[i][j][v];
-        if (nsplit > 1) {
-          zc* w = p.ws + ((long)split * p.batch + bz) * (long)p.M * p.N;
-          w[m + (long)p.M * n] = make_double2(re, im);
-        } else {
-          zc* C = p.C + p.sC * (long)bz;
-          zc out = make_double2(p.alpha.x * re - p.alpha.y * im, p.alpha.x * im + p.alpha.y * re);
-          const long off = m + p.ldc * (long)n;
-          if (p.beta.x != 0.0 || p.beta.y != 0.0) {
-            const zc c = C[off];
-            out.x += p.beta.x * c.x - p.beta.y * c.y;
-            out.y += p.beta.x * c.y + p.beta.y * c.x;
-          }
-          C[off] = out;
-        }
-      }
+void splitk_finish(tt_ctx* ctx, int M, int N, int batch, int nsplit, zc* ws, zc alpha, zc beta, zc* C, long ldc,
+                   long strideC) {
+  GemmParams p;
+  p.M = M; p.N = N; p.K = 0; p.kchunk = 0;
+  p.A = nullptr; p.lda = 0; p.sA = 0;
+  p.B = nullptr; p.ldb = 0; p.sB = 0;
+  p.C = C; p.ldc = ldc; p.sC = strideC;
+  p.alpha = alpha; p.beta = beta; p.batch = batch; p.ws = ws;
+  const long total = (long)M * N * batch;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+  KTimer kt(ctx, "zgemm_reduce", 0.0, 16.0 * (double)total * (nsplit + 1 + (beta.x != 0.0 || beta.y != 0.0)));
+  hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, ctx->stream, p, nsplit);
 }
 
 template <int BM, int BN>
-void launch_tile(int fmt, int opA, int opB, dim3 grid, hipStream_t st, const GemmParams& p) {
-#define TTF_GEMM_CASE(OA, OB)                                                                           \
-  if (opA == OA && opB == OB) {                                                                         \
-    if (fmt == TT_PREC_BF16X3)                                                                          \
-      hipLaunchKernelGGL((zgemm_split_kernel<TT_PREC_BF16X3, OA, OB, BM, BN>), grid, dim3(256), 0, st, p); \
-    else if (fmt == TT_PREC_FP16X3)                                                                     \
-      hipLaunchKernelGGL((zgemm_split_kernel<TT_PREC_FP16X3, OA, OB, BM, BN>), grid, dim3(256), 0, st, p); \
-    else                                                                                                \
-      hipLaunchKernelGGL((zgemm_kernel<OA, OB, BM, BN>), grid, dim3(256), 0, st, p);           \
-    return;                                                                                    \
+void launch_tile(int opA, int opB, dim3 grid, hipStream_t st, const GemmParams& p) {
+#define TTF_GEMM_CASE(OA, OB)                                                        \
+  if (opA == OA && opB == OB) {                                                      \
+    hipLaunchKernelGGL((zgemm_kernel<OA, OB, BM, BN>), grid, dim3(256), 0, st, p); \
+    return;                                                                          \
   }
   TTF_GEMM_CASE(OPN, OPN)
   TTF_GEMM_CASE(OPN, OPT)
@@ -562,8 +278,11 @@ void launch_tile(int fmt, int opA, int opB, dim3 grid, hipStream_t st, const Gem
 void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const zc* A,
                 long lda, long strideA, const zc* B, long ldb, long strideB, zc beta, zc* C, long ldc,
                 long strideC, int batch) {
-  const bool mixed = fmt != TT_PREC_FP64;
-  if (fmt != TT_PREC_FP64 && fmt != TT_PREC_BF16X3 && fmt != TT_PREC_FP16X3) fail(TT_EINVAL, "zgemm: unknown precision");
+  if (fmt == TT_PREC_BF16X3 || fmt == TT_PREC_FP16X3) {
+    zgemm_split(fmt, ctx, opA, opB, M, N, K, alpha, A, lda, strideA, B, ldb, strideB, beta, C, ldc, strideC, batch);
+    return;
+  }
+  if (fmt != TT_PREC_FP64) fail(TT_EINVAL, "zgemm: unknown precision");
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (K <= 0) {
     // C = beta C: reuse the kernel with an empty K range (kernel writes alpha*0 + beta*C)
@@ -589,7 +308,7 @@ void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc 
   // split K when the output grid alone cannot occupy the chip (about two
   // workgroups per compute unit), keeping at least two K steps per split
   int nsplit = 1;
-  const int kb = mixed ? MX_BK : BK;
+  const int kb = BK;
   const int kblocks = (K + kb - 1) / kb;
   if (tiles < 512 && kblocks >= 4) {
     nsplit = (int)std::min<long>((512 + tiles - 1) / tiles, kblocks / 2);
@@ -612,35 +331,26 @@ void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc 
     std::string shape;
     if (ctx->profile_shapes) {
       const char ops[3] = {'N', 'T', 'C'};
-      static const char* cls[3] = {"zgemm:", "zgemm_bf16x3:", "zgemm_fp16x3:"};
-      shape = std::string(cls[fmt]) + ops[opA] + ops[opB] + ":" + std::to_string(M) + "x" +
+      shape = std::string("zgemm:") + ops[opA] + ops[opB] + ":" + std::to_string(M) + "x" +
               std::to_string(N) + "x" +
               std::to_string(K) + "x" + std::to_string(batch);
     }
     KTimer kt2(ctx->profile_shapes ? ctx : nullptr, shape.c_str(), flops, bytes);
     {
-      // the split classes count the 16-bit products they execute (three
-      // per real product) against the 16-bit matrix-core peak
-      static const char* cls[3] = {"zgemm", "zgemm_bf16x3", "zgemm_fp16x3"};
-      KTimer kt(ctx, cls[fmt], mixed ? 3.0 * flops : flops, bytes);
+      KTimer kt(ctx, "zgemm", flops, bytes);
       const dim3 grid(gx, gy, batch * nsplit);
       if (bm == 64 && bn == 64)
-        launch_tile<64, 64>(fmt, opA, opB, grid, ctx->stream, p);
+        launch_tile<64, 64>(opA, opB, grid, ctx->stream, p);
       else if (bm == 128)
-        launch_tile<128, 32>(fmt, opA, opB, grid, ctx->stream, p);
+        launch_tile<128, 32>(opA, opB, grid, ctx->stream, p);
       else if (bm == 64)
-        launch_tile<64, 32>(fmt, opA, opB, grid, ctx->stream, p);
+        launch_tile<64, 32>(opA, opB, grid, ctx->stream, p);
       else if (bn == 32)
-        launch_tile<32, 32>(fmt, opA, opB, grid, ctx->stream, p);
+        launch_tile<32, 32>(opA, opB, grid, ctx->stream, p);
       else
-        launch_tile<32, 64>(fmt, opA, opB, grid, ctx->stream, p);
+        launch_tile<32, 64>(opA, opB, grid, ctx->stream, p);
     }
-    if (nsplit > 1) {
-      const long total = (long)M * N * batch;
-      const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
-      KTimer kt(ctx, "zgemm_reduce", 0.0, 16.0 * (double)total * (nsplit + 1 + (p.beta.x != 0.0 || p.beta.y != 0.0)));
-      hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, ctx->stream, p, nsplit);
-    }
+    if (nsplit > 1) splitk_finish(ctx, M, N, batch, nsplit, p.ws, alpha, beta, C, ldc, strideC);
   }
   TTF_HIP(hipGetLastError());
 }
