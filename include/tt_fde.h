@@ -64,6 +64,14 @@ enum {
   TT_APPLY_SKETCH = 1  /* fused apply + randomised range compression           */
 };
 
+/* Step-truncation schemes of tt_step (Sec. 4.1). */
+enum {
+  TT_STEP_RK4 = 0,      /* classical RK4, four stages (default)                  */
+  TT_STEP_EULER = 1,    /* truncated explicit Euler, eq. (adaptive-euler-method) */
+  TT_STEP_MIDPOINT = 2  /* truncated explicit midpoint,
+                           eq. (adaptive-midpoint-method_2)                      */
+};
+
 /* Arithmetic of the operator application's contractions. */
 enum {
   TT_PREC_FP64 = 0,    /* plain complex FP64                                   */
@@ -227,7 +235,7 @@ typedef struct {
   int precision;         /* a TT_PREC_* value (the operator
                             applications' contractions; QR, SVD, truncation
                             test and sums always FP64) */
-  int pad;
+  int scheme;            /* a TT_STEP_* value */
 } tt_step_opts;
 
 typedef struct {
@@ -236,13 +244,18 @@ typedef struct {
   int ranks[TT_MAX_D + 1];
 } tt_step_report;
 
-/* One classical RK4 step-truncation step of df/dt = L f, in place:
+/* One step-truncation step of df/dt = L f, in place, T = tt_round(eps,
+ * rmax).  TT_STEP_RK4 (classical RK4 with a truncation after every
+ * operator application and every stage combination):
  *   k1 = T[L f],  y2 = T[f + dt/2 k1],  k2 = T[L y2],  y3 = T[f + dt/2 k2],
  *   k3 = T[L y3], y4 = T[f + dt k3],    k4 = T[L y4],
  *   f <- T[f + dt/6 (k1 + 2 k2 + 2 k3 + k4)]
- * with T = tt_round(eps, rmax).  Each of the four stages is one operator
- * application, its truncation, one combination and its truncation
- * (the last stage's combination is the final one). */
+ * Each of the four stages is one operator application, its truncation, one
+ * combination and its truncation (the last stage's combination is the
+ * final one).  TT_STEP_EULER: f <- T[f + dt T[L f]] (one stage).
+ * TT_STEP_MIDPOINT: f <- T[f + dt T[L(f + dt/2 T[L f])]] (two stages; the
+ * stage input f + dt/2 T[L f] is not truncated, as in Sec. 4.1).
+ * rep->stages is 4, 1 or 2.  TT_EINVAL for an unknown scheme. */
 int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt,
             const tt_step_opts* opts, tt_step_report* rep);
 

@@ -24,6 +24,12 @@ one after every stage combination:
     k3 = T[L y3]         y4 = T[f + dt k3]
     k4 = T[L y4]         f+ = T[f + dt/6 (k1 + 2 k2 + 2 k3 + k4)]
 
+The two explicit step-truncation schemes of Sec. 4.1 are taken as written
+there: truncated Euler (eq. (adaptive-euler-method)) f+ = T[f + dt T[L f]],
+and truncated explicit midpoint (eq. (adaptive-midpoint-method_2))
+f+ = T[f + dt T[L(f + dt/2 T[L f])]], whose stage input f + dt/2 T[L f] is
+not truncated.
+
 T is the TT-SVD of the full array with a relative tolerance and a rank cap
 (App. A.1, Alg. 2 applied to an exact representation; sweep order left to
 right, per-bond threshold eps*||f||/sqrt(d-1)).  ``truncate`` returns the
@@ -31,7 +37,10 @@ full array of the truncated TT so the RK4 loop stays on the full grid.
 
 Pins (tests/test_oracle_fullgrid.py): assembly against an independent sparse
 Kronecker-product matrix; RK4 against the matrix exponential of that matrix
-(fourth-order convergence in dt); viscous-only run against the per-axis
+(fourth-order convergence in dt); truncated Euler and midpoint without
+truncation against the matrix polynomials I + dt M and I + dt M + dt^2/2 M^2,
+their global orders one and two against the matrix exponential and their
+Richardson local-error slopes two and three; viscous-only run against the per-axis
 exponential and the continuous closed form (second order in h); deterministic
 initial state against exp(i a.u(t)) of the Galerkin ODE; phi(0,t) = 1 on
 odd-n grids; Hermitian symmetry; TT-SVD error bound and exactness.
@@ -171,6 +180,36 @@ def truncated_rk4_step(f, dt, op, eps_rel, cap=None):
     y4 = t(f + dt * k3)
     k4 = t(op(y4))
     return t(f + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4))
+
+
+def truncated_euler_step(f, dt, op, eps_rel, cap=None):
+    """Truncated explicit Euler, Sec. 4.1 eq. (adaptive-euler-method):
+    f+ = T_r[f + dt T_s[L f]]."""
+    t = lambda x: truncate(x, eps_rel, cap)
+    return t(f + dt * t(op(f)))
+
+
+def truncated_midpoint_step(f, dt, op, eps_rel, cap=None):
+    """Truncated explicit midpoint, Sec. 4.1 eq. (adaptive-midpoint-method_2):
+    f+ = T_a[f + dt T_b[L(f + dt/2 T_g[L f])]]; the stage input
+    f + dt/2 T_g[L f] itself is not truncated."""
+    t = lambda x: truncate(x, eps_rel, cap)
+    g = t(op(f))
+    h = t(op(f + 0.5 * dt * g))
+    return t(f + dt * h)
+
+
+def richardson_local_error(step, f, dt, order):
+    """Local error of one step of size dt of a method of the given order,
+    estimated against the Richardson extrapolation of one order higher
+    built from two steps of dt/2 and the step of dt (the estimate the
+    paper's order study uses, Sec. 5.2):
+        R = (2^p y_half - y_full) / (2^p - 1),  error = ||y_full - R||."""
+    y_full = step(f, dt)
+    y_half = step(step(f, 0.5 * dt), 0.5 * dt)
+    w = 2.0**order
+    r = (w * y_half - y_full) / (w - 1.0)
+    return float(np.linalg.norm((y_full - r).ravel()))
 
 
 def gaussian_ic(mu, sigma, n, length):

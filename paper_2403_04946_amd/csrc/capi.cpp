@@ -310,6 +310,13 @@ int truncation_rank(const std::vector<double>& s, double delta, int cap, double*
       kk = j;
       break;
     }
+  // singular values at roundoff level (sigma^2 <= 4e-30 sum sigma^2) are
+  // zero: the Jacobi SVD does not rotate such columns, so their left
+  // vectors are not orthogonal to the others and U_k U_k^H would stop being
+  // a projector if they were kept (only reachable with eps = 0)
+  int nz = 0;
+  while (nz < k && s[nz] * s[nz] > 4e-30 * tail[0]) ++nz;
+  kk = std::min(kk, std::max(nz, 1));
   if (cap > 0) kk = std::min(kk, cap);
   kk = std::max(kk, 1);
   if (tail_out) *tail_out = std::sqrt(tail[kk]);
@@ -1054,27 +1061,34 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
   ABI_TRY
   require(opts->size == (int)sizeof(tt_step_opts), TT_EINVAL, "tt_step_opts.size mismatch");
   require(opts->rmax >= 1, TT_EINVAL, "tt_step: rmax must be >= 1");
+  require(opts->precision == TT_PREC_FP64 || opts->precision == TT_PREC_BF16X3 || opts->precision == TT_PREC_FP16X3,
+          TT_EINVAL, "tt_step: unknown precision");
+  const int scheme = opts->scheme;
+  require(scheme == TT_STEP_RK4 || scheme == TT_STEP_EULER || scheme == TT_STEP_MIDPOINT, TT_EINVAL,
+          "tt_step: unknown scheme");
   check_same_shape(op, f);
   const int d = f->d, n = f->n, rmax = opts->rmax;
-  // capacities of the temporaries
+  // capacities of the temporaries: stage derivatives k (apply outputs),
+  // stage inputs y (f + c k) and the final combination
   std::vector<int> capk(d + 1), capy(d + 1), capf(d + 1);
   for (int k = 0; k <= d; ++k) {
     const int rk = (k == 0 || k == d) ? 1 : std::max(rmax, f->cap[k]);
     const int base = (k == 0 || k == d) ? 1 : rmax;
+    // the midpoint stage input f + dt/2 k is applied untruncated
+    const int rin = (scheme == TT_STEP_MIDPOINT && k > 0 && k < d) ? rk + base : rk;
     if (opts->apply_mode == TT_APPLY_EXACT)
-      capk[k] = op->R[k] * rk;
+      capk[k] = op->R[k] * rin;
     else
       capk[k] = (k == 0 || k == d) ? 1 : std::max(opts->sketch_rank, rmax);
     capy[k] = (k == 0 || k == d) ? 1 : rk + base;
     capf[k] = (k == 0 || k == d) ? 1 : rk + 4 * base;
   }
-  const std::string key = shape_key(d, n, f->cap, opts->apply_mode * 100000 + opts->sketch_rank * 100 + rmax);
-  require(opts->precision == TT_PREC_FP64 || opts->precision == TT_PREC_BF16X3 || opts->precision == TT_PREC_FP16X3,
-          TT_EINVAL,
-          "tt_step: unknown precision");
+  const std::string key = shape_key(d, n, f->cap, rmax) + ":" + std::to_string(scheme) + ":" +
+                          std::to_string(opts->apply_mode) + ":" + std::to_string(opts->sketch_rank);
   StepTemps& T = step_cache()[{ctx, key}];
   if (!T.ysum) {
-    for (int s = 0; s < 4; ++s) T.k[s] = make_tensor(ctx, d, n, capk);
+    const int nk = scheme == TT_STEP_RK4 ? 4 : scheme == TT_STEP_MIDPOINT ? 2 : 1;
+    for (int s = 0; s < nk; ++s) T.k[s] = make_tensor(ctx, d, n, capk);
     T.ysum = make_tensor(ctx, d, n, capy);
     T.fsum = make_tensor(ctx, d, n, capf);
   }
@@ -1084,30 +1098,54 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
   auto track = [&](const tt_tensor* t) {
     for (int k = 0; k <= d; ++k) maxr = std::max(maxr, t->rank[k]);
   };
-  const tt_tensor* stage_in = f;
-  const double cst[3] = {0.5 * dt, 0.5 * dt, dt};
-  for (int s = 0; s < 4; ++s) {
-    apply_any(ctx, op, stage_in, T.k[s], mode, l, opts->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(s + 1),
-              opts->precision);
+  // stage s: k_s = T[L y_s] with its own sketch seed
+  auto stage = [&](int s, const tt_tensor* in) {
+    apply_any(ctx, op, in, T.k[s], mode, l, opts->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(s + 1), opts->precision);
     round_tensor(ctx, T.k[s], eps, rmax, nullptr);
     track(T.k[s]);
-    if (s < 3) {
-      const tt_tensor* xs[2] = {f, T.k[s]};
-      const zc coef[2] = {Z(1), Z(cst[s])};
-      sum_tensors(ctx, 2, coef, xs, T.ysum);
-      round_tensor(ctx, T.ysum, eps, rmax, nullptr);
-      track(T.ysum);
-      stage_in = T.ysum;
+  };
+  int stages = 0;
+  if (scheme == TT_STEP_RK4) {
+    const tt_tensor* stage_in = f;
+    const double cst[3] = {0.5 * dt, 0.5 * dt, dt};
+    for (int s = 0; s < 4; ++s) {
+      stage(s, stage_in);
+      if (s < 3) {
+        const tt_tensor* xs[2] = {f, T.k[s]};
+        const zc coef[2] = {Z(1), Z(cst[s])};
+        sum_tensors(ctx, 2, coef, xs, T.ysum);
+        round_tensor(ctx, T.ysum, eps, rmax, nullptr);
+        track(T.ysum);
+        stage_in = T.ysum;
+      }
     }
+    const tt_tensor* xs[5] = {f, T.k[0], T.k[1], T.k[2], T.k[3]};
+    const zc coef[5] = {Z(1), Z(dt / 6), Z(dt / 3), Z(dt / 3), Z(dt / 6)};
+    sum_tensors(ctx, 5, coef, xs, T.fsum);
+    stages = 4;
+  } else if (scheme == TT_STEP_EULER) {
+    stage(0, f);
+    const tt_tensor* xs[2] = {f, T.k[0]};
+    const zc coef[2] = {Z(1), Z(dt)};
+    sum_tensors(ctx, 2, coef, xs, T.fsum);
+    stages = 1;
+  } else {
+    stage(0, f);
+    const tt_tensor* ys[2] = {f, T.k[0]};
+    const zc ycoef[2] = {Z(1), Z(0.5 * dt)};
+    sum_tensors(ctx, 2, ycoef, ys, T.ysum);  // not truncated
+    track(T.ysum);
+    stage(1, T.ysum);
+    const tt_tensor* xs[2] = {f, T.k[1]};
+    const zc coef[2] = {Z(1), Z(dt)};
+    sum_tensors(ctx, 2, coef, xs, T.fsum);
+    stages = 2;
   }
-  const tt_tensor* xs[5] = {f, T.k[0], T.k[1], T.k[2], T.k[3]};
-  const zc coef[5] = {Z(1), Z(dt / 6), Z(dt / 3), Z(dt / 3), Z(dt / 6)};
-  sum_tensors(ctx, 5, coef, xs, T.fsum);
   round_tensor(ctx, T.fsum, eps, rmax, nullptr);
   track(T.fsum);
   copy_tensor(ctx, T.fsum, f);
   if (rep) {
-    rep->stages = 4;
+    rep->stages = stages;
     rep->max_rank = maxr;
     for (int k = 0; k <= d; ++k) rep->ranks[k] = f->rank[k];
   }

@@ -20,6 +20,9 @@ TT_APPLY_SKETCH = 1
 TT_PREC_FP64 = 0
 TT_PREC_BF16X3 = 1
 TT_PREC_FP16X3 = 2
+TT_STEP_RK4 = 0
+TT_STEP_EULER = 1
+TT_STEP_MIDPOINT = 2
 TT_ECAPACITY = -3
 ORTH = {0: "none", 1: "right", 2: "left"}
 ERRORS = {
@@ -70,7 +73,7 @@ class StepOpts(ctypes.Structure):
         ("sketch_rank", ctypes.c_int),
         ("seed", ctypes.c_uint64),
         ("precision", ctypes.c_int),
-        ("pad", ctypes.c_int),
+        ("scheme", ctypes.c_int),
     ]
 
 
@@ -354,9 +357,10 @@ def tt_round(ctx, x, eps, rmax=0, report=True):
     }
 
 
-def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0):
+def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0,
+            scheme=TT_STEP_RK4):
     o = StepOpts(ctypes.sizeof(StepOpts), int(rmax), float(eps), int(mode), int(sketch_rank), int(seed),
-                 int(precision), 0)
+                 int(precision), int(scheme))
     rep = StepReport()
     ctx.check(lib().tt_step(ctx.h, op.h, f.h, float(dt), ctypes.byref(o), ctypes.byref(rep)))
     return {"stages": rep.stages, "max_rank": rep.max_rank, "ranks": list(rep.ranks[: f.d + 1])}

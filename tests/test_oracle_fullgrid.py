@@ -71,6 +71,81 @@ def test_rk4_fourth_order_against_matrix_exponential():
     assert all(3.6 < r < 4.4 for r in rates), (errs, rates)
 
 
+def test_truncated_euler_and_midpoint_are_the_matrix_polynomials():
+    """Without truncation the two explicit schemes are the Taylor polynomials
+    of exp(dt M) of degree one and two, M the independently assembled
+    Kronecker-product matrix."""
+    d, n, length, nu, dt = 3, 6, 4.0, 0.05, 3e-2
+    b, dm = galerkin.coefficient_B(d), galerkin.coefficient_D(d)
+    prob = fullgrid.Problem(b, dm, nu, n, length)
+    mat = kron_operator(b, dm, nu, d, n, length)
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal((n,) * d) + 1j * rng.standard_normal((n,) * d)
+    v = f.ravel()
+    mv = mat @ v
+    euler = v + dt * mv
+    midpoint = v + dt * mv + 0.5 * dt * dt * (mat @ mv)
+    got_e = fullgrid.truncated_euler_step(f, dt, prob.apply, 0.0).ravel()
+    got_m = fullgrid.truncated_midpoint_step(f, dt, prob.apply, 0.0).ravel()
+    assert np.linalg.norm(got_e - euler) <= 1e-13 * np.linalg.norm(euler)
+    assert np.linalg.norm(got_m - midpoint) <= 1e-13 * np.linalg.norm(midpoint)
+    # a dropped half in the midpoint stage is caught: it would equal Euler
+    # applied twice less a term of size dt^2/2 |M^2 f|
+    assert np.linalg.norm(got_m - euler) > 1e-3 * np.linalg.norm(euler)
+
+
+@pytest.mark.parametrize("scheme,order", [("euler", 1), ("midpoint", 2)])
+def test_explicit_scheme_global_order_against_matrix_exponential(scheme, order):
+    d, n, length, nu, tend = 3, 7, 4.0, 0.05, 0.2
+    b, dm = galerkin.coefficient_B(d), galerkin.coefficient_D(d)
+    prob = fullgrid.Problem(b, dm, nu, n, length)
+    mat = kron_operator(b, dm, nu, d, n, length)
+    mu, sig = inputs.ic_params(d, 3)
+    f0 = fullgrid.gaussian_ic(mu, sig, n, length)
+    exact = spla.expm_multiply(tend * mat, f0.ravel()).reshape(f0.shape)
+    step = {"euler": fullgrid.truncated_euler_step, "midpoint": fullgrid.truncated_midpoint_step}[scheme]
+    errs = []
+    for steps in (40, 80, 160):
+        f = f0.copy()
+        for _ in range(steps):
+            f = step(f, tend / steps, prob.apply, 0.0)
+        errs.append(fullgrid.rel_l2(f, exact))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(order - 0.25 < r < order + 0.25 for r in rates), (errs, rates)
+
+
+@pytest.mark.parametrize("scheme,order", [("euler", 1), ("midpoint", 2), ("rk4", 4)])
+def test_richardson_local_error_slopes(scheme, order):
+    """The paper's order study: the local error against the Richardson
+    extrapolation falls like dt^(p+1) for a method of order p."""
+    d, n, length, nu = 3, 6, 4.0, 0.05
+    b, dm = galerkin.coefficient_B(d), galerkin.coefficient_D(d)
+    prob = fullgrid.Problem(b, dm, nu, n, length)
+    mu, sig = inputs.ic_params(d, 2)
+    f0 = fullgrid.gaussian_ic(mu, sig, n, length)
+    step = {"euler": lambda f, h: fullgrid.truncated_euler_step(f, h, prob.apply, 0.0),
+            "midpoint": lambda f, h: fullgrid.truncated_midpoint_step(f, h, prob.apply, 0.0),
+            "rk4": lambda f, h: fullgrid.rk4_step(f, h, prob.apply)}[scheme]
+    dts = [2e-2, 1e-2, 5e-3]
+    errs = [fullgrid.richardson_local_error(step, f0, h, order) for h in dts]
+    slopes = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(order + 1 - 0.3 < s < order + 1 + 0.3 for s in slopes), (errs, slopes)
+
+
+def test_richardson_estimate_matches_exact_local_error():
+    """For Euler the Richardson estimate equals the true local error to
+    leading order: both are dt^2/2 |M^2 f| (pins the extrapolation weights)."""
+    d, n, length, nu, dt = 3, 6, 4.0, 0.05, 1e-3
+    b, dm = galerkin.coefficient_B(d), galerkin.coefficient_D(d)
+    prob = fullgrid.Problem(b, dm, nu, n, length)
+    mat = kron_operator(b, dm, nu, d, n, length)
+    mu, sig = inputs.ic_params(d, 2)
+    f0 = fullgrid.gaussian_ic(mu, sig, n, length)
+    est = fullgrid.richardson_local_error(lambda f, h: fullgrid.truncated_euler_step(f, h, prob.apply, 0.0), f0, dt, 1)
+    true = np.linalg.norm(spla.expm_multiply(dt * mat, f0.ravel()) - (f0.ravel() + dt * (mat @ f0.ravel())))
+    assert abs(est / true - 1.0) < 0.05, (est, true)
+
+
 def test_viscous_only_semidiscrete_exact():
     d, n, length, nu, dt, steps = 3, 16, 4.0, 0.05, 1e-3, 50
     b = np.zeros((d, d, d))
