@@ -12,6 +12,8 @@
 // between groups through LDS.  Every column pair meets once per sweep, so
 // this is a cyclic Jacobi method with a block ordering; sweeps stop after
 // the first one without a rotation.
+#include <string>
+
 #include "common.hpp"
 #include "dpp.hpp"
 
@@ -62,6 +64,9 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
 void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
   if (k <= 0) return;
   if (k > JB_MAXK || m > JB_MAXM || m < 1) fail(TT_EINVAL, "jacobi_svd: sizes above the supported maximum of 512");
+  std::string shape;
+  if (ctx->profile_shapes) shape = "jacobi:" + std::to_string(m) + "x" + std::to_string(k);
+  KTimer kt2(ctx->profile_shapes ? ctx : nullptr, shape.c_str(), 0.0, 0.0);
   KTimer kt(ctx, "jacobi_svd", 0.0, 0.0);
   jacobi_blocked(ctx, m, k, B, U, sigma, sweeps);
 }

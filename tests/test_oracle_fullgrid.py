@@ -146,6 +146,47 @@ def test_richardson_estimate_matches_exact_local_error():
     assert abs(est / true - 1.0) < 0.05, (est, true)
 
 
+def test_implicit_steps_match_sparse_direct_solve():
+    """The implicit steps against an LU solve of the independently assembled
+    Kronecker matrix: (I - dt M) x = f and (I - dt/2 M) x = (I + dt/2 M) f."""
+    d, n, length, nu, dt = 3, 7, 4.0, 0.05, 2e-2
+    b, dm = galerkin.coefficient_B(d), galerkin.coefficient_D(d)
+    prob = fullgrid.Problem(b, dm, nu, n, length)
+    mat = kron_operator(b, dm, nu, d, n, length).tocsc()
+    eye = sp.identity(n**d, format="csc", dtype=np.complex128)
+    mu, sig = inputs.ic_params(d, 1)
+    f = fullgrid.gaussian_ic(mu, sig, n, length)
+    v = f.ravel()
+    euler = spla.splu(eye - dt * mat).solve(v)
+    midpoint = spla.splu(eye - 0.5 * dt * mat).solve(v + 0.5 * dt * (mat @ v))
+    got_e = fullgrid.implicit_euler_step(f, dt, prob.apply).ravel()
+    got_m = fullgrid.implicit_midpoint_step(f, dt, prob.apply).ravel()
+    assert np.linalg.norm(got_e - euler) <= 1e-12 * np.linalg.norm(euler)
+    assert np.linalg.norm(got_m - midpoint) <= 1e-12 * np.linalg.norm(midpoint)
+    # the two differ at second order: a swapped shift sign is caught
+    assert np.linalg.norm(got_m - got_e) > 1e-5 * np.linalg.norm(euler)
+
+
+@pytest.mark.parametrize("scheme,order", [("implicit_euler", 1), ("implicit_midpoint", 2)])
+def test_implicit_scheme_global_order(scheme, order):
+    d, n, length, nu, tend = 3, 7, 4.0, 0.05, 0.2
+    b, dm = galerkin.coefficient_B(d), galerkin.coefficient_D(d)
+    prob = fullgrid.Problem(b, dm, nu, n, length)
+    mat = kron_operator(b, dm, nu, d, n, length)
+    mu, sig = inputs.ic_params(d, 3)
+    f0 = fullgrid.gaussian_ic(mu, sig, n, length)
+    exact = spla.expm_multiply(tend * mat, f0.ravel()).reshape(f0.shape)
+    step = getattr(fullgrid, scheme + "_step")
+    errs = []
+    for steps in (20, 40, 80):
+        f = f0.copy()
+        for _ in range(steps):
+            f = step(f, tend / steps, prob.apply)
+        errs.append(fullgrid.rel_l2(f, exact))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(order - 0.25 < r < order + 0.25 for r in rates), (errs, rates)
+
+
 def test_viscous_only_semidiscrete_exact():
     d, n, length, nu, dt, steps = 3, 16, 4.0, 0.05, 1e-3, 50
     b = np.zeros((d, d, d))
