@@ -51,7 +51,7 @@ enum {
   TT_ECAPACITY = -3,   /* a result rank exceeds the output tensor's capacity  */
   TT_ENOMEM = -4,      /* device or host allocation failed                    */
   TT_EHIP = -5,        /* a HIP runtime call failed                           */
-  TT_ENOCONV = -6,     /* Jacobi SVD did not converge within its sweep limit  */
+  TT_ENOCONV = -6,     /* Jacobi SVD or TT-GMRES did not converge in its limit */
   TT_ENONFINITE = -7   /* a non-finite value was detected                     */
 };
 
@@ -68,8 +68,12 @@ enum {
 enum {
   TT_STEP_RK4 = 0,      /* classical RK4, four stages (default)                  */
   TT_STEP_EULER = 1,    /* truncated explicit Euler, eq. (adaptive-euler-method) */
-  TT_STEP_MIDPOINT = 2  /* truncated explicit midpoint,
+  TT_STEP_MIDPOINT = 2, /* truncated explicit midpoint,
                            eq. (adaptive-midpoint-method_2)                      */
+  TT_STEP_IMPLICIT_EULER = 3,    /* implicit step-truncation Euler,
+                                    eq. (EB-linear), TT-GMRES                    */
+  TT_STEP_IMPLICIT_MIDPOINT = 4  /* implicit step-truncation midpoint,
+                                    eq. (MP-linear), TT-GMRES                    */
 };
 
 /* Arithmetic of the operator application's contractions. */
@@ -236,6 +240,11 @@ typedef struct {
                             applications' contractions; QR, SVD, truncation
                             test and sums always FP64) */
   int scheme;            /* a TT_STEP_* value */
+  double gmres_tol;      /* implicit schemes: relative residual target of
+                            TT-GMRES (> 0) */
+  int gmres_max_iter;    /* implicit schemes: Krylov dimension, 1..40 */
+  int krylov_rmax;       /* implicit schemes: rank cap of the Krylov vectors
+                            (0: 2 rmax), at most 256 */
 } tt_step_opts;
 
 typedef struct {
@@ -255,7 +264,13 @@ typedef struct {
  * final one).  TT_STEP_EULER: f <- T[f + dt T[L f]] (one stage).
  * TT_STEP_MIDPOINT: f <- T[f + dt T[L(f + dt/2 T[L f])]] (two stages; the
  * stage input f + dt/2 T[L f] is not truncated, as in Sec. 4.1).
- * rep->stages is 4, 1 or 2.  TT_EINVAL for an unknown scheme. */
+ * rep->stages is 4, 1 or 2.
+ * TT_STEP_IMPLICIT_EULER / TT_STEP_IMPLICIT_MIDPOINT (Sec. 4.1): solve
+ * (I - dt L) x = f, resp. (I - dt/2 L) x = T[f + dt/2 T[L f]], by TT-GMRES
+ * (tt_solve_shifted) started from the explicit Euler / midpoint step, then
+ * f <- T[x]; rep->stages counts the operator applications.  TT_ENOCONV if
+ * GMRES does not reach gmres_tol within gmres_max_iter iterations (f is
+ * then left unchanged).  TT_EINVAL for an unknown scheme. */
 int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt,
             const tt_step_opts* opts, tt_step_report* rep);
 
@@ -287,6 +302,46 @@ int tt_zgemm_mixed(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, i
                    double alpha_im, const double* A, int64_t lda, int64_t strideA, const double* B,
                    int64_t ldb, int64_t strideB, double beta_re, double beta_im, double* C, int64_t ldc,
                    int64_t strideC, int batch);
+
+/* Complex inner product <x, y> = sum over all entries of conj(x) y
+ * (synchronous): left-to-right contraction of the cores, two GEMMs per
+ * core (App. A.1 arithmetic).  out: host array of 2 doubles (re, im). */
+int tt_dot(tt_ctx* ctx, const tt_tensor* x, const tt_tensor* y, double* out);
+
+/* TT-GMRES for the shifted system (I - c L) x = b of the implicit
+ * step-truncation schemes (Sec. 4.1, eq. (EB-linear) / (MP-linear); the
+ * method of the reference cited there): Krylov vectors are TTs truncated to
+ * krylov_eps (relative) and krylov_rmax after every operator application
+ * and orthogonalisation (two classical Gram-Schmidt passes with TT inner
+ * products), the small Hessenberg least-squares problem is solved by Givens
+ * rotations on the host, and the solution x0 + V y is truncated to (eps,
+ * rmax).  x: on entry the initial guess when use_guess (else zero), on exit
+ * the truncated solution (its capacities must hold rmax).  Synchronous. */
+typedef struct {
+  int size;              /* sizeof(tt_solve_opts) */
+  int max_iter;          /* Krylov dimension, 1..40 (no restart) */
+  double tol;            /* relative residual target ||r|| <= tol ||b|| */
+  double krylov_eps;     /* relative truncation of Krylov vectors (> 0) */
+  int krylov_rmax;       /* rank cap of Krylov vectors, 1..256 */
+  int rmax;              /* rank cap of the returned solution */
+  double eps;            /* relative truncation of the returned solution */
+  int apply_mode;        /* TT_APPLY_EXACT or TT_APPLY_SKETCH */
+  int sketch_rank;
+  uint64_t seed;
+  int precision;         /* TT_PREC_* of the operator applications */
+  int use_guess;         /* 1: x holds the initial guess */
+} tt_solve_opts;
+
+typedef struct {
+  int iterations;        /* Krylov vectors generated */
+  int converged;         /* residual estimate <= tol */
+  double residual;       /* final relative residual estimate |g_{k+1}| / ||b|| */
+  int max_rank;          /* largest rank of a Krylov vector */
+  int pad;
+} tt_solve_report;
+
+int tt_solve_shifted(tt_ctx* ctx, const tt_op* op, double c, const tt_tensor* b, tt_tensor* x,
+                     const tt_solve_opts* opts, tt_solve_report* rep);
 
 /* Frobenius norm of x (synchronous; computed by orthogonalisation). */
 int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out);

@@ -2,6 +2,7 @@
 // sweeps, exact and sketched operator application, RK4 step-truncation.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <new>
 #include <tuple>
@@ -636,7 +637,38 @@ std::string shape_key(int d, int n, const std::vector<int>& cap, int extra) {
   return s;
 }
 
+// named temporaries (TT-GMRES and friends), reused while their capacities
+// suffice
+std::map<std::pair<tt_ctx*, std::string>, tt_tensor*>& pool_cache() {
+  static std::map<std::pair<tt_ctx*, std::string>, tt_tensor*> c;
+  return c;
+}
+
+tt_tensor* pooled(tt_ctx* ctx, const std::string& name, int d, int n, const std::vector<int>& cap) {
+  tt_tensor*& t = pool_cache()[{ctx, name}];
+  bool ok = t && t->d == d && t->n == n;
+  for (int k = 0; ok && k <= d; ++k) ok = t->cap[k] >= cap[k];
+  if (!ok) {
+    if (t) {
+      TTF_HIP(hipStreamSynchronize(ctx->stream));
+      free_tensor(t);
+    }
+    t = nullptr;
+    t = make_tensor(ctx, d, n, cap);
+  }
+  return t;
+}
+
 void drop_ctx_caches(tt_ctx* ctx) {
+  auto& pc = pool_cache();
+  for (auto it = pc.begin(); it != pc.end();) {
+    if (it->first.first == ctx) {
+      free_tensor(it->second);
+      it = pc.erase(it);
+    } else {
+      ++it;
+    }
+  }
   auto& sc = step_cache();
   for (auto it = sc.begin(); it != sc.end();) {
     if (it->first.first == ctx) {
@@ -1056,6 +1088,246 @@ int tt_round(tt_ctx* ctx, tt_tensor* x, double eps_rel, int rmax, tt_round_repor
   ABI_CATCH(ctx)
 }
 
+// <x, y> = sum conj(x) y by left-to-right contraction:
+// W_{k+1} = V(X_k)^H (W_k H(Y_k)), W_0 = 1 (App. A.1 arithmetic)
+zc dot_tensors(tt_ctx* ctx, const tt_tensor* x, const tt_tensor* y) {
+  require(x->d == y->d && x->n == y->n, TT_ESHAPE, "tt_dot: shape mismatch");
+  const int d = x->d, n = x->n;
+  size_t wmax = 1, tmax = 1;
+  for (int k = 0; k < d; ++k) {
+    wmax = std::max(wmax, (size_t)x->rank[k + 1] * y->rank[k + 1]);
+    tmax = std::max(tmax, (size_t)x->rank[k] * n * y->rank[k + 1]);
+  }
+  zc* W = (zc*)ctx->get_ws("dot_W", sizeof(zc) * wmax);
+  zc* W2 = (zc*)ctx->get_ws("dot_W2", sizeof(zc) * wmax);
+  zc* T = (zc*)ctx->get_ws("dot_T", sizeof(zc) * tmax);
+  zc* h = (zc*)ctx->host_scratch(sizeof(zc));
+  *h = Z(1);
+  TTF_HIP(hipMemcpyAsync(W, h, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
+  for (int k = 0; k < d; ++k) {
+    const int rx0 = x->rank[k], ry0 = y->rank[k], rx1 = x->rank[k + 1], ry1 = y->rank[k + 1];
+    // T (rx0 x n ry1) = W (rx0 x ry0) H(Y_k)
+    zgemm(ctx, OPN, OPN, rx0, n * ry1, ry0, Z(1), W, rx0, 0, y->core[k], ry0, 0, Z(0), T, rx0, 0);
+    // W' (rx1 x ry1) = V(X_k)^H T, T read as (rx0 n) x ry1
+    zgemm(ctx, OPC, OPN, rx1, ry1, rx0 * n, Z(1), x->core[k], (long)rx0 * n, 0, T, (long)rx0 * n, 0, Z(0), W2, rx1,
+          0);
+    std::swap(W, W2);
+  }
+  TTF_HIP(hipMemcpyAsync(h, W, sizeof(zc), hipMemcpyDeviceToHost, ctx->stream));
+  TTF_HIP(hipStreamSynchronize(ctx->stream));
+  return *h;
+}
+
+// ||x|| of a tensor the last rounding left left-orthogonal: the norm of
+// its last core; otherwise orthogonalise a copy first
+double tensor_norm(tt_ctx* ctx, const tt_tensor* x) {
+  if (x->orth == TT_ORTH_LEFT) return core_norm(ctx, x, x->d - 1);
+  if (x->orth == TT_ORTH_RIGHT || x->d == 1) return core_norm(ctx, x, 0);
+  tt_tensor* tmp = pooled(ctx, "norm_tmp", x->d, x->n, x->rank);
+  copy_tensor(ctx, x, tmp);
+  phase1_right_orth(ctx, tmp);
+  return core_norm(ctx, tmp, 0);
+}
+
+std::vector<int> interior_caps(int d, int c) {
+  std::vector<int> cap(d + 1, c);
+  cap[0] = cap[d] = 1;
+  return cap;
+}
+
+// t <- the zero tensor (all ranks 1)
+void set_zero(tt_ctx* ctx, tt_tensor* t) {
+  for (int k = 0; k < t->d; ++k) fill_zero(ctx, t->core[k], t->n);
+  t->rank.assign(t->d + 1, 1);
+  t->orth = TT_ORTH_NONE;
+}
+
+// out <- T[sum_t coef_t xs_t] for any number of terms: chunks of at most
+// `chunk` terms are summed and truncated in turn (relative tolerance eps,
+// cap rmax), the running sum being the first term of every later chunk.
+// `acc` holds each partial sum; out may be any tensor not among xs.
+void sum_round(tt_ctx* ctx, const std::vector<zc>& coef, const std::vector<const tt_tensor*>& xs, tt_tensor* out,
+               double eps, int rmax, const std::string& tag) {
+  const int d = out->d, n = out->n;
+  const int nt = (int)xs.size();
+  int maxr = 1;
+  for (auto* t : xs)
+    for (int k = 0; k <= d; ++k) maxr = std::max(maxr, t->rank[k]);
+  maxr = std::max(maxr, rmax);
+  // keep every partial sum within the SVD size limit (512)
+  const int chunk = std::max(1, std::min(7, 512 / maxr - 1));
+  tt_tensor* acc = pooled(ctx, tag + "_acc", d, n, interior_caps(d, std::min(512, maxr * (chunk + 1))));
+  tt_tensor* run = pooled(ctx, tag + "_run", d, n, interior_caps(d, maxr));
+  bool have = false;
+  for (int t0 = 0; t0 < nt; t0 += chunk) {
+    const int t1 = std::min(nt, t0 + chunk);
+    std::vector<zc> c;
+    std::vector<const tt_tensor*> x;
+    if (have) {
+      c.push_back(Z(1));
+      x.push_back(run);
+    }
+    for (int t = t0; t < t1; ++t) {
+      c.push_back(coef[t]);
+      x.push_back(xs[t]);
+    }
+    sum_tensors(ctx, (int)x.size(), c.data(), x.data(), acc);
+    round_tensor(ctx, acc, eps, rmax, nullptr);
+    copy_tensor(ctx, acc, run);
+    have = true;
+  }
+  copy_tensor(ctx, run, out);
+}
+
+struct GmresResult {
+  int iterations = 0, converged = 0, max_rank = 0, applications = 0;
+  double residual = 0.0;
+};
+
+// TT-GMRES for (I - c L) x = b; x holds the guess (use_guess) and receives
+// the truncated solution.  Returns the report; the caller decides what a
+// missed tolerance means.
+GmresResult gmres_shifted(tt_ctx* ctx, const tt_op* op, double c, const tt_tensor* b, tt_tensor* x,
+                          const tt_solve_opts& o) {
+  const int d = b->d, n = b->n, m = o.max_iter, kr = o.krylov_rmax;
+  GmresResult res;
+  const auto capk = interior_caps(d, kr);
+  // operator application output capacity
+  std::vector<int> capa(d + 1, 1);
+  for (int k = 1; k < d; ++k)
+    capa[k] = o.apply_mode == TT_APPLY_EXACT ? op->R[k] * std::max(kr, o.rmax) : std::max(o.sketch_rank, kr);
+  tt_tensor* ab = pooled(ctx, "gm_apply", d, n, capa);
+  tt_tensor* w = pooled(ctx, "gm_w", d, n, capk);
+  tt_tensor* x0 = pooled(ctx, "gm_x0", d, n, interior_caps(d, std::max(kr, o.rmax)));
+  std::vector<tt_tensor*> V(m + 1);
+  for (int j = 0; j <= m; ++j) V[j] = pooled(ctx, "gm_V" + std::to_string(j), d, n, capk);
+  uint64_t seed = o.seed;
+  auto apply_shift = [&](const tt_tensor* v, tt_tensor* out) {
+    // out <- T[v - c L v]
+    apply_any(ctx, op, v, ab, o.apply_mode, o.sketch_rank, seed, o.precision);
+    seed += 0x9E3779B97F4A7C15ull;
+    ++res.applications;
+    sum_round(ctx, {Z(1), Z(-c)}, {v, ab}, out, o.krylov_eps, kr, "gm_s");
+  };
+  const double bnorm = tensor_norm(ctx, b);
+  if (bnorm == 0.0) {
+    set_zero(ctx, x);  // the solution is zero
+    res.converged = 1;
+    return res;
+  }
+  // r0 = b - (x0 - c L x0), or b for a zero guess
+  if (o.use_guess) {
+    copy_tensor(ctx, x, x0);
+    apply_shift(x0, w);
+    sum_round(ctx, {Z(1), Z(-1)}, {b, w}, V[0], o.krylov_eps, kr, "gm_s");
+  } else {
+    set_zero(ctx, x0);
+    sum_round(ctx, {Z(1)}, {b}, V[0], o.krylov_eps, kr, "gm_s");
+  }
+  const double beta = tensor_norm(ctx, V[0]);
+  std::vector<std::vector<std::complex<double>>> H(m + 1, std::vector<std::complex<double>>(m, 0.0));
+  std::vector<double> cs(m, 0.0);
+  std::vector<std::complex<double>> sn(m, 0.0), g(m + 1, 0.0);
+  g[0] = beta;
+  int k = 0;
+  res.residual = beta / bnorm;
+  if (res.residual <= o.tol) {
+    res.converged = 1;
+  } else {
+    {
+      const zc inv = Z(1.0 / beta);
+      tt_tensor* t = pooled(ctx, "gm_tmp", d, n, capk);
+      copy_tensor(ctx, V[0], t);
+      sum_tensors(ctx, 1, &inv, std::vector<const tt_tensor*>{t}.data(), V[0]);
+    }
+    for (int j = 0; j < m; ++j) {
+      apply_shift(V[j], w);
+      // two classical Gram-Schmidt passes against V_0..V_j
+      std::vector<std::complex<double>> h(j + 1, 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        std::vector<zc> coef{Z(1)};
+        std::vector<const tt_tensor*> xs{w};
+        for (int i = 0; i <= j; ++i) {
+          const zc p = dot_tensors(ctx, V[i], w);
+          h[i] += std::complex<double>(p.x, p.y);
+          coef.push_back(Z(-p.x, -p.y));
+          xs.push_back(V[i]);
+        }
+        tt_tensor* t = pooled(ctx, "gm_tmp", d, n, capk);
+        copy_tensor(ctx, w, t);
+        xs[0] = t;
+        sum_round(ctx, coef, xs, w, o.krylov_eps, kr, "gm_s");
+      }
+      const double hn = tensor_norm(ctx, w);
+      for (int i = 0; i <= j; ++i) H[i][j] = h[i];
+      H[j + 1][j] = hn;
+      for (int q = 0; q <= d; ++q) res.max_rank = std::max(res.max_rank, w->rank[q]);
+      // previous rotations, then a new one that zeroes H[j+1][j]
+      for (int i = 0; i < j; ++i) {
+        const std::complex<double> a = H[i][j], bb = H[i + 1][j];
+        H[i][j] = cs[i] * a + sn[i] * bb;
+        H[i + 1][j] = -std::conj(sn[i]) * a + cs[i] * bb;
+      }
+      {
+        const std::complex<double> a = H[j][j];
+        const double t = std::abs(a), r = std::hypot(t, hn);
+        if (t == 0.0) {
+          cs[j] = 0.0;
+          sn[j] = 1.0;
+          H[j][j] = hn;
+        } else {
+          cs[j] = t / r;
+          sn[j] = (a / t) * hn / r;
+          H[j][j] = (a / t) * r;
+        }
+        H[j + 1][j] = 0.0;
+        g[j + 1] = -std::conj(sn[j]) * g[j];
+        g[j] = cs[j] * g[j];
+      }
+      k = j + 1;
+      res.residual = std::abs(g[j + 1]) / bnorm;
+      if (res.residual <= o.tol || hn <= 1e-300) {
+        res.converged = res.residual <= o.tol;
+        if (hn <= 1e-300) res.converged = 1;  // exact breakdown: the Krylov space holds the solution
+        break;
+      }
+      const zc inv = Z(1.0 / hn);
+      sum_tensors(ctx, 1, &inv, std::vector<const tt_tensor*>{w}.data(), V[j + 1]);
+    }
+  }
+  res.iterations = k;
+  // y = H^-1 g (upper triangular k x k); x = x0 + V y
+  std::vector<std::complex<double>> y(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    std::complex<double> acc = g[i];
+    for (int j = i + 1; j < k; ++j) acc -= H[i][j] * y[j];
+    y[i] = acc / H[i][i];
+  }
+  std::vector<zc> coef{Z(1)};
+  std::vector<const tt_tensor*> xs{x0};
+  for (int i = 0; i < k; ++i) {
+    coef.push_back(Z(y[i].real(), y[i].imag()));
+    xs.push_back(V[i]);
+  }
+  tt_tensor* xs_out = pooled(ctx, "gm_xout", d, n, interior_caps(d, std::max(kr, o.rmax)));
+  sum_round(ctx, coef, xs, xs_out, std::min(o.krylov_eps, o.eps), std::max(kr, o.rmax), "gm_x");
+  round_tensor(ctx, xs_out, o.eps, o.rmax, nullptr);
+  copy_tensor(ctx, xs_out, x);
+  return res;
+}
+
+void check_solve_opts(const tt_solve_opts& o) {
+  require(o.max_iter >= 1 && o.max_iter <= 40, TT_EINVAL, "TT-GMRES: max_iter must be in 1..40");
+  require(o.tol > 0.0, TT_EINVAL, "TT-GMRES: tol must be > 0");
+  require(o.krylov_eps > 0.0, TT_EINVAL, "TT-GMRES: krylov_eps must be > 0");
+  require(o.krylov_rmax >= 1 && o.krylov_rmax <= 256, TT_EINVAL, "TT-GMRES: krylov_rmax must be in 1..256");
+  require(o.rmax >= 1 && o.eps >= 0.0, TT_EINVAL, "TT-GMRES: bad rmax or eps");
+  require(o.apply_mode == TT_APPLY_EXACT || (o.apply_mode == TT_APPLY_SKETCH && o.sketch_rank >= 1), TT_EINVAL,
+          "TT-GMRES: bad apply mode");
+  require(o.precision == TT_PREC_FP64 || o.precision == TT_PREC_BF16X3 || o.precision == TT_PREC_FP16X3, TT_EINVAL,
+          "TT-GMRES: unknown precision");
+}
+
 int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step_opts* opts, tt_step_report* rep) {
   if (!ctx || !op || !f || !opts) return TT_EINVAL;
   ABI_TRY
@@ -1064,8 +1336,24 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
   require(opts->precision == TT_PREC_FP64 || opts->precision == TT_PREC_BF16X3 || opts->precision == TT_PREC_FP16X3,
           TT_EINVAL, "tt_step: unknown precision");
   const int scheme = opts->scheme;
-  require(scheme == TT_STEP_RK4 || scheme == TT_STEP_EULER || scheme == TT_STEP_MIDPOINT, TT_EINVAL,
-          "tt_step: unknown scheme");
+  require(scheme >= TT_STEP_RK4 && scheme <= TT_STEP_IMPLICIT_MIDPOINT, TT_EINVAL, "tt_step: unknown scheme");
+  const bool implicit = scheme == TT_STEP_IMPLICIT_EULER || scheme == TT_STEP_IMPLICIT_MIDPOINT;
+  tt_solve_opts so{};
+  if (implicit) {
+    so.size = sizeof(so);
+    so.max_iter = opts->gmres_max_iter;
+    so.tol = opts->gmres_tol;
+    so.krylov_eps = 0.1 * std::min(opts->gmres_tol, opts->eps > 0.0 ? opts->eps : opts->gmres_tol);
+    so.krylov_rmax = opts->krylov_rmax > 0 ? opts->krylov_rmax : std::min(256, 2 * opts->rmax);
+    so.rmax = opts->rmax;
+    so.eps = opts->eps;
+    so.apply_mode = opts->apply_mode;
+    so.sketch_rank = opts->sketch_rank;
+    so.seed = opts->seed ^ 0x5DEECE66Dull;
+    so.precision = opts->precision;
+    so.use_guess = 1;
+    check_solve_opts(so);
+  }
   check_same_shape(op, f);
   const int d = f->d, n = f->n, rmax = opts->rmax;
   // capacities of the temporaries: stage derivatives k (apply outputs),
@@ -1075,7 +1363,8 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
     const int rk = (k == 0 || k == d) ? 1 : std::max(rmax, f->cap[k]);
     const int base = (k == 0 || k == d) ? 1 : rmax;
     // the midpoint stage input f + dt/2 k is applied untruncated
-    const int rin = (scheme == TT_STEP_MIDPOINT && k > 0 && k < d) ? rk + base : rk;
+    const bool mid = scheme == TT_STEP_MIDPOINT || scheme == TT_STEP_IMPLICIT_MIDPOINT;
+    const int rin = (mid && k > 0 && k < d) ? rk + base : rk;
     if (opts->apply_mode == TT_APPLY_EXACT)
       capk[k] = op->R[k] * rin;
     else
@@ -1087,7 +1376,9 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
                           std::to_string(opts->apply_mode) + ":" + std::to_string(opts->sketch_rank);
   StepTemps& T = step_cache()[{ctx, key}];
   if (!T.ysum) {
-    const int nk = scheme == TT_STEP_RK4 ? 4 : scheme == TT_STEP_MIDPOINT ? 2 : 1;
+    const int nk = scheme == TT_STEP_RK4                                                   ? 4
+                   : (scheme == TT_STEP_MIDPOINT || scheme == TT_STEP_IMPLICIT_MIDPOINT) ? 2
+                                                                                         : 1;
     for (int s = 0; s < nk; ++s) T.k[s] = make_tensor(ctx, d, n, capk);
     T.ysum = make_tensor(ctx, d, n, capy);
     T.fsum = make_tensor(ctx, d, n, capf);
@@ -1129,7 +1420,7 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
     const zc coef[2] = {Z(1), Z(dt)};
     sum_tensors(ctx, 2, coef, xs, T.fsum);
     stages = 1;
-  } else {
+  } else if (scheme == TT_STEP_MIDPOINT) {
     stage(0, f);
     const tt_tensor* ys[2] = {f, T.k[0]};
     const zc ycoef[2] = {Z(1), Z(0.5 * dt)};
@@ -1140,14 +1431,81 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
     const zc coef[2] = {Z(1), Z(dt)};
     sum_tensors(ctx, 2, coef, xs, T.fsum);
     stages = 2;
+  } else {
+    // implicit: the explicit step of the same kind is the initial guess
+    // (Sec. 4.1: the iteration starts from Psi_dt(G, f))
+    stage(0, f);
+    const tt_tensor* rhs = f;
+    double shift = dt;
+    if (scheme == TT_STEP_IMPLICIT_EULER) {
+      const tt_tensor* xs[2] = {f, T.k[0]};
+      const zc coef[2] = {Z(1), Z(dt)};
+      sum_tensors(ctx, 2, coef, xs, T.fsum);
+      stages = 1;
+    } else {
+      const tt_tensor* ys[2] = {f, T.k[0]};
+      const zc ycoef[2] = {Z(1), Z(0.5 * dt)};
+      sum_tensors(ctx, 2, ycoef, ys, T.ysum);
+      stage(1, T.ysum);
+      const tt_tensor* xs[2] = {f, T.k[1]};
+      const zc coef[2] = {Z(1), Z(dt)};
+      sum_tensors(ctx, 2, coef, xs, T.fsum);
+      // right-hand side T[f + dt/2 T[L f]]
+      round_tensor(ctx, T.ysum, eps, rmax, nullptr);
+      track(T.ysum);
+      rhs = T.ysum;
+      shift = 0.5 * dt;
+      stages = 2;
+    }
+    round_tensor(ctx, T.fsum, eps, rmax, nullptr);
+    const GmresResult gr = gmres_shifted(ctx, op, shift, rhs, T.fsum, so);
+    stages += gr.applications;
+    maxr = std::max(maxr, gr.max_rank);
+    if (!gr.converged)
+      fail(TT_ENOCONV, "tt_step: TT-GMRES reached relative residual " + std::to_string(gr.residual) + " after " +
+                           std::to_string(gr.iterations) + " iterations (tolerance " + std::to_string(so.tol) + ")");
   }
-  round_tensor(ctx, T.fsum, eps, rmax, nullptr);
+  if (!implicit) round_tensor(ctx, T.fsum, eps, rmax, nullptr);  // the solver's output is truncated
   track(T.fsum);
   copy_tensor(ctx, T.fsum, f);
   if (rep) {
     rep->stages = stages;
     rep->max_rank = maxr;
     for (int k = 0; k <= d; ++k) rep->ranks[k] = f->rank[k];
+  }
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_dot(tt_ctx* ctx, const tt_tensor* x, const tt_tensor* y, double* out) {
+  if (!ctx || !x || !y || !out) return TT_EINVAL;
+  ABI_TRY
+  const zc v = dot_tensors(ctx, x, y);
+  out[0] = v.x;
+  out[1] = v.y;
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_solve_shifted(tt_ctx* ctx, const tt_op* op, double c, const tt_tensor* b, tt_tensor* x,
+                     const tt_solve_opts* opts, tt_solve_report* rep) {
+  if (!ctx || !op || !b || !x || !opts) return TT_EINVAL;
+  ABI_TRY
+  require(opts->size == (int)sizeof(tt_solve_opts), TT_EINVAL, "tt_solve_opts.size mismatch");
+  check_solve_opts(*opts);
+  check_same_shape(op, b);
+  check_same_shape(op, x);
+  require(b != x, TT_EINVAL, "tt_solve_shifted: x aliases b");
+  tt_solve_opts o = *opts;
+  // the returned solution must fit x
+  for (int k = 1; k < x->d; ++k) o.rmax = std::min(o.rmax, x->cap[k]);
+  const GmresResult gr = gmres_shifted(ctx, op, c, b, x, o);
+  if (rep) {
+    rep->iterations = gr.iterations;
+    rep->converged = gr.converged;
+    rep->residual = gr.residual;
+    rep->max_rank = gr.max_rank;
+    rep->pad = 0;
   }
   return TT_OK;
   ABI_CATCH(ctx)

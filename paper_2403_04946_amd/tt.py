@@ -23,6 +23,8 @@ TT_PREC_FP16X3 = 2
 TT_STEP_RK4 = 0
 TT_STEP_EULER = 1
 TT_STEP_MIDPOINT = 2
+TT_STEP_IMPLICIT_EULER = 3
+TT_STEP_IMPLICIT_MIDPOINT = 4
 TT_ECAPACITY = -3
 ORTH = {0: "none", 1: "right", 2: "left"}
 ERRORS = {
@@ -74,6 +76,36 @@ class StepOpts(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("precision", ctypes.c_int),
         ("scheme", ctypes.c_int),
+        ("gmres_tol", ctypes.c_double),
+        ("gmres_max_iter", ctypes.c_int),
+        ("krylov_rmax", ctypes.c_int),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_int),
+        ("max_iter", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("krylov_eps", ctypes.c_double),
+        ("krylov_rmax", ctypes.c_int),
+        ("rmax", ctypes.c_int),
+        ("eps", ctypes.c_double),
+        ("apply_mode", ctypes.c_int),
+        ("sketch_rank", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("precision", ctypes.c_int),
+        ("use_guess", ctypes.c_int),
+    ]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("residual", ctypes.c_double),
+        ("max_rank", ctypes.c_int),
+        ("pad", ctypes.c_int),
     ]
 
 
@@ -124,6 +156,8 @@ _SIGS = {
     "tt_step": (I, [P, P, P, D, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport)]),
     "tt_eval": (I, [P, P, P, ctypes.c_int64, P]),
     "tt_norm": (I, [P, P, PD]),
+    "tt_dot": (I, [P, P, P, PD]),
+    "tt_solve_shifted": (I, [P, P, D, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport)]),
     "tt_qr": (I, [P, I, I, P, ctypes.c_int64, P, P]),
     "tt_zgemm_mixed": (I, [P, I, I, I, I, I, I, D, D, P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64,
                            ctypes.c_int64, D, D, P, ctypes.c_int64, ctypes.c_int64, I]),
@@ -358,9 +392,9 @@ def tt_round(ctx, x, eps, rmax=0, report=True):
 
 
 def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0,
-            scheme=TT_STEP_RK4):
+            scheme=TT_STEP_RK4, gmres_tol=1e-10, gmres_max_iter=30, krylov_rmax=0):
     o = StepOpts(ctypes.sizeof(StepOpts), int(rmax), float(eps), int(mode), int(sketch_rank), int(seed),
-                 int(precision), int(scheme))
+                 int(precision), int(scheme), float(gmres_tol), int(gmres_max_iter), int(krylov_rmax))
     rep = StepReport()
     ctx.check(lib().tt_step(ctx.h, op.h, f.h, float(dt), ctypes.byref(o), ctypes.byref(rep)))
     return {"stages": rep.stages, "max_rank": rep.max_rank, "ranks": list(rep.ranks[: f.d + 1])}
@@ -399,6 +433,26 @@ def tt_zgemm(ctx, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc
         ctx.check(lib().tt_zgemm_mixed(ctx.h, int(precision), *args))
     if ctx.torch_stream is not None:
         cur.wait_stream(ctx.torch_stream)
+
+
+def tt_dot(ctx, x, y):
+    """<x, y> = sum conj(x) y (synchronous)."""
+    out = (D * 2)()
+    ctx.check(lib().tt_dot(ctx.h, x.h, y.h, out))
+    return complex(out[0], out[1])
+
+
+def tt_solve_shifted(ctx, op, c, b, x, tol, max_iter=30, krylov_eps=None, krylov_rmax=32, rmax=None, eps=0.0,
+                     mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0, use_guess=False):
+    """TT-GMRES for (I - c L) x = b; returns the solver report as a dict."""
+    o = SolveOpts(ctypes.sizeof(SolveOpts), int(max_iter), float(tol),
+                  float(krylov_eps if krylov_eps is not None else 0.1 * tol), int(krylov_rmax),
+                  int(rmax if rmax is not None else krylov_rmax), float(eps), int(mode), int(sketch_rank), int(seed),
+                  int(precision), int(bool(use_guess)))
+    rep = SolveReport()
+    ctx.check(lib().tt_solve_shifted(ctx.h, op.h, float(c), b.h, x.h, ctypes.byref(o), ctypes.byref(rep)))
+    return {"iterations": rep.iterations, "converged": bool(rep.converged), "residual": rep.residual,
+            "max_rank": rep.max_rank}
 
 
 def tt_norm(ctx, x):
