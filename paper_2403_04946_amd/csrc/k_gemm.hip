@@ -202,33 +202,50 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
       }
 }
 
-__global__ void splitk_reduce(GemmParams p, int nsplit) {
+// C = alpha sum_s ws[s] + beta C.  SK_LANES consecutive lanes share one
+// element: lane u adds splits u, u + SK_LANES, ... (four independent sums),
+// then the lanes' sums are combined by a fixed butterfly, so the result does
+// not depend on timing; many lanes per element keep enough loads in flight
+// for the small outputs (a few thousand elements, up to 128 splits) of the
+// skinny projections.
+constexpr int SK_LANES = 8;
+__global__ __launch_bounds__(256) void splitk_reduce(GemmParams p, int nsplit) {
   const long total = (long)p.M * p.N * p.batch;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+  const int u = threadIdx.x % SK_LANES;
+  const long per_block = 256 / SK_LANES;
+  const long stride = (long)p.batch * p.M * p.N;
+  for (long e0 = blockIdx.x * per_block; e0 < total; e0 += (long)gridDim.x * per_block) {
+    const long e = e0 + threadIdx.x / SK_LANES;
+    const bool live = e < total;
+    double pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};
+    if (live) {
+      const zc* src = p.ws + e;
+      int s = u, q = 0;
+      for (; s + 3 * SK_LANES < nsplit; s += 4 * SK_LANES) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const zc v = src[stride * (s + w * SK_LANES)];
+          pr[w] += v.x;
+          pi[w] += v.y;
+        }
+      }
+      for (; s < nsplit; s += SK_LANES, ++q) {
+        const zc v = src[stride * s];
+        pr[q] += v.x;
+        pi[q] += v.y;
+      }
+    }
+    double re = (pr[0] + pr[1]) + (pr[2] + pr[3]);
+    double im = (pi[0] + pi[1]) + (pi[2] + pi[3]);
+#pragma unroll
+    for (int off = 1; off < SK_LANES; off <<= 1) {
+      re += __shfl_xor(re, off, 64);
+      im += __shfl_xor(im, off, 64);
+    }
+    if (!live || u != 0) continue;
     const int bz = (int)(e / ((long)p.M * p.N));
     const long mn = e - (long)bz * p.M * p.N;
     const int n = (int)(mn / p.M), m = (int)(mn - (long)n * p.M);
-    // eight independent partial sums keep eight loads in flight; they are
-    // combined in a fixed order, so the result does not depend on timing
-    const long stride = (long)p.batch * p.M * p.N;
-    const zc* src = p.ws + (long)bz * p.M * p.N + mn;
-    double pr[8] = {0, 0, 0, 0, 0, 0, 0, 0}, pi[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int s = 0;
-    for (; s + 8 <= nsplit; s += 8) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const zc v = src[stride * (s + u)];
-        pr[u] += v.x;
-        pi[u] += v.y;
-      }
-    }
-    for (int u = 0; s < nsplit; ++s, ++u) {
-      const zc v = src[stride * s];
-      pr[u] += v.x;
-      pi[u] += v.y;
-    }
-    const double re = ((pr[0] + pr[1]) + (pr[2] + pr[3])) + ((pr[4] + pr[5]) + (pr[6] + pr[7]));
-    const double im = ((pi[0] + pi[1]) + (pi[2] + pi[3])) + ((pi[4] + pi[5]) + (pi[6] + pi[7]));
     zc* C = p.C + p.sC * (long)bz;
     zc out = make_double2(p.alpha.x * re - p.alpha.y * im, p.alpha.x * im + p.alpha.y * re);
     const long off = m + p.ldc * (long)n;
@@ -250,7 +267,7 @@ void splitk_finish(tt_ctx* ctx, int M, int N, int batch, int nsplit, zc* ws, zc 
   p.C = C; p.ldc = ldc; p.sC = strideC;
   p.alpha = alpha; p.beta = beta; p.batch = batch; p.ws = ws;
   const long total = (long)M * N * batch;
-  const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+  const int blocks = (int)std::min<long>((total + 256 / SK_LANES - 1) / (256 / SK_LANES), 8192);
   KTimer kt(ctx, "zgemm_reduce", 0.0, 16.0 * (double)total * (nsplit + 1 + (beta.x != 0.0 || beta.y != 0.0)));
   hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, ctx->stream, p, nsplit);
 }
