@@ -356,6 +356,11 @@ void bcgs_put_diag(tt_ctx* ctx, zc* Rd, long ldr, const zc* Rp, int nb, const in
 // trailing entries and stores row r of R, one barrier per step.  Inverse:
 // recursive doubling on diagonal blocks of size h = 1, 2, 4, 8, 16: the
 // off-diagonal block of [A B; 0 C]^{-1} is -A^{-1} (B C^{-1}).
+// Near the identity, G = I + E with every |E_ij| <= 1e-10 (the Gram matrix
+// of an already orthonormalised panel), the factor is taken in closed form:
+// R = I + U with U the upper part of E and U_ii = E_ii / 2, so that
+// R^H R = G + U^H U, and R^{-1} = I - U + U^2 - ..., both truncated after
+// the first-order term: the neglected terms are below (32e-10)^2 ~ 1e-17.
 // On return Rs holds R (zero below the diagonal and beyond nb), Ri its
 // inverse, dinv the reciprocal diagonal; dg holds the original diagonal and
 // *bad = 1 when a pivot falls below tau times it (bad may be null).  Gs and
@@ -364,7 +369,44 @@ __device__ void block_chol_inv(zc (*Gs)[PT_COLS + 1], zc (*Rs)[PT_COLS + 1], zc 
                                zc (*T)[PT_COLS + 1], const double* dg, int nb, double tau, int* bad,
                                double* dinv) {
   __shared__ double piv[PT_COLS][2];  // 1 / d and 1 / sqrt(d) of step r
+  __shared__ double emax[16];
   const int t = threadIdx.x, i = t & 31, j = t >> 5;
+  {
+    // largest entry of G - I, over the workgroup
+    double e = 0.0;
+    if (i < nb && j < nb) {
+      const zc g = Gs[i][j];
+      e = fmax(fabs(g.x - (i == j ? 1.0 : 0.0)), fabs(g.y));
+    }
+    for (int off = 32; off > 0; off >>= 1) e = fmax(e, __shfl_xor(e, off, 64));
+    if ((t & 63) == 0) emax[t >> 6] = e;
+    __syncthreads();
+    double em = 0.0;
+    for (int w = 0; w < 16; ++w) em = fmax(em, emax[w]);
+    if (em <= 1e-10) {
+      zc rv = make_double2(0.0, 0.0), iv = make_double2(0.0, 0.0);
+      if (i < nb && j < nb) {
+        const zc g = Gs[i][j];
+        if (i < j) {
+          rv = g;
+          iv = make_double2(-g.x, -g.y);
+        } else if (i == j) {
+          const double h = 0.5 * (g.x - 1.0);
+          rv = make_double2(1.0 + h, 0.0);
+          iv = make_double2(1.0 - h, 0.0);
+        }
+      } else if (i == j) {  // identity beyond nb
+        rv = make_double2(1.0, 0.0);
+        iv = rv;
+      }
+      Rs[i][j] = rv;
+      Ri[i][j] = iv;
+      if (t < PT_COLS) dinv[t] = (t < nb) ? 1.0 - 0.5 * (Gs[t][t].x - 1.0) : 1.0;
+      // pivots are within 1e-10 of 1: the pivot test passes for tau <= 0.5
+      __syncthreads();
+      return;
+    }
+  }
   Rs[i][j] = make_double2(0.0, 0.0);
   // the pivot of step r is prepared by the thread that last updated it
   auto pivot = [&](int r, double d) {
