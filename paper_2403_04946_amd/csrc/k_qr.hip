@@ -545,14 +545,14 @@ __global__ __launch_bounds__(1024) void bcgs_pip_kernel(const zc* __restrict__ W
 
 // One Cholesky QR pass on the m x nb panel Y given its Gram matrix G
 // (ld nb): every workgroup factors G = R^H R and inverts R itself (nb <= 32,
-// cheap) and replaces its 256 rows by Y R^{-1}; workgroup 0 also writes
-// Rout = R Rprev (R without Rprev) and raises *bad when a pivot falls below
-// tau times its diagonal entry.  The rows are fetched into registers before
-// the factorisation and multiplied in two 128-row tiles through LDS.
+// cheap) and replaces its rpw <= 256 rows by Y R^{-1}; workgroup 0 also
+// writes Rout = R Rprev (R without Rprev) and raises *bad when a pivot falls
+// below tau times its diagonal entry.  The rows are fetched into registers
+// before the factorisation and multiplied in 128-row tiles through LDS.
 __global__ __launch_bounds__(1024) void chol_solve_kernel(zc* __restrict__ Y, long ldy, int m, int nb,
                                                          const zc* __restrict__ G, double tau,
                                                          const zc* __restrict__ Rprev, zc* __restrict__ Rout,
-                                                         int* __restrict__ bad) {
+                                                         int* __restrict__ bad, int rpw) {
   __shared__ zc Gs[PT_COLS][PT_COLS + 1];
   __shared__ zc Rs[PT_COLS][PT_COLS + 1];
   __shared__ zc Ri[PT_COLS][PT_COLS + 1];
@@ -561,8 +561,8 @@ __global__ __launch_bounds__(1024) void chol_solve_kernel(zc* __restrict__ Y, lo
   __shared__ double dg[PT_COLS], dinv[PT_COLS];
   const int t = threadIdx.x;
   const int i = t & 31, j = t >> 5;
-  const long row0 = (long)blockIdx.x * 256;
-  const int rows = (m - row0 < 256) ? (int)(m - row0) : 256;
+  const long row0 = (long)blockIdx.x * rpw;
+  const int rows = (m - row0 < rpw) ? (int)(m - row0) : rpw;
   // thread t holds row t % 256 of the block, columns t / 256 + 4 u
   const int rr = t & 255, cg = t >> 8;
   zc y[8];
@@ -623,8 +623,11 @@ void chol_solve(tt_ctx* ctx, zc* Y, long ldy, int m, int nb, const zc* G, double
                 int* bad) {
   if (nb > PT_COLS) fail(TT_EINVAL, "chol_solve: panel too wide");
   KTimer kt(ctx, "chol_solve", 4.0 * (double)m * nb * nb, 32.0 * (double)m * nb);
-  hipLaunchKernelGGL(chol_solve_kernel, dim3((m + 255) / 256), dim3(1024), 0, ctx->stream, Y, ldy, m, nb, G, tau,
-                     Rprev, Rout, bad);
+  // rows per workgroup: 64 .. 256 in steps of 64, so that the launch fills
+  // the chip in one wave (every workgroup factors G itself)
+  const int rpw = (int)std::min<long>(256, 64 * ((m + 64L * 256 - 1) / (64L * 256)));
+  hipLaunchKernelGGL(chol_solve_kernel, dim3((m + rpw - 1) / rpw), dim3(1024), 0, ctx->stream, Y, ldy, m, nb, G,
+                     tau, Rprev, Rout, bad, rpw);
   TTF_HIP(hipGetLastError());
 }
 
