@@ -44,6 +44,7 @@ PEAK_F64_TFLOPS = 78.6  # FP64: matrix cores and vector units alike
 PEAK_F16_TFLOPS = 2500.0  # dense fp16 / bf16 matrix cores
 PEAK_HBM_GBS = 8000.0
 GATE = 1e-5
+PROFILE_EVERY = 4  # one in four launches of the roofline kernel is event-timed
 PRECISIONS = {"fp64": 0, "bf16x3": 1, "fp16x3": 2}
 
 
@@ -82,7 +83,8 @@ def cpu_baseline(seconds_target=20.0):
 
 # kernel classes that are one kernel each, with the resource that bounds them
 KERNEL_BOUND = {
-    "zgemm": "mfma", "zgemm_fp16x3": "mfma", "zgemm_bf16x3": "mfma", "chol_solve": "alu", "pt_leaf": "alu", "pt_assemble": "hbm", "panel_trmm": "hbm", "bcgs_pip": "alu",
+    "zgemm": "mfma", "zgemm_fp16x3": "mfma", "zgemm_bf16x3": "mfma", "chol_solve": "alu", "pt_leaf": "alu",
+    "jacobi_cross": "alu", "jacobi_circle": "alu", "pt_assemble": "hbm", "panel_trmm": "hbm", "bcgs_pip": "alu",
     "gather_left": "hbm", "gather_right": "hbm", "zgemm_reduce": "hbm", "concat": "hbm",
 }
 
@@ -209,6 +211,7 @@ def main():
     ap.add_argument("--error-steps", type=int, default=2,
                     help="trajectory steps from the initial condition in the error report")
     ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--no-error-report", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -256,6 +259,7 @@ def main():
     dom = dominant(breakdown) if breakdown else "zgemm"
     ctx.reset_stats()
     ctx.set_profile_filter(dom)
+    ctx.set_profile_sampling(PROFILE_EVERY)
     ctx.set_profiling(True)
     stream = ctx.torch_stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -273,6 +277,7 @@ def main():
     kd = ctx.stats(dom)
     ctx.set_profiling(False)
     ctx.set_profile_filter(None)
+    ctx.set_profile_sampling(1)
     assert torch.isfinite(out.real).all() and torch.isfinite(out.imag).all()
 
     stages = 4 * args.steps
@@ -299,7 +304,7 @@ def main():
                     "speedup_of_selected_form": (stages / (ms / 1e3)) / (stages / (ms64 / 1e3))}
         print(f"bench: FP64 reference, {args.steps} timed steps done", file=sys.stderr, flush=True)
     errors = None
-    if prec != 0:
+    if prec != 0 and not args.no_error_report:
         errors = error_report(ctx, tt, op, f0, prec, ell, args.error_steps)
         print("bench: error report done", file=sys.stderr, flush=True)
     roof = roofline(dom, kd)

@@ -117,6 +117,12 @@ int tt_ctx_set_profiling(tt_ctx* ctx, int on);
 /* Restrict event timing to one kernel class (NULL or "" = all classes), so
  * that a timed run pays the event overhead of that class only. */
 int tt_ctx_set_profile_filter(tt_ctx* ctx, const char* kernel);
+
+/* With a profile filter set, time only one in `every` launches of the
+ * filtered class (a uniform sample: its statistics report the sampled
+ * launches, so averages stay unbiased while the event overhead falls).
+ * every >= 1; 1 (the default) times every launch. */
+int tt_ctx_set_profile_sampling(tt_ctx* ctx, int every);
 int tt_ctx_reset_stats(tt_ctx* ctx);
 int tt_ctx_get_stats(tt_ctx* ctx, const char* kernel, double* total_ms,
                      double* flops, double* bytes, long long* launches);

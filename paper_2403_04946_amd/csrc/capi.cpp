@@ -17,9 +17,11 @@ void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) fail(TT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-KTimer::KTimer(tt_ctx* c, const char* nm, double fl, double by) : ctx(c), name(nm), flops(fl), bytes(by) {
+KTimer::KTimer(tt_ctx* c, const char* nm, double fl, double by, bool kernel_events)
+    : ctx(c), name(nm), flops(fl), bytes(by), kernel(kernel_events) {
   if (!ctx || !ctx->profiling) return;
   if (!ctx->profile_only.empty() && ctx->profile_only != nm) return;
+  if (ctx->profile_every > 1 && (ctx->profile_seen++ % ctx->profile_every) != 0) return;
   auto take = [&]() {
     hipEvent_t e;
     if (!ctx->free_events.empty()) {
@@ -32,12 +34,12 @@ KTimer::KTimer(tt_ctx* c, const char* nm, double fl, double by) : ctx(c), name(n
   };
   a = take();
   b = take();
-  TTF_HIP(hipEventRecord(a, ctx->stream));
+  if (!kernel) TTF_HIP(hipEventRecord(a, ctx->stream));
 }
 
 KTimer::~KTimer() {
   if (!a) return;
-  (void)hipEventRecord(b, ctx->stream);
+  if (!kernel) (void)hipEventRecord(b, ctx->stream);
   ctx->pending.push_back({name, a, b, flops, bytes});
 }
 
@@ -82,7 +84,13 @@ void tt_ctx::resolve_stats() {
   for (auto& p : pending) {
     float ms = 0;
     TTF_HIP(hipEventSynchronize(p.b));
-    TTF_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) {
+      // a timed launch that did not happen (an error path): nothing to add
+      (void)hipGetLastError();
+      free_events.push_back(p.a);
+      free_events.push_back(p.b);
+      continue;
+    }
     Stat& s = stats[p.name];
     s.ms += ms;
     s.flops += p.flops;
@@ -838,6 +846,16 @@ int tt_ctx_set_profile_filter(tt_ctx* ctx, const char* kernel) {
   ABI_TRY
   ctx->sync();
   ctx->profile_only = kernel ? kernel : "";
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_ctx_set_profile_sampling(tt_ctx* ctx, int every) {
+  if (!ctx || every < 1) return TT_EINVAL;
+  ABI_TRY
+  ctx->sync();
+  ctx->profile_every = every;
+  ctx->profile_seen = 0;
   return TT_OK;
   ABI_CATCH(ctx)
 }

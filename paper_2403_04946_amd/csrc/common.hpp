@@ -1,6 +1,7 @@
 // Internal declarations of the tensor-train solver library (not installed).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -69,6 +70,8 @@ struct tt_ctx {
   bool profile_shapes = false;  // also key GEMM timings by shape
   long long qr_fallbacks = 0;   // QRs redone in the robust form
   std::string profile_only;     // when set, only this kernel class is timed
+  int profile_every = 1;        // time one in this many launches of it
+  long long profile_seen = 0;
   struct Stat {
     double ms = 0, flops = 0, bytes = 0;
     long long n = 0;
@@ -134,9 +137,23 @@ struct KTimer {
   const char* name;
   double flops, bytes;
   hipEvent_t a = nullptr, b = nullptr;
-  KTimer(tt_ctx* c, const char* nm, double fl, double by);
+  bool kernel = false;  // the events are taken by one kernel dispatch itself
+  // kernel_events: the timed region is exactly one launch made with
+  // TTF_LAUNCH, whose dispatch records the start and stop events (kernel
+  // execution time, without the dispatch gap a stream event would include)
+  KTimer(tt_ctx* c, const char* nm, double fl, double by, bool kernel_events = false);
   ~KTimer();
 };
+
+// hipLaunchKernelGGL, or hipExtLaunchKernelGGL with the events of an active
+// kernel-event timer
+#define TTF_LAUNCH(kt, kfn, grid, block, shmem, stream, ...)                                    \
+  do {                                                                                          \
+    if ((kt).a && (kt).kernel)                                                                  \
+      hipExtLaunchKernelGGL(kfn, grid, block, shmem, stream, (kt).a, (kt).b, 0, __VA_ARGS__);   \
+    else                                                                                        \
+      hipLaunchKernelGGL(kfn, grid, block, shmem, stream, __VA_ARGS__);                         \
+  } while (0)
 
 // ------------------------------------------------------- kernel launchers
 // op codes for GEMM operands

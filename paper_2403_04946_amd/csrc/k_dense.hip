@@ -314,15 +314,31 @@ template <int RPL, int GS>
 void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int round, int inner_max, int sweep,
                        int* rot, double tol, const double* fro2) {
   const size_t slot = sizeof(zc) * GS * RPL;
+  // algorithmic work: a column pair that meets costs 16 m flops for its
+  // three inner products and 24 m for the rotation (counted as applied);
+  // bytes: the columns read and written once
+  const double pair = 40.0 * m;
+  double pairs, cols;
+  if (kind == 0) {
+    pairs = 0.5 * k * (k - 1) * inner_max;
+    cols = k;
+  } else if (kind == 1) {
+    pairs = 0.5 * JB_COLS * (JB_COLS - 1) * ((k + JB_COLS - 1) / JB_COLS);
+    cols = k;
+  } else {
+    pairs = (double)JB_COLS * JB_COLS * (P / 2);
+    cols = 2.0 * JB_COLS * (P / 2);
+  }
+  KTimer kt(ctx, kind == 2 ? "jacobi_cross" : "jacobi_circle", pair * pairs, 2.0 * 16.0 * m * cols, true);
   if (kind == 0)  // whole matrix (k <= 32) in one workgroup
-    hipLaunchKernelGGL((jacobi_circle_kernel<RPL, 16, GS>), dim3(1), dim3(16 * GS), 16 * slot, ctx->stream, B, m, k,
-                       inner_max, sweep, rot, tol, fro2);
+    TTF_LAUNCH(kt, (jacobi_circle_kernel<RPL, 16, GS>), dim3(1), dim3(16 * GS), 16 * slot, ctx->stream, B, m, k,
+               inner_max, sweep, rot, tol, fro2);
   else if (kind == 1)  // every block of JB_COLS columns on its own
-    hipLaunchKernelGGL((jacobi_circle_kernel<RPL, JB_COLS / 2, GS>), dim3((k + JB_COLS - 1) / JB_COLS),
-                       dim3(JB_COLS / 2 * GS), JB_COLS / 2 * slot, ctx->stream, B, m, k, 1, sweep, rot, tol, fro2);
+    TTF_LAUNCH(kt, (jacobi_circle_kernel<RPL, JB_COLS / 2, GS>), dim3((k + JB_COLS - 1) / JB_COLS),
+               dim3(JB_COLS / 2 * GS), JB_COLS / 2 * slot, ctx->stream, B, m, k, 1, sweep, rot, tol, fro2);
   else
-    hipLaunchKernelGGL((jacobi_cross_kernel<RPL, GS, JB_COLS>), dim3(P / 2), dim3(JB_COLS * GS), JB_COLS * slot,
-                       ctx->stream, B, m, k, P, round, sweep, rot, tol, fro2);
+    TTF_LAUNCH(kt, (jacobi_cross_kernel<RPL, GS, JB_COLS>), dim3(P / 2), dim3(JB_COLS * GS), JB_COLS * slot,
+               ctx->stream, B, m, k, P, round, sweep, rot, tol, fro2);
   TTF_HIP(hipGetLastError());
 }
 

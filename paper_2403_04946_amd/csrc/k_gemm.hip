@@ -273,11 +273,11 @@ void splitk_finish(tt_ctx* ctx, int M, int N, int batch, int nsplit, zc* ws, zc 
 }
 
 template <int BM, int BN>
-void launch_tile(int opA, int opB, dim3 grid, hipStream_t st, const GemmParams& p) {
-#define TTF_GEMM_CASE(OA, OB)                                                        \
-  if (opA == OA && opB == OB) {                                                      \
-    hipLaunchKernelGGL((zgemm_kernel<OA, OB, BM, BN>), grid, dim3(256), 0, st, p); \
-    return;                                                                          \
+void launch_tile(KTimer& kt, int opA, int opB, dim3 grid, hipStream_t st, const GemmParams& p) {
+#define TTF_GEMM_CASE(OA, OB)                                                    \
+  if (opA == OA && opB == OB) {                                                  \
+    TTF_LAUNCH(kt, (zgemm_kernel<OA, OB, BM, BN>), grid, dim3(256), 0, st, p); \
+    return;                                                                      \
   }
   TTF_GEMM_CASE(OPN, OPN)
   TTF_GEMM_CASE(OPN, OPT)
@@ -354,18 +354,18 @@ void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc 
     }
     KTimer kt2(ctx->profile_shapes ? ctx : nullptr, shape.c_str(), flops, bytes);
     {
-      KTimer kt(ctx, "zgemm", flops, bytes);
+      KTimer kt(ctx, "zgemm", flops, bytes, true);
       const dim3 grid(gx, gy, batch * nsplit);
       if (bm == 64 && bn == 64)
-        launch_tile<64, 64>(opA, opB, grid, ctx->stream, p);
+        launch_tile<64, 64>(kt, opA, opB, grid, ctx->stream, p);
       else if (bm == 128)
-        launch_tile<128, 32>(opA, opB, grid, ctx->stream, p);
+        launch_tile<128, 32>(kt, opA, opB, grid, ctx->stream, p);
       else if (bm == 64)
-        launch_tile<64, 32>(opA, opB, grid, ctx->stream, p);
+        launch_tile<64, 32>(kt, opA, opB, grid, ctx->stream, p);
       else if (bn == 32)
-        launch_tile<32, 32>(opA, opB, grid, ctx->stream, p);
+        launch_tile<32, 32>(kt, opA, opB, grid, ctx->stream, p);
       else
-        launch_tile<32, 64>(opA, opB, grid, ctx->stream, p);
+        launch_tile<32, 64>(kt, opA, opB, grid, ctx->stream, p);
     }
     if (nsplit > 1) splitk_finish(ctx, M, N, batch, nsplit, p.ws, alpha, beta, C, ldc, strideC);
   }

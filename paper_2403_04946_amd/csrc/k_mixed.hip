@@ -339,11 +339,11 @@ __global__ __launch_bounds__(256, 2) void zgemm_planes_kernel(PlaneGemm p) {
 }
 
 template <int TI, int TJ>
-static void launch_planes(int fmt, dim3 grid, hipStream_t st, const PlaneGemm& p) {
+static void launch_planes(KTimer& kt, int fmt, dim3 grid, hipStream_t st, const PlaneGemm& p) {
   if (fmt == TT_PREC_BF16X3)
-    hipLaunchKernelGGL((zgemm_planes_kernel<TT_PREC_BF16X3, TI, TJ>), grid, dim3(256), 0, st, p);
+    TTF_LAUNCH(kt, (zgemm_planes_kernel<TT_PREC_BF16X3, TI, TJ>), grid, dim3(256), 0, st, p);
   else
-    hipLaunchKernelGGL((zgemm_planes_kernel<TT_PREC_FP16X3, TI, TJ>), grid, dim3(256), 0, st, p);
+    TTF_LAUNCH(kt, (zgemm_planes_kernel<TT_PREC_FP16X3, TI, TJ>), grid, dim3(256), 0, st, p);
 }
 
 void zgemm_split(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc alpha, const zc* A, long lda,
@@ -400,16 +400,16 @@ void zgemm_split(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc
     {
       // the class counts the 16-bit products it executes (three per real
       // product) against the 16-bit matrix-core peak
-      KTimer kt(ctx, fmt == TT_PREC_BF16X3 ? "zgemm_bf16x3" : "zgemm_fp16x3", 3.0 * flops, bytes);
+      KTimer kt(ctx, fmt == TT_PREC_BF16X3 ? "zgemm_bf16x3" : "zgemm_fp16x3", 3.0 * flops, bytes, true);
       const dim3 grid(gx, gy, batch * nsplit);
       if (ti == 2 && tj == 2)
-        launch_planes<2, 2>(fmt, grid, ctx->stream, p);
+        launch_planes<2, 2>(kt, fmt, grid, ctx->stream, p);
       else if (ti == 1 && tj == 2)
-        launch_planes<1, 2>(fmt, grid, ctx->stream, p);
+        launch_planes<1, 2>(kt, fmt, grid, ctx->stream, p);
       else if (ti == 2)
-        launch_planes<2, 1>(fmt, grid, ctx->stream, p);
+        launch_planes<2, 1>(kt, fmt, grid, ctx->stream, p);
       else
-        launch_planes<1, 1>(fmt, grid, ctx->stream, p);
+        launch_planes<1, 1>(kt, fmt, grid, ctx->stream, p);
     }
     if (nsplit > 1) splitk_finish(ctx, M, N, batch, nsplit, p.ws, alpha, beta, C, ldc, strideC);
   }

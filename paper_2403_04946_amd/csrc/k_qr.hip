@@ -622,12 +622,12 @@ __global__ __launch_bounds__(1024) void chol_solve_kernel(zc* __restrict__ Y, lo
 void chol_solve(tt_ctx* ctx, zc* Y, long ldy, int m, int nb, const zc* G, double tau, const zc* Rprev, zc* Rout,
                 int* bad) {
   if (nb > PT_COLS) fail(TT_EINVAL, "chol_solve: panel too wide");
-  KTimer kt(ctx, "chol_solve", 4.0 * (double)m * nb * nb, 32.0 * (double)m * nb);
+  KTimer kt(ctx, "chol_solve", 4.0 * (double)m * nb * nb, 32.0 * (double)m * nb, true);
   // rows per workgroup: 64 .. 256 in steps of 64, so that the launch fills
   // the chip in one wave (every workgroup factors G itself)
   const int rpw = (int)std::min<long>(256, 64 * ((m + 64L * 256 - 1) / (64L * 256)));
-  hipLaunchKernelGGL(chol_solve_kernel, dim3((m + rpw - 1) / rpw), dim3(1024), 0, ctx->stream, Y, ldy, m, nb, G,
-                     tau, Rprev, Rout, bad, rpw);
+  TTF_LAUNCH(kt, chol_solve_kernel, dim3((m + rpw - 1) / rpw), dim3(1024), 0, ctx->stream, Y, ldy, m, nb, G, tau,
+             Rprev, Rout, bad, rpw);
   TTF_HIP(hipGetLastError());
 }
 

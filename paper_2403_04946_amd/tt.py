@@ -156,6 +156,7 @@ _SIGS = {
     "tt_step": (I, [P, P, P, D, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport)]),
     "tt_eval": (I, [P, P, P, ctypes.c_int64, P]),
     "tt_norm": (I, [P, P, PD]),
+    "tt_ctx_set_profile_sampling": (I, [P, I]),
     "tt_dot": (I, [P, P, P, PD]),
     "tt_solve_shifted": (I, [P, P, D, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport)]),
     "tt_qr": (I, [P, I, I, P, ctypes.c_int64, P, P]),
@@ -228,6 +229,9 @@ class Context:
         """Event timing per kernel class; with shapes=True every GEMM is also
         recorded under "zgemm:<ops>:MxNxKxbatch"."""
         self.check(lib().tt_ctx_set_profiling(self.h, (2 if shapes else 1) if on else 0))
+
+    def set_profile_sampling(self, every):
+        self.check(lib().tt_ctx_set_profile_sampling(self.h, int(every)))
 
     def set_profile_filter(self, kernel=None):
         """Time only the given kernel class (None: all classes)."""
