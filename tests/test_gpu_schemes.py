@@ -127,7 +127,7 @@ def test_unknown_scheme_is_rejected(ctx):
     mu, sig = inputs.ic_params(3, 0)
     f.set_gaussian(mu, sig, L)
     with pytest.raises(tt.TTError):
-        tt.tt_step(ctx, op, f, 1e-3, 4, 1e-8, tt.TT_APPLY_EXACT, 0, 1, scheme=3)
+        tt.tt_step(ctx, op, f, 1e-3, 4, 1e-8, tt.TT_APPLY_EXACT, 0, 1, scheme=9)
     f.close()
     op.close()
 
