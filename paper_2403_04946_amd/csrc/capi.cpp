@@ -236,11 +236,20 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* ba
 // Cholesky QR twice, level 1 by the Householder TSQR, both finishing with
 // the Pythagorean second pass; level 2 uses the Householder TSQR for both
 // passes and cannot fail.
+// With deferred_bad, only the fast form runs and its flag is or-ed into
+// *deferred_bad (device) without a host synchronisation: the caller reads
+// it at its next synchronisation and redoes the work from start_level 1.
 template <class Load>
-void qr_checked(tt_ctx* ctx, int m, int k, zc* q, zc* r, Load load) {
+void qr_checked(tt_ctx* ctx, int m, int k, zc* q, zc* r, Load load, int* deferred_bad = nullptr,
+                int start_level = 0) {
+  if (deferred_bad) {
+    load();
+    bcgs_qr_inplace(ctx, m, k, q, r, 0, deferred_bad);
+    return;
+  }
   int* bad = (int*)ctx->get_ws("qr_bad", 64);
   int* h = (int*)ctx->host_scratch(64);
-  for (int level = 0; level < 2; ++level) {
+  for (int level = start_level; level < 2; ++level) {
     zero_ints(ctx, bad, 1);
     load();
     bcgs_qr_inplace(ctx, m, k, q, r, level, bad);
@@ -254,14 +263,16 @@ void qr_checked(tt_ctx* ctx, int m, int k, zc* q, zc* r, Load load) {
 }
 
 // QR of A (m x k, ld lda, m >= k): Q (m x k, ld m), R (k x k, ld k).
-void tsqr(tt_ctx* ctx, int m, int k, const zc* a, long lda, zc* q, zc* r) {
-  qr_checked(ctx, m, k, q, r, [&]() { copy_matrix(ctx, a, lda, q, m, m, k); });
+void tsqr(tt_ctx* ctx, int m, int k, const zc* a, long lda, zc* q, zc* r, int* deferred_bad = nullptr,
+          int start_level = 0) {
+  qr_checked(ctx, m, k, q, r, [&]() { copy_matrix(ctx, a, lda, q, m, m, k); }, deferred_bad, start_level);
 }
 
 // LQ of A (k x m, ld lda, k <= m): A = R^H Qt^H with Qt (m x k, ld m) having
 // orthonormal columns; returns Qt and R (k x k upper).
-void tsqr_lq(tt_ctx* ctx, int k, int m, const zc* a, long lda, zc* qt, zc* r) {
-  qr_checked(ctx, m, k, qt, r, [&]() { conj_transpose(ctx, a, lda, qt, m, k, m); });
+void tsqr_lq(tt_ctx* ctx, int k, int m, const zc* a, long lda, zc* qt, zc* r, int* deferred_bad = nullptr,
+             int start_level = 0) {
+  qr_checked(ctx, m, k, qt, r, [&]() { conj_transpose(ctx, a, lda, qt, m, k, m); }, deferred_bad, start_level);
 }
 
 int bounded_pow(int n, int e, int cap) {
@@ -363,24 +374,41 @@ void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_repo
     zc* carry = (zc*)ctx->get_ws("p2_carry", sizeof(zc) * (size_t)sq * k);
     zc* tmp = (zc*)ctx->get_ws("p2_tmp", sizeof(zc) * (size_t)sq * n * rr);
     const zc* V = x->core[c];
-    if (m >= k) {
-      // V = Q R and R = R2^H Q2^H: R and B = R2^H share their left singular
-      // vectors; one-sided Jacobi converges in far fewer sweeps on the
-      // lower-triangular B than on R itself
-      tsqr(ctx, m, k, V, m, Q, R);
-      zc* Q2 = (zc*)ctx->get_ws("p2_q2", sizeof(zc) * (size_t)k * k);
-      zc* R2 = (zc*)ctx->get_ws("p2_r2", sizeof(zc) * (size_t)k * k);
-      tsqr_lq(ctx, k, k, R, k, Q2, R2);
-      conj_transpose(ctx, R2, k, B, k, k, k);
-    } else {
-      // V^H (k x m) = Q' R' ; SVD of R'^H gives the left vectors of V
-      tsqr_lq(ctx, m, k, V, m, Q, R);
-      conj_transpose(ctx, R, m, B, m, m, m);  // B = R'^H
-    }
-    jacobi_svd(ctx, sq, sq, B, U, sig, sw);
+    int* qbad = (int*)(sig + sq + 4);  // fast-form QR flag, read with sigma
+    // the factorisations only read the core, so a failed fast form is
+    // redone from the start (deferred: no synchronisation of its own)
+    auto factor = [&](bool fast) {
+      int* db = fast ? qbad : nullptr;
+      const int lvl = fast ? 0 : 1;
+      if (fast) zero_ints(ctx, qbad, 1);
+      if (m >= k) {
+        // V = Q R and R = R2^H Q2^H: R and B = R2^H share their left
+        // singular vectors; one-sided Jacobi converges in far fewer sweeps
+        // on the lower-triangular B than on R itself
+        tsqr(ctx, m, k, V, m, Q, R, db, lvl);
+        zc* Q2 = (zc*)ctx->get_ws("p2_q2", sizeof(zc) * (size_t)k * k);
+        zc* R2 = (zc*)ctx->get_ws("p2_r2", sizeof(zc) * (size_t)k * k);
+        tsqr_lq(ctx, k, k, R, k, Q2, R2, db, lvl);
+        conj_transpose(ctx, R2, k, B, k, k, k);
+      } else {
+        // V^H (k x m) = Q' R' ; SVD of R'^H gives the left vectors of V
+        tsqr_lq(ctx, m, k, V, m, Q, R, db, lvl);
+        conj_transpose(ctx, R, m, B, m, m, m);  // B = R'^H
+      }
+      jacobi_svd(ctx, sq, sq, B, U, sig, sw);
+    };
     double* h = (double*)ctx->host_scratch(sizeof(double) * (sq + 8));
+    factor(true);
     TTF_HIP(hipMemcpyAsync(h, sig, sizeof(double) * (sq + 8), hipMemcpyDeviceToHost, ctx->stream));
     TTF_HIP(hipStreamSynchronize(ctx->stream));
+    int qb = 0;
+    std::memcpy(&qb, (char*)(h + sq + 4), sizeof(int));
+    if (qb) {
+      ctx->qr_fallbacks += 1;
+      factor(false);
+      TTF_HIP(hipMemcpyAsync(h, sig, sizeof(double) * (sq + 8), hipMemcpyDeviceToHost, ctx->stream));
+      TTF_HIP(hipStreamSynchronize(ctx->stream));
+    }
     std::vector<double> s(h, h + sq);
     for (double v : s)
       if (!std::isfinite(v)) fail(TT_ENONFINITE, "non-finite singular value in tt_round");

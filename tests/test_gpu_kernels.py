@@ -186,6 +186,30 @@ def test_round_rank_deficient_inputs(ctx):
     assert np.abs(full(z)).max() < 1e-12 * np.abs(fullgrid.tt_to_full(x)).max()
 
 
+def test_round_redoes_a_failed_fast_factorisation(ctx):
+    """Two columns of the first core that differ by 1e-9: the Cholesky QR
+    fast form of the truncation sweep fails its pivot test; the bond is
+    factored again in the robust form (the fast form's flag is read with the
+    singular values) and the result is the oracle's rounding."""
+    rng = np.random.default_rng(21)
+    d, n = 3, 64
+    x = inputs.random_tt(d, n, [1, 40, 8, 1], 11)
+    c0 = x[0].copy()
+    c0[0, :, 5] = c0[0, :, 4] + 1e-9 * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    x[0] = c0
+    t = upload(ctx, x, caps=40)
+    ctx.reset_stats()
+    tt.tt_round(ctx, t, 1e-13, 0)
+    fallbacks = ctx.dump_stats()["qr_fallbacks"]["launches"]
+    ref, _ = tt_ref.tt_round(x, 1e-13, None)
+    assert fallbacks >= 1
+    assert t.ranks() == tt_ref.tt_ranks(ref)
+    assert rel(full(t), fullgrid.tt_to_full(ref)) < 1e-10
+    for c in t.get_cores()[:-1]:
+        v = c.reshape(-1, c.shape[2], order="F")
+        assert np.abs(v.conj().T @ v - np.eye(v.shape[1])).max() < 1e-12
+
+
 def test_round_wide_first_core(ctx):
     # first-core rank above n: the phase-2 factor is wide
     x = tt_ref.tt_add(inputs.random_tt(3, 4, 5, 8), inputs.random_tt(3, 4, 5, 9))
