@@ -65,9 +65,14 @@ def apply_along(mat, f, axis):
 
 
 class Problem:
-    """Discrete Burgers-Hopf operator on a full n^d grid."""
+    """Discrete Burgers-Hopf operator on a full n^d grid.
 
-    def __init__(self, b, dm, nu, n, length):
+    diffusion > 0 adds the numerical-diffusion stabilisation of Sec. 5.2
+    (explicit runs): kappa sum_k d^2 phi / da_k^2 with kappa = diffusion,
+    the caller choosing kappa proportional to dt (Lax-Wendroff-like)."""
+
+    def __init__(self, b, dm, nu, n, length, diffusion=0.0):
+        self.diffusion = float(diffusion)
         self.b = np.asarray(b, dtype=np.float64)
         self.dm = np.asarray(dm, dtype=np.float64)
         self.d = self.b.shape[0]
@@ -108,6 +113,9 @@ class Problem:
                 if self.dm[k, j] != 0.0:
                     inner += (self.nu * self.dm[k, j]) * gf[j]
             out += self.coord(k) * inner
+        if self.diffusion != 0.0:
+            for j in range(d):
+                out += self.diffusion * second[(j, j)]
         return out
 
 

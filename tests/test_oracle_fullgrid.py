@@ -146,6 +146,39 @@ def test_richardson_estimate_matches_exact_local_error():
     assert abs(est / true - 1.0) < 0.05, (est, true)
 
 
+def test_numerical_diffusion_term():
+    """The stabilisation term kappa sum_k d^2/da_k^2: the grid operator with
+    it equals the Kronecker assembly plus kappa sum_k L2_k, and on its own
+    (B = D = 0) its semi-discrete flow is the per-axis matrix exponential of
+    kappa L2 (a product of one-dimensional heat flows)."""
+    d, n, length, nu, kappa = 3, 7, 4.0, 0.05, 0.02
+    b, dm = galerkin.coefficient_B(d), galerkin.coefficient_D(d)
+    prob = fullgrid.Problem(b, dm, nu, n, length, diffusion=kappa)
+    mat = kron_operator(b, dm, nu, d, n, length)
+    l2 = sp.csr_matrix(fd.second_derivative(n, length))
+    eye = sp.identity(n, format="csr")
+    for k in range(d):
+        term = None
+        for j in range(d):
+            m = l2 if j == k else eye
+            term = m if term is None else sp.kron(term, m, format="csr")
+        mat = mat + kappa * term
+    rng = np.random.default_rng(9)
+    f = rng.standard_normal((n,) * d) + 1j * rng.standard_normal((n,) * d)
+    assert np.linalg.norm(prob.apply(f).ravel() - mat @ f.ravel()) <= 1e-12 * np.linalg.norm(mat @ f.ravel())
+    # heat flow alone: exp(t kappa sum_k L2_k) = kron of exp(t kappa L2)
+    heat = fullgrid.Problem(np.zeros((d, d, d)), np.zeros((d, d)), 0.0, n, length, diffusion=kappa)
+    t = 0.3
+    g = f.copy()
+    for _ in range(300):
+        g = fullgrid.rk4_step(g, t / 300, heat.apply)
+    e1 = __import__("scipy.linalg", fromlist=["expm"]).expm(t * kappa * fd.second_derivative(n, length))
+    ref = f
+    for k in range(d):
+        ref = fullgrid.apply_along(e1, ref, k)
+    assert fullgrid.rel_l2(g, ref) < 1e-10
+
+
 def test_implicit_steps_match_sparse_direct_solve():
     """The implicit steps against an LU solve of the independently assembled
     Kronecker matrix: (I - dt M) x = f and (I - dt/2 M) x = (I + dt/2 M) f."""
