@@ -173,6 +173,18 @@ int tt_op_create_burgers_hopf(tt_ctx* ctx, int d, int n, double L, double nu, tt
  * semi-discrete solution is known in closed form). */
 int tt_op_create_burgers_hopf_scaled(tt_ctx* ctx, int d, int n, double L, double nu,
                                      double advection, tt_op** out);
+/* The general form: advection scales the B term as above; diffusion >= 0
+ * adds the numerical-diffusion stabilisation kappa sum_k d^2/da_k^2 of the
+ * explicit runs of Sec. 5.2 (kappa = diffusion, chosen by the caller
+ * proportional to dt; 0 gives the plain operator). */
+typedef struct {
+  int size;              /* sizeof(tt_op_opts) */
+  int pad;
+  double advection;      /* 1: Burgers-Hopf */
+  double diffusion;      /* kappa >= 0 */
+} tt_op_opts;
+int tt_op_create_burgers_hopf_ex(tt_ctx* ctx, int d, int n, double L, double nu, const tt_op_opts* opts,
+                                 tt_op** out);
 int tt_op_destroy(tt_op* op);
 /* Bond dimensions R[0..d] of the operator's TT-matrix form. */
 int tt_op_get_ranks(const tt_op* op, int* R);

@@ -1011,8 +1011,8 @@ int tt_op_create_burgers_hopf(tt_ctx* ctx, int d, int n, double L, double nu, tt
   return tt_op_create_burgers_hopf_scaled(ctx, d, n, L, nu, 1.0, out);
 }
 
-int tt_op_create_burgers_hopf_scaled(tt_ctx* ctx, int d, int n, double L, double nu, double advection,
-                                     tt_op** out) {
+static int create_op(tt_ctx* ctx, int d, int n, double L, double nu, double advection, double diffusion,
+                     tt_op** out) {
   if (!out) return TT_EINVAL;
   tt_op* op = nullptr;
   ABI_TRY
@@ -1020,12 +1020,14 @@ int tt_op_create_burgers_hopf_scaled(tt_ctx* ctx, int d, int n, double L, double
   require(d >= 1 && d <= TT_MAX_D, TT_EINVAL, "d must be in 1..128");
   require(n >= 4, TT_EINVAL, "n must be at least 4");
   require(L > 0 && nu >= 0, TT_EINVAL, "need L > 0 and nu >= 0");
+  require(diffusion >= 0, TT_EINVAL, "numerical diffusion must be >= 0");
   op = new tt_op;
   op->d = d;
   op->n = n;
   op->L = L;
   op->nu = nu;
   op->adv = advection;
+  op->diff = diffusion;
   build_burgers_hopf(op);
   if (ctx) upload_op(ctx, op);
   *out = op;
@@ -1040,6 +1042,20 @@ int tt_op_create_burgers_hopf_scaled(tt_ctx* ctx, int d, int n, double L, double
     free_op(op);
     return TT_EINVAL;
   }
+}
+
+int tt_op_create_burgers_hopf_scaled(tt_ctx* ctx, int d, int n, double L, double nu, double advection,
+                                     tt_op** out) {
+  return create_op(ctx, d, n, L, nu, advection, 0.0, out);
+}
+
+int tt_op_create_burgers_hopf_ex(tt_ctx* ctx, int d, int n, double L, double nu, const tt_op_opts* opts,
+                                 tt_op** out) {
+  if (!opts || opts->size != (int)sizeof(tt_op_opts)) {
+    if (ctx) ctx->last_error = "tt_op_opts.size mismatch";
+    return TT_EINVAL;
+  }
+  return create_op(ctx, d, n, L, nu, opts->advection, opts->diffusion, out);
 }
 
 int tt_op_destroy(tt_op* op) {

@@ -104,6 +104,7 @@ struct tt_tensor {
 struct tt_op {
   int d = 0, n = 0;
   double L = 0, nu = 0, adv = 1.0;
+  double diff = 0.0;                  // numerical-diffusion coefficient kappa
   std::vector<double> B, D;           // host coefficients
   std::vector<double> grid;           // a_i
   std::vector<int> tap_col;           // [NOPS][n][NTAPS]

@@ -17,6 +17,9 @@
 // a_i = -L + 2L i/(n-1), centred second-order differences, and second-order
 // one-sided boundary rows.
 //
+// An optional numerical-diffusion stabilisation (Sec. 5.2, explicit runs)
+// adds kappa sum_k d^2/da_k^2: d one-site terms L2.
+//
 // TT-matrix form: the operator is a sum of products of one-axis operators
 // on at most three sites (X = multiply by a, G = d/da, L2 = d^2/da^2, and
 // the same-site compositions XG, XL2; multiplication by a_k acts after the
@@ -205,6 +208,13 @@ void build_burgers_hopf(tt_op* op) {
     t.ops.push_back({k, OP_XG});
     terms.push_back(t);
   }
+  if (op->diff != 0.0)
+    for (int k = 0; k < d; ++k) {
+      Term t;
+      t.coef = cplx(op->diff, 0.0);
+      t.ops.push_back({k, OP_L2});
+      terms.push_back(t);
+    }
   // ---- automaton
   // channel key: (kind, site, op); kind 0 = I, 1 = F, 2 = A, 3 = B
   using Key = std::tuple<int, int, int>;

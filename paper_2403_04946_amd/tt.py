@@ -82,6 +82,15 @@ class StepOpts(ctypes.Structure):
     ]
 
 
+class OpOpts(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_int),
+        ("pad", ctypes.c_int),
+        ("advection", ctypes.c_double),
+        ("diffusion", ctypes.c_double),
+    ]
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [
         ("size", ctypes.c_int),
@@ -156,6 +165,7 @@ _SIGS = {
     "tt_step": (I, [P, P, P, D, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport)]),
     "tt_eval": (I, [P, P, P, ctypes.c_int64, P]),
     "tt_norm": (I, [P, P, PD]),
+    "tt_op_create_burgers_hopf_ex": (I, [P, I, I, D, D, P, P]),
     "tt_ctx_set_profile_sampling": (I, [P, I]),
     "tt_dot": (I, [P, P, P, PD]),
     "tt_solve_shifted": (I, [P, P, D, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport)]),
@@ -320,11 +330,12 @@ class Tensor:
 class Operator:
     """Burgers-Hopf operator; ctx=None builds a host-only operator."""
 
-    def __init__(self, ctx, d, n, length, nu, advection=1.0):
+    def __init__(self, ctx, d, n, length, nu, advection=1.0, diffusion=0.0):
         self.ctx, self.d, self.n = ctx, d, n
         h = P()
-        rc = lib().tt_op_create_burgers_hopf_scaled(ctx.h if ctx else None, d, n, float(length), float(nu),
-                                                    float(advection), ctypes.byref(h))
+        o = OpOpts(ctypes.sizeof(OpOpts), 0, float(advection), float(diffusion))
+        rc = lib().tt_op_create_burgers_hopf_ex(ctx.h if ctx else None, d, n, float(length), float(nu),
+                                                ctypes.byref(o), ctypes.byref(h))
         if rc != 0:
             raise TTError(rc, "tt_op_create_burgers_hopf failed")
         self.h = h
