@@ -201,6 +201,90 @@ def error_report(ctx, tt, op, f0, prec, ell, traj_steps):
     return rep
 
 
+def main_batched(args):
+    """Batched form: uneven independent instances (the batched workload's
+    distribution: d uniform 8..64, n in {32, 64, 128}, nu log-uniform
+    1e-3..1e-1, rank caps 16..96), each a seeded random TT with every
+    interior rank at its cap, sketch width cap + 16, split-FP16x3 sketch
+    contractions, dt = 2e-4, eps = 1e-6, stepped concurrently by
+    tt_step_batch with one context (host thread and stream) per instance,
+    against the same instances stepped one after another."""
+    import torch
+
+    from paper_2403_04946_amd import inputs, tt
+
+    torch.cuda.init()
+    specs = inputs.batch_instances(args.instances, 4)
+    nctx = len(specs)
+    ctxs = [tt.Context(0) for _ in range(nctx)]
+    objs = []
+    for i, sp in enumerate(specs):
+        c = ctxs[i]
+        op = tt.Operator(c, sp["d"], sp["n"], 8.0, sp["nu"])
+        f = tt.Tensor(c, sp["d"], sp["n"], sp["cap"])
+        f.set_cores(inputs.random_tt(sp["d"], sp["n"], sp["cap"], sp["seed"]))
+        objs.append((c, op, f))
+    n = len(specs)
+    caps = [sp["cap"] for sp in specs]
+    ells = [sp["cap"] + 16 for sp in specs]
+    seeds = [sp["seed"] for sp in specs]
+
+    def batched(sel):
+        st = tt.tt_step_batch([objs[i][0] for i in sel], [objs[i][1] for i in sel], [objs[i][2] for i in sel],
+                              [DT] * len(sel), [caps[i] for i in sel], [EPS] * len(sel), tt.TT_APPLY_SKETCH,
+                              [ells[i] for i in sel], [seeds[i] for i in sel], precision=tt.TT_PREC_FP16X3)
+        if any(st):
+            why = {i: tt.lib().tt_last_error(objs[i][0].h).decode() for i, v in zip(sel, st) if v}
+            free, total = torch.cuda.mem_get_info()
+            raise RuntimeError(f"batched step failed: {st} {why}; device memory free {free / 1e9:.1f} of "
+                               f"{total / 1e9:.1f} GB")
+
+    everyone = list(range(n))
+    for w in range(args.warmup):
+        batched(everyone)
+        print(f"bench: batched warm-up {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        batched(everyone)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    print("bench: batched steps done", file=sys.stderr, flush=True)
+    # the same instances one after another, each alone on its context
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        for i in everyone:
+            batched([i])
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    print("bench: sequential steps done", file=sys.stderr, flush=True)
+    stages = 4 * n * args.steps
+    result = {
+        "metric": "instance RK stages/sec, batched form",
+        "value": stages / tb,
+        "unit": "instance-stages/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * tb / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp16x3+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ("uneven independent Burgers-Hopf instances: d 8..64, n in {32,64,128}, nu 1e-3..1e-1, "
+                         "caps 16..96, saturated ranks, split-FP16x3 sketch contractions"),
+            "instances": n, "contexts": nctx, "dt": DT, "eps": EPS,
+            "instance_shapes": [[sp["d"], sp["n"], sp["cap"]] for sp in specs],
+        },
+        "sequential_reference": {"value": stages / ts, "unit": "instance-stages/s", "seconds": ts},
+        "speedup_over_sequential": ts / tb,
+        "roofline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,10 +297,19 @@ def main():
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-error-report", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--form", choices=["metric", "batched"], default="metric",
+                    help="batched: the batched form on uneven instances (its own JSON line)")
+    ap.add_argument("--instances", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.form == "batched":
+        # more hardware queues than the default 4, so the contexts' streams
+        # do not share queues (set before the HIP runtime starts)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+        main_batched(args)
+        return
 
     import torch
 

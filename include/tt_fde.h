@@ -292,6 +292,18 @@ typedef struct {
 int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt,
             const tt_step_opts* opts, tt_step_report* rep);
 
+/* Batched form: `count` independent instances, instance i being one
+ * tt_step(ctxs[i], ops[i], fs[i], dts[i], &opts[i], &reps[i]) (reps may be
+ * NULL).  Instances with the same context run in order on one host thread
+ * and that context's stream; distinct contexts run on their own threads,
+ * so their kernels overlap on the GPU (each instance alone leaves most of
+ * the chip idle: its kernels are small and latency-bound).  Every context
+ * must be used by this call only.  status[i] receives instance i's return
+ * code (an instance that fails leaves the others running); the call
+ * returns TT_OK or the first nonzero status.  Synchronous. */
+int tt_step_batch(int count, tt_ctx* const* ctxs, const tt_op* const* ops, tt_tensor* const* fs,
+                  const double* dts, const tt_step_opts* opts, tt_step_report* reps, int* status);
+
 /* out[p] = x[idx[p, 0], ..., idx[p, d-1]] (iterated matrix product,
  * App. A.1).  idx: device int32 array npts x d (row p contiguous);
  * out: device array of npts complex values. */

@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <mutex>
+#include <thread>
 #include <cstring>
 #include <new>
 #include <tuple>
@@ -289,7 +291,8 @@ void phase1_right_orth(tt_ctx* ctx, tt_tensor* x) {
     const int p0 = r[c], p1 = r[c + 1];
     const int N = n * p1;
     const int rl = r[c - 1];
-    zc* tmp = (zc*)ctx->get_ws("ph1_tmp", sizeof(zc) * (size_t)rl * n * std::max(p0, N));
+    // the new C_{c-1} has N columns when H(C_c) is taller than wide, else p0
+    zc* tmp = (zc*)ctx->get_ws("ph1_tmp", sizeof(zc) * (size_t)rl * n * (p0 > N ? N : p0));
     if (p0 > N) {
       // H(C_c) is taller than wide: C_c <- I, C_{c-1} <- C_{c-1} H(C_c)
       zgemm(ctx, OPN, OPN, rl * n, N, p0, Z(1), x->core[c - 1], (long)rl * n, 0, x->core[c], p0, 0, Z(0), tmp,
@@ -658,6 +661,14 @@ struct StepTemps {
   tt_tensor* y = nullptr;
   tt_tensor* fsum = nullptr;
 };
+// the temporaries caches are shared by every context; contexts may step on
+// different host threads (tt_step_batch), so lookups and inserts are
+// serialised (map references stay valid across inserts)
+std::mutex& cache_mutex() {
+  static std::mutex m;
+  return m;
+}
+
 std::map<std::pair<tt_ctx*, std::string>, StepTemps>& step_cache() {
   static std::map<std::pair<tt_ctx*, std::string>, StepTemps> c;
   return c;
@@ -681,7 +692,10 @@ std::map<std::pair<tt_ctx*, std::string>, tt_tensor*>& pool_cache() {
 }
 
 tt_tensor* pooled(tt_ctx* ctx, const std::string& name, int d, int n, const std::vector<int>& cap) {
-  tt_tensor*& t = pool_cache()[{ctx, name}];
+  tt_tensor*& t = [&]() -> tt_tensor*& {
+    std::lock_guard<std::mutex> lock(cache_mutex());
+    return pool_cache()[{ctx, name}];
+  }();
   bool ok = t && t->d == d && t->n == n;
   for (int k = 0; ok && k <= d; ++k) ok = t->cap[k] >= cap[k];
   if (!ok) {
@@ -696,6 +710,7 @@ tt_tensor* pooled(tt_ctx* ctx, const std::string& name, int d, int n, const std:
 }
 
 void drop_ctx_caches(tt_ctx* ctx) {
+  std::lock_guard<std::mutex> lock(cache_mutex());
   auto& pc = pool_cache();
   for (auto it = pc.begin(); it != pc.end();) {
     if (it->first.first == ctx) {
@@ -1436,7 +1451,10 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
   }
   const std::string key = shape_key(d, n, f->cap, rmax) + ":" + std::to_string(scheme) + ":" +
                           std::to_string(opts->apply_mode) + ":" + std::to_string(opts->sketch_rank);
-  StepTemps& T = step_cache()[{ctx, key}];
+  StepTemps& T = [&]() -> StepTemps& {
+    std::lock_guard<std::mutex> lock(cache_mutex());
+    return step_cache()[{ctx, key}];
+  }();
   if (!T.ysum) {
     const int nk = scheme == TT_STEP_RK4                                                   ? 4
                    : (scheme == TT_STEP_MIDPOINT || scheme == TT_STEP_IMPLICIT_MIDPOINT) ? 2
@@ -1573,6 +1591,36 @@ int tt_solve_shifted(tt_ctx* ctx, const tt_op* op, double c, const tt_tensor* b,
   ABI_CATCH(ctx)
 }
 
+int tt_step_batch(int count, tt_ctx* const* ctxs, const tt_op* const* ops, tt_tensor* const* fs, const double* dts,
+                  const tt_step_opts* opts, tt_step_report* reps, int* status) {
+  if (count < 0 || (count > 0 && (!ctxs || !ops || !fs || !dts || !opts || !status))) return TT_EINVAL;
+  // one host thread per distinct context, running its instances in order on
+  // the context's stream: the instances of different contexts overlap on
+  // the GPU
+  std::vector<tt_ctx*> order;
+  std::map<tt_ctx*, std::vector<int>> work;
+  for (int i = 0; i < count; ++i) {
+    if (!ctxs[i]) return TT_EINVAL;
+    if (!work.count(ctxs[i])) order.push_back(ctxs[i]);
+    work[ctxs[i]].push_back(i);
+  }
+  auto run = [&](tt_ctx* ctx) {
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+      for (int i : work[ctx]) status[i] = TT_EHIP;
+      return;
+    }
+    for (int i : work[ctx]) status[i] = tt_step(ctx, ops[i], fs[i], dts[i], &opts[i], reps ? &reps[i] : nullptr);
+  };
+  std::vector<std::thread> threads;
+  threads.reserve(order.size());
+  for (size_t t = 1; t < order.size(); ++t) threads.emplace_back(run, order[t]);
+  if (!order.empty()) run(order[0]);
+  for (auto& th : threads) th.join();
+  for (int i = 0; i < count; ++i)
+    if (status[i] != TT_OK) return status[i];
+  return TT_OK;
+}
+
 int tt_eval(tt_ctx* ctx, const tt_tensor* x, const int32_t* idx, int64_t npts, double* out) {
   if (!ctx || !x || (npts > 0 && (!idx || !out))) return TT_EINVAL;
   ABI_TRY
@@ -1629,7 +1677,10 @@ int tt_zgemm_mixed(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, i
 int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out) {
   if (!ctx || !x || !out) return TT_EINVAL;
   ABI_TRY
-  tt_tensor*& tmp = norm_cache()[{ctx, shape_key(x->d, x->n, x->cap, -1)}];
+  tt_tensor*& tmp = [&]() -> tt_tensor*& {
+    std::lock_guard<std::mutex> lock(cache_mutex());
+    return norm_cache()[{ctx, shape_key(x->d, x->n, x->cap, -1)}];
+  }();
   if (!tmp) tmp = make_tensor(ctx, x->d, x->n, x->cap);
   copy_tensor(ctx, x, tmp);
   if (tmp->orth != TT_ORTH_RIGHT && x->d > 1) phase1_right_orth(ctx, tmp);

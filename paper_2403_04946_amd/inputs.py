@@ -48,3 +48,22 @@ def random_points(d, n, npts, seed):
     """Uniform random grid index tuples, int32 array (npts, d)."""
     rng = np.random.default_rng(seed)
     return rng.integers(0, n, size=(npts, d), dtype=np.int64).astype(np.int32)
+
+
+def batch_instances(count, seed, d_range=(8, 64), n_choices=(32, 64, 128), nu_range=(1e-3, 1e-1),
+                    cap_range=(16, 96)):
+    """Seeded parameters of uneven independent instances (the batched
+    workload): d uniform on d_range (inclusive), n from n_choices, nu
+    log-uniform on nu_range, rank cap uniform on cap_range (inclusive), and
+    the Gaussian initial-condition parameters of each instance (ic_params
+    with the instance's own seed).  Returns a list of dicts."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        d = int(rng.integers(d_range[0], d_range[1] + 1))
+        n = int(rng.choice(n_choices))
+        nu = float(np.exp(rng.uniform(np.log(nu_range[0]), np.log(nu_range[1]))))
+        cap = int(rng.integers(cap_range[0], cap_range[1] + 1))
+        mu, sigma = ic_params(d, 1000 * seed + i)
+        out.append({"d": d, "n": n, "nu": nu, "cap": cap, "mu": mu, "sigma": sigma, "seed": 1000 * seed + i})
+    return out

@@ -165,6 +165,7 @@ _SIGS = {
     "tt_step": (I, [P, P, P, D, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport)]),
     "tt_eval": (I, [P, P, P, ctypes.c_int64, P]),
     "tt_norm": (I, [P, P, PD]),
+    "tt_step_batch": (I, [I, P, P, P, PD, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport), PI]),
     "tt_op_create_burgers_hopf_ex": (I, [P, I, I, D, D, P, P]),
     "tt_ctx_set_profile_sampling": (I, [P, I]),
     "tt_dot": (I, [P, P, P, PD]),
@@ -413,6 +414,23 @@ def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=
     rep = StepReport()
     ctx.check(lib().tt_step(ctx.h, op.h, f.h, float(dt), ctypes.byref(o), ctypes.byref(rep)))
     return {"stages": rep.stages, "max_rank": rep.max_rank, "ranks": list(rep.ranks[: f.d + 1])}
+
+
+def tt_step_batch(ctxs, ops, fs, dts, rmaxs, epss, mode=TT_APPLY_EXACT, sketch_ranks=None, seeds=None,
+                  precision=0, scheme=TT_STEP_RK4):
+    """Independent instances stepped concurrently (one host thread and
+    stream per distinct context).  Returns the per-instance status codes."""
+    n = len(fs)
+    sketch_ranks = sketch_ranks if sketch_ranks is not None else [0] * n
+    seeds = seeds if seeds is not None else [0] * n
+    opts = (StepOpts * n)(*[StepOpts(ctypes.sizeof(StepOpts), int(rmaxs[i]), float(epss[i]), int(mode),
+                                     int(sketch_ranks[i]), int(seeds[i]), int(precision), int(scheme), 1e-10, 30, 0)
+                            for i in range(n)])
+    reps = (StepReport * n)()
+    status = (I * n)()
+    lib().tt_step_batch(n, (P * n)(*[c.h.value for c in ctxs]), (P * n)(*[o.h.value for o in ops]),
+                        (P * n)(*[f.h.value for f in fs]), (D * n)(*[float(v) for v in dts]), opts, reps, status)
+    return list(status)
 
 
 def tt_eval(ctx, x, idx, out):

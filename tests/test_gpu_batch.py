@@ -1,0 +1,87 @@
+"""Batched form: independent, uneven instances stepped concurrently by
+tt_step_batch (one host thread and stream per context).  Each instance's
+result must be bit-identical to stepping it alone, and one instance is
+checked against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import full, make_ctx, rel
+from oracle import fullgrid, galerkin
+from paper_2403_04946_amd import inputs, tt
+
+pytestmark = pytest.mark.gpu
+L = 4.0
+
+
+def _instances():
+    # small uneven instances (the batched workload's structure at sizes the
+    # oracle can check): d 3..5, n 16 or 32, caps 4..16
+    return inputs.batch_instances(6, 3, d_range=(3, 5), n_choices=(16, 32), nu_range=(1e-3, 1e-1),
+                                  cap_range=(4, 16))
+
+
+def _build(ctx, spec):
+    op = tt.Operator(ctx, spec["d"], spec["n"], L, spec["nu"])
+    f = tt.Tensor(ctx, spec["d"], spec["n"], spec["cap"])
+    f.set_gaussian(spec["mu"], spec["sigma"], L)
+    return op, f
+
+
+def test_batch_equals_sequential():
+    specs = _instances()
+    ctxs = [make_ctx() for _ in range(3)]
+    batch = [_build(ctxs[i % 3], s) for i, s in enumerate(specs)]
+    single_ctx = make_ctx()
+    seq = [_build(single_ctx, s) for s in specs]
+    dt, steps = 1e-3, 4
+    for step in range(steps):
+        status = tt.tt_step_batch([ctxs[i % 3] for i in range(len(specs))], [b[0] for b in batch],
+                                  [b[1] for b in batch], [dt] * len(specs), [s["cap"] for s in specs],
+                                  [1e-10] * len(specs), tt.TT_APPLY_SKETCH, [4 * s["cap"] for s in specs],
+                                  [s["seed"] + step for s in specs], precision=tt.TT_PREC_FP16X3)
+        assert status == [0] * len(specs), status
+        for s, (op, f) in zip(specs, seq):
+            tt.tt_step(single_ctx, op, f, dt, s["cap"], 1e-10, tt.TT_APPLY_SKETCH, 4 * s["cap"], s["seed"] + step,
+                       precision=tt.TT_PREC_FP16X3)
+    for s, (op_b, f_b), (op_s, f_s) in zip(specs, batch, seq):
+        assert f_b.ranks() == f_s.ranks()
+        for cb, cs in zip(f_b.get_cores(), f_s.get_cores()):
+            assert np.array_equal(cb, cs)
+    for op, f in batch + seq:
+        f.close()
+        op.close()
+    for c in ctxs + [single_ctx]:
+        c.close()
+
+
+def test_batch_instance_matches_oracle_and_errors_stay_local():
+    """An uncapped d=3 instance beside others: it matches the oracle's RK4;
+    an instance given an invalid option fails alone with its own status."""
+    ctxs = [make_ctx() for _ in range(3)]
+    d, n, nu, dt, steps = 3, 32, 0.05, 1e-3, 5
+    mu, sig = inputs.ic_params(d, 0)
+    specs = [{"d": d, "n": n, "nu": nu, "cap": n, "mu": mu, "sigma": sig}]
+    specs += [dict(s) for s in _instances()[:2]]
+    objs = [_build(ctxs[i], s) for i, s in enumerate(specs)]
+    for step in range(steps):
+        st = tt.tt_step_batch(ctxs, [o[0] for o in objs], [o[1] for o in objs], [dt] * 3, [s["cap"] for s in specs],
+                              [1e-13, 1e-10, 1e-10], tt.TT_APPLY_EXACT)
+        assert st == [0, 0, 0], st
+    prob = fullgrid.Problem(galerkin.coefficient_B(d), galerkin.coefficient_D(d), nu, n, L)
+    g = fullgrid.gaussian_ic(mu, sig, n, L)
+    for _ in range(steps):
+        g = fullgrid.rk4_step(g, dt, prob.apply)
+    assert rel(full(objs[0][1]), g) < 1e-10
+    # a rank cap of 0 is invalid: instance 1 fails, instances 0 and 2 step
+    before = full(objs[1][1])
+    st = tt.tt_step_batch(ctxs, [o[0] for o in objs], [o[1] for o in objs], [dt] * 3, [n, 0, specs[2]["cap"]],
+                          [1e-13, 1e-10, 1e-10], tt.TT_APPLY_EXACT)
+    assert st[0] == 0 and st[1] == -1 and st[2] == 0, st
+    assert np.array_equal(full(objs[1][1]), before)
+    g = fullgrid.rk4_step(g, dt, prob.apply)
+    assert rel(full(objs[0][1]), g) < 1e-10
+    for op, f in objs:
+        f.close()
+        op.close()
+    for c in ctxs:
+        c.close()
