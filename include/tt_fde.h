@@ -373,6 +373,18 @@ typedef struct {
 int tt_solve_shifted(tt_ctx* ctx, const tt_op* op, double c, const tt_tensor* b, tt_tensor* x,
                      const tt_solve_opts* opts, tt_solve_report* rep);
 
+/* Randomised rounding with per-bond sketch widths (the randomised tt_round
+ * of the learned form): y = the sketched product of x with the identity
+ * operator, i.e. left Gaussian TT sketches of widths[k] (Philox key seed)
+ * and a right-to-left sweep of LQ factorisations; y is right-orthonormal
+ * with rank k <= widths[k] (widths: d+1 ints, ends ignored, each within
+ * y's capacity).  *rel_err (may be NULL) receives ||x - y|| / ||x|| from
+ * exact TT inner products (||x||^2 + ||y||^2 - 2 Re <x, y>), the a
+ * posteriori check that decides whether the deterministic rounding is
+ * needed.  Synchronous. */
+int tt_round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y,
+                        double* rel_err);
+
 /* Frobenius norm of x (synchronous; computed by orthogonalisation). */
 int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out);
 

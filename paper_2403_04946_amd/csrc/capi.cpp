@@ -463,7 +463,7 @@ void apply_exact(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y)
 }
 
 void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int l, uint64_t seed,
-                  int precision) {
+                  int precision, const int* widths = nullptr) {
   // the sketch contractions in plain FP64 or a split 16-bit form (mixed)
   auto gemm = [ctx, precision](tt_ctx*, int opA, int opB, int M, int N, int K, zc alpha, const zc* A, long lda,
                                 long sA, const zc* B, long ldb, long sB, zc beta, zc* C, long ldc, long sC,
@@ -475,7 +475,11 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
   const auto& R = op->R;
   require(l >= 1, TT_EINVAL, "tt_apply: sketch rank must be >= 1");
   std::vector<int> ll(d + 1);
-  for (int m = 0; m <= d; ++m) ll[m] = std::min(bounded_pow(n, m, l), bounded_pow(n, d - m, l));
+  // sketch width per bond (uniform l, or the given widths)
+  for (int m = 0; m <= d; ++m) {
+    const int w = widths ? std::max(1, widths[m]) : l;
+    ll[m] = std::min(bounded_pow(n, m, w), bounded_pow(n, d - m, w));
+  }
   for (int m = 0; m <= d; ++m) require(ll[m] <= y->cap[m], TT_ECAPACITY, "tt_apply: output capacity below sketch rank");
   if (d == 1) {
     apply_exact_core(ctx, op, 0, x->core[0], 1, 1, y->core[0]);
@@ -709,8 +713,27 @@ tt_tensor* pooled(tt_ctx* ctx, const std::string& name, int d, int n, const std:
   return t;
 }
 
+// identity operators (randomised rounding), built once per context and shape
+std::map<std::tuple<tt_ctx*, int, int>, tt_op*>& identity_ops() {
+  static std::map<std::tuple<tt_ctx*, int, int>, tt_op*> c;
+  return c;
+}
+
+void free_op(tt_op* op);
+
 void drop_ctx_caches(tt_ctx* ctx) {
   std::lock_guard<std::mutex> lock(cache_mutex());
+  {
+    auto& io = identity_ops();
+    for (auto it = io.begin(); it != io.end();) {
+      if (std::get<0>(it->first) == ctx) {
+        free_op(it->second);
+        it = io.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
   auto& pc = pool_cache();
   for (auto it = pc.begin(); it != pc.end();) {
     if (it->first.first == ctx) {
@@ -1619,6 +1642,52 @@ int tt_step_batch(int count, tt_ctx* const* ctxs, const tt_op* const* ops, tt_te
   for (int i = 0; i < count; ++i)
     if (status[i] != TT_OK) return status[i];
   return TT_OK;
+}
+
+const tt_op* identity_op(tt_ctx* ctx, int d, int n) {
+  std::lock_guard<std::mutex> lock(cache_mutex());
+  tt_op*& op = identity_ops()[{ctx, d, n}];
+  if (!op) {
+    tt_op* o = new tt_op;
+    o->d = d;
+    o->n = n;
+    o->L = 1.0;
+    o->nu = 0.0;
+    o->adv = 0.0;
+    o->ident = 1.0;
+    build_burgers_hopf(o);
+    upload_op(ctx, o);
+    op = o;
+  }
+  return op;
+}
+
+// Randomised rounding with per-bond sketch widths: the sketched product with
+// the identity operator (left Gaussian TT sketches, right-to-left sweep of
+// LQ factorisations; right-orthonormal result of ranks <= widths), and its
+// relative error ||x - y|| / ||x|| from exact TT inner products.
+double round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y) {
+  const tt_op* op = identity_op(ctx, x->d, x->n);
+  int l = 1;
+  for (int k = 0; k <= x->d; ++k) l = std::max(l, widths[k]);
+  apply_sketch(ctx, op, x, y, l, seed, TT_PREC_FP64, widths);
+  const zc xx = dot_tensors(ctx, x, x), yy = dot_tensors(ctx, y, y), xy = dot_tensors(ctx, x, y);
+  const double e2 = xx.x + yy.x - 2.0 * xy.x;
+  return xx.x > 0.0 ? std::sqrt(std::max(0.0, e2) / xx.x) : 0.0;
+}
+
+int tt_round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y,
+                        double* rel_err) {
+  if (!ctx || !x || !y || !widths) return TT_EINVAL;
+  ABI_TRY
+  require(x->d == y->d && x->n == y->n, TT_ESHAPE, "tt_round_randomized: shape mismatch");
+  require(x != y, TT_EINVAL, "tt_round_randomized: y aliases x");
+  for (int k = 1; k < x->d; ++k)
+    require(widths[k] >= 1 && widths[k] <= y->cap[k], TT_ECAPACITY, "tt_round_randomized: width beyond capacity");
+  const double e = round_randomized(ctx, x, widths, seed, y);
+  if (rel_err) *rel_err = e;
+  return TT_OK;
+  ABI_CATCH(ctx)
 }
 
 int tt_eval(tt_ctx* ctx, const tt_tensor* x, const int32_t* idx, int64_t npts, double* out) {

@@ -105,6 +105,7 @@ struct tt_op {
   int d = 0, n = 0;
   double L = 0, nu = 0, adv = 1.0;
   double diff = 0.0;                  // numerical-diffusion coefficient kappa
+  double ident = 0.0;                 // coefficient of an identity term
   std::vector<double> B, D;           // host coefficients
   std::vector<double> grid;           // a_i
   std::vector<int> tap_col;           // [NOPS][n][NTAPS]

@@ -208,6 +208,14 @@ void build_burgers_hopf(tt_op* op) {
     t.ops.push_back({k, OP_XG});
     terms.push_back(t);
   }
+  if (op->ident != 0.0) {
+    // ident * I as a one-site term (I at the first site): with no other
+    // term the automaton has one channel per bond, R = 1
+    Term t;
+    t.coef = cplx(op->ident, 0.0);
+    t.ops.push_back({0, OP_I});
+    terms.push_back(t);
+  }
   if (op->diff != 0.0)
     for (int k = 0; k < d; ++k) {
       Term t;

@@ -165,6 +165,7 @@ _SIGS = {
     "tt_step": (I, [P, P, P, D, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport)]),
     "tt_eval": (I, [P, P, P, ctypes.c_int64, P]),
     "tt_norm": (I, [P, P, PD]),
+    "tt_round_randomized": (I, [P, P, PI, ctypes.c_uint64, P, PD]),
     "tt_step_batch": (I, [I, P, P, P, PD, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport), PI]),
     "tt_op_create_burgers_hopf_ex": (I, [P, I, I, D, D, P, P]),
     "tt_ctx_set_profile_sampling": (I, [P, I]),
@@ -486,6 +487,15 @@ def tt_solve_shifted(ctx, op, c, b, x, tol, max_iter=30, krylov_eps=None, krylov
     ctx.check(lib().tt_solve_shifted(ctx.h, op.h, float(c), b.h, x.h, ctypes.byref(o), ctypes.byref(rep)))
     return {"iterations": rep.iterations, "converged": bool(rep.converged), "residual": rep.residual,
             "max_rank": rep.max_rank}
+
+
+def tt_round_randomized(ctx, x, widths, seed, y):
+    """Randomised rounding of x into y with per-bond sketch widths (d+1
+    ints); returns the relative error ||x - y|| / ||x||."""
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    e = D()
+    ctx.check(lib().tt_round_randomized(ctx.h, x.h, _ip(w), int(seed), y.h, ctypes.byref(e)))
+    return e.value
 
 
 def tt_norm(ctx, x):
