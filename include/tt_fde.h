@@ -385,6 +385,33 @@ int tt_solve_shifted(tt_ctx* ctx, const tt_op* op, double c, const tt_tensor* b,
 int tt_round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y,
                         double* rel_err);
 
+/* ---------------------------------------------------- rank predictor MLP */
+/* The learned form's per-bond rank predictor: n_in -> width -> width -> 1
+ * with ReLU hidden layers, FP16 parameters with FP32 accumulation on the
+ * device, FP32 master parameters and Adam (beta 0.9, 0.999, eps 1e-8) for
+ * training on the loss L = (1 / 2B) sum_b (y_b - t_b)^2.  Parameter vector
+ * (host float32, tt_mlp_param_count of them): W1 (width x n_in, row-major),
+ * b1 (width), W2 (width x width), b2 (width), W3 (1 x width), b3 (1).
+ * Samples: a device float32 matrix B x n_in (row-major), targets and
+ * outputs device float32 vectors of B; B at most max_batch.  Every sum runs
+ * in a fixed order: results are deterministic.  All calls are on the
+ * context's stream; the ones returning host values synchronise. */
+typedef struct tt_mlp tt_mlp;
+int tt_mlp_create(tt_ctx* ctx, int n_in, int width, int max_batch, tt_mlp** out);
+int tt_mlp_destroy(tt_mlp* m);
+int tt_mlp_param_count(const tt_mlp* m);
+/* set the FP32 master parameters (their FP16 copy follows; Adam restarts) */
+int tt_mlp_set_params(tt_ctx* ctx, tt_mlp* m, const float* host);
+/* as_used = 0: the master parameters; 1: the FP16 values the forward uses */
+int tt_mlp_get_params(tt_ctx* ctx, const tt_mlp* m, float* host, int as_used);
+int tt_mlp_forward(tt_ctx* ctx, tt_mlp* m, const float* x, int B, float* y);
+/* loss and gradient (host, nparams floats; either may be NULL) at the
+ * FP16 parameters */
+int tt_mlp_gradients(tt_ctx* ctx, tt_mlp* m, const float* x, const float* t, int B, float* loss, float* grad);
+/* `iters` full-batch Adam steps at learning rate lr; *loss (may be NULL)
+ * receives the loss after them */
+int tt_mlp_train(tt_ctx* ctx, tt_mlp* m, const float* x, const float* t, int B, int iters, float lr, float* loss);
+
 /* Frobenius norm of x (synchronous; computed by orthogonalisation). */
 int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out);
 

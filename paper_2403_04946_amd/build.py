@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libttfde.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["problem.cpp", "capi.cpp", "k_gemm.hip", "k_mixed.hip", "k_dense.hip", "k_qr.hip", "k_tt.hip"]
+SOURCES = ["problem.cpp", "capi.cpp", "k_gemm.hip", "k_mixed.hip", "k_mlp.hip", "k_dense.hip", "k_qr.hip", "k_tt.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

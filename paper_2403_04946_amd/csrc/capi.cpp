@@ -1787,3 +1787,149 @@ int tt_svd_small(tt_ctx* ctx, int m, int k, double* B, double* U, double* sigma,
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------ rank predictor MLP
+struct tt_mlp {
+  ttf::MlpDev d;
+};
+
+namespace {
+void mlp_free(tt_mlp* m) {
+  if (!m) return;
+  for (void* ptr : {(void*)m->d.p, (void*)m->d.ph, (void*)m->d.g, (void*)m->d.m, (void*)m->d.v, (void*)m->d.act,
+                    (void*)m->d.loss})
+    if (ptr) (void)hipFree(ptr);
+  delete m;
+}
+}  // namespace
+
+extern "C" {
+
+int tt_mlp_create(tt_ctx* ctx, int n_in, int width, int max_batch, tt_mlp** out) {
+  if (!ctx || !out) return TT_EINVAL;
+  tt_mlp* m = nullptr;
+  ABI_TRY
+  *out = nullptr;
+  require(n_in >= 1 && n_in <= 1024 && width >= 1 && width <= 1024 && max_batch >= 1, TT_EINVAL,
+          "tt_mlp_create: n_in, width in 1..1024, max_batch >= 1");
+  m = new tt_mlp;
+  auto& d = m->d;
+  d.n_in = n_in;
+  d.width = width;
+  d.bcap = max_batch;
+  d.nparams = width * n_in + width + width * width + width + width + 1;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(TT_ENOMEM, "tt_mlp_create: allocation failed");
+    }
+  };
+  // float arrays padded to whole complex values: they are cleared with
+  // fill_zero, which writes 16-byte elements
+  const size_t padded = 4 * (((size_t)d.nparams + 3) / 4);
+  alloc((void**)&d.p, sizeof(float) * padded);
+  alloc((void**)&d.ph, sizeof(_Float16) * d.nparams);
+  alloc((void**)&d.g, sizeof(float) * d.nparams);
+  alloc((void**)&d.m, sizeof(float) * padded);
+  alloc((void**)&d.v, sizeof(float) * padded);
+  alloc((void**)&d.act, sizeof(float) * ((size_t)max_batch * (4 * (size_t)width + 3)));
+  alloc((void**)&d.loss, sizeof(float) * 4);
+  fill_zero(ctx, (zc*)d.p, (d.nparams + 3) / 4);
+  fill_zero(ctx, (zc*)d.m, (d.nparams + 3) / 4);
+  fill_zero(ctx, (zc*)d.v, (d.nparams + 3) / 4);
+  ttf::mlp_refresh_half(ctx, d);
+  *out = m;
+  return TT_OK;
+  }
+  catch (const ttf::Error& e) {
+    ctx->last_error = e.msg;
+    mlp_free(m);
+    return e.code;
+  }
+  catch (...) {
+    mlp_free(m);
+    return TT_EINVAL;
+  }
+}
+
+int tt_mlp_destroy(tt_mlp* m) {
+  mlp_free(m);
+  return TT_OK;
+}
+
+int tt_mlp_param_count(const tt_mlp* m) { return m ? m->d.nparams : TT_EINVAL; }
+
+int tt_mlp_set_params(tt_ctx* ctx, tt_mlp* m, const float* host) {
+  if (!ctx || !m || !host) return TT_EINVAL;
+  ABI_TRY
+  auto& d = m->d;
+  TTF_HIP(hipMemcpyAsync(d.p, host, sizeof(float) * d.nparams, hipMemcpyHostToDevice, ctx->stream));
+  fill_zero(ctx, (zc*)d.m, (d.nparams + 3) / 4);
+  fill_zero(ctx, (zc*)d.v, (d.nparams + 3) / 4);
+  d.step = 0;
+  ttf::mlp_refresh_half(ctx, d);
+  ctx->sync();
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_mlp_get_params(tt_ctx* ctx, const tt_mlp* m, float* host, int as_used) {
+  if (!ctx || !m || !host) return TT_EINVAL;
+  ABI_TRY
+  const auto& d = m->d;
+  const float* src = d.p;
+  if (as_used) {
+    float* tmp = (float*)ctx->get_ws("mlp_tmp", sizeof(float) * d.nparams);
+    ttf::mlp_half_values(ctx, d, tmp);
+    src = tmp;
+  }
+  TTF_HIP(hipMemcpyAsync(host, src, sizeof(float) * d.nparams, hipMemcpyDeviceToHost, ctx->stream));
+  ctx->sync();
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_mlp_forward(tt_ctx* ctx, tt_mlp* m, const float* x, int B, float* y) {
+  if (!ctx || !m || !x || !y) return TT_EINVAL;
+  ABI_TRY
+  auto& d = m->d;
+  require(B >= 1 && B <= d.bcap, TT_EINVAL, "tt_mlp_forward: batch above the capacity given at creation");
+  float* h1 = d.act;
+  float* h2 = h1 + (long)d.bcap * d.width;
+  ttf::mlp_forward(ctx, d, x, B, h1, h2, y);
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_mlp_gradients(tt_ctx* ctx, tt_mlp* m, const float* x, const float* t, int B, float* loss, float* grad) {
+  if (!ctx || !m || !x || !t) return TT_EINVAL;
+  ABI_TRY
+  auto& d = m->d;
+  require(B >= 1 && B <= d.bcap, TT_EINVAL, "tt_mlp_gradients: batch above the capacity given at creation");
+  ttf::mlp_gradients(ctx, d, x, t, B, d.loss);
+  if (loss) TTF_HIP(hipMemcpyAsync(loss, d.loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+  if (grad) TTF_HIP(hipMemcpyAsync(grad, d.g, sizeof(float) * d.nparams, hipMemcpyDeviceToHost, ctx->stream));
+  ctx->sync();
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_mlp_train(tt_ctx* ctx, tt_mlp* m, const float* x, const float* t, int B, int iters, float lr, float* loss) {
+  if (!ctx || !m || !x || !t) return TT_EINVAL;
+  ABI_TRY
+  auto& d = m->d;
+  require(B >= 1 && B <= d.bcap && iters >= 0 && lr > 0.0f, TT_EINVAL, "tt_mlp_train: bad batch, iters or lr");
+  for (int it = 0; it < iters; ++it) {
+    ttf::mlp_gradients(ctx, d, x, t, B, d.loss);
+    ttf::mlp_adam_step(ctx, d, lr);
+  }
+  if (loss) {
+    ttf::mlp_gradients(ctx, d, x, t, B, d.loss);
+    TTF_HIP(hipMemcpyAsync(loss, d.loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+  }
+  ctx->sync();
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+}  // extern "C"

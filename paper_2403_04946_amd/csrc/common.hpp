@@ -157,6 +157,23 @@ struct KTimer {
       hipLaunchKernelGGL(kfn, grid, block, shmem, stream, __VA_ARGS__);                         \
   } while (0)
 
+// ---------------------------------------------------- rank predictor MLP
+struct MlpDev {
+  int n_in = 0, width = 0, nparams = 0, bcap = 0, step = 0;
+  float* p = nullptr;       // FP32 master parameters
+  _Float16* ph = nullptr;   // FP16 parameters used by the forward pass
+  float* g = nullptr;       // gradients
+  float* m = nullptr;       // Adam moments
+  float* v = nullptr;
+  float* act = nullptr;     // activations and deltas for bcap samples
+  float* loss = nullptr;    // one float
+};
+void mlp_forward(tt_ctx* ctx, const MlpDev& m, const float* X, int B, float* h1, float* h2, float* y);
+void mlp_gradients(tt_ctx* ctx, const MlpDev& m, const float* X, const float* T, int B, float* loss_dev);
+void mlp_adam_step(tt_ctx* ctx, MlpDev& m, float lr);
+void mlp_refresh_half(tt_ctx* ctx, MlpDev& m);
+void mlp_half_values(tt_ctx* ctx, const MlpDev& m, float* out_dev);
+
 // ------------------------------------------------------- kernel launchers
 // op codes for GEMM operands
 enum { OPN = 0, OPT = 1, OPC = 2 };

@@ -165,6 +165,14 @@ _SIGS = {
     "tt_step": (I, [P, P, P, D, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport)]),
     "tt_eval": (I, [P, P, P, ctypes.c_int64, P]),
     "tt_norm": (I, [P, P, PD]),
+    "tt_mlp_create": (I, [P, I, I, I, ctypes.POINTER(P)]),
+    "tt_mlp_destroy": (I, [P]),
+    "tt_mlp_param_count": (I, [P]),
+    "tt_mlp_set_params": (I, [P, P, P]),
+    "tt_mlp_get_params": (I, [P, P, P, I]),
+    "tt_mlp_forward": (I, [P, P, P, I, P]),
+    "tt_mlp_gradients": (I, [P, P, P, P, I, ctypes.POINTER(ctypes.c_float), P]),
+    "tt_mlp_train": (I, [P, P, P, P, I, I, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]),
     "tt_round_randomized": (I, [P, P, PI, ctypes.c_uint64, P, PD]),
     "tt_step_batch": (I, [I, P, P, P, PD, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport), PI]),
     "tt_op_create_burgers_hopf_ex": (I, [P, I, I, D, D, P, P]),
@@ -496,6 +504,62 @@ def tt_round_randomized(ctx, x, widths, seed, y):
     e = D()
     ctx.check(lib().tt_round_randomized(ctx.h, x.h, _ip(w), int(seed), y.h, ctypes.byref(e)))
     return e.value
+
+
+class MLP:
+    """The rank predictor network on the device (see tt_mlp_* in the
+    header); inputs and targets are torch float32 tensors on the device."""
+
+    def __init__(self, ctx, n_in, width, max_batch):
+        self.ctx, self.n_in, self.width = ctx, n_in, width
+        h = P()
+        ctx.check(lib().tt_mlp_create(ctx.h, n_in, width, max_batch, ctypes.byref(h)))
+        self.h = h
+        self.nparams = lib().tt_mlp_param_count(h)
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        self.ctx.check(lib().tt_mlp_set_params(self.ctx.h, self.h, a.ctypes.data_as(P)))
+
+    def get_params(self, as_used=False):
+        a = np.empty(self.nparams, dtype=np.float32)
+        self.ctx.check(lib().tt_mlp_get_params(self.ctx.h, self.h, a.ctypes.data_as(P), int(bool(as_used))))
+        return a
+
+    def forward(self, x):
+        import torch
+
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        cur = torch.cuda.current_stream()
+        if self.ctx.torch_stream is not None:
+            self.ctx.torch_stream.wait_stream(cur)
+        self.ctx.check(lib().tt_mlp_forward(self.ctx.h, self.h, P(x.data_ptr()), int(x.shape[0]), P(y.data_ptr())))
+        self.ctx.sync()
+        return y
+
+    def gradients(self, x, t):
+        import torch
+
+        torch.cuda.synchronize()
+        loss = ctypes.c_float()
+        g = np.empty(self.nparams, dtype=np.float32)
+        self.ctx.check(lib().tt_mlp_gradients(self.ctx.h, self.h, P(x.data_ptr()), P(t.data_ptr()), int(x.shape[0]),
+                                              ctypes.byref(loss), g.ctypes.data_as(P)))
+        return loss.value, g
+
+    def train(self, x, t, iters, lr):
+        import torch
+
+        torch.cuda.synchronize()
+        loss = ctypes.c_float()
+        self.ctx.check(lib().tt_mlp_train(self.ctx.h, self.h, P(x.data_ptr()), P(t.data_ptr()), int(x.shape[0]),
+                                          int(iters), float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if self.h:
+            lib().tt_mlp_destroy(self.h)
+            self.h = None
 
 
 def tt_norm(ctx, x):
