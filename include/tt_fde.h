@@ -236,6 +236,9 @@ typedef struct {
   double sigma_min_kept[TT_MAX_D];
   double norm;                 /* ||x|| before truncation */
   int jacobi_sweeps_max;
+  int pad;
+  double sv_last[TT_MAX_D][8]; /* per bond the 8 smallest kept singular values,
+                                  decreasing, zeros in front when fewer */
 } tt_round_report;
 
 /* TT rounding (App. A.1, Alg. 2 mirrored): right-to-left orthogonalisation
@@ -263,12 +266,28 @@ typedef struct {
   int gmres_max_iter;    /* implicit schemes: Krylov dimension, 1..40 */
   int krylov_rmax;       /* implicit schemes: rank cap of the Krylov vectors
                             (0: 2 rmax), at most 256 */
+  const int* learned_widths; /* learned form (RK4): NULL, or d+1 per-bond sketch
+                            widths (entries 1..512; the end entries are
+                            ignored). Every truncation of a sum in the step
+                            (the stage inputs and the final combination) is
+                            then a randomised rounding to these widths
+                            (tt_round_randomized), accepted when its a
+                            posteriori relative error is at most
+                            learned_tol and finished by the deterministic
+                            rounding of its small result; otherwise the
+                            deterministic rounding of the sum is used */
+  double learned_tol;    /* relative error accepted from a randomised rounding */
 } tt_step_opts;
 
 typedef struct {
   int stages;
   int max_rank;          /* largest rank of any truncated tensor in the step */
   int ranks[TT_MAX_D + 1];
+  int learned_used;      /* randomised truncations tried (learned form) */
+  int learned_fallback;  /* ... of which missed learned_tol (deterministic used) */
+  double learned_err;    /* the largest a posteriori relative error among them */
+  double final_norm;     /* norm of the final combination (explicit schemes) */
+  double final_sv[TT_MAX_D][8]; /* sv_last of the final rounding */
 } tt_step_report;
 
 /* One step-truncation step of df/dt = L f, in place, T = tt_round(eps,
@@ -426,8 +445,8 @@ int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out);
 int tt_qr(tt_ctx* ctx, int m, int k, const double* A, int64_t lda, double* Q, double* R);
 
 /* Building block exposed for testing: one-sided Jacobi SVD of the small
- * factor of a TT truncation (App. A.4): B (m x k, ld m, m <= 512 and
- * k <= 512, overwritten) has left singular vectors U (m x k, ld m; columns
+ * factor of a TT truncation (App. A.4): B (m x k, ld m, m <= 1024 and
+ * k <= 1024, overwritten) has left singular vectors U (m x k, ld m; columns
  * in order of decreasing singular value, a zero column for a zero singular
  * value) and singular values sigma (k doubles, decreasing).  sweeps
  * (host int, may be null) receives the number of sweeps.  Device pointers;

@@ -438,6 +438,10 @@ void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_repo
     if (rep) {
       rep->tail[c] = tail;
       rep->sigma_min_kept[c] = s[kk - 1];
+      for (int j = 0; j < 8; ++j) {
+        const int idx = kk - 8 + j;
+        rep->sv_last[c][j] = idx >= 0 ? s[idx] : 0.0;
+      }
     }
   }
   x->orth = TT_ORTH_LEFT;
@@ -1428,6 +1432,9 @@ void check_solve_opts(const tt_solve_opts& o) {
           "TT-GMRES: unknown precision");
 }
 
+void randomized_into(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y);
+double sum_rel_error(tt_ctx* ctx, int npieces, const zc* coef, const tt_tensor* const* pieces, const tt_tensor* y);
+
 int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step_opts* opts, tt_step_report* rep) {
   if (!ctx || !op || !f || !opts) return TT_EINVAL;
   ABI_TRY
@@ -1438,6 +1445,13 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
   const int scheme = opts->scheme;
   require(scheme >= TT_STEP_RK4 && scheme <= TT_STEP_IMPLICIT_MIDPOINT, TT_EINVAL, "tt_step: unknown scheme");
   const bool implicit = scheme == TT_STEP_IMPLICIT_EULER || scheme == TT_STEP_IMPLICIT_MIDPOINT;
+  if (opts->learned_widths) {
+    require(scheme == TT_STEP_RK4, TT_EINVAL, "tt_step: learned_widths needs the RK4 scheme");
+    require(opts->learned_tol >= 0.0, TT_EINVAL, "tt_step: learned_tol must be >= 0");
+    for (int k = 0; k <= f->d; ++k)
+      require(opts->learned_widths[k] >= 1 && opts->learned_widths[k] <= 512, TT_EINVAL,
+              "tt_step: learned_widths outside [1, 512]");
+  }
   tt_solve_opts so{};
   if (implicit) {
     so.size = sizeof(so);
@@ -1492,6 +1506,40 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
   auto track = [&](const tt_tensor* t) {
     for (int k = 0; k <= d; ++k) maxr = std::max(maxr, t->rank[k]);
   };
+  // T[x] of a sum x = sum_i coef_i pieces_i: the deterministic rounding, or
+  // (learned form, given widths) the randomised rounding to those widths
+  // followed by the deterministic rounding of its small result when the a
+  // posteriori error is within learned_tol, else the deterministic rounding
+  // of x itself (fallback). Returns the tensor holding the result.
+  int learned_used = 0, learned_fallback = 0;
+  double learned_err = 0.0;
+  std::vector<const tt_tensor*> final_pieces;
+  std::vector<zc> final_coef;
+  auto truncate = [&](tt_tensor* x, int npieces, const zc* coef, const tt_tensor* const* pieces, const char* slot,
+                      uint64_t salt, tt_round_report* rrep) -> tt_tensor* {
+    if (!opts->learned_widths || npieces == 0) {
+      round_tensor(ctx, x, eps, rmax, rrep);
+      return x;
+    }
+    std::vector<int> w(d + 1, 1);
+    int wmax = 1;
+    for (int k = 1; k < d; ++k) {
+      w[k] = std::max(1, std::min(opts->learned_widths[k], x->rank[k]));
+      wmax = std::max(wmax, w[k]);
+    }
+    tt_tensor* y = pooled(ctx, slot, d, n, interior_caps(d, std::max(wmax, rmax)));
+    randomized_into(ctx, x, w.data(), opts->seed ^ (0xA5A5A5A5ull * salt), y);
+    const double err = sum_rel_error(ctx, npieces, coef, pieces, y);
+    ++learned_used;
+    learned_err = std::max(learned_err, err);
+    if (err <= opts->learned_tol) {
+      round_tensor(ctx, y, eps, rmax, rrep);
+      return y;
+    }
+    ++learned_fallback;
+    round_tensor(ctx, x, eps, rmax, rrep);
+    return x;
+  };
   // stage s: k_s = T[L y_s] with its own sketch seed
   auto stage = [&](int s, const tt_tensor* in) {
     apply_any(ctx, op, in, T.k[s], mode, l, opts->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(s + 1), opts->precision);
@@ -1508,14 +1556,15 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
         const tt_tensor* xs[2] = {f, T.k[s]};
         const zc coef[2] = {Z(1), Z(cst[s])};
         sum_tensors(ctx, 2, coef, xs, T.ysum);
-        round_tensor(ctx, T.ysum, eps, rmax, nullptr);
-        track(T.ysum);
-        stage_in = T.ysum;
+        stage_in = truncate(T.ysum, 2, coef, xs, "learned_ys", (uint64_t)s + 1, nullptr);
+        track(stage_in);
       }
     }
     const tt_tensor* xs[5] = {f, T.k[0], T.k[1], T.k[2], T.k[3]};
     const zc coef[5] = {Z(1), Z(dt / 6), Z(dt / 3), Z(dt / 3), Z(dt / 6)};
     sum_tensors(ctx, 5, coef, xs, T.fsum);
+    final_pieces.assign(xs, xs + 5);
+    final_coef.assign(coef, coef + 5);
     stages = 4;
   } else if (scheme == TT_STEP_EULER) {
     stage(0, f);
@@ -1568,9 +1617,23 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
       fail(TT_ENOCONV, "tt_step: TT-GMRES reached relative residual " + std::to_string(gr.residual) + " after " +
                            std::to_string(gr.iterations) + " iterations (tolerance " + std::to_string(so.tol) + ")");
   }
-  if (!implicit) round_tensor(ctx, T.fsum, eps, rmax, nullptr);  // the solver's output is truncated
-  track(T.fsum);
-  copy_tensor(ctx, T.fsum, f);
+  tt_round_report frep;
+  std::memset(&frep, 0, sizeof(frep));
+  const tt_tensor* result = T.fsum;
+  if (!implicit)  // (the implicit solver's output is truncated already)
+    result = truncate(T.fsum, (int)final_pieces.size(), final_coef.data(), final_pieces.data(), "learned_yf", 5,
+                      &frep);
+  if (rep) {
+    rep->learned_used = learned_used;
+    rep->learned_fallback = learned_fallback;
+    rep->learned_err = learned_err;
+  }
+  track(result);
+  copy_tensor(ctx, result, f);
+  if (rep) {
+    rep->final_norm = frep.norm;
+    std::memcpy(rep->final_sv, frep.sv_last, sizeof(frep.sv_last));
+  }
   if (rep) {
     rep->stages = stages;
     rep->max_rank = maxr;
@@ -1666,14 +1729,43 @@ const tt_op* identity_op(tt_ctx* ctx, int d, int n) {
 // the identity operator (left Gaussian TT sketches, right-to-left sweep of
 // LQ factorisations; right-orthonormal result of ranks <= widths), and its
 // relative error ||x - y|| / ||x|| from exact TT inner products.
-double round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y) {
+void randomized_into(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y) {
   const tt_op* op = identity_op(ctx, x->d, x->n);
   int l = 1;
   for (int k = 0; k <= x->d; ++k) l = std::max(l, widths[k]);
   apply_sketch(ctx, op, x, y, l, seed, TT_PREC_FP64, widths);
+}
+
+double round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y) {
+  randomized_into(ctx, x, widths, seed, y);
   const zc xx = dot_tensors(ctx, x, x), yy = dot_tensors(ctx, y, y), xy = dot_tensors(ctx, x, y);
   const double e2 = xx.x + yy.x - 2.0 * xy.x;
   return xx.x > 0.0 ? std::sqrt(std::max(0.0, e2) / xx.x) : 0.0;
+}
+
+// ||x - y|| / ||x|| for x = sum_i coef_i pieces_i, expanded over the pieces
+// so that no inner product involves the wide concatenated sum:
+// ||x||^2 = sum_ij conj(c_i) c_j <p_i, p_j>, <x, y> = sum_i conj(c_i) <p_i, y>.
+// Norms of orthogonalised pieces (and of y, right-orthonormal) come from one
+// core. The expansion cancels: it resolves errors down to about 1e-7.
+double sum_rel_error(tt_ctx* ctx, int npieces, const zc* coef, const tt_tensor* const* pieces, const tt_tensor* y) {
+  double xx = 0.0, xy = 0.0;
+  for (int i = 0; i < npieces; ++i) {
+    const double ci2 = coef[i].x * coef[i].x + coef[i].y * coef[i].y;
+    const double ni = tensor_norm(ctx, pieces[i]);
+    xx += ci2 * ni * ni;
+    for (int j = i + 1; j < npieces; ++j) {
+      const zc g = dot_tensors(ctx, pieces[i], pieces[j]);
+      // 2 Re(conj(c_i) c_j g)
+      const zc cc = {coef[i].x * coef[j].x + coef[i].y * coef[j].y, coef[i].x * coef[j].y - coef[i].y * coef[j].x};
+      xx += 2.0 * (cc.x * g.x - cc.y * g.y);
+    }
+    const zc h = dot_tensors(ctx, pieces[i], y);
+    xy += coef[i].x * h.x + coef[i].y * h.y;  // Re(conj(c_i) h)
+  }
+  const double ny = tensor_norm(ctx, y);
+  const double e2 = xx + ny * ny - 2.0 * xy;
+  return xx > 0.0 ? std::sqrt(std::max(0.0, e2) / xx) : 0.0;
 }
 
 int tt_round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y,
@@ -1773,7 +1865,7 @@ int tt_qr(tt_ctx* ctx, int m, int k, const double* A, int64_t lda, double* Q, do
 int tt_svd_small(tt_ctx* ctx, int m, int k, double* B, double* U, double* sigma, int* sweeps) {
   if (!ctx) return TT_EINVAL;
   ABI_TRY
-  require(m >= 1 && k >= 1 && m <= 512 && k <= 512, TT_EINVAL, "tt_svd_small: need 1 <= m, k <= 512");
+  require(m >= 1 && k >= 1 && m <= 1024 && k <= 1024, TT_EINVAL, "tt_svd_small: need 1 <= m, k <= 1024");
   require(B && U && sigma, TT_EINVAL, "tt_svd_small: null pointer");
   int* sw = (int*)ctx->get_ws("svd_small_sweeps", 64);
   jacobi_svd(ctx, m, k, (zc*)B, (zc*)U, sigma, sw);

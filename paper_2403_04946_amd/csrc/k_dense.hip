@@ -19,7 +19,7 @@
 
 namespace ttf {
 
-constexpr int JB_NORMS = 512;  // columns of the finishing kernel
+constexpr int JB_NORMS = 1024;  // columns of the finishing kernel
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -43,8 +43,9 @@ constexpr int JAC_THREADS = 1024;
 constexpr int JAC_GROUPS = JAC_THREADS / 16;
 constexpr int JAC_MAX_SWEEPS = 60;
 constexpr int JB_COLS = 8;     // columns per block
-constexpr int JB_MAXM = 512;   // rows supported by the register-resident form
-constexpr int JB_MAXK = 512;   // columns
+constexpr int JB_MAXM = 1024;  // rows supported by the register-resident form
+constexpr int JB_MAXK = 1024;  // columns
+constexpr int JB_XCHUNK = 8;   // rows per lane moved through LDS at a time
 constexpr int JB_MAXS = 64;    // sweep counters
 
 // round-robin pairing of players 0..P-1 (P even) in round r
@@ -63,7 +64,7 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
 
 void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
   if (k <= 0) return;
-  if (k > JB_MAXK || m > JB_MAXM || m < 1) fail(TT_EINVAL, "jacobi_svd: sizes above the supported maximum of 512");
+  if (k > JB_MAXK || m > JB_MAXM || m < 1) fail(TT_EINVAL, "jacobi_svd: sizes above the supported maximum of 1024");
   std::string shape;
   if (ctx->profile_shapes) shape = "jacobi:" + std::to_string(m) + "x" + std::to_string(k);
   KTimer kt2(ctx->profile_shapes ? ctx : nullptr, shape.c_str(), 0.0, 0.0);
@@ -142,12 +143,13 @@ template <int RPL, int W, int GS>
 __global__ __launch_bounds__(GS * W) void jacobi_circle_kernel(zc* __restrict__ B, int m, int k, int inner_max,
                                                                int sweep, int* __restrict__ rot, double tol,
                                                                const double* __restrict__ fro2) {
-  extern __shared__ double2 xch[];  // W slots of GS RPL rows
+  extern __shared__ double2 xch[];  // W slots of GS XC rows
   __shared__ int wg_rot;
   if (sweep > 0 && rot[sweep - 1] == 0) return;
   const double abs2 = 1e-30 * fro2[0];  // (1e-15 |B|_F)^2
   constexpr int NP = 2 * W - 1;
-  constexpr int LD = GS * RPL;
+  constexpr int XC = RPL < JB_XCHUNK ? RPL : JB_XCHUNK;  // rows per lane per exchange
+  constexpr int LD = GS * XC;
   const int c0 = blockIdx.x * 2 * W;
   const int w = threadIdx.x / GS, lane = threadIdx.x % GS;
   zc xt[RPL], xb[RPL];
@@ -171,28 +173,37 @@ __global__ __launch_bounds__(GS * W) void jacobi_circle_kernel(zc* __restrict__ 
       // shift: bottoms move to the previous group (the last one takes its
       // own top), then tops to the next one (group 1 takes group 0's old
       // bottom, left in slot 0 by the first phase)
-      __syncthreads();
+      // (the rows go through LDS XC per lane at a time)
 #pragma unroll
-      for (int j = 0; j < RPL; ++j) mine[lane + GS * j] = xb[j];
-      __syncthreads();
-      if (w <= W - 2) {
-        const zc* src = mine + LD;
+      for (int c = 0; c < RPL; c += XC) {
+        __syncthreads();
 #pragma unroll
-        for (int j = 0; j < RPL; ++j) xb[j] = src[lane + GS * j];
-      } else {
+        for (int j = 0; j < XC; ++j)
+          if (c + j < RPL) mine[lane + GS * j] = xb[c + j];
+        __syncthreads();
+        if (w <= W - 2) {
+          const zc* src = mine + LD;
 #pragma unroll
-        for (int j = 0; j < RPL; ++j) xb[j] = xt[j];
-      }
-      __syncthreads();
-      if (w >= 1 && w <= W - 2) {
+          for (int j = 0; j < XC; ++j)
+            if (c + j < RPL) xb[c + j] = src[lane + GS * j];
+        } else {
 #pragma unroll
-        for (int j = 0; j < RPL; ++j) mine[lane + GS * j] = xt[j];
-      }
-      __syncthreads();
-      if (w >= 1) {
-        const zc* src = mine - LD;
+          for (int j = 0; j < XC; ++j)
+            if (c + j < RPL) xb[c + j] = xt[c + j];
+        }
+        __syncthreads();
+        if (w >= 1 && w <= W - 2) {
 #pragma unroll
-        for (int j = 0; j < RPL; ++j) xt[j] = src[lane + GS * j];
+          for (int j = 0; j < XC; ++j)
+            if (c + j < RPL) mine[lane + GS * j] = xt[c + j];
+        }
+        __syncthreads();
+        if (w >= 1) {
+          const zc* src = mine - LD;
+#pragma unroll
+          for (int j = 0; j < XC; ++j)
+            if (c + j < RPL) xt[c + j] = src[lane + GS * j];
+        }
       }
     }
     const int tot = jacobi_count(nrot, &wg_rot, rot, sweep + it);
@@ -217,11 +228,12 @@ template <int RPL, int GS, int BC>
 __global__ __launch_bounds__(BC * GS) void jacobi_cross_kernel(zc* __restrict__ B, int m, int k, int P, int round,
                                                                int sweep, int* __restrict__ rot, double tol,
                                                                const double* __restrict__ fro2) {
-  extern __shared__ double2 xch[];  // BC slots of GS RPL rows
+  extern __shared__ double2 xch[];  // BC slots of GS XC rows
   __shared__ int wg_rot;
   if (sweep > 0 && rot[sweep - 1] == 0) return;
   const double abs2 = 1e-30 * fro2[0];  // (1e-15 |B|_F)^2
-  constexpr int LD = GS * RPL;
+  constexpr int XC = RPL < JB_XCHUNK ? RPL : JB_XCHUNK;  // rows per lane per exchange
+  constexpr int LD = GS * XC;
   int ba, bb;
   rr_pair(P, round, blockIdx.x, ba, bb);
   const int w = threadIdx.x / GS, lane = threadIdx.x % GS;
@@ -243,12 +255,17 @@ __global__ __launch_bounds__(BC * GS) void jacobi_cross_kernel(zc* __restrict__ 
     const int cb = bb * BC + (w + st) % BC;
     if (ca < k && cb < k) nrot += jacobi_rotate<RPL, GS>(xa, xb, tol, abs2);
     if (st == BC - 1) break;
-    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) mine[lane + GS * j] = xb[j];
-    __syncthreads();
+    for (int c = 0; c < RPL; c += XC) {
+      __syncthreads();
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) xb[j] = next[lane + GS * j];
+      for (int j = 0; j < XC; ++j)
+        if (c + j < RPL) mine[lane + GS * j] = xb[c + j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < XC; ++j)
+        if (c + j < RPL) xb[c + j] = next[lane + GS * j];
+    }
   }
   jacobi_count(nrot, &wg_rot, rot, sweep);
   const int cb = bb * BC + (w + BC - 1) % BC;
@@ -313,7 +330,7 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(int m, int k, const
 template <int RPL, int GS>
 void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int round, int inner_max, int sweep,
                        int* rot, double tol, const double* fro2) {
-  const size_t slot = sizeof(zc) * GS * RPL;
+  const size_t slot = sizeof(zc) * GS * (RPL < JB_XCHUNK ? RPL : JB_XCHUNK);
   // algorithmic work: a column pair that meets costs 16 m flops for its
   // three inner products and 24 m for the rotation (counted as applied);
   // bytes: the columns read and written once
@@ -330,10 +347,13 @@ void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int ro
     cols = 2.0 * JB_COLS * (P / 2);
   }
   KTimer kt(ctx, kind == 2 ? "jacobi_cross" : "jacobi_circle", pair * pairs, 2.0 * 16.0 * m * cols, true);
-  if (kind == 0)  // whole matrix (k <= 32) in one workgroup
-    TTF_LAUNCH(kt, (jacobi_circle_kernel<RPL, 16, GS>), dim3(1), dim3(16 * GS), 16 * slot, ctx->stream, B, m, k,
-               inner_max, sweep, rot, tol, fro2);
-  else if (kind == 1)  // every block of JB_COLS columns on its own
+  if (kind == 0) {  // whole matrix (k <= 32, at most 320 rows) in one workgroup
+    if constexpr (GS == 32)
+      TTF_LAUNCH(kt, (jacobi_circle_kernel<RPL, 16, GS>), dim3(1), dim3(16 * GS), 16 * slot, ctx->stream, B, m, k,
+                 inner_max, sweep, rot, tol, fro2);
+    else
+      fail(TT_EINVAL, "jacobi_svd: single-workgroup form needs at most 320 rows");
+  } else if (kind == 1)  // every block of JB_COLS columns on its own
     TTF_LAUNCH(kt, (jacobi_circle_kernel<RPL, JB_COLS / 2, GS>), dim3((k + JB_COLS - 1) / JB_COLS),
                dim3(JB_COLS / 2 * GS), JB_COLS / 2 * slot, ctx->stream, B, m, k, 1, sweep, rot, tol, fro2);
   else
@@ -350,7 +370,7 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
   double* fro2 = (double*)(rot + JB_MAXS);
   frob_norm2(ctx, B, (long)m * k, fro2);
   // a 32-lane group per column pair up to 320 rows (at most 10 rows per
-  // lane), a whole wavefront beyond
+  // lane), a whole wavefront beyond (up to 16 rows per lane)
   auto launch = [&](int kind, int P, int round, int inner_max, int sweep, int* rot, double tol) {
     const double* f2 = fro2;
     if (m <= 64)
@@ -363,8 +383,12 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
       jacobi_launch_rpl<8, 32>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else if (m <= 320)
       jacobi_launch_rpl<10, 32>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
-    else
+    else if (m <= 512)
       jacobi_launch_rpl<8, 64>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
+    else if (m <= 640)
+      jacobi_launch_rpl<10, 64>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
+    else
+      jacobi_launch_rpl<16, 64>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
   };
   const double tol = 1e-15 * sqrt((double)m);
   const int nblk = (k + JB_COLS - 1) / JB_COLS;
@@ -372,7 +396,7 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, ctx->stream, rot, JB_MAXS);
   TTF_HIP(hipGetLastError());
   int nsweeps = 0;
-  if (k <= 32) {
+  if (k <= 32 && m <= 320) {
     launch(0, 2, 0, JAC_MAX_SWEEPS, 0, rot, tol);
     nsweeps = JAC_MAX_SWEEPS;
   } else {

@@ -53,6 +53,8 @@ class RoundReport(ctypes.Structure):
         ("sigma_min_kept", ctypes.c_double * MAX_D),
         ("norm", ctypes.c_double),
         ("jacobi_sweeps_max", ctypes.c_int),
+        ("pad", ctypes.c_int),
+        ("sv_last", (ctypes.c_double * 8) * MAX_D),
     ]
 
 
@@ -79,6 +81,8 @@ class StepOpts(ctypes.Structure):
         ("gmres_tol", ctypes.c_double),
         ("gmres_max_iter", ctypes.c_int),
         ("krylov_rmax", ctypes.c_int),
+        ("learned_widths", ctypes.POINTER(ctypes.c_int)),
+        ("learned_tol", ctypes.c_double),
     ]
 
 
@@ -123,6 +127,11 @@ class StepReport(ctypes.Structure):
         ("stages", ctypes.c_int),
         ("max_rank", ctypes.c_int),
         ("ranks", ctypes.c_int * (MAX_D + 1)),
+        ("learned_used", ctypes.c_int),
+        ("learned_fallback", ctypes.c_int),
+        ("learned_err", ctypes.c_double),
+        ("final_norm", ctypes.c_double),
+        ("final_sv", (ctypes.c_double * 8) * MAX_D),
     ]
 
 
@@ -413,16 +422,31 @@ def tt_round(ctx, x, eps, rmax=0, report=True):
         "sigma_min_kept": list(rep.sigma_min_kept[: max(d - 1, 0)]),
         "norm": rep.norm,
         "jacobi_sweeps_max": rep.jacobi_sweeps_max,
+        "sv_last": [list(rep.sv_last[c]) for c in range(max(d - 1, 0))],
     }
 
 
 def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0,
-            scheme=TT_STEP_RK4, gmres_tol=1e-10, gmres_max_iter=30, krylov_rmax=0):
+            scheme=TT_STEP_RK4, gmres_tol=1e-10, gmres_max_iter=30, krylov_rmax=0,
+            learned_widths=None, learned_tol=1e-6):
+    """One step; ``learned_widths`` (d+1 ints) selects the learned form, whose
+    truncations of sums are randomised roundings to these widths, checked."""
+    widths = None
+    if learned_widths is not None:
+        if len(learned_widths) != f.d + 1:
+            raise ValueError("learned_widths needs d+1 entries")
+        widths = (ctypes.c_int * (f.d + 1))(*[int(w) for w in learned_widths])
     o = StepOpts(ctypes.sizeof(StepOpts), int(rmax), float(eps), int(mode), int(sketch_rank), int(seed),
-                 int(precision), int(scheme), float(gmres_tol), int(gmres_max_iter), int(krylov_rmax))
+                 int(precision), int(scheme), float(gmres_tol), int(gmres_max_iter), int(krylov_rmax),
+                 ctypes.cast(widths, ctypes.POINTER(ctypes.c_int)) if widths is not None else None,
+                 float(learned_tol))
     rep = StepReport()
     ctx.check(lib().tt_step(ctx.h, op.h, f.h, float(dt), ctypes.byref(o), ctypes.byref(rep)))
-    return {"stages": rep.stages, "max_rank": rep.max_rank, "ranks": list(rep.ranks[: f.d + 1])}
+    nb = max(f.d - 1, 0)
+    return {"stages": rep.stages, "max_rank": rep.max_rank, "ranks": list(rep.ranks[: f.d + 1]),
+            "learned_used": rep.learned_used, "learned_fallback": rep.learned_fallback,
+            "learned_err": rep.learned_err, "final_norm": rep.final_norm,
+            "final_sv": [list(rep.final_sv[c]) for c in range(nb)]}
 
 
 def tt_step_batch(ctxs, ops, fs, dts, rmaxs, epss, mode=TT_APPLY_EXACT, sketch_ranks=None, seeds=None,

@@ -112,7 +112,7 @@ def test_qr_and_svd_reject_bad_shapes(ctx):
     null = tt.P(0)
     assert tt.lib().tt_qr(ctx.h, 4, 8, null, 4, null, null) == -1  # m < k
     assert tt.lib().tt_qr(ctx.h, 8, 0, null, 8, null, null) == -1  # k < 1
-    assert tt.lib().tt_svd_small(ctx.h, 513, 4, null, null, null, None) == -1  # beyond 512 rows
+    assert tt.lib().tt_svd_small(ctx.h, 1025, 4, null, null, null, None) == -1  # beyond 1024 rows
     ctx.sync()
 
 
@@ -129,7 +129,7 @@ def _svd(ctx, b):
 
 
 @pytest.mark.parametrize("m,k", [(1, 1), (16, 16), (33, 33), (80, 80), (128, 128), (320, 320), (500, 500), (200, 50),
-                                 (64, 100)])
+                                 (64, 100), (640, 640), (700, 24), (1000, 1000), (1024, 300)])
 def test_svd_small_matches_numpy(ctx, m, k):
     rng = np.random.default_rng(m + 7 * k)
     b = _cplx(rng, m, k)

@@ -116,3 +116,115 @@ def test_mlp_training_is_deterministic_and_learns(ctx):
     print(f"training loss {l0:.4f} -> {l1:.4f}")
     assert l1 < 0.1 * l0
     assert l1 == l1b and np.array_equal(p1, p2)
+
+
+# ------------------------------------------------------------------ learned step
+def _instances(count, seed, d_range):
+    return inputs.batch_instances(count, seed, d_range=d_range, n_choices=(64,), nu_range=(0.02, 0.1),
+                                  cap_range=(64, 64))
+
+
+LEN_L, DT_L, EPS_L, ELL_L = 12.0, 5e-4, 1e-6, 80
+
+
+def _rel_tt(ctx, a, b):
+    """||a - b|| / ||b|| from TT inner products (resolves about 1e-8)."""
+    aa = tt.tt_dot(ctx, a, a).real
+    bb = tt.tt_dot(ctx, b, b).real
+    ab = tt.tt_dot(ctx, a, b).real
+    return float(np.sqrt(max(aa + bb - 2 * ab, 0.0) / bb))
+
+
+def _trajectory(ctx, inst, steps, predictor=None, seed=0):
+    from paper_2403_04946_amd import learned
+
+    d, n, nu, cap = inst["d"], inst["n"], inst["nu"], inst["cap"]
+    op = tt.Operator(ctx, d, n, LEN_L, nu)
+    f = tt.Tensor(ctx, d, n, cap)
+    f.set_gaussian(inst["mu"], inst["sigma"], LEN_L)
+    recs = learned.run_trajectory(ctx, op, f, steps, DT_L, cap, EPS_L, ELL_L, nu, predictor=predictor, seed=seed)
+    return op, f, recs
+
+
+def test_learned_step_widths_checked_and_fallback(ctx):
+    """The learned step with given widths: accepted when the widths cover
+    the ranks the deterministic rounding keeps (result within the
+    tolerance of the plain step), and the deterministic fallback, bit for
+    bit the plain step, when they are too small."""
+    inst = _instances(1, 5, (8, 8))[0]
+    d, n, nu, cap = inst["d"], inst["n"], inst["nu"], inst["cap"]
+    op = tt.Operator(ctx, d, n, LEN_L, nu)
+    a = tt.Tensor(ctx, d, n, cap)
+    a.set_gaussian(inst["mu"], inst["sigma"], LEN_L)
+    for s in range(3):
+        tt.tt_step(ctx, op, a, DT_L, cap, EPS_L, tt.TT_APPLY_SKETCH, ELL_L, s)
+    b = tt.Tensor(ctx, d, n, cap)
+    c = tt.Tensor(ctx, d, n, cap)
+    b.copy_from(a)
+    c.copy_from(a)
+    rp = tt.tt_step(ctx, op, a, DT_L, cap, EPS_L, tt.TT_APPLY_SKETCH, ELL_L, 9)
+    wide = [1] + [r + 8 for r in rp["ranks"][1:-1]] + [1]
+    rl = tt.tt_step(ctx, op, b, DT_L, cap, EPS_L, tt.TT_APPLY_SKETCH, ELL_L, 9, learned_widths=wide,
+                    learned_tol=1e-6)
+    print("accepted:", rl["learned_used"], rl["learned_fallback"], rl["learned_err"])
+    assert rl["learned_used"] == 4 and rl["learned_fallback"] == 0 and rl["learned_err"] <= 1e-6
+    assert _rel_tt(ctx, b, a) < 1e-5
+    narrow = [1] + [2] * (d - 1) + [1]
+    rn = tt.tt_step(ctx, op, c, DT_L, cap, EPS_L, tt.TT_APPLY_SKETCH, ELL_L, 9, learned_widths=narrow,
+                    learned_tol=1e-6)
+    assert rn["learned_used"] == 4 and rn["learned_fallback"] == 4 and rn["learned_err"] > 1e-6
+    # the fallback is the plain step
+    assert c.ranks() == a.ranks()
+    assert all(np.array_equal(x, y) for x, y in zip(c.get_cores(), a.get_cores()))
+    with pytest.raises(ValueError):
+        tt.tt_step(ctx, op, c, DT_L, cap, EPS_L, tt.TT_APPLY_SKETCH, ELL_L, 9, learned_widths=narrow[:-1])
+    with pytest.raises(tt.TTError):
+        tt.tt_step(ctx, op, c, DT_L, cap, EPS_L, tt.TT_APPLY_SKETCH, ELL_L, 9, learned_widths=narrow,
+                   scheme=tt.TT_STEP_EULER)
+    for t_ in (a, b, c):
+        t_.close()
+
+
+def test_learned_form_gain_over_plain(ctx):
+    """The rank predictor trained on the GPU from plain-solver rank
+    histories, then the learned trajectory of a held-out instance against
+    the plain one from the same initial condition: what the network gains
+    (step time) and what it costs (difference to the plain trajectory,
+    fallbacks)."""
+    from paper_2403_04946_amd import learned
+
+    steps = 14
+    xs, ys = [], []
+    for inst in _instances(4, 21, (6, 12)):
+        op, f, recs = _trajectory(ctx, inst, steps)
+        x, y = learned.samples_from_records(recs)
+        xs.append(x)
+        ys.append(y)
+        f.close()
+    x, y = np.concatenate(xs), np.concatenate(ys)
+    pred = learned.RankPredictor(ctx, 64, max_batch=4096, seed=1)
+    l0, l1 = pred.fit(x, y)
+    print(f"{x.shape[0]} bond-step samples; training loss {l0:.4e} -> {l1:.4e}")
+    assert l1 < 0.05 * l0
+    test_inst = _instances(1, 77, (10, 10))[0]
+    op, fp, plain = _trajectory(ctx, test_inst, steps, seed=3)
+    # accuracy on the held-out trajectory: next ranks from this step's report
+    xt, yt = learned.samples_from_records(plain)
+    rhat = pred.predict(xt)
+    print("held-out rank error: mean |r^ - r| =", np.abs(rhat - yt).mean(), " max", np.abs(rhat - yt).max())
+    assert np.abs(rhat - yt).mean() < 2.0
+    _, fl, lrn = _trajectory(ctx, test_inst, steps, predictor=pred, seed=3)
+    used = sum(r["learned_used"] for r in lrn)
+    fb = sum(r["learned_fallback"] for r in lrn)
+    tp = float(np.median([r["wall"] for r in plain[1:]]))
+    tl = float(np.median([r["wall"] for r in lrn[1:]]))
+    diff = _rel_tt(ctx, fl, fp)
+    print(f"plain {tp * 1e3:.1f} ms/step, learned {tl * 1e3:.1f} ms/step (gain {tp / tl:.2f}x); "
+          f"randomised roundings {used}, fallbacks {fb}; difference to plain after {steps} steps {diff:.2e}")
+    assert used >= 4 * (steps - 1) - 4  # the predictor kept the learned path on
+    assert fb <= used // 4
+    assert diff < 2e-5
+    assert tl < tp
+    pred.close()
+    fp.close()
+    fl.close()

@@ -1,0 +1,56 @@
+"""Host logic of the learned form: the predictor's features, the width rule
+and the training pairs taken from a trajectory (no GPU)."""
+import math
+
+import numpy as np
+
+from paper_2403_04946_amd import learned
+
+
+def _report(d, rank, sv_scale):
+    ranks = [1] + [rank] * (d - 1) + [1]
+    sv = [[0.0] * 3 + [sv_scale * 10.0 ** (-j) for j in range(5)] for _ in range(d - 1)]
+    return ranks, sv
+
+
+def test_bond_features_layout():
+    d, rmax = 5, 32
+    ranks, sv = _report(d, 8, 2.0)
+    x = learned.bond_features(ranks, sv, 4.0, 0.05, 0.25, rmax)
+    assert x.shape == (d - 1, learned.N_FEATURES) and x.dtype == np.float32
+    assert np.allclose(x[:, 0], 8 / rmax)
+    # zeros in front of the tail are floored at 1e-20: log10 / 10 = -2
+    assert np.allclose(x[:, 1:4], -2.0)
+    # kept values relative to the norm: 2/4 * 10^-j
+    assert np.allclose(x[0, 4:9], [math.log10(0.5 * 10.0 ** (-j)) / 10 for j in range(5)], atol=1e-6)
+    assert np.allclose(x[:, 9], math.log10(0.05))
+    assert np.allclose(x[:, 10], 0.25)
+    assert np.allclose(x[:, 11], [k / d for k in range(1, d)])
+    assert np.allclose(x[:, 12], math.log10(4.0) / d)
+
+
+def test_widths_rule():
+    assert learned.widths_from_ranks([3, 5, 4], 4, 16) == [1, 11, 13, 12, 1]
+    assert learned.widths_from_ranks([3, 16, 4], 4, 16) is None  # a bond at the cap
+    assert learned.widths_from_ranks([0, 1], 3, 16) == [1, 9, 9, 1]
+    assert learned.widths_from_ranks([509], 2, 600) == [1, 512, 1]
+
+
+def test_samples_from_records_pairs_features_with_next_ranks():
+    recs = []
+    for s in range(3):
+        ranks, sv = _report(4, 2 + s, 1.0)
+        recs.append({"ranks": ranks, "features": learned.bond_features(ranks, sv, 1.0, 0.1, 0.1 * s, 16)})
+    x, y = learned.samples_from_records(recs)
+    assert x.shape == (6, learned.N_FEATURES)
+    assert np.array_equal(y, np.array([3, 3, 3, 4, 4, 4], dtype=np.float32))
+    assert np.array_equal(x[:3], recs[0]["features"]) and np.array_equal(x[3:], recs[1]["features"])
+    x0, y0 = learned.samples_from_records(recs[:1])
+    assert x0.shape == (0, learned.N_FEATURES) and y0.shape == (0,)
+
+
+def test_he_init_matches_the_parameter_count():
+    p = learned.he_init(13, 128, 0)
+    assert p.dtype == np.float32
+    assert p.size == 128 * 13 + 128 + 128 * 128 + 128 + 128 + 1
+    assert np.all(p[128 * 13:128 * 13 + 128] == 0)
