@@ -285,6 +285,114 @@ def main_batched(args):
     print(json.dumps(result), flush=True)
 
 
+def main_learned(args):
+    """Learned form: the rank predictor (device MLP) trained on rank
+    histories of plain trajectories, then held-out trajectories stepped in
+    the plain and the learned form from the same initial condition.
+    Instances: seeded Gaussian initial conditions, n = 64 on [-6, 6], nu
+    log-uniform 0.02..0.1, rank cap 64, eps = 1e-6, dt = 5e-4, sketched
+    apply of width 80 in FP64; training d uniform 6..16, held-out d 10..14.
+    These are tolerance-limited trajectories (ranks below the cap); where the
+    cap binds (the saturated metric shapes) the predicted ranks reach the
+    cap and the step runs plain."""
+    import numpy as np
+    import torch
+
+    from paper_2403_04946_amd import inputs, learned, tt
+
+    torch.cuda.init()
+    ctx = tt.Context(0)
+    length, dt, eps, ell, cap = 12.0, 5e-4, 1e-6, 80, 64
+
+    def instances(count, seed, d_range):
+        return inputs.batch_instances(count, seed, d_range=d_range, n_choices=(64,), nu_range=(0.02, 0.1),
+                                      cap_range=(cap, cap))
+
+    def trajectory(inst, steps, predictor=None, seed=0):
+        op = tt.Operator(ctx, inst["d"], inst["n"], length, inst["nu"])
+        f = tt.Tensor(ctx, inst["d"], inst["n"], cap)
+        f.set_gaussian(inst["mu"], inst["sigma"], length)
+        recs = learned.run_trajectory(ctx, op, f, steps, dt, cap, eps, ell, inst["nu"], predictor=predictor,
+                                      seed=seed)
+        return op, f, recs
+
+    t0 = time.perf_counter()
+    xs, ys = [], []
+    train = instances(args.train_instances, 21, (6, 16))
+    for i, inst in enumerate(train):
+        _, f, recs = trajectory(inst, args.train_steps)
+        x, y = learned.samples_from_records(recs)
+        xs.append(x)
+        ys.append(y)
+        f.close()
+        print(f"bench: training trajectory {i + 1}/{len(train)} (d={inst['d']}) done", file=sys.stderr, flush=True)
+    x, y = np.concatenate(xs), np.concatenate(ys)
+    capture_s = time.perf_counter() - t0
+    pred = learned.RankPredictor(ctx, cap, max_batch=max(4096, x.shape[0]), seed=1)
+    t0 = time.perf_counter()
+    l0, l1 = pred.fit(x, y)
+    train_s = time.perf_counter() - t0
+    print(f"bench: predictor trained on {x.shape[0]} samples", file=sys.stderr, flush=True)
+
+    def rel_tt(a, b):
+        aa, bb, ab = tt.tt_dot(ctx, a, a).real, tt.tt_dot(ctx, b, b).real, tt.tt_dot(ctx, a, b).real
+        return float(np.sqrt(max(aa + bb - 2 * ab, 0.0) / bb))
+
+    held = instances(args.instances_learned, 77, (10, 14))
+    tp = tl = 0.0
+    used = fb = 0
+    diffs, rank_err = [], []
+    for i, inst in enumerate(held):
+        _, fp, plain = trajectory(inst, args.steps + 1, seed=3)
+        _, fl, lrn = trajectory(inst, args.steps + 1, predictor=pred, seed=3)
+        # the first step of either has no report to predict from: untimed
+        tp += sum(r["wall"] for r in plain[1:])
+        tl += sum(r["wall"] for r in lrn[1:])
+        used += sum(r["learned_used"] for r in lrn)
+        fb += sum(r["learned_fallback"] for r in lrn)
+        diffs.append(rel_tt(fl, fp))
+        xt, yt = learned.samples_from_records(plain)
+        rank_err.append(float(np.abs(pred.predict(xt) - yt).mean()))
+        fp.close()
+        fl.close()
+        print(f"bench: held-out instance {i + 1}/{len(held)} (d={inst['d']}) done", file=sys.stderr, flush=True)
+    stages = 4 * args.steps * len(held)
+    result = {
+        "metric": "RK stages/sec, learned form vs plain (deterministic rounding) on the same trajectories",
+        "value": stages / tl,
+        "unit": "RK stages/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": 1e3 * tl / (args.steps * len(held)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ("Burgers-Hopf TT RK4 trajectories from seeded Gaussian initial conditions, tolerance-"
+                         "limited ranks: n=64 on [-6,6], nu 0.02..0.1, cap 64, eps 1e-6, dt 5e-4, sketched "
+                         "apply width 80, FP64; held-out d 10..14"),
+            "held_out_shapes": [[h["d"], h["n"], cap] for h in held],
+            "training": {"instances": len(train), "d_range": [6, 16], "steps": args.train_steps,
+                         "samples": int(x.shape[0]), "loss_before": l0, "loss_after": l1,
+                         "capture_s": capture_s, "train_s": train_s},
+        },
+        "plain_reference": {"value": stages / tp, "unit": "RK stages/s", "ms_per_step":
+                            1e3 * tp / (args.steps * len(held))},
+        "gain_over_plain": tp / tl,
+        "randomised_roundings": used,
+        "fallbacks": fb,
+        "rel_diff_to_plain_after_steps": diffs,
+        "predictor_mean_abs_rank_error": rank_err,
+        "learned_tol": 1e-6,
+        "roofline": None,
+    }
+    pred.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,9 +405,13 @@ def main():
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-error-report", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["metric", "batched"], default="metric",
-                    help="batched: the batched form on uneven instances (its own JSON line)")
+    ap.add_argument("--form", choices=["metric", "batched", "learned"], default="metric",
+                    help="batched: the batched form on uneven instances; learned: the learned form against the "
+                         "plain one on tolerance-limited trajectories (each its own JSON line)")
     ap.add_argument("--instances", type=int, default=16)
+    ap.add_argument("--train-instances", type=int, default=12)
+    ap.add_argument("--train-steps", type=int, default=20)
+    ap.add_argument("--instances-learned", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -309,6 +421,9 @@ def main():
         # do not share queues (set before the HIP runtime starts)
         os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
         main_batched(args)
+        return
+    if args.form == "learned":
+        main_learned(args)
         return
 
     import torch
