@@ -185,13 +185,42 @@ typedef struct {
 } tt_op_opts;
 int tt_op_create_burgers_hopf_ex(tt_ctx* ctx, int d, int n, double L, double nu, const tt_op_opts* opts,
                                  tt_op** out);
+/* The CDF equation (Sec. 5, eq. (eqn:cdf-burgers)): the joint cumulative
+ * distribution F(u_1..u_d, t) of the stochastic Burgers equation with
+ * reaction alpha sin(pi u) and viscosity gamma (eq. (eqn:burgers-rxn)) at d
+ * evenly spaced points of the circle, periodic second-order differences in
+ * x.  With D1, D2 those difference matrices (spacing 2 pi / d):
+ *   dF/dt = sum_i [-gamma D2_ii u_i - alpha sin(pi u_i)] dF/du_i
+ *         + sum_{i != j} [D1_ij u_i - gamma D2_ij] (u_j - J_j) dF/du_i
+ * (J_j the cumulative integral along u_j from the lower end; the reaction
+ * enters once).  Phase space [-box, box]^d with n points per axis, centred
+ * second-order differences with outflow boundaries (dF/du = 0 there),
+ * trapezoid rule for J.  Real coefficients; tensors stay complex (imaginary
+ * parts zero).  TT-matrix form over the local operators of
+ * tt_op_export_local_ops; bond dimension at most 10.  ctx may be NULL
+ * (host-only operator). */
+typedef struct {
+  int size;              /* sizeof(tt_cdf_opts) */
+  int pad;
+  double box;            /* half-width of the phase-space box (> 0) */
+  double gamma;          /* viscosity (>= 0) */
+  double alpha;          /* reaction amplitude */
+  double diffusion;      /* kappa >= 0: kappa sum_k d2F/du_k^2 (numerical diffusion) */
+} tt_cdf_opts;
+int tt_op_create_cdf_burgers(tt_ctx* ctx, int d, int n, const tt_cdf_opts* opts, tt_op** out);
+/* The CDF equation's initial condition: the product of zero-mean Gaussian
+ * CDFs 0.5 (1 + erf(u_k / (sigma sqrt 2))) on the grid of [-box, box]
+ * (rank one; needs interior capacity >= 1). */
+int tt_tensor_set_cdf_gaussian(tt_ctx* ctx, tt_tensor* t, double sigma, double box);
 int tt_op_destroy(tt_op* op);
 /* Bond dimensions R[0..d] of the operator's TT-matrix form. */
 int tt_op_get_ranks(const tt_op* op, int* R);
 /* Host-side export for inspection and tests (no device work):
  *   coefficients: B (d*d*d, index (k*d + j)*d + l) and D (d*d, k*d + j);
  *   local operators: nops*n*n doubles, op-major, row-major n x n matrices,
- *     in the order I, X, G, L2, XG, XL2 (returns nops via *nops);
+ *     in the order I, X, G, L2, XG, XL2, SG = diag(sin(pi u)) G,
+ *     K = X - J (J the cumulative trapezoid integral; the last two used by
+ *     the CDF equation) (returns nops via *nops);
  *   site entries: for site m (0-based) the transitions
  *     (alpha, beta, local op, coefficient re/im) of the automaton.
  *     Call with NULL arrays to query the count. */

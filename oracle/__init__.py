@@ -16,6 +16,9 @@ equations"):
 * ``fullgrid``     - the semi-discrete operator on the full grid, classical
                      RK4, and step-truncation with full-grid TT-SVD
                      (Sec. 4.1 eq. (eqn:discrete-flow-trunc-intro)).
+* ``cdf``          - the CDF equation of the stochastic Burgers equation
+                     with reaction (Sec. 5, eq. (eqn:cdf-burgers)) on the
+                     full grid, and its closed-form pins.
 * ``closed_forms`` - exact solutions used as pins (viscous-only transport,
                      per-axis matrix exponential, deterministic initial state).
 * ``tt_ref``       - TT format arithmetic written from App. A.1

@@ -773,8 +773,10 @@ void drop_ctx_caches(tt_ctx* ctx) {
 void upload_op(tt_ctx* ctx, tt_op* op) {
   const int d = op->d, n = op->n;
   op->ctx = ctx;
-  TTF_HIP(hipMalloc(&op->d_tap_col, sizeof(int) * op->tap_col.size()));
-  TTF_HIP(hipMalloc(&op->d_tap_w, sizeof(double) * op->tap_w.size()));
+  TTF_HIP(hipMalloc(&op->d_tap_ptr, sizeof(int) * op->tap_ptr.size()));
+  TTF_HIP(hipMalloc(&op->d_tap_col, sizeof(int) * std::max<size_t>(1, op->tap_col.size())));
+  TTF_HIP(hipMalloc(&op->d_tap_w, sizeof(double) * std::max<size_t>(1, op->tap_w.size())));
+  TTF_HIP(hipMemcpy(op->d_tap_ptr, op->tap_ptr.data(), sizeof(int) * op->tap_ptr.size(), hipMemcpyHostToDevice));
   TTF_HIP(hipMemcpy(op->d_tap_col, op->tap_col.data(), sizeof(int) * op->tap_col.size(), hipMemcpyHostToDevice));
   TTF_HIP(hipMemcpy(op->d_tap_w, op->tap_w.data(), sizeof(double) * op->tap_w.size(), hipMemcpyHostToDevice));
   (void)n;
@@ -823,6 +825,7 @@ void upload_op(tt_ctx* ctx, tt_op* op) {
 void free_op(tt_op* op) {
   if (!op) return;
   if (op->ctx) {
+    (void)hipFree(op->d_tap_ptr);
     (void)hipFree(op->d_tap_col);
     (void)hipFree(op->d_tap_w);
     for (auto& sd : op->dev) {
@@ -1049,6 +1052,54 @@ int tt_tensor_set_gaussian(tt_ctx* ctx, tt_tensor* t, const double* mu, const do
   ABI_CATCH(ctx)
 }
 
+int tt_tensor_set_cdf_gaussian(tt_ctx* ctx, tt_tensor* t, double sigma, double box) {
+  if (!ctx || !t) return TT_EINVAL;
+  ABI_TRY
+  require(box > 0 && sigma > 0, TT_EINVAL, "need box > 0 and sigma > 0");
+  for (int k = 0; k < t->d; ++k) cdf_gaussian_factor(ctx, t->core[k], t->n, box, sigma);
+  t->rank.assign(t->d + 1, 1);
+  t->orth = TT_ORTH_NONE;
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_op_create_cdf_burgers(tt_ctx* ctx, int d, int n, const tt_cdf_opts* opts, tt_op** out) {
+  if (!out) return TT_EINVAL;
+  if (!opts || opts->size != (int)sizeof(tt_cdf_opts)) {
+    if (ctx) ctx->last_error = "tt_cdf_opts.size mismatch";
+    return TT_EINVAL;
+  }
+  tt_op* op = nullptr;
+  ABI_TRY
+  *out = nullptr;
+  require(d >= 1 && d <= TT_MAX_D, TT_EINVAL, "d must be in 1..128");
+  require(n >= 4, TT_EINVAL, "n must be at least 4");
+  require(opts->box > 0 && opts->gamma >= 0 && opts->diffusion >= 0, TT_EINVAL,
+          "need box > 0, gamma >= 0 and diffusion >= 0");
+  op = new tt_op;
+  op->kind = 1;
+  op->d = d;
+  op->n = n;
+  op->L = opts->box;
+  op->gamma = opts->gamma;
+  op->alpha = opts->alpha;
+  op->diff = opts->diffusion;
+  build_cdf_burgers(op);
+  if (ctx) upload_op(ctx, op);
+  *out = op;
+  return TT_OK;
+  }
+  catch (const ttf::Error& e) {
+    if (ctx) ctx->last_error = e.msg;
+    free_op(op);
+    return e.code;
+  }
+  catch (...) {
+    free_op(op);
+    return TT_EINVAL;
+  }
+}
+
 int tt_op_create_burgers_hopf(tt_ctx* ctx, int d, int n, double L, double nu, tt_op** out) {
   return tt_op_create_burgers_hopf_scaled(ctx, d, n, L, nu, 1.0, out);
 }
@@ -1127,11 +1178,11 @@ int tt_op_export_local_ops(const tt_op* op, int* nops, double* mats) {
   if (mats) {
     std::memset(mats, 0, sizeof(double) * NOPS * n * n);
     for (int o = 0; o < NOPS; ++o)
-      for (int i = 0; i < n; ++i)
-        for (int t = 0; t < NTAPS; ++t) {
-          const size_t ti = ((size_t)o * n + i) * NTAPS + t;
-          mats[((size_t)o * n + i) * n + op->tap_col[ti]] += op->tap_w[ti];
-        }
+      for (int i = 0; i < n; ++i) {
+        const int row = o * n + i;
+        for (int ti = op->tap_ptr[row]; ti < op->tap_ptr[row + 1]; ++ti)
+          mats[(size_t)row * n + op->tap_col[ti]] += op->tap_w[ti];
+      }
   }
   return TT_OK;
 }

@@ -24,10 +24,15 @@ struct Error {
 void hip_check(hipError_t e, const char* what);
 #define TTF_HIP(call) ::ttf::hip_check((call), #call)
 
-// Local (one-axis) operators of the grid discretisation.  Every row has at
-// most four non-zeros; they are stored as taps (column, weight).
-enum LocalOp { OP_I = 0, OP_X = 1, OP_G = 2, OP_L2 = 3, OP_XG = 4, OP_XL2 = 5, NOPS = 6 };
-constexpr int NTAPS = 4;
+// Local (one-axis) operators of the grid discretisation, stored row by row
+// as taps (column, weight) in compressed rows: the non-zeros of row i of
+// operator o are taps tap_ptr[o n + i] .. tap_ptr[o n + i + 1] - 1.  The
+// finite-difference operators have at most four per row; the cumulative
+// (trapezoid) integral of the CDF equation is lower triangular.
+//   I identity, X multiply by the coordinate, G first derivative, L2 second
+//   derivative, XG = X G, XL2 = X L2, SG = diag(sin(pi u)) G, K = X - J with
+//   J the cumulative trapezoid integral from the lower end of the axis.
+enum LocalOp { OP_I = 0, OP_X = 1, OP_G = 2, OP_L2 = 3, OP_XG = 4, OP_XL2 = 5, OP_SG = 6, OP_K = 7, NOPS = 8 };
 
 // Automaton transition (TT-matrix entry) at one site.
 struct Entry {
@@ -108,12 +113,16 @@ struct tt_op {
   double ident = 0.0;                 // coefficient of an identity term
   std::vector<double> B, D;           // host coefficients
   std::vector<double> grid;           // a_i
-  std::vector<int> tap_col;           // [NOPS][n][NTAPS]
-  std::vector<double> tap_w;          // [NOPS][n][NTAPS]
+  int kind = 0;                       // 0 Burgers-Hopf characteristic function, 1 CDF equation
+  double gamma = 0.0, alpha = 0.0;    // CDF equation: viscosity and reaction amplitude
+  std::vector<int> tap_ptr;           // NOPS n + 1 row starts
+  std::vector<int> tap_col;           // columns of the taps
+  std::vector<double> tap_w;          // weights of the taps
   std::vector<int> R;                 // bond dimensions, d+1
   std::vector<std::vector<ttf::Entry>> site;
   // device copies (when created with a context)
   tt_ctx* ctx = nullptr;
+  int* d_tap_ptr = nullptr;
   int* d_tap_col = nullptr;
   double* d_tap_w = nullptr;
   struct SiteDev {
@@ -132,6 +141,7 @@ namespace ttf {
 
 // ---------------------------------------------------------- host builder
 void build_burgers_hopf(tt_op* op);  // fills everything but device data
+void build_cdf_burgers(tt_op* op);   // the CDF equation (kind 1), likewise
 
 // --------------------------------------------------------------- profiling
 struct KTimer {
@@ -236,6 +246,7 @@ void concat_core(tt_ctx* ctx, int nterms, const zc* const* src, const int* r0s, 
 void tt_eval_kernel(tt_ctx* ctx, int d, int n, const zc* const* cores, const int* ranks,
                     const int32_t* idx, int64_t npts, zc* out);
 void gaussian_factor(tt_ctx* ctx, zc* core, int n, double L, double mu, double sigma);
+void cdf_gaussian_factor(tt_ctx* ctx, zc* core, int n, double box, double sigma);
 void identity_core(tt_ctx* ctx, zc* core, int n, int r1);  // (n r1) x n x r1, I
 void apply_exact_core(tt_ctx* ctx, const tt_op* op, int site, const zc* x, int r0, int r1,
                       zc* y);

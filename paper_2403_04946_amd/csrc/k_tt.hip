@@ -157,6 +157,21 @@ __global__ void gaussian_factor_kernel(zc* core, int n, double L, double mu, dou
   core[i] = make_double2(mag * c, mag * s);
 }
 
+// one rank-one factor of the CDF equation's initial condition: the
+// Gaussian CDF 0.5 (1 + erf(u / (sigma sqrt 2))) on u_i = -box + 2 box i/(n-1)
+__global__ void cdf_gaussian_factor_kernel(zc* core, int n, double box, double sigma) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double u = -box + 2.0 * box * i / (n - 1);
+  core[i] = make_double2(0.5 * (1.0 + erf(u / (sigma * sqrt(2.0)))), 0.0);
+}
+
+void cdf_gaussian_factor(tt_ctx* ctx, zc* core, int n, double box, double sigma) {
+  hipLaunchKernelGGL(cdf_gaussian_factor_kernel, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, core, n, box,
+                     sigma);
+  TTF_HIP(hipGetLastError());
+}
+
 void gaussian_factor(tt_ctx* ctx, zc* core, int n, double L, double mu, double sigma) {
   hipLaunchKernelGGL(gaussian_factor_kernel, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, core, n, L, mu,
                      sigma);
@@ -189,7 +204,8 @@ __global__ void zero_kernel(zc* y, long total) {
 }
 
 __global__ void apply_exact_kernel(const DevBlock* __restrict__ blocks, const DevBlockOp* __restrict__ bops,
-                                   int nblocks, const int* __restrict__ tcol, const double* __restrict__ tw,
+                                   int nblocks, const int* __restrict__ tptr, const int* __restrict__ tcol,
+                                   const double* __restrict__ tw,
                                    const zc* __restrict__ x, int n, int r0, int r1, int R0, int R1,
                                    zc* __restrict__ y) {
   const long per = (long)r0 * n * r1;
@@ -206,10 +222,9 @@ __global__ void apply_exact_kernel(const DevBlock* __restrict__ blocks, const De
     for (int o = 0; o < blk.count; ++o) {
       const DevBlockOp bo = bops[blk.first + o];
       double vr = 0, vi = 0;
-      for (int t = 0; t < NTAPS; ++t) {
-        const long ti = ((long)bo.lop * n + i) * NTAPS + t;
+      const int row = bo.lop * n + i;
+      for (int ti = tptr[row]; ti < tptr[row + 1]; ++ti) {
         const double w = tw[ti];
-        if (w == 0.0) continue;
         const zc xv = x[a + (long)r0 * (tcol[ti] + (long)n * b)];
         vr += w * xv.x;
         vi += w * xv.y;
@@ -234,7 +249,7 @@ void apply_exact_core(tt_ctx* ctx, const tt_op* op, int site, const zc* x, int r
   blocks = (int)std::min<long>((total + 255) / 256, 16384);
   if (total > 0)
     hipLaunchKernelGGL(apply_exact_kernel, dim3(blocks), dim3(256), 0, ctx->stream, sd.blocks, sd.bops, sd.nblocks,
-                       op->d_tap_col, op->d_tap_w, x, n, r0, r1, R0, R1, y);
+                       op->d_tap_ptr, op->d_tap_col, op->d_tap_w, x, n, r0, r1, R0, R1, y);
   TTF_HIP(hipGetLastError());
 }
 
@@ -242,7 +257,8 @@ void apply_exact_core(tt_ctx* ctx, const tt_op* op, int site, const zc* x, int r
 // Left:  W[j, i, b, beta] = sum_{(alpha, o, c) -> beta} c * sum_t w_t V[j, alpha, col_t, b]
 //        V layout j + l (alpha + R0 (i' + n b)); W layout j + l (i + n (b + r1 beta)).
 __global__ void gather_left_kernel(const int* __restrict__ ptr, const DevEntry* __restrict__ ent,
-                                   const int* __restrict__ tcol, const double* __restrict__ tw,
+                                   const int* __restrict__ tptr, const int* __restrict__ tcol,
+                                   const double* __restrict__ tw,
                                    const zc* __restrict__ V, zc* __restrict__ W, int l, int n, int r1, int R0,
                                    int R1) {
   const long total = (long)l * n * r1 * R1;
@@ -256,10 +272,9 @@ __global__ void gather_left_kernel(const int* __restrict__ ptr, const DevEntry* 
     for (int q = ptr[beta]; q < ptr[beta + 1]; ++q) {
       const DevEntry en = ent[q];
       double vr = 0, vi = 0;
-      for (int t = 0; t < NTAPS; ++t) {
-        const long ti = ((long)en.lop * n + i) * NTAPS + t;
+      const int row = en.lop * n + i;
+      for (int ti = tptr[row]; ti < tptr[row + 1]; ++ti) {
         const double w = tw[ti];
-        if (w == 0.0) continue;
         const zc v = V[j + (long)l * (en.other + (long)R0 * (tcol[ti] + (long)n * b))];
         vr += w * v.x;
         vi += w * v.y;
@@ -277,14 +292,15 @@ void gather_left(tt_ctx* ctx, const tt_op* op, int site, const zc* V, zc* W, int
   const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
   KTimer kt(ctx, "gather_left", 0.0, 32.0 * total);
   hipLaunchKernelGGL(gather_left_kernel, dim3(blocks), dim3(256), 0, ctx->stream, op->dev[site].in_ptr,
-                     op->dev[site].in_ent, op->d_tap_col, op->d_tap_w, V, W, l, n, r1, R0, R1);
+                     op->dev[site].in_ent, op->d_tap_ptr, op->d_tap_col, op->d_tap_w, V, W, l, n, r1, R0, R1);
   TTF_HIP(hipGetLastError());
 }
 
 // Right: Z[a, alpha, i, q] = sum_{alpha -> (beta, o, c)} c * sum_t w_t V2[a, col_t, beta, q]
 //        V2 layout a + r0 (i' + n (beta + R1 q)); Z layout a + r0 (alpha + R0 (i + n q)).
 __global__ void gather_right_kernel(const int* __restrict__ ptr, const DevEntry* __restrict__ ent,
-                                    const int* __restrict__ tcol, const double* __restrict__ tw,
+                                    const int* __restrict__ tptr, const int* __restrict__ tcol,
+                                    const double* __restrict__ tw,
                                     const zc* __restrict__ V2, zc* __restrict__ Z, int r0, int n, int s, int R0,
                                     int R1) {
   const long total = (long)r0 * R0 * n * s;
@@ -298,10 +314,9 @@ __global__ void gather_right_kernel(const int* __restrict__ ptr, const DevEntry*
     for (int p = ptr[alpha]; p < ptr[alpha + 1]; ++p) {
       const DevEntry en = ent[p];
       double vr = 0, vi = 0;
-      for (int t = 0; t < NTAPS; ++t) {
-        const long ti = ((long)en.lop * n + i) * NTAPS + t;
+      const int row = en.lop * n + i;
+      for (int ti = tptr[row]; ti < tptr[row + 1]; ++ti) {
         const double w = tw[ti];
-        if (w == 0.0) continue;
         const zc v = V2[a + (long)r0 * (tcol[ti] + (long)n * (en.other + (long)R1 * q))];
         vr += w * v.x;
         vi += w * v.y;
@@ -319,7 +334,7 @@ void gather_right(tt_ctx* ctx, const tt_op* op, int site, const zc* V2, zc* Z, i
   const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
   KTimer kt(ctx, "gather_right", 0.0, 32.0 * total);
   hipLaunchKernelGGL(gather_right_kernel, dim3(blocks), dim3(256), 0, ctx->stream, op->dev[site].out_ptr,
-                     op->dev[site].out_ent, op->d_tap_col, op->d_tap_w, V2, Z, r0, n, s, R0, R1);
+                     op->dev[site].out_ent, op->d_tap_ptr, op->d_tap_col, op->d_tap_w, V2, Z, r0, n, s, R0, R1);
   TTF_HIP(hipGetLastError());
 }
 

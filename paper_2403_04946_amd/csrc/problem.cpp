@@ -20,6 +20,9 @@
 // An optional numerical-diffusion stabilisation (Sec. 5.2, explicit runs)
 // adds kappa sum_k d^2/da_k^2: d one-site terms L2.
 //
+// The CDF equation (Sec. 5, eq. (eqn:cdf-burgers), the paper's own
+// workload) is built by build_cdf_burgers below from the same automaton.
+//
 // TT-matrix form: the operator is a sum of products of one-axis operators
 // on at most three sites (X = multiply by a, G = d/da, L2 = d^2/da^2, and
 // the same-site compositions XG, XL2; multiplication by a_k acts after the
@@ -105,6 +108,31 @@ struct Term {
   std::vector<std::pair<int, int>> ops;  // (site, local op), sorted by site
 };
 
+// Rows of the local operators as lists of (column, weight); zero weights
+// are dropped.  finish() packs them into the compressed rows of tt_op.
+struct TapRows {
+  int n;
+  std::vector<std::vector<std::pair<int, double>>> rows;
+  explicit TapRows(int n_) : n(n_), rows((size_t)NOPS * n_) {}
+  void add(int o, int i, int col, double w) {
+    if (w != 0.0) rows[(size_t)o * n + i].push_back({col, w});
+  }
+  void finish(tt_op* op) const {
+    op->tap_ptr.assign(rows.size() + 1, 0);
+    op->tap_col.clear();
+    op->tap_w.clear();
+    for (size_t r = 0; r < rows.size(); ++r) {
+      for (const auto& cw : rows[r]) {
+        op->tap_col.push_back(cw.first);
+        op->tap_w.push_back(cw.second);
+      }
+      op->tap_ptr[r + 1] = (int)op->tap_col.size();
+    }
+  }
+};
+
+void build_automaton(tt_op* op, const std::vector<Term>& terms);
+
 }  // namespace
 
 void build_burgers_hopf(tt_op* op) {
@@ -134,15 +162,9 @@ void build_burgers_hopf(tt_op* op) {
   const double h = 2.0 * L / (n - 1);
   op->grid.resize(n);
   for (int i = 0; i < n; ++i) op->grid[i] = -L + 2.0 * L * i / (n - 1);
-  op->tap_col.assign((size_t)NOPS * n * NTAPS, 0);
-  op->tap_w.assign((size_t)NOPS * n * NTAPS, 0.0);
-  auto set = [&](int o, int i, int t, int col, double w) {
-    op->tap_col[((size_t)o * n + i) * NTAPS + t] = col;
-    op->tap_w[((size_t)o * n + i) * NTAPS + t] = w;
-  };
+  TapRows taps(n);
+  auto set = [&](int o, int i, int, int col, double w) { taps.add(o, i, col, w); };
   for (int i = 0; i < n; ++i) {
-    for (int t = 0; t < NTAPS; ++t)
-      for (int o = 0; o < NOPS; ++o) set(o, i, t, i, 0.0);
     set(OP_I, i, 0, i, 1.0);
     set(OP_X, i, 0, i, op->grid[i]);
     // first derivative
@@ -181,6 +203,7 @@ void build_burgers_hopf(tt_op* op) {
       set(OP_XL2, i, t, lc[t], op->grid[i] * lw[t]);
     }
   }
+  taps.finish(op);
   // ---- operator terms
   std::vector<Term> terms;
   const cplx half_i(0.0, 0.5);
@@ -223,6 +246,13 @@ void build_burgers_hopf(tt_op* op) {
       t.ops.push_back({k, OP_L2});
       terms.push_back(t);
     }
+  build_automaton(op, terms);
+}
+
+namespace {
+
+void build_automaton(tt_op* op, const std::vector<Term>& terms) {
+  const int d = op->d;
   // ---- automaton
   // channel key: (kind, site, op); kind 0 = I, 1 = F, 2 = A, 3 = B
   using Key = std::tuple<int, int, int>;
@@ -243,12 +273,13 @@ void build_burgers_hopf(tt_op* op) {
       path.push_back({s1, KI, KF, o1, t.coef, false});
     } else if (ns == 2) {
       const int s2 = t.ops[1].first, o2 = t.ops[1].second;
-      if (is_xg(o1)) {
+      // the shared channel waits after an X or G end; a term with
+      // composite ops at both ends waits after its first one
+      if (is_xg(o1) || !is_xg(o2)) {
         Key a{2, s1, o1};
         path.push_back({s1, KI, a, o1, 1.0, true});
         path.push_back({s2, a, KF, o2, t.coef, false});
       } else {
-        if (!is_xg(o2)) fail(TT_EINVAL, "two-site term without an X or G end");
         Key b{3, s2, o2};
         path.push_back({s1, KI, b, o1, t.coef, false});
         path.push_back({s2, b, KF, o2, 1.0, true});
@@ -305,6 +336,117 @@ void build_burgers_hopf(tt_op* op) {
     e.cim = kv.second.imag();
     op->site[s].push_back(e);
   }
+}
+
+}  // namespace
+
+// The CDF equation of the stochastic Burgers equation with reaction
+// R(u) = alpha sin(pi u) (Sec. 5, eq. (eqn:burgers-rxn) and
+// eq. (eqn:cdf-burgers)) on N = d evenly spaced points of the circle.  With
+// D1, D2 the periodic second-order first- and second-difference matrices
+// (spacing 2 pi / N), the semi-discrete velocity of point i is
+// v_i = -u_i (D1 u)_i + gamma (D2 u)_i + R(u_i); integrating the Liouville
+// equation over the phase variables up to u gives
+//
+//   dF/dt = sum_i [ -gamma D2_ii u_i - R(u_i) ] dF/du_i
+//         + sum_{i != j} [ D1_ij u_i - gamma D2_ij ] (u_j - J_j) dF/du_i,
+//
+// J_j being the cumulative integral along u_j from the lower end of the
+// box.  The reaction enters once, as in the velocity (the equation as
+// printed repeats it in a separate last sum).  Phase space: [-box, box]^N,
+// n points per axis (ends included); centred second-order differences with
+// outflow boundaries (dF/du = 0: the boundary rows of G are zero), the
+// trapezoid rule for J.  Local operators: X, G, XG, SG = sin(pi u) G and
+// K = X - J; the terms are one-site (XG, SG) and two-site (XG or G at i,
+// K at j = i +- 1 mod N).  op->L is the box half-width, op->gamma and
+// op->alpha the coefficients, op->diff an optional kappa sum_k d2F/du_k^2
+// (interior rows of L2; the boundary rows are zero).
+void build_cdf_burgers(tt_op* op) {
+  const int d = op->d, n = op->n;
+  const double box = op->L, gamma = op->gamma, alpha = op->alpha;
+  const double h = 2.0 * box / (n - 1);
+  op->grid.resize(n);
+  for (int i = 0; i < n; ++i) op->grid[i] = -box + 2.0 * box * i / (n - 1);
+  TapRows taps(n);
+  for (int i = 0; i < n; ++i) {
+    const double u = op->grid[i];
+    taps.add(OP_I, i, i, 1.0);
+    taps.add(OP_X, i, i, u);
+    if (i > 0 && i < n - 1) {
+      const double w = 1.0 / (2 * h), w2 = 1.0 / (h * h);
+      taps.add(OP_G, i, i - 1, -w);
+      taps.add(OP_G, i, i + 1, w);
+      taps.add(OP_XG, i, i - 1, -u * w);
+      taps.add(OP_XG, i, i + 1, u * w);
+      const double sn = std::sin(M_PI * u);
+      taps.add(OP_SG, i, i - 1, -sn * w);
+      taps.add(OP_SG, i, i + 1, sn * w);
+      taps.add(OP_L2, i, i - 1, w2);
+      taps.add(OP_L2, i, i, -2.0 * w2);
+      taps.add(OP_L2, i, i + 1, w2);
+      taps.add(OP_XL2, i, i - 1, u * w2);
+      taps.add(OP_XL2, i, i, -2.0 * u * w2);
+      taps.add(OP_XL2, i, i + 1, u * w2);
+    }
+    // K = X - J, (J g)_i = h (g_0 / 2 + g_1 + ... + g_{i-1} + g_i / 2)
+    for (int c = 0; c <= i; ++c) {
+      double w = 0.0;
+      if (i > 0) w = -h * ((c == 0 || c == i) ? 0.5 : 1.0);
+      if (c == i) w += u;
+      taps.add(OP_K, i, c, w);
+    }
+  }
+  taps.finish(op);
+  // periodic difference matrices on the circle
+  const double dx = 2.0 * M_PI / d;
+  std::vector<double> D1((size_t)d * d, 0.0), D2((size_t)d * d, 0.0);
+  for (int i = 0; i < d; ++i) {
+    const int ip = (i + 1) % d, im = (i + d - 1) % d;
+    D1[(size_t)i * d + ip] += 1.0 / (2 * dx);
+    D1[(size_t)i * d + im] -= 1.0 / (2 * dx);
+    D2[(size_t)i * d + i] -= 2.0 / (dx * dx);
+    D2[(size_t)i * d + ip] += 1.0 / (dx * dx);
+    D2[(size_t)i * d + im] += 1.0 / (dx * dx);
+  }
+  for (double& v : D1)
+    if (std::fabs(v) < 1e-12) v = 0.0;
+  for (double& v : D2)
+    if (std::fabs(v) < 1e-12) v = 0.0;
+  op->B.clear();
+  op->D = D2;
+  std::vector<Term> terms;
+  auto one = [&](int i, int o, double c) {
+    if (c == 0.0) return;
+    Term t;
+    t.coef = cplx(c, 0.0);
+    t.ops.push_back({i, o});
+    terms.push_back(t);
+  };
+  auto two = [&](int i, int oi, int j, int oj, double c) {
+    if (c == 0.0) return;
+    Term t;
+    t.coef = cplx(c, 0.0);
+    if (i < j) {
+      t.ops.push_back({i, oi});
+      t.ops.push_back({j, oj});
+    } else {
+      t.ops.push_back({j, oj});
+      t.ops.push_back({i, oi});
+    }
+    terms.push_back(t);
+  };
+  for (int i = 0; i < d; ++i) {
+    one(i, OP_XG, -gamma * D2[(size_t)i * d + i]);
+    one(i, OP_SG, -alpha);
+    if (op->diff != 0.0) one(i, OP_L2, op->diff);
+    for (int j = 0; j < d; ++j) {
+      if (j == i) continue;
+      two(i, OP_XG, j, OP_K, D1[(size_t)i * d + j]);
+      two(i, OP_G, j, OP_K, -gamma * D2[(size_t)i * d + j]);
+    }
+  }
+  if (terms.empty()) fail(TT_EINVAL, "CDF operator without terms (gamma, alpha and the advection all vanish)");
+  build_automaton(op, terms);
 }
 
 }  // namespace ttf

@@ -95,6 +95,17 @@ class OpOpts(ctypes.Structure):
     ]
 
 
+class CdfOpts(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_int),
+        ("pad", ctypes.c_int),
+        ("box", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("diffusion", ctypes.c_double),
+    ]
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [
         ("size", ctypes.c_int),
@@ -185,6 +196,8 @@ _SIGS = {
     "tt_round_randomized": (I, [P, P, PI, ctypes.c_uint64, P, PD]),
     "tt_step_batch": (I, [I, P, P, P, PD, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport), PI]),
     "tt_op_create_burgers_hopf_ex": (I, [P, I, I, D, D, P, P]),
+    "tt_op_create_cdf_burgers": (I, [P, I, I, ctypes.POINTER(CdfOpts), P]),
+    "tt_tensor_set_cdf_gaussian": (I, [P, P, D, D]),
     "tt_ctx_set_profile_sampling": (I, [P, I]),
     "tt_dot": (I, [P, P, P, PD]),
     "tt_solve_shifted": (I, [P, P, D, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport)]),
@@ -337,6 +350,10 @@ class Tensor:
         sigma = np.ascontiguousarray(sigma, dtype=np.float64)
         self.ctx.check(lib().tt_tensor_set_gaussian(self.ctx.h, self.h, _dp(mu), _dp(sigma), float(length)))
 
+    def set_cdf_gaussian(self, sigma, box):
+        """The CDF equation's initial condition (product of Gaussian CDFs)."""
+        self.ctx.check(lib().tt_tensor_set_cdf_gaussian(self.ctx.h, self.h, float(sigma), float(box)))
+
     def copy_from(self, other):
         self.ctx.check(lib().tt_tensor_copy(self.ctx.h, other.h, self.h))
 
@@ -390,6 +407,21 @@ class Operator:
         if self.h:
             lib().tt_op_destroy(self.h)
             self.h = None
+
+
+class CdfOperator(Operator):
+    """Operator of the CDF equation (tt_op_create_cdf_burgers); ctx=None
+    builds a host-only operator."""
+
+    def __init__(self, ctx, d, n, box=1.3, gamma=0.05, alpha=1.0, diffusion=0.0):
+        self.ctx, self.d, self.n = ctx, d, n
+        h = P()
+        o = CdfOpts(ctypes.sizeof(CdfOpts), 0, float(box), float(gamma), float(alpha), float(diffusion))
+        rc = lib().tt_op_create_cdf_burgers(ctx.h if ctx else None, d, n, ctypes.byref(o), ctypes.byref(h))
+        if rc != 0:
+            msg = lib().tt_last_error(ctx.h).decode() if ctx else "tt_op_create_cdf_burgers failed"
+            raise TTError(rc, msg)
+        self.h = h
 
 
 def tt_apply(ctx, op, x, y, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0):
