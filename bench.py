@@ -95,7 +95,7 @@ def dominant(stats):
     return max(cand, key=cand.get)
 
 
-def roofline(name, kd):
+def roofline(name, kd, with_traffic=True):
     bound = KERNEL_BOUND[name]
     sec = kd["ms"] / 1e3
     if bound == "hbm":
@@ -105,7 +105,7 @@ def roofline(name, kd):
         achieved, unit, work = kd["flops"] / sec / 1e12, "TFLOP/s", "flops"
     return {
         "bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-        "traffic": traffic_per_launch(name), "kernel": name, "launches": kd["launches"],
+        "traffic": traffic_per_launch(name) if with_traffic else None, "kernel": name, "launches": kd["launches"],
         "avg_launch_us": 1e3 * kd["ms"] / max(kd["launches"], 1),
         "algorithmic_flops_per_launch": kd["flops"] / max(kd["launches"], 1),
         "algorithmic_bytes_per_launch": kd["bytes"] / max(kd["launches"], 1),
@@ -393,6 +393,95 @@ def main_learned(args):
     print(json.dumps(result), flush=True)
 
 
+def main_cdf(args):
+    """The paper's own workload: the CDF equation of the stochastic Burgers
+    equation with reaction (Sec. 5) at N = 20 points of the circle, n = 64
+    points per phase variable on [-1.3, 1.3], explicit midpoint
+    step-truncation (the paper's integrator) at TT ranks above 100: a seeded
+    random TT with every interior rank 128 (cap 128), sketched apply of
+    width 144, eps 1e-8, dt 1e-3, gamma 0.05, alpha 1 (the paper states
+    neither coefficient), all in FP64 (complex storage; the CDF is real).
+    Reported beside the paper's figure for the same size on its CPU
+    workstation (about 45 minutes per step at ranks above 100)."""
+    import torch
+
+    from paper_2403_04946_amd import inputs, tt
+
+    torch.cuda.init()
+    d, n, box, cap, ell, eps, dt = 20, 64, 1.3, 128, 144, 1e-8, 1e-3
+    ctx = tt.Context(0)
+    op = tt.CdfOperator(ctx, d, n, box, 0.05, 1.0)
+    f0 = tt.Tensor(ctx, d, n, cap)
+    f0.set_cores(inputs.random_tt(d, n, cap, 0))
+    f = tt.Tensor(ctx, d, n, cap)
+    f.copy_from(f0)
+
+    def step():
+        return tt.tt_step(ctx, op, f, dt, cap, eps, tt.TT_APPLY_SKETCH, ell, 7, scheme=tt.TT_STEP_MIDPOINT)
+
+    breakdown = None
+    for i in range(args.warmup):
+        if i == args.warmup - 1:
+            ctx.reset_stats()
+            ctx.set_profiling(True)
+        step()
+        f.copy_from(f0)
+        if i == args.warmup - 1:
+            breakdown = ctx.dump_stats()
+            ctx.set_profiling(False)
+        print(f"bench: CDF warm-up step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    ctx.sync()
+    dom = dominant(breakdown) if breakdown else "zgemm"
+    ctx.reset_stats()
+    ctx.set_profile_filter(dom)
+    ctx.set_profile_sampling(PROFILE_EVERY)
+    ctx.set_profiling(True)
+    stream = ctx.torch_stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    rep = None
+    for _ in range(args.steps):
+        rep = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kd = ctx.stats(dom)
+    ctx.set_profiling(False)
+    ctx.set_profile_filter(None)
+    ctx.set_profile_sampling(1)
+    print("bench: CDF timed steps done", file=sys.stderr, flush=True)
+    sec = ms / 1e3 / args.steps
+    paper_sec = 45 * 60.0
+    result = {
+        "metric": "seconds per explicit-midpoint step, CDF equation N=20, n=64, TT ranks 128",
+        "value": sec,
+        "unit": "s/step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": sec / paper_sec,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ("CDF equation of the stochastic Burgers equation with reaction, explicit midpoint "
+                         "step-truncation, N=20, n=64 on [-1.3,1.3], gamma 0.05, alpha 1, cap 128, eps 1e-8, "
+                         "dt 1e-3, sketched apply width 144, FP64; input a seeded random TT with interior ranks 128"),
+            "stage_max_rank": rep["max_rank"] if rep else None,
+            "final_ranks_max": max(f.ranks()),
+        },
+        "paper_context": {"seconds_per_step": paper_sec, "hardware": "Intel i9-7980XE workstation (CPU)",
+                          "ranks": "above 100", "speedup_of_this_run": paper_sec / sec},
+        "roofline": roofline(dom, kd, with_traffic=False),
+        "kernels_ms_profiled_warmup_step": {k: round(v["ms"], 3) for k, v in (breakdown or {}).items()
+                                            if k != "qr_fallbacks"},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -405,7 +494,7 @@ def main():
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-error-report", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["metric", "batched", "learned"], default="metric",
+    ap.add_argument("--form", choices=["metric", "batched", "learned", "cdf"], default="metric",
                     help="batched: the batched form on uneven instances; learned: the learned form against the "
                          "plain one on tolerance-limited trajectories (each its own JSON line)")
     ap.add_argument("--instances", type=int, default=16)
@@ -424,6 +513,9 @@ def main():
         return
     if args.form == "learned":
         main_learned(args)
+        return
+    if args.form == "cdf":
+        main_cdf(args)
         return
 
     import torch
