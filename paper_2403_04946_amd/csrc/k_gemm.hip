@@ -322,12 +322,15 @@ void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc 
   }
   const int gx = (N + bn - 1) / bn, gy = (M + bm - 1) / bm;
   const long tiles = (long)gx * gy * batch;
-  // split K when the output grid alone cannot occupy the chip (about two
-  // workgroups per compute unit), keeping at least two K steps per split
+  // split K when the output grid alone cannot occupy the chip (fewer tiles
+  // than compute units) and the output is small enough for the partial sums
+  // to be cheap to reduce (at most 256K elements: the tall panel updates of
+  // the QR factorisations run unsplit), up to about two workgroups per
+  // compute unit, keeping at least two K steps per split
   int nsplit = 1;
   const int kb = BK;
   const int kblocks = (K + kb - 1) / kb;
-  if (tiles < 512 && kblocks >= 4) {
+  if (tiles < 256 && (long)M * N * batch <= (1L << 18) && kblocks >= 4) {
     nsplit = (int)std::min<long>((512 + tiles - 1) / tiles, kblocks / 2);
     nsplit = std::max(1, std::min(nsplit, 128));
   }
