@@ -45,7 +45,8 @@ PEAK_F16_TFLOPS = 2500.0  # dense fp16 / bf16 matrix cores
 PEAK_HBM_GBS = 8000.0
 GATE = 1e-5
 PROFILE_EVERY = 4  # one in four launches of the roofline kernel is event-timed
-PRECISIONS = {"fp64": 0, "bf16x3": 1, "fp16x3": 2}
+PRECISIONS = {"fp64": 0, "bf16x3": 1, "fp16x3": 2, "fp32": 3}
+PEAK_F32_TFLOPS = 157.3  # FP32 matrix cores
 
 
 def cpu_baseline(seconds_target=20.0):
@@ -83,7 +84,8 @@ def cpu_baseline(seconds_target=20.0):
 
 # kernel classes that are one kernel each, with the resource that bounds them
 KERNEL_BOUND = {
-    "zgemm": "mfma", "zgemm_fp16x3": "mfma", "zgemm_bf16x3": "mfma", "chol_solve": "alu", "pt_leaf": "alu",
+    "zgemm": "mfma", "zgemm_fp16x3": "mfma", "zgemm_bf16x3": "mfma", "zgemm_fp32": "mfma", "chol_solve": "alu",
+    "pt_leaf": "alu",
     "jacobi_cross": "alu", "jacobi_circle": "alu", "pt_assemble": "hbm", "panel_trmm": "hbm", "bcgs_pip": "alu",
     "gather_left": "hbm", "gather_right": "hbm", "zgemm_reduce": "hbm", "concat": "hbm",
 }
@@ -101,7 +103,8 @@ def roofline(name, kd, with_traffic=True):
     if bound == "hbm":
         achieved, peak, unit, work = kd["bytes"] / sec / 1e9, PEAK_HBM_GBS, "GB/s", "bytes"
     else:
-        peak = PEAK_F16_TFLOPS if name in ("zgemm_fp16x3", "zgemm_bf16x3") else PEAK_F64_TFLOPS
+        peak = (PEAK_F16_TFLOPS if name in ("zgemm_fp16x3", "zgemm_bf16x3")
+                else PEAK_F32_TFLOPS if name == "zgemm_fp32" else PEAK_F64_TFLOPS)
         achieved, unit, work = kd["flops"] / sec / 1e12, "TFLOP/s", "flops"
     return {
         "bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
@@ -620,13 +623,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {0: "f64", 1: "bf16x3+f64", 2: "fp16x3+f64"}[prec],
+        "dtype": {0: "f64", 1: "bf16x3+f64", 2: "fp16x3+f64", 3: "fp32+f64"}[prec],
         "data": "synthetic",
         "config": {
             "workload": ("Burgers-Hopf TT RK4 step-truncation, saturated ranks, "
                          + {0: "plain complex FP64",
                             1: "sketch contractions split-BF16x3 (FP32 accumulate), QR/SVD/truncation FP64",
-                            2: "sketch contractions split-FP16x3 (FP32 accumulate), QR/SVD/truncation FP64"}[prec]),
+                            2: "sketch contractions split-FP16x3 (FP32 accumulate), QR/SVD/truncation FP64",
+                            3: "sketch contractions FP32 (FP32 matrix cores, FP64 across K steps), "
+                               "QR/SVD/truncation FP64"}[prec]),
             "precision": args.precision,
             "d": D, "n": N, "L": LEN, "nu": NU, "rank_cap": CAP, "eps": EPS, "dt": DT,
             "apply": f"sketched (width {ell})", "input": "seeded random TT, all interior ranks 64",

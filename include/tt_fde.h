@@ -82,9 +82,12 @@ enum {
   TT_PREC_BF16X3 = 1,  /* split-BF16x3 on the bf16 matrix cores, FP32
                           accumulation (about 17 significant bits; see
                           tt_zgemm_mixed)                                      */
-  TT_PREC_FP16X3 = 2   /* split-FP16x3 on the fp16 matrix cores with a
+  TT_PREC_FP16X3 = 2,  /* split-FP16x3 on the fp16 matrix cores with a
                           power-of-two scale per K stage, FP32 accumulation
                           (about 22 significant bits)                          */
+  TT_PREC_FP32 = 3     /* operands rounded to FP32 on the fp32 matrix cores,
+                          FP32 accumulation within each K step of 16 and FP64
+                          across them (the FP32 form)                          */
 };
 
 typedef struct tt_ctx tt_ctx;
@@ -235,7 +238,8 @@ typedef struct {
   int size;              /* sizeof(tt_apply_opts) */
   int mode;              /* TT_APPLY_EXACT or TT_APPLY_SKETCH */
   int sketch_rank;       /* sketch width l for TT_APPLY_SKETCH (>= 1) */
-  int precision;         /* TT_PREC_FP64, or TT_PREC_BF16X3 / TT_PREC_FP16X3:
+  int precision;         /* TT_PREC_FP64, or TT_PREC_BF16X3 / TT_PREC_FP16X3 /
+                            TT_PREC_FP32:
                             the sketch contractions in that split 16-bit
                             form (mixed form; the exact product and
                             everything else stay FP64) */
@@ -374,8 +378,10 @@ int tt_zgemm(tt_ctx* ctx, int opA, int opB, int M, int N, int K, double alpha_re
  * precision TT_PREC_BF16X3: bfloat16 halves, error about 1e-5 of
  * |op(A)| |op(B)| per entry.  TT_PREC_FP16X3: half-precision halves with a
  * power-of-two scale per 32-wide K stage of each operand tile, error about
- * 5e-7 of the same.  Other arguments and layout as tt_zgemm; TT_EINVAL for
- * any other precision. */
+ * 5e-7 of the same.  TT_PREC_FP32 (not split): operands rounded to FP32
+ * on the fp32 matrix cores, FP32 sums over K steps of 16 added in FP64,
+ * error about 1e-6 of the same.  Other arguments and layout as tt_zgemm;
+ * TT_EINVAL for any other precision. */
 int tt_zgemm_mixed(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, int K, double alpha_re,
                    double alpha_im, const double* A, int64_t lda, int64_t strideA, const double* B,
                    int64_t ldb, int64_t strideB, double beta_re, double beta_im, double* C, int64_t ldc,

@@ -578,7 +578,9 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
 
 void apply_any(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int mode, int l, uint64_t seed,
                int precision) {
-  require(precision == TT_PREC_FP64 || precision == TT_PREC_BF16X3 || precision == TT_PREC_FP16X3, TT_EINVAL,
+  require(precision == TT_PREC_FP64 || precision == TT_PREC_BF16X3 || precision == TT_PREC_FP16X3 ||
+              precision == TT_PREC_FP32,
+          TT_EINVAL,
           "tt_apply: unknown precision");
   check_same_shape(op, x);
   require(x->d == y->d && x->n == y->n, TT_ESHAPE, "tt_apply: x and y shapes differ");
@@ -1479,7 +1481,9 @@ void check_solve_opts(const tt_solve_opts& o) {
   require(o.rmax >= 1 && o.eps >= 0.0, TT_EINVAL, "TT-GMRES: bad rmax or eps");
   require(o.apply_mode == TT_APPLY_EXACT || (o.apply_mode == TT_APPLY_SKETCH && o.sketch_rank >= 1), TT_EINVAL,
           "TT-GMRES: bad apply mode");
-  require(o.precision == TT_PREC_FP64 || o.precision == TT_PREC_BF16X3 || o.precision == TT_PREC_FP16X3, TT_EINVAL,
+  require(o.precision == TT_PREC_FP64 || o.precision == TT_PREC_BF16X3 || o.precision == TT_PREC_FP16X3 ||
+              o.precision == TT_PREC_FP32,
+          TT_EINVAL,
           "TT-GMRES: unknown precision");
 }
 
@@ -1491,7 +1495,8 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
   ABI_TRY
   require(opts->size == (int)sizeof(tt_step_opts), TT_EINVAL, "tt_step_opts.size mismatch");
   require(opts->rmax >= 1, TT_EINVAL, "tt_step: rmax must be >= 1");
-  require(opts->precision == TT_PREC_FP64 || opts->precision == TT_PREC_BF16X3 || opts->precision == TT_PREC_FP16X3,
+  require(opts->precision == TT_PREC_FP64 || opts->precision == TT_PREC_BF16X3 || opts->precision == TT_PREC_FP16X3 ||
+              opts->precision == TT_PREC_FP32,
           TT_EINVAL, "tt_step: unknown precision");
   const int scheme = opts->scheme;
   require(scheme >= TT_STEP_RK4 && scheme <= TT_STEP_IMPLICIT_MIDPOINT, TT_EINVAL, "tt_step: unknown scheme");
@@ -1873,8 +1878,8 @@ int tt_zgemm_mixed(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, i
                    int batch) {
   if (!ctx) return TT_EINVAL;
   ABI_TRY
-  require(precision == TT_PREC_BF16X3 || precision == TT_PREC_FP16X3, TT_EINVAL,
-          "tt_zgemm_mixed: precision must be TT_PREC_BF16X3 or TT_PREC_FP16X3");
+  require(precision == TT_PREC_BF16X3 || precision == TT_PREC_FP16X3 || precision == TT_PREC_FP32, TT_EINVAL,
+          "tt_zgemm_mixed: precision must be TT_PREC_BF16X3, TT_PREC_FP16X3 or TT_PREC_FP32");
   require(opA >= 0 && opA <= 2 && opB >= 0 && opB <= 2, TT_EINVAL, "tt_zgemm_mixed: op must be 0, 1 or 2");
   require(M >= 0 && N >= 0 && K >= 0 && batch >= 1, TT_EINVAL, "tt_zgemm_mixed: negative size");
   require(C && ((A && B) || K == 0), TT_EINVAL, "tt_zgemm_mixed: null pointer");

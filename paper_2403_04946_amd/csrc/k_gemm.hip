@@ -14,6 +14,12 @@
 // and imaginary planes so every MFMA operand is one 8-byte LDS read per lane.
 // Large K with a small output grid is split over workgroups (split-K) into a
 // workspace and reduced deterministically by a second kernel.
+//
+// The FP32 form (TT_PREC_FP32) is the same kernel with the operands rounded
+// to float in the LDS staging and v_mfma_f32_16x16x4f32 products; each K
+// step of 16 is accumulated in float and then added into double
+// accumulators, so the error per entry stays near 2^-24 times the sum of
+// |a||b| of one K step, whatever K is.
 #include <string>
 
 #include "common.hpp"
@@ -21,6 +27,7 @@
 namespace ttf {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 16, PAD = 1;
 
@@ -51,13 +58,14 @@ __device__ inline zc load_op(const zc* X, long ld, int r, int c, int R, int Ccou
 // (BM/2) x (BN/2) block of (BM/32) x (BN/32) MFMA tiles of 16 x 16.
 // blockIdx.x runs over N tiles (fastest), so consecutive workgroups share
 // the A tile through L2.
-template <int OPA, int OPB, int BM, int BN>
+template <int OPA, int OPB, int BM, int BN, typename RT = double>
 __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
+  constexpr bool F32 = sizeof(RT) == 4;
   constexpr int TI = BM / 32, TJ = BN / 32;
   constexpr int RA = BM * BK / 256, RB = BN * BK / 256;  // elements per thread
-  __shared__ double Ar[BK][BM + PAD], Ai[BK][BM + PAD];  // Ai holds -Im(A)
-  __shared__ double Ap[BK][BM + PAD];                    // +Im(A)
-  __shared__ double Br[BK][BN + PAD], Bi[BK][BN + PAD];
+  __shared__ RT Ar[BK][BM + PAD], Ai[BK][BM + PAD];  // Ai holds -Im(A)
+  __shared__ RT Ap[BK][BM + PAD];                    // +Im(A)
+  __shared__ RT Br[BK][BN + PAD], Bi[BK][BN + PAD];
 
   const int nsplit = gridDim.z / p.batch;
   const int bz = blockIdx.z % p.batch;
@@ -121,16 +129,16 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
     for (int r = 0; r < RA; ++r) {
       int mm, kk;
       a_idx(r, mm, kk);
-      Ar[kk][mm] = ra[r].x;
-      Ai[kk][mm] = -ra[r].y;
-      Ap[kk][mm] = ra[r].y;
+      Ar[kk][mm] = (RT)ra[r].x;
+      Ai[kk][mm] = -(RT)ra[r].y;
+      Ap[kk][mm] = (RT)ra[r].y;
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       int kk, nn;
       b_idx(r, kk, nn);
-      Br[kk][nn] = rb[r].x;
-      Bi[kk][nn] = rb[r].y;
+      Br[kk][nn] = (RT)rb[r].x;
+      Bi[kk][nn] = (RT)rb[r].y;
     }
   };
 
@@ -142,29 +150,74 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
     if (more) gload(k0 + BK);
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
-      double ar[TI], an[TI], ap[TI], br[TJ], bi[TJ];
-#pragma unroll
-      for (int i = 0; i < TI; ++i) {
-        ar[i] = Ar[ks + lk][wm + 16 * i + lr];
-        an[i] = Ai[ks + lk][wm + 16 * i + lr];
-        ap[i] = Ap[ks + lk][wm + 16 * i + lr];
-      }
-#pragma unroll
-      for (int j = 0; j < TJ; ++j) {
-        br[j] = Br[ks + lk][wn + 16 * j + lr];
-        bi[j] = Bi[ks + lk][wn + 16 * j + lr];
-      }
+    if constexpr (F32) {
+      // one K step in float, then into the double accumulators
+      flt4 fR[TI][TJ], fI[TI][TJ];
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < TJ; ++j) {
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[i], bi[j], accR[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[i], br[j], accI[i][j], 0, 0, 0);
+          fR[i][j] = flt4{0, 0, 0, 0};
+          fI[i][j] = flt4{0, 0, 0, 0};
         }
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 4) {
+        float ar[TI], an[TI], ap[TI], br[TJ], bi[TJ];
+#pragma unroll
+        for (int i = 0; i < TI; ++i) {
+          ar[i] = Ar[ks + lk][wm + 16 * i + lr];
+          an[i] = Ai[ks + lk][wm + 16 * i + lr];
+          ap[i] = Ap[ks + lk][wm + 16 * i + lr];
+        }
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          br[j] = Br[ks + lk][wn + 16 * j + lr];
+          bi[j] = Bi[ks + lk][wn + 16 * j + lr];
+        }
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) {
+            fR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], fR[i][j], 0, 0, 0);
+            fR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(an[i], bi[j], fR[i][j], 0, 0, 0);
+            fI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bi[j], fI[i][j], 0, 0, 0);
+            fI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[i], br[j], fI[i][j], 0, 0, 0);
+          }
+      }
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            accR[i][j][v] += (double)fR[i][j][v];
+            accI[i][j][v] += (double)fI[i][j][v];
+          }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 4) {
+        double ar[TI], an[TI], ap[TI], br[TJ], bi[TJ];
+#pragma unroll
+        for (int i = 0; i < TI; ++i) {
+          ar[i] = Ar[ks + lk][wm + 16 * i + lr];
+          an[i] = Ai[ks + lk][wm + 16 * i + lr];
+          ap[i] = Ap[ks + lk][wm + 16 * i + lr];
+        }
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          br[j] = Br[ks + lk][wn + 16 * j + lr];
+          bi[j] = Bi[ks + lk][wn + 16 * j + lr];
+        }
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) {
+            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
+            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[i], bi[j], accR[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[i], br[j], accI[i][j], 0, 0, 0);
+          }
+      }
     }
     __syncthreads();
     if (more) {
@@ -173,15 +226,16 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
     }
   }
 
-  // v_mfma_f64_16x16x4f64 result layout: register v of lane l holds
-  // D[4 v + l/16][l % 16] of each 16 x 16 tile
+  // result layout: register v of lane l holds D[4 v + l/16][l % 16] of
+  // each 16 x 16 tile for v_mfma_f64_16x16x4f64, D[4 (l/16) + v][l % 16]
+  // for v_mfma_f32_16x16x4f32
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm + 16 * i + 4 * v + lk;
+        const int m = m0 + wm + 16 * i + (F32 ? 4 * lk + v : 4 * v + lk);
         const int n = n0 + wn + 16 * j + lr;
         if (m >= p.M || n >= p.N) continue;
         const double re = accR[i][j][v], im = accI[i][j][v];
@@ -272,12 +326,12 @@ void splitk_finish(tt_ctx* ctx, int M, int N, int batch, int nsplit, zc* ws, zc 
   hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, ctx->stream, p, nsplit);
 }
 
-template <int BM, int BN>
+template <int BM, int BN, typename RT = double>
 void launch_tile(KTimer& kt, int opA, int opB, dim3 grid, hipStream_t st, const GemmParams& p) {
-#define TTF_GEMM_CASE(OA, OB)                                                    \
-  if (opA == OA && opB == OB) {                                                  \
-    TTF_LAUNCH(kt, (zgemm_kernel<OA, OB, BM, BN>), grid, dim3(256), 0, st, p); \
-    return;                                                                      \
+#define TTF_GEMM_CASE(OA, OB)                                                        \
+  if (opA == OA && opB == OB) {                                                      \
+    TTF_LAUNCH(kt, (zgemm_kernel<OA, OB, BM, BN, RT>), grid, dim3(256), 0, st, p); \
+    return;                                                                          \
   }
   TTF_GEMM_CASE(OPN, OPN)
   TTF_GEMM_CASE(OPN, OPT)
@@ -299,7 +353,8 @@ void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc 
     zgemm_split(fmt, ctx, opA, opB, M, N, K, alpha, A, lda, strideA, B, ldb, strideB, beta, C, ldc, strideC, batch);
     return;
   }
-  if (fmt != TT_PREC_FP64) fail(TT_EINVAL, "zgemm: unknown precision");
+  if (fmt != TT_PREC_FP64 && fmt != TT_PREC_FP32) fail(TT_EINVAL, "zgemm: unknown precision");
+  const bool f32 = fmt == TT_PREC_FP32;
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (K <= 0) {
     // C = beta C: reuse the kernel with an empty K range (kernel writes alpha*0 + beta*C)
@@ -357,9 +412,20 @@ void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc 
     }
     KTimer kt2(ctx->profile_shapes ? ctx : nullptr, shape.c_str(), flops, bytes);
     {
-      KTimer kt(ctx, "zgemm", flops, bytes, true);
+      KTimer kt(ctx, f32 ? "zgemm_fp32" : "zgemm", flops, bytes, true);
       const dim3 grid(gx, gy, batch * nsplit);
-      if (bm == 64 && bn == 64)
+      if (f32) {
+        if (bm == 64 && bn == 64)
+          launch_tile<64, 64, float>(kt, opA, opB, grid, ctx->stream, p);
+        else if (bm == 128)
+          launch_tile<128, 32, float>(kt, opA, opB, grid, ctx->stream, p);
+        else if (bm == 64)
+          launch_tile<64, 32, float>(kt, opA, opB, grid, ctx->stream, p);
+        else if (bn == 32)
+          launch_tile<32, 32, float>(kt, opA, opB, grid, ctx->stream, p);
+        else
+          launch_tile<32, 64, float>(kt, opA, opB, grid, ctx->stream, p);
+      } else if (bm == 64 && bn == 64)
         launch_tile<64, 64>(kt, opA, opB, grid, ctx->stream, p);
       else if (bm == 128)
         launch_tile<128, 32>(kt, opA, opB, grid, ctx->stream, p);

@@ -20,6 +20,7 @@ TT_APPLY_SKETCH = 1
 TT_PREC_FP64 = 0
 TT_PREC_BF16X3 = 1
 TT_PREC_FP16X3 = 2
+TT_PREC_FP32 = 3
 TT_STEP_RK4 = 0
 TT_STEP_EULER = 1
 TT_STEP_MIDPOINT = 2
@@ -516,7 +517,8 @@ def tt_zgemm(ctx, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc
              precision=TT_PREC_FP64):
     """Device GEMM on torch complex128 buffers A, B, C (column-major views),
     ordered against torch's current stream like tt_eval; precision selects
-    plain FP64 (tt_zgemm) or a split 16-bit matrix-core form (tt_zgemm_mixed)."""
+    plain FP64 (tt_zgemm), a split 16-bit matrix-core form or FP32
+    (tt_zgemm_mixed)."""
     import torch
 
     cur = torch.cuda.current_stream()

@@ -60,7 +60,7 @@ def test_zgemm_against_numpy(ctx, M, N, K, batch, opa, opb):
      (8, 200, 0, 1), (4100, 20, 37, 1), (300, 32, 3000, 1), (33, 96, 700, 2)],
 )
 @pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (2, 0), (0, 1), (0, 2), (2, 2)])
-@pytest.mark.parametrize("prec", [tt.TT_PREC_BF16X3, tt.TT_PREC_FP16X3])
+@pytest.mark.parametrize("prec", [tt.TT_PREC_BF16X3, tt.TT_PREC_FP16X3, tt.TT_PREC_FP32])
 def test_zgemm_split_error_bound(ctx, M, N, K, batch, opa, opb, prec):
     """Split 16-bit products.  BF16x3: each real operand is represented to
     2^-17 relative by hi + lo, so every entry is within a small multiple of
@@ -68,7 +68,10 @@ def test_zgemm_split_error_bound(ctx, M, N, K, batch, opa, opb, prec):
     keeps 2^-22 relative, FP32 accumulation over a 32-wide K stage adds at
     most 12 roundings of 2^-24, so 2^-18 (|op(A)| |op(B)|) bounds every
     entry, plus an absolute term for components far below their stage's
-    largest (those fall into half's subnormal range).  beta C is FP64."""
+    largest (those fall into half's subnormal range).  FP32 (not split):
+    operands rounded to 2^-24, at most 32 float additions per 16-wide K
+    step, FP64 beyond: 2^-17 (|op(A)| |op(B)|) bounds every entry.  beta C
+    is FP64."""
     import torch
 
     rng = np.random.default_rng(M * 1000 + N * 10 + K + opa * 7 + opb + 5)
@@ -85,7 +88,8 @@ def test_zgemm_split_error_bound(ctx, M, N, K, batch, opa, opb, prec):
     tt.tt_zgemm(ctx, opa, opb, M, N, K, alpha, A, max(lda, 1), As[0].size, B, max(ldb, 1), Bs[0].size, beta, C, M,
                 M * N, batch, precision=prec)
     got = C.cpu().numpy()
-    coef, typical = (4 * 2.0 ** -16, 2e-5) if prec == tt.TT_PREC_BF16X3 else (2.0 ** -18, 1e-6)
+    coef, typical = {tt.TT_PREC_BF16X3: (4 * 2.0 ** -16, 2e-5), tt.TT_PREC_FP16X3: (2.0 ** -18, 1e-6),
+                     tt.TT_PREC_FP32: (2.0 ** -17, 1e-6)}[prec]
     for b in range(batch):
         g = got[b * M * N:(b + 1) * M * N].reshape((M, N), order="F")
         absprod = np.abs(_op(As[b], opa)) @ np.abs(_op(Bs[b], opb))

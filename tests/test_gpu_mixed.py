@@ -62,10 +62,10 @@ def _combine(ctx, coefs, xs, caps):
     return z
 
 
-@pytest.mark.parametrize("prec,bound", [(tt.TT_PREC_FP16X3, GATE), (tt.TT_PREC_BF16X3, 1e-3)])
+@pytest.mark.parametrize("prec,bound", [(tt.TT_PREC_FP16X3, GATE), (tt.TT_PREC_BF16X3, 1e-3), (tt.TT_PREC_FP32, GATE)])
 def test_mixed_sketched_apply_saturated(ctx, op, prec, bound):
     """The timed regime: a seeded random TT with every interior rank 64.
-    FP16x3 is within the gate of FP64; BF16x3 within 1e-3."""
+    FP16x3 and FP32 are within the gate of FP64; BF16x3 within 1e-3."""
     x = upload(ctx, inputs.random_tt(D, N, CAP, 0), caps=CAP)
     y64 = tt.Tensor(ctx, D, N, ELL)
     ymx = tt.Tensor(ctx, D, N, ELL)
@@ -121,7 +121,8 @@ def test_mixed_stages_from_identical_inputs(ctx, op):
     f.close()
 
 
-def test_mixed_step_from_identical_input(ctx, op):
+@pytest.mark.parametrize("prec", [tt.TT_PREC_FP16X3, tt.TT_PREC_FP32])
+def test_mixed_step_from_identical_input(ctx, op, prec):
     """Whole RK4 steps through tt_step from the same Gaussian initial state."""
     mu, sig = inputs.ic_params(D, 1)
     f64 = tt.Tensor(ctx, D, N, CAP)
@@ -129,12 +130,35 @@ def test_mixed_step_from_identical_input(ctx, op):
     fmx = tt.Tensor(ctx, D, N, CAP)
     fmx.copy_from(f64)
     tt.tt_step(ctx, op, f64, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ELL, 12345, precision=tt.TT_PREC_FP64)
-    tt.tt_step(ctx, op, fmx, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ELL, 12345, precision=tt.TT_PREC_FP16X3)
+    tt.tt_step(ctx, op, fmx, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ELL, 12345, precision=prec)
     err = _rel_tt(ctx, fmx, f64)
-    print(f"FP16x3 vs FP64 RK4 step from the initial condition, d=50: rel L2 {err:.2e}")
-    assert err < GATE, err
+    print(f"precision {prec} vs FP64 RK4 step from the initial condition, d=50: rel L2 {err:.2e}")
+    assert 0.0 < err < GATE, err
     for t in (f64, fmx):
         t.close()
+
+
+def test_fp32_form_at_the_fp32_configuration(ctx):
+    """The FP32 form at its own configuration (d=20, n=64 on [-6, 6],
+    nu=0.02, cap 32, tolerance 1e-8, dt 5e-4, sketched apply of width 48):
+    three RK4 steps from the Gaussian initial condition, each from the FP64
+    path's input, within the gate of the FP64 step."""
+    d, n, length, nu, cap, eps, dt, ell = 20, 64, 6.0, 0.02, 32, 1e-8, 5e-4, 48
+    op2 = tt.Operator(ctx, d, n, length, nu)
+    mu, sig = inputs.ic_params(d, 0)
+    f64 = tt.Tensor(ctx, d, n, cap)
+    f64.set_gaussian(mu, sig, length)
+    f32 = tt.Tensor(ctx, d, n, cap)
+    for s in range(3):
+        f32.copy_from(f64)
+        tt.tt_step(ctx, op2, f64, dt, cap, eps, tt.TT_APPLY_SKETCH, ell, 50 + s, precision=tt.TT_PREC_FP64)
+        tt.tt_step(ctx, op2, f32, dt, cap, eps, tt.TT_APPLY_SKETCH, ell, 50 + s, precision=tt.TT_PREC_FP32)
+        err = _rel_tt(ctx, f32, f64)
+        print(f"FP32 vs FP64 step {s} at d=20: rel L2 {err:.2e}, ranks {max(f64.ranks())}")
+        assert 0.0 < err < GATE, (s, err)
+    for t in (f64, f32):
+        t.close()
+    op2.close()
 
 
 def test_mixed_config1_trajectory_against_oracle(ctx):
@@ -168,7 +192,7 @@ def test_mixed_precision_is_rejected_when_unknown(ctx):
         tt.tt_apply(ctx, op, x, y, tt.TT_APPLY_SKETCH, 8, 1, precision=7)
     f = upload(ctx, inputs.random_tt(d, n, 2, 0), caps=4)
     with pytest.raises(tt.TTError):
-        tt.tt_step(ctx, op, f, 1e-3, 4, 1e-8, tt.TT_APPLY_SKETCH, 8, 1, precision=3)
+        tt.tt_step(ctx, op, f, 1e-3, 4, 1e-8, tt.TT_APPLY_SKETCH, 8, 1, precision=4)
     for t in (x, y, f):
         t.close()
     op.close()
