@@ -15,6 +15,10 @@ configuration.  One step = one RK4 step-truncation step (4 stages: four
 sketched operator applications, their truncations, the stage combinations
 and their truncations) followed by a pointwise read-out of 1024 entries.
 
+Before timing, the GEMM launch shapes (tile and split-K factor) of one
+step of each timed form are tuned by the library's autotuner (untimed
+set-up; `--no-autotune` keeps the shape rule).
+
 Prints one JSON line.  `value` is stages per second (4 per step) of the
 selected form over the timed steps, with the input resident in device
 memory; `fp64_reference` times the plain FP64 form the same way from the
@@ -246,6 +250,24 @@ def main_batched(args):
     for w in range(args.warmup):
         batched(everyone)
         print(f"bench: batched warm-up {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    # tiles from the autotuner: the GEMM shapes of one batched step over all
+    # instances, the heaviest tuned (untimed set-up; the sequential
+    # reference below uses the same table)
+    from paper_2403_04946_amd import autotune
+
+    t0 = time.perf_counter()
+    for c in ctxs:
+        c.reset_stats()
+        c.set_profiling(True, shapes=True)
+    batched(everyone)
+    shapes = {}
+    for c in ctxs:
+        autotune.gemm_shapes(c.dump_stats(), shapes)
+        c.set_profiling(False)
+        c.reset_stats()
+    tuned = autotune.tune(ctxs[0], shapes, top=args.autotune_top)
+    tune_s = time.perf_counter() - t0
+    print(f"bench: autotuned {len(tuned)} GEMM shapes in {tune_s:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -281,6 +303,7 @@ def main_batched(args):
             "instances": n, "contexts": nctx, "dt": DT, "eps": EPS,
             "instance_shapes": [[sp["d"], sp["n"], sp["cap"]] for sp in specs],
         },
+        "gemm_autotune": {"shapes_tuned": len(tuned), "seconds": tune_s},
         "sequential_reference": {"value": stages / ts, "unit": "instance-stages/s", "seconds": ts},
         "speedup_over_sequential": ts / tb,
         "roofline": None,
@@ -501,6 +524,10 @@ def main():
                     help="batched: the batched form on uneven instances; learned: the learned form against the "
                          "plain one on tolerance-limited trajectories (each its own JSON line)")
     ap.add_argument("--instances", type=int, default=16)
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the GEMM launch-shape rule (by default the shapes of one step of each timed form "
+                         "are tuned before timing)")
+    ap.add_argument("--autotune-top", type=int, default=64)
     ap.add_argument("--train-instances", type=int, default=12)
     ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--instances-learned", type=int, default=3)
@@ -543,6 +570,16 @@ def main():
         tt.tt_eval(ctx, f, idx, out)
         return rep
 
+    tuned = None
+    if args.autotune:
+        # GEMM launch shapes of one step, the heaviest tuned (untimed set-up)
+        from paper_2403_04946_amd import autotune
+
+        t0 = time.perf_counter()
+        shapes = autotune.profile_shapes(ctx, step)
+        res = autotune.tune(ctx, shapes, top=args.autotune_top)
+        tuned = {"shapes_tuned": len(res), "seconds": time.perf_counter() - t0}
+        print(f"bench: autotuned {len(res)} GEMM shapes", file=sys.stderr, flush=True)
     # warm-up; the last warm-up step is profiled per kernel class to find
     # the dominant kernel, whose launches alone are then timed with HIP
     # events inside the timed region (so the step time carries the event
@@ -589,8 +626,14 @@ def main():
 
     fp64_ref = None
     if prec != 0 and not args.no_fp64_reference:
-        # the plain FP64 form from the same input, timed the same way
+        # the plain FP64 form from the same input, timed the same way (its
+        # own GEMM shapes tuned first, like the selected form's)
         f.copy_from(f0)
+        if args.autotune:
+            from paper_2403_04946_amd import autotune
+
+            autotune.tune(ctx, autotune.profile_shapes(ctx, lambda: step(0)), top=args.autotune_top)
+            f.copy_from(f0)
         step(0)
         ctx.sync()
         torch.cuda.synchronize()
@@ -642,6 +685,7 @@ def main():
         "kernels_ms_profiled_warmup_step": kernels_ms,
         "qr_fallbacks": int((breakdown or {}).get("qr_fallbacks", {"launches": 0})["launches"]),
         "wall_s": wall,
+        "gemm_autotune": tuned,
         "final_ranks_max": final_ranks_max,
         "step_max_rank": rep["max_rank"] if rep else None,
     }

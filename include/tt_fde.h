@@ -387,6 +387,29 @@ int tt_zgemm_mixed(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, i
                    int64_t ldb, int64_t strideB, double beta_re, double beta_im, double* C, int64_t ldc,
                    int64_t strideC, int batch);
 
+/* GEMM launch-shape autotuner (process-wide table).  Every GEMM of the
+ * library picks its workgroup tile and split-K factor by a rule of the
+ * output shape; an entry of this table replaces the rule for one exact
+ * (precision, opA, opB, M, N, K, batch).  tt_gemm_autotune times every
+ * candidate tile (FP64/FP32: 64x64, 128x32, 64x32, 32x32, 32x64; split
+ * 16-bit: 64x64, 32x64, 64x32, 32x32 as TI x TJ blocks of 32) with every
+ * power-of-two split-K factor up to half the K steps, on random operands it
+ * allocates (and frees) itself, three timed runs each after one warm-up on
+ * the context's stream, and stores the fastest; choice (3 ints, may be
+ * NULL): tile a, b and the split factor; best_us (may be NULL): its time.
+ * Synchronous; it allocates device memory, so it is a set-up step, not for
+ * code under graph capture.  Different split factors sum in different
+ * groupings: results differ at rounding level from the untuned rule, and
+ * are deterministic for a given table.  Table entries are 10 ints:
+ * precision, opA, opB, M, N, K, batch, a, b, split; get/set copy one entry
+ * (TT_EINVAL for an index out of range or an invalid entry). */
+int tt_gemm_autotune(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, int K, int batch, int* choice,
+                     double* best_us);
+int tt_gemm_table_count(void);
+int tt_gemm_table_get(int index, int* entry);
+int tt_gemm_table_set(const int* entry);
+int tt_gemm_table_clear(void);
+
 /* Complex inner product <x, y> = sum over all entries of conj(x) y
  * (synchronous): left-to-right contraction of the cores, two GEMMs per
  * core (App. A.1 arithmetic).  out: host array of 2 doubles (re, im). */

@@ -1891,6 +1891,132 @@ int tt_zgemm_mixed(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, i
   ABI_CATCH(ctx)
 }
 
+// ------------------------------------------------------------ autotuner
+namespace {
+// the launch shapes a GEMM of this form may take (tile codes as in GemmChoice)
+std::vector<std::pair<int, int>> gemm_tiles(int precision) {
+  if (precision == TT_PREC_FP64 || precision == TT_PREC_FP32) return {{64, 64}, {128, 32}, {64, 32}, {32, 32}, {32, 64}};
+  return {{2, 2}, {1, 2}, {2, 1}, {1, 1}};
+}
+bool gemm_choice_valid(int precision, int a, int b, int nsplit) {
+  if (nsplit < 1 || nsplit > 128) return false;
+  for (const auto& t : gemm_tiles(precision))
+    if (t.first == a && t.second == b) return true;
+  return false;
+}
+struct ForceGuard {
+  ~ForceGuard() { ttf::gemm_force(nullptr); }
+};
+}  // namespace
+
+int tt_gemm_autotune(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, int K, int batch, int* choice,
+                     double* best_us) {
+  if (!ctx) return TT_EINVAL;
+  zc* bufs[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  auto release = [&]() {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (zc*& b : bufs)
+      if (b) (void)hipFree(b), b = nullptr;
+    for (hipEvent_t& e : ev)
+      if (e) (void)hipEventDestroy(e), e = nullptr;
+  };
+  try {
+    require(precision >= TT_PREC_FP64 && precision <= TT_PREC_FP32, TT_EINVAL, "tt_gemm_autotune: unknown precision");
+    require(opA >= 0 && opA <= 2 && opB >= 0 && opB <= 2, TT_EINVAL, "tt_gemm_autotune: op must be 0, 1 or 2");
+    require(M >= 1 && N >= 1 && K >= 1 && batch >= 1, TT_EINVAL, "tt_gemm_autotune: sizes must be positive");
+    const size_t na = (size_t)M * K * batch, nb = (size_t)K * N * batch, nc = (size_t)M * N * batch;
+    require(na <= (1ull << 28) && nb <= (1ull << 28) && nc <= (1ull << 28), TT_EINVAL,
+            "tt_gemm_autotune: operands above 2^28 elements");
+    const size_t ns[3] = {na, nb, nc};
+    for (int i = 0; i < 3; ++i)
+      if (hipMalloc((void**)&bufs[i], sizeof(zc) * ns[i]) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(TT_ENOMEM, "tt_gemm_autotune: allocation failed");
+      }
+    sketch_core(ctx, bufs[0], (long)na, 0x5EEDull, 1, 1.0);
+    sketch_core(ctx, bufs[1], (long)nb, 0x5EEDull, 2, 1.0);
+    fill_zero(ctx, bufs[2], (long)nc);
+    const int lda = opA == OPN ? M : K, ldb = opB == OPN ? K : N;
+    TTF_HIP(hipEventCreate(&ev[0]));
+    TTF_HIP(hipEventCreate(&ev[1]));
+    const int kstep = (precision == TT_PREC_FP64 || precision == TT_PREC_FP32) ? 16 : 32;
+    const int kblocks = (K + kstep - 1) / kstep;
+    ForceGuard guard;
+    double best = 1e300;
+    GemmChoice bestc;
+    for (const auto& t : gemm_tiles(precision))
+      for (int sp = 1; sp <= 128; sp *= 2) {
+        if (sp > 1 && sp > kblocks / 2) break;
+        GemmChoice c;
+        c.a = t.first;
+        c.b = t.second;
+        c.nsplit = sp;
+        gemm_force(&c);
+        auto run = [&]() {
+          zgemm_prec(precision, ctx, opA, opB, M, N, K, Z(1), bufs[0], lda, (long)M * K, bufs[1], ldb, (long)K * N,
+                     Z(0), bufs[2], M, (long)M * N, batch);
+        };
+        run();
+        double tmin = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+          TTF_HIP(hipEventRecord(ev[0], ctx->stream));
+          run();
+          TTF_HIP(hipEventRecord(ev[1], ctx->stream));
+          TTF_HIP(hipEventSynchronize(ev[1]));
+          float ms = 0.f;
+          TTF_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+          tmin = std::min(tmin, (double)ms * 1e3);
+        }
+        gemm_force(nullptr);
+        if (tmin < best) {
+          best = tmin;
+          bestc = c;
+        }
+      }
+    const int e[10] = {precision, opA, opB, M, N, K, batch, bestc.a, bestc.b, bestc.nsplit};
+    gemm_table_put(e);
+    if (choice) {
+      choice[0] = bestc.a;
+      choice[1] = bestc.b;
+      choice[2] = bestc.nsplit;
+    }
+    if (best_us) *best_us = best;
+    release();
+    return TT_OK;
+  } catch (const ttf::Error& e) {
+    release();
+    ctx->last_error = e.msg;
+    return e.code;
+  } catch (...) {
+    release();
+    return TT_EINVAL;
+  }
+}
+
+int tt_gemm_table_count(void) { return gemm_table_count(); }
+
+int tt_gemm_table_get(int index, int* entry) {
+  if (!entry) return TT_EINVAL;
+  return gemm_table_entry(index, entry) ? TT_OK : TT_EINVAL;
+}
+
+int tt_gemm_table_set(const int* entry) {
+  if (!entry) return TT_EINVAL;
+  const int p = entry[0];
+  if (p < TT_PREC_FP64 || p > TT_PREC_FP32) return TT_EINVAL;
+  if (entry[1] < 0 || entry[1] > 2 || entry[2] < 0 || entry[2] > 2) return TT_EINVAL;
+  if (entry[3] < 0 || entry[4] < 0 || entry[5] < 0 || entry[6] < 1) return TT_EINVAL;
+  if (!gemm_choice_valid(p, entry[7], entry[8], entry[9])) return TT_EINVAL;
+  gemm_table_put(entry);
+  return TT_OK;
+}
+
+int tt_gemm_table_clear(void) {
+  gemm_table_clear();
+  return TT_OK;
+}
+
 int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out) {
   if (!ctx || !x || !out) return TT_EINVAL;
   ABI_TRY

@@ -203,6 +203,21 @@ void zgemm_split(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc
                  int batch);
 // C = alpha sum_s ws[s] + beta C over nsplit split-K partials
 // ws[s][batch][N][M] (fixed summation order)
+// Tuned GEMM launch shapes (the autotuner's table, process-wide): for a
+// GEMM of the given form and shape, the workgroup tile (a, b: BM x BN of the
+// FP64/FP32 kernel, or TI x TJ 32-blocks of the split 16-bit kernel) and the
+// split-K factor.  A forced choice (set by the tuner on its own thread)
+// takes precedence over the table.
+struct GemmChoice {
+  int a = 0, b = 0, nsplit = 0;
+};
+bool gemm_choice(int fmt, int opA, int opB, int M, int N, int K, int batch, GemmChoice* out);
+void gemm_force(const GemmChoice* c);  // nullptr: none (calling thread only)
+// table entries as 10 ints: fmt, opA, opB, M, N, K, batch, a, b, nsplit
+void gemm_table_put(const int* e);
+int gemm_table_count();
+bool gemm_table_entry(int index, int* e);
+void gemm_table_clear();
 void splitk_finish(tt_ctx* ctx, int M, int N, int batch, int nsplit, zc* ws, zc alpha, zc beta, zc* C, long ldc,
                    long strideC);
 

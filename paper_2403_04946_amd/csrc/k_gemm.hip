@@ -20,11 +20,78 @@
 // step of 16 is accumulated in float and then added into double
 // accumulators, so the error per entry stays near 2^-24 times the sum of
 // |a||b| of one K step, whatever K is.
+#include <atomic>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 
 #include "common.hpp"
 
 namespace ttf {
+
+// ------------------------------------------------------ tuned choices
+namespace {
+using GemmKey = std::tuple<int, int, int, int, int, int, int>;
+std::map<GemmKey, GemmChoice>& gemm_table() {
+  static std::map<GemmKey, GemmChoice> t;
+  return t;
+}
+std::mutex& gemm_table_mutex() {
+  static std::mutex m;
+  return m;
+}
+std::atomic<int> gemm_table_size{0};
+thread_local const GemmChoice* gemm_forced = nullptr;
+}  // namespace
+
+void gemm_force(const GemmChoice* c) { gemm_forced = c; }
+
+bool gemm_choice(int fmt, int opA, int opB, int M, int N, int K, int batch, GemmChoice* out) {
+  if (gemm_forced) {
+    *out = *gemm_forced;
+    return true;
+  }
+  if (gemm_table_size.load(std::memory_order_relaxed) == 0) return false;
+  std::lock_guard<std::mutex> lock(gemm_table_mutex());
+  auto it = gemm_table().find(GemmKey{fmt, opA, opB, M, N, K, batch});
+  if (it == gemm_table().end()) return false;
+  *out = it->second;
+  return true;
+}
+
+void gemm_table_put(const int* e) {
+  std::lock_guard<std::mutex> lock(gemm_table_mutex());
+  GemmChoice c;
+  c.a = e[7];
+  c.b = e[8];
+  c.nsplit = e[9];
+  gemm_table()[GemmKey{e[0], e[1], e[2], e[3], e[4], e[5], e[6]}] = c;
+  gemm_table_size.store((int)gemm_table().size());
+}
+
+int gemm_table_count() {
+  std::lock_guard<std::mutex> lock(gemm_table_mutex());
+  return (int)gemm_table().size();
+}
+
+bool gemm_table_entry(int index, int* e) {
+  std::lock_guard<std::mutex> lock(gemm_table_mutex());
+  if (index < 0 || index >= (int)gemm_table().size()) return false;
+  auto it = gemm_table().begin();
+  std::advance(it, index);
+  const GemmKey& k = it->first;
+  e[0] = std::get<0>(k); e[1] = std::get<1>(k); e[2] = std::get<2>(k); e[3] = std::get<3>(k);
+  e[4] = std::get<4>(k); e[5] = std::get<5>(k); e[6] = std::get<6>(k);
+  e[7] = it->second.a; e[8] = it->second.b; e[9] = it->second.nsplit;
+  return true;
+}
+
+void gemm_table_clear() {
+  std::lock_guard<std::mutex> lock(gemm_table_mutex());
+  gemm_table().clear();
+  gemm_table_size.store(0);
+}
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
@@ -375,7 +442,7 @@ void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc 
     bm = 32;
     bn = 64;
   }
-  const int gx = (N + bn - 1) / bn, gy = (M + bm - 1) / bm;
+  int gx = (N + bn - 1) / bn, gy = (M + bm - 1) / bm;
   const long tiles = (long)gx * gy * batch;
   // split K when the output grid alone cannot occupy the chip (fewer tiles
   // than compute units) and the output is small enough for the partial sums
@@ -388,6 +455,20 @@ void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc 
   if (tiles < 256 && (long)M * N * batch <= (1L << 18) && kblocks >= 4) {
     nsplit = (int)std::min<long>((512 + tiles - 1) / tiles, kblocks / 2);
     nsplit = std::max(1, std::min(nsplit, 128));
+  }
+  {
+    // a tuned launch shape for this GEMM replaces the rule above
+    GemmChoice c;
+    if (gemm_choice(fmt, opA, opB, M, N, K, batch, &c)) {
+      const bool ok = (c.a == 64 && (c.b == 64 || c.b == 32)) || (c.a == 128 && c.b == 32) ||
+                      (c.a == 32 && (c.b == 32 || c.b == 64));
+      if (!ok || c.nsplit < 1 || c.nsplit > 128) fail(TT_EINVAL, "zgemm: bad tuned launch shape");
+      bm = c.a;
+      bn = c.b;
+      gx = (N + bn - 1) / bn;
+      gy = (M + bm - 1) / bm;
+      nsplit = std::max(1, std::min(c.nsplit, std::max(1, kblocks)));
+    }
   }
   int kchunk = ((kblocks + nsplit - 1) / nsplit) * kb;
   if (K == 0) kchunk = 0;
@@ -406,7 +487,7 @@ void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc 
     std::string shape;
     if (ctx->profile_shapes) {
       const char ops[3] = {'N', 'T', 'C'};
-      shape = std::string("zgemm:") + ops[opA] + ops[opB] + ":" + std::to_string(M) + "x" +
+      shape = std::string(f32 ? "zgemm_fp32:" : "zgemm:") + ops[opA] + ops[opB] + ":" + std::to_string(M) + "x" +
               std::to_string(N) + "x" +
               std::to_string(K) + "x" + std::to_string(batch);
     }

@@ -376,11 +376,20 @@ void zgemm_split(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc
   int ti = 2, tj = 2;
   if (M <= 32) ti = 1;
   if (N <= 32) tj = 1;
+  GemmChoice tuned;
+  const bool have_tuned = gemm_choice(fmt, opA, opB, M, N, K, batch, &tuned);
+  if (have_tuned) {
+    if (tuned.a < 1 || tuned.a > 2 || tuned.b < 1 || tuned.b > 2 || tuned.nsplit < 1 || tuned.nsplit > 128)
+      fail(TT_EINVAL, "zgemm_split: bad tuned launch shape");
+    ti = tuned.a;
+    tj = tuned.b;
+  }
   const int bm = 32 * ti, bn = 32 * tj;
   const int gx = (M + bm - 1) / bm, gy = (N + bn - 1) / bn;
   const long tiles = (long)gx * gy * batch;
   int nsplit = 1;
   if (tiles < 512 && KB >= 4) nsplit = (int)std::max<long>(1, std::min<long>({(512 + tiles - 1) / tiles, KB / 2, 128}));
+  if (have_tuned) nsplit = std::max(1, std::min(tuned.nsplit, std::max(1, KB)));
   int kbchunk = KB > 0 ? (KB + nsplit - 1) / nsplit : 0;
   nsplit = KB > 0 ? (KB + kbchunk - 1) / kbchunk : 1;
   p.kbchunk = kbchunk;

@@ -198,6 +198,11 @@ _SIGS = {
     "tt_step_batch": (I, [I, P, P, P, PD, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport), PI]),
     "tt_op_create_burgers_hopf_ex": (I, [P, I, I, D, D, P, P]),
     "tt_op_create_cdf_burgers": (I, [P, I, I, ctypes.POINTER(CdfOpts), P]),
+    "tt_gemm_autotune": (I, [P, I, I, I, I, I, I, I, PI, PD]),
+    "tt_gemm_table_count": (I, []),
+    "tt_gemm_table_get": (I, [I, PI]),
+    "tt_gemm_table_set": (I, [PI]),
+    "tt_gemm_table_clear": (I, []),
     "tt_tensor_set_cdf_gaussian": (I, [P, P, D, D]),
     "tt_ctx_set_profile_sampling": (I, [P, I]),
     "tt_dot": (I, [P, P, P, PD]),
@@ -618,6 +623,40 @@ class MLP:
         if self.h:
             lib().tt_mlp_destroy(self.h)
             self.h = None
+
+
+def gemm_autotune(ctx, precision, opA, opB, M, N, K, batch=1):
+    """Time every launch shape of one GEMM and keep the fastest in the
+    process-wide table; returns ((a, b, split), microseconds)."""
+    c = (ctypes.c_int * 3)()
+    us = ctypes.c_double()
+    ctx.check(lib().tt_gemm_autotune(ctx.h, int(precision), int(opA), int(opB), int(M), int(N), int(K), int(batch),
+                                     c, ctypes.byref(us)))
+    return (c[0], c[1], c[2]), us.value
+
+
+def gemm_table():
+    """The tuned entries: lists of 10 ints (precision, opA, opB, M, N, K,
+    batch, a, b, split)."""
+    out = []
+    for i in range(lib().tt_gemm_table_count()):
+        e = (ctypes.c_int * 10)()
+        if lib().tt_gemm_table_get(i, e) != 0:
+            break
+        out.append(list(e))
+    return out
+
+
+def gemm_table_set(entries):
+    for e in entries:
+        arr = (ctypes.c_int * 10)(*[int(v) for v in e])
+        rc = lib().tt_gemm_table_set(arr)
+        if rc != 0:
+            raise TTError(rc, f"invalid GEMM table entry {list(e)}")
+
+
+def gemm_table_clear():
+    lib().tt_gemm_table_clear()
 
 
 def tt_norm(ctx, x):
