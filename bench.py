@@ -528,6 +528,8 @@ def main():
                     help="keep the GEMM launch-shape rule (by default the shapes of one step of each timed form "
                          "are tuned before timing)")
     ap.add_argument("--autotune-top", type=int, default=64)
+    ap.add_argument("--autotune-save", default=None, help="write the tuned GEMM table (JSON) at the end")
+    ap.add_argument("--autotune-load", default=None, help="use this GEMM table instead of tuning")
     ap.add_argument("--train-instances", type=int, default=12)
     ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--instances-learned", type=int, default=3)
@@ -571,7 +573,14 @@ def main():
         return rep
 
     tuned = None
-    if args.autotune:
+    if args.autotune_load:
+        # a table written by an earlier run (--autotune-save)
+        from paper_2403_04946_amd import autotune
+
+        autotune.load(args.autotune_load)
+        tuned = {"loaded": args.autotune_load, "entries": len(tt.gemm_table())}
+        args.autotune = False
+    elif args.autotune:
         # GEMM launch shapes of one step, the heaviest tuned (untimed set-up)
         from paper_2403_04946_amd import autotune
 
@@ -653,6 +662,10 @@ def main():
     if prec != 0 and not args.no_error_report:
         errors = error_report(ctx, tt, op, f0, prec, ell, args.error_steps)
         print("bench: error report done", file=sys.stderr, flush=True)
+    if args.autotune_save:
+        from paper_2403_04946_amd import autotune
+
+        autotune.save(args.autotune_save)
     roof = roofline(dom, kd)
     kernels_ms = {k: round(v["ms"], 3) for k, v in (breakdown or {}).items() if k != "qr_fallbacks"}
     result = {
