@@ -54,3 +54,40 @@ def test_he_init_matches_the_parameter_count():
     assert p.dtype == np.float32
     assert p.size == 128 * 13 + 128 + 128 * 128 + 128 + 128 + 1
     assert np.all(p[128 * 13:128 * 13 + 128] == 0)
+
+
+def test_autotune_shape_keys_are_parsed():
+    from paper_2403_04946_amd import autotune, tt
+
+    stats = {
+        "zgemm:NC:300x32x3000x1": {"ms": 1.5},
+        "zgemm_fp16x3:CN:64x80x10240x2": {"ms": 2.0},
+        "zgemm_fp32:TN:8x8x8x1": {"ms": 0.1},
+        "zgemm": {"ms": 9.0},  # a kernel class, not a shape
+        "jacobi:320x320": {"ms": 3.0},
+    }
+    got = autotune.gemm_shapes(stats)
+    assert got == {(tt.TT_PREC_FP64, 0, 2, 300, 32, 3000, 1): 1.5,
+                   (tt.TT_PREC_FP16X3, 2, 0, 64, 80, 10240, 2): 2.0,
+                   (tt.TT_PREC_FP32, 1, 0, 8, 8, 8, 1): 0.1}
+    more = autotune.gemm_shapes({"zgemm:NC:300x32x3000x1": {"ms": 0.5}}, got)
+    assert more[(tt.TT_PREC_FP64, 0, 2, 300, 32, 3000, 1)] == 2.0
+
+
+def test_gemm_table_roundtrip_without_a_device(tmp_path):
+    from paper_2403_04946_amd import autotune, tt
+
+    tt.gemm_table_clear()
+    tt.gemm_table_set([[0, 0, 2, 64, 64, 128, 1, 32, 64, 4], [2, 2, 0, 16, 16, 64, 1, 1, 1, 2]])
+    path = str(tmp_path / "t.json")
+    autotune.save(path)
+    saved = tt.gemm_table()
+    tt.gemm_table_clear()
+    assert tt.gemm_table() == []
+    autotune.load(path)
+    assert tt.gemm_table() == saved and len(saved) == 2
+    import pytest
+
+    with pytest.raises(tt.TTError):
+        tt.gemm_table_set([[2, 0, 0, 8, 8, 8, 1, 64, 64, 1]])  # split 16-bit tiles are 1 or 2 blocks
+    tt.gemm_table_clear()
