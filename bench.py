@@ -366,7 +366,7 @@ def main_learned(args):
 
     held = instances(args.instances_learned, 77, (10, 14))
     tp = tl = 0.0
-    used = fb = 0
+    used = fb = afb = aused = 0
     diffs, rank_err = [], []
     for i, inst in enumerate(held):
         _, fp, plain = trajectory(inst, args.steps + 1, seed=3)
@@ -376,6 +376,8 @@ def main_learned(args):
         tl += sum(r["wall"] for r in lrn[1:])
         used += sum(r["learned_used"] for r in lrn)
         fb += sum(r["learned_fallback"] for r in lrn)
+        afb += sum(r["apply_fallback"] for r in lrn)
+        aused += sum(1 for r in lrn if r["apply_widths"] is not None)
         diffs.append(rel_tt(fl, fp))
         xt, yt = learned.samples_from_records(plain)
         rank_err.append(float(np.abs(pred.predict(xt) - yt).mean()))
@@ -410,6 +412,8 @@ def main_learned(args):
         "gain_over_plain": tp / tl,
         "randomised_roundings": used,
         "fallbacks": fb,
+        "steps_with_learned_apply_widths": aused,
+        "stage_applications_redone": afb,
         "rel_diff_to_plain_after_steps": diffs,
         "predictor_mean_abs_rank_error": rank_err,
         "learned_tol": 1e-6,

@@ -310,6 +310,13 @@ typedef struct {
                             rounding of its small result; otherwise the
                             deterministic rounding of the sum is used */
   double learned_tol;    /* relative error accepted from a randomised rounding */
+  const int* learned_apply_widths; /* learned form (RK4, sketched apply): NULL,
+                            or d+1 per-bond sketch widths (1..512, the end
+                            entries ignored, capped at sketch_rank) for the
+                            stage applications; a stage whose rounded
+                            derivative reaches its width at a bond (the
+                            width may have cut it) is applied again at
+                            sketch_rank (fallback) */
 } tt_step_opts;
 
 typedef struct {
@@ -321,6 +328,9 @@ typedef struct {
   double learned_err;    /* the largest a posteriori relative error among them */
   double final_norm;     /* norm of the final combination (explicit schemes) */
   double final_sv[TT_MAX_D][8]; /* sv_last of the final rounding */
+  int k_ranks[TT_MAX_D + 1];  /* per bond, the largest rank of the rounded
+                                 stage derivatives (explicit schemes) */
+  int learned_apply_fallback; /* stages applied again at sketch_rank */
 } tt_step_report;
 
 /* One step-truncation step of df/dt = L f, in place, T = tt_round(eps,

@@ -1501,6 +1501,13 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
   const int scheme = opts->scheme;
   require(scheme >= TT_STEP_RK4 && scheme <= TT_STEP_IMPLICIT_MIDPOINT, TT_EINVAL, "tt_step: unknown scheme");
   const bool implicit = scheme == TT_STEP_IMPLICIT_EULER || scheme == TT_STEP_IMPLICIT_MIDPOINT;
+  if (opts->learned_apply_widths) {
+    require(scheme == TT_STEP_RK4 && opts->apply_mode == TT_APPLY_SKETCH, TT_EINVAL,
+            "tt_step: learned_apply_widths needs the RK4 scheme and the sketched apply");
+    for (int k = 0; k <= f->d; ++k)
+      require(opts->learned_apply_widths[k] >= 1 && opts->learned_apply_widths[k] <= 512, TT_EINVAL,
+              "tt_step: learned_apply_widths outside [1, 512]");
+  }
   if (opts->learned_widths) {
     require(scheme == TT_STEP_RK4, TT_EINVAL, "tt_step: learned_widths needs the RK4 scheme");
     require(opts->learned_tol >= 0.0, TT_EINVAL, "tt_step: learned_tol must be >= 0");
@@ -1597,9 +1604,34 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
     return x;
   };
   // stage s: k_s = T[L y_s] with its own sketch seed
+  std::vector<int> kr(d + 1, 0);
+  int apply_fallback = 0;
+  // learned form: per-bond sketch widths for the stage applications
+  std::vector<int> aw;
+  if (opts->learned_apply_widths && mode == TT_APPLY_SKETCH) {
+    aw.assign(d + 1, 1);
+    for (int k = 1; k < d; ++k) aw[k] = std::max(1, std::min(opts->learned_apply_widths[k], l));
+  }
   auto stage = [&](int s, const tt_tensor* in) {
-    apply_any(ctx, op, in, T.k[s], mode, l, opts->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(s + 1), opts->precision);
-    round_tensor(ctx, T.k[s], eps, rmax, nullptr);
+    const uint64_t seed = opts->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(s + 1);
+    bool done = false;
+    if (!aw.empty()) {
+      int lw = 1;
+      for (int k = 0; k <= d; ++k) lw = std::max(lw, aw[k]);
+      apply_sketch(ctx, op, in, T.k[s], lw, seed, opts->precision, aw.data());
+      round_tensor(ctx, T.k[s], eps, rmax, nullptr);
+      // a bond whose rounded rank reaches a width below the plain one may
+      // have been cut by the sketch: apply the stage again at full width
+      done = true;
+      for (int k = 1; k < d && done; ++k)
+        if (aw[k] < l && T.k[s]->rank[k] >= aw[k]) done = false;
+      if (!done) ++apply_fallback;
+    }
+    if (!done) {
+      apply_any(ctx, op, in, T.k[s], mode, l, seed, opts->precision);
+      round_tensor(ctx, T.k[s], eps, rmax, nullptr);
+    }
+    for (int k = 0; k <= d; ++k) kr[k] = std::max(kr[k], T.k[s]->rank[k]);
     track(T.k[s]);
   };
   int stages = 0;
@@ -1683,6 +1715,8 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
     rep->learned_used = learned_used;
     rep->learned_fallback = learned_fallback;
     rep->learned_err = learned_err;
+    rep->learned_apply_fallback = apply_fallback;
+    for (int k = 0; k <= d; ++k) rep->k_ranks[k] = kr[k];
   }
   track(result);
   copy_tensor(ctx, result, f);

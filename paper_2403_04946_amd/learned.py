@@ -22,6 +22,11 @@ step are the predicted ranks plus ``OVERSAMPLE``; when a predicted rank
 reaches the cap the rounding is cap-limited, the randomised result cannot
 meet a tolerance that the deterministic rounding itself misses, and the step
 runs without the learned widths.
+
+The stage applications' sketch widths follow the ranks the previous step's
+rounded stage derivatives kept (plus the same oversampling); a stage whose
+rounded derivative reaches its width at some bond is applied again at the
+plain width.
 """
 import math
 import time
@@ -65,6 +70,16 @@ def widths_from_ranks(pred, d, rmax, oversample=OVERSAMPLE):
     if pred.size == 0 or int(pred.max()) >= rmax:
         return None
     return [1] + [int(min(512, max(1, p) + oversample)) for p in pred] + [1]
+
+
+def apply_widths(k_ranks, rmax, sketch_rank, oversample=OVERSAMPLE):
+    """Sketch widths of the stage applications from the ranks the previous
+    step's rounded stage derivatives kept, or None when a bond reached the
+    cap there (a cap-limited derivative gives no bound on the width)."""
+    inner = [int(r) for r in k_ranks[1:-1]]
+    if not inner or max(inner) >= rmax:
+        return None
+    return [1] + [min(sketch_rank, max(1, r) + oversample) for r in inner] + [1]
 
 
 def he_init(n_in, width, seed):
@@ -126,17 +141,19 @@ def run_trajectory(ctx, op, f, steps, dt, rmax, eps, sketch_rank, nu, predictor=
     for s in range(steps):
         ctx.sync()
         t0 = time.perf_counter()
-        widths = None
+        widths = awidths = None
         if predictor is not None and rep is not None:
             feats = bond_features(rep["ranks"], rep["final_sv"], rep["final_norm"], nu, t, rmax)
             widths = widths_from_ranks(predictor.predict(feats), f.d, rmax)
+            awidths = apply_widths(rep["k_ranks"], rmax, sketch_rank) if widths is not None else None
         rep = tt.tt_step(ctx, op, f, dt, rmax, eps, tt.TT_APPLY_SKETCH, sketch_rank, seed + s, precision=precision,
-                         learned_widths=widths, learned_tol=tol)
+                         learned_widths=widths, learned_tol=tol, learned_apply_widths=awidths)
         ctx.sync()
         wall = time.perf_counter() - t0
         t += dt
         rec = {"wall": wall, "ranks": rep["ranks"], "widths": widths, "learned_used": rep["learned_used"],
                "learned_fallback": rep["learned_fallback"], "learned_err": rep["learned_err"],
+               "apply_widths": awidths, "apply_fallback": rep["learned_apply_fallback"],
                "features": bond_features(rep["ranks"], rep["final_sv"], rep["final_norm"], nu, t, rmax)}
         recs.append(rec)
         if on_step is not None:

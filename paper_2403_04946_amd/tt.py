@@ -84,6 +84,7 @@ class StepOpts(ctypes.Structure):
         ("krylov_rmax", ctypes.c_int),
         ("learned_widths", ctypes.POINTER(ctypes.c_int)),
         ("learned_tol", ctypes.c_double),
+        ("learned_apply_widths", ctypes.POINTER(ctypes.c_int)),
     ]
 
 
@@ -144,6 +145,8 @@ class StepReport(ctypes.Structure):
         ("learned_err", ctypes.c_double),
         ("final_norm", ctypes.c_double),
         ("final_sv", (ctypes.c_double * 8) * MAX_D),
+        ("k_ranks", ctypes.c_int * (MAX_D + 1)),
+        ("learned_apply_fallback", ctypes.c_int),
     ]
 
 
@@ -466,25 +469,34 @@ def tt_round(ctx, x, eps, rmax=0, report=True):
 
 def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0,
             scheme=TT_STEP_RK4, gmres_tol=1e-10, gmres_max_iter=30, krylov_rmax=0,
-            learned_widths=None, learned_tol=1e-6):
+            learned_widths=None, learned_tol=1e-6, learned_apply_widths=None):
     """One step; ``learned_widths`` (d+1 ints) selects the learned form, whose
-    truncations of sums are randomised roundings to these widths, checked."""
-    widths = None
-    if learned_widths is not None:
-        if len(learned_widths) != f.d + 1:
-            raise ValueError("learned_widths needs d+1 entries")
-        widths = (ctypes.c_int * (f.d + 1))(*[int(w) for w in learned_widths])
+    truncations of sums are randomised roundings to these widths, checked;
+    ``learned_apply_widths`` (d+1 ints) sets the stage applications' sketch
+    widths per bond (checked for saturation)."""
+
+    def arr(v, name):
+        if v is None:
+            return None
+        if len(v) != f.d + 1:
+            raise ValueError(f"{name} needs d+1 entries")
+        return (ctypes.c_int * (f.d + 1))(*[int(w) for w in v])
+
+    widths = arr(learned_widths, "learned_widths")
+    awidths = arr(learned_apply_widths, "learned_apply_widths")
+    ip = ctypes.POINTER(ctypes.c_int)
     o = StepOpts(ctypes.sizeof(StepOpts), int(rmax), float(eps), int(mode), int(sketch_rank), int(seed),
                  int(precision), int(scheme), float(gmres_tol), int(gmres_max_iter), int(krylov_rmax),
-                 ctypes.cast(widths, ctypes.POINTER(ctypes.c_int)) if widths is not None else None,
-                 float(learned_tol))
+                 ctypes.cast(widths, ip) if widths is not None else None, float(learned_tol),
+                 ctypes.cast(awidths, ip) if awidths is not None else None)
     rep = StepReport()
     ctx.check(lib().tt_step(ctx.h, op.h, f.h, float(dt), ctypes.byref(o), ctypes.byref(rep)))
     nb = max(f.d - 1, 0)
     return {"stages": rep.stages, "max_rank": rep.max_rank, "ranks": list(rep.ranks[: f.d + 1]),
             "learned_used": rep.learned_used, "learned_fallback": rep.learned_fallback,
             "learned_err": rep.learned_err, "final_norm": rep.final_norm,
-            "final_sv": [list(rep.final_sv[c]) for c in range(nb)]}
+            "final_sv": [list(rep.final_sv[c]) for c in range(nb)],
+            "k_ranks": list(rep.k_ranks[: f.d + 1]), "learned_apply_fallback": rep.learned_apply_fallback}
 
 
 def tt_step_batch(ctxs, ops, fs, dts, rmaxs, epss, mode=TT_APPLY_EXACT, sketch_ranks=None, seeds=None,

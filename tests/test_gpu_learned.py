@@ -185,6 +185,39 @@ def test_learned_step_widths_checked_and_fallback(ctx):
         t_.close()
 
 
+def test_learned_apply_widths_checked_and_fallback(ctx):
+    """Stage applications at per-bond sketch widths: above the ranks the
+    derivatives keep, no stage is redone and the step is within the
+    tolerance of the plain one; at width 2 every stage reaches its width,
+    is applied again at the plain width, and the step is the plain one."""
+    inst = _instances(1, 6, (8, 8))[0]
+    d, n, nu, cap = inst["d"], inst["n"], inst["nu"], inst["cap"]
+    op = tt.Operator(ctx, d, n, LEN_L, nu)
+    f0 = tt.Tensor(ctx, d, n, cap)
+    f0.set_gaussian(inst["mu"], inst["sigma"], LEN_L)
+    for s in range(3):
+        tt.tt_step(ctx, op, f0, DT_L, cap, EPS_L, tt.TT_APPLY_SKETCH, ELL_L, s)
+    a, b, c = (tt.Tensor(ctx, d, n, cap) for _ in range(3))
+    for t_ in (a, b, c):
+        t_.copy_from(f0)
+    rp = tt.tt_step(ctx, op, a, DT_L, cap, EPS_L, tt.TT_APPLY_SKETCH, ELL_L, 9)
+    assert max(rp["k_ranks"][1:-1]) < ELL_L - 8
+    wide = [1] + [r + 8 for r in rp["k_ranks"][1:-1]] + [1]
+    rw = tt.tt_step(ctx, op, b, DT_L, cap, EPS_L, tt.TT_APPLY_SKETCH, ELL_L, 9, learned_apply_widths=wide)
+    print("k ranks", rp["k_ranks"], "fallbacks", rw["learned_apply_fallback"], "diff", _rel_tt(ctx, b, a))
+    assert rw["learned_apply_fallback"] == 0
+    assert _rel_tt(ctx, b, a) < 1e-5
+    narrow = [1] + [2] * (d - 1) + [1]
+    rn = tt.tt_step(ctx, op, c, DT_L, cap, EPS_L, tt.TT_APPLY_SKETCH, ELL_L, 9, learned_apply_widths=narrow)
+    assert rn["learned_apply_fallback"] == 4
+    assert c.ranks() == a.ranks()
+    assert all(np.array_equal(x, y) for x, y in zip(c.get_cores(), a.get_cores()))
+    with pytest.raises(tt.TTError):
+        tt.tt_step(ctx, op, c, DT_L, cap, EPS_L, tt.TT_APPLY_EXACT, ELL_L, 9, learned_apply_widths=narrow)
+    for t_ in (f0, a, b, c):
+        t_.close()
+
+
 def test_learned_form_gain_over_plain(ctx):
     """The rank predictor trained on the GPU from plain-solver rank
     histories, then the learned trajectory of a held-out instance against
@@ -216,11 +249,13 @@ def test_learned_form_gain_over_plain(ctx):
     _, fl, lrn = _trajectory(ctx, test_inst, steps, predictor=pred, seed=3)
     used = sum(r["learned_used"] for r in lrn)
     fb = sum(r["learned_fallback"] for r in lrn)
+    afb = sum(r["apply_fallback"] for r in lrn)
     tp = float(np.median([r["wall"] for r in plain[1:]]))
     tl = float(np.median([r["wall"] for r in lrn[1:]]))
     diff = _rel_tt(ctx, fl, fp)
     print(f"plain {tp * 1e3:.1f} ms/step, learned {tl * 1e3:.1f} ms/step (gain {tp / tl:.2f}x); "
-          f"randomised roundings {used}, fallbacks {fb}; difference to plain after {steps} steps {diff:.2e}")
+          f"randomised roundings {used}, fallbacks {fb}, stage applications redone {afb}; "
+          f"difference to plain after {steps} steps {diff:.2e}")
     assert used >= 4 * (steps - 1) - 4  # the predictor kept the learned path on
     assert fb <= used // 4
     assert diff < 2e-5

@@ -36,6 +36,12 @@ def test_widths_rule():
     assert learned.widths_from_ranks([509], 2, 600) == [1, 512, 1]
 
 
+def test_apply_widths_rule():
+    assert learned.apply_widths([1, 10, 20, 1], 64, 80) == [1, 18, 28, 1]
+    assert learned.apply_widths([1, 10, 78, 1], 96, 80) == [1, 18, 80, 1]  # capped at the plain width
+    assert learned.apply_widths([1, 64, 20, 1], 64, 80) is None  # a derivative at the cap
+
+
 def test_samples_from_records_pairs_features_with_next_ranks():
     recs = []
     for s in range(3):
