@@ -261,19 +261,40 @@ def main_batched(args):
         c.set_profiling(True, shapes=True)
     batched(everyone)
     shapes = {}
+    classes = {}
     for c in ctxs:
-        autotune.gemm_shapes(c.dump_stats(), shapes)
+        st = c.dump_stats()
+        autotune.gemm_shapes(st, shapes)
+        for k, v in st.items():
+            if k in KERNEL_BOUND:
+                classes.setdefault(k, {"ms": 0.0})["ms"] += v["ms"]
         c.set_profiling(False)
         c.reset_stats()
+    # the roofline kernel: the class with the most time in that step; its
+    # launches (one in PROFILE_EVERY) are event-timed in the timed step
+    dom = dominant(classes) if classes else "zgemm"
     tuned = autotune.tune(ctxs[0], shapes, top=args.autotune_top)
     tune_s = time.perf_counter() - t0
     print(f"bench: autotuned {len(tuned)} GEMM shapes in {tune_s:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    for c in ctxs:
+        c.reset_stats()
+        c.set_profile_filter(dom)
+        c.set_profile_sampling(PROFILE_EVERY)
+        c.set_profiling(True)
     t0 = time.perf_counter()
     for s in range(args.steps):
         batched(everyone)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    kd = {"ms": 0.0, "flops": 0.0, "bytes": 0.0, "launches": 0}
+    for c in ctxs:
+        st = c.stats(dom)
+        for k in kd:
+            kd[k] += st[k]
+        c.set_profiling(False)
+        c.set_profile_filter(None)
+        c.set_profile_sampling(1)
     print("bench: batched steps done", file=sys.stderr, flush=True)
     # the same instances one after another, each alone on its context
     t0 = time.perf_counter()
@@ -306,7 +327,9 @@ def main_batched(args):
         "gemm_autotune": {"shapes_tuned": len(tuned), "seconds": tune_s},
         "sequential_reference": {"value": stages / ts, "unit": "instance-stages/s", "seconds": ts},
         "speedup_over_sequential": ts / tb,
-        "roofline": None,
+        # launches of the class from all instances overlap in time: the
+        # figure is per launch (summed durations), not the chip's aggregate
+        "roofline": roofline(dom, kd, with_traffic=False) if kd["launches"] else None,
     }
     print(json.dumps(result), flush=True)
 
@@ -365,12 +388,32 @@ def main_learned(args):
         return float(np.sqrt(max(aa + bb - 2 * ab, 0.0) / bb))
 
     held = instances(args.instances_learned, 77, (10, 14))
+    # the roofline kernel: the class with the most time in one profiled plain
+    # step of the first held-out instance; during the held-out trajectories
+    # (plain and learned alike) one launch in PROFILE_EVERY of it is
+    # event-timed, and the learned ones' launches make the roofline
+    op_p, f_p, _ = trajectory(held[0], 1)
+    ctx.reset_stats()
+    ctx.set_profiling(True)
+    tt.tt_step(ctx, op_p, f_p, dt, cap, eps, tt.TT_APPLY_SKETCH, ell, 1)
+    dom = dominant(ctx.dump_stats())
+    ctx.set_profiling(False)
+    f_p.close()
+    ctx.set_profile_filter(dom)
+    ctx.set_profile_sampling(PROFILE_EVERY)
+    kd = {"ms": 0.0, "flops": 0.0, "bytes": 0.0, "launches": 0}
     tp = tl = 0.0
     used = fb = afb = aused = 0
     diffs, rank_err = [], []
     for i, inst in enumerate(held):
+        ctx.set_profiling(True)
         _, fp, plain = trajectory(inst, args.steps + 1, seed=3)
+        ctx.reset_stats()
         _, fl, lrn = trajectory(inst, args.steps + 1, predictor=pred, seed=3)
+        st = ctx.stats(dom)
+        for k in kd:
+            kd[k] += st[k]
+        ctx.set_profiling(False)
         # the first step of either has no report to predict from: untimed
         tp += sum(r["wall"] for r in plain[1:])
         tl += sum(r["wall"] for r in lrn[1:])
@@ -417,7 +460,7 @@ def main_learned(args):
         "rel_diff_to_plain_after_steps": diffs,
         "predictor_mean_abs_rank_error": rank_err,
         "learned_tol": 1e-6,
-        "roofline": None,
+        "roofline": roofline(dom, kd, with_traffic=False) if kd["launches"] else None,
     }
     pred.close()
     print(json.dumps(result), flush=True)
