@@ -1991,7 +1991,12 @@ int tt_gemm_autotune(tt_ctx* ctx, int precision, int opA, int opB, int M, int N,
           zgemm_prec(precision, ctx, opA, opB, M, N, K, Z(1), bufs[0], lda, (long)M * K, bufs[1], ldb, (long)K * N,
                      Z(0), bufs[2], M, (long)M * N, batch);
         };
-        run();
+        try {
+          run();
+        } catch (const ttf::Error&) {  // a shape this candidate cannot launch (grid limits)
+          gemm_force(nullptr);
+          continue;
+        }
         double tmin = 1e300;
         for (int rep = 0; rep < 3; ++rep) {
           TTF_HIP(hipEventRecord(ev[0], ctx->stream));
@@ -2008,6 +2013,7 @@ int tt_gemm_autotune(tt_ctx* ctx, int precision, int opA, int opB, int M, int N,
           bestc = c;
         }
       }
+    require(best < 1e300, TT_EINVAL, "tt_gemm_autotune: no candidate could be launched");
     const int e[10] = {precision, opA, opB, M, N, K, batch, bestc.a, bestc.b, bestc.nsplit};
     gemm_table_put(e);
     if (choice) {
