@@ -323,10 +323,12 @@ class Context:
 
 class Tensor:
     def __init__(self, ctx, d, n, caps):
-        caps = np.ascontiguousarray(caps, dtype=np.int32)
-        if caps.size == 1 and d > 1:
-            c = int(caps.ravel()[0])
+        caps = np.ascontiguousarray(caps, dtype=np.int32).ravel()
+        if caps.size == 1 and d >= 1:
+            c = int(caps[0])
             caps = np.array([1] + [c] * (d - 1) + [1], dtype=np.int32)
+        if caps.size != d + 1:
+            raise ValueError(f"Tensor: need 1 or d+1 = {d + 1} rank capacities, got {caps.size}")
         self.ctx, self.d, self.n = ctx, d, n
         self.caps = caps
         h = P()
@@ -342,6 +344,15 @@ class Tensor:
         return ORTH[lib().tt_tensor_get_orth(self.h)]
 
     def set_cores(self, cores):
+        if len(cores) != self.d:
+            raise ValueError(f"set_cores: need {self.d} cores, got {len(cores)}")
+        for k, c in enumerate(cores):
+            c = np.asarray(c)
+            left = 1 if k == 0 else np.asarray(cores[k - 1]).shape[2]
+            if c.ndim != 3 or c.shape[0] != left or c.shape[1] != self.n:
+                raise ValueError(f"set_cores: core {k} has shape {c.shape}, expected ({left}, {self.n}, r)")
+        if np.asarray(cores[-1]).shape[2] != 1:
+            raise ValueError("set_cores: the last core must have right rank 1")
         ranks = np.array([1] + [c.shape[2] for c in cores], dtype=np.int32)
         bufs = [np.ascontiguousarray(np.asarray(c, dtype=np.complex128).ravel(order="F")) for c in cores]
         ptrs = (P * self.d)(*[b.ctypes.data for b in bufs])
@@ -355,8 +366,10 @@ class Tensor:
         return [b.reshape((r[k], self.n, r[k + 1]), order="F") for k, b in enumerate(bufs)]
 
     def set_gaussian(self, mu, sigma, length):
-        mu = np.ascontiguousarray(mu, dtype=np.float64)
-        sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+        mu = np.ascontiguousarray(mu, dtype=np.float64).ravel()
+        sigma = np.ascontiguousarray(sigma, dtype=np.float64).ravel()
+        if mu.size < self.d or sigma.size < self.d:
+            raise ValueError(f"set_gaussian: need {self.d} means and widths")
         self.ctx.check(lib().tt_tensor_set_gaussian(self.ctx.h, self.h, _dp(mu), _dp(sigma), float(length)))
 
     def set_cdf_gaussian(self, sigma, box):
@@ -504,6 +517,8 @@ def tt_step_batch(ctxs, ops, fs, dts, rmaxs, epss, mode=TT_APPLY_EXACT, sketch_r
     """Independent instances stepped concurrently (one host thread and
     stream per distinct context).  Returns the per-instance status codes."""
     n = len(fs)
+    if not (len(ctxs) == len(ops) == len(dts) == len(rmaxs) == len(epss) == n):
+        raise ValueError("tt_step_batch: one context, operator, dt, rmax and eps per instance")
     sketch_ranks = sketch_ranks if sketch_ranks is not None else [0] * n
     seeds = seeds if seeds is not None else [0] * n
     opts = (StepOpts * n)(*[StepOpts(ctypes.sizeof(StepOpts), int(rmaxs[i]), float(epss[i]), int(mode),
@@ -522,6 +537,12 @@ def tt_eval(ctx, x, idx, out):
     (which reads out)."""
     import torch
 
+    if idx.dim() != 2 or idx.shape[1] != x.d or idx.dtype != torch.int32 or not idx.is_contiguous():
+        raise ValueError(f"tt_eval: idx must be a contiguous int32 (npts, {x.d}) tensor")
+    if out.dtype != torch.complex128 or not out.is_contiguous() or out.numel() < idx.shape[0]:
+        raise ValueError("tt_eval: out must be a contiguous complex128 tensor of npts entries")
+    if idx.shape[0] and (not idx.is_cuda or not out.is_cuda):
+        raise ValueError("tt_eval: idx and out must be device tensors")
     cur = torch.cuda.current_stream()
     if ctx.torch_stream is not None:
         ctx.torch_stream.wait_stream(cur)
@@ -538,6 +559,17 @@ def tt_zgemm(ctx, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc
     (tt_zgemm_mixed)."""
     import torch
 
+    def need(t, rows, cols, ld, stride, name):
+        # elements the column-major operand spans: the last batch's last column
+        if rows == 0 or cols == 0:
+            return
+        span = (batch - 1) * stride + (cols - 1) * ld + rows
+        if t.dtype != torch.complex128 or not t.is_cuda or t.numel() < span:
+            raise ValueError(f"tt_zgemm: {name} must be a device complex128 buffer of at least {span} elements")
+
+    need(A, M if opA == 0 else K, K if opA == 0 else M, lda, sA, "A")
+    need(B, K if opB == 0 else N, N if opB == 0 else K, ldb, sB, "B")
+    need(C, M, N, ldc, sC, "C")
     cur = torch.cuda.current_stream()
     if ctx.torch_stream is not None:
         ctx.torch_stream.wait_stream(cur)
@@ -575,7 +607,9 @@ def tt_solve_shifted(ctx, op, c, b, x, tol, max_iter=30, krylov_eps=None, krylov
 def tt_round_randomized(ctx, x, widths, seed, y):
     """Randomised rounding of x into y with per-bond sketch widths (d+1
     ints); returns the relative error ||x - y|| / ||x||."""
-    w = np.ascontiguousarray(widths, dtype=np.int32)
+    w = np.ascontiguousarray(widths, dtype=np.int32).ravel()
+    if w.size != x.d + 1:
+        raise ValueError(f"tt_round_randomized: need d+1 = {x.d + 1} widths")
     e = D()
     ctx.check(lib().tt_round_randomized(ctx.h, x.h, _ip(w), int(seed), y.h, ctypes.byref(e)))
     return e.value

@@ -110,3 +110,10 @@ def test_viscous_only_operator():
     ref = prob.apply(f).ravel()
     assert np.linalg.norm(dense @ f.ravel() - ref) <= 1e-12 * np.linalg.norm(ref)
     op.close()
+
+
+def test_tensor_capacities_are_checked_before_the_call():
+    # one capacity is spread over the interior bonds (d = 1 has none); any
+    # other count is rejected on the host
+    with pytest.raises(ValueError):
+        tt.Tensor(None, 3, 8, [1, 4, 1])
