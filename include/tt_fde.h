@@ -201,7 +201,10 @@ int tt_op_create_burgers_hopf_ex(tt_ctx* ctx, int d, int n, double L, double nu,
  * trapezoid rule for J.  Real coefficients; tensors stay complex (imaginary
  * parts zero).  TT-matrix form over the local operators of
  * tt_op_export_local_ops; bond dimension at most 10.  ctx may be NULL
- * (host-only operator). */
+ * (host-only operator).  *out is owned by the caller (tt_op_destroy).
+ * TT_EINVAL for d outside 1..128, n < 4, a size mismatch of opts, box <= 0,
+ * gamma < 0 or diffusion < 0, or when no term remains (d = 1 with gamma,
+ * alpha and diffusion all zero). */
 typedef struct {
   int size;              /* sizeof(tt_cdf_opts) */
   int pad;
@@ -211,9 +214,11 @@ typedef struct {
   double diffusion;      /* kappa >= 0: kappa sum_k d2F/du_k^2 (numerical diffusion) */
 } tt_cdf_opts;
 int tt_op_create_cdf_burgers(tt_ctx* ctx, int d, int n, const tt_cdf_opts* opts, tt_op** out);
-/* The CDF equation's initial condition: the product of zero-mean Gaussian
- * CDFs 0.5 (1 + erf(u_k / (sigma sqrt 2))) on the grid of [-box, box]
- * (rank one; needs interior capacity >= 1). */
+/* The CDF equation's initial condition (Sec. 5, the paper's product of
+ * zero-mean Gaussian CDFs): 0.5 (1 + erf(u_k / (sigma sqrt 2))) on the grid
+ * u_i = -box + 2 box i / (n-1) of every axis; t becomes rank one (any
+ * capacity suffices).  Asynchronous on the context's stream; TT_EINVAL for
+ * box <= 0 or sigma <= 0. */
 int tt_tensor_set_cdf_gaussian(tt_ctx* ctx, tt_tensor* t, double sigma, double box);
 int tt_op_destroy(tt_op* op);
 /* Bond dimensions R[0..d] of the operator's TT-matrix form. */
