@@ -89,6 +89,9 @@ struct tt_ctx {
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> free_events;
+  // sweeps the last Jacobi SVD of each size (m, k) needed: the next one of
+  // that size launches as many before its first convergence check
+  std::map<std::pair<int, int>, int> jacobi_sweeps_seen;
 
   void* get_ws(const std::string& name, size_t bytes);
   void* host_scratch(size_t bytes);

@@ -400,9 +400,17 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
     launch(0, 2, 0, JAC_MAX_SWEEPS, 0, rot, tol);
     nsweeps = JAC_MAX_SWEEPS;
   } else {
+    // sweeps are launched in batches between host checks of the rotation
+    // counts; a sweep launched after the one without rotations returns at
+    // once but still costs its launches, so the first batch is as long as
+    // the last SVD of this size needed (6 for a new size), the later ones
+    // short.  The launched count does not change the result.
     int* h = (int*)ctx->host_scratch(sizeof(int) * JB_MAXS);
-    int batch = 6;
+    auto seen = ctx->jacobi_sweeps_seen.find({m, k});
+    const bool known = seen != ctx->jacobi_sweeps_seen.end();
+    int batch = known ? std::max(2, seen->second) : 6;
     bool done = false;
+    int converged = 0;
     while (!done && nsweeps < JAC_MAX_SWEEPS) {
       for (int b = 0; b < batch && nsweeps < JAC_MAX_SWEEPS; ++b, ++nsweeps) {
         launch(1, P, 0, 1, nsweeps, rot, tol);
@@ -410,10 +418,14 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
       }
       TTF_HIP(hipMemcpyAsync(h, rot, sizeof(int) * nsweeps, hipMemcpyDeviceToHost, ctx->stream));
       TTF_HIP(hipStreamSynchronize(ctx->stream));
-      for (int s = 0; s < nsweeps; ++s)
-        if (h[s] == 0) done = true;
-      batch = 2;
+      for (int s = 0; s < nsweeps && !done; ++s)
+        if (h[s] == 0) {
+          done = true;
+          converged = s + 1;
+        }
+      batch = known ? 1 : 2;
     }
+    if (done) ctx->jacobi_sweeps_seen[{m, k}] = converged;
   }
   hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(1024), 0, ctx->stream, m, k, B, U, sigma, rot, nsweeps,
                      sweeps);
