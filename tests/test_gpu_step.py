@@ -121,8 +121,16 @@ def test_viscous_only_matches_exponential(ctx, d, n, length, nu, dt, steps):
     assert err < 1e-10, err
 
 
-@pytest.mark.parametrize("rank,ell", [(1, 128), (2, 256)])
-def test_sketched_apply_at_benchmark_shape_matches_pointwise_oracle(ctx, rank, ell):
+@pytest.mark.parametrize("rank,ell,prec,tol", [(1, 128, tt.TT_PREC_FP64, 1e-10), (2, 256, tt.TT_PREC_FP64, 1e-10),
+                                               (1, 128, tt.TT_PREC_FP16X3, 3e-5), (2, 256, tt.TT_PREC_FP16X3, 3e-5),
+                                               (1, 128, tt.TT_PREC_FP32, 3e-5)])
+def test_sketched_apply_at_benchmark_shape_matches_pointwise_oracle(ctx, rank, ell, prec, tol):
+    """The benchmark's operator (d=50, n=128) applied by the sketch in the
+    plain, mixed and FP32 forms to inputs whose product the sketch width
+    covers, against the oracle's operator evaluated point by point (the
+    worst sampled point relative to the largest sampled |L x|: for the
+    16-bit products about 1.5e-5, against their 1e-5 relative-L2 gate on
+    whole stages)."""
     import torch
 
     d, n, length, nu = 50, 128, 8.0, 0.01
@@ -130,13 +138,15 @@ def test_sketched_apply_at_benchmark_shape_matches_pointwise_oracle(ctx, rank, e
     x = inputs.random_tt(d, n, rank, 20 + rank)
     tx = upload(ctx, x)
     ty = tt.Tensor(ctx, d, n, ell)
-    tt.tt_apply(ctx, op, tx, ty, tt.TT_APPLY_SKETCH, sketch_rank=ell, seed=9)
+    tt.tt_apply(ctx, op, tx, ty, tt.TT_APPLY_SKETCH, sketch_rank=ell, seed=9, precision=prec)
     idx = inputs.random_points(d, n, 12, 21)
     out = torch.zeros(12, dtype=torch.complex128, device="cuda")
     tt.tt_eval(ctx, ty, torch.from_numpy(idx).cuda(), out)
     ref = tt_ref.operator_at_points(x, idx, galerkin.coefficient_B(d), galerkin.coefficient_D(d), nu, n, length)
     scale = np.abs(ref).max()
-    assert np.abs(out.cpu().numpy() - ref).max() < 1e-10 * scale
+    err = np.abs(out.cpu().numpy() - ref).max() / scale
+    print(f"precision {prec}, rank {rank}: max pointwise error {err:.2e} of max |L x|")
+    assert err < tol
     op.close()
 
 
