@@ -85,3 +85,45 @@ def test_batch_instance_matches_oracle_and_errors_stay_local():
         op.close()
     for c in ctxs:
         c.close()
+
+
+def test_batch_mixes_operators_and_precisions():
+    """Characteristic-function and CDF-equation instances in one batch, in
+    FP64, FP32 and split-FP16x3 (one precision per call: three calls over
+    the same contexts), each bit-identical to its own stepping alone."""
+    ctxs = [make_ctx() for _ in range(2)]
+    alone = make_ctx()
+    specs = [("bh", 4, 16, 8), ("cdf", 3, 24, 10), ("bh", 5, 16, 6), ("cdf", 4, 16, 8)]
+
+    def build(ctx, kind, d, n, cap, seed):
+        if kind == "bh":
+            op = tt.Operator(ctx, d, n, L, 0.03)
+            f = tt.Tensor(ctx, d, n, cap)
+            mu, sig = inputs.ic_params(d, seed)
+            f.set_gaussian(mu, sig, L)
+        else:
+            op = tt.CdfOperator(ctx, d, n, 1.3, 0.05, 1.0)
+            f = tt.Tensor(ctx, d, n, cap)
+            f.set_cdf_gaussian(0.25, 1.3)
+        return op, f
+
+    for prec in (tt.TT_PREC_FP64, tt.TT_PREC_FP32, tt.TT_PREC_FP16X3):
+        batch = [build(ctxs[i % 2], *s, i) for i, s in enumerate(specs)]
+        seq = [build(alone, *s, i) for i, s in enumerate(specs)]
+        caps = [s[3] for s in specs]
+        for step in range(2):
+            status = tt.tt_step_batch([ctxs[i % 2] for i in range(len(specs))], [b[0] for b in batch],
+                                      [b[1] for b in batch], [1e-3] * len(specs), caps, [1e-10] * len(specs),
+                                      tt.TT_APPLY_SKETCH, [3 * c for c in caps], [7 + step] * len(specs),
+                                      precision=prec)
+            assert status == [0] * len(specs), status
+            for (op, f), c in zip(seq, caps):
+                tt.tt_step(alone, op, f, 1e-3, c, 1e-10, tt.TT_APPLY_SKETCH, 3 * c, 7 + step, precision=prec)
+        for (ob, fb), (os_, fs) in zip(batch, seq):
+            assert fb.ranks() == fs.ranks()
+            assert all(np.array_equal(x, y) for x, y in zip(fb.get_cores(), fs.get_cores()))
+        for op, f in batch + seq:
+            f.close()
+            op.close()
+    for c in ctxs + [alone]:
+        c.close()
