@@ -177,14 +177,13 @@ __global__ __launch_bounds__(GS * W) void jacobi_circle_kernel(zc* __restrict__ 
                                                                const double* __restrict__ fro2) {
   extern __shared__ double2 xch[];  // W slots of GS XC rows
   __shared__ int wg_rot;
-  if (sweep > 0 && rot[sweep - 1] == 0) return;
-  const double abs2 = 1e-30 * fro2[0];  // (1e-15 |B|_F)^2
   constexpr int NP = 2 * W - 1;
   constexpr int XC = RPL < JB_XCHUNK ? RPL : JB_XCHUNK;  // rows per lane per exchange
   constexpr int LD = GS * XC;
   const int c0 = blockIdx.x * 2 * W;
   const int w = threadIdx.x / GS, lane = threadIdx.x % GS;
   zc xt[RPL], xb[RPL];
+  // columns requested before the convergence flag is read (overlapping loads)
   {
     const int ct = c0 + w, cb = c0 + 2 * W - 1 - w;
 #pragma unroll
@@ -194,6 +193,9 @@ __global__ __launch_bounds__(GS * W) void jacobi_circle_kernel(zc* __restrict__ 
       xb[j] = (cb < k && row < m) ? B[row + (long)m * cb] : make_double2(0.0, 0.0);
     }
   }
+  const double f2 = fro2[0];
+  if (sweep > 0 && rot[sweep - 1] == 0) return;
+  const double abs2 = 1e-30 * f2;  // (1e-15 |B|_F)^2
   zc* mine = xch + (long)LD * w;
   for (int it = 0; it < inner_max; ++it) {
     int nrot = 0;
@@ -252,6 +254,13 @@ __global__ __launch_bounds__(GS * W) void jacobi_circle_kernel(zc* __restrict__ 
   }
 }
 
+// rows per lane per exchange of the cross kernel: its two sets of slots
+// stay within 64 KB of LDS
+constexpr int cross_chunk(int rpl, int gs) {
+  const int c = gs == 64 ? JB_XCHUNK / 2 : JB_XCHUNK;
+  return rpl < c ? rpl : c;
+}
+
 // All BC x BC column pairs between blocks a and b (BC columns each; the
 // pair of workgroup g in round `round` of a round-robin over P blocks):
 // group w keeps column BC a + w and meets column BC b + (w + s) mod BC in
@@ -260,17 +269,17 @@ template <int RPL, int GS, int BC>
 __global__ __launch_bounds__(BC * GS) void jacobi_cross_kernel(zc* __restrict__ B, int m, int k, int P, int round,
                                                                int sweep, int* __restrict__ rot, double tol,
                                                                const double* __restrict__ fro2) {
-  extern __shared__ double2 xch[];  // BC slots of GS XC rows
+  extern __shared__ double2 xch[];  // two sets of BC slots of GS XC rows
   __shared__ int wg_rot;
-  if (sweep > 0 && rot[sweep - 1] == 0) return;
-  const double abs2 = 1e-30 * fro2[0];  // (1e-15 |B|_F)^2
-  constexpr int XC = RPL < JB_XCHUNK ? RPL : JB_XCHUNK;  // rows per lane per exchange
+  constexpr int XC = cross_chunk(RPL, GS);  // rows per lane per exchange
   constexpr int LD = GS * XC;
   int ba, bb;
   rr_pair(P, round, blockIdx.x, ba, bb);
   const int w = threadIdx.x / GS, lane = threadIdx.x % GS;
   const int ca = ba * BC + w;
   zc xa[RPL], xb[RPL];
+  // the columns are requested before the convergence flag is read, so the
+  // two memory latencies overlap
   {
     const int cb = bb * BC + w;
 #pragma unroll
@@ -280,23 +289,30 @@ __global__ __launch_bounds__(BC * GS) void jacobi_cross_kernel(zc* __restrict__ 
       xb[j] = (cb < k && row < m) ? B[row + (long)m * cb] : make_double2(0.0, 0.0);
     }
   }
+  const double f2 = fro2[0];
+  if (sweep > 0 && rot[sweep - 1] == 0) return;
+  const double abs2 = 1e-30 * f2;  // (1e-15 |B|_F)^2
+  // two sets of exchange slots used alternately: a slot is written again
+  // only two exchanges later, after a barrier that follows every read of
+  // it, so one barrier per exchange suffices
   zc* mine = xch + (long)LD * w;
   const zc* next = xch + (long)LD * ((w + 1) % BC);
-  int nrot = 0;
+  int nrot = 0, set = 0;
   for (int st = 0; st < BC; ++st) {
     const int cb = bb * BC + (w + st) % BC;
     if (ca < k && cb < k) nrot += jacobi_rotate<RPL, GS>(xa, xb, tol, abs2);
     if (st == BC - 1) break;
 #pragma unroll
     for (int c = 0; c < RPL; c += XC) {
+      const long off = set ? (long)LD * BC : 0;
+      set ^= 1;
+#pragma unroll
+      for (int j = 0; j < XC; ++j)
+        if (c + j < RPL) mine[off + lane + GS * j] = xb[c + j];
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < XC; ++j)
-        if (c + j < RPL) mine[lane + GS * j] = xb[c + j];
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < XC; ++j)
-        if (c + j < RPL) xb[c + j] = next[lane + GS * j];
+        if (c + j < RPL) xb[c + j] = next[off + lane + GS * j];
     }
   }
   jacobi_count(nrot, &wg_rot, rot, sweep);
@@ -389,7 +405,8 @@ void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int ro
     TTF_LAUNCH(kt, (jacobi_circle_kernel<RPL, JB_COLS / 2, GS>), dim3((k + JB_COLS - 1) / JB_COLS),
                dim3(JB_COLS / 2 * GS), JB_COLS / 2 * slot, ctx->stream, B, m, k, 1, sweep, rot, tol, fro2);
   else
-    TTF_LAUNCH(kt, (jacobi_cross_kernel<RPL, GS, JB_COLS>), dim3(P / 2), dim3(JB_COLS * GS), JB_COLS * slot,
+    TTF_LAUNCH(kt, (jacobi_cross_kernel<RPL, GS, JB_COLS>), dim3(P / 2), dim3(JB_COLS * GS),
+               2 * JB_COLS * sizeof(zc) * GS * cross_chunk(RPL, GS),
                ctx->stream, B, m, k, P, round, sweep, rot, tol, fro2);
   TTF_HIP(hipGetLastError());
 }
