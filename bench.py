@@ -715,6 +715,12 @@ def main():
         autotune.save(args.autotune_save)
     roof = roofline(dom, kd)
     kernels_ms = {k: round(v["ms"], 3) for k, v in (breakdown or {}).items() if k != "qr_fallbacks"}
+    # per kernel class of the profiled warm-up step: launches and the
+    # algorithmic rates over its event-timed duration (profiling included)
+    kernel_rates = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                        "tflops": round(v["flops"] / (v["ms"] * 1e9), 3) if v["ms"] > 0 and v["flops"] > 0 else None,
+                        "gbps": round(v["bytes"] / (v["ms"] * 1e6), 1) if v["ms"] > 0 and v["bytes"] > 0 else None}
+                    for k, v in (breakdown or {}).items() if k != "qr_fallbacks"}
     result = {
         "metric": "RK stages/sec at d=50,n=128,r<=64 vs plain FP64 at rel-L2 err <=1e-5",
         "value": value,
@@ -743,6 +749,7 @@ def main():
         "fp64_reference": fp64_ref,
         "error_vs_fp64": errors,
         "kernels_ms_profiled_warmup_step": kernels_ms,
+        "kernel_rates_profiled_warmup_step": kernel_rates,
         "qr_fallbacks": int((breakdown or {}).get("qr_fallbacks", {"launches": 0})["launches"]),
         "wall_s": wall,
         "gemm_autotune": tuned,

@@ -16,6 +16,7 @@
 
 #include "common.hpp"
 #include "dpp.hpp"
+#include "recip.hpp"
 
 namespace ttf {
 
@@ -83,27 +84,6 @@ __device__ inline double group_sum(double x) {
   return x;
 }
 
-// 1 / sqrt(a) for a normal a > 0: the hardware estimate refined by two
-// Newton steps y <- y + y (1/2 - a y^2 / 2) (each squares the relative error)
-__device__ inline double rsqrt_newton(double a) {
-  double y = __builtin_amdgcn_rsq(a);
-  const double h = 0.5 * a;
-  double r = fma(-h * y, y, 0.5);
-  y = fma(y, r, y);
-  r = fma(-h * y, y, 0.5);
-  return fma(y, r, y);
-}
-
-// 1 / a for a normal a: the hardware estimate and two Newton steps
-// y <- y + y (1 - a y)
-__device__ inline double rcp_newton(double a) {
-  double y = __builtin_amdgcn_rcp(a);
-  double e = fma(-a, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-a, y, 1.0);
-  return fma(y, e, y);
-}
-
 // Rotate the column pair (x, y) so that x^H y = 0 unless they already are
 // to the tolerance; returns 1 when a rotation was applied.
 template <int RPL, int GS>
@@ -125,7 +105,7 @@ __device__ inline int jacobi_rotate(zc (&x)[RPL], zc (&y)[RPL], double tol, doub
   // pairs with a negligible column (squared norm below abs2) are left alone
   if (!(g2 > tol * tol * al * be) || g2 == 0.0 || al < abs2 || be < abs2) return 0;
   double ig, tt, cs;
-  if (g2 >= 0x1p-900) {
+  if (g2 >= 0x1p-900 && g2 <= 0x1p900) {
     // one dependent chain of reciprocal square roots and one reciprocal
     ig = rsqrt_newton(g2);  // 1 / |g|
     const double zeta = (be - al) * (0.5 * ig);
@@ -133,7 +113,7 @@ __device__ inline int jacobi_rotate(zc (&x)[RPL], zc (&y)[RPL], double tol, doub
     const double t = rcp_newton(fabs(zeta) + q * rsqrt_newton(q));
     tt = zeta >= 0 ? t : -t;
     cs = rsqrt_newton(fma(tt, tt, 1.0));
-  } else {  // |g| this small only for a matrix of Frobenius norm below 1e-45
+  } else {  // |g| outside [2^-450, 2^450]: Frobenius norm below 1e-45 or above 3e67
     ig = 1.0 / sqrt(g2);
     const double zeta = (be - al) * (0.5 * ig);
     tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
