@@ -95,6 +95,10 @@ KERNEL_BOUND = {
 }
 
 
+# event counters of the library's statistics (no timing)
+COUNTERS = {"qr_fallbacks", "jacobi_svds", "jacobi_sweeps_launched", "jacobi_sweeps_needed", "jacobi_check_passed"}
+
+
 def dominant(stats):
     """The single-kernel class with the most time in a profiled step."""
     cand = {k: v["ms"] for k, v in stats.items() if k in KERNEL_BOUND}
@@ -550,7 +554,7 @@ def main_cdf(args):
                           "ranks": "above 100", "speedup_of_this_run": paper_sec / sec},
         "roofline": roofline(dom, kd, with_traffic=False),
         "kernels_ms_profiled_warmup_step": {k: round(v["ms"], 3) for k, v in (breakdown or {}).items()
-                                            if k != "qr_fallbacks"},
+                                            if k not in COUNTERS},
     }
     print(json.dumps(result), flush=True)
 
@@ -714,13 +718,13 @@ def main():
 
         autotune.save(args.autotune_save)
     roof = roofline(dom, kd)
-    kernels_ms = {k: round(v["ms"], 3) for k, v in (breakdown or {}).items() if k != "qr_fallbacks"}
+    kernels_ms = {k: round(v["ms"], 3) for k, v in (breakdown or {}).items() if k not in COUNTERS}
     # per kernel class of the profiled warm-up step: launches and the
     # algorithmic rates over its event-timed duration (profiling included)
     kernel_rates = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                         "tflops": round(v["flops"] / (v["ms"] * 1e9), 3) if v["ms"] > 0 and v["flops"] > 0 else None,
                         "gbps": round(v["bytes"] / (v["ms"] * 1e6), 1) if v["ms"] > 0 and v["bytes"] > 0 else None}
-                    for k, v in (breakdown or {}).items() if k != "qr_fallbacks"}
+                    for k, v in (breakdown or {}).items() if k not in COUNTERS}
     result = {
         "metric": "RK stages/sec at d=50,n=128,r<=64 vs plain FP64 at rel-L2 err <=1e-5",
         "value": value,
@@ -751,6 +755,8 @@ def main():
         "kernels_ms_profiled_warmup_step": kernels_ms,
         "kernel_rates_profiled_warmup_step": kernel_rates,
         "qr_fallbacks": int((breakdown or {}).get("qr_fallbacks", {"launches": 0})["launches"]),
+        "jacobi_profiled_warmup_step": {k: int((breakdown or {}).get(k, {"launches": 0})["launches"])
+                                        for k in sorted(COUNTERS) if k.startswith("jacobi_")},
         "wall_s": wall,
         "gemm_autotune": tuned,
         "final_ranks_max": final_ranks_max,

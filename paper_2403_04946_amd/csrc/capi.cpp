@@ -941,6 +941,7 @@ int tt_ctx_reset_stats(tt_ctx* ctx) {
   ctx->sync();
   ctx->stats.clear();
   ctx->qr_fallbacks = 0;
+  ctx->jacobi_svds = ctx->jacobi_sweeps_launched = ctx->jacobi_sweeps_needed = ctx->jacobi_check_passed = 0;
   return TT_OK;
   ABI_CATCH(ctx)
 }
@@ -969,6 +970,14 @@ int tt_ctx_dump_stats(tt_ctx* ctx, char* buf, long cap) {
   char line[512];
   std::snprintf(line, sizeof(line), "qr_fallbacks %lld 0 0 0\n", ctx->qr_fallbacks);
   out += line;
+  const std::pair<const char*, long long> counters[] = {{"jacobi_svds", ctx->jacobi_svds},
+                                                        {"jacobi_sweeps_launched", ctx->jacobi_sweeps_launched},
+                                                        {"jacobi_sweeps_needed", ctx->jacobi_sweeps_needed},
+                                                        {"jacobi_check_passed", ctx->jacobi_check_passed}};
+  for (const auto& c : counters) {
+    std::snprintf(line, sizeof(line), "%s %lld 0 0 0\n", c.first, c.second);
+    out += line;
+  }
   for (const auto& kv : ctx->stats) {
     std::snprintf(line, sizeof(line), "%s %lld %.6f %.6g %.6g\n", kv.first.c_str(), kv.second.n, kv.second.ms,
                   kv.second.flops, kv.second.bytes);

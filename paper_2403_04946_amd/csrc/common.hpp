@@ -74,6 +74,9 @@ struct tt_ctx {
   bool profiling = false;
   bool profile_shapes = false;  // also key GEMM timings by shape
   long long qr_fallbacks = 0;   // QRs redone in the robust form
+  // blocked Jacobi SVDs: count, sweeps launched, sweeps up to convergence,
+  // and how many ended on the all-pairs rotation test
+  long long jacobi_svds = 0, jacobi_sweeps_launched = 0, jacobi_sweeps_needed = 0, jacobi_check_passed = 0;
   std::string profile_only;     // when set, only this kernel class is timed
   int profile_every = 1;        // time one in this many launches of it
   long long profile_seen = 0;

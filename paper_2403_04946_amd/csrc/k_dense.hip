@@ -86,9 +86,14 @@ __device__ inline double group_sum(double x) {
 
 // Rotate the column pair (x, y) so that x^H y = 0 unless they already are
 // to the tolerance; returns 1 when a rotation was applied.
+// Squared norms al, be of the columns x, y of a pair and g = x^H y (gr +
+// i gi), summed over the GS lanes of the group: each lane adds its RPL rows
+// in order, then the lane sums are combined in a fixed tree, so every
+// kernel that calls this sees the same bits for the same columns.
 template <int RPL, int GS>
-__device__ inline int jacobi_rotate(zc (&x)[RPL], zc (&y)[RPL], double tol, double abs2) {
-  double al = 0, be = 0, gr = 0, gi = 0;
+__device__ inline void jacobi_pair_sums(const zc (&x)[RPL], const zc (&y)[RPL], double& al, double& be, double& gr,
+                                        double& gi) {
+  al = 0, be = 0, gr = 0, gi = 0;
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
     const zc a = x[j], c = y[j];
@@ -101,9 +106,21 @@ __device__ inline int jacobi_rotate(zc (&x)[RPL], zc (&y)[RPL], double tol, doub
   be = group_sum<GS>(be);
   gr = group_sum<GS>(gr);
   gi = group_sum<GS>(gi);
+}
+
+// The rotation test: |g| above tol times the geometric mean of the column
+// norms; pairs with a negligible column (squared norm below abs2) are left
+// alone.
+__device__ inline bool jacobi_needs_rotation(double al, double be, double g2, double tol, double abs2) {
+  return g2 > tol * tol * al * be && g2 != 0.0 && al >= abs2 && be >= abs2;
+}
+
+template <int RPL, int GS>
+__device__ inline int jacobi_rotate(zc (&x)[RPL], zc (&y)[RPL], double tol, double abs2) {
+  double al, be, gr, gi;
+  jacobi_pair_sums<RPL, GS>(x, y, al, be, gr, gi);
   const double g2 = gr * gr + gi * gi;
-  // pairs with a negligible column (squared norm below abs2) are left alone
-  if (!(g2 > tol * tol * al * be) || g2 == 0.0 || al < abs2 || be < abs2) return 0;
+  if (!jacobi_needs_rotation(al, be, g2, tol, abs2)) return 0;
   double ig, tt, cs;
   if (g2 >= 0x1p-900 && g2 <= 0x1p900) {
     // one dependent chain of reciprocal square roots and one reciprocal
@@ -355,6 +372,63 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(int m, int k, const
   }
 }
 
+// Convergence test over every column pair at once: workgroup t takes the
+// t-th pair of blocks (a <= b) in the order (0,0), (0,1), (1,1), (0,2), ...
+// and meets the pairs between them in the layout of the cross kernel
+// (within one block, each unordered pair once), applying the rotation
+// test to the same sums a sweep would compute, without rotating.  A pair
+// that would be rotated raises *failed to `label` (atomic maximum, so the
+// host reads whether the test labelled `label` failed without clearing).
+template <int RPL, int GS, int BC>
+__global__ __launch_bounds__(BC * GS) void jacobi_check_kernel(const zc* __restrict__ B, int m, int k, double tol,
+                                                               const double* __restrict__ fro2,
+                                                               int* __restrict__ failed, int label) {
+  extern __shared__ double2 xch[];  // two sets of BC slots of GS XC rows
+  constexpr int XC = cross_chunk(RPL, GS);
+  constexpr int LD = GS * XC;
+  int bb = 0, t = blockIdx.x;
+  while (t > bb) t -= ++bb;  // t-th pair: block bb, block ba = t <= bb
+  const int ba = t;
+  const int w = threadIdx.x / GS, lane = threadIdx.x % GS;
+  const int ca = ba * BC + w;
+  zc xa[RPL], xb[RPL];
+  {
+    const int cb = bb * BC + w;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      const int row = lane + GS * j;
+      xa[j] = (ca < k && row < m) ? B[row + (long)m * ca] : make_double2(0.0, 0.0);
+      xb[j] = (cb < k && row < m) ? B[row + (long)m * cb] : make_double2(0.0, 0.0);
+    }
+  }
+  const double abs2 = 1e-30 * fro2[0];
+  zc* mine = xch + (long)LD * w;
+  const zc* next = xch + (long)LD * ((w + 1) % BC);
+  int bad = 0, set = 0;
+  for (int st = 0; st < BC; ++st) {
+    const int cb = bb * BC + (w + st) % BC;
+    if (ca < k && cb < k && (ba != bb || ca < cb)) {
+      double al, be, gr, gi;
+      jacobi_pair_sums<RPL, GS>(xa, xb, al, be, gr, gi);
+      bad |= jacobi_needs_rotation(al, be, gr * gr + gi * gi, tol, abs2) ? 1 : 0;
+    }
+    if (st == BC - 1) break;
+#pragma unroll
+    for (int c = 0; c < RPL; c += XC) {
+      const long off = set ? (long)LD * BC : 0;
+      set ^= 1;
+#pragma unroll
+      for (int j = 0; j < XC; ++j)
+        if (c + j < RPL) mine[off + lane + GS * j] = xb[c + j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < XC; ++j)
+        if (c + j < RPL) xb[c + j] = next[off + lane + GS * j];
+    }
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicMax(failed, label);
+}
+
 template <int RPL, int GS>
 void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int round, int inner_max, int sweep,
                        int* rot, double tol, const double* fro2) {
@@ -373,6 +447,15 @@ void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int ro
   } else {
     pairs = (double)JB_COLS * JB_COLS * (P / 2);
     cols = 2.0 * JB_COLS * (P / 2);
+  }
+  if (kind == 3) {  // the all-pairs convergence test (P = number of blocks, inner_max = label)
+    const int nb = P;
+    KTimer kc(ctx, "jacobi_check", 16.0 * m * 0.5 * k * (k - 1.0), 16.0 * m * k * (nb + 1.0), true);
+    TTF_LAUNCH(kc, (jacobi_check_kernel<RPL, GS, JB_COLS>), dim3(nb * (nb + 1) / 2), dim3(JB_COLS * GS),
+               2 * JB_COLS * sizeof(zc) * GS * cross_chunk(RPL, GS), ctx->stream, B, m, k, tol, fro2, rot + JB_MAXS,
+               inner_max);
+    TTF_HIP(hipGetLastError());
+    return;
   }
   KTimer kt(ctx, kind == 2 ? "jacobi_cross" : "jacobi_circle", pair * pairs, 2.0 * 16.0 * m * cols, true);
   if (kind == 0) {  // whole matrix (k <= 32, at most 320 rows) in one workgroup
@@ -395,8 +478,10 @@ void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int ro
 // inside a block) followed by the P - 1 rounds of a round-robin over the
 // blocks (all pairs between two blocks), so each column pair meets once.
 void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
+  // rot[0 .. JB_MAXS): rotations per sweep; rot[JB_MAXS]: the last
+  // orthogonality check that failed; then |B|_F^2 (8-byte aligned)
   int* rot = (int*)ctx->get_ws("jac_rot", sizeof(int) * JB_MAXS + 64);
-  double* fro2 = (double*)(rot + JB_MAXS);
+  double* fro2 = (double*)(rot + JB_MAXS + 2);
   frob_norm2(ctx, B, (long)m * k, fro2);
   // a 32-lane group per column pair up to 320 rows (at most 10 rows per
   // lane), a whole wavefront beyond (up to 16 rows per lane)
@@ -422,39 +507,55 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
   const double tol = 1e-15 * sqrt((double)m);
   const int nblk = (k + JB_COLS - 1) / JB_COLS;
   const int P = nblk + (nblk & 1);
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, ctx->stream, rot, JB_MAXS);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, ctx->stream, rot, JB_MAXS + 1);
   TTF_HIP(hipGetLastError());
   int nsweeps = 0;
   if (k <= 32 && m <= 320) {
     launch(0, 2, 0, JAC_MAX_SWEEPS, 0, rot, tol);
     nsweeps = JAC_MAX_SWEEPS;
   } else {
-    // sweeps are launched in batches between host checks of the rotation
-    // counts; a sweep launched after the one without rotations returns at
-    // once but still costs its launches, so the first batch is as long as
-    // the last SVD of this size needed (6 for a new size), the later ones
-    // short.  The launched count does not change the result.
-    int* h = (int*)ctx->host_scratch(sizeof(int) * JB_MAXS);
+    // Sweeps are launched in batches between host checks.  After a batch
+    // one launch applies the rotation test to every column pair at once
+    // (the same sums a sweep computes): when no pair would be rotated, the
+    // next sweep would rotate nothing, and the iteration ends without it.
+    // A sweep without rotations also ends the iteration.  A sweep launched
+    // after convergence returns at once but still costs its launches, so
+    // the first batch is as long as the last SVD of this size needed (5 for
+    // a new size), the later ones one sweep.  The launched count does not
+    // change the result.
+    int* h = (int*)ctx->host_scratch(sizeof(int) * (JB_MAXS + 1));
     auto seen = ctx->jacobi_sweeps_seen.find({m, k});
     const bool known = seen != ctx->jacobi_sweeps_seen.end();
-    int batch = known ? std::max(2, seen->second) : 6;
+    int batch = known ? std::max(1, seen->second) : 5;
     bool done = false;
-    int converged = 0;
+    int converged = 0, rotating = 0;  // sweeps until converged; of them with rotations
     while (!done && nsweeps < JAC_MAX_SWEEPS) {
       for (int b = 0; b < batch && nsweeps < JAC_MAX_SWEEPS; ++b, ++nsweeps) {
         launch(1, P, 0, 1, nsweeps, rot, tol);
         for (int r = 0; r < P - 1; ++r) launch(2, P, r, 1, nsweeps, rot, tol);
       }
-      TTF_HIP(hipMemcpyAsync(h, rot, sizeof(int) * nsweeps, hipMemcpyDeviceToHost, ctx->stream));
+      launch(3, nblk, 0, nsweeps, 0, rot, tol);  // the test labelled nsweeps
+      TTF_HIP(hipMemcpyAsync(h, rot, sizeof(int) * (JB_MAXS + 1), hipMemcpyDeviceToHost, ctx->stream));
       TTF_HIP(hipStreamSynchronize(ctx->stream));
       for (int s = 0; s < nsweeps && !done; ++s)
         if (h[s] == 0) {
           done = true;
           converged = s + 1;
+          rotating = s;
         }
-      batch = known ? 1 : 2;
+      if (!done && h[JB_MAXS] < nsweeps) {
+        done = true;
+        converged = rotating = nsweeps;
+        ctx->jacobi_check_passed += 1;
+      }
+      batch = 1;
     }
-    if (done) ctx->jacobi_sweeps_seen[{m, k}] = converged;
+    // the next SVD of this size starts with as many sweeps as this one
+    // rotated in: after them the test would have ended this one
+    if (done) ctx->jacobi_sweeps_seen[{m, k}] = std::max(1, rotating);
+    ctx->jacobi_svds += 1;
+    ctx->jacobi_sweeps_launched += nsweeps;
+    ctx->jacobi_sweeps_needed += converged;
   }
   hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(1024), 0, ctx->stream, m, k, B, U, sigma, rot, nsweeps,
                      sweeps);
