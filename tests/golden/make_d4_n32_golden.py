@@ -1,4 +1,4 @@
-"""Write tests/golden/c1_cap8_100steps.npz with the CPU oracle only.
+"""Write tests/golden/d4_n32_cap8_100steps.npz with the CPU oracle only.
 
 Workload: d = 4 Fourier modes, n = 32 points on [-4, 4], nu = 0.05, Gaussian
 initial condition from paper_2403_04946_amd.inputs.ic_params(4, seed=0),
@@ -10,7 +10,7 @@ operation of a step is the capped truncation), together with the smallest
 ratio sigma_8/sigma_9 met at any truncation where sigma_9 exceeds the tolerance (a gap near 1 would
 make the truncated tensor ill-determined).
 
-Run: python tests/golden/make_c1_golden.py   (about 5 minutes on 8 cores)
+Run: python tests/golden/make_d4_n32_golden.py   (about 5 minutes on 8 cores)
 """
 import os
 import sys
@@ -60,7 +60,7 @@ def main():
     ranks = [c.shape[2] for c in cores[:-1]]
     # the field is exactly rank <= CAP; drop numerically zero directions
     cores, _ = fullgrid.tt_svd(f, 1e-15, CAP)
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c1_cap8_100steps.npz")
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "d4_n32_cap8_100steps.npz")
     arrays = {f"core{k}": c for k, c in enumerate(cores)}
     np.savez_compressed(out, mu=mu, sigma=sig, norm=np.linalg.norm(f), min_gap=min_gap[0],
                         full_ranks=np.array(ranks), **arrays)

@@ -163,3 +163,27 @@ def test_svd_small_graded_and_rank_deficient(ctx):
     # principal angle between the two 50-dimensional spaces is tiny
     cosines = np.linalg.svd(uq[:, :50].conj().T @ u[:, :50], compute_uv=False)
     assert cosines.min() > 1 - 1e-10
+
+
+def test_jacobi_ends_on_the_all_pairs_test(ctx):
+    """The blocked Jacobi SVD stops when one all-pairs application of the
+    rotation test finds nothing to rotate, instead of running a sweep that
+    rotates nothing.  The same matrix twice: the same sweep count and
+    bitwise the same factors; the second run's first batch is as long as
+    the first run needed, so it ends on that test and launches no sweep
+    more than it needs."""
+    rng = np.random.default_rng(11)
+    b = _cplx(rng, 128, 128)
+    ctx.reset_stats()
+    u1, s1, w1 = _svd(ctx, b)
+    st1 = ctx.dump_stats()
+    u2, s2, w2 = _svd(ctx, b)
+    st = ctx.dump_stats()
+    assert st["jacobi_svds"]["launches"] == 2
+    assert st["jacobi_check_passed"]["launches"] - st1["jacobi_check_passed"]["launches"] == 1
+    assert w1 == w2 and 1 < w1 < 60
+    assert np.array_equal(s1, s2) and np.array_equal(u1, u2)
+    second_launched = st["jacobi_sweeps_launched"]["launches"] - st1["jacobi_sweeps_launched"]["launches"]
+    second_needed = st["jacobi_sweeps_needed"]["launches"] - st1["jacobi_sweeps_needed"]["launches"]
+    assert second_launched == second_needed == w1
+    ctx.reset_stats()

@@ -16,7 +16,7 @@ from oracle import closed_forms, fd, fullgrid, galerkin, tt_ref
 from paper_2403_04946_amd import inputs, tt
 
 pytestmark = pytest.mark.gpu
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c1_cap8_100steps.npz")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "d4_n32_cap8_100steps.npz")
 D, N, L, NU, DT = 4, 32, 4.0, 0.05, 1e-3
 
 
@@ -58,7 +58,7 @@ def test_uncapped_matches_plain_oracle(ctx, d, n):
     assert err < 1e-10, float(err)
 
 
-def test_c1_capped_matches_truncation_aware_oracle(ctx):
+def test_d4_n32_capped_matches_truncation_aware_oracle(ctx):
     mu, sig = inputs.ic_params(D, 0)
     f, _ = gpu_run(ctx, D, N, L, NU, mu, sig, DT, 5, 1e-12, 8)
     prob = oracle_problem()
@@ -69,17 +69,17 @@ def test_c1_capped_matches_truncation_aware_oracle(ctx):
     assert rel(full(f), g) < 1e-10
 
 
-def test_c1_cap8_100_steps_matches_golden(ctx):
+def test_d4_n32_cap8_100_steps_matches_golden(ctx):
     z = np.load(GOLDEN, allow_pickle=False)
     mu, sig = z["mu"], z["sigma"]
     ref = fullgrid.tt_to_full([z[f"core{k}"] for k in range(D)])
     f, _ = gpu_run(ctx, D, N, L, NU, mu, sig, DT, 100, 1e-12, 8)
     err = rel(full(f), ref)
-    print(f"c1 100 steps: rel L2 {err:.3e}, ranks {f.ranks()}, min gap {float(z['min_gap']):.4f}")
+    print(f"d=4 n=32 cap 8, 100 steps: rel L2 {err:.3e}, ranks {f.ranks()}, min gap {float(z['min_gap']):.4f}")
     assert err < 1e-10
 
 
-def test_c1_sketched_apply_matches_exact(ctx):
+def test_d4_n32_sketched_apply_matches_exact(ctx):
     mu, sig = inputs.ic_params(D, 0)
     a, _ = gpu_run(ctx, D, N, L, NU, mu, sig, DT, 10, 1e-12, 8)
     b, _ = gpu_run(ctx, D, N, L, NU, mu, sig, DT, 10, 1e-12, 8, mode=tt.TT_APPLY_SKETCH, ell=96)
