@@ -256,18 +256,30 @@ void apply_exact_core(tt_ctx* ctx, const tt_op* op, int site, const zc* x, int r
 // --------------------------------------------------- sketched-apply gathers
 // Left:  W[j, i, b, beta] = sum_{(alpha, o, c) -> beta} c * sum_t w_t V[j, alpha, col_t, b]
 //        V layout j + l (alpha + R0 (i' + n b)); W layout j + l (i + n (b + r1 beta)).
-__global__ void gather_left_kernel(const int* __restrict__ ptr, const DevEntry* __restrict__ ent,
-                                   const int* __restrict__ tptr, const int* __restrict__ tcol,
-                                   const double* __restrict__ tw,
-                                   const zc* __restrict__ V, zc* __restrict__ W, int l, int n, int r1, int R0,
-                                   int R1) {
-  const long total = (long)l * n * r1 * R1;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    const int j = (int)(e % l);
-    long rest = e / l;
-    const int i = (int)(rest % n);
-    rest /= n;
-    const int b = (int)(rest % r1), beta = (int)(rest / r1);
+// One workgroup per (chunk of 256 consecutive output rows, automaton index,
+// outer index): the automaton entries of a workgroup are uniform (scalar
+// loads, no divergence), the per-element index arithmetic is 32-bit, and
+// consecutive workgroups run through every automaton index of one outer
+// index before the next, so the input slice of that outer index is reused
+// from the caches.  Workgroups loop over (chunk, index, outer) triples when
+// there are more than the grid holds.
+constexpr int GATHER_WG = 256;
+constexpr long GATHER_MAX_GRID = 1L << 20;
+
+__global__ __launch_bounds__(GATHER_WG) void gather_left_kernel(
+    const int* __restrict__ ptr, const DevEntry* __restrict__ ent, const int* __restrict__ tptr,
+    const int* __restrict__ tcol, const double* __restrict__ tw, const zc* __restrict__ V, zc* __restrict__ W, int l,
+    int n, int r1, int R0, int R1) {
+  const int rows = l * n;  // (j, i) pairs, j fastest: W is contiguous over them
+  const int nchunk = (rows + GATHER_WG - 1) / GATHER_WG;
+  const long nwg = (long)nchunk * R1 * r1;
+  for (long wg = blockIdx.x; wg < nwg; wg += gridDim.x) {
+    const int chunk = (int)(wg % nchunk);
+    const long rest = wg / nchunk;
+    const int beta = (int)(rest % R1), b = (int)(rest / R1);
+    const int idx = chunk * GATHER_WG + (int)threadIdx.x;
+    if (idx >= rows) continue;
+    const int j = idx % l, i = idx / l;
     double sr = 0, si = 0;
     for (int q = ptr[beta]; q < ptr[beta + 1]; ++q) {
       const DevEntry en = ent[q];
@@ -275,41 +287,46 @@ __global__ void gather_left_kernel(const int* __restrict__ ptr, const DevEntry* 
       const int row = en.lop * n + i;
       for (int ti = tptr[row]; ti < tptr[row + 1]; ++ti) {
         const double w = tw[ti];
-        const zc v = V[j + (long)l * (en.other + (long)R0 * (tcol[ti] + (long)n * b))];
+        const zc v = V[j + (long)l * (en.other + R0 * (tcol[ti] + n * b))];
         vr += w * v.x;
         vi += w * v.y;
       }
       sr += en.cre * vr - en.cim * vi;
       si += en.cre * vi + en.cim * vr;
     }
-    W[e] = make_double2(sr, si);
+    W[idx + (long)rows * (b + (long)r1 * beta)] = make_double2(sr, si);
   }
 }
 
 void gather_left(tt_ctx* ctx, const tt_op* op, int site, const zc* V, zc* W, int l, int r1) {
   const int n = op->n, R0 = op->R[site], R1 = op->R[site + 1];
   const long total = (long)l * n * r1 * R1;
-  const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
+  const long nwg = (long)((l * n + GATHER_WG - 1) / GATHER_WG) * R1 * r1;
+  if (nwg == 0) return;
   KTimer kt(ctx, "gather_left", 0.0, 32.0 * total);
-  hipLaunchKernelGGL(gather_left_kernel, dim3(blocks), dim3(256), 0, ctx->stream, op->dev[site].in_ptr,
-                     op->dev[site].in_ent, op->d_tap_ptr, op->d_tap_col, op->d_tap_w, V, W, l, n, r1, R0, R1);
+  hipLaunchKernelGGL(gather_left_kernel, dim3((unsigned)std::min(nwg, GATHER_MAX_GRID)), dim3(GATHER_WG), 0,
+                     ctx->stream, op->dev[site].in_ptr, op->dev[site].in_ent, op->d_tap_ptr, op->d_tap_col,
+                     op->d_tap_w, V, W, l, n, r1, R0, R1);
   TTF_HIP(hipGetLastError());
 }
 
 // Right: Z[a, alpha, i, q] = sum_{alpha -> (beta, o, c)} c * sum_t w_t V2[a, col_t, beta, q]
 //        V2 layout a + r0 (i' + n (beta + R1 q)); Z layout a + r0 (alpha + R0 (i + n q)).
-__global__ void gather_right_kernel(const int* __restrict__ ptr, const DevEntry* __restrict__ ent,
-                                    const int* __restrict__ tptr, const int* __restrict__ tcol,
-                                    const double* __restrict__ tw,
-                                    const zc* __restrict__ V2, zc* __restrict__ Z, int r0, int n, int s, int R0,
-                                    int R1) {
-  const long total = (long)r0 * R0 * n * s;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    const int a = (int)(e % r0);
-    long rest = e / r0;
-    const int alpha = (int)(rest % R0);
-    rest /= R0;
-    const int i = (int)(rest % n), q = (int)(rest / n);
+//        Workgroups as on the left, over (chunk of (a, i) pairs, alpha, q).
+__global__ __launch_bounds__(GATHER_WG) void gather_right_kernel(
+    const int* __restrict__ ptr, const DevEntry* __restrict__ ent, const int* __restrict__ tptr,
+    const int* __restrict__ tcol, const double* __restrict__ tw, const zc* __restrict__ V2, zc* __restrict__ Z,
+    int r0, int n, int s, int R0, int R1) {
+  const int rows = r0 * n;  // (a, i) pairs, a fastest
+  const int nchunk = (rows + GATHER_WG - 1) / GATHER_WG;
+  const long nwg = (long)nchunk * R0 * s;
+  for (long wg = blockIdx.x; wg < nwg; wg += gridDim.x) {
+    const int chunk = (int)(wg % nchunk);
+    const long rest = wg / nchunk;
+    const int alpha = (int)(rest % R0), q = (int)(rest / R0);
+    const int idx = chunk * GATHER_WG + (int)threadIdx.x;
+    if (idx >= rows) continue;
+    const int a = idx % r0, i = idx / r0;
     double sr = 0, si = 0;
     for (int p = ptr[alpha]; p < ptr[alpha + 1]; ++p) {
       const DevEntry en = ent[p];
@@ -324,17 +341,19 @@ __global__ void gather_right_kernel(const int* __restrict__ ptr, const DevEntry*
       sr += en.cre * vr - en.cim * vi;
       si += en.cre * vi + en.cim * vr;
     }
-    Z[e] = make_double2(sr, si);
+    Z[a + (long)r0 * (alpha + (long)R0 * (i + (long)n * q))] = make_double2(sr, si);
   }
 }
 
 void gather_right(tt_ctx* ctx, const tt_op* op, int site, const zc* V2, zc* Z, int r0, int s) {
   const int n = op->n, R0 = op->R[site], R1 = op->R[site + 1];
   const long total = (long)r0 * R0 * n * s;
-  const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
+  const long nwg = (long)((r0 * n + GATHER_WG - 1) / GATHER_WG) * R0 * s;
+  if (nwg == 0) return;
   KTimer kt(ctx, "gather_right", 0.0, 32.0 * total);
-  hipLaunchKernelGGL(gather_right_kernel, dim3(blocks), dim3(256), 0, ctx->stream, op->dev[site].out_ptr,
-                     op->dev[site].out_ent, op->d_tap_ptr, op->d_tap_col, op->d_tap_w, V2, Z, r0, n, s, R0, R1);
+  hipLaunchKernelGGL(gather_right_kernel, dim3((unsigned)std::min(nwg, GATHER_MAX_GRID)), dim3(GATHER_WG), 0,
+                     ctx->stream, op->dev[site].out_ptr, op->dev[site].out_ent, op->d_tap_ptr, op->d_tap_col,
+                     op->d_tap_w, V2, Z, r0, n, s, R0, R1);
   TTF_HIP(hipGetLastError());
 }
 
