@@ -73,26 +73,29 @@ __global__ __launch_bounds__(256) void split_planes_kernel(const zc* __restrict_
   const int t = threadIdx.x, row = t >> 2, ks = (t & 3) * 8;
   const int r = r0 + row;
   const int kbase = kb * SP_K;
-  zc v[8];
+  // the 64 x SP_K tile goes through LDS, read so that consecutive lanes
+  // take consecutive addresses: along K (32 lanes per row) when K is
+  // contiguous, along the rows otherwise
+  __shared__ zc T[SP_K][65];
   if constexpr (KCONTIG) {
+    const int kk = t & (SP_K - 1), k = kbase + kk;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int k = kbase + ks + j;
-      v[j] = (r < R && k < K) ? Xb[k + ld * (long)r] : make_double2(0.0, 0.0);
+      const int rr = (t >> 5) + 8 * j;
+      T[kk][rr] = (r0 + rr < R && k < K) ? Xb[k + ld * (long)(r0 + rr)] : make_double2(0.0, 0.0);
     }
   } else {
-    // rows contiguous in memory: read along rows, transpose through LDS
-    __shared__ zc T[SP_K][65];
     const int rr = t & 63;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int kk = (t >> 6) + 4 * j, k = kbase + kk;
       T[kk][rr] = (r0 + rr < R && k < K) ? Xb[(r0 + rr) + ld * (long)k] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = T[ks + j][row];
   }
+  __syncthreads();
+  zc v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = T[ks + j][row];
   double mx = 0.0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
