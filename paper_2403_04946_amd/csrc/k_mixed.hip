@@ -174,8 +174,10 @@ template <int FMT, int TI, int TJ>
 __global__ __launch_bounds__(256, 2) void zgemm_planes_kernel(PlaneGemm p) {
   constexpr int BM = 32 * TI, BN = 32 * TJ;
   constexpr int QA = BM / 16, QB = BN / 16;  // 16-byte chunks per thread
-  __shared__ __align__(16) unsigned short As[BM * SP_LROW];
-  __shared__ __align__(16) unsigned short Bs[BN * SP_LROW];
+  // the operand tiles; after the K loop the same memory stages the output
+  __shared__ __align__(16) unsigned short AB[(BM + BN) * SP_LROW];
+  unsigned short* const As = AB;
+  unsigned short* const Bs = AB + BM * SP_LROW;
   __shared__ int ea_s[BM], eb_s[BN];
 
   const int nsplit = gridDim.z / p.batch;
@@ -314,31 +316,47 @@ __global__ __launch_bounds__(256, 2) void zgemm_planes_kernel(PlaneGemm p) {
     }
   }
 
+  // Output through LDS, half the tile's columns at a time (the two wave
+  // columns in turn): each wave leaves its values in a column-major tile
+  // (BM + 1 rows per column: conflict-free), then consecutive lanes store
+  // consecutive rows of a column.
+  constexpr int HN = BN / 2, LDT = BM + 1;
+  static_assert(HN * LDT * 16 <= (BM + BN) * SP_LROW * 2, "output staging exceeds the operand tiles");
+  zc* const T = reinterpret_cast<zc*>(AB);
 #pragma unroll
-  for (int i = 0; i < TI; ++i)
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    if ((wave >> 1) == h) {
 #pragma unroll
-    for (int j = 0; j < TJ; ++j)
+      for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm + 16 * i + 4 * lq + v;
-        const int n = n0 + wn + 16 * j + lr;
-        if (m >= p.M || n >= p.N) continue;
-        const double re = dR[i][j][v], im = dI[i][j][v];
-        if (nsplit > 1) {
-          zc* w = p.ws + ((long)split * p.batch + bz) * (long)p.M * p.N;
-          w[m + (long)p.M * n] = make_double2(re, im);
-        } else {
-          zc* C = p.C + p.sC * (long)bz;
-          zc out = make_double2(p.alpha.x * re - p.alpha.y * im, p.alpha.x * im + p.alpha.y * re);
-          const long off = m + p.ldc * (long)n;
-          if (p.beta.x != 0.0 || p.beta.y != 0.0) {
-            const zc c = C[off];
-            out.x += p.beta.x * c.x - p.beta.y * c.y;
-            out.y += p.beta.x * c.y + p.beta.y * c.x;
-          }
-          C[off] = out;
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            T[(16 * j + lr) * LDT + wm + 16 * i + 4 * lq + v] = make_double2(dR[i][j][v], dI[i][j][v]);
+    }
+    __syncthreads();
+    for (int e = t; e < BM * HN; e += 256) {
+      const int row = e % BM, col = e / BM;
+      const int m = m0 + row, n = n0 + h * HN + col;
+      if (m >= p.M || n >= p.N) continue;
+      const zc d = T[col * LDT + row];
+      if (nsplit > 1) {
+        zc* w = p.ws + ((long)split * p.batch + bz) * (long)p.M * p.N;
+        w[m + (long)p.M * n] = d;
+      } else {
+        zc* C = p.C + p.sC * (long)bz;
+        zc out = make_double2(p.alpha.x * d.x - p.alpha.y * d.y, p.alpha.x * d.y + p.alpha.y * d.x);
+        const long off = m + p.ldc * (long)n;
+        if (p.beta.x != 0.0 || p.beta.y != 0.0) {
+          const zc c = C[off];
+          out.x += p.beta.x * c.x - p.beta.y * c.y;
+          out.y += p.beta.x * c.y + p.beta.y * c.x;
         }
+        C[off] = out;
       }
+    }
+  }
 }
 
 template <int TI, int TJ>
