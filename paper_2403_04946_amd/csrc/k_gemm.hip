@@ -130,17 +130,9 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
   constexpr bool F32 = sizeof(RT) == 4;
   constexpr int TI = BM / 32, TJ = BN / 32;
   constexpr int RA = BM * BK / 256, RB = BN * BK / 256;  // elements per thread
-  // operand tiles Ar, Ai (-Im(A)), Ap (+Im(A)), Br, Bi; after the K loop
-  // the same memory stages the output (half the tile's columns at a time)
-  constexpr int OP_BYTES = (3 * BK * (BM + PAD) + 2 * BK * (BN + PAD)) * (int)sizeof(RT);
-  constexpr int HN = BN / 2, LDT = BM + 1;
-  constexpr int STG_BYTES = HN * LDT * 16;
-  __shared__ __align__(16) char smem[OP_BYTES > STG_BYTES ? OP_BYTES : STG_BYTES];
-  RT (*const Ar)[BM + PAD] = reinterpret_cast<RT (*)[BM + PAD]>(smem);
-  RT (*const Ai)[BM + PAD] = Ar + BK;
-  RT (*const Ap)[BM + PAD] = Ai + BK;
-  RT (*const Br)[BN + PAD] = reinterpret_cast<RT (*)[BN + PAD]>(Ap + BK);
-  RT (*const Bi)[BN + PAD] = Br + BK;
+  __shared__ RT Ar[BK][BM + PAD], Ai[BK][BM + PAD];  // Ai holds -Im(A)
+  __shared__ RT Ap[BK][BM + PAD];                    // +Im(A)
+  __shared__ RT Br[BK][BN + PAD], Bi[BK][BN + PAD];
 
   const int nsplit = gridDim.z / p.batch;
   const int bz = blockIdx.z % p.batch;
@@ -303,45 +295,32 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmParams p) {
 
   // result layout: register v of lane l holds D[4 v + l/16][l % 16] of
   // each 16 x 16 tile for v_mfma_f64_16x16x4f64, D[4 (l/16) + v][l % 16]
-  // for v_mfma_f32_16x16x4f32.  The waves of one column half leave their
-  // values in a column-major LDS tile (BM + 1 rows per column), then
-  // consecutive lanes store consecutive rows of a column.
-  zc* const T = reinterpret_cast<zc*>(smem);
+  // for v_mfma_f32_16x16x4f32
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    __syncthreads();
-    if ((wave >> 1) == h) {
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int i = 0; i < TI; ++i)
+    for (int j = 0; j < TJ; ++j)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            T[(16 * j + lr) * LDT + wm + 16 * i + (F32 ? 4 * lk + v : 4 * v + lk)] =
-                make_double2(accR[i][j][v], accI[i][j][v]);
-    }
-    __syncthreads();
-    for (int e = t; e < BM * HN; e += 256) {
-      const int row = e % BM, col = e / BM;
-      const int m = m0 + row, n = n0 + h * HN + col;
-      if (m >= p.M || n >= p.N) continue;
-      const zc d = T[col * LDT + row];
-      if (nsplit > 1) {
-        zc* w = p.ws + ((long)split * p.batch + bz) * (long)p.M * p.N;
-        w[m + (long)p.M * n] = d;
-      } else {
-        zc* C = p.C + p.sC * (long)bz;
-        zc out = make_double2(p.alpha.x * d.x - p.alpha.y * d.y, p.alpha.x * d.y + p.alpha.y * d.x);
-        const long off = m + p.ldc * (long)n;
-        if (p.beta.x != 0.0 || p.beta.y != 0.0) {
-          const zc c = C[off];
-          out.x += p.beta.x * c.x - p.beta.y * c.y;
-          out.y += p.beta.x * c.y + p.beta.y * c.x;
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm + 16 * i + (F32 ? 4 * lk + v : 4 * v + lk);
+        const int n = n0 + wn + 16 * j + lr;
+        if (m >= p.M || n >= p.N) continue;
+        const double re = accR[i][j][v], im = accI[i][j][v];
+        if (nsplit > 1) {
+          zc* w = p.ws + ((long)split * p.batch + bz) * (long)p.M * p.N;
+          w[m + (long)p.M * n] = make_double2(re, im);
+        } else {
+          zc* C = p.C + p.sC * (long)bz;
+          zc out = make_double2(p.alpha.x * re - p.alpha.y * im, p.alpha.x * im + p.alpha.y * re);
+          const long off = m + p.ldc * (long)n;
+          if (p.beta.x != 0.0 || p.beta.y != 0.0) {
+            const zc c = C[off];
+            out.x += p.beta.x * c.x - p.beta.y * c.y;
+            out.y += p.beta.x * c.y + p.beta.y * c.x;
+          }
+          C[off] = out;
         }
-        C[off] = out;
       }
-    }
-  }
 }
 
 // C = alpha sum_s ws[s] + beta C.  SK_LANES consecutive lanes share one
