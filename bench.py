@@ -277,7 +277,7 @@ def main_batched(args):
     # the roofline kernel: the class with the most time in that step; its
     # launches (one in PROFILE_EVERY) are event-timed in the timed step
     dom = dominant(classes) if classes else "zgemm"
-    tuned = autotune.tune(ctxs[0], shapes, top=args.autotune_top)
+    tuned = autotune.tune(ctxs[0], shapes, top=args.autotune_top or 64)
     tune_s = time.perf_counter() - t0
     print(f"bench: autotuned {len(tuned)} GEMM shapes in {tune_s:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -578,7 +578,9 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the GEMM launch-shape rule (by default the shapes of one step of each timed form "
                          "are tuned before timing)")
-    ap.add_argument("--autotune-top", type=int, default=64)
+    ap.add_argument("--autotune-top", type=int, default=None,
+                    help="GEMM shapes tuned, heaviest first (default: 200, every shape of a step, for the "
+                         "metric form; 64 for the batched form)")
     ap.add_argument("--autotune-save", default=None, help="write the tuned GEMM table (JSON) at the end")
     ap.add_argument("--autotune-load", default=None, help="use this GEMM table instead of tuning")
     ap.add_argument("--train-instances", type=int, default=12)
@@ -637,7 +639,7 @@ def main():
 
         t0 = time.perf_counter()
         shapes = autotune.profile_shapes(ctx, step)
-        res = autotune.tune(ctx, shapes, top=args.autotune_top)
+        res = autotune.tune(ctx, shapes, top=args.autotune_top or 200)
         tuned = {"shapes_tuned": len(res), "seconds": time.perf_counter() - t0}
         print(f"bench: autotuned {len(res)} GEMM shapes", file=sys.stderr, flush=True)
     # warm-up; the last warm-up step is profiled per kernel class to find
@@ -692,7 +694,7 @@ def main():
         if args.autotune:
             from paper_2403_04946_amd import autotune
 
-            autotune.tune(ctx, autotune.profile_shapes(ctx, lambda: step(0)), top=args.autotune_top)
+            autotune.tune(ctx, autotune.profile_shapes(ctx, lambda: step(0)), top=args.autotune_top or 200)
             f.copy_from(f0)
         step(0)
         ctx.sync()
