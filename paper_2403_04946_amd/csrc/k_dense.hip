@@ -10,8 +10,9 @@
 // pairs between the two blocks.  A column pair is held in registers by a
 // group of 32 lanes (a whole wavefront beyond 320 rows); columns move
 // between groups through LDS.  Every column pair meets once per sweep, so
-// this is a cyclic Jacobi method with a block ordering; sweeps stop after
-// the first one without a rotation.
+// this is a cyclic Jacobi method with a block ordering; the iteration stops
+// when a sweep would rotate no pair, found by one launch that applies the
+// rotation test to every pair at once (or by a sweep without a rotation).
 #include <string>
 
 #include "common.hpp"
