@@ -156,7 +156,7 @@ def test_implicit_order_study_on_device(ctx, name):
 
 
 @pytest.mark.parametrize("name", sorted(IMPLICIT))
-def test_capped_implicit_step_at_config1(ctx, name):
+def test_capped_implicit_step_at_d4_n32(ctx, name):
     """d=4, n=32, cap 8, eps 1e-12: the truncations bind (the midpoint's
     right-hand side is truncated before the solve, the oracle's is not), so
     the device and the oracle may differ at the truncation level (measured:

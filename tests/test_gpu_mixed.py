@@ -161,7 +161,7 @@ def test_fp32_form_at_the_fp32_configuration(ctx):
     op2.close()
 
 
-def test_mixed_config1_trajectory_against_oracle(ctx):
+def test_mixed_d4_n32_trajectory_against_oracle(ctx):
     """d=4, n=32, cap 8 for 20 steps with the sketched apply in the FP16x3
     form: within the gate of the truncation-aware FP64 oracle."""
     d, n, length, nu, dt, steps, eps, cap = 4, 32, 4.0, 0.05, 1e-3, 20, 1e-12, 8
