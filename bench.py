@@ -588,7 +588,7 @@ def main():
     ap.add_argument("--instances-learned", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.form == "batched":
         # more hardware queues than the default 4, so the contexts' streams

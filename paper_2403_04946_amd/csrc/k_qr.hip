@@ -8,7 +8,7 @@
 //   assembled top-down.  Householder reflections keep Q orthonormal to
 //   working precision whatever the rank of the panel.
 // * Helpers of the block Gram-Schmidt QR that orthogonalises wide matrices
-//   panel by panel (the driver is in capi.cpp).
+//   panel by panel (the host loop is in capi.cpp).
 #include "common.hpp"
 #include "dpp.hpp"
 #include "rng.hpp"
