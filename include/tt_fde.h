@@ -127,6 +127,20 @@ int tt_ctx_set_profile_filter(tt_ctx* ctx, const char* kernel);
  * every >= 1; 1 (the default) times every launch. */
 int tt_ctx_set_profile_sampling(tt_ctx* ctx, int every);
 int tt_ctx_reset_stats(tt_ctx* ctx);
+
+/* Context options.  TT_OPT_JACOBI_MAX_SWEEPS (1..60, default 60): sweep
+ * limit of every Jacobi SVD on this context (the truncation SVD of App. A.4
+ * inside tt_round / tt_step, and tt_svd_small).  An SVD that has not
+ * converged at its limit is an error: the call fails with TT_ENOCONV and
+ * takes no truncation from it.  A small limit forces that path, so callers
+ * can test their handling of it.  TT_OPT_QR_MIN_LEVEL (0..2, default 0):
+ * the first form every orthogonalisation tries (0: Cholesky QR twice per
+ * panel with the checked fast second pass, 1: Householder panels with the
+ * fast second pass, 2: Householder panels twice); each form falls back to
+ * the next when its checks fail, so results agree to rounding.  TT_EINVAL
+ * for an unknown option or a value out of range. */
+enum { TT_OPT_JACOBI_MAX_SWEEPS = 1, TT_OPT_QR_MIN_LEVEL = 2 };
+int tt_ctx_set_option(tt_ctx* ctx, int option, long long value);
 int tt_ctx_get_stats(tt_ctx* ctx, const char* kernel, double* total_ms,
                      double* flops, double* bytes, long long* launches);
 /* All recorded keys as text, one line each: "key launches total_ms flops
@@ -249,13 +263,23 @@ typedef struct {
                             form (mixed form; the exact product and
                             everything else stay FP64) */
   uint64_t seed;         /* counter-based RNG key for the Gaussian sketch */
+  int power;             /* SKETCH: subspace-iteration passes after the
+                            first sweep, 0..8 */
+  int pad;
 } tt_apply_opts;
 
 /* y <- L x.  EXACT: the TT-matrix product (Sec. 3 operator applied core by
  * core; ranks R_k r_k; y needs that capacity).  SKETCH: y is the projection
- * of L x onto a right-orthonormal basis found by a Gaussian TT sketch of
- * width l (randomised range finder, left sketches then a right-to-left
- * sweep); ranks <= l; exact whenever l >= the ranks of L x. */
+ * of L x onto bases found by a randomised range finder in TT form of width
+ * l: left Gaussian TT sketches of L x, then a right-to-left sweep of LQ
+ * factorisations giving right-orthonormal cores; each of `power` further
+ * sweeps runs the other way with the previous sweep's interface chains in
+ * place of the sketch (a subspace-iteration step per bond), so y is
+ * right-orthonormal after an even number of them and left-orthonormal after
+ * an odd one.  Ranks <= l (bounded by n^k and n^(d-k)); exact whenever l
+ * reaches the ranks of L x.  The projection of L x onto a truncation of
+ * it is, at Sec. 4.1's truncation T, an approximation of T[L x]: its error
+ * against the exact T[L x] falls with l and with the passes. */
 int tt_apply(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y,
              const tt_apply_opts* opts);
 
@@ -277,6 +301,10 @@ typedef struct {
   int pad;
   double sv_last[TT_MAX_D][8]; /* per bond the 8 smallest kept singular values,
                                   decreasing, zeros in front when fewer */
+  double sigma_first_cut[TT_MAX_D]; /* per bond the largest discarded singular
+                                  value (0 when none is discarded): with
+                                  sigma_min_kept it gives the gap at the cut,
+                                  near 1 where the truncation is ill-determined */
 } tt_round_report;
 
 /* TT rounding (App. A.1, Alg. 2 mirrored): right-to-left orthogonalisation
@@ -322,6 +350,9 @@ typedef struct {
                             derivative reaches its width at a bond (the
                             width may have cut it) is applied again at
                             sketch_rank (fallback) */
+  int sketch_power;      /* subspace-iteration passes of every sketched
+                            apply (tt_apply_opts.power), 0..8 */
+  int pad2;
 } tt_step_opts;
 
 typedef struct {
@@ -511,15 +542,18 @@ int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out);
  * orthogonalisation of the TT sweeps (the QR of V(C) and the LQ of H(C),
  * App. A.1, Alg. 1-2).  A (m x k, ld lda >= m, m >= k >= 1) = Q R with Q
  * (m x k, ld m) orthonormal and R (k x k, ld k) upper triangular, also for
- * rank-deficient A (columns dependent on earlier ones get R columns that
- * are zero below the projection coefficients).  Device pointers to
+ * rank-deficient A: a column whose residual after projection onto the
+ * earlier ones is below 1e-13 of its own norm or of the Frobenius norm of A
+ * is dependent; its R column is zero below the projection coefficients and
+ * its Q column a random direction orthogonal to the others (so A = Q R
+ * holds to about 1e-13 of |A|_F).  Device pointers to
  * interleaved complex doubles; A is not modified; synchronous (one host
  * synchronisation per attempt of the checked fast path). */
 int tt_qr(tt_ctx* ctx, int m, int k, const double* A, int64_t lda, double* Q, double* R);
 
 /* Building block exposed for testing: one-sided Jacobi SVD of the small
- * factor of a TT truncation (App. A.4): B (m x k, ld m, m <= 1024 and
- * k <= 1024, overwritten) has left singular vectors U (m x k, ld m; columns
+ * factor of a TT truncation (App. A.4): B (m x k, ld m, m <= 1536 and
+ * k <= 1536, overwritten) has left singular vectors U (m x k, ld m; columns
  * in order of decreasing singular value, a zero column for a zero singular
  * value) and singular values sigma (k doubles, decreasing).  sweeps
  * (host int, may be null) receives the number of sweeps.  Device pointers;

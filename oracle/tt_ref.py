@@ -69,10 +69,6 @@ def tt_add(x, y, alpha=1.0, beta=1.0):
     return out
 
 
-def tt_scale(x, alpha):
-    return [alpha * x[0]] + [c.copy() for c in x[1:]]
-
-
 def right_orthogonalize(cores):
     """Right-to-left LQ sweep; cores 2..d become right-orthonormal:
     H(C_k) H(C_k)^H = I (App. A.1, mirror of Alg. 1)."""

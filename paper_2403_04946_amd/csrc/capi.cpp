@@ -169,9 +169,10 @@ void ptsqr_inplace(tt_ctx* ctx, int m, int k, zc* q, long ldq, zc* r, long ldr, 
 // orthonormal, R (k x k, ld k) upper triangular, A = Q R.  The matrix is
 // factored in place: q holds A on entry and Q on exit.
 // Per panel: project out the earlier columns (W = Q^H A_p, A_p -= Q W);
-// replace every column whose residual is below 1e-13 of its norm (a column
-// dependent on the earlier ones, or zero) by a Gaussian vector, to be
-// left out of R; factor the panel (Q1 R1); then project once more.
+// replace every column whose residual is below 1e-13 of its norm or of the
+// matrix's Frobenius norm (a column dependent on the earlier ones to
+// working accuracy, or zero) by a Gaussian vector, to be left out of R;
+// factor the panel (Q1 R1); then project once more.
 // level 0 factors the panel by Cholesky QR twice, levels 1 and 2 by the
 // Householder TSQR; levels 0 and 1 finish with the Pythagorean shortcut
 // (Cholesky of I - W2^H W2, see bcgs_pip), level 2 factors the reprojected
@@ -184,7 +185,9 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* ba
   // small work: W2, T (k x NB), R1, R2, Rpp (NB x NB), flags, norm partials
   const size_t kb = (size_t)k * NB, bb = (size_t)NB * NB;
   const int G = bcgs_flag_groups(m);
-  zc* W2 = (zc*)ctx->get_ws("bcgs_small", sizeof(zc) * (2 * kb + 6 * bb) + sizeof(double) * ((size_t)(G + 1) * NB));
+  const int GF = sqnorm_groups((long)m * k);
+  zc* W2 = (zc*)ctx->get_ws("bcgs_small",
+                            sizeof(zc) * (2 * kb + 6 * bb) + sizeof(double) * ((size_t)(G + 1) * NB + GF));
   zc* T = W2 + kb;
   zc* R1 = T + kb;
   zc* R2 = R1 + bb;
@@ -194,6 +197,8 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* ba
   zc* Rinv = Ra + bb;
   int* flags = (int*)(Rinv + bb);
   double* part = (double*)(Rinv + bb) + NB;  // NB ints fit in NB doubles
+  double* fpart = part + (size_t)G * NB;
+  sqnorm_partial(ctx, q, (long)m * k, fpart);  // the matrix's squared norm, in GF parts
   for (int p0 = 0; p0 < k; p0 += NB) {
     const int nb = std::min(NB, k - p0);
     zc* Ap = q + (long)m * p0;
@@ -202,7 +207,7 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* ba
       zgemm(ctx, OPC, OPN, p0, nb, m, Z(1), q, m, 0, Ap, m, 0, Z(0), Rp, k, 0);
       zgemm(ctx, OPN, OPN, m, nb, p0, Z(-1), q, m, 0, Rp, k, 0, Z(1), Ap, m, 0);
     }
-    bcgs_flag(ctx, Ap, m, m, nb, Rp, k, p0, flags, part);
+    bcgs_flag(ctx, Ap, m, m, nb, Rp, k, p0, flags, part, fpart, GF);
     bcgs_random(ctx, Ap, m, m, nb, flags, 0x243F6A8885A308D3ull, p0);
     if (level == 0) {
       // Cholesky QR twice: Y = Y Ra^{-1}, then again with Rb; R1 = Rb Ra
@@ -244,7 +249,8 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* ba
 template <class Load>
 void qr_checked(tt_ctx* ctx, int m, int k, zc* q, zc* r, Load load, int* deferred_bad = nullptr,
                 int start_level = 0) {
-  if (deferred_bad) {
+  start_level = std::max(start_level, ctx->qr_min_level);
+  if (deferred_bad && start_level == 0) {
     load();
     bcgs_qr_inplace(ctx, m, k, q, r, 0, deferred_bad);
     return;
@@ -417,6 +423,9 @@ void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_repo
       if (!std::isfinite(v)) fail(TT_ENONFINITE, "non-finite singular value in tt_round");
     int swp = 0;
     std::memcpy(&swp, (char*)(h + sq + 2), sizeof(int));
+    // an SVD stopped at its sweep limit leaves U unorthogonal: no truncation
+    // may be taken from it
+    require(swp > 0, TT_ENOCONV, "tt_round: Jacobi SVD did not converge within its sweep limit");
     sweeps_max = std::max(sweeps_max, swp);
     int capk = x->cap[c + 1];
     if (rmax > 0) capk = std::min(capk, rmax);
@@ -438,6 +447,7 @@ void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_repo
     if (rep) {
       rep->tail[c] = tail;
       rep->sigma_min_kept[c] = s[kk - 1];
+      rep->sigma_first_cut[c] = kk < sq ? s[kk] : 0.0;
       for (int j = 0; j < 8; ++j) {
         const int idx = kk - 8 + j;
         rep->sv_last[c][j] = idx >= 0 ? s[idx] : 0.0;
@@ -466,8 +476,21 @@ void apply_exact(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y)
   y->orth = TT_ORTH_NONE;
 }
 
+// Sketched operator application: y = the projection of L x onto bases found
+// by a randomised range finder in TT form.  Pass 0 draws Gaussian TT
+// sketches and contracts them with the left parts of L x (left chains S_m);
+// pass 1 sweeps right to left: at site m the contraction M = S_m Z_m of the
+// left chain with the right part of L x (already projected onto the bases
+// found to its right) is factored by LQ, whose orthonormal rows are the new
+// right-orthonormal core, and the right chain P_m = Z_m Q carries the
+// projection one site on.  Each of the `power` further passes sweeps the
+// other way with the previous pass's chains in place of the sketch (a
+// subspace-iteration step: the bases of a bond become the range of L x
+// restricted to the other side's bases), ending left-orthonormal after an
+// odd count and right-orthonormal after an even one.  Exact whenever the
+// widths reach the ranks of L x.
 void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int l, uint64_t seed,
-                  int precision, const int* widths = nullptr) {
+                  int precision, const int* widths = nullptr, int power = 0) {
   // the sketch contractions in plain FP64 or a split 16-bit form (mixed)
   auto gemm = [ctx, precision](tt_ctx*, int opA, int opB, int M, int N, int K, zc alpha, const zc* A, long lda,
                                 long sA, const zc* B, long ldb, long sB, zc beta, zc* C, long ldc, long sC,
@@ -478,6 +501,7 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
   const auto& r = x->rank;
   const auto& R = op->R;
   require(l >= 1, TT_EINVAL, "tt_apply: sketch rank must be >= 1");
+  require(power >= 0 && power <= 8, TT_EINVAL, "tt_apply: power passes must be 0..8");
   std::vector<int> ll(d + 1);
   // sketch width per bond (uniform l, or the given widths)
   for (int m = 0; m <= d; ++m) {
@@ -492,8 +516,8 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
     return;
   }
   // workspace sizes
-  size_t big0 = 0, big1 = 0, sk_total = 0, om = 0;
-  std::vector<size_t> sk_off(d + 1, 0);
+  size_t big0 = 0, big1 = 0, sk_total = 0, p_total = 0, om = 0;
+  std::vector<size_t> sk_off(d + 1, 0), p_off(d + 1, 0);
   for (int m = 0; m < d; ++m) {
     big0 = std::max(big0, (size_t)ll[m] * R[m] * n * r[m + 1]);          // V
     big1 = std::max(big1, (size_t)ll[m] * n * r[m + 1] * R[m + 1]);      // W
@@ -504,29 +528,28 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
   for (int m = 0; m <= d; ++m) {
     sk_off[m] = sk_total;
     sk_total += (size_t)ll[m] * r[m] * R[m];
+    p_off[m] = p_total;
+    p_total += (size_t)r[m] * R[m] * ll[m];
   }
   zc* V = (zc*)ctx->get_ws("sk_big0", sizeof(zc) * big0);
   zc* W = (zc*)ctx->get_ws("sk_big1", sizeof(zc) * big1);
-  zc* S = (zc*)ctx->get_ws("sk_S", sizeof(zc) * sk_total);
+  zc* S = (zc*)ctx->get_ws("sk_S", sizeof(zc) * sk_total);   // left chains
+  zc* P = (zc*)ctx->get_ws("sk_P", sizeof(zc) * p_total);    // right chains
   zc* omega = (zc*)ctx->get_ws("sk_omega", sizeof(zc) * om);
-  size_t pmax = 0, mmax = 0;
-  for (int m = 0; m <= d; ++m) pmax = std::max(pmax, (size_t)r[m] * R[m] * ll[m]);
-  for (int m = 1; m < d; ++m) mmax = std::max(mmax, (size_t)ll[m] * n * ll[m + 1]);
-  zc* P = (zc*)ctx->get_ws("sk_P", sizeof(zc) * pmax);
-  zc* P2 = (zc*)ctx->get_ws("sk_P2", sizeof(zc) * pmax);
+  size_t mmax = 0;
+  for (int m = 0; m < d; ++m) mmax = std::max(mmax, (size_t)ll[m] * n * ll[m + 1]);
   zc* M = (zc*)ctx->get_ws("sk_M", sizeof(zc) * std::max<size_t>(mmax, 1));
   zc* Qm = (zc*)ctx->get_ws("sk_Q", sizeof(zc) * std::max<size_t>(mmax, 1));
-  zc* Rm = (zc*)ctx->get_ws("sk_R", sizeof(zc) * (size_t)l * l);
-  // power-of-two scales of the sketch chains: [0] current exponent, [1] the
-  // sum of the exponents taken out of P (restored in the last core)
+  int lmax = 1;
+  for (int m = 0; m <= d; ++m) lmax = std::max(lmax, ll[m]);
+  zc* Rm = (zc*)ctx->get_ws("sk_R", sizeof(zc) * (size_t)lmax * lmax);
+  // power-of-two scales of the chains: [0] current exponent, [1] the sum of
+  // the exponents taken out of the chain that carries the projection
+  // (restored in the pass's last core)
   int* pexp = (int*)ctx->get_ws("sk_pow2", 64);
-  zero_ints(ctx, pexp, 2);
-  // S_0 = 1
-  {
-    const zc one = Z(1);
-    TTF_HIP(hipMemcpyAsync(S + sk_off[0], &one, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
-  }
-  // ---- left sketches S_{m+1} = omega_m^T (Y_m contracted with S_m)
+  const zc one = Z(1);
+  // ---- pass 0: Gaussian left sketches S_{m+1} = omega_m^T (Y_m contracted with S_m), S_0 = 1
+  TTF_HIP(hipMemcpyAsync(S + sk_off[0], &one, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
   for (int m = 0; m + 1 < d; ++m) {
     const int lm = ll[m], lp = ll[m + 1], r0 = r[m], r1 = r[m + 1], R0 = R[m], R1 = R[m + 1];
     const zc* Sm = S + sk_off[m];
@@ -540,44 +563,83 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
     // the range found does not depend on the scale of S
     pow2_normalize(ctx, S + sk_off[m + 1], (long)lp * r1 * R1, pexp, false);
   }
-  // ---- right-to-left compression
-  std::vector<int> s(d + 1, 1);
-  // P_d = 1 (r_d = R_d = s_d = 1)
-  {
-    const zc one = Z(1);
-    TTF_HIP(hipMemcpyAsync(P, &one, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
-  }
-  for (int m = d - 1; m >= 0; --m) {
-    const int r0 = r[m], r1 = r[m + 1], R0 = R[m], R1 = R[m + 1], sp = s[m + 1];
-    // V2[a, i', beta, q] = V(C_m) P_{m+1}
-    gemm(ctx, OPN, OPN, r0 * n, R1 * sp, r1, Z(1), x->core[m], (long)r0 * n, 0, P, r1, 0, Z(0), V,
-          (long)r0 * n, 0, 1);
-    if (m == 0) {
-      gather_right(ctx, op, 0, V, y->core[0], 1, sp);
-      pow2_restore(ctx, y->core[0], (long)n * sp, pexp);
-      break;
+  // ---- right-to-left pass with the left chains S: right-orthonormal y and
+  // the right chains P_m = Z_m Q_m ((r_m R_m) x l_m, layout [a, alpha, q])
+  auto right_to_left = [&]() {
+    zero_ints(ctx, pexp, 2);
+    TTF_HIP(hipMemcpyAsync(P + p_off[d], &one, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
+    int sp = 1;
+    for (int m = d - 1; m >= 0; --m) {
+      const int r0 = r[m], r1 = r[m + 1], R0 = R[m], R1 = R[m + 1];
+      // V2[a, i', beta, q] = V(C_m) P_{m+1}
+      gemm(ctx, OPN, OPN, r0 * n, R1 * sp, r1, Z(1), x->core[m], (long)r0 * n, 0, P + p_off[m + 1], r1, 0, Z(0),
+            V, (long)r0 * n, 0, 1);
+      if (m == 0) {
+        gather_right(ctx, op, 0, V, y->core[0], 1, sp);
+        pow2_restore(ctx, y->core[0], (long)n * sp, pexp);
+        break;
+      }
+      gather_right(ctx, op, m, V, W, r0, sp);  // Z in W
+      const int lm = ll[m];
+      const int N = n * sp;
+      // M = S_m Z  (l_m x n s_{m+1})
+      gemm(ctx, OPN, OPN, lm, N, r0 * R0, Z(1), S + sk_off[m], lm, 0, W, (long)r0 * R0, 0, Z(0), M, lm, 0, 1);
+      // M = R^H Qt^H: the new core is Qt^H (right-orthonormal rows)
+      tsqr_lq(ctx, lm, N, M, lm, Qm, Rm);
+      conj_transpose(ctx, Qm, N, y->core[m], lm, N, lm);
+      y->rank[m] = lm;
+      // P_m = Z Q^H = Z Qt  ((r0 R0) x l_m)
+      gemm(ctx, OPN, OPN, r0 * R0, lm, N, Z(1), W, (long)r0 * R0, 0, Qm, N, 0, Z(0), P + p_off[m], (long)r0 * R0, 0,
+            1);
+      pow2_normalize(ctx, P + p_off[m], (long)r0 * R0 * lm, pexp, true);
+      sp = lm;
     }
-    gather_right(ctx, op, m, V, W, r0, sp);  // Z in W
-    const int lm = ll[m];
-    const int N = n * sp;
-    // M = S_m Z  (l_m x n s_{m+1})
-    gemm(ctx, OPN, OPN, lm, N, r0 * R0, Z(1), S + sk_off[m], lm, 0, W, (long)r0 * R0, 0, Z(0), M, lm, 0, 1);
-    // M = R^H Qt^H: the new core is Qt^H (right-orthonormal rows)
-    tsqr_lq(ctx, lm, N, M, lm, Qm, Rm);
-    conj_transpose(ctx, Qm, N, y->core[m], lm, N, lm);
-    s[m] = lm;
-    // P_m = Z Q^H = Z Qt  ((r0 R0) x l_m), layout [a, alpha, q]
-    gemm(ctx, OPN, OPN, r0 * R0, lm, N, Z(1), W, (long)r0 * R0, 0, Qm, N, 0, Z(0), P2, (long)r0 * R0, 0, 1);
-    pow2_normalize(ctx, P2, (long)r0 * R0 * lm, pexp, true);
-    std::swap(P, P2);
+    y->rank[0] = y->rank[d] = 1;
+    y->orth = TT_ORTH_RIGHT;
+  };
+  // ---- left-to-right pass with the right chains P: left-orthonormal y and
+  // the left chains S_{m+1} = U_m^H W_m (layout [j, a, alpha], as the sketch's)
+  auto left_to_right = [&]() {
+    zero_ints(ctx, pexp, 2);
+    TTF_HIP(hipMemcpyAsync(S + sk_off[0], &one, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
+    int sm = 1;
+    for (int m = 0; m < d; ++m) {
+      const int r0 = r[m], r1 = r[m + 1], R0 = R[m], R1 = R[m + 1];
+      gemm(ctx, OPN, OPN, sm, n * r1, r0, Z(1), S + sk_off[m], sm, (long)sm * r0, x->core[m], r0, 0, Z(0), V,
+            (long)sm * R0, sm, R0);
+      if (m == d - 1) {
+        gather_left(ctx, op, m, V, y->core[m], sm, 1);
+        pow2_restore(ctx, y->core[m], (long)sm * n, pexp);
+        break;
+      }
+      gather_left(ctx, op, m, V, W, sm, r1);  // W: (s_m n) x (r1 R1)
+      const int lp = ll[m + 1];
+      const int rows = sm * n;
+      // M = W P_{m+1}  ((s_m n) x l_{m+1}); M = U R, U the new left-orthonormal core
+      gemm(ctx, OPN, OPN, rows, lp, r1 * R1, Z(1), W, rows, 0, P + p_off[m + 1], (long)r1 * R1, 0, Z(0), M, rows, 0,
+            1);
+      tsqr(ctx, rows, lp, M, rows, y->core[m], Rm);
+      y->rank[m + 1] = lp;
+      // S_{m+1} = U^H W  (l_{m+1} x (r1 R1))
+      gemm(ctx, OPC, OPN, lp, r1 * R1, rows, Z(1), y->core[m], rows, 0, W, rows, 0, Z(0), S + sk_off[m + 1], lp, 0,
+            1);
+      pow2_normalize(ctx, S + sk_off[m + 1], (long)lp * r1 * R1, pexp, true);
+      sm = lp;
+    }
+    y->rank[0] = y->rank[d] = 1;
+    y->orth = TT_ORTH_LEFT;
+  };
+  right_to_left();
+  for (int p = 1; p <= power; ++p) {
+    if (p & 1)
+      left_to_right();
+    else
+      right_to_left();
   }
-  for (int m = 0; m <= d; ++m) y->rank[m] = s[m];
-  y->rank[0] = 1;
-  y->orth = TT_ORTH_RIGHT;
 }
 
 void apply_any(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int mode, int l, uint64_t seed,
-               int precision) {
+               int precision, int power = 0) {
   require(precision == TT_PREC_FP64 || precision == TT_PREC_BF16X3 || precision == TT_PREC_FP16X3 ||
               precision == TT_PREC_FP32,
           TT_EINVAL,
@@ -589,7 +651,7 @@ void apply_any(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, i
   if (mode == TT_APPLY_EXACT)
     apply_exact(ctx, op, x, y);
   else if (mode == TT_APPLY_SKETCH)
-    apply_sketch(ctx, op, x, y, l, seed, precision);
+    apply_sketch(ctx, op, x, y, l, seed, precision, nullptr, power);
   else
     fail(TT_EINVAL, "tt_apply: unknown mode");
 }
@@ -935,6 +997,23 @@ int tt_ctx_set_profile_sampling(tt_ctx* ctx, int every) {
   ABI_CATCH(ctx)
 }
 
+int tt_ctx_set_option(tt_ctx* ctx, int option, long long value) {
+  if (!ctx) return TT_EINVAL;
+  ABI_TRY
+  if (option == TT_OPT_QR_MIN_LEVEL) {
+    require(value >= 0 && value <= 2, TT_EINVAL, "tt_ctx_set_option: QR level must be 0..2");
+    ctx->qr_min_level = (int)value;
+    return TT_OK;
+  }
+  if (option == TT_OPT_JACOBI_MAX_SWEEPS) {
+    require(value >= 1 && value <= 60, TT_EINVAL, "tt_ctx_set_option: Jacobi sweep limit must be 1..60");
+    ctx->jacobi_max_sweeps = (int)value;
+    return TT_OK;
+  }
+  fail(TT_EINVAL, "tt_ctx_set_option: unknown option");
+  ABI_CATCH(ctx)
+}
+
 int tt_ctx_reset_stats(tt_ctx* ctx) {
   if (!ctx) return TT_EINVAL;
   ABI_TRY
@@ -1218,7 +1297,7 @@ int tt_apply(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, con
   if (!ctx || !op || !x || !y || !opts) return TT_EINVAL;
   ABI_TRY
   require(opts->size == (int)sizeof(tt_apply_opts), TT_EINVAL, "tt_apply_opts.size mismatch");
-  apply_any(ctx, op, x, y, opts->mode, opts->sketch_rank, opts->seed, opts->precision);
+  apply_any(ctx, op, x, y, opts->mode, opts->sketch_rank, opts->seed, opts->precision, opts->power);
   return TT_OK;
   ABI_CATCH(ctx)
 }
@@ -1543,23 +1622,30 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
   check_same_shape(op, f);
   const int d = f->d, n = f->n, rmax = opts->rmax;
   // capacities of the temporaries: stage derivatives k (apply outputs),
-  // stage inputs y (f + c k) and the final combination
+  // stage inputs y (f + c k) and the final combination.  Every rounded
+  // tensor has rank at most base = min(rmax, n^k, n^(d-k)) at bond k; f has
+  // at most its capacity.
   std::vector<int> capk(d + 1), capy(d + 1), capf(d + 1);
+  const int big = 1 << 30;
   for (int k = 0; k <= d; ++k) {
-    const int rk = (k == 0 || k == d) ? 1 : std::max(rmax, f->cap[k]);
-    const int base = (k == 0 || k == d) ? 1 : rmax;
+    const bool end = k == 0 || k == d;
+    const int bound = std::min(bounded_pow(n, k, big), bounded_pow(n, d - k, big));
+    const int fr = end ? 1 : f->cap[k];
+    const int base = end ? 1 : std::min(rmax, bound);
     // the midpoint stage input f + dt/2 k is applied untruncated
     const bool mid = scheme == TT_STEP_MIDPOINT || scheme == TT_STEP_IMPLICIT_MIDPOINT;
-    const int rin = (mid && k > 0 && k < d) ? rk + base : rk;
+    const int rin = (mid && !end) ? fr + base : std::max(fr, base);
     if (opts->apply_mode == TT_APPLY_EXACT)
       capk[k] = op->R[k] * rin;
     else
-      capk[k] = (k == 0 || k == d) ? 1 : std::max(opts->sketch_rank, rmax);
-    capy[k] = (k == 0 || k == d) ? 1 : rk + base;
-    capf[k] = (k == 0 || k == d) ? 1 : rk + 4 * base;
+      capk[k] = end ? 1 : std::max(std::min(opts->sketch_rank, bound), base);
+    capy[k] = end ? 1 : fr + base;
+    capf[k] = end ? 1 : fr + 4 * base;
   }
-  const std::string key = shape_key(d, n, f->cap, rmax) + ":" + std::to_string(scheme) + ":" +
-                          std::to_string(opts->apply_mode) + ":" + std::to_string(opts->sketch_rank);
+  // the operator's bond dimensions set the exact apply's capacities
+  std::string key = shape_key(d, n, f->cap, rmax) + ":" + std::to_string(scheme) + ":" +
+                    std::to_string(opts->apply_mode) + ":" + std::to_string(opts->sketch_rank) + ":R";
+  for (int k = 0; k <= d; ++k) key += "," + std::to_string(op->R[k]);
   StepTemps& T = [&]() -> StepTemps& {
     std::lock_guard<std::mutex> lock(cache_mutex());
     return step_cache()[{ctx, key}];
@@ -1627,7 +1713,7 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
     if (!aw.empty()) {
       int lw = 1;
       for (int k = 0; k <= d; ++k) lw = std::max(lw, aw[k]);
-      apply_sketch(ctx, op, in, T.k[s], lw, seed, opts->precision, aw.data());
+      apply_sketch(ctx, op, in, T.k[s], lw, seed, opts->precision, aw.data(), opts->sketch_power);
       round_tensor(ctx, T.k[s], eps, rmax, nullptr);
       // a bond whose rounded rank reaches a width below the plain one may
       // have been cut by the sketch: apply the stage again at full width
@@ -1637,7 +1723,7 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
       if (!done) ++apply_fallback;
     }
     if (!done) {
-      apply_any(ctx, op, in, T.k[s], mode, l, seed, opts->precision);
+      apply_any(ctx, op, in, T.k[s], mode, l, seed, opts->precision, opts->sketch_power);
       round_tensor(ctx, T.k[s], eps, rmax, nullptr);
     }
     for (int k = 0; k <= d; ++k) kr[k] = std::max(kr[k], T.k[s]->rank[k]);
@@ -2096,7 +2182,7 @@ int tt_qr(tt_ctx* ctx, int m, int k, const double* A, int64_t lda, double* Q, do
 int tt_svd_small(tt_ctx* ctx, int m, int k, double* B, double* U, double* sigma, int* sweeps) {
   if (!ctx) return TT_EINVAL;
   ABI_TRY
-  require(m >= 1 && k >= 1 && m <= 1024 && k <= 1024, TT_EINVAL, "tt_svd_small: need 1 <= m, k <= 1024");
+  require(m >= 1 && k >= 1 && m <= 1536 && k <= 1536, TT_EINVAL, "tt_svd_small: need 1 <= m, k <= 1536");
   require(B && U && sigma, TT_EINVAL, "tt_svd_small: null pointer");
   int* sw = (int*)ctx->get_ws("svd_small_sweeps", 64);
   jacobi_svd(ctx, m, k, (zc*)B, (zc*)U, sigma, sw);
@@ -2104,7 +2190,7 @@ int tt_svd_small(tt_ctx* ctx, int m, int k, double* B, double* U, double* sigma,
   TTF_HIP(hipMemcpyAsync(h, sw, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   ctx->sync();
   if (sweeps) *sweeps = h[0];
-  require(h[0] < 60, TT_ENOCONV, "tt_svd_small: Jacobi did not converge in 60 sweeps");
+  require(h[0] > 0, TT_ENOCONV, "tt_svd_small: Jacobi did not converge within its sweep limit");
   return TT_OK;
   ABI_CATCH(ctx)
 }

@@ -21,7 +21,7 @@
 
 namespace ttf {
 
-constexpr int JB_NORMS = 1024;  // columns of the finishing kernel
+constexpr int JB_NORMS = 1536;  // columns of the finishing kernel
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -45,8 +45,8 @@ constexpr int JAC_THREADS = 1024;
 constexpr int JAC_GROUPS = JAC_THREADS / 16;
 constexpr int JAC_MAX_SWEEPS = 60;
 constexpr int JB_COLS = 8;     // columns per block
-constexpr int JB_MAXM = 1024;  // rows supported by the register-resident form
-constexpr int JB_MAXK = 1024;  // columns
+constexpr int JB_MAXM = 1536;  // rows supported by the register-resident form
+constexpr int JB_MAXK = 1536;  // columns
 constexpr int JB_XCHUNK = 8;   // rows per lane moved through LDS at a time
 constexpr int JB_MAXS = 64;    // sweep counters
 
@@ -66,7 +66,7 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
 
 void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
   if (k <= 0) return;
-  if (k > JB_MAXK || m > JB_MAXM || m < 1) fail(TT_EINVAL, "jacobi_svd: sizes above the supported maximum of 1024");
+  if (k > JB_MAXK || m > JB_MAXM || m < 1) fail(TT_EINVAL, "jacobi_svd: sizes above the supported maximum of 1536");
   std::string shape;
   if (ctx->profile_shapes) shape = "jacobi:" + std::to_string(m) + "x" + std::to_string(k);
   KTimer kt2(ctx->profile_shapes ? ctx : nullptr, shape.c_str(), 0.0, 0.0);
@@ -335,11 +335,13 @@ void zero_ints(tt_ctx* ctx, int* x, int n) {
 }
 
 // singular values (column norms) sorted decreasingly, ties by index; U =
-// normalised columns in that order; sweeps = first sweep without rotation + 1
+// normalised columns in that order; sweeps = first sweep without rotation
+// + 1, or nsweeps when the all-pairs test labelled nsweeps ran (checked) and
+// passed, else -1: the iteration stopped at its sweep limit unconverged
 __global__ __launch_bounds__(1024) void jacobi_finish_kernel(int m, int k, const zc* __restrict__ B,
                                                              zc* __restrict__ U, double* __restrict__ sigma,
                                                              const int* __restrict__ rot, int nsweeps,
-                                                             int* __restrict__ sweeps_out) {
+                                                             int checked, int* __restrict__ sweeps_out) {
   __shared__ double norms[JB_NORMS];
   const int t = threadIdx.x, g = t >> 4, l16 = t & 15;
   for (int c = g; c < k; c += JAC_GROUPS) {
@@ -369,7 +371,10 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(int m, int k, const
   if (t == 0) {
     int s = 0;
     while (s < nsweeps && rot[s] != 0) ++s;
-    *sweeps_out = s < nsweeps ? s + 1 : nsweeps;
+    if (s < nsweeps)
+      *sweeps_out = s + 1;
+    else
+      *sweeps_out = (checked && rot[JB_MAXS] < nsweeps) ? nsweeps : -1;
   }
 }
 
@@ -502,18 +507,21 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
       jacobi_launch_rpl<8, 64>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
     else if (m <= 640)
       jacobi_launch_rpl<10, 64>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
-    else
+    else if (m <= 1024)
       jacobi_launch_rpl<16, 64>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
+    else
+      jacobi_launch_rpl<24, 64>(ctx, kind, m, k, B, P, round, inner_max, sweep, rot, tol, f2);
   };
   const double tol = 1e-15 * sqrt((double)m);
   const int nblk = (k + JB_COLS - 1) / JB_COLS;
   const int P = nblk + (nblk & 1);
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, ctx->stream, rot, JB_MAXS + 1);
   TTF_HIP(hipGetLastError());
-  int nsweeps = 0;
+  int nsweeps = 0, checked = 0;
+  const int max_sweeps = std::max(1, std::min(JAC_MAX_SWEEPS, ctx->jacobi_max_sweeps));
   if (k <= 32 && m <= 320) {
-    launch(0, 2, 0, JAC_MAX_SWEEPS, 0, rot, tol);
-    nsweeps = JAC_MAX_SWEEPS;
+    launch(0, 2, 0, max_sweeps, 0, rot, tol);
+    nsweeps = max_sweeps;
   } else {
     // Sweeps are launched in batches between host checks.  After a batch
     // one launch applies the rotation test to every column pair at once
@@ -530,12 +538,13 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
     int batch = known ? std::max(1, seen->second) : 5;
     bool done = false;
     int converged = 0, rotating = 0;  // sweeps until converged; of them with rotations
-    while (!done && nsweeps < JAC_MAX_SWEEPS) {
-      for (int b = 0; b < batch && nsweeps < JAC_MAX_SWEEPS; ++b, ++nsweeps) {
+    while (!done && nsweeps < max_sweeps) {
+      for (int b = 0; b < batch && nsweeps < max_sweeps; ++b, ++nsweeps) {
         launch(1, P, 0, 1, nsweeps, rot, tol);
         for (int r = 0; r < P - 1; ++r) launch(2, P, r, 1, nsweeps, rot, tol);
       }
       launch(3, nblk, 0, nsweeps, 0, rot, tol);  // the test labelled nsweeps
+      checked = 1;
       TTF_HIP(hipMemcpyAsync(h, rot, sizeof(int) * (JB_MAXS + 1), hipMemcpyDeviceToHost, ctx->stream));
       TTF_HIP(hipStreamSynchronize(ctx->stream));
       for (int s = 0; s < nsweeps && !done; ++s)
@@ -559,7 +568,7 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
     ctx->jacobi_sweeps_needed += converged;
   }
   hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(1024), 0, ctx->stream, m, k, B, U, sigma, rot, nsweeps,
-                     sweeps);
+                     checked, sweeps);
   TTF_HIP(hipGetLastError());
 }
 

@@ -27,6 +27,9 @@ TT_STEP_MIDPOINT = 2
 TT_STEP_IMPLICIT_EULER = 3
 TT_STEP_IMPLICIT_MIDPOINT = 4
 TT_ECAPACITY = -3
+TT_ENOCONV = -6
+TT_OPT_JACOBI_MAX_SWEEPS = 1
+TT_OPT_QR_MIN_LEVEL = 2
 ORTH = {0: "none", 1: "right", 2: "left"}
 ERRORS = {
     -1: "TT_EINVAL",
@@ -56,6 +59,7 @@ class RoundReport(ctypes.Structure):
         ("jacobi_sweeps_max", ctypes.c_int),
         ("pad", ctypes.c_int),
         ("sv_last", (ctypes.c_double * 8) * MAX_D),
+        ("sigma_first_cut", ctypes.c_double * MAX_D),
     ]
 
 
@@ -66,6 +70,8 @@ class ApplyOpts(ctypes.Structure):
         ("sketch_rank", ctypes.c_int),
         ("precision", ctypes.c_int),
         ("seed", ctypes.c_uint64),
+        ("power", ctypes.c_int),
+        ("pad", ctypes.c_int),
     ]
 
 
@@ -85,6 +91,8 @@ class StepOpts(ctypes.Structure):
         ("learned_widths", ctypes.POINTER(ctypes.c_int)),
         ("learned_tol", ctypes.c_double),
         ("learned_apply_widths", ctypes.POINTER(ctypes.c_int)),
+        ("sketch_power", ctypes.c_int),
+        ("pad2", ctypes.c_int),
     ]
 
 
@@ -164,6 +172,7 @@ _SIGS = {
     "tt_ctx_stream": (P, [P]),
     "tt_ctx_set_profiling": (I, [P, I]),
     "tt_ctx_reset_stats": (I, [P]),
+    "tt_ctx_set_option": (I, [P, I, ctypes.c_longlong]),
     "tt_ctx_get_stats": (I, [P, ctypes.c_char_p, PD, PD, PD, ctypes.POINTER(ctypes.c_longlong)]),
     "tt_tensor_create": (I, [P, I, I, PI, ctypes.POINTER(P)]),
     "tt_tensor_destroy": (I, [P]),
@@ -307,6 +316,9 @@ class Context:
     def reset_stats(self):
         self.check(lib().tt_ctx_reset_stats(self.h))
 
+    def set_option(self, option, value):
+        self.check(lib().tt_ctx_set_option(self.h, int(option), int(value)))
+
     def stats(self, kernel):
         ms, fl, by, n = D(), D(), D(), ctypes.c_longlong()
         self.check(
@@ -446,8 +458,8 @@ class CdfOperator(Operator):
         self.h = h
 
 
-def tt_apply(ctx, op, x, y, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0):
-    o = ApplyOpts(ctypes.sizeof(ApplyOpts), mode, sketch_rank, int(precision), seed)
+def tt_apply(ctx, op, x, y, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0, power=0):
+    o = ApplyOpts(ctypes.sizeof(ApplyOpts), mode, sketch_rank, int(precision), seed, int(power), 0)
     ctx.check(lib().tt_apply(ctx.h, op.h, x.h, y.h, ctypes.byref(o)))
 
 
@@ -477,12 +489,13 @@ def tt_round(ctx, x, eps, rmax=0, report=True):
         "norm": rep.norm,
         "jacobi_sweeps_max": rep.jacobi_sweeps_max,
         "sv_last": [list(rep.sv_last[c]) for c in range(max(d - 1, 0))],
+        "sigma_first_cut": list(rep.sigma_first_cut[: max(d - 1, 0)]),
     }
 
 
 def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0,
             scheme=TT_STEP_RK4, gmres_tol=1e-10, gmres_max_iter=30, krylov_rmax=0,
-            learned_widths=None, learned_tol=1e-6, learned_apply_widths=None):
+            learned_widths=None, learned_tol=1e-6, learned_apply_widths=None, power=0):
     """One step; ``learned_widths`` (d+1 ints) selects the learned form, whose
     truncations of sums are randomised roundings to these widths, checked;
     ``learned_apply_widths`` (d+1 ints) sets the stage applications' sketch
@@ -501,7 +514,7 @@ def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=
     o = StepOpts(ctypes.sizeof(StepOpts), int(rmax), float(eps), int(mode), int(sketch_rank), int(seed),
                  int(precision), int(scheme), float(gmres_tol), int(gmres_max_iter), int(krylov_rmax),
                  ctypes.cast(widths, ip) if widths is not None else None, float(learned_tol),
-                 ctypes.cast(awidths, ip) if awidths is not None else None)
+                 ctypes.cast(awidths, ip) if awidths is not None else None, int(power), 0)
     rep = StepReport()
     ctx.check(lib().tt_step(ctx.h, op.h, f.h, float(dt), ctypes.byref(o), ctypes.byref(rep)))
     nb = max(f.d - 1, 0)
@@ -513,7 +526,7 @@ def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=
 
 
 def tt_step_batch(ctxs, ops, fs, dts, rmaxs, epss, mode=TT_APPLY_EXACT, sketch_ranks=None, seeds=None,
-                  precision=0, scheme=TT_STEP_RK4):
+                  precision=0, scheme=TT_STEP_RK4, power=0):
     """Independent instances stepped concurrently (one host thread and
     stream per distinct context).  Returns the per-instance status codes."""
     n = len(fs)
@@ -522,7 +535,8 @@ def tt_step_batch(ctxs, ops, fs, dts, rmaxs, epss, mode=TT_APPLY_EXACT, sketch_r
     sketch_ranks = sketch_ranks if sketch_ranks is not None else [0] * n
     seeds = seeds if seeds is not None else [0] * n
     opts = (StepOpts * n)(*[StepOpts(ctypes.sizeof(StepOpts), int(rmaxs[i]), float(epss[i]), int(mode),
-                                     int(sketch_ranks[i]), int(seeds[i]), int(precision), int(scheme), 1e-10, 30, 0)
+                                     int(sketch_ranks[i]), int(seeds[i]), int(precision), int(scheme), 1e-10, 30, 0,
+                                     None, 1e-6, None, int(power), 0)
                             for i in range(n)])
     reps = (StepReport * n)()
     status = (I * n)()

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from gpu_util import make_ctx
-from paper_2403_04946_amd import tt
+from paper_2403_04946_amd import inputs, tt
 
 pytestmark = pytest.mark.gpu
 
@@ -112,7 +112,7 @@ def test_qr_and_svd_reject_bad_shapes(ctx):
     null = tt.P(0)
     assert tt.lib().tt_qr(ctx.h, 4, 8, null, 4, null, null) == -1  # m < k
     assert tt.lib().tt_qr(ctx.h, 8, 0, null, 8, null, null) == -1  # k < 1
-    assert tt.lib().tt_svd_small(ctx.h, 1025, 4, null, null, null, None) == -1  # beyond 1024 rows
+    assert tt.lib().tt_svd_small(ctx.h, 1537, 4, null, null, null, None) == -1  # beyond 1536 rows
     ctx.sync()
 
 
@@ -129,7 +129,8 @@ def _svd(ctx, b):
 
 
 @pytest.mark.parametrize("m,k", [(1, 1), (16, 16), (33, 33), (80, 80), (128, 128), (320, 320), (500, 500), (200, 50),
-                                 (64, 100), (640, 640), (700, 24), (1000, 1000), (1024, 300)])
+                                 (64, 100), (640, 640), (700, 24), (1000, 1000), (1024, 300), (1344, 1344),
+                                 (1536, 200)])
 def test_svd_small_matches_numpy(ctx, m, k):
     rng = np.random.default_rng(m + 7 * k)
     b = _cplx(rng, m, k)
@@ -187,3 +188,31 @@ def test_jacobi_ends_on_the_all_pairs_test(ctx):
     second_needed = st["jacobi_sweeps_needed"]["launches"] - st1["jacobi_sweeps_needed"]["launches"]
     assert second_launched == second_needed == w1
     ctx.reset_stats()
+
+
+def test_jacobi_sweep_limit_is_an_error(ctx):
+    """A Jacobi SVD that reaches its sweep limit unconverged fails with
+    TT_ENOCONV instead of handing back unorthogonal factors; the limit is
+    forced from the host (one sweep), so every kernel still ends normally.
+    Both the blocked form and the single-workgroup form (k <= 32), and a
+    TT rounding whose truncation SVD stops unconverged."""
+    rng = np.random.default_rng(5)
+    ctx.set_option(tt.TT_OPT_JACOBI_MAX_SWEEPS, 1)
+    try:
+        for m, k in [(128, 128), (40, 24)]:
+            with pytest.raises(tt.TTError) as e:
+                _svd(ctx, _cplx(rng, m, k))
+            assert e.value.code == tt.TT_ENOCONV
+        x = tt.Tensor(ctx, 4, 16, 64)
+        x.set_cores(inputs.random_tt(4, 16, [1, 16, 64, 16, 1], 3))
+        with pytest.raises(tt.TTError) as e:
+            tt.tt_round(ctx, x, 1e-6, 16)
+        assert e.value.code == tt.TT_ENOCONV
+        x.close()
+    finally:
+        ctx.set_option(tt.TT_OPT_JACOBI_MAX_SWEEPS, 60)
+    # the default limit converges on the same kind of input
+    _, s, sweeps = _svd(ctx, _cplx(rng, 128, 128))
+    assert 1 < sweeps < 60
+    with pytest.raises(tt.TTError):
+        ctx.set_option(tt.TT_OPT_JACOBI_MAX_SWEEPS, 0)

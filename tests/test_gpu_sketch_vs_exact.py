@@ -1,0 +1,192 @@
+"""The sketched operator application against the method's own T[L x].
+
+Step-truncation (Sec. 4.1, eq. (eqn:discrete-flow-trunc-intro)) applies the
+operator exactly and then truncates (App. A.1, Alg. 2): T[L x].  At d = 20,
+n = 64 (the FP64/FP32 workload: [-6, 6], nu = 0.02, rank cap 32, relative
+tolerance 1e-8) the exact TT-matrix product still fits on one GPU (bond
+ranks R_k r_k <= 1280), so the exact T[L x] is computed here by
+tt_apply(EXACT) and tt_round, and the sketched application (width l,
+`power` subspace-iteration passes) is compared with it, through the C ABI.
+
+Measures (both sides rounded by the same deterministic tt_round):
+  * distance   ||T[S(L x)] - T[L x]|| / ||T[L x]||  (concatenated difference);
+  * excess     ||L x - T[S(L x)]|| / ||L x - T[L x]|| - 1, how much further
+               from L x the sketched truncation lands than the optimal one
+               (inner-product expansion; L x is too wide to difference).
+Where the cap cuts between nearly equal singular values, T[L x] is not
+unique to within its gap, so the distance there says more about the gap than
+about the sketch; the excess is insensitive to it.  The gaps are printed.
+
+Inputs: a trajectory state (the Gaussian initial condition of seed 0 after
+10 steps of the plain form) and a saturated random TT (every interior rank
+32, i.i.d. complex Gaussian cores), the benchmark's kind of input.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import make_ctx
+from paper_2403_04946_amd import inputs, tt
+
+pytestmark = pytest.mark.gpu
+
+D, N, L, NU, CAP, EPS, DT = 20, 64, 6.0, 0.02, 32, 1e-8, 5e-4
+
+
+@pytest.fixture(scope="module")
+def env():
+    ctx = make_ctx()
+    op = tt.Operator(ctx, D, N, L, NU)
+    mu, sig = inputs.ic_params(D, 0)
+    traj = tt.Tensor(ctx, D, N, CAP)
+    traj.set_gaussian(mu, sig, L)
+    for _ in range(10):
+        tt.tt_step(ctx, op, traj, DT, CAP, EPS, tt.TT_APPLY_SKETCH, 80, 7)
+    sat = tt.Tensor(ctx, D, N, CAP)
+    sat.set_cores(inputs.random_tt(D, N, CAP, 0))
+    yield ctx, op, {"trajectory": traj, "saturated": sat}
+    for t in (traj, sat):
+        t.close()
+    op.close()
+    ctx.sync()
+    ctx.close()
+
+
+def bounded(w):
+    return [1] + [min(w, N ** min(k, 6), N ** min(D - k, 6)) for k in range(1, D)] + [1]
+
+
+def dot(ctx, a, b):
+    return tt.tt_dot(ctx, a, b)
+
+
+def rounded(ctx, y, eps, cap):
+    """T[y] into a tensor sized by its ranks (y itself is left unchanged)."""
+    tmp = tt.Tensor(ctx, D, N, y.caps)
+    tmp.copy_from(y)
+    rep = tt.tt_round(ctx, tmp, eps, cap)
+    out = tt.Tensor(ctx, D, N, tmp.ranks())
+    out.copy_from(tmp)
+    tmp.close()
+    return out, rep
+
+
+def distance(ctx, a, b):
+    """||a - b|| / ||b|| from the concatenated difference (no cancellation)."""
+    ra, rb = a.ranks(), b.ranks()
+    diff = tt.Tensor(ctx, D, N, [1] + [ra[k] + rb[k] for k in range(1, D)] + [1])
+    tt.tt_axpy(ctx, 1.0, a, -1.0, b, diff)
+    v = tt.tt_norm(ctx, diff) / tt.tt_norm(ctx, b)
+    diff.close()
+    return v
+
+
+def exact(ctx, op, x):
+    R, r = op.ranks(), x.ranks()
+    y = tt.Tensor(ctx, D, N, [R[k] * r[k] for k in range(D + 1)])
+    tt.tt_apply(ctx, op, x, y, tt.TT_APPLY_EXACT)
+    return y
+
+
+def sketched(ctx, op, x, width, power, seed=12345):
+    y = tt.Tensor(ctx, D, N, bounded(width))
+    tt.tt_apply(ctx, op, x, y, tt.TT_APPLY_SKETCH, width, seed, power=power)
+    return y
+
+
+def excess(ctx, lx, lx2, t_opt, t):
+    """||Lx - t|| / ||Lx - t_opt|| - 1 by the expansion of both squares."""
+    def err2(u):
+        return lx2 - 2.0 * dot(ctx, u, lx).real + dot(ctx, u, u).real
+    return np.sqrt(max(err2(t), 0.0) / err2(t_opt)) - 1.0
+
+
+@pytest.mark.parametrize("which", ["trajectory", "saturated"])
+@pytest.mark.parametrize("power", [0, 1, 2])
+def test_full_width_sketch_is_the_exact_apply(env, which, power):
+    """At a width above every bond rank of L x (1280 here) the sketch spans
+    the whole range: S(L x) = L x, with or without power passes.  Checked on
+    the apply itself (inner-product expansion, resolution about 1e-7) and,
+    on the trajectory state, on a tolerance-limited truncation of both
+    (relative 1e-6, no cap; concatenated difference) to 1e-10."""
+    ctx, op, xs = env
+    x = xs[which]
+    lx = exact(ctx, op, x)
+    y = sketched(ctx, op, x, 1400, power)
+    lx2 = dot(ctx, lx, lx).real
+    e_apply = np.sqrt(max(lx2 - 2.0 * dot(ctx, y, lx).real + dot(ctx, y, y).real, 0.0) / lx2)
+    print(f"{which}, width 1400, power {power}: |S(Lx) - Lx| / |Lx| = {e_apply:.2e} (expansion)")
+    assert e_apply < 1e-6
+    if which == "trajectory":
+        a, _ = rounded(ctx, lx, 1e-6, 0)
+        b, _ = rounded(ctx, y, 1e-6, 0)
+        e = distance(ctx, b, a)
+        print(f"  tolerance-limited truncations (ranks up to {max(a.ranks())}): distance {e:.2e}")
+        assert e < 1e-10
+        a.close()
+        b.close()
+    y.close()
+    lx.close()
+
+
+# plain form of the sketched apply: width 2.5 x cap with two power passes
+PLAIN_WIDTH, PLAIN_POWER = 80, 2
+
+
+def test_width_and_power_against_exact_truncation(env):
+    """Cap-limited truncation of the trajectory state (the FP64 workload's
+    cap 32 and tolerance 1e-8): the table of distance and excess over widths
+    40, 64 (twice the cap), 80 and 128 and 0..2 power passes.  Power passes
+    never make the sketch worse and bring the plain form (width 80, two
+    passes) within 2% of the optimal truncation error (excess) and within
+    2e-3 of T[L x] (distance)."""
+    ctx, op, xs = env
+    x = xs["trajectory"]
+    lx = exact(ctx, op, x)
+    lx2 = dot(ctx, lx, lx).real
+    t_opt, rep = rounded(ctx, lx, EPS, CAP)
+    gaps = [a / b for a, b in zip(rep["sigma_min_kept"], rep["sigma_first_cut"]) if b > 0]
+    trunc = np.sqrt(max(lx2 - dot(ctx, t_opt, t_opt).real, 0.0) / lx2)
+    print(f"T[Lx]: ranks {t_opt.ranks()}, |Lx - T[Lx]| / |Lx| = {trunc:.3e}, "
+          f"smallest gap sigma_k / sigma_k+1 at a cut {min(gaps):.4f}")
+    table = {}
+    for w in (40, 64, 80, 128):
+        for q in (0, 1, 2):
+            y = sketched(ctx, op, x, w, q)
+            t, _ = rounded(ctx, y, EPS, CAP)
+            table[w, q] = (distance(ctx, t, t_opt), excess(ctx, lx, lx2, t_opt, t))
+            print(f"width {w:4d} power {q}: distance {table[w, q][0]:.3e}  excess {table[w, q][1]:.3e}")
+            t.close()
+            y.close()
+    for w in (40, 64, 80, 128):
+        assert table[w, 2][1] <= table[w, 0][1] + 1e-6
+        assert table[w, 2][0] <= table[w, 0][0]
+    d_plain, x_plain = table[PLAIN_WIDTH, PLAIN_POWER]
+    assert x_plain < 0.02
+    assert d_plain < 2e-3
+    t_opt.close()
+    lx.close()
+
+
+def test_saturated_input_is_beyond_any_narrow_sketch(env):
+    """On the saturated random input L x has a nearly flat spectrum up to
+    rank 1280 and the cap discards several times the kept norm: no sketch
+    narrower than the rank finds T[L x] (distance of order one), which is
+    why that input serves for timing only.  Recorded, with the excess."""
+    ctx, op, xs = env
+    x = xs["saturated"]
+    lx = exact(ctx, op, x)
+    lx2 = dot(ctx, lx, lx).real
+    t_opt, rep = rounded(ctx, lx, EPS, CAP)
+    nt = tt.tt_norm(ctx, t_opt)
+    print(f"saturated: |T[Lx]| / |Lx| = {nt / np.sqrt(lx2):.3e}, largest relative tail "
+          f"{max(rep['tail']) / nt:.2f}")
+    for w, q in ((80, 0), (80, 2), (256, 2)):
+        y = sketched(ctx, op, x, w, q)
+        t, _ = rounded(ctx, y, EPS, CAP)
+        dist, exc = distance(ctx, t, t_opt), excess(ctx, lx, lx2, t_opt, t)
+        print(f"width {w} power {q}: distance {dist:.3e} excess {exc:.3e}")
+        assert np.isfinite(dist) and exc > -1e-6
+        t.close()
+        y.close()
+    t_opt.close()
+    lx.close()

@@ -17,6 +17,7 @@ from paper_2403_04946_amd import inputs, tt
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "d4_n32_cap8_100steps.npz")
+GOLDEN_UNCAPPED = os.path.join(os.path.dirname(__file__), "golden", "d4_n32_uncapped_100steps.npz")
 D, N, L, NU, DT = 4, 32, 4.0, 0.05, 1e-3
 
 
@@ -56,6 +57,34 @@ def test_uncapped_matches_plain_oracle(ctx, d, n):
         g = fullgrid.rk4_step(g, DT, prob.apply)
     err = rel(full(f), g)
     assert err < 1e-10, float(err)
+
+
+def test_d4_n32_uncapped_100_steps_matches_plain_oracle(ctx):
+    """The first workload without a rank cap: tolerance 1e-13, rank cap n^2
+    (the largest unfolding rank at d = 4, so it never binds), exact operator
+    application, 100 RK4 steps of dt = 1e-3; all 32^4 points against the
+    oracle's plain full-grid RK4 (golden written by
+    tests/golden/make_d4_n32_uncapped_golden.py, stored as a TT-SVD within
+    1e-13 of the oracle's array).  Target 1e-10 relative L2."""
+    z = np.load(GOLDEN_UNCAPPED, allow_pickle=False)
+    mu, sig = z["mu"], z["sigma"]
+    ref = fullgrid.tt_to_full([z[f"core{k}"] for k in range(D)])
+    assert float(z["store_err"]) < 1e-12
+    caps = [1, N, N * N, N, 1]
+    op = tt.Operator(ctx, D, N, L, NU)
+    f = tt.Tensor(ctx, D, N, caps)
+    f.set_gaussian(mu, sig, L)
+    maxr = 0
+    for _ in range(100):
+        rep = tt.tt_step(ctx, op, f, DT, N * N, 1e-13, tt.TT_APPLY_EXACT)
+        maxr = max(maxr, rep["max_rank"])
+    op.close()
+    err = rel(full(f), ref)
+    print(f"d=4 n=32 uncapped (eps 1e-13), 100 steps: rel L2 {err:.3e} vs plain RK4, ranks {f.ranks()}, "
+          f"largest truncated rank {maxr}")
+    assert abs(np.linalg.norm(full(f)) / float(z["norm"]) - 1) < 1e-10
+    assert err < 1e-10
+    f.close()
 
 
 def test_d4_n32_capped_matches_truncation_aware_oracle(ctx):
