@@ -80,10 +80,59 @@ def cpu_baseline(seconds_target=20.0):
         "value": 4.0 * steps / el,
         "unit": "RK stages/s",
         "cores": int(threads),
+        "host": host_info(),
         "kind": "oracle",
         "sample": (f"{steps} full-grid RK4 step-truncation steps (cap 8, eps 1e-12) at d=4, n=32 "
                    f"({el:.1f} s); the d=50, n=128 grid (128^50 points) cannot be formed on a CPU"),
     }
+
+
+def host_info():
+    """CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+def gpu_oracle_workload(steps=20):
+    """The oracle's workload on the GPU through the library (d = 4, n = 32,
+    cap 8, eps 1e-12, dt 1e-3, exact apply, RK4 from the seeded Gaussian
+    initial condition): stages/s beside the oracle's."""
+    import torch
+
+    from paper_2403_04946_amd import inputs, tt
+
+    ctx = tt.Context(0)
+    op = tt.Operator(ctx, 4, 32, 4.0, 0.05)
+    f = tt.Tensor(ctx, 4, 32, 8)
+    mu, sig = inputs.ic_params(4, 0)
+    f.set_gaussian(mu, sig, 4.0)
+    for _ in range(2):
+        tt.tt_step(ctx, op, f, 1e-3, 8, 1e-12, tt.TT_APPLY_EXACT)
+    f.set_gaussian(mu, sig, 4.0)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tt.tt_step(ctx, op, f, 1e-3, 8, 1e-12, tt.TT_APPLY_EXACT)
+    ctx.sync()
+    el = time.perf_counter() - t0
+    op.close()
+    f.close()
+    ctx.close()
+    return {"value": 4.0 * steps / el, "unit": "RK stages/s",
+            "sample": f"{steps} RK4 step-truncation steps of the oracle's workload (d=4, n=32, cap 8) on the GPU"}
 
 
 # kernel classes that are one kernel each, with the resource that bounds them
@@ -155,7 +204,7 @@ def rel_tt(ctx, tt, a, b):
     return r
 
 
-def stage_errors(ctx, tt, op, f, prec, ell, seed, c=0.5 * DT):
+def stage_errors(ctx, tt, op, f, prec, ell, seed, c=0.5 * DT, power=0):
     """One stage from the identical input f in FP64 and in `prec`: relative
     L2 of the truncated stage derivative k and of the stage output
     y = T[f + c k]."""
@@ -163,7 +212,7 @@ def stage_errors(ctx, tt, op, f, prec, ell, seed, c=0.5 * DT):
     ks = []
     for p in (0, prec):
         k = tt.Tensor(ctx, D, N, max(ell, CAP))
-        tt.tt_apply(ctx, op, f, k, tt.TT_APPLY_SKETCH, ell, seed, precision=p)
+        tt.tt_apply(ctx, op, f, k, tt.TT_APPLY_SKETCH, ell, seed, precision=p, power=power)
         tt.tt_round(ctx, k, EPS, CAP, report=False)
         y = tt.Tensor(ctx, D, N, 2 * CAP)
         tt.tt_axpy(ctx, 1.0, f, c, k, y)
@@ -177,7 +226,7 @@ def stage_errors(ctx, tt, op, f, prec, ell, seed, c=0.5 * DT):
     return out
 
 
-def error_report(ctx, tt, op, f0, prec, ell, traj_steps):
+def error_report(ctx, tt, op, f0, prec, ell, traj_steps, power=0):
     """Errors of the `prec` form against plain FP64 from identical inputs:
     one stage and one step in the timed (saturated) regime, then along the
     FP64 trajectory from the seeded Gaussian initial condition every stage
@@ -185,23 +234,23 @@ def error_report(ctx, tt, op, f0, prec, ell, traj_steps):
     from paper_2403_04946_amd import inputs
 
     rep = {"gate": GATE}
-    rep["saturated_stage"] = stage_errors(ctx, tt, op, f0, prec, ell, 99)
+    rep["saturated_stage"] = stage_errors(ctx, tt, op, f0, prec, ell, 99, power=power)
     a, b = tt.Tensor(ctx, D, N, CAP), tt.Tensor(ctx, D, N, CAP)
     a.copy_from(f0)
     b.copy_from(f0)
-    tt.tt_step(ctx, op, a, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 7, precision=0)
-    tt.tt_step(ctx, op, b, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 7, precision=prec)
+    tt.tt_step(ctx, op, a, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 7, precision=0, power=power)
+    tt.tt_step(ctx, op, b, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 7, precision=prec, power=power)
     rep["saturated_step"] = rel_tt(ctx, tt, b, a)
     mu, sig = inputs.ic_params(D, 0)
     a.set_gaussian(mu, sig, LEN)
     ks, ys, steps = [], [], []
     for s in range(traj_steps):
-        se = stage_errors(ctx, tt, op, a, prec, ell, 1000 + s)
+        se = stage_errors(ctx, tt, op, a, prec, ell, 1000 + s, power=power)
         ks.append(se["k"])
         ys.append(se["stage_output"])
         b.copy_from(a)
-        tt.tt_step(ctx, op, b, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 500 + s, precision=prec)
-        tt.tt_step(ctx, op, a, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 500 + s, precision=0)
+        tt.tt_step(ctx, op, b, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 500 + s, precision=prec, power=power)
+        tt.tt_step(ctx, op, a, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, 500 + s, precision=0, power=power)
         steps.append(rel_tt(ctx, tt, b, a))
     rep["trajectory_from_ic"] = {"stage_k": ks, "stage_output": ys, "step": steps}
     worst = max([rep["saturated_stage"]["stage_output"], rep["saturated_step"]] + ys + steps)
@@ -540,7 +589,7 @@ def main_cdf(args):
         "ms_per_step": 1e3 * sec,
         "higher_is_better": False,
         "scaling": "weak",
-        "vs_baseline": sec / paper_sec,
+        "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
@@ -565,6 +614,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sketch-rank", type=int, default=80)
+    ap.add_argument("--sketch-power", type=int, default=2,
+                    help="subspace-iteration passes of every sketched apply (0 = the plain range finder)")
     ap.add_argument("--precision", choices=sorted(PRECISIONS), default="fp16x3")
     ap.add_argument("--error-steps", type=int, default=2,
                     help="trajectory steps from the initial condition in the error report")
@@ -618,10 +669,11 @@ def main():
     idx = torch.from_numpy(inputs.random_points(D, N, 1024, 1)).cuda()
     out = torch.empty(1024, dtype=torch.complex128, device="cuda")
     ell = args.sketch_rank
+    power = args.sketch_power
     seed = 12345
 
     def step(p=prec):
-        rep = tt.tt_step(ctx, op, f, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, seed, precision=p)
+        rep = tt.tt_step(ctx, op, f, DT, CAP, EPS, tt.TT_APPLY_SKETCH, ell, seed, precision=p, power=power)
         tt.tt_eval(ctx, f, idx, out)
         return rep
 
@@ -713,7 +765,7 @@ def main():
         print(f"bench: FP64 reference, {args.steps} timed steps done", file=sys.stderr, flush=True)
     errors = None
     if prec != 0 and not args.no_error_report:
-        errors = error_report(ctx, tt, op, f0, prec, ell, args.error_steps)
+        errors = error_report(ctx, tt, op, f0, prec, ell, args.error_steps, power=power)
         print("bench: error report done", file=sys.stderr, flush=True)
     if args.autotune_save:
         from paper_2403_04946_amd import autotune
@@ -749,7 +801,9 @@ def main():
                                "QR/SVD/truncation FP64"}[prec]),
             "precision": args.precision,
             "d": D, "n": N, "L": LEN, "nu": NU, "rank_cap": CAP, "eps": EPS, "dt": DT,
-            "apply": f"sketched (width {ell})", "input": "seeded random TT, all interior ranks 64",
+            "apply": f"sketched (width {ell}, {power} subspace-iteration passes)",
+            "sketch_width": ell, "sketch_power": power,
+            "input": "seeded random TT, all interior ranks 64",
         },
         "roofline": roof,
         "fp64_reference": fp64_ref,
@@ -766,6 +820,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
+        result["cpu_baseline"]["gpu_same_workload"] = gpu_oracle_workload()
     print(json.dumps(result), flush=True)
 
 

@@ -261,7 +261,11 @@ typedef struct {
                             TT_PREC_FP32:
                             the sketch contractions in that split 16-bit
                             form (mixed form; the exact product and
-                            everything else stay FP64) */
+                            everything else stay FP64).  With power > 0
+                            only the Gaussian sketch sweep uses it (its
+                            error just changes the random start); the
+                            subspace-iteration and projection sweeps are
+                            FP64 */
   uint64_t seed;         /* counter-based RNG key for the Gaussian sketch */
   int power;             /* SKETCH: subspace-iteration passes after the
                             first sweep, 0..8 */
@@ -543,10 +547,9 @@ int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out);
  * App. A.1, Alg. 1-2).  A (m x k, ld lda >= m, m >= k >= 1) = Q R with Q
  * (m x k, ld m) orthonormal and R (k x k, ld k) upper triangular, also for
  * rank-deficient A: a column whose residual after projection onto the
- * earlier ones is below 1e-13 of its own norm or of the Frobenius norm of A
- * is dependent; its R column is zero below the projection coefficients and
- * its Q column a random direction orthogonal to the others (so A = Q R
- * holds to about 1e-13 of |A|_F).  Device pointers to
+ * earlier ones is below 1e-13 of its own norm is dependent; its R column is
+ * zero below the projection coefficients and its Q column a random
+ * direction orthogonal to the others.  Device pointers to
  * interleaved complex doubles; A is not modified; synchronous (one host
  * synchronisation per attempt of the checked fast path). */
 int tt_qr(tt_ctx* ctx, int m, int k, const double* A, int64_t lda, double* Q, double* R);

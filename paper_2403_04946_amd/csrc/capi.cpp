@@ -169,14 +169,14 @@ void ptsqr_inplace(tt_ctx* ctx, int m, int k, zc* q, long ldq, zc* r, long ldr, 
 // orthonormal, R (k x k, ld k) upper triangular, A = Q R.  The matrix is
 // factored in place: q holds A on entry and Q on exit.
 // Per panel: project out the earlier columns (W = Q^H A_p, A_p -= Q W);
-// replace every column whose residual is below 1e-13 of its norm or of the
-// matrix's Frobenius norm (a column dependent on the earlier ones to
-// working accuracy, or zero) by a Gaussian vector, to be left out of R;
-// factor the panel (Q1 R1); then project once more.
+// replace every column whose residual is below 1e-13 of its norm (a column
+// dependent on the earlier ones to working accuracy, or zero) by a Gaussian
+// vector, to be left out of R; factor the panel (Q1 R1); then project once
+// more.
 // level 0 factors the panel by Cholesky QR twice, levels 1 and 2 by the
 // Householder TSQR; levels 0 and 1 finish with the Pythagorean shortcut
 // (Cholesky of I - W2^H W2, see bcgs_pip), level 2 factors the reprojected
-// panel again with the TSQR.  Shortcuts raise *bad when they are not safe
+// panel again with the TSQR and projects and factors it a third time.  Shortcuts raise *bad when they are not safe
 // for the data (bad may be null at level 2).
 void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* bad) {
   require(m >= k && k >= 1, TT_EINVAL, "qr: need m >= k >= 1");
@@ -185,9 +185,7 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* ba
   // small work: W2, T (k x NB), R1, R2, Rpp (NB x NB), flags, norm partials
   const size_t kb = (size_t)k * NB, bb = (size_t)NB * NB;
   const int G = bcgs_flag_groups(m);
-  const int GF = sqnorm_groups((long)m * k);
-  zc* W2 = (zc*)ctx->get_ws("bcgs_small",
-                            sizeof(zc) * (2 * kb + 6 * bb) + sizeof(double) * ((size_t)(G + 1) * NB + GF));
+  zc* W2 = (zc*)ctx->get_ws("bcgs_small", sizeof(zc) * (2 * kb + 6 * bb) + sizeof(double) * ((size_t)(G + 1) * NB));
   zc* T = W2 + kb;
   zc* R1 = T + kb;
   zc* R2 = R1 + bb;
@@ -197,8 +195,7 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* ba
   zc* Rinv = Ra + bb;
   int* flags = (int*)(Rinv + bb);
   double* part = (double*)(Rinv + bb) + NB;  // NB ints fit in NB doubles
-  double* fpart = part + (size_t)G * NB;
-  sqnorm_partial(ctx, q, (long)m * k, fpart);  // the matrix's squared norm, in GF parts
+  const uint64_t rseed = 0x243F6A8885A308D3ull;
   for (int p0 = 0; p0 < k; p0 += NB) {
     const int nb = std::min(NB, k - p0);
     zc* Ap = q + (long)m * p0;
@@ -207,10 +204,11 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* ba
       zgemm(ctx, OPC, OPN, p0, nb, m, Z(1), q, m, 0, Ap, m, 0, Z(0), Rp, k, 0);
       zgemm(ctx, OPN, OPN, m, nb, p0, Z(-1), q, m, 0, Rp, k, 0, Z(1), Ap, m, 0);
     }
-    bcgs_flag(ctx, Ap, m, m, nb, Rp, k, p0, flags, part, fpart, GF);
-    bcgs_random(ctx, Ap, m, m, nb, flags, 0x243F6A8885A308D3ull, p0);
+    bcgs_flag(ctx, Ap, m, m, nb, Rp, k, p0, flags, part);
+    bcgs_random(ctx, Ap, m, m, nb, flags, rseed, p0);
     if (level == 0) {
       // Cholesky QR twice: Y = Y Ra^{-1}, then again with Rb; R1 = Rb Ra
+      // (a column dependent within the panel makes a pivot fail the test)
       zgemm(ctx, OPC, OPN, nb, nb, m, Z(1), Ap, m, 0, Ap, m, 0, Z(0), Gm, nb, 0);
       chol_solve(ctx, Ap, m, m, nb, Gm, 1e-12, nullptr, Ra, bad);
       zgemm(ctx, OPC, OPN, nb, nb, m, Z(1), Ap, m, 0, Ap, m, 0, Z(0), Gm, nb, 0);
@@ -225,11 +223,22 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* ba
     zgemm(ctx, OPC, OPN, p0, nb, m, Z(1), q, m, 0, Ap, m, 0, Z(0), W2, p0, 0);
     zgemm(ctx, OPN, OPN, m, nb, p0, Z(-1), q, m, 0, W2, p0, 0, Z(1), Ap, m, 0);
     if (level == 2) {
+      // Householder factor of the reprojected panel, then a third projection
+      // and factorisation: a column that the second projection left with
+      // little more than rounding error (nearly in the span of the earlier
+      // columns) is normalised by the factorisation, and only one more pass
+      // makes it orthogonal to them to working accuracy
       ptsqr_inplace(ctx, m, nb, Ap, m, R2, nb, 0);
       zgemm(ctx, OPN, OPN, nb, nb, nb, Z(1), R2, nb, 0, R1, nb, 0, Z(0), Rpp, nb, 0);
       zgemm(ctx, OPN, OPN, p0, nb, nb, Z(1), W2, p0, 0, R1, nb, 0, Z(0), T, p0, 0);
       bcgs_masked_add(ctx, Rp, k, T, p0, p0, nb, flags);
-      bcgs_put_diag(ctx, r + (long)k * p0 + p0, k, Rpp, nb, flags);
+      zgemm(ctx, OPC, OPN, p0, nb, m, Z(1), q, m, 0, Ap, m, 0, Z(0), W2, p0, 0);
+      zgemm(ctx, OPN, OPN, m, nb, p0, Z(-1), q, m, 0, W2, p0, 0, Z(1), Ap, m, 0);
+      ptsqr_inplace(ctx, m, nb, Ap, m, R2, nb, 0);
+      zgemm(ctx, OPN, OPN, nb, nb, nb, Z(1), R2, nb, 0, Rpp, nb, 0, Z(0), Gm, nb, 0);
+      zgemm(ctx, OPN, OPN, p0, nb, nb, Z(1), W2, p0, 0, Rpp, nb, 0, Z(0), T, p0, 0);
+      bcgs_masked_add(ctx, Rp, k, T, p0, p0, nb, flags);
+      bcgs_put_diag(ctx, r + (long)k * p0 + p0, k, Gm, nb, flags);
     } else {
       bcgs_pip(ctx, W2, p0, nb, R1, Rp, r + (long)k * p0 + p0, k, flags, R2, bad);
       panel_trmm(ctx, Ap, m, m, nb, R2);
@@ -491,11 +500,17 @@ void apply_exact(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y)
 // widths reach the ranks of L x.
 void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int l, uint64_t seed,
                   int precision, const int* widths = nullptr, int power = 0) {
-  // the sketch contractions in plain FP64 or a split 16-bit form (mixed)
-  auto gemm = [ctx, precision](tt_ctx*, int opA, int opB, int M, int N, int K, zc alpha, const zc* A, long lda,
-                                long sA, const zc* B, long ldb, long sB, zc beta, zc* C, long ldc, long sC,
-                                int batch) {
-    zgemm_prec(precision, ctx, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
+  // the sketch contractions in plain FP64 or a split 16-bit form (mixed).
+  // With power passes only the Gaussian sketch pass takes `precision`: its
+  // arithmetic error only changes the random start of the subspace
+  // iteration, while in the later passes it perturbs the bases found and
+  // the projection itself, which at cap-limited cuts the truncation
+  // amplifies (split-FP16x3 there puts stage outputs 2e-5 from FP64 at
+  // d = 50; in the sketch pass alone, 4e-6)
+  int prec = precision;
+  auto gemm = [ctx, &prec](tt_ctx*, int opA, int opB, int M, int N, int K, zc alpha, const zc* A, long lda, long sA,
+                           const zc* B, long ldb, long sB, zc beta, zc* C, long ldc, long sC, int batch) {
+    zgemm_prec(prec, ctx, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
   };
   const int d = x->d, n = x->n;
   const auto& r = x->rank;
@@ -545,24 +560,29 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
   zc* Rm = (zc*)ctx->get_ws("sk_R", sizeof(zc) * (size_t)lmax * lmax);
   // power-of-two scales of the chains: [0] current exponent, [1] the sum of
   // the exponents taken out of the chain that carries the projection
-  // (restored in the pass's last core)
+  // (restored in the pass's last core); [8] the deferred flag of the fast QR
+  // form, read once after the whole application
   int* pexp = (int*)ctx->get_ws("sk_pow2", 64);
+  int* qr_flag = pexp + 8;
+  const int qr_level = 0;
   const zc one = Z(1);
   // ---- pass 0: Gaussian left sketches S_{m+1} = omega_m^T (Y_m contracted with S_m), S_0 = 1
-  TTF_HIP(hipMemcpyAsync(S + sk_off[0], &one, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
-  for (int m = 0; m + 1 < d; ++m) {
-    const int lm = ll[m], lp = ll[m + 1], r0 = r[m], r1 = r[m + 1], R0 = R[m], R1 = R[m + 1];
-    const zc* Sm = S + sk_off[m];
-    // V[j, alpha, i', b] = sum_a S_m[j, a, alpha] C_m[a, i', b]  (batched over alpha)
-    gemm(ctx, OPN, OPN, lm, n * r1, r0, Z(1), Sm, lm, (long)lm * r0, x->core[m], r0, 0, Z(0), V, (long)lm * R0,
-          lm, R0);
-    gather_left(ctx, op, m, V, W, lm, r1);
-    sketch_core(ctx, omega, (long)lm * n * lp, seed, m, 1.0 / std::sqrt((double)lp));
-    gemm(ctx, OPT, OPN, lp, r1 * R1, lm * n, Z(1), omega, (long)lm * n, 0, W, (long)lm * n, 0, Z(0),
-          S + sk_off[m + 1], lp, 0, 1);
-    // the range found does not depend on the scale of S
-    pow2_normalize(ctx, S + sk_off[m + 1], (long)lp * r1 * R1, pexp, false);
-  }
+  auto sketch_pass = [&]() {
+    TTF_HIP(hipMemcpyAsync(S + sk_off[0], &one, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
+    for (int m = 0; m + 1 < d; ++m) {
+      const int lm = ll[m], lp = ll[m + 1], r0 = r[m], r1 = r[m + 1], R0 = R[m], R1 = R[m + 1];
+      const zc* Sm = S + sk_off[m];
+      // V[j, alpha, i', b] = sum_a S_m[j, a, alpha] C_m[a, i', b]  (batched over alpha)
+      gemm(ctx, OPN, OPN, lm, n * r1, r0, Z(1), Sm, lm, (long)lm * r0, x->core[m], r0, 0, Z(0), V, (long)lm * R0,
+            lm, R0);
+      gather_left(ctx, op, m, V, W, lm, r1);
+      sketch_core(ctx, omega, (long)lm * n * lp, seed, m, 1.0 / std::sqrt((double)lp));
+      gemm(ctx, OPT, OPN, lp, r1 * R1, lm * n, Z(1), omega, (long)lm * n, 0, W, (long)lm * n, 0, Z(0),
+            S + sk_off[m + 1], lp, 0, 1);
+      // the range found does not depend on the scale of S
+      pow2_normalize(ctx, S + sk_off[m + 1], (long)lp * r1 * R1, pexp, false);
+    }
+  };
   // ---- right-to-left pass with the left chains S: right-orthonormal y and
   // the right chains P_m = Z_m Q_m ((r_m R_m) x l_m, layout [a, alpha, q])
   auto right_to_left = [&]() {
@@ -585,7 +605,7 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
       // M = S_m Z  (l_m x n s_{m+1})
       gemm(ctx, OPN, OPN, lm, N, r0 * R0, Z(1), S + sk_off[m], lm, 0, W, (long)r0 * R0, 0, Z(0), M, lm, 0, 1);
       // M = R^H Qt^H: the new core is Qt^H (right-orthonormal rows)
-      tsqr_lq(ctx, lm, N, M, lm, Qm, Rm);
+      tsqr_lq(ctx, lm, N, M, lm, Qm, Rm, qr_flag, qr_level);
       conj_transpose(ctx, Qm, N, y->core[m], lm, N, lm);
       y->rank[m] = lm;
       // P_m = Z Q^H = Z Qt  ((r0 R0) x l_m)
@@ -618,7 +638,7 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
       // M = W P_{m+1}  ((s_m n) x l_{m+1}); M = U R, U the new left-orthonormal core
       gemm(ctx, OPN, OPN, rows, lp, r1 * R1, Z(1), W, rows, 0, P + p_off[m + 1], (long)r1 * R1, 0, Z(0), M, rows, 0,
             1);
-      tsqr(ctx, rows, lp, M, rows, y->core[m], Rm);
+      tsqr(ctx, rows, lp, M, rows, y->core[m], Rm, qr_flag, qr_level);
       y->rank[m + 1] = lp;
       // S_{m+1} = U^H W  (l_{m+1} x (r1 R1))
       gemm(ctx, OPC, OPN, lp, r1 * R1, rows, Z(1), y->core[m], rows, 0, W, rows, 0, Z(0), S + sk_off[m + 1], lp, 0,
@@ -629,12 +649,28 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
     y->rank[0] = y->rank[d] = 1;
     y->orth = TT_ORTH_LEFT;
   };
-  right_to_left();
-  for (int p = 1; p <= power; ++p) {
-    if (p & 1)
-      left_to_right();
-    else
-      right_to_left();
+  // the factorisations of every sweep take the fast form with one deferred
+  // check; when it was unsafe for some panel, the sweeps run again with
+  // every factorisation checked (and redone robustly) on its own
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (attempt == 0) zero_ints(ctx, qr_flag, 1);
+    else qr_flag = nullptr;  // every factorisation checked on its own
+    prec = precision;
+    sketch_pass();
+    prec = power > 0 ? TT_PREC_FP64 : precision;
+    right_to_left();
+    for (int p = 1; p <= power; ++p) {
+      if (p & 1)
+        left_to_right();
+      else
+        right_to_left();
+    }
+    if (attempt == 1) break;
+    int* h = (int*)ctx->host_scratch(64);
+    TTF_HIP(hipMemcpyAsync(h, qr_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    TTF_HIP(hipStreamSynchronize(ctx->stream));
+    if (h[0] == 0) break;
+    ctx->qr_fallbacks += 1;
   }
 }
 

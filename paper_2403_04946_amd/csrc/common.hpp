@@ -237,10 +237,8 @@ int pt_max_rows();
 int pt_max_cols();
 // block Gram-Schmidt helpers (k_qr.hip)
 void bcgs_flag(tt_ctx* ctx, const zc* Y, long ldy, int m, int nb, const zc* W, long ldw, int p0, int* flags,
-               double* part, const double* fpart, int GF);
-int bcgs_flag_groups(int m);
-int sqnorm_groups(long total);  // partial sums of sqnorm_partial
-void sqnorm_partial(tt_ctx* ctx, const zc* A, long total, double* fpart);  // partial sums used by bcgs_flag (part holds groups * nb)
+               double* part);
+int bcgs_flag_groups(int m);  // partial sums used by bcgs_flag (part holds groups * nb)
 void bcgs_pip(tt_ctx* ctx, const zc* W2, int p0, int nb, const zc* R1, zc* Ro, zc* Rd, long ldr, const int* flags,
               zc* R2inv, int* bad);
 void chol_solve(tt_ctx* ctx, zc* Y, long ldy, int m, int nb, const zc* G, double tau, const zc* Rprev, zc* Rout,

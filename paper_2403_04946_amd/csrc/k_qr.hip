@@ -261,23 +261,18 @@ __global__ __launch_bounds__(256) void colnorm_partial_kernel(const zc* __restri
 }
 
 // flag[c] = 1 when the residual of panel column c after projection is below
-// 1e-13 of the column's norm or below 1e-13 of the Frobenius norm of the
-// whole matrix (a column left with rounding noise only is dependent too:
-// normalised, its noise would enter Q as a direction of no accuracy): the
-// squared residual is the sum of the G partial norms (fixed order), the
-// projected part the squared norm of the coefficients W (p0 rows, leading
-// dimension ldw), the matrix's squared norm the sum of its GF partials
+// 1e-13 of the column's norm: the squared residual is the sum of the G
+// partial norms (fixed order), the projected part the squared norm of the
+// coefficients W (p0 rows, leading dimension ldw).  The test is relative to
+// the column alone: the columns of one factorisation may differ in scale by
+// many orders (the cores of a sum of TTs carry the norms of its terms).
 __global__ __launch_bounds__(1024) void bcgs_flag_kernel(const double* __restrict__ part, int G, int nb,
                                                          const zc* __restrict__ W, long ldw, int p0,
-                                                         const double* __restrict__ fpart, int GF,
                                                          int* __restrict__ flags) {
   // 32 lanes per column (two DPP rows), fixed summation order
   const int c = threadIdx.x >> 5, l = threadIdx.x & 31;
   if (c >= nb) return;
-  double res2 = 0, w2 = 0, f2 = 0;
-  for (int g = l; g < GF; g += 32) f2 += fpart[g];
-  f2 = row16_sum(f2);
-  f2 += __shfl_xor(f2, 16, 64);
+  double res2 = 0, w2 = 0;
   for (int g = l; g < G; g += 32) res2 += part[(long)g * nb + c];
   for (int i = l; i < p0; i += 32) {
     const zc w = W[i + ldw * c];
@@ -288,33 +283,10 @@ __global__ __launch_bounds__(1024) void bcgs_flag_kernel(const double* __restric
   res2 += __shfl_xor(res2, 16, 64);
   w2 += __shfl_xor(w2, 16, 64);
   const double tot = res2 + w2;
-  if (l == 0) flags[c] = (!(res2 > 1e-26 * tot) || !(res2 > 0.0) || !(res2 > 1e-26 * f2)) ? 1 : 0;
+  if (l == 0) flags[c] = (!(res2 > 1e-26 * tot) || !(res2 > 0.0)) ? 1 : 0;
 }
 
-// fpart[g] = squared norm of the g-th of GF contiguous chunks of the m x k
-// matrix A (ld m)
-__global__ __launch_bounds__(256) void sqnorm_partial_kernel(const zc* __restrict__ A, long total,
-                                                             double* __restrict__ fpart) {
-  __shared__ double red[4];
-  const int g = blockIdx.x, GF = gridDim.x;
-  const long e0 = (long)g * total / GF, e1 = (long)(g + 1) * total / GF;
-  double s = 0;
-  for (long e = e0 + threadIdx.x; e < e1; e += 256) {
-    const zc v = A[e];
-    s += v.x * v.x + v.y * v.y;
-  }
-  s = wave_sum64(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) fpart[g] = (red[0] + red[1]) + (red[2] + red[3]);
-}
 
-int sqnorm_groups(long total) { return (int)std::max<long>(1, std::min<long>(1024, total / 4096)); }
-
-void sqnorm_partial(tt_ctx* ctx, const zc* A, long total, double* fpart) {
-  hipLaunchKernelGGL(sqnorm_partial_kernel, dim3(sqnorm_groups(total)), dim3(256), 0, ctx->stream, A, total, fpart);
-  TTF_HIP(hipGetLastError());
-}
 
 // flagged columns are replaced by standard complex Gaussian vectors
 __global__ void bcgs_random_kernel(zc* __restrict__ Qp, long ldq, int m, int nb, const int* __restrict__ flags,
@@ -351,11 +323,10 @@ __global__ void bcgs_put_diag_kernel(zc* __restrict__ Rd, long ldr, const zc* __
 }
 
 void bcgs_flag(tt_ctx* ctx, const zc* Y, long ldy, int m, int nb, const zc* W, long ldw, int p0, int* flags,
-               double* part, const double* fpart, int GF) {
+               double* part) {
   const int G = bcgs_flag_groups(m);
   hipLaunchKernelGGL(colnorm_partial_kernel, dim3(G), dim3(256), 0, ctx->stream, Y, ldy, m, nb, part);
-  hipLaunchKernelGGL(bcgs_flag_kernel, dim3(1), dim3(1024), 0, ctx->stream, part, G, nb, W, ldw, p0, fpart, GF,
-                     flags);
+  hipLaunchKernelGGL(bcgs_flag_kernel, dim3(1), dim3(1024), 0, ctx->stream, part, G, nb, W, ldw, p0, flags);
   TTF_HIP(hipGetLastError());
 }
 
