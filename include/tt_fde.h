@@ -563,6 +563,17 @@ int tt_qr(tt_ctx* ctx, int m, int k, const double* A, int64_t lda, double* Q, do
  * synchronous.  TT_ENOCONV when 60 sweeps did not converge. */
 int tt_svd_small(tt_ctx* ctx, int m, int k, double* B, double* U, double* sigma, int* sweeps);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): tt_svd_small with the
+ * same arguments, layout and results, allocating nothing.  Its sweep
+ * counters live in a per-GPU static device array of 1 KiB (held until the
+ * process ends), set up when a context is created on that GPU; the call
+ * synchronises the context's stream to read the sweep count.  Calls that
+ * overlap on one GPU (two streams or threads) share that array and race:
+ * serialise them.  TT_EINVAL for sizes outside 1..1536 or while profiling
+ * is on (event timing allocates events); TT_ENOCONV as tt_svd_small. */
+int tt_svd_small_noalloc(tt_ctx* ctx, int m, int k, double* B, double* U, double* sigma, int* sweeps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -954,6 +954,7 @@ int tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
   TTF_HIP(hipGetDeviceCount(&ndev));
   require(device >= 0 && device < ndev, TT_EINVAL, "tt_ctx_create: no such device");
   TTF_HIP(hipSetDevice(device));
+  noalloc_scratch_init(device);
   ctx = new tt_ctx;
   ctx->device = device;
   if (hip_stream) {
@@ -2227,6 +2228,19 @@ int tt_svd_small(tt_ctx* ctx, int m, int k, double* B, double* U, double* sigma,
   ctx->sync();
   if (sweeps) *sweeps = h[0];
   require(h[0] > 0, TT_ENOCONV, "tt_svd_small: Jacobi did not converge within its sweep limit");
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_svd_small_noalloc(tt_ctx* ctx, int m, int k, double* B, double* U, double* sigma, int* sweeps) {
+  if (!ctx) return TT_EINVAL;
+  ABI_TRY
+  require(B && U && sigma, TT_EINVAL, "tt_svd_small_noalloc: null pointer");
+  require(!ctx->profiling, TT_EINVAL, "tt_svd_small_noalloc: profiling records events (allocates); turn it off");
+  int h = 0;
+  jacobi_svd_noalloc(ctx, m, k, (zc*)B, (zc*)U, sigma, &h);
+  if (sweeps) *sweeps = h;
+  require(h > 0, TT_ENOCONV, "tt_svd_small_noalloc: Jacobi did not converge within its sweep limit");
   return TT_OK;
   ABI_CATCH(ctx)
 }

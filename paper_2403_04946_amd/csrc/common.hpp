@@ -257,6 +257,10 @@ void conj_transpose(tt_ctx* ctx, const zc* src, long lds, zc* dst, long ldd, int
 // sigma = 0).  Writes the
 // number of sweeps used to *sweeps (device int).
 void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps);
+// the same with its counters in the per-device static scratch (allocates
+// nothing; *sweeps_host is a host int, the call synchronises)
+void jacobi_svd_noalloc(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps_host);
+void noalloc_scratch_init(int device);  // once per device, that device current
 
 // Elementwise / small helpers.
 void set_identity(tt_ctx* ctx, zc* A, int m, int k, long lda);  // A = I (m x k)

@@ -13,6 +13,7 @@
 // this is a cyclic Jacobi method with a block ordering; the iteration stops
 // when a sweep would rotate no pair, found by one launch that applies the
 // rotation test to every pair at once (or by a sweep without a rotation).
+#include <mutex>
 #include <string>
 
 #include "common.hpp"
@@ -49,6 +50,8 @@ constexpr int JB_MAXM = 1536;  // rows supported by the register-resident form
 constexpr int JB_MAXK = 1536;  // columns
 constexpr int JB_XCHUNK = 8;   // rows per lane moved through LDS at a time
 constexpr int JB_MAXS = 64;    // sweep counters
+// counters of one SVD: JB_MAXS + 2 ints, then |B|_F^2 (a double)
+constexpr size_t JB_ROT_BYTES = sizeof(int) * (JB_MAXS + 2) + 64;
 
 // round-robin pairing of players 0..P-1 (P even) in round r
 __device__ inline void rr_pair(int P, int r, int i, int& a, int& b) {
@@ -62,7 +65,7 @@ __device__ inline void rr_pair(int P, int r, int i, int& a, int& b) {
   }
 }
 
-void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps);
+void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps, int* rot_ext = nullptr);
 
 void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
   if (k <= 0) return;
@@ -72,6 +75,46 @@ void jacobi_svd(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* swe
   KTimer kt2(ctx->profile_shapes ? ctx : nullptr, shape.c_str(), 0.0, 0.0);
   KTimer kt(ctx, "jacobi_svd", 0.0, 0.0);
   jacobi_blocked(ctx, m, k, B, U, sigma, sweeps);
+}
+
+// ------------------------------------------ allocation-free variant
+// The counters of jacobi_svd_noalloc live in a file-scope device array, one
+// copy per GPU, whose address is looked up once per device (the host-side
+// name is not a device address); NOALLOC_BYTES bytes, held until the
+// process ends.  Every call on a GPU uses that GPU's copy.
+constexpr size_t NOALLOC_BYTES = 1024;
+static_assert(JB_ROT_BYTES + sizeof(int) <= NOALLOC_BYTES, "counters exceed the static scratch");
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex noalloc_mu;
+static void* noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+void noalloc_scratch_init(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) fail(TT_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (noalloc_ptr[device]) return;
+  void* p = nullptr;
+  hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  if (!p) fail(TT_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+  noalloc_ptr[device] = p;
+}
+
+void jacobi_svd_noalloc(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps_host) {
+  if (k > JB_MAXK || m > JB_MAXM || m < 1 || k < 1)
+    fail(TT_EINVAL, "tt_svd_small_noalloc: sizes outside 1..1536");
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (ctx->device >= 0 && ctx->device < NOALLOC_MAX_DEVICES) base = noalloc_ptr[ctx->device];
+  }
+  if (!base) fail(TT_EHIP, "tt_svd_small_noalloc: the scratch of this device was not set up");
+  int* rot = (int*)base;
+  int* sw = (int*)((char*)base + JB_ROT_BYTES);
+  jacobi_blocked(ctx, m, k, B, U, sigma, sw, rot);
+  int h = 0;
+  TTF_HIP(hipMemcpyAsync(&h, sw, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  TTF_HIP(hipStreamSynchronize(ctx->stream));
+  *sweeps_host = h;
 }
 
 // ------------------------------------------------ block-parallel Jacobi
@@ -483,10 +526,12 @@ void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int ro
 // Blocks of JB_COLS columns; one sweep = every block on its own (all pairs
 // inside a block) followed by the P - 1 rounds of a round-robin over the
 // blocks (all pairs between two blocks), so each column pair meets once.
-void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps) {
+// rot_ext: caller-provided counters (JB_ROT_BYTES of device memory); the
+// run then allocates nothing and records nothing in the context
+void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int* sweeps, int* rot_ext) {
   // rot[0 .. JB_MAXS): rotations per sweep; rot[JB_MAXS]: the last
   // orthogonality check that failed; then |B|_F^2 (8-byte aligned)
-  int* rot = (int*)ctx->get_ws("jac_rot", sizeof(int) * JB_MAXS + 64);
+  int* rot = rot_ext ? rot_ext : (int*)ctx->get_ws("jac_rot", JB_ROT_BYTES);
   double* fro2 = (double*)(rot + JB_MAXS + 2);
   frob_norm2(ctx, B, (long)m * k, fro2);
   // a 32-lane group per column pair up to 320 rows (at most 10 rows per
@@ -532,7 +577,8 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
     // the first batch is as long as the last SVD of this size needed (5 for
     // a new size), the later ones one sweep.  The launched count does not
     // change the result.
-    int* h = (int*)ctx->host_scratch(sizeof(int) * (JB_MAXS + 1));
+    int hbuf[JB_MAXS + 1];
+    int* h = rot_ext ? hbuf : (int*)ctx->host_scratch(sizeof(int) * (JB_MAXS + 1));
     auto seen = ctx->jacobi_sweeps_seen.find({m, k});
     const bool known = seen != ctx->jacobi_sweeps_seen.end();
     int batch = known ? std::max(1, seen->second) : 5;
@@ -562,7 +608,7 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
     }
     // the next SVD of this size starts with as many sweeps as this one
     // rotated in: after them the test would have ended this one
-    if (done) ctx->jacobi_sweeps_seen[{m, k}] = std::max(1, rotating);
+    if (done && !rot_ext) ctx->jacobi_sweeps_seen[{m, k}] = std::max(1, rotating);
     ctx->jacobi_svds += 1;
     ctx->jacobi_sweeps_launched += nsweeps;
     ctx->jacobi_sweeps_needed += converged;

@@ -223,6 +223,7 @@ _SIGS = {
     "tt_zgemm_mixed": (I, [P, I, I, I, I, I, I, D, D, P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64,
                            ctypes.c_int64, D, D, P, ctypes.c_int64, ctypes.c_int64, I]),
     "tt_svd_small": (I, [P, I, I, P, P, P, PI]),
+    "tt_svd_small_noalloc": (I, [P, I, I, P, P, P, PI]),
     "tt_zgemm": (I, [P, I, I, I, I, I, D, D, P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64,
                      ctypes.c_int64, D, D, P, ctypes.c_int64, ctypes.c_int64, I]),
 }
@@ -741,9 +742,10 @@ def tt_qr(ctx, A, Q, R):
     ctx.check(lib().tt_qr(ctx.h, m, k, P(A.data_ptr()), lda, P(Q.data_ptr()), P(R.data_ptr())))
 
 
-def tt_svd_small(ctx, B, U, sigma):
+def tt_svd_small(ctx, B, U, sigma, noalloc=False):
     """One-sided Jacobi SVD of the column-major complex128 device matrix B
-    (m x k, overwritten): U (m x k) and sigma (k float64); returns sweeps."""
+    (m x k, overwritten): U (m x k) and sigma (k float64); returns sweeps.
+    noalloc=True calls tt_svd_small_noalloc (same results, no allocation)."""
     import torch
 
     m, k = B.shape[0], B.shape[1]
@@ -753,6 +755,6 @@ def tt_svd_small(ctx, B, U, sigma):
     if ctx.torch_stream is not None:
         ctx.torch_stream.wait_stream(cur)
     sw = ctypes.c_int()
-    ctx.check(lib().tt_svd_small(ctx.h, m, k, P(B.data_ptr()), P(U.data_ptr()), P(sigma.data_ptr()),
-                                 ctypes.byref(sw)))
+    fn = lib().tt_svd_small_noalloc if noalloc else lib().tt_svd_small
+    ctx.check(fn(ctx.h, m, k, P(B.data_ptr()), P(U.data_ptr()), P(sigma.data_ptr()), ctypes.byref(sw)))
     return sw.value
