@@ -128,6 +128,18 @@ def rk4_step(f, dt, op):
     return f + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
+def bond_cap(cap, bond):
+    """The rank cap of bond `bond` (1..d-1): cap is None (no cap), one int
+    for every bond, or d+1 per-bond values (entry b for bond b; <= 0 means
+    no cap there)."""
+    if cap is None:
+        return None
+    if np.isscalar(cap):
+        return int(cap)
+    c = int(cap[bond])
+    return c if c > 0 else None
+
+
 def truncation_rank(sigma, delta, cap):
     """Smallest k >= 1 whose discarded tail sqrt(sum_{i>k} s_i^2) <= delta,
     then capped.  Cut by index only."""
@@ -146,6 +158,7 @@ def truncation_rank(sigma, delta, cap):
 
 def tt_svd(f, eps_rel, cap=None):
     """TT-SVD of a full array, left to right (Alg. 2 on an exact TT).
+    cap: as in bond_cap.
 
     Returns (cores, sigmas) with cores[c] of shape (r_{c-1}, n_c, r_c) and
     sigmas[c] the singular values at bond c (before truncation).
@@ -161,7 +174,7 @@ def tt_svd(f, eps_rel, cap=None):
     for c in range(d - 1):
         mat = rest.reshape(r_prev * dims[c], -1)
         u, s, vh = np.linalg.svd(mat, full_matrices=False)
-        k = truncation_rank(s, delta, cap)
+        k = truncation_rank(s, delta, bond_cap(cap, c + 1))
         cores.append(u[:, :k].reshape(r_prev, dims[c], k))
         sigmas.append(s)
         rest = s[:k, None] * vh[:k, :]

@@ -30,7 +30,7 @@ operator at d = 4.
 import numpy as np
 
 from . import fd
-from .fullgrid import truncation_rank, tt_to_full  # noqa: F401  (re-export)
+from .fullgrid import bond_cap, truncation_rank, tt_to_full  # noqa: F401  (re-export)
 
 
 def tt_eval(cores, idx):
@@ -91,8 +91,9 @@ def tt_norm(cores):
 
 def tt_round(cores, eps_rel, cap=None):
     """TT rounding: right-to-left orthogonalisation, then a left-to-right
-    truncated-SVD sweep (mirror of Alg. 2).  Returns (cores, info) where info
-    holds the per-bond singular values and kept ranks."""
+    truncated-SVD sweep (mirror of Alg. 2).  cap: None, one cap for every
+    bond, or d+1 per-bond caps (fullgrid.bond_cap).  Returns (cores, info)
+    where info holds the per-bond singular values and kept ranks."""
     c = right_orthogonalize(cores)
     d = len(c)
     norm = float(np.linalg.norm(c[0].ravel()))
@@ -102,7 +103,7 @@ def tt_round(cores, eps_rel, cap=None):
         r0, n, r1 = c[k].shape
         v = c[k].reshape(r0 * n, r1)
         u, s, wh = np.linalg.svd(v, full_matrices=False)
-        kk = truncation_rank(s, delta, cap)
+        kk = truncation_rank(s, delta, bond_cap(cap, k + 1))
         c[k] = u[:, :kk].reshape(r0, n, kk)
         carry = s[:kk, None] * wh[:kk, :]  # (kk, r1)
         c[k + 1] = np.einsum("ab,bic->aic", carry, c[k + 1])

@@ -68,6 +68,32 @@ def test_round_equals_full_grid_tt_svd():
         assert fullgrid.rel_l2(full(y), ref) < 1e-11
 
 
+@pytest.mark.parametrize("bond,cap", [(1, 2), (2, 5), (3, 3), (4, 1)])
+def test_round_with_one_capped_bond_is_the_best_approximation_of_that_unfolding(bond, cap):
+    # with no tolerance and a cap on one bond only, the sweep reaches that
+    # bond with an exact orthonormal left factor, so the result is the best
+    # rank-`cap` approximation of the bond's unfolding (Eckart-Young):
+    # checked against a numpy SVD of the full unfolding, for the TT rounding
+    # and for the full-grid TT-SVD
+    d, n = 5, 4
+    x = inputs.random_tt(d, n, [1, 4, 9, 7, 3, 1], 12)
+    f = full(x)
+    u, s, vh = np.linalg.svd(f.reshape(n ** bond, -1), full_matrices=False)
+    best = ((u[:, :cap] * s[:cap]) @ vh[:cap]).reshape(f.shape)
+    caps = [0] * (d + 1)
+    caps[bond] = cap
+    y, info = tt_ref.tt_round(x, 0.0, caps)
+    assert info["ranks"][bond - 1] == cap
+    assert fullgrid.rel_l2(full(y), best) < 1e-12
+    assert fullgrid.rel_l2(fullgrid.truncate(f, 0.0, caps), best) < 1e-12
+    # a list of equal caps is the single cap; non-positive entries are none
+    z, _ = tt_ref.tt_round(x, 0.0, [7, 2, 2, 2, 2, 9])
+    w, _ = tt_ref.tt_round(x, 0.0, 2)
+    assert fullgrid.rel_l2(full(z), full(w)) < 1e-13
+    v, _ = tt_ref.tt_round(x, 0.0, [0, -1, 0, 0, 0, 0])
+    assert fullgrid.rel_l2(full(v), f) < 1e-13
+
+
 def test_diff_norm_small_differences():
     x = inputs.random_tt(4, 5, 3, 6)
     y = [c.copy() for c in x]
