@@ -94,11 +94,37 @@ typedef struct tt_ctx tt_ctx;
 typedef struct tt_tensor tt_tensor;
 typedef struct tt_op tt_op;
 
+/* Storage precision of a tensor's cores. */
+typedef enum {
+  TT_C128 = 0,  /* complex double (interleaved pairs of doubles) */
+  TT_C64 = 1    /* complex float: half the memory at rest; every call works
+                   on complex-double copies of the C64 tensors it touches
+                   (held in context workspaces) and rounds results back */
+} tt_dtype;
+
+/* Device-memory provider of a context (for example a bridge to a caching
+ * allocator).  alloc returns `bytes` of device memory usable on `stream`
+ * (a hipStream_t), or NULL when it cannot (the library call then fails
+ * with TT_ENOMEM); free returns a block alloc gave.  `user` is passed
+ * back unchanged.  Both are called from the thread that makes the library
+ * call, possibly several at once from tt_step_batch. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* p, void* stream, void* user);
+  void* user;
+} tt_allocator;
+
 /* ---------------------------------------------------------------- context */
 
 /* Create a context on HIP device `device`.  hip_stream is a hipStream_t or
- * NULL (the context then creates its own default-priority stream). */
-int tt_ctx_create(int device, void* hip_stream, tt_ctx** out);
+ * NULL (the context then creates its own default-priority stream).  alloc
+ * (may be NULL: hipMalloc / hipFree) provides every device allocation made
+ * for this context: tensor cores, operator tables, workspaces, the
+ * predictor network; the struct is copied.  Workspaces grow to the largest
+ * size a call needed and are kept: after one call at the largest shapes
+ * (tt_step_reserve), later calls at those or smaller shapes allocate
+ * nothing.  Destroy tensors, operators and networks before their context. */
+int tt_ctx_create(int device, void* hip_stream, const tt_allocator* alloc, tt_ctx** out);
 int tt_ctx_destroy(tt_ctx* ctx);
 /* Wait for all work enqueued on the context's stream. */
 int tt_ctx_sync(tt_ctx* ctx);
@@ -153,21 +179,30 @@ int tt_ctx_dump_stats(tt_ctx* ctx, char* buf, long cap);
 
 /* ---------------------------------------------------------------- tensors */
 
-/* Tensor with d modes of size n and rank capacities rank_cap[0..d]
- * (rank_cap[0] and rank_cap[d] must be 1).  Cores are allocated at capacity.
- * Initial ranks are all 1 with zero cores. */
-int tt_tensor_create(tt_ctx* ctx, int d, int n, const int* rank_cap, tt_tensor** out);
+/* Tensor with d modes of sizes n[0..d-1] (each >= 4) and rank capacities
+ * rank_cap[0..d] (rank_cap[0] and rank_cap[d] must be 1), cores stored as
+ * `dtype`.  Cores are allocated at capacity (through the context's
+ * allocator).  Initial ranks are all 1 with zero cores.  Tensors whose mode
+ * sizes differ serve the TT arithmetic (tt_round, tt_axpy, tt_sum, tt_dot,
+ * tt_norm, tt_eval, copies); the operator calls need every size equal to
+ * the operator's n (TT_ESHAPE otherwise). */
+int tt_tensor_create(tt_ctx* ctx, int d, const int* n, const int* rank_cap, tt_dtype dtype, tt_tensor** out);
+/* Mode sizes (d ints) and storage type of a tensor. */
+int tt_tensor_get_modes(const tt_tensor* t, int* n, int* dtype);
 int tt_tensor_destroy(tt_tensor* t);
 /* Copy host cores in (synchronous).  ranks[0..d]; cores[k] points to
- * 2*ranks[k]*n*ranks[k+1] doubles in the layout above. */
+ * 2*ranks[k]*n_k*ranks[k+1] doubles in the layout above (complex double on
+ * the host whatever the storage type; C64 storage rounds them). */
 int tt_tensor_set_cores(tt_tensor* t, const int* ranks, const double* const* cores);
 /* Current ranks (host copy; reflects all completed work - call after
  * tt_ctx_sync for work still in flight). */
 int tt_tensor_get_ranks(const tt_tensor* t, int* ranks);
-/* Copy cores out to host buffers sized by the current ranks (synchronous). */
+/* Copy cores out to host buffers sized by the current ranks, as complex
+ * double (synchronous). */
 int tt_tensor_get_cores(const tt_tensor* t, double* const* cores);
 int tt_tensor_get_orth(const tt_tensor* t);
-/* dst <- src (same d, n; dst capacities must hold src's ranks). */
+/* dst <- src (same d and mode sizes; dst capacities must hold src's ranks;
+ * storage types may differ: the copy converts). */
 int tt_tensor_copy(tt_ctx* ctx, const tt_tensor* src, tt_tensor* dst);
 /* Rank-one Gaussian characteristic function on the grid a_i = -L + 2Li/(n-1):
  * phi0(a) = prod_k exp(i mu_k a_k - sigma_k^2 a_k^2 / 2)
@@ -314,11 +349,14 @@ typedef struct {
 /* TT rounding (App. A.1, Alg. 2 mirrored): right-to-left orthogonalisation
  * (skipped when x is already right-orthogonal), then a left-to-right sweep
  * of truncated SVDs.  Per bond the smallest rank k >= 1 whose discarded tail
- * is <= eps_rel * ||x|| / sqrt(d - 1) is kept, then k <= rmax (rmax <= 0:
- * no cap) and k <= the capacity of x.  Output cores 1..d-1 are
- * left-orthonormal.  rep may be NULL; when given it is filled on return
- * (the call then synchronises). */
-int tt_round(tt_ctx* ctx, tt_tensor* x, double eps_rel, int rmax, tt_round_report* rep);
+ * is <= eps_rel * ||x|| / sqrt(d - 1) is kept, then k <= rmax[b] (rmax:
+ * NULL for no cap, or d+1 ints whose entry b caps bond b, <= 0 meaning no
+ * cap there; the end entries are ignored) and k <= the capacity of x.
+ * Output cores 1..d-1 are left-orthonormal.  rep may be NULL; when given
+ * it is filled on return (the call then synchronises).  TT_ENOCONV when a
+ * truncation SVD stops at its sweep limit (x then holds the rounding up to
+ * that bond, a valid TT of the same tensor up to the tails cut so far). */
+int tt_round(tt_ctx* ctx, tt_tensor* x, double eps_rel, const int* rmax, tt_round_report* rep);
 
 typedef struct {
   int size;              /* sizeof(tt_step_opts) */
@@ -393,6 +431,13 @@ typedef struct {
  * then left unchanged).  TT_EINVAL for an unknown scheme. */
 int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt,
             const tt_step_opts* opts, tt_step_report* rep);
+
+/* Sizes every workspace and temporary tt_step needs for f's capacities:
+ * one step (opts, dt) of a copy of f's shape with every interior rank at
+ * its capacity (seeded random cores); f is not read or changed.  After it,
+ * tt_step on tensors of that shape with these options allocates nothing
+ * (synchronous; it allocates). */
+int tt_step_reserve(tt_ctx* ctx, const tt_op* op, const tt_tensor* f, double dt, const tt_step_opts* opts);
 
 /* Batched form: `count` independent instances, instance i being one
  * tt_step(ctxs[i], ops[i], fs[i], dts[i], &opts[i], &reps[i]) (reps may be

@@ -49,21 +49,36 @@ KTimer::~KTimer() {
 
 using namespace ttf;
 
+void* tt_ctx::dev_alloc(size_t bytes) {
+  if (has_allocator) return allocator.alloc(bytes, (void*)stream, allocator.user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void tt_ctx::dev_free(void* p) {
+  if (!p) return;
+  if (has_allocator)
+    allocator.free(p, (void*)stream, allocator.user);
+  else
+    (void)hipFree(p);
+}
+
 void* tt_ctx::get_ws(const std::string& name, size_t bytes) {
   Buf& b = ws[name];
   if (b.bytes >= bytes && b.p) return b.p;
   if (b.p) {
     TTF_HIP(hipStreamSynchronize(stream));
-    TTF_HIP(hipFree(b.p));
+    dev_free(b.p);
     b.p = nullptr;
     b.bytes = 0;
   }
   const size_t want = std::max<size_t>(bytes + bytes / 8, 4096);
-  if (hipMalloc(&b.p, want) != hipSuccess) {
-    (void)hipGetLastError();
-    b.p = nullptr;
-    fail(TT_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed (" + name + ")");
-  }
+  b.p = dev_alloc(want);
+  if (!b.p) fail(TT_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed (" + name + ")");
   b.bytes = want;
   return b.p;
 }
@@ -300,19 +315,20 @@ int bounded_pow(int n, int e, int cap) {
 
 // ------------------------------------------------------- TT rounding
 void phase1_right_orth(tt_ctx* ctx, tt_tensor* x) {
-  const int d = x->d, n = x->n;
+  const int d = x->d;
   auto& r = x->rank;
   for (int c = d - 1; c >= 1; --c) {
+    const int n = x->nk[c], nl = x->nk[c - 1];
     const int p0 = r[c], p1 = r[c + 1];
     const int N = n * p1;
     const int rl = r[c - 1];
     // the new C_{c-1} has N columns when H(C_c) is taller than wide, else p0
-    zc* tmp = (zc*)ctx->get_ws("ph1_tmp", sizeof(zc) * (size_t)rl * n * (p0 > N ? N : p0));
+    zc* tmp = (zc*)ctx->get_ws("ph1_tmp", sizeof(zc) * (size_t)rl * nl * (p0 > N ? N : p0));
     if (p0 > N) {
       // H(C_c) is taller than wide: C_c <- I, C_{c-1} <- C_{c-1} H(C_c)
-      zgemm(ctx, OPN, OPN, rl * n, N, p0, Z(1), x->core[c - 1], (long)rl * n, 0, x->core[c], p0, 0, Z(0), tmp,
-            (long)rl * n, 0);
-      copy_d2d(ctx, x->core[c - 1], tmp, (size_t)rl * n * N);
+      zgemm(ctx, OPN, OPN, rl * nl, N, p0, Z(1), x->core[c - 1], (long)rl * nl, 0, x->core[c], p0, 0, Z(0), tmp,
+            (long)rl * nl, 0);
+      copy_d2d(ctx, x->core[c - 1], tmp, (size_t)rl * nl * N);
       identity_core(ctx, x->core[c], n, p1);
       r[c] = N;
     } else {
@@ -321,9 +337,9 @@ void phase1_right_orth(tt_ctx* ctx, tt_tensor* x) {
       tsqr_lq(ctx, p0, N, x->core[c], p0, qt, R);
       conj_transpose(ctx, qt, N, x->core[c], p0, N, p0);  // C_c <- Qt^H
       // C_{c-1} <- C_{c-1} L, L = R^H
-      zgemm(ctx, OPN, OPC, rl * n, p0, p0, Z(1), x->core[c - 1], (long)rl * n, 0, R, p0, 0, Z(0), tmp,
-            (long)rl * n, 0);
-      copy_d2d(ctx, x->core[c - 1], tmp, (size_t)rl * n * p0);
+      zgemm(ctx, OPN, OPC, rl * nl, p0, p0, Z(1), x->core[c - 1], (long)rl * nl, 0, R, p0, 0, Z(0), tmp,
+            (long)rl * nl, 0);
+      copy_d2d(ctx, x->core[c - 1], tmp, (size_t)rl * nl * p0);
     }
   }
   x->orth = TT_ORTH_RIGHT;
@@ -361,8 +377,12 @@ int truncation_rank(const std::vector<double>& s, double delta, int cap, double*
   return kk;
 }
 
-void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_report* rep) {
-  const int d = x->d, n = x->n;
+// caps: per-bond rank caps (d+1 ints, <= 0: none), or null with rmax for
+// every bond (rmax <= 0: none)
+void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_report* rep,
+                  const int* caps = nullptr) {
+  require(x->dtype == TT_C128, TT_EINVAL, "internal: rounding needs complex-double storage");
+  const int d = x->d;
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));
     rep->d = d;
@@ -380,6 +400,7 @@ void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_repo
   const double delta = eps * norm / std::sqrt((double)(d - 1));
   int sweeps_max = 0;
   for (int c = 0; c < d - 1; ++c) {
+    const int n = x->nk[c], n1 = x->nk[c + 1];
     const int m = r[c] * n, k = r[c + 1];
     const int rr = r[c + 2];
     const int sq = std::min(m, k);  // size of the square factor
@@ -390,7 +411,7 @@ void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_repo
     double* sig = (double*)ctx->get_ws("p2_sig", sizeof(double) * (sq + 8));
     int* sw = (int*)(sig + sq + 2);
     zc* carry = (zc*)ctx->get_ws("p2_carry", sizeof(zc) * (size_t)sq * k);
-    zc* tmp = (zc*)ctx->get_ws("p2_tmp", sizeof(zc) * (size_t)sq * n * rr);
+    zc* tmp = (zc*)ctx->get_ws("p2_tmp", sizeof(zc) * (size_t)sq * n1 * rr);
     const zc* V = x->core[c];
     int* qbad = (int*)(sig + sq + 4);  // fast-form QR flag, read with sigma
     // the factorisations only read the core, so a failed fast form is
@@ -437,7 +458,8 @@ void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_repo
     require(swp > 0, TT_ENOCONV, "tt_round: Jacobi SVD did not converge within its sweep limit");
     sweeps_max = std::max(sweeps_max, swp);
     int capk = x->cap[c + 1];
-    if (rmax > 0) capk = std::min(capk, rmax);
+    const int cb = caps ? caps[c + 1] : rmax;
+    if (cb > 0) capk = std::min(capk, cb);
     double tail = 0;
     const int kk = truncation_rank(s, delta, capk, &tail);
     if (m >= k) {
@@ -450,8 +472,8 @@ void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_repo
       copy_d2d(ctx, x->core[c], U, (size_t)m * kk);
     }
     // C_{c+1} <- carry H(C_{c+1})
-    zgemm(ctx, OPN, OPN, kk, n * rr, k, Z(1), carry, kk, 0, x->core[c + 1], k, 0, Z(0), tmp, kk, 0);
-    copy_d2d(ctx, x->core[c + 1], tmp, (size_t)kk * n * rr);
+    zgemm(ctx, OPN, OPN, kk, n1 * rr, k, Z(1), carry, kk, 0, x->core[c + 1], k, 0, Z(0), tmp, kk, 0);
+    copy_d2d(ctx, x->core[c + 1], tmp, (size_t)kk * n1 * rr);
     r[c + 1] = kk;
     if (rep) {
       rep->tail[c] = tail;
@@ -474,6 +496,7 @@ void round_tensor(tt_ctx* ctx, tt_tensor* x, double eps, int rmax, tt_round_repo
 // --------------------------------------------------------- operator apply
 void check_same_shape(const tt_op* op, const tt_tensor* x) {
   require(op->d == x->d && op->n == x->n, TT_ESHAPE, "operator and tensor shapes differ");
+  require(x->dtype == TT_C128, TT_EINVAL, "internal: operator calls need complex-double storage");
 }
 
 void apply_exact(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y) {
@@ -695,10 +718,12 @@ void apply_any(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, i
 // ------------------------------------------------------------------ sums
 void sum_tensors(tt_ctx* ctx, int nterms, const zc* coef, const tt_tensor* const* xs, tt_tensor* z) {
   require(nterms >= 1 && nterms <= 8, TT_EINVAL, "tt_sum: 1..8 terms supported");
-  const int d = z->d, n = z->n;
+  const int d = z->d;
+  require(z->dtype == TT_C128, TT_EINVAL, "internal: sums need complex-double storage");
   std::vector<int> rk(d + 1, 0);
   for (int t = 0; t < nterms; ++t) {
-    require(xs[t] && xs[t]->d == d && xs[t]->n == n, TT_ESHAPE, "tt_sum: shape mismatch");
+    require(xs[t] && xs[t]->d == d && xs[t]->nk == z->nk, TT_ESHAPE, "tt_sum: shape mismatch");
+    require(xs[t]->dtype == TT_C128, TT_EINVAL, "internal: sums need complex-double storage");
     require(xs[t] != z, TT_EINVAL, "tt_sum: output aliases an input");
   }
   rk[0] = rk[d] = 1;
@@ -715,49 +740,72 @@ void sum_tensors(tt_ctx* ctx, int nterms, const zc* coef, const tt_tensor* const
       r1s[t] = xs[t]->rank[k + 1];
     }
     const int kind = (d == 1) ? 3 : (k == 0 ? 0 : (k == d - 1 ? 2 : 1));
-    concat_core(ctx, nterms, src.data(), r0s.data(), r1s.data(), coef, kind, n, z->core[k], rk[k], rk[k + 1]);
+    concat_core(ctx, nterms, src.data(), r0s.data(), r1s.data(), coef, kind, z->nk[k], z->core[k], rk[k], rk[k + 1]);
   }
   z->rank = rk;
   z->orth = TT_ORTH_NONE;
 }
 
-tt_tensor* make_tensor(tt_ctx* ctx, int d, int n, const std::vector<int>& cap) {
+tt_tensor* make_tensor_nk(tt_ctx* ctx, int d, const std::vector<int>& nk, const std::vector<int>& cap,
+                          int dtype = TT_C128) {
   require(d >= 1 && d <= TT_MAX_D, TT_EINVAL, "tensor dimension must be in 1..128");
-  require(n >= 4, TT_EINVAL, "mode size must be at least 4");
+  require((int)nk.size() == d, TT_EINVAL, "one mode size per mode");
+  for (int v : nk) require(v >= 4, TT_EINVAL, "mode size must be at least 4");
+  require(dtype == TT_C128 || dtype == TT_C64, TT_EINVAL, "unknown storage type");
   require((int)cap.size() == d + 1 && cap[0] == 1 && cap[d] == 1, TT_EINVAL, "rank capacities must start and end with 1");
   for (int c : cap) require(c >= 1, TT_EINVAL, "rank capacities must be positive");
   tt_tensor* t = new tt_tensor;
   t->ctx = ctx;
+  t->release = ctx->releaser();
   t->d = d;
-  t->n = n;
+  t->nk = nk;
+  t->n = nk[0];
+  for (int v : nk)
+    if (v != nk[0]) t->n = 0;
+  t->dtype = dtype;
   t->cap = cap;
   t->rank.assign(d + 1, 1);
   t->core.assign(d, nullptr);
   for (int k = 0; k < d; ++k) {
-    const size_t bytes = sizeof(zc) * t->cap_elems(k);
-    if (hipMalloc(&t->core[k], bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      for (int j = 0; j < k; ++j) (void)hipFree(t->core[j]);
+    // whole complex doubles (a complex-float core of odd length gets one
+    // spare entry), so the clear below stays inside the block
+    const size_t bytes = (t->esize() * t->cap_elems(k) + sizeof(zc) - 1) / sizeof(zc) * sizeof(zc);
+    t->core[k] = (zc*)ctx->dev_alloc(bytes);
+    if (!t->core[k]) {
+      for (int j = 0; j < k; ++j) ctx->dev_free(t->core[j]);
       delete t;
       fail(TT_ENOMEM, "tensor core allocation failed");
     }
-    TTF_HIP(hipMemsetAsync(t->core[k], 0, bytes, ctx->stream));
+    fill_zero(ctx, t->core[k], (long)(bytes / sizeof(zc)));
   }
   return t;
 }
 
+tt_tensor* make_tensor(tt_ctx* ctx, int d, int n, const std::vector<int>& cap) {
+  return make_tensor_nk(ctx, d, std::vector<int>(std::max(d, 0), n), cap);
+}
+
 void free_tensor(tt_tensor* t) {
   if (!t) return;
-  for (auto p : t->core)
-    if (p) (void)hipFree(p);
+  for (auto p : t->core) t->release(p);
   delete t;
 }
 
 void copy_tensor(tt_ctx* ctx, const tt_tensor* src, tt_tensor* dst) {
-  require(src->d == dst->d && src->n == dst->n, TT_ESHAPE, "tt_tensor_copy: shape mismatch");
+  require(src->d == dst->d && src->nk == dst->nk, TT_ESHAPE, "tt_tensor_copy: shape mismatch");
   for (int k = 0; k <= src->d; ++k) require(src->rank[k] <= dst->cap[k], TT_ECAPACITY, "tt_tensor_copy: capacity too small");
   if (src == dst) return;
-  for (int k = 0; k < src->d; ++k) copy_d2d(ctx, dst->core[k], src->core[k], src->elems(k));
+  for (int k = 0; k < src->d; ++k) {
+    const long e = (long)src->elems(k);
+    if (src->dtype == dst->dtype) {
+      if (e > 0 && dst->core[k] != src->core[k])
+        TTF_HIP(hipMemcpyAsync(dst->core[k], src->core[k], src->esize() * e, hipMemcpyDeviceToDevice, ctx->stream));
+    } else if (src->dtype == TT_C64) {
+      widen_c64(ctx, src->core[k], dst->core[k], e);
+    } else {
+      narrow_c128(ctx, src->core[k], dst->core[k], e);
+    }
+  }
   dst->rank = src->rank;
   dst->orth = src->orth;
 }
@@ -799,12 +847,13 @@ std::map<std::pair<tt_ctx*, std::string>, tt_tensor*>& pool_cache() {
   return c;
 }
 
-tt_tensor* pooled(tt_ctx* ctx, const std::string& name, int d, int n, const std::vector<int>& cap) {
+tt_tensor* pooled_nk(tt_ctx* ctx, const std::string& name, int d, const std::vector<int>& nk,
+                     const std::vector<int>& cap, int dtype = TT_C128) {
   tt_tensor*& t = [&]() -> tt_tensor*& {
     std::lock_guard<std::mutex> lock(cache_mutex());
     return pool_cache()[{ctx, name}];
   }();
-  bool ok = t && t->d == d && t->n == n;
+  bool ok = t && t->d == d && t->nk == nk && t->dtype == dtype;
   for (int k = 0; ok && k <= d; ++k) ok = t->cap[k] >= cap[k];
   if (!ok) {
     if (t) {
@@ -812,9 +861,35 @@ tt_tensor* pooled(tt_ctx* ctx, const std::string& name, int d, int n, const std:
       free_tensor(t);
     }
     t = nullptr;
-    t = make_tensor(ctx, d, n, cap);
+    t = make_tensor_nk(ctx, d, nk, cap, dtype);
   }
   return t;
+}
+
+tt_tensor* pooled(tt_ctx* ctx, const std::string& name, int d, int n, const std::vector<int>& cap) {
+  return pooled_nk(ctx, name, d, std::vector<int>(d, n), cap);
+}
+
+// A complex-double working copy of a C64 tensor for the length of one call
+// (the tensor itself when it is stored as complex double); `load` copies
+// its content in.  `narrow_back` stores a working copy's result into the
+// C64 tensor it stands for.
+tt_tensor* widened(tt_ctx* ctx, const tt_tensor* x, const char* slot, bool load = true) {
+  if (x->dtype == TT_C128) return const_cast<tt_tensor*>(x);
+  tt_tensor* w = pooled_nk(ctx, std::string("c64:") + slot, x->d, x->nk, x->cap);
+  if (load) {
+    copy_tensor(ctx, x, w);
+    w->rank = x->rank;
+    w->orth = x->orth;
+  }
+  return w;
+}
+
+void narrow_back(tt_ctx* ctx, const tt_tensor* w, tt_tensor* x) {
+  if (w == x) return;
+  copy_tensor(ctx, w, x);
+  x->rank = w->rank;
+  x->orth = w->orth;
 }
 
 // identity operators (randomised rounding), built once per context and shape
@@ -873,9 +948,14 @@ void drop_ctx_caches(tt_ctx* ctx) {
 void upload_op(tt_ctx* ctx, tt_op* op) {
   const int d = op->d, n = op->n;
   op->ctx = ctx;
-  TTF_HIP(hipMalloc(&op->d_tap_ptr, sizeof(int) * op->tap_ptr.size()));
-  TTF_HIP(hipMalloc(&op->d_tap_col, sizeof(int) * std::max<size_t>(1, op->tap_col.size())));
-  TTF_HIP(hipMalloc(&op->d_tap_w, sizeof(double) * std::max<size_t>(1, op->tap_w.size())));
+  op->release = ctx->releaser();
+  auto dalloc = [ctx](void** dst, size_t bytes) {
+    *dst = ctx->dev_alloc(bytes);
+    if (!*dst) fail(TT_ENOMEM, "operator upload: device allocation failed");
+  };
+  dalloc((void**)&op->d_tap_ptr, sizeof(int) * op->tap_ptr.size());
+  dalloc((void**)&op->d_tap_col, sizeof(int) * std::max<size_t>(1, op->tap_col.size()));
+  dalloc((void**)&op->d_tap_w, sizeof(double) * std::max<size_t>(1, op->tap_w.size()));
   TTF_HIP(hipMemcpy(op->d_tap_ptr, op->tap_ptr.data(), sizeof(int) * op->tap_ptr.size(), hipMemcpyHostToDevice));
   TTF_HIP(hipMemcpy(op->d_tap_col, op->tap_col.data(), sizeof(int) * op->tap_col.size(), hipMemcpyHostToDevice));
   TTF_HIP(hipMemcpy(op->d_tap_w, op->tap_w.data(), sizeof(double) * op->tap_w.size(), hipMemcpyHostToDevice));
@@ -910,7 +990,7 @@ void upload_op(tt_ctx* ctx, tt_op* op) {
     auto& sd = op->dev[s];
     sd.nblocks = (int)blocks.size();
     auto up = [&](void** dst, const void* src, size_t bytes) {
-      TTF_HIP(hipMalloc(dst, std::max<size_t>(bytes, 16)));
+      dalloc(dst, std::max<size_t>(bytes, 16));
       if (bytes) TTF_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
     };
     up((void**)&sd.in_ptr, inp.data(), sizeof(int) * inp.size());
@@ -925,16 +1005,17 @@ void upload_op(tt_ctx* ctx, tt_op* op) {
 void free_op(tt_op* op) {
   if (!op) return;
   if (op->ctx) {
-    (void)hipFree(op->d_tap_ptr);
-    (void)hipFree(op->d_tap_col);
-    (void)hipFree(op->d_tap_w);
+    const ttf::DevFree& f = op->release;
+    f(op->d_tap_ptr);
+    f(op->d_tap_col);
+    f(op->d_tap_w);
     for (auto& sd : op->dev) {
-      (void)hipFree(sd.in_ptr);
-      (void)hipFree(sd.out_ptr);
-      (void)hipFree(sd.in_ent);
-      (void)hipFree(sd.out_ent);
-      (void)hipFree(sd.blocks);
-      (void)hipFree(sd.bops);
+      f(sd.in_ptr);
+      f(sd.out_ptr);
+      f(sd.in_ent);
+      f(sd.out_ent);
+      f(sd.blocks);
+      f(sd.bops);
     }
   }
   delete op;
@@ -945,11 +1026,12 @@ void free_op(tt_op* op) {
 // =================================================================== ABI
 extern "C" {
 
-int tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
+int tt_ctx_create(int device, void* hip_stream, const tt_allocator* alloc, tt_ctx** out) {
   tt_ctx* ctx = nullptr;
   ABI_TRY
   require(out != nullptr, TT_EINVAL, "tt_ctx_create: out is NULL");
   *out = nullptr;
+  require(!alloc || (alloc->alloc && alloc->free), TT_EINVAL, "tt_ctx_create: allocator without alloc or free");
   int ndev = 0;
   TTF_HIP(hipGetDeviceCount(&ndev));
   require(device >= 0 && device < ndev, TT_EINVAL, "tt_ctx_create: no such device");
@@ -957,6 +1039,10 @@ int tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
   noalloc_scratch_init(device);
   ctx = new tt_ctx;
   ctx->device = device;
+  if (alloc) {
+    ctx->allocator = *alloc;
+    ctx->has_allocator = true;
+  }
   if (hip_stream) {
     ctx->stream = (hipStream_t)hip_stream;
   } else {
@@ -980,8 +1066,7 @@ int tt_ctx_destroy(tt_ctx* ctx) {
   if (!ctx) return TT_EINVAL;
   (void)hipStreamSynchronize(ctx->stream);
   drop_ctx_caches(ctx);
-  for (auto& kv : ctx->ws)
-    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto& kv : ctx->ws) ctx->dev_free(kv.second.p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   for (auto& p : ctx->pending) {
     (void)hipEventDestroy(p.a);
@@ -1106,12 +1191,22 @@ int tt_ctx_dump_stats(tt_ctx* ctx, char* buf, long cap) {
   ABI_CATCH(ctx)
 }
 
-int tt_tensor_create(tt_ctx* ctx, int d, int n, const int* rank_cap, tt_tensor** out) {
-  if (!ctx || !rank_cap || !out) return TT_EINVAL;
+int tt_tensor_create(tt_ctx* ctx, int d, const int* n, const int* rank_cap, tt_dtype dtype, tt_tensor** out) {
+  if (!ctx || !n || !rank_cap || !out) return TT_EINVAL;
   ABI_TRY
-  *out = make_tensor(ctx, d, n, std::vector<int>(rank_cap, rank_cap + d + 1));
+  *out = nullptr;
+  require(d >= 1 && d <= TT_MAX_D, TT_EINVAL, "tensor dimension must be in 1..128");
+  *out = make_tensor_nk(ctx, d, std::vector<int>(n, n + d), std::vector<int>(rank_cap, rank_cap + d + 1), (int)dtype);
   return TT_OK;
   ABI_CATCH(ctx)
+}
+
+int tt_tensor_get_modes(const tt_tensor* t, int* n, int* dtype) {
+  if (!t) return TT_EINVAL;
+  if (n)
+    for (int k = 0; k < t->d; ++k) n[k] = t->nk[k];
+  if (dtype) *dtype = t->dtype;
+  return TT_OK;
 }
 
 int tt_tensor_destroy(tt_tensor* t) {
@@ -1130,8 +1225,15 @@ int tt_tensor_set_cores(tt_tensor* t, const int* ranks, const double* const* cor
   TTF_HIP(hipStreamSynchronize(ctx->stream));
   for (int k = 0; k < t->d; ++k) {
     require(cores[k] != nullptr, TT_EINVAL, "null core pointer");
-    const size_t bytes = sizeof(zc) * (size_t)ranks[k] * t->n * ranks[k + 1];
-    TTF_HIP(hipMemcpy(t->core[k], cores[k], bytes, hipMemcpyHostToDevice));
+    const size_t elems = (size_t)ranks[k] * t->nk[k] * ranks[k + 1];
+    if (t->dtype == TT_C128) {
+      TTF_HIP(hipMemcpy(t->core[k], cores[k], sizeof(zc) * elems, hipMemcpyHostToDevice));
+    } else {
+      zc* stage = (zc*)ctx->get_ws("c64_stage", sizeof(zc) * elems);
+      TTF_HIP(hipMemcpy(stage, cores[k], sizeof(zc) * elems, hipMemcpyHostToDevice));
+      narrow_c128(ctx, stage, t->core[k], (long)elems);
+      TTF_HIP(hipStreamSynchronize(ctx->stream));
+    }
   }
   t->rank.assign(ranks, ranks + t->d + 1);
   t->orth = TT_ORTH_NONE;
@@ -1152,7 +1254,14 @@ int tt_tensor_get_cores(const tt_tensor* t, double* const* cores) {
   TTF_HIP(hipStreamSynchronize(ctx->stream));
   for (int k = 0; k < t->d; ++k) {
     require(cores[k] != nullptr, TT_EINVAL, "null core pointer");
-    TTF_HIP(hipMemcpy(cores[k], t->core[k], sizeof(zc) * t->elems(k), hipMemcpyDeviceToHost));
+    if (t->dtype == TT_C128) {
+      TTF_HIP(hipMemcpy(cores[k], t->core[k], sizeof(zc) * t->elems(k), hipMemcpyDeviceToHost));
+    } else {
+      zc* stage = (zc*)ctx->get_ws("c64_stage", sizeof(zc) * t->elems(k));
+      widen_c64(ctx, t->core[k], stage, (long)t->elems(k));
+      TTF_HIP(hipStreamSynchronize(ctx->stream));
+      TTF_HIP(hipMemcpy(cores[k], stage, sizeof(zc) * t->elems(k), hipMemcpyDeviceToHost));
+    }
   }
   return TT_OK;
   ABI_CATCH(ctx)
@@ -1172,9 +1281,11 @@ int tt_tensor_set_gaussian(tt_ctx* ctx, tt_tensor* t, const double* mu, const do
   if (!ctx || !t || !mu || !sigma) return TT_EINVAL;
   ABI_TRY
   require(L > 0, TT_EINVAL, "L must be positive");
-  for (int k = 0; k < t->d; ++k) gaussian_factor(ctx, t->core[k], t->n, L, mu[k], sigma[k]);
-  t->rank.assign(t->d + 1, 1);
-  t->orth = TT_ORTH_NONE;
+  tt_tensor* w = widened(ctx, t, "t", false);
+  for (int k = 0; k < t->d; ++k) gaussian_factor(ctx, w->core[k], t->nk[k], L, mu[k], sigma[k]);
+  w->rank.assign(t->d + 1, 1);
+  w->orth = TT_ORTH_NONE;
+  narrow_back(ctx, w, t);
   return TT_OK;
   ABI_CATCH(ctx)
 }
@@ -1183,9 +1294,11 @@ int tt_tensor_set_cdf_gaussian(tt_ctx* ctx, tt_tensor* t, double sigma, double b
   if (!ctx || !t) return TT_EINVAL;
   ABI_TRY
   require(box > 0 && sigma > 0, TT_EINVAL, "need box > 0 and sigma > 0");
-  for (int k = 0; k < t->d; ++k) cdf_gaussian_factor(ctx, t->core[k], t->n, box, sigma);
-  t->rank.assign(t->d + 1, 1);
-  t->orth = TT_ORTH_NONE;
+  tt_tensor* w = widened(ctx, t, "t", false);
+  for (int k = 0; k < t->d; ++k) cdf_gaussian_factor(ctx, w->core[k], t->nk[k], box, sigma);
+  w->rank.assign(t->d + 1, 1);
+  w->orth = TT_ORTH_NONE;
+  narrow_back(ctx, w, t);
   return TT_OK;
   ABI_CATCH(ctx)
 }
@@ -1334,7 +1447,11 @@ int tt_apply(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, con
   if (!ctx || !op || !x || !y || !opts) return TT_EINVAL;
   ABI_TRY
   require(opts->size == (int)sizeof(tt_apply_opts), TT_EINVAL, "tt_apply_opts.size mismatch");
-  apply_any(ctx, op, x, y, opts->mode, opts->sketch_rank, opts->seed, opts->precision, opts->power);
+  require(x != y, TT_EINVAL, "tt_apply: y must not alias x");
+  tt_tensor* xw = widened(ctx, x, "x");
+  tt_tensor* yw = widened(ctx, y, "y", false);
+  apply_any(ctx, op, xw, yw, opts->mode, opts->sketch_rank, opts->seed, opts->precision, opts->power);
+  narrow_back(ctx, yw, y);
   return TT_OK;
   ABI_CATCH(ctx)
 }
@@ -1343,9 +1460,12 @@ int tt_axpy(tt_ctx* ctx, double ar, double ai, const tt_tensor* x, double br, do
             tt_tensor* z) {
   if (!ctx || !x || !y || !z) return TT_EINVAL;
   ABI_TRY
-  const tt_tensor* xs[2] = {x, y};
+  require(z != x && z != y, TT_EINVAL, "tt_axpy: z aliases an input");
+  const tt_tensor* xs[2] = {widened(ctx, x, "s0"), widened(ctx, y, "s1")};
   const zc coef[2] = {Z(ar, ai), Z(br, bi)};
-  sum_tensors(ctx, 2, coef, xs, z);
+  tt_tensor* zw = widened(ctx, z, "z", false);
+  sum_tensors(ctx, 2, coef, xs, zw);
+  narrow_back(ctx, zw, z);
   return TT_OK;
   ABI_CATCH(ctx)
 }
@@ -1355,17 +1475,26 @@ int tt_sum(tt_ctx* ctx, int nterms, const double* coef, const tt_tensor* const* 
   ABI_TRY
   require(nterms >= 1 && nterms <= 8, TT_EINVAL, "tt_sum: 1..8 terms");
   std::vector<zc> c(nterms);
-  for (int t = 0; t < nterms; ++t) c[t] = Z(coef[2 * t], coef[2 * t + 1]);
-  sum_tensors(ctx, nterms, c.data(), xs, z);
+  std::vector<const tt_tensor*> xw(nterms);
+  for (int t = 0; t < nterms; ++t) {
+    c[t] = Z(coef[2 * t], coef[2 * t + 1]);
+    require(xs[t] && xs[t] != z, TT_EINVAL, "tt_sum: null input or output aliasing an input");
+    xw[t] = widened(ctx, xs[t], ("s" + std::to_string(t)).c_str());
+  }
+  tt_tensor* zw = widened(ctx, z, "z", false);
+  sum_tensors(ctx, nterms, c.data(), xw.data(), zw);
+  narrow_back(ctx, zw, z);
   return TT_OK;
   ABI_CATCH(ctx)
 }
 
-int tt_round(tt_ctx* ctx, tt_tensor* x, double eps_rel, int rmax, tt_round_report* rep) {
+int tt_round(tt_ctx* ctx, tt_tensor* x, double eps_rel, const int* rmax, tt_round_report* rep) {
   if (!ctx || !x) return TT_EINVAL;
   ABI_TRY
   require(eps_rel >= 0, TT_EINVAL, "tt_round: eps must be >= 0");
-  round_tensor(ctx, x, eps_rel, rmax, rep);
+  tt_tensor* xw = widened(ctx, x, "x");
+  round_tensor(ctx, xw, eps_rel, 0, rep, rmax);
+  narrow_back(ctx, xw, x);
   return TT_OK;
   ABI_CATCH(ctx)
 }
@@ -1373,12 +1502,13 @@ int tt_round(tt_ctx* ctx, tt_tensor* x, double eps_rel, int rmax, tt_round_repor
 // <x, y> = sum conj(x) y by left-to-right contraction:
 // W_{k+1} = V(X_k)^H (W_k H(Y_k)), W_0 = 1 (App. A.1 arithmetic)
 zc dot_tensors(tt_ctx* ctx, const tt_tensor* x, const tt_tensor* y) {
-  require(x->d == y->d && x->n == y->n, TT_ESHAPE, "tt_dot: shape mismatch");
-  const int d = x->d, n = x->n;
+  require(x->d == y->d && x->nk == y->nk, TT_ESHAPE, "tt_dot: shape mismatch");
+  require(x->dtype == TT_C128 && y->dtype == TT_C128, TT_EINVAL, "internal: dot needs complex-double storage");
+  const int d = x->d;
   size_t wmax = 1, tmax = 1;
   for (int k = 0; k < d; ++k) {
     wmax = std::max(wmax, (size_t)x->rank[k + 1] * y->rank[k + 1]);
-    tmax = std::max(tmax, (size_t)x->rank[k] * n * y->rank[k + 1]);
+    tmax = std::max(tmax, (size_t)x->rank[k] * x->nk[k] * y->rank[k + 1]);
   }
   zc* W = (zc*)ctx->get_ws("dot_W", sizeof(zc) * wmax);
   zc* W2 = (zc*)ctx->get_ws("dot_W2", sizeof(zc) * wmax);
@@ -1388,6 +1518,7 @@ zc dot_tensors(tt_ctx* ctx, const tt_tensor* x, const tt_tensor* y) {
   TTF_HIP(hipMemcpyAsync(W, h, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
   for (int k = 0; k < d; ++k) {
     const int rx0 = x->rank[k], ry0 = y->rank[k], rx1 = x->rank[k + 1], ry1 = y->rank[k + 1];
+    const int n = x->nk[k];
     // T (rx0 x n ry1) = W (rx0 x ry0) H(Y_k)
     zgemm(ctx, OPN, OPN, rx0, n * ry1, ry0, Z(1), W, rx0, 0, y->core[k], ry0, 0, Z(0), T, rx0, 0);
     // W' (rx1 x ry1) = V(X_k)^H T, T read as (rx0 n) x ry1
@@ -1405,7 +1536,7 @@ zc dot_tensors(tt_ctx* ctx, const tt_tensor* x, const tt_tensor* y) {
 double tensor_norm(tt_ctx* ctx, const tt_tensor* x) {
   if (x->orth == TT_ORTH_LEFT) return core_norm(ctx, x, x->d - 1);
   if (x->orth == TT_ORTH_RIGHT || x->d == 1) return core_norm(ctx, x, 0);
-  tt_tensor* tmp = pooled(ctx, "norm_tmp", x->d, x->n, x->rank);
+  tt_tensor* tmp = pooled_nk(ctx, "norm_tmp", x->d, x->nk, x->rank);
   copy_tensor(ctx, x, tmp);
   phase1_right_orth(ctx, tmp);
   return core_norm(ctx, tmp, 0);
@@ -1419,7 +1550,7 @@ std::vector<int> interior_caps(int d, int c) {
 
 // t <- the zero tensor (all ranks 1)
 void set_zero(tt_ctx* ctx, tt_tensor* t) {
-  for (int k = 0; k < t->d; ++k) fill_zero(ctx, t->core[k], t->n);
+  for (int k = 0; k < t->d; ++k) fill_zero(ctx, t->core[k], t->nk[k]);
   t->rank.assign(t->d + 1, 1);
   t->orth = TT_ORTH_NONE;
 }
@@ -1618,6 +1749,12 @@ double sum_rel_error(tt_ctx* ctx, int npieces, const zc* coef, const tt_tensor* 
 int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step_opts* opts, tt_step_report* rep) {
   if (!ctx || !op || !f || !opts) return TT_EINVAL;
   ABI_TRY
+  if (f->dtype != TT_C128) {
+    tt_tensor* fw = widened(ctx, f, "f");
+    const int rc = tt_step(ctx, op, fw, dt, opts, rep);
+    if (rc == TT_OK) narrow_back(ctx, fw, f);
+    return rc;
+  }
   require(opts->size == (int)sizeof(tt_step_opts), TT_EINVAL, "tt_step_opts.size mismatch");
   require(opts->rmax >= 1, TT_EINVAL, "tt_step: rmax must be >= 1");
   require(opts->precision == TT_PREC_FP64 || opts->precision == TT_PREC_BF16X3 || opts->precision == TT_PREC_FP16X3 ||
@@ -1868,7 +2005,7 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
 int tt_dot(tt_ctx* ctx, const tt_tensor* x, const tt_tensor* y, double* out) {
   if (!ctx || !x || !y || !out) return TT_EINVAL;
   ABI_TRY
-  const zc v = dot_tensors(ctx, x, y);
+  const zc v = dot_tensors(ctx, widened(ctx, x, "x"), widened(ctx, y, "y"));
   out[0] = v.x;
   out[1] = v.y;
   return TT_OK;
@@ -1880,10 +2017,17 @@ int tt_solve_shifted(tt_ctx* ctx, const tt_op* op, double c, const tt_tensor* b,
   if (!ctx || !op || !b || !x || !opts) return TT_EINVAL;
   ABI_TRY
   require(opts->size == (int)sizeof(tt_solve_opts), TT_EINVAL, "tt_solve_opts.size mismatch");
+  require(b != x, TT_EINVAL, "tt_solve_shifted: x aliases b");
+  if (b->dtype != TT_C128 || x->dtype != TT_C128) {
+    tt_tensor* bw = widened(ctx, b, "b");
+    tt_tensor* xw = widened(ctx, x, "x");
+    const int rc = tt_solve_shifted(ctx, op, c, bw, xw, opts, rep);
+    if (rc == TT_OK) narrow_back(ctx, xw, x);
+    return rc;
+  }
   check_solve_opts(*opts);
   check_same_shape(op, b);
   check_same_shape(op, x);
-  require(b != x, TT_EINVAL, "tt_solve_shifted: x aliases b");
   tt_solve_opts o = *opts;
   // the returned solution must fit x
   for (int k = 1; k < x->d; ++k) o.rmax = std::min(o.rmax, x->cap[k]);
@@ -1896,6 +2040,44 @@ int tt_solve_shifted(tt_ctx* ctx, const tt_op* op, double c, const tt_tensor* b,
     rep->pad = 0;
   }
   return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_step_reserve(tt_ctx* ctx, const tt_op* op, const tt_tensor* f, double dt, const tt_step_opts* opts) {
+  if (!ctx || !op || !f || !opts) return TT_EINVAL;
+  ABI_TRY
+  check_same_shape(op, f->dtype == TT_C128 ? f : widened(ctx, f, "f"));
+  // steps on a tensor of f's shape and storage with every interior rank at
+  // its capacity (random cores): the largest shapes a step can meet.  One
+  // step per starting form of the QR factorisations (the later forms are
+  // fallbacks that a step takes only on ill-conditioned input, with
+  // workspaces of their own), and the largest split-K workspace.
+  ctx->get_ws("gemm_splitk", sizeof(zc) * SPLITK_WS_ELEMS);
+  tt_tensor* g = pooled_nk(ctx, "reserve", f->d, f->nk, f->cap);
+  tt_tensor* gs = f->dtype == TT_C128 ? g : pooled_nk(ctx, "reserve_c64", f->d, f->nk, f->cap, f->dtype);
+  const int saved_level = ctx->qr_min_level;
+  int rc = TT_OK;
+  try {
+    for (int level = saved_level; level <= 2 && rc == TT_OK; ++level) {
+      for (int k = 0; k < f->d; ++k) {
+        g->rank[k] = f->cap[k];
+        sketch_core(ctx, g->core[k], (long)g->cap_elems(k), 0x5EEDu + (uint64_t)k, k,
+                    1.0 / std::sqrt(2.0 * f->nk[k] * f->cap[k]));
+      }
+      g->rank[f->d] = 1;
+      g->orth = TT_ORTH_NONE;
+      if (gs != g) narrow_back(ctx, g, gs);
+      ctx->qr_min_level = level;
+      tt_step_report rep;
+      rc = tt_step(ctx, op, gs, dt, opts, &rep);
+    }
+  } catch (...) {
+    ctx->qr_min_level = saved_level;
+    throw;
+  }
+  ctx->qr_min_level = saved_level;
+  ctx->sync();
+  return rc;
   ABI_CATCH(ctx)
 }
 
@@ -1994,11 +2176,14 @@ int tt_round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint
                         double* rel_err) {
   if (!ctx || !x || !y || !widths) return TT_EINVAL;
   ABI_TRY
-  require(x->d == y->d && x->n == y->n, TT_ESHAPE, "tt_round_randomized: shape mismatch");
+  require(x->d == y->d && x->nk == y->nk && x->n > 0, TT_ESHAPE,
+          "tt_round_randomized: shape mismatch (equal mode sizes needed)");
   require(x != y, TT_EINVAL, "tt_round_randomized: y aliases x");
   for (int k = 1; k < x->d; ++k)
     require(widths[k] >= 1 && widths[k] <= y->cap[k], TT_ECAPACITY, "tt_round_randomized: width beyond capacity");
-  const double e = round_randomized(ctx, x, widths, seed, y);
+  tt_tensor* yw = widened(ctx, y, "y", false);
+  const double e = round_randomized(ctx, widened(ctx, x, "x"), widths, seed, yw);
+  narrow_back(ctx, yw, y);
   if (rel_err) *rel_err = e;
   return TT_OK;
   ABI_CATCH(ctx)
@@ -2008,16 +2193,9 @@ int tt_eval(tt_ctx* ctx, const tt_tensor* x, const int32_t* idx, int64_t npts, d
   if (!ctx || !x || (npts > 0 && (!idx || !out))) return TT_EINVAL;
   ABI_TRY
   for (int k = 0; k <= x->d; ++k) require(x->rank[k] <= 512, TT_EINVAL, "tt_eval: ranks above 512 unsupported");
-  const int d = x->d;
-  std::vector<const zc*> ptrs(x->core.begin(), x->core.end());
-  std::vector<int> ranks(x->rank.begin(), x->rank.end());
-  char* meta = (char*)ctx->get_ws("eval_meta", sizeof(void*) * d + sizeof(int) * (d + 1) + 64);
-  TTF_HIP(hipMemcpyAsync(meta, ptrs.data(), sizeof(void*) * d, hipMemcpyHostToDevice, ctx->stream));
-  TTF_HIP(hipMemcpyAsync(meta + sizeof(void*) * d, ranks.data(), sizeof(int) * (d + 1), hipMemcpyHostToDevice,
-                         ctx->stream));
-  // pageable sources: wait so the host vectors may go out of scope
-  TTF_HIP(hipStreamSynchronize(ctx->stream));
-  tt_eval_kernel(ctx, d, x->n, (const zc* const*)meta, (const int*)(meta + sizeof(void*) * d), idx, npts, (zc*)out);
+  const tt_tensor* xw = widened(ctx, x, "x");
+  // the core table travels as kernel arguments: nothing to copy or wait for
+  tt_eval_kernel(ctx, xw->d, xw->nk.data(), xw->core.data(), xw->rank.data(), idx, npts, (zc*)out);
   return TT_OK;
   ABI_CATCH(ctx)
 }
@@ -2083,7 +2261,7 @@ int tt_gemm_autotune(tt_ctx* ctx, int precision, int opA, int opB, int M, int N,
   auto release = [&]() {
     (void)hipStreamSynchronize(ctx->stream);
     for (zc*& b : bufs)
-      if (b) (void)hipFree(b), b = nullptr;
+      if (b) ctx->dev_free(b), b = nullptr;
     for (hipEvent_t& e : ev)
       if (e) (void)hipEventDestroy(e), e = nullptr;
   };
@@ -2095,11 +2273,10 @@ int tt_gemm_autotune(tt_ctx* ctx, int precision, int opA, int opB, int M, int N,
     require(na <= (1ull << 28) && nb <= (1ull << 28) && nc <= (1ull << 28), TT_EINVAL,
             "tt_gemm_autotune: operands above 2^28 elements");
     const size_t ns[3] = {na, nb, nc};
-    for (int i = 0; i < 3; ++i)
-      if (hipMalloc((void**)&bufs[i], sizeof(zc) * ns[i]) != hipSuccess) {
-        (void)hipGetLastError();
-        fail(TT_ENOMEM, "tt_gemm_autotune: allocation failed");
-      }
+    for (int i = 0; i < 3; ++i) {
+      bufs[i] = (zc*)ctx->dev_alloc(sizeof(zc) * ns[i]);
+      if (!bufs[i]) fail(TT_ENOMEM, "tt_gemm_autotune: allocation failed");
+    }
     sketch_core(ctx, bufs[0], (long)na, 0x5EEDull, 1, 1.0);
     sketch_core(ctx, bufs[1], (long)nb, 0x5EEDull, 2, 1.0);
     fill_zero(ctx, bufs[2], (long)nc);
@@ -2192,11 +2369,13 @@ int tt_gemm_table_clear(void) {
 int tt_norm(tt_ctx* ctx, const tt_tensor* x, double* out) {
   if (!ctx || !x || !out) return TT_EINVAL;
   ABI_TRY
+  std::string key = shape_key(x->d, x->n, x->cap, -1);
+  for (int v : x->nk) key += ";" + std::to_string(v);
   tt_tensor*& tmp = [&]() -> tt_tensor*& {
     std::lock_guard<std::mutex> lock(cache_mutex());
-    return norm_cache()[{ctx, shape_key(x->d, x->n, x->cap, -1)}];
+    return norm_cache()[{ctx, key}];
   }();
-  if (!tmp) tmp = make_tensor(ctx, x->d, x->n, x->cap);
+  if (!tmp) tmp = make_tensor_nk(ctx, x->d, x->nk, x->cap);
   copy_tensor(ctx, x, tmp);
   if (tmp->orth != TT_ORTH_RIGHT && x->d > 1) phase1_right_orth(ctx, tmp);
   *out = core_norm(ctx, tmp, 0);
@@ -2250,6 +2429,7 @@ int tt_svd_small_noalloc(tt_ctx* ctx, int m, int k, double* B, double* U, double
 // ------------------------------------------------------ rank predictor MLP
 struct tt_mlp {
   ttf::MlpDev d;
+  ttf::DevFree release;  // returns its device memory
 };
 
 namespace {
@@ -2257,7 +2437,7 @@ void mlp_free(tt_mlp* m) {
   if (!m) return;
   for (void* ptr : {(void*)m->d.p, (void*)m->d.ph, (void*)m->d.g, (void*)m->d.m, (void*)m->d.v, (void*)m->d.act,
                     (void*)m->d.loss})
-    if (ptr) (void)hipFree(ptr);
+    m->release(ptr);
   delete m;
 }
 }  // namespace
@@ -2272,16 +2452,15 @@ int tt_mlp_create(tt_ctx* ctx, int n_in, int width, int max_batch, tt_mlp** out)
   require(n_in >= 1 && n_in <= 1024 && width >= 1 && width <= 1024 && max_batch >= 1, TT_EINVAL,
           "tt_mlp_create: n_in, width in 1..1024, max_batch >= 1");
   m = new tt_mlp;
+  m->release = ctx->releaser();
   auto& d = m->d;
   d.n_in = n_in;
   d.width = width;
   d.bcap = max_batch;
   d.nparams = width * n_in + width + width * width + width + width + 1;
   auto alloc = [&](void** p, size_t bytes) {
-    if (hipMalloc(p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      fail(TT_ENOMEM, "tt_mlp_create: allocation failed");
-    }
+    *p = ctx->dev_alloc(bytes);
+    if (!*p) fail(TT_ENOMEM, "tt_mlp_create: allocation failed");
   };
   // float arrays padded to whole complex values: they are cleared with
   // fill_zero, which writes 16-byte elements

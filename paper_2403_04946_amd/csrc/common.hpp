@@ -15,6 +15,11 @@ namespace ttf {
 
 using zc = double2;  // complex double, interleaved (re, im)
 
+// Split-K partial sums of one GEMM never take more than this many complex
+// doubles (64 MiB): the split count is lowered to fit, so one workspace of
+// this size serves every GEMM of a context.
+constexpr size_t SPLITK_WS_ELEMS = size_t(1) << 22;
+
 // ------------------------------------------------------------------ errors
 struct Error {
   int code;
@@ -58,6 +63,24 @@ struct DevBlockOp {
 }  // namespace ttf
 
 // ------------------------------------------------------------ opaque types
+namespace ttf {
+// where a block of device memory goes back to: the allocator of the
+// context that made it (kept by value, so an object may be destroyed after
+// its context) or hipFree
+struct DevFree {
+  tt_allocator a{};
+  bool has = false;
+  hipStream_t stream = nullptr;
+  void operator()(void* p) const {
+    if (!p) return;
+    if (has)
+      a.free(p, (void*)stream, a.user);
+    else
+      (void)hipFree(p);
+  }
+};
+}  // namespace ttf
+
 struct tt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -98,20 +121,40 @@ struct tt_ctx {
   int jacobi_max_sweeps = 60;   // sweep limit of every Jacobi SVD (tt_ctx_set_option)
   int qr_min_level = 0;         // most economical QR form allowed (tt_ctx_set_option)
 
+  // device memory: through the caller's allocator when one was given at
+  // creation, else hipMalloc / hipFree; dev_alloc returns null on failure
+  tt_allocator allocator{};
+  bool has_allocator = false;
+  void* dev_alloc(size_t bytes);
+  void dev_free(void* p);
+  ttf::DevFree releaser() const {
+    ttf::DevFree r;
+    r.a = allocator;
+    r.has = has_allocator;
+    r.stream = stream;
+    return r;
+  }
+
   void* get_ws(const std::string& name, size_t bytes);
   void* host_scratch(size_t bytes);
   void sync();
   void resolve_stats();
 };
 
+
 struct tt_tensor {
   tt_ctx* ctx = nullptr;
-  int d = 0, n = 0;
+  ttf::DevFree release;          // returns the cores' memory
+  int d = 0;
+  int n = 0;                     // the common mode size; 0 when the sizes differ
+  int dtype = TT_C128;           // storage of the cores (TT_C64: complex float)
+  std::vector<int> nk;           // mode sizes n_1..n_d
   std::vector<int> cap, rank;
-  std::vector<ttf::zc*> core;
+  std::vector<ttf::zc*> core;    // complex double, or complex float for TT_C64
   int orth = TT_ORTH_NONE;
-  size_t cap_elems(int k) const { return (size_t)cap[k] * n * cap[k + 1]; }
-  size_t elems(int k) const { return (size_t)rank[k] * n * rank[k + 1]; }
+  size_t cap_elems(int k) const { return (size_t)cap[k] * nk[k] * cap[k + 1]; }
+  size_t elems(int k) const { return (size_t)rank[k] * nk[k] * rank[k + 1]; }
+  size_t esize() const { return dtype == TT_C64 ? 8 : 16; }
 };
 
 struct tt_op {
@@ -130,6 +173,7 @@ struct tt_op {
   std::vector<std::vector<ttf::Entry>> site;
   // device copies (when created with a context)
   tt_ctx* ctx = nullptr;
+  ttf::DevFree release;
   int* d_tap_ptr = nullptr;
   int* d_tap_col = nullptr;
   double* d_tap_w = nullptr;
@@ -270,7 +314,9 @@ void frob_norm2(tt_ctx* ctx, const zc* x, long n, double* out_dev);  // single v
 // TT kernels
 void concat_core(tt_ctx* ctx, int nterms, const zc* const* src, const int* r0s, const int* r1s,
                  const zc* coefs, int kind, int n, zc* dst, int R0, int R1);
-void tt_eval_kernel(tt_ctx* ctx, int d, int n, const zc* const* cores, const int* ranks,
+void widen_c64(tt_ctx* ctx, const void* src, zc* dst, long n);      // complex float -> double
+void narrow_c128(tt_ctx* ctx, const zc* src, void* dst, long n);    // complex double -> float
+void tt_eval_kernel(tt_ctx* ctx, int d, const int* nk, const zc* const* cores, const int* ranks,
                     const int32_t* idx, int64_t npts, zc* out);
 void gaussian_factor(tt_ctx* ctx, zc* core, int n, double L, double mu, double sigma);
 void cdf_gaussian_factor(tt_ctx* ctx, zc* core, int n, double box, double sigma);

@@ -470,6 +470,7 @@ void zgemm_prec(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc 
       nsplit = std::max(1, std::min(c.nsplit, std::max(1, kblocks)));
     }
   }
+  nsplit = (int)std::max<size_t>(1, std::min<size_t>(nsplit, SPLITK_WS_ELEMS / std::max<size_t>(1, (size_t)M * N * batch)));
   int kchunk = ((kblocks + nsplit - 1) / nsplit) * kb;
   if (K == 0) kchunk = 0;
   nsplit = (K == 0) ? 1 : (K + kchunk - 1) / kchunk;

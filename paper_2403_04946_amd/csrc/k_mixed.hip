@@ -411,6 +411,7 @@ void zgemm_split(int fmt, tt_ctx* ctx, int opA, int opB, int M, int N, int K, zc
   int nsplit = 1;
   if (tiles < 512 && KB >= 4) nsplit = (int)std::max<long>(1, std::min<long>({(512 + tiles - 1) / tiles, KB / 2, 128}));
   if (have_tuned) nsplit = std::max(1, std::min(tuned.nsplit, std::max(1, KB)));
+  nsplit = (int)std::max<size_t>(1, std::min<size_t>(nsplit, SPLITK_WS_ELEMS / std::max<size_t>(1, (size_t)M * N * batch)));
   int kbchunk = KB > 0 ? (KB + nsplit - 1) / nsplit : 0;
   nsplit = KB > 0 ? (KB + kbchunk - 1) / kbchunk : 1;
   p.kbchunk = kbchunk;

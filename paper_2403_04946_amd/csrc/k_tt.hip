@@ -88,12 +88,15 @@ void concat_core(tt_ctx* ctx, int nterms, const zc* const* src, const int* r0s, 
 // f[i_1..i_d] = C_1[0,i_1,:] C_2[:,i_2,:] ... C_d[:,i_d,0] (App. A.1), one
 // wavefront per point, the running row vector in LDS.
 constexpr int EVAL_RMAX = 512;
+// passed by value (about 2 KB of kernel arguments): no device copy of the
+// core table, so the read-out needs no synchronisation
 struct EvalArgs {
-  const zc* const* cores;
-  const int* ranks;
+  const zc* cores[TT_MAX_D];
+  int ranks[TT_MAX_D + 1];
+  int nk[TT_MAX_D];
   const int32_t* idx;
   long npts;
-  int d, n;
+  int d;
   zc* out;
 };
 
@@ -108,15 +111,16 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
     bool bad = false;
     for (int k = 0; k < a.d; ++k) {
       const int r0 = a.ranks[k], r1 = a.ranks[k + 1];
+      const int nk = a.nk[k];
       int i = a.idx[pt * a.d + k];
-      if (i < 0 || i >= a.n) {  // out-of-range index: result is NaN
+      if (i < 0 || i >= nk) {  // out-of-range index: result is NaN
         bad = true;
         i = 0;
       }
       const zc* C = a.cores[k] + (long)r0 * i;
       for (int b = lane; b < r1; b += 64) {
         double sr = 0, si = 0;
-        const zc* col = C + (long)r0 * a.n * b;
+        const zc* col = C + (long)r0 * nk * b;
         for (int q = 0; q < r0; ++q) {
           const zc v = cur[q], c = col[q];
           sr += v.x * c.x - v.y * c.y;
@@ -136,13 +140,51 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
   }
 }
 
-void tt_eval_kernel(tt_ctx* ctx, int d, int n, const zc* const* cores, const int* ranks,
+void tt_eval_kernel(tt_ctx* ctx, int d, const int* nk, const zc* const* cores, const int* ranks,
                     const int32_t* idx, int64_t npts, zc* out) {
   if (npts <= 0) return;
-  EvalArgs a{cores, ranks, idx, (long)npts, d, n, out};
+  EvalArgs a{};
+  for (int k = 0; k < d; ++k) {
+    a.cores[k] = cores[k];
+    a.nk[k] = nk[k];
+  }
+  for (int k = 0; k <= d; ++k) a.ranks[k] = ranks[k];
+  a.idx = idx;
+  a.npts = (long)npts;
+  a.d = d;
+  a.out = out;
   const int blocks = (int)std::min<long>((npts + 3) / 4, 65536);
   KTimer kt(ctx, "eval", 0.0, 0.0);
   hipLaunchKernelGGL(eval_kernel, dim3(blocks), dim3(256), 0, ctx->stream, a);
+  TTF_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------- storage conversion
+__global__ void widen_kernel(const float2* __restrict__ src, zc* __restrict__ dst, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const float2 v = src[e];
+    dst[e] = make_double2((double)v.x, (double)v.y);
+  }
+}
+
+__global__ void narrow_kernel(const zc* __restrict__ src, float2* __restrict__ dst, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const zc v = src[e];
+    dst[e] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+void widen_c64(tt_ctx* ctx, const void* src, zc* dst, long n) {
+  if (n <= 0) return;
+  const int blocks = (int)std::min<long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(widen_kernel, dim3(blocks), dim3(256), 0, ctx->stream, (const float2*)src, dst, n);
+  TTF_HIP(hipGetLastError());
+}
+
+void narrow_c128(tt_ctx* ctx, const zc* src, void* dst, long n) {
+  if (n <= 0) return;
+  const int blocks = (int)std::min<long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(narrow_kernel, dim3(blocks), dim3(256), 0, ctx->stream, src, (float2*)dst, n);
   TTF_HIP(hipGetLastError());
 }
 

@@ -28,6 +28,9 @@ TT_STEP_IMPLICIT_EULER = 3
 TT_STEP_IMPLICIT_MIDPOINT = 4
 TT_ECAPACITY = -3
 TT_ENOCONV = -6
+TT_ENOMEM = -4
+TT_C128 = 0
+TT_C64 = 1
 TT_OPT_JACOBI_MAX_SWEEPS = 1
 TT_OPT_QR_MIN_LEVEL = 2
 ORTH = {0: "none", 1: "right", 2: "left"}
@@ -165,7 +168,7 @@ PI = ctypes.POINTER(ctypes.c_int)
 PD = ctypes.POINTER(ctypes.c_double)
 
 _SIGS = {
-    "tt_ctx_create": (I, [I, P, ctypes.POINTER(P)]),
+    "tt_ctx_create": (I, [I, P, P, ctypes.POINTER(P)]),
     "tt_ctx_destroy": (I, [P]),
     "tt_ctx_sync": (I, [P]),
     "tt_last_error": (ctypes.c_char_p, [P]),
@@ -174,7 +177,8 @@ _SIGS = {
     "tt_ctx_reset_stats": (I, [P]),
     "tt_ctx_set_option": (I, [P, I, ctypes.c_longlong]),
     "tt_ctx_get_stats": (I, [P, ctypes.c_char_p, PD, PD, PD, ctypes.POINTER(ctypes.c_longlong)]),
-    "tt_tensor_create": (I, [P, I, I, PI, ctypes.POINTER(P)]),
+    "tt_tensor_create": (I, [P, I, PI, PI, I, ctypes.POINTER(P)]),
+    "tt_tensor_get_modes": (I, [P, PI, PI]),
     "tt_tensor_destroy": (I, [P]),
     "tt_tensor_set_cores": (I, [P, PI, ctypes.POINTER(P)]),
     "tt_tensor_get_ranks": (I, [P, PI]),
@@ -194,8 +198,9 @@ _SIGS = {
     "tt_apply": (I, [P, P, P, P, ctypes.POINTER(ApplyOpts)]),
     "tt_axpy": (I, [P, D, D, P, D, D, P, P]),
     "tt_sum": (I, [P, I, PD, ctypes.POINTER(P), P]),
-    "tt_round": (I, [P, P, D, I, ctypes.POINTER(RoundReport)]),
+    "tt_round": (I, [P, P, D, PI, ctypes.POINTER(RoundReport)]),
     "tt_step": (I, [P, P, P, D, ctypes.POINTER(StepOpts), ctypes.POINTER(StepReport)]),
+    "tt_step_reserve": (I, [P, P, P, D, ctypes.POINTER(StepOpts)]),
     "tt_eval": (I, [P, P, P, ctypes.c_int64, P]),
     "tt_norm": (I, [P, P, PD]),
     "tt_mlp_create": (I, [P, I, I, I, ctypes.POINTER(P)]),
@@ -258,20 +263,73 @@ def _dp(a):
     return a.ctypes.data_as(PD)
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class AllocatorStruct(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """tt_allocator bridge to PyTorch's caching allocator: every device
+    allocation of a context comes from (and returns to) torch's pool on the
+    context's stream.  Counts its calls (``allocs``, ``frees``); ``fail``
+    makes every later allocation return NULL; ``bytes`` sums the sizes
+    allocated."""
+
+    def __init__(self, device):
+        self.device = device
+        self.allocs = 0
+        self.frees = 0
+        self.bytes = 0
+        self.fail = False
+
+        def _alloc(nbytes, stream, user):
+            import torch
+
+            if self.fail:
+                return None
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+            except Exception:  # out of memory: the library reports TT_ENOMEM
+                return None
+            self.allocs += 1
+            self.bytes += int(nbytes)
+            return p
+
+        def _free(p, stream, user):
+            import torch
+
+            torch.cuda.caching_allocator_delete(p)
+            self.frees += 1
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.struct = AllocatorStruct(self._alloc, self._free, None)
+
+
 class Context:
     """A device context.  All library work runs on one HIP stream: ``stream``
     (a torch stream or a raw hipStream_t integer) or, by default, a dedicated
-    default-priority torch stream (``self.torch_stream``)."""
+    default-priority torch stream (``self.torch_stream``).  Device memory
+    comes from ``allocator``: "torch" (the default, PyTorch's caching
+    allocator through TorchAllocator), None (hipMalloc), or an object with
+    a ``struct`` AllocatorStruct (kept alive by the context)."""
 
-    def __init__(self, device=0, stream=None):
+    def __init__(self, device=0, stream=None, allocator="torch"):
         import torch
 
         if stream is None:
             stream = torch.cuda.Stream(device=device)
         self.torch_stream = stream if hasattr(stream, "cuda_stream") else None
         handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        if allocator == "torch":
+            allocator = TorchAllocator(device)
+        self.allocator = allocator
         h = P()
-        rc = lib().tt_ctx_create(device, P(handle), ctypes.byref(h))
+        a = ctypes.byref(allocator.struct) if allocator is not None else None
+        rc = lib().tt_ctx_create(device, P(handle), a, ctypes.byref(h))
         if rc != 0:
             raise TTError(rc, "tt_ctx_create failed")
         self.h = h
@@ -335,17 +393,25 @@ class Context:
 
 
 class Tensor:
-    def __init__(self, ctx, d, n, caps):
+    """A device TT with d modes of size n (an int, or d sizes), rank
+    capacities caps (one interior value or d+1), cores stored as dtype
+    (TT_C128 or TT_C64)."""
+
+    def __init__(self, ctx, d, n, caps, dtype=TT_C128):
         caps = np.ascontiguousarray(caps, dtype=np.int32).ravel()
         if caps.size == 1 and d >= 1:
             c = int(caps[0])
             caps = np.array([1] + [c] * (d - 1) + [1], dtype=np.int32)
         if caps.size != d + 1:
             raise ValueError(f"Tensor: need 1 or d+1 = {d + 1} rank capacities, got {caps.size}")
-        self.ctx, self.d, self.n = ctx, d, n
+        modes = np.ascontiguousarray(np.broadcast_to(np.asarray(n, dtype=np.int32), (d,)), dtype=np.int32)
+        self.ctx, self.d = ctx, d
+        self.modes = [int(v) for v in modes]
+        self.n = self.modes[0] if len(set(self.modes)) == 1 else None
+        self.dtype = dtype
         self.caps = caps
         h = P()
-        ctx.check(lib().tt_tensor_create(ctx.h, d, n, _ip(caps), ctypes.byref(h)))
+        ctx.check(lib().tt_tensor_create(ctx.h, d, _ip(modes), _ip(caps), int(dtype), ctypes.byref(h)))
         self.h = h
 
     def ranks(self):
@@ -362,8 +428,8 @@ class Tensor:
         for k, c in enumerate(cores):
             c = np.asarray(c)
             left = 1 if k == 0 else np.asarray(cores[k - 1]).shape[2]
-            if c.ndim != 3 or c.shape[0] != left or c.shape[1] != self.n:
-                raise ValueError(f"set_cores: core {k} has shape {c.shape}, expected ({left}, {self.n}, r)")
+            if c.ndim != 3 or c.shape[0] != left or c.shape[1] != self.modes[k]:
+                raise ValueError(f"set_cores: core {k} has shape {c.shape}, expected ({left}, {self.modes[k]}, r)")
         if np.asarray(cores[-1]).shape[2] != 1:
             raise ValueError("set_cores: the last core must have right rank 1")
         ranks = np.array([1] + [c.shape[2] for c in cores], dtype=np.int32)
@@ -373,10 +439,10 @@ class Tensor:
 
     def get_cores(self):
         r = self.ranks()
-        bufs = [np.empty(r[k] * self.n * r[k + 1], dtype=np.complex128) for k in range(self.d)]
+        bufs = [np.empty(r[k] * self.modes[k] * r[k + 1], dtype=np.complex128) for k in range(self.d)]
         ptrs = (P * self.d)(*[b.ctypes.data for b in bufs])
         self.ctx.check(lib().tt_tensor_get_cores(self.h, ptrs))
-        return [b.reshape((r[k], self.n, r[k + 1]), order="F") for k, b in enumerate(bufs)]
+        return [b.reshape((r[k], self.modes[k], r[k + 1]), order="F") for k, b in enumerate(bufs)]
 
     def set_gaussian(self, mu, sigma, length):
         mu = np.ascontiguousarray(mu, dtype=np.float64).ravel()
@@ -478,8 +544,16 @@ def tt_sum(ctx, coefs, xs, z):
 
 
 def tt_round(ctx, x, eps, rmax=0, report=True):
+    """rmax: an int for every bond (<= 0: no cap), or d+1 per-bond caps."""
+    if np.isscalar(rmax):
+        caps = None if int(rmax) <= 0 else np.full(x.d + 1, int(rmax), dtype=np.int32)
+    else:
+        caps = np.ascontiguousarray(rmax, dtype=np.int32).ravel()
+        if caps.size != x.d + 1:
+            raise ValueError("tt_round: need d+1 per-bond caps")
     rep = RoundReport()
-    ctx.check(lib().tt_round(ctx.h, x.h, float(eps), int(rmax), ctypes.byref(rep) if report else None))
+    ctx.check(lib().tt_round(ctx.h, x.h, float(eps), _ip(caps) if caps is not None else None,
+                             ctypes.byref(rep) if report else None))
     if not report:
         return None
     d = rep.d
@@ -496,11 +570,13 @@ def tt_round(ctx, x, eps, rmax=0, report=True):
 
 def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0,
             scheme=TT_STEP_RK4, gmres_tol=1e-10, gmres_max_iter=30, krylov_rmax=0,
-            learned_widths=None, learned_tol=1e-6, learned_apply_widths=None, power=0):
+            learned_widths=None, learned_tol=1e-6, learned_apply_widths=None, power=0, reserve=False):
     """One step; ``learned_widths`` (d+1 ints) selects the learned form, whose
     truncations of sums are randomised roundings to these widths, checked;
     ``learned_apply_widths`` (d+1 ints) sets the stage applications' sketch
-    widths per bond (checked for saturation)."""
+    widths per bond (checked for saturation).  ``reserve``: instead of
+    stepping f, size every workspace for steps of f's shape with these
+    options (tt_step_reserve; f is left unchanged)."""
 
     def arr(v, name):
         if v is None:
@@ -516,6 +592,9 @@ def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=
                  int(precision), int(scheme), float(gmres_tol), int(gmres_max_iter), int(krylov_rmax),
                  ctypes.cast(widths, ip) if widths is not None else None, float(learned_tol),
                  ctypes.cast(awidths, ip) if awidths is not None else None, int(power), 0)
+    if reserve:
+        ctx.check(lib().tt_step_reserve(ctx.h, op.h, f.h, float(dt), ctypes.byref(o)))
+        return None
     rep = StepReport()
     ctx.check(lib().tt_step(ctx.h, op.h, f.h, float(dt), ctypes.byref(o), ctypes.byref(rep)))
     nb = max(f.d - 1, 0)
@@ -524,6 +603,12 @@ def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=
             "learned_err": rep.learned_err, "final_norm": rep.final_norm,
             "final_sv": [list(rep.final_sv[c]) for c in range(nb)],
             "k_ranks": list(rep.k_ranks[: f.d + 1]), "learned_apply_fallback": rep.learned_apply_fallback}
+
+
+def tt_step_reserve(ctx, op, f, dt, rmax, eps, **kw):
+    """tt_step_reserve with tt_step's options: after it, tt_step on tensors
+    of f's shape with the same options allocates no device memory."""
+    return tt_step(ctx, op, f, dt, rmax, eps, reserve=True, **kw)
 
 
 def tt_step_batch(ctxs, ops, fs, dts, rmaxs, epss, mode=TT_APPLY_EXACT, sketch_ranks=None, seeds=None,

@@ -1,0 +1,248 @@
+"""The C ABI's storage and resource contract, through the Python binding:
+device memory from the caller's allocator (tt_allocator, here PyTorch's
+caching allocator), tt_step_reserve's promise that later steps of a shape
+allocate nothing, per-bond rank caps of the rounding (Alg. 2), tensors whose
+mode sizes differ (the TT arithmetic of App. A.1), complex-float storage,
+and tt_eval's read-out without a host synchronisation.  Values against the
+oracle (oracle.tt_ref, oracle.fullgrid) or against the complex-double form
+of the same call."""
+import numpy as np
+import pytest
+
+from gpu_util import make_ctx
+from oracle import fullgrid, tt_ref
+from paper_2403_04946_amd import inputs, tt
+
+pytestmark = pytest.mark.gpu
+
+D, N, L, NU, CAP, EPS, DT = 8, 32, 4.0, 0.05, 16, 1e-8, 1e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = make_ctx()
+    yield c
+    c.sync()
+    c.close()
+
+
+def _gaussian(c, dtype=tt.TT_C128, caps=CAP):
+    f = tt.Tensor(c, D, N, caps, dtype)
+    mu, sig = inputs.ic_params(D, 0)
+    f.set_gaussian(mu, sig, L)
+    return f
+
+
+def test_context_memory_comes_from_the_allocator():
+    import torch
+
+    c = tt.Context(0)
+    a = c.allocator
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated(0)
+    n0 = a.allocs
+    x = tt.Tensor(c, 6, 16, 32)
+    core_bytes = 16 * 16 * (32 + 4 * 32 * 32 + 32)
+    assert a.allocs - n0 >= 6
+    assert torch.cuda.memory_allocated(0) - before >= core_bytes
+    f0 = a.frees
+    x.close()
+    c.sync()
+    assert a.frees - f0 == a.allocs - n0
+    assert torch.cuda.memory_allocated(0) == before
+    c.close()
+
+
+@pytest.mark.parametrize("mode,width,power,prec,dtype", [
+    (tt.TT_APPLY_EXACT, 0, 0, tt.TT_PREC_FP64, tt.TT_C128),
+    (tt.TT_APPLY_SKETCH, 40, 2, tt.TT_PREC_FP64, tt.TT_C128),
+    (tt.TT_APPLY_SKETCH, 40, 0, tt.TT_PREC_FP16X3, tt.TT_C128),
+    (tt.TT_APPLY_SKETCH, 40, 2, tt.TT_PREC_FP64, tt.TT_C64),
+])
+def test_steps_after_reserve_allocate_nothing(mode, width, power, prec, dtype):
+    c = tt.Context(0)
+    a = c.allocator
+    op = tt.Operator(c, D, N, L, NU)
+    f = _gaussian(c, dtype)
+    kw = dict(mode=mode, sketch_rank=width, seed=3, precision=prec, power=power)
+    tt.tt_step_reserve(c, op, f, DT, CAP, EPS, **kw)
+    assert f.ranks() == [1] * (D + 1)
+    n0, f0 = a.allocs, a.frees
+    for _ in range(3):
+        tt.tt_step(c, op, f, DT, CAP, EPS, **kw)
+    c.sync()
+    print(f"mode {mode} width {width} power {power} precision {prec} dtype {dtype}: ranks {f.ranks()}, "
+          f"{n0} allocations before the steps")
+    assert max(f.ranks()) > 1
+    assert (a.allocs, a.frees) == (n0, f0)
+    f.close()
+    op.close()
+    c.close()
+
+
+def test_failed_allocation_is_reported_and_the_context_stays_usable():
+    c = tt.Context(0)
+    a = c.allocator
+    a.fail = True
+    with pytest.raises(tt.TTError) as e:
+        tt.Tensor(c, 4, 8, 4)
+    assert e.value.code == tt.TT_ENOMEM
+    a.fail = False
+    op = tt.Operator(c, D, N, L, NU)
+    f = _gaussian(c)
+    a.fail = True
+    with pytest.raises(tt.TTError) as e:
+        tt.tt_step(c, op, f, DT, CAP, EPS)
+    assert e.value.code == tt.TT_ENOMEM
+    a.fail = False
+    g = _gaussian(c)
+    tt.tt_step(c, op, g, DT, CAP, EPS)
+    # the same step in a context that allocates with hipMalloc
+    h = tt.Context(0, allocator=None)
+    oph = tt.Operator(h, D, N, L, NU)
+    gh = _gaussian(h)
+    tt.tt_step(h, oph, gh, DT, CAP, EPS)
+    assert tt_ref.tt_diff_norm(g.get_cores(), gh.get_cores()) <= 1e-13 * tt_ref.tt_norm(gh.get_cores())
+    for t in (f, g, op, gh, oph):
+        t.close()
+    c.close()
+    h.close()
+
+
+def _decaying(d, modes, ranks, seed):
+    """A TT with a decaying spectrum at every bond: a random TT plus 0.05
+    times a random TT of higher ranks (i.i.d. complex Gaussian cores)."""
+    rng = np.random.default_rng(seed)
+
+    def rand(rr):
+        cs = []
+        for k in range(d):
+            shape = (rr[k], modes[k], rr[k + 1])
+            cs.append((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(modes[k] * rr[k]))
+        return cs
+
+    lo = rand([1] + [max(1, r // 3) for r in ranks[1:-1]] + [1])
+    return tt_ref.tt_add(lo, rand(ranks), 1.0, 0.05)
+
+
+@pytest.mark.parametrize("caps", [[0, 3, 0, 5, 2, 0, 0], [9, 1, 4, 4, 4, 1, 9], [0, 0, 0, 0, 0, 0, 0]])
+def test_per_bond_caps_match_oracle(ctx, caps):
+    d, n = 6, 8
+    x = _decaying(d, [n] * d, [1, 6, 12, 15, 12, 6, 1], 31)
+    ref, info = tt_ref.tt_round([cc.copy() for cc in x], 1e-6, caps)
+    t = tt.Tensor(ctx, d, n, tt_ref.tt_ranks(x))
+    t.set_cores(x)
+    tt.tt_round(ctx, t, 1e-6, caps)
+    err = tt_ref.tt_diff_norm(t.get_cores(), ref) / tt_ref.tt_norm(ref)
+    print(f"caps {caps}: ranks {t.ranks()} (oracle {[1] + info['ranks'] + [1]}), difference {err:.2e}")
+    assert t.ranks() == [1] + info["ranks"] + [1]
+    assert err < 1e-11
+    t.close()
+
+
+MODES = [5, 9, 4, 12, 7]
+
+
+def test_ragged_modes_match_oracle(ctx):
+    d = len(MODES)
+    x = _decaying(d, MODES, [1, 3, 6, 6, 4, 1], 41)
+    y = _decaying(d, MODES, [1, 2, 5, 7, 3, 1], 43)
+    tx = tt.Tensor(ctx, d, MODES, tt_ref.tt_ranks(x))
+    tx.set_cores(x)
+    ty = tt.Tensor(ctx, d, MODES, tt_ref.tt_ranks(y))
+    ty.set_cores(y)
+    assert tx.modes == MODES and tx.n is None
+    fx, fy = fullgrid.tt_to_full(x), fullgrid.tt_to_full(y)
+    assert abs(tt.tt_norm(ctx, tx) - np.linalg.norm(fx)) < 1e-13 * np.linalg.norm(fx)
+    dot = tt.tt_dot(ctx, tx, ty)
+    ref = np.vdot(fx.ravel(), fy.ravel())
+    assert abs(dot - ref) < 1e-13 * np.linalg.norm(fx) * np.linalg.norm(fy)
+    # a sum, rounded, against the oracle's rounding of the sum
+    rx, ry = tt_ref.tt_ranks(x), tt_ref.tt_ranks(y)
+    s = tt.Tensor(ctx, d, MODES, [1] + [a + b for a, b in zip(rx[1:-1], ry[1:-1])] + [1])
+    tt.tt_axpy(ctx, 0.7, tx, -1.3, ty, s)
+    tt.tt_round(ctx, s, 1e-8, 0)
+    ref_s, info = tt_ref.tt_round(tt_ref.tt_add(x, y, 0.7, -1.3), 1e-8, None)
+    assert s.ranks() == [1] + info["ranks"] + [1]
+    assert tt_ref.tt_diff_norm(s.get_cores(), ref_s) < 1e-12 * tt_ref.tt_norm(ref_s)
+    # point values
+    import torch
+
+    rng = np.random.default_rng(5)
+    idx = np.ascontiguousarray(np.stack([rng.integers(0, m, 3000) for m in MODES], axis=1), dtype=np.int32)
+    out = torch.empty(3000, dtype=torch.complex128, device="cuda")
+    tt.tt_eval(ctx, tx, torch.from_numpy(idx).cuda(), out)
+    torch.cuda.synchronize()
+    assert np.abs(out.cpu().numpy() - fx[tuple(idx.T)]).max() < 1e-13 * np.abs(fx).max()
+    # the operator needs every mode size equal to its own
+    op = tt.Operator(ctx, d, 8, L, NU)
+    with pytest.raises(tt.TTError) as e:
+        tt.tt_apply(ctx, op, tx, s, tt.TT_APPLY_EXACT)
+    assert e.value.code == -2
+    for t in (tx, ty, s, op):
+        t.close()
+
+
+def test_c64_storage_rounds_and_steps_like_c128(ctx):
+    a = ctx.allocator
+    x = _decaying(D, [N] * D, [1] + [12] * (D - 1) + [1], 51)
+    x32 = [cc.astype(np.complex64).astype(np.complex128) for cc in x]
+    b0 = a.bytes
+    caps = tt_ref.tt_ranks(x)
+    t64 = tt.Tensor(ctx, D, N, caps, tt.TT_C64)
+    b64 = a.bytes - b0
+    t128 = tt.Tensor(ctx, D, N, caps)
+    b128 = a.bytes - b0 - b64
+    assert 2 * b64 == b128
+    t64.set_cores(x)
+    got = t64.get_cores()
+    assert all(np.array_equal(g, r) for g, r in zip(got, x32))
+    t128.set_cores(x32)
+    # the cap cuts at the spectrum's large gap (rank 4 | 0.05 x rank 12)
+    tt.tt_round(ctx, t64, 1e-6, 4)
+    tt.tt_round(ctx, t128, 1e-6, 4)
+    ref = t128.get_cores()
+    assert t64.ranks() == t128.ranks()
+    assert tt_ref.tt_diff_norm(t64.get_cores(), ref) < 1e-6 * tt_ref.tt_norm(ref)
+    # steps of the Gaussian initial condition in both storages
+    op = tt.Operator(ctx, D, N, L, NU)
+    f64, f128 = _gaussian(ctx, tt.TT_C64), _gaussian(ctx, tt.TT_C128)
+    for _ in range(3):
+        tt.tt_step(ctx, op, f64, DT, CAP, EPS)
+        tt.tt_step(ctx, op, f128, DT, CAP, EPS)
+    r = f128.get_cores()
+    e = tt_ref.tt_diff_norm(f64.get_cores(), r) / tt_ref.tt_norm(r)
+    print(f"C64 vs C128 storage after 3 steps: {e:.2e}")
+    assert e < 1e-6
+    for t in (t64, t128, f64, f128, op):
+        t.close()
+
+
+def test_eval_returns_before_the_stream_finishes(ctx):
+    """tt_eval enqueues one kernel and returns: with a long GEMM queued
+    before it on the context's stream, the call comes back while the stream
+    is still busy, and the values are right once it has finished."""
+    import torch
+
+    x = _decaying(D, [N] * D, [1] + [6] * (D - 1) + [1], 61)
+    t = tt.Tensor(ctx, D, N, tt_ref.tt_ranks(x))
+    t.set_cores(x)
+    m = 3072
+    A = torch.randn(m * m, dtype=torch.complex128, device="cuda")
+    C = torch.zeros(m * m, dtype=torch.complex128, device="cuda")
+    rng = np.random.default_rng(7)
+    idx = np.ascontiguousarray(rng.integers(0, N, (2000, D)), dtype=np.int32)
+    idx_d = torch.from_numpy(idx).cuda()
+    out = torch.empty(2000, dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    ctx.sync()
+    for _ in range(4):
+        tt.tt_zgemm(ctx, 0, 0, m, m, m, 1.0, A, m, 0, A, m, 0, 0.0, C, m, 0)
+    tt.tt_eval(ctx, t, idx_d, out)
+    busy = not ctx.torch_stream.query()
+    ctx.sync()
+    torch.cuda.synchronize()
+    assert busy
+    ref = tt_ref.tt_eval(x, idx)
+    assert np.abs(out.cpu().numpy() - ref).max() < 1e-13 * np.abs(ref).max()
+    t.close()

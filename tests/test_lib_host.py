@@ -94,8 +94,10 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert h.tt_op_create_burgers_hopf(None, 0, 8, 4.0, 0.1, ctypes.byref(out)) == -1
     assert h.tt_op_create_burgers_hopf(None, 4, 2, 4.0, 0.1, ctypes.byref(out)) == -1
     assert h.tt_op_create_burgers_hopf(None, 4, 8, -1.0, 0.1, ctypes.byref(out)) == -1
-    assert h.tt_tensor_create(None, 4, 8, None, ctypes.byref(out)) == -1
-    assert h.tt_round(None, None, 0.0, 0, None) == -1
+    modes = (ctypes.c_int * 4)(8, 8, 8, 8)
+    assert h.tt_tensor_create(None, 4, modes, None, 0, ctypes.byref(out)) == -1
+    assert h.tt_round(None, None, 0.0, None, None) == -1
+    assert h.tt_ctx_create(0, None, None, None) == -1
     assert h.tt_ctx_sync(None) == -1
 
 
