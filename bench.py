@@ -519,6 +519,84 @@ def main_learned(args):
     print(json.dumps(result), flush=True)
 
 
+TRAJECTORIES = {
+    # d, n, L, nu, cap, eps, dt, sketch width
+    "d20": (20, 64, 6.0, 0.02, 32, 1e-8, 5e-4, 80),
+    "d50": (50, 128, 8.0, 0.01, 64, 1e-6, 2e-4, 80),
+}
+
+
+def main_trajectory(args):
+    """A trajectory from the initial condition (Sec. 4.1 explicit RK4
+    step-truncation, which has a time-step restriction), logged per step:
+    bond ranks, ||phi||, phi at the origin's nearest node, the largest
+    |phi| over 4096 sampled nodes and the step time.  The run stops when a
+    sampled |phi| exceeds 1 + phi_tol (a characteristic function is bounded
+    by 1), ||phi|| exceeds `growth` times its initial value or stops being
+    finite: the explicit scheme has become unstable.  Workloads: d20 (n=64 on
+    [-6, 6], nu 0.02, cap 32, eps 1e-8, dt 5e-4; Gaussian or rank-3
+    tridiagonal-covariance IC) and d50 (n=128 on [-8, 8], nu 0.01, cap 64,
+    eps 1e-6, dt 2e-4).  One JSON line per step to --log, a summary line to
+    stdout."""
+    import numpy as np
+    import torch
+
+    from paper_2403_04946_amd import inputs, tt
+
+    torch.cuda.init()
+    d, n, length, nu, cap, eps, dt, ell = TRAJECTORIES[args.trajectory]
+    prec = PRECISIONS[args.precision]
+    ctx = tt.Context(0)
+    op = tt.Operator(ctx, d, n, length, nu)
+    f = tt.Tensor(ctx, d, n, cap)
+    if args.ic == "tridiag":
+        mu, sig, rho = inputs.ic_params_tridiag(d, 0)
+        ic_rep = f.set_gaussian_tridiag(mu, sig, rho, length, 0.0, 3)
+        ic_tail = max(ic_rep["tail"]) / ic_rep["norm"]
+    else:
+        mu, sig = inputs.ic_params(d, 0)
+        f.set_gaussian(mu, sig, length)
+        ic_tail = 0.0
+    idx = inputs.random_points(d, n, 4096, 3)
+    idx[0] = n // 2  # the node next to the origin
+    idx_d = torch.from_numpy(idx).cuda()
+    out = torch.empty(4096, dtype=torch.complex128, device="cuda")
+    norm0 = tt.tt_norm(ctx, f)
+    log = open(args.log, "w") if args.log else None
+    t0 = time.perf_counter()
+    status, last = "completed", None
+    for s in range(1, args.steps + 1):
+        ts = time.perf_counter()
+        rep = tt.tt_step(ctx, op, f, dt, cap, eps, tt.TT_APPLY_SKETCH, ell, 1000 + s, precision=prec,
+                         power=args.sketch_power)
+        tt.tt_eval(ctx, f, idx_d, out)
+        v = out.cpu().numpy()
+        nrm = tt.tt_norm(ctx, f)
+        rec = {"step": s, "t": s * dt, "max_rank": max(f.ranks()), "norm": nrm, "norm_ratio": nrm / norm0,
+               "phi_origin_node": [float(v[0].real), float(v[0].imag)], "max_abs_sampled": float(np.abs(v).max()),
+               "step_s": time.perf_counter() - ts, "step_max_rank": rep["max_rank"]}
+        last = rec
+        if log:
+            log.write(json.dumps(rec) + "\n")
+            log.flush()
+        if s % 10 == 0 or s == 1:
+            print(f"bench: trajectory step {s}: rank {rec['max_rank']}, |phi| ratio {rec['norm_ratio']:.6f}, "
+                  f"max sampled |phi| {rec['max_abs_sampled']:.6f}", file=sys.stderr, flush=True)
+        if not np.isfinite(nrm) or nrm > args.growth * norm0 or rec["max_abs_sampled"] > 1.0 + args.phi_tol:
+            status = (f"unstable at step {s}: ||phi|| / ||phi0|| = {nrm / norm0:.3e}, "
+                      f"max sampled |phi| = {rec['max_abs_sampled']:.3e}")
+            break
+        if time.perf_counter() - t0 > args.max_seconds:
+            status = f"stopped at the time limit after step {s}"
+            break
+    result = {"form": "trajectory", "workload": args.trajectory, "ic": args.ic, "precision": args.precision,
+              "sketch_width": ell, "sketch_power": args.sketch_power,
+              "d": d, "n": n, "L": length, "nu": nu, "rank_cap": cap, "eps": eps, "dt": dt,
+              "ic_discarded_tail": ic_tail, "norm0": norm0, "status": status, "last": last,
+              "wall_s": time.perf_counter() - t0}
+    print(json.dumps(result), flush=True)
+
+
 def main_cdf(args):
     """The paper's own workload: the CDF equation of the stochastic Burgers
     equation with reaction (Sec. 5) at N = 20 points of the circle, n = 64
@@ -614,7 +692,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sketch-rank", type=int, default=80)
-    ap.add_argument("--sketch-power", type=int, default=2,
+    ap.add_argument("--sketch-power", type=int, default=1,
                     help="subspace-iteration passes of every sketched apply (0 = the plain range finder)")
     ap.add_argument("--precision", choices=sorted(PRECISIONS), default="fp16x3")
     ap.add_argument("--error-steps", type=int, default=2,
@@ -622,9 +700,19 @@ def main():
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-error-report", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["metric", "batched", "learned", "cdf"], default="metric",
+    ap.add_argument("--form", choices=["metric", "batched", "learned", "cdf", "trajectory"], default="metric",
                     help="batched: the batched form on uneven instances; learned: the learned form against the "
-                         "plain one on tolerance-limited trajectories (each its own JSON line)")
+                         "plain one on tolerance-limited trajectories; trajectory: a logged run from the initial "
+                         "condition (each its own JSON line)")
+    ap.add_argument("--trajectory", choices=sorted(TRAJECTORIES), default="d20")
+    ap.add_argument("--ic", choices=["gaussian", "tridiag"], default="gaussian")
+    ap.add_argument("--log", default=None, help="trajectory: per-step JSON lines to this file")
+    ap.add_argument("--growth", type=float, default=1e3,
+                    help="trajectory: stop when ||phi|| exceeds this multiple of its initial value")
+    ap.add_argument("--phi-tol", type=float, default=1e-3,
+                    help="trajectory: stop when a sampled |phi| exceeds 1 + this (a characteristic function "
+                         "has |phi| <= 1; the grid L2 norm itself grows as the distribution concentrates)")
+    ap.add_argument("--max-seconds", type=float, default=240.0, help="trajectory: wall-clock limit")
     ap.add_argument("--instances", type=int, default=16)
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the GEMM launch-shape rule (by default the shapes of one step of each timed form "
@@ -652,6 +740,9 @@ def main():
         return
     if args.form == "cdf":
         main_cdf(args)
+        return
+    if args.form == "trajectory":
+        main_trajectory(args)
         return
 
     import torch

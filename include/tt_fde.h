@@ -163,9 +163,17 @@ int tt_ctx_reset_stats(tt_ctx* ctx);
  * the first form every orthogonalisation tries (0: Cholesky QR twice per
  * panel with the checked fast second pass, 1: Householder panels with the
  * fast second pass, 2: Householder panels twice); each form falls back to
- * the next when its checks fail, so results agree to rounding.  TT_EINVAL
- * for an unknown option or a value out of range. */
-enum { TT_OPT_JACOBI_MAX_SWEEPS = 1, TT_OPT_QR_MIN_LEVEL = 2 };
+ * the next when its checks fail, so results agree to rounding.
+ * TT_OPT_JACOBI_FUSED (0 or 1, default 1): 1 runs each batch of Jacobi
+ * sweeps as one launch whose workgroups meet at grid barriers between the
+ * rounds of a sweep (SVDs up to 1024 columns), 0 launches every round on
+ * its own; both apply the same rotations in the same order, so the results
+ * are bitwise the same.  TT_OPT_JACOBI_WAIT_LIMIT (0 .. 2^40, default
+ * 2^20): polls a workgroup of the fused form makes at one barrier before it
+ * gives up; every workgroup then returns and the call fails with
+ * TT_ENOCONV (0 forces that path for tests).  TT_EINVAL for an unknown
+ * option or a value out of range. */
+enum { TT_OPT_JACOBI_MAX_SWEEPS = 1, TT_OPT_QR_MIN_LEVEL = 2, TT_OPT_JACOBI_FUSED = 3, TT_OPT_JACOBI_WAIT_LIMIT = 4 };
 int tt_ctx_set_option(tt_ctx* ctx, int option, long long value);
 int tt_ctx_get_stats(tt_ctx* ctx, const char* kernel, double* total_ms,
                      double* flops, double* bytes, long long* launches);
@@ -357,6 +365,18 @@ typedef struct {
  * truncation SVD stops at its sweep limit (x then holds the rounding up to
  * that bond, a valid TT of the same tensor up to the tails cut so far). */
 int tt_round(tt_ctx* ctx, tt_tensor* x, double eps_rel, const int* rmax, tt_round_report* rep);
+
+/* Gaussian characteristic function with tridiagonal covariance (amplitudes
+ * u ~ N(mu, Sigma), Sigma_kk = sigma_k^2, Sigma_k,k+1 = rho_k sigma_k
+ * sigma_k+1): phi0(a) = prod_k exp(i mu_k a_k - sigma_k^2 a_k^2 / 2)
+ * prod_k exp(-rho_k sigma_k sigma_k+1 a_k a_k+1) on the grid a_i = -L + 2Li/(n-1).  The
+ * exact nearest-neighbour product has bond ranks n; t receives its
+ * rounding (eps_rel, rmax and rep as in tt_round; t's capacities must hold
+ * the rounded ranks, TT_ECAPACITY otherwise).  rho: d-1 values in
+ * (-1/2, 1/2), which keeps Sigma positive definite. */
+int tt_tensor_set_gaussian_tridiag(tt_ctx* ctx, tt_tensor* t, const double* mu, const double* sigma,
+                                   const double* rho, double L, double eps_rel, const int* rmax,
+                                   tt_round_report* rep);
 
 typedef struct {
   int size;              /* sizeof(tt_step_opts) */

@@ -40,6 +40,36 @@ def viscous_continuous_factors(mu, sigma, nu, t, n, length):
     return out
 
 
+def tridiag_gaussian_tt(mu, sigma, rho, n, length):
+    """Exact TT of the Gaussian characteristic function with tridiagonal
+    covariance (Sigma_kk = sigma_k^2, Sigma_k,k+1 = rho_k sigma_k sigma_k+1),
+    phi0(a) = exp(i mu.a - a^T Sigma a / 2): the product of the one-axis
+    factors exp(i mu_k a_k - sigma_k^2 a_k^2 / 2) and the neighbour factors
+    exp(-rho_k sigma_k sigma_k+1 a_k a_k+1).  Core k carries the previous
+    coordinate on its left bond and repeats its own on the right one, so
+    interior bond ranks are n."""
+    a = fd.grid(n, length)
+    d = len(mu)
+    cores = []
+    for k in range(d):
+        own = np.exp(1j * mu[k] * a - 0.5 * sigma[k] ** 2 * a**2)
+        left = np.ones((1, n)) if k == 0 else np.exp(-rho[k - 1] * sigma[k - 1] * sigma[k] * np.outer(a, a))
+        core = left[:, :, None] * own[None, :, None]  # (r0, n, 1)
+        if k < d - 1:
+            core = core * np.eye(n)[None, :, :]  # repeat the coordinate: (r0, n, n)
+        cores.append(core.astype(np.complex128))
+    return cores
+
+
+def viscous_continuous_tridiag(mu, sigma, rho, nu, t):
+    """Parameters of the exact viscous-only solution from the tridiagonal
+    Gaussian: phi(a, t) = phi0(s a) with s_k = exp(-nu kappa_k^2 t), the same
+    kind of Gaussian with mu_k s_k, sigma_k s_k and unchanged rho."""
+    kap = wavenumbers(len(mu)).astype(np.float64)
+    s = np.exp(-nu * kap**2 * t)
+    return np.asarray(mu) * s, np.asarray(sigma) * s, np.asarray(rho)
+
+
 def viscous_semidiscrete_propagator(dkk, nu, t, n, length):
     """expm(t * nu * D_kk * X G) for one axis."""
     x = fd.position(n, length)

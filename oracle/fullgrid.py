@@ -285,6 +285,21 @@ def gaussian_ic(mu, sigma, n, length):
     return out
 
 
+def tridiag_gaussian_ic(mu, sigma, rho, n, length):
+    """exp(i mu.a - a^T Sigma a / 2) on the full grid, Sigma tridiagonal
+    with Sigma_kk = sigma_k^2 and Sigma_k,k+1 = rho_k sigma_k sigma_k+1: the
+    characteristic function of amplitudes u ~ N(mu, Sigma), evaluated from
+    the quadratic form."""
+    d = len(mu)
+    sig = np.diag(np.asarray(sigma, dtype=np.float64) ** 2)
+    for k in range(d - 1):
+        sig[k, k + 1] = sig[k + 1, k] = rho[k] * sigma[k] * sigma[k + 1]
+    a = fd.grid(n, length)
+    pts = np.stack(np.meshgrid(*([a] * d), indexing="ij"), axis=-1)  # (n,)*d + (d,)
+    quad = np.einsum("...j,jk,...k->...", pts, sig, pts)
+    return np.exp(1j * pts @ np.asarray(mu, dtype=np.float64) - 0.5 * quad)
+
+
 def gaussian_ic_factors(mu, sigma, n, length):
     """The d one-dimensional factors of the rank-one Gaussian IC."""
     a = fd.grid(n, length)

@@ -518,9 +518,10 @@ void apply_exact(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y)
 // projection one site on.  Each of the `power` further passes sweeps the
 // other way with the previous pass's chains in place of the sketch (a
 // subspace-iteration step: the bases of a bond become the range of L x
-// restricted to the other side's bases), ending left-orthonormal after an
-// odd count and right-orthonormal after an even one.  Exact whenever the
-// widths reach the ranks of L x.
+// restricted to the other side's bases).  For an odd count the sketches
+// are drawn from the right instead (right chains, first pass left to
+// right), so that the last pass always runs right to left and y ends
+// right-orthonormal.  Exact whenever the widths reach the ranks of L x.
 void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int l, uint64_t seed,
                   int precision, const int* widths = nullptr, int power = 0) {
   // the sketch contractions in plain FP64 or a split 16-bit form (mixed).
@@ -606,6 +607,24 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
       pow2_normalize(ctx, S + sk_off[m + 1], (long)lp * r1 * R1, pexp, false);
     }
   };
+  // ---- Gaussian right sketches P_m = (Z_m contracted with P_{m+1}) omega_m,
+  // P_d = 1 (the mirror of pass 0, for an odd number of power passes)
+  auto right_sketch_pass = [&]() {
+    TTF_HIP(hipMemcpyAsync(P + p_off[d], &one, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
+    int sp = 1;
+    for (int m = d - 1; m >= 1; --m) {
+      const int r0 = r[m], r1 = r[m + 1], R0 = R[m], R1 = R[m + 1];
+      gemm(ctx, OPN, OPN, r0 * n, R1 * sp, r1, Z(1), x->core[m], (long)r0 * n, 0, P + p_off[m + 1], r1, 0, Z(0),
+           V, (long)r0 * n, 0, 1);
+      gather_right(ctx, op, m, V, W, r0, sp);  // Z: (r0 R0) x (n s_{m+1})
+      const int lm = ll[m];
+      sketch_core(ctx, omega, (long)n * sp * lm, seed ^ 0x5851F42D4C957F2Dull, m, 1.0 / std::sqrt((double)lm));
+      gemm(ctx, OPN, OPN, r0 * R0, lm, n * sp, Z(1), W, (long)r0 * R0, 0, omega, (long)n * sp, 0, Z(0),
+           P + p_off[m], (long)r0 * R0, 0, 1);
+      pow2_normalize(ctx, P + p_off[m], (long)r0 * R0 * lm, pexp, false);
+      sp = lm;
+    }
+  };
   // ---- right-to-left pass with the left chains S: right-orthonormal y and
   // the right chains P_m = Z_m Q_m ((r_m R_m) x l_m, layout [a, alpha, q])
   auto right_to_left = [&]() {
@@ -678,12 +697,19 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
   for (int attempt = 0; attempt < 2; ++attempt) {
     if (attempt == 0) zero_ints(ctx, qr_flag, 1);
     else qr_flag = nullptr;  // every factorisation checked on its own
+    // the passes alternate and the last one runs right to left (y right-
+    // orthonormal, so a rounding of y skips its orthogonalisation sweep):
+    // an even count of power passes starts from left sketches, an odd one
+    // from right sketches
     prec = precision;
-    sketch_pass();
+    const bool from_right = (power & 1) != 0;
+    if (from_right)
+      right_sketch_pass();
+    else
+      sketch_pass();
     prec = power > 0 ? TT_PREC_FP64 : precision;
-    right_to_left();
-    for (int p = 1; p <= power; ++p) {
-      if (p & 1)
+    for (int p = 0; p <= power; ++p) {
+      if (((p & 1) != 0) != from_right)
         left_to_right();
       else
         right_to_left();
@@ -1132,6 +1158,16 @@ int tt_ctx_set_option(tt_ctx* ctx, int option, long long value) {
     ctx->jacobi_max_sweeps = (int)value;
     return TT_OK;
   }
+  if (option == TT_OPT_JACOBI_FUSED) {
+    require(value == 0 || value == 1, TT_EINVAL, "tt_ctx_set_option: the fused Jacobi switch is 0 or 1");
+    ctx->jacobi_fused = (int)value;
+    return TT_OK;
+  }
+  if (option == TT_OPT_JACOBI_WAIT_LIMIT) {
+    require(value >= 0 && value <= (1LL << 40), TT_EINVAL, "tt_ctx_set_option: wait limit must be 0..2^40");
+    ctx->jacobi_wait_limit = (long)value;
+    return TT_OK;
+  }
   fail(TT_EINVAL, "tt_ctx_set_option: unknown option");
   ABI_CATCH(ctx)
 }
@@ -1286,6 +1322,34 @@ int tt_tensor_set_gaussian(tt_ctx* ctx, tt_tensor* t, const double* mu, const do
   w->rank.assign(t->d + 1, 1);
   w->orth = TT_ORTH_NONE;
   narrow_back(ctx, w, t);
+  return TT_OK;
+  ABI_CATCH(ctx)
+}
+
+int tt_tensor_set_gaussian_tridiag(tt_ctx* ctx, tt_tensor* t, const double* mu, const double* sigma,
+                                   const double* rho, double L, double eps_rel, const int* rmax,
+                                   tt_round_report* rep) {
+  if (!ctx || !t || !mu || !sigma || (t->d > 1 && !rho)) return TT_EINVAL;
+  ABI_TRY
+  require(L > 0, TT_EINVAL, "L must be positive");
+  require(eps_rel >= 0, TT_EINVAL, "eps must be >= 0");
+  const int d = t->d;
+  for (int k = 0; k + 1 < d; ++k)
+    require(std::fabs(rho[k]) < 0.5, TT_EINVAL, "correlations must lie in (-1/2, 1/2)");
+  // the exact nearest-neighbour product (bond k has the rank of mode k)
+  std::vector<int> cap(d + 1, 1);
+  for (int k = 1; k < d; ++k) cap[k] = t->nk[k - 1];
+  tt_tensor* e = pooled_nk(ctx, "nn_ic", d, t->nk, cap);
+  for (int k = 0; k < d; ++k) {
+    const double c = k > 0 ? rho[k - 1] * sigma[k - 1] * sigma[k] : 0.0;
+    nn_gaussian_core(ctx, e->core[k], cap[k], t->nk[k], cap[k + 1], k > 0 ? t->nk[k - 1] : 1, L, mu[k], sigma[k], c);
+  }
+  e->rank = cap;
+  e->orth = TT_ORTH_NONE;
+  round_tensor(ctx, e, eps_rel, 0, rep, rmax);
+  copy_tensor(ctx, e, t);
+  t->rank = e->rank;
+  t->orth = e->orth;
   return TT_OK;
   ABI_CATCH(ctx)
 }

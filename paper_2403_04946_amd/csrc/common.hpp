@@ -120,6 +120,8 @@ struct tt_ctx {
   std::map<std::pair<int, int>, int> jacobi_sweeps_seen;
   int jacobi_max_sweeps = 60;   // sweep limit of every Jacobi SVD (tt_ctx_set_option)
   int qr_min_level = 0;         // most economical QR form allowed (tt_ctx_set_option)
+  int jacobi_fused = 1;         // sweeps of a Jacobi SVD in one launch per batch (tt_ctx_set_option)
+  long jacobi_wait_limit = 1L << 20;  // polls of a fused-sweep barrier before it gives up
 
   // device memory: through the caller's allocator when one was given at
   // creation, else hipMalloc / hipFree; dev_alloc returns null on failure
@@ -319,6 +321,8 @@ void narrow_c128(tt_ctx* ctx, const zc* src, void* dst, long n);    // complex d
 void tt_eval_kernel(tt_ctx* ctx, int d, const int* nk, const zc* const* cores, const int* ranks,
                     const int32_t* idx, int64_t npts, zc* out);
 void gaussian_factor(tt_ctx* ctx, zc* core, int n, double L, double mu, double sigma);
+void nn_gaussian_core(tt_ctx* ctx, zc* core, int r0, int n, int r1, int nprev, double L, double mu, double sigma,
+                      double c);
 void cdf_gaussian_factor(tt_ctx* ctx, zc* core, int n, double box, double sigma);
 void identity_core(tt_ctx* ctx, zc* core, int n, int r1);  // (n r1) x n x r1, I
 void apply_exact_core(tt_ctx* ctx, const tt_op* op, int site, const zc* x, int r0, int r1,

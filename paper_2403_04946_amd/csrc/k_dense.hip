@@ -50,8 +50,18 @@ constexpr int JB_MAXM = 1536;  // rows supported by the register-resident form
 constexpr int JB_MAXK = 1536;  // columns
 constexpr int JB_XCHUNK = 8;   // rows per lane moved through LDS at a time
 constexpr int JB_MAXS = 64;    // sweep counters
-// counters of one SVD: JB_MAXS + 2 ints, then |B|_F^2 (a double)
+// counters of one SVD: JB_MAXS + 2 ints, |B|_F^2 (a double), then the
+// arrival count and give-up flag of the fused sweeps' barrier
+constexpr int JB_BAR = JB_MAXS + 4;
 constexpr size_t JB_ROT_BYTES = sizeof(int) * (JB_MAXS + 2) + 64;
+static_assert(sizeof(int) * (JB_BAR + 2) <= JB_ROT_BYTES, "barrier words beyond the counters");
+// workgroups of a fused launch (P / 2) up to which the sweeps run fused:
+// all of them must be resident at once, which this many are on any
+// MI355X even beside other work
+constexpr int JB_FUSED_MAX_WG = 64;
+// rows up to which the sweeps run fused (beyond, the columns held in
+// registers by both phases would spill)
+constexpr int JB_FUSED_MAXM = 640;
 
 // round-robin pairing of players 0..P-1 (P even) in round r
 __device__ inline void rr_pair(int P, int r, int i, int& a, int& b) {
@@ -478,6 +488,180 @@ __global__ __launch_bounds__(BC * GS) void jacobi_check_kernel(const zc* __restr
   if (__syncthreads_or(bad) && threadIdx.x == 0) atomicMax(failed, label);
 }
 
+// ------------------------------------------ one launch per batch of sweeps
+// Grid-wide barrier of the fused sweeps.  Every workgroup adds one arrival
+// to bar[0] and waits until `target` arrivals are counted.  The wait is
+// bounded: after `limit` polls, or once another workgroup has given up
+// (bar[1] set), it gives up and sets bar[1]; the workgroups then return and
+// the host reports the SVD as unconverged.  Device-scope fences publish the
+// columns written before the barrier and drop stale cached copies after it
+// (the L2 caches of the chiplets are not coherent with each other).
+__device__ inline bool fused_barrier(int* bar, int target, long limit, int* gave_up_lds) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int gave_up = 0;
+    long polls = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (polls >= limit || __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        gave_up = 1;
+        __hip_atomic_store(bar + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      ++polls;
+      __builtin_amdgcn_s_sleep(2);
+    }
+    *gave_up_lds = gave_up;
+  }
+  __syncthreads();
+  __threadfence();
+  return *gave_up_lds != 0;
+}
+
+// Sweeps sweep0 .. sweep0 + nsw - 1 of the block Jacobi in one launch of
+// P/2 workgroups: per sweep, the within-block phase (workgroup g runs blocks
+// 2g and 2g + 1, four lane groups each, as the circle kernel with W = 4),
+// then the P - 1 rounds of the round-robin (as the cross kernel), with a
+// grid barrier after every phase.  The rotations, their order and the
+// counts are those of the one-launch-per-phase form, so the results are
+// bitwise the same.  A sweep starts only when the previous one rotated.
+template <int RPL, int GS, int BC>
+__global__ __launch_bounds__(BC * GS) void jacobi_fused_kernel(zc* __restrict__ B, int m, int k, int P, int sweep0,
+                                                               int nsw, int* __restrict__ rot, double tol,
+                                                               const double* __restrict__ fro2, int* __restrict__ bar,
+                                                               long limit) {
+  extern __shared__ double2 xch[];
+  __shared__ int wg_rot, prev_rot, gave_up;
+  constexpr int W = BC / 2;  // lane groups per block in the within-block phase
+  constexpr int NP = 2 * W - 1;
+  constexpr int XCC = RPL < JB_XCHUNK ? RPL : JB_XCHUNK;
+  constexpr int LDC = GS * XCC;
+  constexpr int XC = cross_chunk(RPL, GS);
+  constexpr int LD = GS * XC;
+  const int w = threadIdx.x / GS, lane = threadIdx.x % GS;
+  const double abs2 = 1e-30 * fro2[0];  // (1e-15 |B|_F)^2
+  const int nwg = gridDim.x;
+  int arrivals = 0;
+  for (int s = sweep0; s < sweep0 + nsw; ++s) {
+    if (s > 0) {
+      if (threadIdx.x == 0) prev_rot = __hip_atomic_load(&rot[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      if (prev_rot == 0) return;
+    }
+    {  // within-block phase
+      const int wl = w % W;
+      const int c0 = (2 * (int)blockIdx.x + w / W) * BC;
+      const int ct = c0 + wl, cb = c0 + 2 * W - 1 - wl;
+      zc xt[RPL], xb[RPL];
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        const int row = lane + GS * j;
+        xt[j] = (ct < k && row < m) ? B[row + (long)m * ct] : make_double2(0.0, 0.0);
+        xb[j] = (cb < k && row < m) ? B[row + (long)m * cb] : make_double2(0.0, 0.0);
+      }
+      zc* mine = xch + (long)LDC * w;
+      int nrot = 0;
+      for (int r = 0; r < NP; ++r) {
+        const int pt = (wl == 0) ? 0 : ((wl - 1 - r) % NP + NP) % NP + 1;
+        const int pb = ((2 * W - 2 - wl - r) % NP + NP) % NP + 1;
+        if (c0 + pt < k && c0 + pb < k) nrot += jacobi_rotate<RPL, GS>(xt, xb, tol, abs2);
+#pragma unroll
+        for (int c = 0; c < RPL; c += XCC) {
+          __syncthreads();
+#pragma unroll
+          for (int j = 0; j < XCC; ++j)
+            if (c + j < RPL) mine[lane + GS * j] = xb[c + j];
+          __syncthreads();
+          if (wl <= W - 2) {
+            const zc* src = mine + LDC;
+#pragma unroll
+            for (int j = 0; j < XCC; ++j)
+              if (c + j < RPL) xb[c + j] = src[lane + GS * j];
+          } else {
+#pragma unroll
+            for (int j = 0; j < XCC; ++j)
+              if (c + j < RPL) xb[c + j] = xt[c + j];
+          }
+          __syncthreads();
+          if (wl >= 1 && wl <= W - 2) {
+#pragma unroll
+            for (int j = 0; j < XCC; ++j)
+              if (c + j < RPL) mine[lane + GS * j] = xt[c + j];
+          }
+          __syncthreads();
+          if (wl >= 1) {
+            const zc* src = mine - LDC;
+#pragma unroll
+            for (int j = 0; j < XCC; ++j)
+              if (c + j < RPL) xt[c + j] = src[lane + GS * j];
+          }
+        }
+      }
+      jacobi_count(nrot, &wg_rot, rot, s);
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        const int row = lane + GS * j;
+        if (row < m) {
+          if (ct < k) B[row + (long)m * ct] = xt[j];
+          if (cb < k) B[row + (long)m * cb] = xb[j];
+        }
+      }
+    }
+    arrivals += nwg;
+    if (fused_barrier(bar, arrivals, limit, &gave_up)) return;
+    for (int round = 0; round < P - 1; ++round) {
+      int ba, bb;
+      rr_pair(P, round, blockIdx.x, ba, bb);
+      const int ca = ba * BC + w;
+      zc xa[RPL], xb[RPL];
+      {
+        const int cb = bb * BC + w;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const int row = lane + GS * j;
+          xa[j] = (ca < k && row < m) ? B[row + (long)m * ca] : make_double2(0.0, 0.0);
+          xb[j] = (cb < k && row < m) ? B[row + (long)m * cb] : make_double2(0.0, 0.0);
+        }
+      }
+      zc* mine = xch + (long)LD * w;
+      const zc* next = xch + (long)LD * ((w + 1) % BC);
+      int nrot = 0, set = 0;
+      for (int st = 0; st < BC; ++st) {
+        const int cb = bb * BC + (w + st) % BC;
+        if (ca < k && cb < k) nrot += jacobi_rotate<RPL, GS>(xa, xb, tol, abs2);
+        if (st == BC - 1) break;
+#pragma unroll
+        for (int c = 0; c < RPL; c += XC) {
+          const long off = set ? (long)LD * BC : 0;
+          set ^= 1;
+#pragma unroll
+          for (int j = 0; j < XC; ++j)
+            if (c + j < RPL) mine[off + lane + GS * j] = xb[c + j];
+          __syncthreads();
+#pragma unroll
+          for (int j = 0; j < XC; ++j)
+            if (c + j < RPL) xb[c + j] = next[off + lane + GS * j];
+        }
+      }
+      jacobi_count(nrot, &wg_rot, rot, s);
+      {
+        const int cb = bb * BC + (w + BC - 1) % BC;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const int row = lane + GS * j;
+          if (row < m) {
+            if (ca < k) B[row + (long)m * ca] = xa[j];
+            if (cb < k) B[row + (long)m * cb] = xb[j];
+          }
+        }
+      }
+      arrivals += nwg;
+      if (fused_barrier(bar, arrivals, limit, &gave_up)) return;
+    }
+  }
+}
+
 template <int RPL, int GS>
 void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int round, int inner_max, int sweep,
                        int* rot, double tol, const double* fro2) {
@@ -496,6 +680,20 @@ void jacobi_launch_rpl(tt_ctx* ctx, int kind, int m, int k, zc* B, int P, int ro
   } else {
     pairs = (double)JB_COLS * JB_COLS * (P / 2);
     cols = 2.0 * JB_COLS * (P / 2);
+  }
+  if (kind == 4) {  // inner_max sweeps from `sweep` in one launch
+    if constexpr (RPL * GS > JB_FUSED_MAXM) {
+      fail(TT_EINVAL, "jacobi_svd: the fused form takes at most 640 rows");
+    } else {
+    constexpr int XCC = RPL < JB_XCHUNK ? RPL : JB_XCHUNK;
+    const size_t lds = std::max(sizeof(zc) * JB_COLS * GS * XCC, 2 * JB_COLS * sizeof(zc) * GS * cross_chunk(RPL, GS));
+    const double sweep_pairs = 0.5 * (double)k * (k - 1.0);
+    KTimer kf(ctx, "jacobi_fused", pair * sweep_pairs * inner_max, 2.0 * 16.0 * m * (double)k * P * inner_max, true);
+    TTF_LAUNCH(kf, (jacobi_fused_kernel<RPL, GS, JB_COLS>), dim3(P / 2), dim3(JB_COLS * GS), lds, ctx->stream, B, m,
+               k, P, sweep, inner_max, rot, tol, fro2, rot + JB_BAR, ctx->jacobi_wait_limit);
+    TTF_HIP(hipGetLastError());
+    }
+    return;
   }
   if (kind == 3) {  // the all-pairs convergence test (P = number of blocks, inner_max = label)
     const int nb = P;
@@ -577,22 +775,33 @@ void jacobi_blocked(tt_ctx* ctx, int m, int k, zc* B, zc* U, double* sigma, int*
     // the first batch is as long as the last SVD of this size needed (5 for
     // a new size), the later ones one sweep.  The launched count does not
     // change the result.
-    int hbuf[JB_MAXS + 1];
-    int* h = rot_ext ? hbuf : (int*)ctx->host_scratch(sizeof(int) * (JB_MAXS + 1));
+    int hbuf[JB_BAR + 2];
+    int* h = rot_ext ? hbuf : (int*)ctx->host_scratch(sizeof(int) * (JB_BAR + 2));
+    const bool fused = ctx->jacobi_fused && P / 2 <= JB_FUSED_MAX_WG && m <= JB_FUSED_MAXM;
     auto seen = ctx->jacobi_sweeps_seen.find({m, k});
     const bool known = seen != ctx->jacobi_sweeps_seen.end();
     int batch = known ? std::max(1, seen->second) : 5;
     bool done = false;
     int converged = 0, rotating = 0;  // sweeps until converged; of them with rotations
     while (!done && nsweeps < max_sweeps) {
-      for (int b = 0; b < batch && nsweeps < max_sweeps; ++b, ++nsweeps) {
-        launch(1, P, 0, 1, nsweeps, rot, tol);
-        for (int r = 0; r < P - 1; ++r) launch(2, P, r, 1, nsweeps, rot, tol);
+      if (fused) {
+        const int nsw = std::min(batch, max_sweeps - nsweeps);
+        hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, ctx->stream, rot + JB_BAR, 2);
+        TTF_HIP(hipGetLastError());
+        launch(4, P, 0, nsw, nsweeps, rot, tol);
+        nsweeps += nsw;
+      } else {
+        for (int b = 0; b < batch && nsweeps < max_sweeps; ++b, ++nsweeps) {
+          launch(1, P, 0, 1, nsweeps, rot, tol);
+          for (int r = 0; r < P - 1; ++r) launch(2, P, r, 1, nsweeps, rot, tol);
+        }
       }
       launch(3, nblk, 0, nsweeps, 0, rot, tol);  // the test labelled nsweeps
       checked = 1;
-      TTF_HIP(hipMemcpyAsync(h, rot, sizeof(int) * (JB_MAXS + 1), hipMemcpyDeviceToHost, ctx->stream));
+      TTF_HIP(hipMemcpyAsync(h, rot, sizeof(int) * (JB_BAR + 2), hipMemcpyDeviceToHost, ctx->stream));
       TTF_HIP(hipStreamSynchronize(ctx->stream));
+      if (fused && h[JB_BAR + 1] != 0)
+        fail(TT_ENOCONV, "jacobi_svd: a workgroup of the fused sweeps gave up waiting at a grid barrier");
       for (int s = 0; s < nsweeps && !done; ++s)
         if (h[s] == 0) {
           done = true;

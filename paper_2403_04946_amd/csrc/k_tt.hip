@@ -214,6 +214,40 @@ void cdf_gaussian_factor(tt_ctx* ctx, zc* core, int n, double box, double sigma)
   TTF_HIP(hipGetLastError());
 }
 
+// core k of the nearest-neighbour product TT of a Gaussian characteristic
+// function with tridiagonal covariance: entry (p, i, q) of the r0 x n x r1
+// core (layout p + r0 (i + n q)) is
+//   exp(-c a_p a_i) exp(i mu a_i - sigma^2 a_i^2 / 2) [i == q]
+// where the left index p carries the previous coordinate (r0 = its n, or 1
+// with c = 0 at the first core) and the right index repeats the current one
+// (r1 = n, or 1 at the last core); a_i = -L + 2 L i / (n - 1) on every axis.
+__global__ void nn_gaussian_core_kernel(zc* core, int r0, int n, int r1, int nprev, double L, double mu,
+                                        double sigma, double c) {
+  const long total = (long)r0 * n * r1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int p = (int)(e % r0), i = (int)((e / r0) % n), q = (int)(e / ((long)r0 * n));
+    if (r1 > 1 && q != i) {
+      core[e] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double a = -L + 2.0 * L * i / (n - 1);
+    const double ap = (r0 > 1) ? -L + 2.0 * L * p / (nprev - 1) : 0.0;
+    const double mag = exp(-0.5 * sigma * sigma * a * a - c * ap * a);
+    double s, co;
+    sincos(mu * a, &s, &co);
+    core[e] = make_double2(mag * co, mag * s);
+  }
+}
+
+void nn_gaussian_core(tt_ctx* ctx, zc* core, int r0, int n, int r1, int nprev, double L, double mu, double sigma,
+                      double c) {
+  const long total = (long)r0 * n * r1;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(nn_gaussian_core_kernel, dim3(blocks), dim3(256), 0, ctx->stream, core, r0, n, r1, nprev, L,
+                     mu, sigma, c);
+  TTF_HIP(hipGetLastError());
+}
+
 void gaussian_factor(tt_ctx* ctx, zc* core, int n, double L, double mu, double sigma) {
   hipLaunchKernelGGL(gaussian_factor_kernel, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, core, n, L, mu,
                      sigma);

@@ -21,6 +21,17 @@ def ic_params(d, seed, mean_var=0.25, sigma_lo=0.3, sigma_hi=1.0):
     return mu, sigma
 
 
+def ic_params_tridiag(d, seed, mean_var=0.25, sigma_lo=0.3, sigma_hi=1.0, rho_max=0.3):
+    """Parameters of the Gaussian initial condition with tridiagonal
+    covariance: mu, sigma as ic_params, then the d-1 neighbour correlations
+    rho_k ~ U(-rho_max, rho_max), from one default_rng(seed) in that order."""
+    rng = np.random.default_rng(seed)
+    mu = rng.normal(0.0, np.sqrt(mean_var), size=d)
+    sigma = rng.uniform(sigma_lo, sigma_hi, size=d)
+    rho = rng.uniform(-rho_max, rho_max, size=max(d - 1, 0))
+    return mu, sigma, rho
+
+
 def random_tt(d, n, rank, seed, scale=None):
     """Random complex TT cores with i.i.d. standard complex Gaussian entries.
 

@@ -33,6 +33,8 @@ TT_C128 = 0
 TT_C64 = 1
 TT_OPT_JACOBI_MAX_SWEEPS = 1
 TT_OPT_QR_MIN_LEVEL = 2
+TT_OPT_JACOBI_FUSED = 3
+TT_OPT_JACOBI_WAIT_LIMIT = 4
 ORTH = {0: "none", 1: "right", 2: "left"}
 ERRORS = {
     -1: "TT_EINVAL",
@@ -186,6 +188,7 @@ _SIGS = {
     "tt_tensor_get_orth": (I, [P]),
     "tt_tensor_copy": (I, [P, P, P]),
     "tt_tensor_set_gaussian": (I, [P, P, PD, PD, D]),
+    "tt_tensor_set_gaussian_tridiag": (I, [P, P, PD, PD, PD, D, D, PI, ctypes.POINTER(RoundReport)]),
     "tt_op_create_burgers_hopf": (I, [P, I, I, D, D, ctypes.POINTER(P)]),
     "tt_op_create_burgers_hopf_scaled": (I, [P, I, I, D, D, D, ctypes.POINTER(P)]),
     "tt_op_destroy": (I, [P]),
@@ -451,6 +454,23 @@ class Tensor:
             raise ValueError(f"set_gaussian: need {self.d} means and widths")
         self.ctx.check(lib().tt_tensor_set_gaussian(self.ctx.h, self.h, _dp(mu), _dp(sigma), float(length)))
 
+    def set_gaussian_tridiag(self, mu, sigma, rho, length, eps=0.0, rmax=0):
+        """The rounding (eps, rmax as in tt_round) of the Gaussian
+        characteristic function with tridiagonal covariance; returns the
+        rounding report."""
+        mu = np.ascontiguousarray(mu, dtype=np.float64).ravel()
+        sigma = np.ascontiguousarray(sigma, dtype=np.float64).ravel()
+        rho = np.ascontiguousarray(rho, dtype=np.float64).ravel()
+        if mu.size < self.d or sigma.size < self.d or rho.size < self.d - 1:
+            raise ValueError(f"set_gaussian_tridiag: need {self.d} means and widths and {self.d - 1} correlations")
+        caps = _caps(rmax, self.d)
+        rep = RoundReport()
+        self.ctx.check(lib().tt_tensor_set_gaussian_tridiag(self.ctx.h, self.h, _dp(mu), _dp(sigma), _dp(rho),
+                                                            float(length), float(eps),
+                                                            _ip(caps) if caps is not None else None,
+                                                            ctypes.byref(rep)))
+        return _report(rep)
+
     def set_cdf_gaussian(self, sigma, box):
         """The CDF equation's initial condition (product of Gaussian CDFs)."""
         self.ctx.check(lib().tt_tensor_set_cdf_gaussian(self.ctx.h, self.h, float(sigma), float(box)))
@@ -543,19 +563,17 @@ def tt_sum(ctx, coefs, xs, z):
     ctx.check(lib().tt_sum(ctx.h, len(xs), _dp(c), ptrs, z.h))
 
 
-def tt_round(ctx, x, eps, rmax=0, report=True):
-    """rmax: an int for every bond (<= 0: no cap), or d+1 per-bond caps."""
+def _caps(rmax, d):
+    """None (no cap), or d+1 int32 per-bond caps from an int or a list."""
     if np.isscalar(rmax):
-        caps = None if int(rmax) <= 0 else np.full(x.d + 1, int(rmax), dtype=np.int32)
-    else:
-        caps = np.ascontiguousarray(rmax, dtype=np.int32).ravel()
-        if caps.size != x.d + 1:
-            raise ValueError("tt_round: need d+1 per-bond caps")
-    rep = RoundReport()
-    ctx.check(lib().tt_round(ctx.h, x.h, float(eps), _ip(caps) if caps is not None else None,
-                             ctypes.byref(rep) if report else None))
-    if not report:
-        return None
+        return None if int(rmax) <= 0 else np.full(d + 1, int(rmax), dtype=np.int32)
+    caps = np.ascontiguousarray(rmax, dtype=np.int32).ravel()
+    if caps.size != d + 1:
+        raise ValueError("need d+1 per-bond caps")
+    return caps
+
+
+def _report(rep):
     d = rep.d
     return {
         "ranks": list(rep.ranks[: d + 1]),
@@ -566,6 +584,15 @@ def tt_round(ctx, x, eps, rmax=0, report=True):
         "sv_last": [list(rep.sv_last[c]) for c in range(max(d - 1, 0))],
         "sigma_first_cut": list(rep.sigma_first_cut[: max(d - 1, 0)]),
     }
+
+
+def tt_round(ctx, x, eps, rmax=0, report=True):
+    """rmax: an int for every bond (<= 0: no cap), or d+1 per-bond caps."""
+    caps = _caps(rmax, x.d)
+    rep = RoundReport()
+    ctx.check(lib().tt_round(ctx.h, x.h, float(eps), _ip(caps) if caps is not None else None,
+                             ctypes.byref(rep) if report else None))
+    return _report(rep) if report else None
 
 
 def tt_step(ctx, op, f, dt, rmax, eps, mode=TT_APPLY_EXACT, sketch_rank=0, seed=0, precision=0,

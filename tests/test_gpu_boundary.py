@@ -57,7 +57,7 @@ def test_context_memory_comes_from_the_allocator():
     (tt.TT_APPLY_EXACT, 0, 0, tt.TT_PREC_FP64, tt.TT_C128),
     (tt.TT_APPLY_SKETCH, 40, 2, tt.TT_PREC_FP64, tt.TT_C128),
     (tt.TT_APPLY_SKETCH, 40, 0, tt.TT_PREC_FP16X3, tt.TT_C128),
-    (tt.TT_APPLY_SKETCH, 40, 2, tt.TT_PREC_FP64, tt.TT_C64),
+    (tt.TT_APPLY_SKETCH, 40, 1, tt.TT_PREC_FP16X3, tt.TT_C64),
 ])
 def test_steps_after_reserve_allocate_nothing(mode, width, power, prec, dtype):
     c = tt.Context(0)

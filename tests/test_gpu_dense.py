@@ -216,3 +216,49 @@ def test_jacobi_sweep_limit_is_an_error(ctx):
     assert 1 < sweeps < 60
     with pytest.raises(tt.TTError):
         ctx.set_option(tt.TT_OPT_JACOBI_MAX_SWEEPS, 0)
+
+
+@pytest.mark.parametrize("m,k", [(40, 200), (64, 64), (150, 133), (320, 320), (500, 257), (640, 640), (256, 1024)])
+def test_fused_sweeps_match_the_launch_per_round_form(ctx, m, k):
+    """The sweeps of one batch in one launch (workgroups meeting at grid
+    barriers between rounds) against one launch per round: the same
+    rotations in the same order, so bitwise the same factors and sweep
+    count, on a graded matrix."""
+    rng = np.random.default_rng(3 * m + k)
+    b = _cplx(rng, m, k) * np.logspace(0, -6, k)[None, :]
+    ctx.set_option(tt.TT_OPT_JACOBI_FUSED, 0)
+    try:
+        u0, s0, w0 = _svd(ctx, b)
+    finally:
+        ctx.set_option(tt.TT_OPT_JACOBI_FUSED, 1)
+    u1, s1, w1 = _svd(ctx, b)
+    # the count says where convergence was seen (a sweep without rotations,
+    # or the all-pairs test after a batch), which depends on the batch
+    # lengths (taken from the previous SVD of the size), not on the rotations
+    assert abs(w0 - w1) <= 1 and 1 < w1 < 60
+    assert np.array_equal(s0, s1) and np.array_equal(u0, u1)
+    sn = np.linalg.svd(b, compute_uv=False)
+    r = min(m, k)
+    assert np.abs(s1[:r] - sn).max() < 1e-12 * sn[0]
+
+
+def test_fused_barrier_wait_is_bounded(ctx):
+    """A workgroup of the fused form polls a bounded number of times at each
+    grid barrier.  With the limit forced to 0 from the host the workgroups
+    give up, every kernel returns normally and the SVD fails with
+    TT_ENOCONV; with the default limit the same context then computes the
+    SVD."""
+    rng = np.random.default_rng(9)
+    b = _cplx(rng, 256, 256)
+    ctx.set_option(tt.TT_OPT_JACOBI_WAIT_LIMIT, 0)
+    try:
+        with pytest.raises(tt.TTError) as e:
+            _svd(ctx, b)
+        assert e.value.code == tt.TT_ENOCONV
+    finally:
+        ctx.set_option(tt.TT_OPT_JACOBI_WAIT_LIMIT, 1 << 20)
+    _, s, w = _svd(ctx, b)
+    sn = np.linalg.svd(b, compute_uv=False)
+    assert 1 < w < 60 and np.abs(s - sn).max() < 1e-12 * sn[0]
+    with pytest.raises(tt.TTError):
+        ctx.set_option(tt.TT_OPT_JACOBI_FUSED, 2)

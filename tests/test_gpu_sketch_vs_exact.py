@@ -116,6 +116,8 @@ def test_full_width_sketch_is_the_exact_apply(env, which, power):
     e_apply = np.sqrt(max(lx2 - 2.0 * dot(ctx, y, lx).real + dot(ctx, y, y).real, 0.0) / lx2)
     print(f"{which}, width 1400, power {power}: |S(Lx) - Lx| / |Lx| = {e_apply:.2e} (expansion)")
     assert e_apply < 1e-6
+    # every pass count ends with a right-to-left pass
+    assert y.orth() == "right"
     if which == "trajectory":
         a, _ = rounded(ctx, lx, 1e-6, 0)
         b, _ = rounded(ctx, y, 1e-6, 0)
@@ -128,17 +130,17 @@ def test_full_width_sketch_is_the_exact_apply(env, which, power):
     lx.close()
 
 
-# plain form of the sketched apply: width 2.5 x cap with two power passes
-PLAIN_WIDTH, PLAIN_POWER = 80, 2
+# plain form of the sketched apply: width 2.5 x cap with one power pass
+PLAIN_WIDTH, PLAIN_POWER = 80, 1
 
 
 def test_width_and_power_against_exact_truncation(env):
     """Cap-limited truncation of the trajectory state (the FP64 workload's
     cap 32 and tolerance 1e-8): the table of distance and excess over widths
     40, 64 (twice the cap), 80 and 128 and 0..2 power passes.  Power passes
-    never make the sketch worse and bring the plain form (width 80, two
-    passes) within 2% of the optimal truncation error (excess) and within
-    2e-3 of T[L x] (distance)."""
+    never make the sketch worse and bring the plain form (width 80, one
+    pass) within 1% of the optimal truncation error (excess) and within
+    2.5e-3 of T[L x] (distance)."""
     ctx, op, xs = env
     x = xs["trajectory"]
     lx = exact(ctx, op, x)
@@ -158,11 +160,12 @@ def test_width_and_power_against_exact_truncation(env):
             t.close()
             y.close()
     for w in (40, 64, 80, 128):
-        assert table[w, 2][1] <= table[w, 0][1] + 1e-6
-        assert table[w, 2][0] <= table[w, 0][0]
+        for q in (1, 2):
+            assert table[w, q][1] <= table[w, 0][1] + 1e-6
+            assert table[w, q][0] <= table[w, 0][0]
     d_plain, x_plain = table[PLAIN_WIDTH, PLAIN_POWER]
-    assert x_plain < 0.02
-    assert d_plain < 2e-3
+    assert x_plain < 0.01
+    assert d_plain < 2.5e-3
     t_opt.close()
     lx.close()
 

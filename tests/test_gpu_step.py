@@ -250,3 +250,44 @@ def test_step_at_benchmark_shape_properties(ctx):
     # sketch accuracy only
     asym = float(np.abs(v[:100] - np.conj(v[100:])).max() / np.abs(v).max())
     assert asym < 1e-4, asym
+
+
+def test_tridiagonal_ic_matches_oracle_rounding(ctx):
+    """The rank-3 initial condition with tridiagonal covariance at d=20,
+    n=64 on [-6, 6] (seed 0): the device builds the exact nearest-neighbour
+    product (bond ranks 64) and rounds it to rank 3, against the oracle's
+    rounding of its own exact TT; the discarded tails are printed."""
+    d, n, length = 20, 64, 6.0
+    mu, sig, rho = inputs.ic_params_tridiag(d, 0)
+    f = tt.Tensor(ctx, d, n, 3)
+    rep = f.set_gaussian_tridiag(mu, sig, rho, length, 0.0, 3)
+    ref, info = tt_ref.tt_round(closed_forms.tridiag_gaussian_tt(mu, sig, rho, n, length), 0.0, 3)
+    tails = [np.sqrt(np.sum(s[3:] ** 2)) / info["norm"] for s in info["sigma"]]
+    gaps = [s[2] / s[3] for s in info["sigma"]]
+    print(f"rank-3 IC: largest discarded tail {max(tails):.2e} (relative), smallest gap {min(gaps):.1f}; "
+          f"device tails {max(rep['tail']) / rep['norm']:.2e}")
+    assert f.ranks() == [1] + [3] * (d - 1) + [1]
+    err = tt_ref.tt_diff_norm(f.get_cores(), ref) / tt_ref.tt_norm(ref)
+    assert err < 1e-10, err
+    assert max(tails) < 1e-2
+    f.close()
+
+
+def test_viscous_only_from_tridiagonal_ic_matches_exponential(ctx):
+    """Viscous-only RK4 (B = 0) at d=20, n=64, nu=0.02, dt=5e-4 from the
+    rank-3 tridiagonal-covariance IC: the semi-discrete exact solution is the
+    per-axis matrix exponential applied to the IC's cores (ranks kept)."""
+    d, n, length, nu, dt, steps = 20, 64, 6.0, 0.02, 5e-4, 40
+    mu, sig, rho = inputs.ic_params_tridiag(d, 0)
+    op = tt.Operator(ctx, d, n, length, nu, advection=0.0)
+    f = tt.Tensor(ctx, d, n, 8)
+    f.set_gaussian_tridiag(mu, sig, rho, length, 0.0, 3)
+    for _ in range(steps):
+        tt.tt_step(ctx, op, f, dt, 8, 1e-13, tt.TT_APPLY_SKETCH, 16, 1)
+    ic, _ = tt_ref.tt_round(closed_forms.tridiag_gaussian_tt(mu, sig, rho, n, length), 0.0, 3)
+    ex = closed_forms.viscous_semidiscrete_cores(ic, np.diag(galerkin.coefficient_D(d)), nu, dt * steps, n, length)
+    err = tt_ref.tt_diff_norm(f.get_cores(), ex) / tt_ref.tt_norm(ex)
+    print(f"viscous-only from the rank-3 IC, {steps} steps: ranks {max(f.ranks())}, error {err:.2e}")
+    assert err < 1e-10, err
+    f.close()
+    op.close()

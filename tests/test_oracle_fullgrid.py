@@ -4,7 +4,7 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from oracle import closed_forms, fd, fullgrid, galerkin
+from oracle import closed_forms, fd, fullgrid, galerkin, tt_ref
 from paper_2403_04946_amd import inputs
 
 
@@ -328,3 +328,45 @@ def test_truncated_step_without_truncation_is_rk4():
     a = fullgrid.rk4_step(f, 1e-2, prob.apply)
     c = fullgrid.truncated_rk4_step(f, 1e-2, prob.apply, 0.0)
     assert fullgrid.rel_l2(c, a) < 1e-13
+
+
+def test_tridiagonal_ic_tt_is_the_quadratic_form():
+    # the nearest-neighbour product TT against the characteristic function
+    # evaluated from the covariance matrix; rho = 0 is the rank-one IC
+    d, n, length = 4, 9, 3.0
+    mu, sig, rho = inputs.ic_params_tridiag(d, 5)
+    full_tt = fullgrid.tt_to_full(closed_forms.tridiag_gaussian_tt(mu, sig, rho, n, length))
+    ref = fullgrid.tridiag_gaussian_ic(mu, sig, rho, n, length)
+    assert fullgrid.rel_l2(full_tt, ref) < 1e-14
+    assert tt_ref.tt_ranks(closed_forms.tridiag_gaussian_tt(mu, sig, rho, n, length)) == [1, n, n, n, 1]
+    zero = fullgrid.tridiag_gaussian_ic(mu, sig, np.zeros(d - 1), n, length)
+    assert fullgrid.rel_l2(zero, fullgrid.gaussian_ic(mu, sig, n, length)) < 1e-15
+    # a characteristic function: phi(0) = 1 (odd n), |phi| <= 1, phi(-a) = conj phi(a)
+    c = (n - 1) // 2
+    assert abs(ref[(c,) * d] - 1.0) < 1e-15
+    assert np.abs(ref).max() <= 1.0 + 1e-15
+    assert np.abs(ref[::-1, ::-1, ::-1, ::-1] - np.conj(ref)).max() < 1e-15
+    # the correlations matter: a dropped sign or a shifted index changes it
+    assert fullgrid.rel_l2(fullgrid.tridiag_gaussian_ic(mu, sig, -rho, n, length), ref) > 1e-3
+    assert fullgrid.rel_l2(fullgrid.tridiag_gaussian_ic(mu, sig, rho[::-1], n, length), ref) > 1e-3
+
+
+def test_viscous_only_tridiagonal_continuous_second_order_in_h():
+    # with B = 0 the exact solution from a correlated Gaussian is the same
+    # kind of Gaussian with mu, sigma scaled by exp(-nu kappa^2 t) and the
+    # correlations unchanged; the grid RK4 solution converges to it at
+    # second order in h
+    d, length, nu, tend = 2, 6.0, 0.5, 0.5
+    b = np.zeros((d, d, d))
+    dm = galerkin.coefficient_D(d)
+    mu, sig, rho = np.array([0.6, -0.4]), np.array([0.5, 0.7]), np.array([0.28])
+    errs = []
+    for n in (33, 65, 129):
+        prob = fullgrid.Problem(b, dm, nu, n, length)
+        f = fullgrid.tridiag_gaussian_ic(mu, sig, rho, n, length)
+        for _ in range(25):
+            f = fullgrid.rk4_step(f, tend / 25, prob.apply)
+        mt, st, rt = closed_forms.viscous_continuous_tridiag(mu, sig, rho, nu, tend)
+        errs.append(fullgrid.rel_l2(f, fullgrid.tridiag_gaussian_ic(mt, st, rt, n, length)))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[0] < 1e-2 and all(1.7 < r < 2.4 for r in rates), (errs, rates)
