@@ -32,7 +32,13 @@ It shares no code, header, table or constant with the HIP path.  Inputs
 in as arrays; the oracle draws no random numbers itself.
 
 Parity status per function is stated in each module header.  Every function
-here is pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_*.py``
-against a closed form, an invariant, a hand-derived value or a brute-force
-computation; none is "parity unpinned".
+here is pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_*.py``,
+directly or through the pinned function that calls it (helpers such as the
+one-axis propagator or the shifted solve), against a closed form, an
+invariant, a hand-derived value or a brute-force computation.  What the
+pins cannot fix is where the truncated steps place their truncations:
+that is a reading of Sec. 4.1 shared with the device path (each
+truncation's arithmetic is pinned: a step without truncation is the
+classical scheme, and a truncation is the full-grid TT-SVD, which equals
+the TT rounding).
 """

@@ -14,7 +14,14 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
    the semi-discrete system is the per-axis matrix exponential applied to
    each TT core (ranks preserved).
 
-3. Deterministic initial state.  The Hopf characteristic functional of a
+3. Correlated Gaussian initial condition.  The characteristic function of
+   amplitudes u ~ N(mu, Sigma) with tridiagonal Sigma is a product of
+   one-axis and nearest-neighbour factors, an exact TT with bond ranks n;
+   under the viscous-only flow it stays such a Gaussian with mu and sigma
+   scaled per axis and the correlations unchanged (Sigma(t) = S Sigma S,
+   S = exp(nu D t) diagonal).
+
+4. Deterministic initial state.  The Hopf characteristic functional of a
    deterministic solution is exp(i <u, theta>) (Sec. 1 / Sec. 5 definition
    of Phi).  Projected on the Fourier modes: if u(0) = mu exactly, then
    phi(a,t) = exp(i a . u(t)) where u(t) solves the Galerkin ODE
