@@ -171,9 +171,18 @@ int tt_ctx_reset_stats(tt_ctx* ctx);
  * are bitwise the same.  TT_OPT_JACOBI_WAIT_LIMIT (0 .. 2^40, default
  * 2^20): polls a workgroup of the fused form makes at one barrier before it
  * gives up; every workgroup then returns and the call fails with
- * TT_ENOCONV (0 forces that path for tests).  TT_EINVAL for an unknown
- * option or a value out of range. */
-enum { TT_OPT_JACOBI_MAX_SWEEPS = 1, TT_OPT_QR_MIN_LEVEL = 2, TT_OPT_JACOBI_FUSED = 3, TT_OPT_JACOBI_WAIT_LIMIT = 4 };
+ * TT_ENOCONV (0 forces that path for tests).  TT_OPT_QR_WIDE_PANELS (0 or
+ * 1, default 0): the Cholesky form of the orthogonalisations takes panels
+ * of 64 columns (1: the factor and its inverse formed once per pass, then
+ * a triangular update) or 32 (0); results agree to rounding.  TT_EINVAL for an
+ * unknown option or a value out of range. */
+enum {
+  TT_OPT_JACOBI_MAX_SWEEPS = 1,
+  TT_OPT_QR_MIN_LEVEL = 2,
+  TT_OPT_JACOBI_FUSED = 3,
+  TT_OPT_JACOBI_WAIT_LIMIT = 4,
+  TT_OPT_QR_WIDE_PANELS = 5
+};
 int tt_ctx_set_option(tt_ctx* ctx, int option, long long value);
 int tt_ctx_get_stats(tt_ctx* ctx, const char* kernel, double* total_ms,
                      double* flops, double* bytes, long long* launches);

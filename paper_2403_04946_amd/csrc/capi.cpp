@@ -188,19 +188,25 @@ void ptsqr_inplace(tt_ctx* ctx, int m, int k, zc* q, long ldq, zc* r, long ldr, 
 // dependent on the earlier ones to working accuracy, or zero) by a Gaussian
 // vector, to be left out of R; factor the panel (Q1 R1); then project once
 // more.
-// level 0 factors the panel by Cholesky QR twice, levels 1 and 2 by the
-// Householder TSQR; levels 0 and 1 finish with the Pythagorean shortcut
+// level 0 factors the panel by Cholesky QR twice (panels of 32 columns, or
+// of 64 with TT_OPT_QR_WIDE_PANELS 1), levels 1 and 2 by the Householder
+// TSQR (panels of 32); levels 0 and 1 finish with the Pythagorean shortcut
 // (Cholesky of I - W2^H W2, see bcgs_pip), level 2 factors the reprojected
 // panel again with the TSQR and projects and factors it a third time.  Shortcuts raise *bad when they are not safe
 // for the data (bad may be null at level 2).
 void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* bad) {
   require(m >= k && k >= 1, TT_EINVAL, "qr: need m >= k >= 1");
-  const int NB = pt_max_cols();
+  // level 0 takes panels of 64 columns (Cholesky factor and inverse in one
+  // workgroup, then a triangular update), levels 1 and 2 panels of 32
+  // (the Householder leaves' width)
+  const bool wide = level == 0 && ctx->qr_wide;
+  const int NB = wide ? WIDE_NB : pt_max_cols();
   fill_zero(ctx, r, (long)k * k);
-  // small work: W2, T (k x NB), R1, R2, Rpp (NB x NB), flags, norm partials
-  const size_t kb = (size_t)k * NB, bb = (size_t)NB * NB;
+  // small work: W2, T (k x NB), R1, R2, Rpp, Gm, Ra, Rinv (NB x NB), flags,
+  // norm partials; sized for the widest panel
+  const size_t kb = (size_t)k * WIDE_NB, bb = (size_t)WIDE_NB * WIDE_NB;
   const int G = bcgs_flag_groups(m);
-  zc* W2 = (zc*)ctx->get_ws("bcgs_small", sizeof(zc) * (2 * kb + 6 * bb) + sizeof(double) * ((size_t)(G + 1) * NB));
+  zc* W2 = (zc*)ctx->get_ws("bcgs_small", sizeof(zc) * (2 * kb + 6 * bb) + sizeof(double) * ((size_t)(G + 1) * WIDE_NB));
   zc* T = W2 + kb;
   zc* R1 = T + kb;
   zc* R2 = R1 + bb;
@@ -209,7 +215,7 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* ba
   zc* Ra = Gm + bb;
   zc* Rinv = Ra + bb;
   int* flags = (int*)(Rinv + bb);
-  double* part = (double*)(Rinv + bb) + NB;  // NB ints fit in NB doubles
+  double* part = (double*)(Rinv + bb) + WIDE_NB;  // WIDE_NB ints fit in WIDE_NB doubles
   const uint64_t rseed = 0x243F6A8885A308D3ull;
   for (int p0 = 0; p0 < k; p0 += NB) {
     const int nb = std::min(NB, k - p0);
@@ -221,6 +227,30 @@ void bcgs_qr_inplace(tt_ctx* ctx, int m, int k, zc* q, zc* r, int level, int* ba
     }
     bcgs_flag(ctx, Ap, m, m, nb, Rp, k, p0, flags, part);
     bcgs_random(ctx, Ap, m, m, nb, flags, rseed, p0);
+    if (wide) {
+      // Cholesky QR twice, the factor and its inverse formed once per pass;
+      // then, past the first panel, the second projection and the
+      // Pythagorean factor of I - W2^H W2 (as bcgs_pip, absolute pivot test)
+      zgemm(ctx, OPC, OPN, nb, nb, m, Z(1), Ap, m, 0, Ap, m, 0, Z(0), Gm, nb, 0);
+      chol_factor_wide(ctx, Gm, nb, nb, 1e-12, false, nullptr, Ra, nb, nullptr, Rinv, bad);
+      panel_trmm_wide(ctx, Ap, m, m, nb, Rinv);
+      zgemm(ctx, OPC, OPN, nb, nb, m, Z(1), Ap, m, 0, Ap, m, 0, Z(0), Gm, nb, 0);
+      chol_factor_wide(ctx, Gm, nb, nb, 0.5, false, Ra, R1, nb, nullptr, Rinv, bad);
+      panel_trmm_wide(ctx, Ap, m, m, nb, Rinv);
+      if (p0 == 0) {
+        bcgs_put_diag(ctx, r, k, R1, nb, flags);
+        continue;
+      }
+      zgemm(ctx, OPC, OPN, p0, nb, m, Z(1), q, m, 0, Ap, m, 0, Z(0), W2, p0, 0);
+      zgemm(ctx, OPN, OPN, m, nb, p0, Z(-1), q, m, 0, W2, p0, 0, Z(1), Ap, m, 0);
+      set_identity(ctx, Gm, nb, nb, nb);
+      zgemm(ctx, OPC, OPN, nb, nb, p0, Z(-1), W2, p0, 0, W2, p0, 0, Z(1), Gm, nb, 0);
+      chol_factor_wide(ctx, Gm, nb, nb, 1e-2, true, R1, r + (long)k * p0 + p0, k, flags, Rinv, bad);
+      zgemm(ctx, OPN, OPN, p0, nb, nb, Z(1), W2, p0, 0, R1, nb, 0, Z(0), T, p0, 0);
+      bcgs_masked_add(ctx, Rp, k, T, p0, p0, nb, flags);
+      panel_trmm_wide(ctx, Ap, m, m, nb, Rinv);
+      continue;
+    }
     if (level == 0) {
       // Cholesky QR twice: Y = Y Ra^{-1}, then again with Rb; R1 = Rb Ra
       // (a column dependent within the panel makes a pivot fail the test)
@@ -1156,6 +1186,11 @@ int tt_ctx_set_option(tt_ctx* ctx, int option, long long value) {
   if (option == TT_OPT_JACOBI_MAX_SWEEPS) {
     require(value >= 1 && value <= 60, TT_EINVAL, "tt_ctx_set_option: Jacobi sweep limit must be 1..60");
     ctx->jacobi_max_sweeps = (int)value;
+    return TT_OK;
+  }
+  if (option == TT_OPT_QR_WIDE_PANELS) {
+    require(value == 0 || value == 1, TT_EINVAL, "tt_ctx_set_option: the wide-panel switch is 0 or 1");
+    ctx->qr_wide = (int)value;
     return TT_OK;
   }
   if (option == TT_OPT_JACOBI_FUSED) {

@@ -20,6 +20,9 @@ using zc = double2;  // complex double, interleaved (re, im)
 // this size serves every GEMM of a context.
 constexpr size_t SPLITK_WS_ELEMS = size_t(1) << 22;
 
+// panel width of the fast QR form
+constexpr int WIDE_NB = 64;
+
 // ------------------------------------------------------------------ errors
 struct Error {
   int code;
@@ -120,6 +123,7 @@ struct tt_ctx {
   std::map<std::pair<int, int>, int> jacobi_sweeps_seen;
   int jacobi_max_sweeps = 60;   // sweep limit of every Jacobi SVD (tt_ctx_set_option)
   int qr_min_level = 0;         // most economical QR form allowed (tt_ctx_set_option)
+  int qr_wide = 0;              // 64-column panels in the fast QR form (tt_ctx_set_option)
   int jacobi_fused = 1;         // sweeps of a Jacobi SVD in one launch per batch (tt_ctx_set_option)
   long jacobi_wait_limit = 1L << 20;  // polls of a fused-sweep barrier before it gives up
 
@@ -290,6 +294,11 @@ void bcgs_pip(tt_ctx* ctx, const zc* W2, int p0, int nb, const zc* R1, zc* Ro, z
 void chol_solve(tt_ctx* ctx, zc* Y, long ldy, int m, int nb, const zc* G, double tau, const zc* Rprev, zc* Rout,
                 int* bad);
 void panel_trmm(tt_ctx* ctx, zc* Z, long ldz, int m, int nb, const zc* Rinv);
+// the same for panels of up to 64 columns, and the Cholesky factor and
+// inverse of an up to 64 x 64 Gram matrix in one workgroup
+void panel_trmm_wide(tt_ctx* ctx, zc* Z, long ldz, int m, int nb, const zc* Rinv);
+void chol_factor_wide(tt_ctx* ctx, const zc* G, long ldg, int nb, double tau, bool absolute, const zc* Rprev,
+                      zc* Rout, long ldo, const int* flags, zc* Rinv, int* bad);
 void zero_ints(tt_ctx* ctx, int* x, int n);
 void bcgs_random(tt_ctx* ctx, zc* Qp, long ldq, int m, int nb, const int* flags, uint64_t seed, int tag);
 void bcgs_masked_add(tt_ctx* ctx, zc* Rd, long ldr, const zc* W, long ldw, int rows, int nb, const int* flags);

@@ -269,19 +269,17 @@ __global__ __launch_bounds__(256) void colnorm_partial_kernel(const zc* __restri
 __global__ __launch_bounds__(1024) void bcgs_flag_kernel(const double* __restrict__ part, int G, int nb,
                                                          const zc* __restrict__ W, long ldw, int p0,
                                                          int* __restrict__ flags) {
-  // 32 lanes per column (two DPP rows), fixed summation order
-  const int c = threadIdx.x >> 5, l = threadIdx.x & 31;
+  // 16 lanes (one DPP row) per column, up to 64 columns, fixed summation order
+  const int c = threadIdx.x >> 4, l = threadIdx.x & 15;
   if (c >= nb) return;
   double res2 = 0, w2 = 0;
-  for (int g = l; g < G; g += 32) res2 += part[(long)g * nb + c];
-  for (int i = l; i < p0; i += 32) {
+  for (int g = l; g < G; g += 16) res2 += part[(long)g * nb + c];
+  for (int i = l; i < p0; i += 16) {
     const zc w = W[i + ldw * c];
     w2 += w.x * w.x + w.y * w.y;
   }
   res2 = row16_sum(res2);
   w2 = row16_sum(w2);
-  res2 += __shfl_xor(res2, 16, 64);
-  w2 += __shfl_xor(w2, 16, 64);
   const double tot = res2 + w2;
   if (l == 0) flags[c] = (!(res2 > 1e-26 * tot) || !(res2 > 0.0)) ? 1 : 0;
 }
@@ -676,6 +674,265 @@ void panel_trmm(tt_ctx* ctx, zc* Z, long ldz, int m, int nb, const zc* Rinv) {
   if (nb > PT_COLS) fail(TT_EINVAL, "panel_trmm: panel too wide");
   KTimer kt(ctx, "panel_trmm", 4.0 * (double)m * nb * nb, 32.0 * (double)m * nb);
   hipLaunchKernelGGL(panel_trmm_kernel, dim3((m + 63) / 64), dim3(256), 0, ctx->stream, Z, ldz, m, nb, Rinv);
+  TTF_HIP(hipGetLastError());
+}
+
+// ----------------------------------------------- 64-column panels
+// Cholesky factor and inverse of an nb x nb Hermitian matrix G (ld ldg,
+// nb <= 64) by one workgroup of 1024 threads, each owning the entries
+// (i, j) with i = t % 64 and j = t / 64 + 16 u, u < 4.  G = R^H R, R upper
+// triangular: step r subtracts conj(G[r][a]) G[r][b] / G[r][r] from the
+// trailing upper triangle (one barrier per step; the pivot of the next step
+// is prepared by the thread that last updated it) and row r of R is the
+// untouched row r of G scaled by 1/sqrt(pivot).  The inverse is built by
+// recursive doubling on diagonal blocks of size h = 1 .. 32 (the
+// off-diagonal block of [A B; 0 C]^{-1} is -A^{-1} (B C^{-1})), B C^{-1}
+// kept in the free lower triangle.  Near the identity (every |G - I| <=
+// 1e-10) R = I + U and R^{-1} = I - U to first order (U the upper part of
+// G - I with half its diagonal), the neglected terms below (64e-10)^2.
+// A pivot d of step r fails when d <= tau dg_r or d <= 0, dg_r the
+// original diagonal (or 1 with `absolute`); *bad is then set (bad may be
+// null) and 1 taken in its place.  Outputs: Rinv (ld nb) and Rout (ld ldo)
+// = R Rprev (or R without Rprev), both upper, with the columns flagged in
+// `flags` (may be null) zeroed in Rout.
+__global__ __launch_bounds__(1024) void chol_factor_wide_kernel(const zc* __restrict__ G, long ldg, int nb, double tau,
+                                                                int absolute, const zc* __restrict__ Rprev,
+                                                                zc* __restrict__ Rout, long ldo,
+                                                                const int* __restrict__ flags, zc* __restrict__ Rinv,
+                                                                int* __restrict__ bad) {
+  extern __shared__ double2 wide_lds[];
+  zc (*A)[65] = reinterpret_cast<zc (*)[65]>(wide_lds);             // G, then R (upper) and B C^{-1} (lower)
+  zc (*Ri)[65] = reinterpret_cast<zc (*)[65]>(wide_lds + 64 * 65);  // R^{-1}
+  __shared__ double piv[64][2];
+  __shared__ double dg[64], rs[64];
+  __shared__ double emax[16];
+  const int t = threadIdx.x, i = t & 63, j0 = t >> 6;
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + 16 * u;
+    A[i][j] = (i < nb && j < nb) ? G[i + ldg * j] : make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  if (t < 64) dg[t] = (t < nb && !absolute) ? G[t + ldg * t].x : 1.0;
+  double e = 0.0;
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + 16 * u;
+    if (i < nb && j < nb) {
+      const zc g = G[i + ldg * j];
+      e = fmax(e, fmax(fabs(g.x - (i == j ? 1.0 : 0.0)), fabs(g.y)));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) e = fmax(e, __shfl_xor(e, off, 64));
+  if ((t & 63) == 0) emax[t >> 6] = e;
+  __syncthreads();
+  double em = 0.0;
+  for (int w = 0; w < 16; ++w) em = fmax(em, emax[w]);
+  if (em <= 1e-10) {
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + 16 * u;
+      zc rv = make_double2(0.0, 0.0), iv = make_double2(0.0, 0.0);
+      const zc g = A[i][j];
+      if (i < j && j < nb) {
+        rv = g;
+        iv = make_double2(-g.x, -g.y);
+      } else if (i == j) {
+        const double h = (i < nb) ? 0.5 * (g.x - 1.0) : 0.0;
+        rv = make_double2(1.0 + h, 0.0);
+        iv = make_double2(1.0 - h, 0.0);
+      }
+      Ri[i][j] = iv;
+      A[i][j] = rv;  // each thread reads and writes only its own entries here
+    }
+  } else {
+    auto pivot = [&](int r, double d) {
+      const bool ok = d > tau * dg[r] && d > 0.0;
+      if (!ok && bad) *bad = 1;
+      const double is = 1.0 / sqrt(ok ? d : 1.0);
+      piv[r][0] = is * is;
+      piv[r][1] = is;
+    };
+    if (t == 0 && nb > 0) pivot(0, A[0][0].x);
+    __syncthreads();
+    for (int r = 0; r < nb; ++r) {
+      const double id = piv[r][0];
+      if (i > r && i < nb) {
+        const zc x = A[r][i];
+        for (int u = 0; u < 4; ++u) {
+          const int j = j0 + 16 * u;
+          if (j >= i && j < nb) {
+            const zc y = A[r][j];
+            zc g = A[i][j];
+            g.x -= (x.x * y.x + x.y * y.y) * id;  // conj(x) y / d
+            g.y -= (x.x * y.y - x.y * y.x) * id;
+            A[i][j] = g;
+            if (i == r + 1 && j == r + 1) pivot(r + 1, g.x);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // R from the untouched rows; identity beyond nb
+    if (t < 64) rs[t] = (t < nb) ? piv[t][1] : 1.0;
+    __syncthreads();
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + 16 * u;
+      zc v = make_double2(0.0, 0.0);
+      if (i == j)
+        v = make_double2(1.0 / rs[i], 0.0);
+      else if (i < j && j < nb)
+        v = make_double2(A[i][j].x * rs[i], A[i][j].y * rs[i]);
+      if (i <= j) A[i][j] = v;
+      Ri[i][j] = (i == j) ? make_double2(rs[i], 0.0) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int h = 1; h < 64; h *= 2) {
+      bool blk[4];
+      for (int u = 0; u < 4; ++u) {  // T = B C^{-1}, stored transposed in the lower triangle
+        const int j = j0 + 16 * u;
+        const int s0 = (i / (2 * h)) * (2 * h);
+        blk[u] = i < s0 + h && j >= s0 + h && j < s0 + 2 * h;
+        if (blk[u]) {
+          double sr = 0, si = 0;
+          for (int q = s0 + h; q <= j; ++q) {
+            const zc a = A[i][q], b = Ri[q][j];
+            sr += a.x * b.x - a.y * b.y;
+            si += a.x * b.y + a.y * b.x;
+          }
+          A[j][i] = make_double2(sr, si);
+        }
+      }
+      __syncthreads();
+      for (int u = 0; u < 4; ++u) {  // X = -A^{-1} T
+        const int j = j0 + 16 * u;
+        if (blk[u]) {
+          const int s0 = (i / (2 * h)) * (2 * h);
+          double sr = 0, si = 0;
+          for (int q = i; q < s0 + h; ++q) {
+            const zc a = Ri[i][q], b = A[j][q];
+            sr += a.x * b.x - a.y * b.y;
+            si += a.x * b.y + a.y * b.x;
+          }
+          Ri[i][j] = make_double2(-sr, -si);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + 16 * u;
+    if (i < nb && j < nb) Rinv[i + (long)nb * j] = Ri[i][j];
+  }
+  if (Rprev) {  // Rprev into the inverse's place
+    __syncthreads();
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + 16 * u;
+      Ri[i][j] = (i < nb && j < nb) ? Rprev[i + (long)nb * j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+  }
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + 16 * u;
+    if (i >= nb || j >= nb) continue;
+    zc v = make_double2(0.0, 0.0);
+    if (i <= j && !(flags && flags[j])) {
+      if (Rprev) {
+        double sr = 0, si = 0;
+        for (int q = i; q <= j; ++q) {
+          const zc a = A[i][q], b = Ri[q][j];
+          sr += a.x * b.x - a.y * b.y;
+          si += a.x * b.y + a.y * b.x;
+        }
+        v = make_double2(sr, si);
+      } else {
+        v = A[i][j];
+      }
+    }
+    Rout[i + ldo * j] = v;
+  }
+}
+
+constexpr size_t WIDE_FACTOR_LDS = 2 * 64 * 65 * sizeof(zc);
+
+void chol_factor_wide(tt_ctx* ctx, const zc* G, long ldg, int nb, double tau, bool absolute, const zc* Rprev,
+                      zc* Rout, long ldo, const int* flags, zc* Rinv, int* bad) {
+  if (nb < 1 || nb > 64) fail(TT_EINVAL, "chol_factor_wide: panel width must be 1..64");
+  static bool attr_set = false;
+  if (!attr_set) {
+    TTF_HIP(hipFuncSetAttribute((const void*)chol_factor_wide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)WIDE_FACTOR_LDS));
+    attr_set = true;
+  }
+  KTimer kt(ctx, "chol_factor", (4.0 / 3.0) * 8.0 * nb * (double)nb * nb, 32.0 * nb * (double)nb, true);
+  TTF_LAUNCH(kt, chol_factor_wide_kernel, dim3(1), dim3(1024), WIDE_FACTOR_LDS, ctx->stream, G, ldg, nb, tau,
+             absolute ? 1 : 0, Rprev, Rout, ldo, flags, Rinv, bad);
+  TTF_HIP(hipGetLastError());
+}
+
+// Z <- Z Rinv for the m x nb panel Z (ld ldz, nb <= 64), Rinv upper nb x nb
+// (ld nb, zero below the diagonal): 64 rows per workgroup, the rows and
+// Rinv staged in LDS; thread (a, b) forms the 4 x 4 outputs of rows
+// a + 16 u and columns b + 16 v (consecutive lanes read consecutive rows,
+// and the Rinv entries a wavefront reads are four distinct words)
+__global__ __launch_bounds__(256) void panel_trmm_wide_kernel(zc* __restrict__ Z, long ldz, int m, int nb,
+                                                              const zc* __restrict__ Rinv) {
+  extern __shared__ double2 wide_lds[];
+  zc (*tile)[65] = reinterpret_cast<zc (*)[65]>(wide_lds);            // tile[c][r]
+  zc (*Ri)[65] = reinterpret_cast<zc (*)[65]>(wide_lds + 64 * 65);   // Ri[q][c]
+  const long row0 = (long)blockIdx.x * 64;
+  const int t = threadIdx.x;
+  const int rows = (m - row0 < 64) ? (int)(m - row0) : 64;
+  for (int e = t; e < 64 * nb; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    tile[c][r] = (r < rows) ? Z[row0 + r + ldz * c] : make_double2(0.0, 0.0);
+  }
+  for (int e = t; e < nb * nb; e += 256) {
+    const int q = e % nb, c = e / nb;
+    Ri[q][c] = Rinv[e];
+  }
+  __syncthreads();
+  const int a = t & 15, b = t >> 4;
+  double ar[4][4], ai[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ar[u][v] = ai[u][v] = 0.0;
+  for (int q = 0; q < nb; ++q) {
+    zc x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = tile[q][a + 16 * u];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) y[v] = (b + 16 * v < nb) ? Ri[q][b + 16 * v] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        ar[u][v] += x[u].x * y[v].x - x[u].y * y[v].y;
+        ai[u][v] += x[u].x * y[v].y + x[u].y * y[v].x;
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = a + 16 * u;
+    if (r >= rows) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = b + 16 * v;
+      if (c < nb) Z[row0 + r + ldz * c] = make_double2(ar[u][v], ai[u][v]);
+    }
+  }
+}
+
+void panel_trmm_wide(tt_ctx* ctx, zc* Z, long ldz, int m, int nb, const zc* Rinv) {
+  if (nb < 1 || nb > 64) fail(TT_EINVAL, "panel_trmm_wide: panel width must be 1..64");
+  if (m <= 0) return;
+  static bool attr_set = false;
+  if (!attr_set) {
+    TTF_HIP(hipFuncSetAttribute((const void*)panel_trmm_wide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)WIDE_FACTOR_LDS));
+    attr_set = true;
+  }
+  KTimer kt(ctx, "panel_trmm", 4.0 * (double)m * nb * nb, 32.0 * (double)m * nb, true);
+  TTF_LAUNCH(kt, panel_trmm_wide_kernel, dim3((m + 63) / 64), dim3(256), WIDE_FACTOR_LDS, ctx->stream, Z, ldz, m, nb,
+             Rinv);
   TTF_HIP(hipGetLastError());
 }
 

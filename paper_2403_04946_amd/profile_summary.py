@@ -5,7 +5,8 @@
         kernel family are also summed into one line per family).
     python -m paper_2403_04946_amd.profile_summary pmc <counter_collection.csv> <counter> [kernel-substring]
         Per-kernel-family totals and per-dispatch averages of one counter
-        (summed over its hardware instances), in KiB as rocprofv3 reports it.
+        (summed over its hardware instances; FETCH_SIZE and WRITE_SIZE in KiB
+        as rocprofv3 reports them, other counters as counts).
 """
 import collections
 import csv
@@ -58,7 +59,8 @@ def pmc(path, counter, sub=None):
             continue
         fam[f][0] += 1
         fam[f][1] += v
-    print(f"| kernel family | dispatches | {counter} total KiB | per dispatch KiB |")
+    unit = " KiB" if counter in ("FETCH_SIZE", "WRITE_SIZE") else ""
+    print(f"| kernel family | dispatches | {counter} total{unit} | per dispatch{unit} |")
     print("|---|---:|---:|---:|")
     for k, (n, v) in sorted(fam.items(), key=lambda kv: -kv[1][1]):
         print(f"| `{k}` | {n} | {v:.0f} | {v / n:.1f} |")

@@ -262,3 +262,32 @@ def test_fused_barrier_wait_is_bounded(ctx):
     assert 1 < w < 60 and np.abs(s - sn).max() < 1e-12 * sn[0]
     with pytest.raises(tt.TTError):
         ctx.set_option(tt.TT_OPT_JACOBI_FUSED, 2)
+
+
+@pytest.mark.parametrize("m,k", [(8192, 64), (10240, 80), (16384, 128), (4096, 320), (300, 300), (2000, 17)])
+def test_wide_panels_match_narrow_panels(ctx, m, k):
+    """The Cholesky form with panels of 64 columns (one factor and inverse
+    per pass) against panels of 32, on the shapes of the benchmark's
+    factorisations and on a square and a narrow one: both satisfy the
+    defining identities, and their R factors agree to rounding (the QR of a
+    full-rank matrix is unique up to column phases, fixed here by R's real
+    positive diagonal)."""
+    rng = np.random.default_rng(m + k)
+    a = _cplx(rng, m, k) * np.logspace(0, -4, k)[None, :]
+    out = {}
+    for wide in (1, 0):
+        ctx.set_option(tt.TT_OPT_QR_WIDE_PANELS, wide)
+        try:
+            ctx.reset_stats()
+            q, r = _qr(ctx, a)
+            out[wide] = (q, r, _fallbacks(ctx))
+        finally:
+            ctx.set_option(tt.TT_OPT_QR_WIDE_PANELS, 0)
+        _check_qr(a, q, r)
+        assert np.all(np.abs(np.diag(r).imag) < 1e-12 * np.abs(np.diag(r)).max())
+        assert np.all(np.diag(r).real > 0)
+    assert out[1][2] == 0 and out[0][2] == 0  # the fast form sufficed
+    rn = np.abs(out[0][1]).max()
+    assert np.abs(out[1][1] - out[0][1]).max() < 1e-11 * rn
+    with pytest.raises(tt.TTError):
+        ctx.set_option(tt.TT_OPT_QR_WIDE_PANELS, 2)

@@ -41,23 +41,26 @@ def _qr(ctx, a):
     return Q.cpu().numpy(), R.cpu().numpy()
 
 
-@pytest.mark.parametrize("level", [0, 1, 2])
+@pytest.mark.parametrize("level,wide", [(0, 1), (0, 0), (1, 1), (2, 1)])
 @pytest.mark.parametrize("m,k,rank,graded", [(1000, 576, 230, True), (1000, 576, 230, False), (700, 200, 100, False),
                                              (4096, 300, 45, True)])
-def test_qr_with_dependence_inside_panels(ctx, level, m, k, rank, graded):
+def test_qr_with_dependence_inside_panels(ctx, level, wide, m, k, rank, graded):
     """A = G1 G2 of rank `rank` (not a multiple of the panel width, so a
     panel holds independent and dependent columns), optionally with a
-    graded spectrum; every starting form of the factorisation."""
+    graded spectrum; every starting form of the factorisation (the Cholesky
+    form with panels of 64 and of 32 columns)."""
     rng = np.random.default_rng(m + k + rank)
     g1 = _cplx(rng, m, rank)
     if graded:
         g1 *= np.logspace(0, -9, rank)[None, :]
     a = g1 @ _cplx(rng, rank, k)
     ctx.set_option(tt.TT_OPT_QR_MIN_LEVEL, level)
+    ctx.set_option(tt.TT_OPT_QR_WIDE_PANELS, wide)
     try:
         q, r = _qr(ctx, a)
     finally:
         ctx.set_option(tt.TT_OPT_QR_MIN_LEVEL, 0)
+        ctx.set_option(tt.TT_OPT_QR_WIDE_PANELS, 0)
     na = np.linalg.norm(a)
     assert np.linalg.norm(a - q @ r) < 1e-12 * na
     assert np.abs(q.conj().T @ q - np.eye(k)).max() < 1e-12
