@@ -579,10 +579,12 @@ int tt_solve_shifted(tt_ctx* ctx, const tt_op* op, double c, const tt_tensor* b,
  * operator, i.e. left Gaussian TT sketches of widths[k] (Philox key seed)
  * and a right-to-left sweep of LQ factorisations; y is right-orthonormal
  * with rank k <= widths[k] (widths: d+1 ints, ends ignored, each within
- * y's capacity).  *rel_err (may be NULL) receives ||x - y|| / ||x|| from
- * exact TT inner products (||x||^2 + ||y||^2 - 2 Re <x, y>), the a
- * posteriori check that decides whether the deterministic rounding is
- * needed.  Synchronous. */
+ * y's capacity).  *rel_err (may be NULL) receives an estimate of
+ * ||x - y|| / ||x|| by an independent Gaussian TT sketch Omega of 64 rows
+ * (bond rank 64, its own Philox key): ||Omega x - Omega y|| / ||Omega x||,
+ * from chain contractions only (no factorisation, no cancellation of
+ * squares); the a posteriori check that decides whether the deterministic
+ * rounding is needed.  Synchronous. */
 int tt_round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y,
                         double* rel_err);
 

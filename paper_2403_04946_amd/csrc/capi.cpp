@@ -1843,7 +1843,8 @@ void check_solve_opts(const tt_solve_opts& o) {
 }
 
 void randomized_into(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y);
-double sum_rel_error(tt_ctx* ctx, int npieces, const zc* coef, const tt_tensor* const* pieces, const tt_tensor* y);
+double sketch_rel_error(tt_ctx* ctx, int npieces, const zc* coef, const tt_tensor* const* pieces,
+                        const tt_tensor* y, uint64_t seed);
 
 int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step_opts* opts, tt_step_report* rep) {
   if (!ctx || !op || !f || !opts) return TT_EINVAL;
@@ -1960,7 +1961,7 @@ int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step
     }
     tt_tensor* y = pooled(ctx, slot, d, n, interior_caps(d, std::max(wmax, rmax)));
     randomized_into(ctx, x, w.data(), opts->seed ^ (0xA5A5A5A5ull * salt), y);
-    const double err = sum_rel_error(ctx, npieces, coef, pieces, y);
+    const double err = sketch_rel_error(ctx, npieces, coef, pieces, y, opts->seed ^ (0x5BD1E995ull * salt));
     ++learned_used;
     learned_err = std::max(learned_err, err);
     if (err <= opts->learned_tol) {
@@ -2239,36 +2240,70 @@ void randomized_into(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_
   apply_sketch(ctx, op, x, y, l, seed, TT_PREC_FP64, widths);
 }
 
-double round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y) {
-  randomized_into(ctx, x, widths, seed, y);
-  const zc xx = dot_tensors(ctx, x, x), yy = dot_tensors(ctx, y, y), xy = dot_tensors(ctx, x, y);
-  const double e2 = xx.x + yy.x - 2.0 * xy.x;
-  return xx.x > 0.0 ? std::sqrt(std::max(0.0, e2) / xx.x) : 0.0;
+// A posteriori error of a randomised rounding y of x = sum_i coef_i p_i by
+// an independent Gaussian TT sketch: Omega maps a TT to LSK_WIDTH numbers
+// through random cores of bond rank LSK_WIDTH (Philox, its own key), and the
+// estimate is ||Omega x - Omega y|| / ||Omega x||, Omega x = sum_i coef_i
+// Omega p_i.  Only chain contractions (GEMMs, no factorisation), piece by
+// piece, so no product touches the wide concatenated sum, and the
+// difference is formed between two vectors: no cancellation of squares.
+// For a fixed TT z, ||Omega z||^2 / LSK_WIDTH estimates ||z||^2 without
+// bias; the ratio's spread is measured against the exact difference norm.
+constexpr int LSK_WIDTH = 64;
+
+void sketch_vector(tt_ctx* ctx, const tt_tensor* x, uint64_t seed, zc alpha, zc* acc, bool first) {
+  const int d = x->d, s = LSK_WIDTH;
+  int rmax = 1;
+  for (int k = 0; k <= d; ++k) rmax = std::max(rmax, x->rank[k]);
+  size_t vmax = 1, omax = 1;
+  for (int k = 0; k < d; ++k) {
+    const int sp = k == 0 ? 1 : s;
+    vmax = std::max(vmax, (size_t)sp * x->nk[k] * x->rank[k + 1]);
+    omax = std::max(omax, (size_t)sp * x->nk[k] * s);
+  }
+  zc* C = (zc*)ctx->get_ws("lsk_C", sizeof(zc) * (size_t)s * rmax);
+  zc* C2 = (zc*)ctx->get_ws("lsk_C2", sizeof(zc) * (size_t)s * rmax);
+  zc* V = (zc*)ctx->get_ws("lsk_V", sizeof(zc) * vmax);
+  zc* Om = (zc*)ctx->get_ws("lsk_Om", sizeof(zc) * omax);
+  const zc one = Z(1);
+  TTF_HIP(hipMemcpyAsync(C, &one, sizeof(zc), hipMemcpyHostToDevice, ctx->stream));
+  for (int k = 0; k < d; ++k) {
+    const int sp = k == 0 ? 1 : s, r0 = x->rank[k], r1 = x->rank[k + 1], n = x->nk[k];
+    // V = C (sp x r0) times the core (r0 x n r1): (sp n) x r1
+    zgemm(ctx, OPN, OPN, sp, n * r1, r0, Z(1), C, sp, 0, x->core[k], r0, 0, Z(0), V, sp, 0);
+    sketch_core(ctx, Om, (long)sp * n * s, seed, k, 1.0 / std::sqrt((double)s));
+    // C' = Omega_k^T V: s x r1 (at the last site r1 = 1: the sketch vector)
+    const bool last = k == d - 1;
+    zgemm(ctx, OPT, OPN, s, r1, sp * n, last ? alpha : Z(1), Om, (long)sp * n, 0, V, (long)sp * n, 0,
+          last && !first ? Z(1) : Z(0), last ? acc : C2, s, 0);
+    std::swap(C, C2);
+  }
 }
 
-// ||x - y|| / ||x|| for x = sum_i coef_i pieces_i, expanded over the pieces
-// so that no inner product involves the wide concatenated sum:
-// ||x||^2 = sum_ij conj(c_i) c_j <p_i, p_j>, <x, y> = sum_i conj(c_i) <p_i, y>.
-// Norms of orthogonalised pieces (and of y, right-orthonormal) come from one
-// core. The expansion cancels: it resolves errors down to about 1e-7.
-double sum_rel_error(tt_ctx* ctx, int npieces, const zc* coef, const tt_tensor* const* pieces, const tt_tensor* y) {
-  double xx = 0.0, xy = 0.0;
-  for (int i = 0; i < npieces; ++i) {
-    const double ci2 = coef[i].x * coef[i].x + coef[i].y * coef[i].y;
-    const double ni = tensor_norm(ctx, pieces[i]);
-    xx += ci2 * ni * ni;
-    for (int j = i + 1; j < npieces; ++j) {
-      const zc g = dot_tensors(ctx, pieces[i], pieces[j]);
-      // 2 Re(conj(c_i) c_j g)
-      const zc cc = {coef[i].x * coef[j].x + coef[i].y * coef[j].y, coef[i].x * coef[j].y - coef[i].y * coef[j].x};
-      xx += 2.0 * (cc.x * g.x - cc.y * g.y);
-    }
-    const zc h = dot_tensors(ctx, pieces[i], y);
-    xy += coef[i].x * h.x + coef[i].y * h.y;  // Re(conj(c_i) h)
+double sketch_rel_error(tt_ctx* ctx, int npieces, const zc* coef, const tt_tensor* const* pieces,
+                        const tt_tensor* y, uint64_t seed) {
+  const int s = LSK_WIDTH;
+  zc* acc = (zc*)ctx->get_ws("lsk_acc", sizeof(zc) * 2 * s);
+  const uint64_t key = seed ^ 0xD1B54A32D192ED03ull;  // independent of the rounding's sketch
+  for (int i = 0; i < npieces; ++i) sketch_vector(ctx, pieces[i], key, coef[i], acc, i == 0);
+  sketch_vector(ctx, y, key, Z(1), acc + s, true);
+  zc* h = (zc*)ctx->host_scratch(sizeof(zc) * 2 * s);
+  TTF_HIP(hipMemcpyAsync(h, acc, sizeof(zc) * 2 * s, hipMemcpyDeviceToHost, ctx->stream));
+  TTF_HIP(hipStreamSynchronize(ctx->stream));
+  double num = 0.0, den = 0.0;
+  for (int j = 0; j < s; ++j) {
+    const double dr = h[j].x - h[s + j].x, di = h[j].y - h[s + j].y;
+    num += dr * dr + di * di;
+    den += h[j].x * h[j].x + h[j].y * h[j].y;
   }
-  const double ny = tensor_norm(ctx, y);
-  const double e2 = xx + ny * ny - 2.0 * xy;
-  return xx > 0.0 ? std::sqrt(std::max(0.0, e2) / xx) : 0.0;
+  return den > 0.0 ? std::sqrt(num / den) : 0.0;
+}
+
+double round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y) {
+  randomized_into(ctx, x, widths, seed, y);
+  const zc one = Z(1);
+  const tt_tensor* px = x;
+  return sketch_rel_error(ctx, 1, &one, &px, y, seed);
 }
 
 int tt_round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y,
