@@ -519,6 +519,91 @@ def main_learned(args):
     print(json.dumps(result), flush=True)
 
 
+def main_learned_full(args):
+    """Learned form at its own configuration: the predictor trained on
+    bond-step samples of plain trajectories at seeded d in 20..80 (n=64 on
+    [-6, 6], cap 64, eps 1e-6, dt 5e-4, nu log-uniform 0.005..0.1), then a
+    trajectory at d=100, n=128 on [-8, 8], nu=0.005, cap 128, eps 1e-6,
+    dt 2e-4 from the seeded Gaussian IC, stepped plain and learned.  Per
+    step it records the share of bonds whose rank sits at the cap (there the
+    rounding is cap-limited and the learned form runs plain), the
+    predictor's rank error, the randomised roundings tried and accepted,
+    the largest sketch estimate of their error, and the step times."""
+    import numpy as np
+    import torch
+
+    from paper_2403_04946_amd import inputs, learned, tt
+
+    torch.cuda.init()
+    ctx = tt.Context(0)
+    ell = 80
+    t0 = time.perf_counter()
+    xs, ys = [], []
+    train = inputs.batch_instances(args.train_instances, 31, d_range=(20, 80), n_choices=(64,),
+                                   nu_range=(0.005, 0.1), cap_range=(64, 64))
+    for i, inst in enumerate(train):
+        op = tt.Operator(ctx, inst["d"], 64, 6.0, inst["nu"])
+        f = tt.Tensor(ctx, inst["d"], 64, 64)
+        f.set_gaussian(inst["mu"], inst["sigma"], 6.0)
+        recs = learned.run_trajectory(ctx, op, f, args.train_steps, 5e-4, 64, 1e-6, ell, inst["nu"], seed=i)
+        x, y = learned.samples_from_records(recs)
+        xs.append(x)
+        ys.append(y)
+        f.close()
+        op.close()
+        print(f"bench: training trajectory {i + 1}/{len(train)} (d={inst['d']}, {x.shape[0]} samples) done",
+              file=sys.stderr, flush=True)
+    x, y = np.concatenate(xs), np.concatenate(ys)
+    capture_s = time.perf_counter() - t0
+    # targets are rank / cap: the network trained at cap 64 predicts a share
+    # of the cap, read at the evaluation's cap 128
+    pred = learned.RankPredictor(ctx, 64, max_batch=max(4096, x.shape[0]), seed=1)
+    t0 = time.perf_counter()
+    l0, l1 = pred.fit(x, y)
+    train_s = time.perf_counter() - t0
+    print(f"bench: predictor trained on {x.shape[0]} samples", file=sys.stderr, flush=True)
+    pred.rmax = 128
+    d, n, length, nu, cap, eps, dt = 100, 128, 8.0, 0.005, 128, 1e-6, 2e-4
+    mu, sig = inputs.ic_params(d, 5)
+    out = {}
+    for form in ("plain", "learned"):
+        op = tt.Operator(ctx, d, n, length, nu)
+        f = tt.Tensor(ctx, d, n, cap)
+        f.set_gaussian(mu, sig, length)
+        steps = []
+
+        def note(s, rec):
+            inner = rec["ranks"][1:-1]
+            steps.append({"step": s + 1, "wall_s": rec["wall"], "max_rank": max(inner),
+                          "bonds_at_cap": sum(1 for r in inner if r >= cap) / len(inner),
+                          "widths_predicted": rec["widths"] is not None,
+                          "randomised_roundings": rec["learned_used"], "fallbacks": rec["learned_fallback"],
+                          "largest_estimate": rec["learned_err"]})
+            print(f"bench: {form} d=100 step {s + 1}: max rank {max(inner)}, "
+                  f"{steps[-1]['bonds_at_cap']:.2f} of the bonds at the cap, {rec['wall']:.1f} s",
+                  file=sys.stderr, flush=True)
+
+        recs = learned.run_trajectory(ctx, op, f, args.steps, dt, cap, eps, ell, nu,
+                                      predictor=pred if form == "learned" else None, seed=3, on_step=note)
+        if form == "plain":
+            xt, yt = learned.samples_from_records(recs)
+            rank_err = float(np.abs(pred.predict(xt) - yt).mean()) if xt.shape[0] else None
+        out[form] = steps
+        f.close()
+        op.close()
+    result = {
+        "form": "learned, full configuration",
+        "training": {"instances": len(train), "d_range": [20, 80], "n": 64, "cap": 64, "steps": args.train_steps,
+                     "samples": int(x.shape[0]), "loss_before": l0, "loss_after": l1, "capture_s": capture_s,
+                     "train_s": train_s},
+        "evaluation": {"d": d, "n": n, "L": length, "nu": nu, "cap": cap, "eps": eps, "dt": dt,
+                       "sketch_width": ell, "predictor_mean_abs_rank_error": rank_err},
+        "plain": out["plain"], "learned": out["learned"], "learned_tol": 1e-6,
+    }
+    pred.close()
+    print(json.dumps(result), flush=True)
+
+
 TRAJECTORIES = {
     # d, n, L, nu, cap, eps, dt, sketch width
     "d20": (20, 64, 6.0, 0.02, 32, 1e-8, 5e-4, 80),
@@ -700,7 +785,8 @@ def main():
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-error-report", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["metric", "batched", "learned", "cdf", "trajectory"], default="metric",
+    ap.add_argument("--form", choices=["metric", "batched", "learned", "learned-full", "cdf", "trajectory"],
+                    default="metric",
                     help="batched: the batched form on uneven instances; learned: the learned form against the "
                          "plain one on tolerance-limited trajectories; trajectory: a logged run from the initial "
                          "condition (each its own JSON line)")
@@ -737,6 +823,9 @@ def main():
         return
     if args.form == "learned":
         main_learned(args)
+        return
+    if args.form == "learned-full":
+        main_learned_full(args)
         return
     if args.form == "cdf":
         main_cdf(args)
