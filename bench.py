@@ -265,99 +265,125 @@ def main_batched(args):
     """Batched form: uneven independent instances (the batched workload's
     distribution: d uniform 8..64, n in {32, 64, 128}, nu log-uniform
     1e-3..1e-1, rank caps 16..96), each a seeded random TT with every
-    interior rank at its cap, sketch width cap + 16, split-FP16x3 sketch
-    contractions, dt = 2e-4, eps = 1e-6, stepped concurrently by
-    tt_step_batch with one context (host thread and stream) per instance,
-    against the same instances stepped one after another."""
+    interior rank at its cap, sketch width cap + 16 with one power pass,
+    split-FP16x3 sketch pass, dt = 2e-4, eps = 1e-6.  The instances run in
+    waves sized to HBM: ordered longest first by a cost estimate (d n cap^3)
+    and packed greedily into waves of at most --wave instances whose
+    estimated temporaries (45 x 16 d n cap^2 bytes each: the final RK4
+    combination of rank 5 cap and its rounding) stay within --wave-gb; a
+    wave steps all its instances concurrently by tt_step_batch, one context
+    (host thread and stream) per instance, and frees them before the next.
+    Instances of one wave have similar cost, so few wait on a straggler.
+    The reference steps the instances of the first and the last wave one
+    after another."""
     import torch
 
     from paper_2403_04946_amd import inputs, tt
 
     torch.cuda.init()
     specs = inputs.batch_instances(args.instances, 4)
-    nctx = len(specs)
-    ctxs = [tt.Context(0) for _ in range(nctx)]
-    objs = []
-    for i, sp in enumerate(specs):
-        c = ctxs[i]
+    n = len(specs)
+    cost = [sp["d"] * sp["n"] * sp["cap"] ** 3 for sp in specs]
+    mem = [45 * 16 * sp["d"] * sp["n"] * sp["cap"] ** 2 for sp in specs]
+    order = sorted(range(n), key=lambda i: -cost[i])
+    waves, cur, cur_mem = [], [], 0
+    for i in order:
+        if cur and (len(cur) == args.wave or cur_mem + mem[i] > args.wave_gb * 1e9):
+            waves.append(cur)
+            cur, cur_mem = [], 0
+        cur.append(i)
+        cur_mem += mem[i]
+    if cur:
+        waves.append(cur)
+    print(f"bench: {n} instances in {len(waves)} waves of {[len(w) for w in waves]}", file=sys.stderr, flush=True)
+
+    def build(i):
+        sp = specs[i]
+        c = tt.Context(0)
         op = tt.Operator(c, sp["d"], sp["n"], 8.0, sp["nu"])
         f = tt.Tensor(c, sp["d"], sp["n"], sp["cap"])
         f.set_cores(inputs.random_tt(sp["d"], sp["n"], sp["cap"], sp["seed"]))
-        objs.append((c, op, f))
-    n = len(specs)
-    caps = [sp["cap"] for sp in specs]
-    ells = [sp["cap"] + 16 for sp in specs]
-    seeds = [sp["seed"] for sp in specs]
+        return c, op, f
 
-    def batched(sel):
+    def step(objs, sel):
         st = tt.tt_step_batch([objs[i][0] for i in sel], [objs[i][1] for i in sel], [objs[i][2] for i in sel],
-                              [DT] * len(sel), [caps[i] for i in sel], [EPS] * len(sel), tt.TT_APPLY_SKETCH,
-                              [ells[i] for i in sel], [seeds[i] for i in sel], precision=tt.TT_PREC_FP16X3)
+                              [DT] * len(sel), [specs[i]["cap"] for i in sel], [EPS] * len(sel),
+                              tt.TT_APPLY_SKETCH, [specs[i]["cap"] + 16 for i in sel], [specs[i]["seed"] for i in sel],
+                              precision=tt.TT_PREC_FP16X3, power=args.sketch_power)
         if any(st):
             why = {i: tt.lib().tt_last_error(objs[i][0].h).decode() for i, v in zip(sel, st) if v}
             free, total = torch.cuda.mem_get_info()
             raise RuntimeError(f"batched step failed: {st} {why}; device memory free {free / 1e9:.1f} of "
                                f"{total / 1e9:.1f} GB")
 
-    everyone = list(range(n))
-    for w in range(args.warmup):
-        batched(everyone)
-        print(f"bench: batched warm-up {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    # tiles from the autotuner: the GEMM shapes of one batched step over all
-    # instances, the heaviest tuned (untimed set-up; the sequential
-    # reference below uses the same table)
-    from paper_2403_04946_amd import autotune
+    def release(objs):
+        for c, op, f in objs.values():
+            f.close()
+            op.close()
+            c.close()
 
-    t0 = time.perf_counter()
-    for c in ctxs:
-        c.reset_stats()
-        c.set_profiling(True, shapes=True)
-    batched(everyone)
-    shapes = {}
-    classes = {}
-    for c in ctxs:
-        st = c.dump_stats()
-        autotune.gemm_shapes(st, shapes)
-        for k, v in st.items():
-            if k in KERNEL_BOUND:
-                classes.setdefault(k, {"ms": 0.0})["ms"] += v["ms"]
-        c.set_profiling(False)
-        c.reset_stats()
-    # the roofline kernel: the class with the most time in that step; its
-    # launches (one in PROFILE_EVERY) are event-timed in the timed step
-    dom = dominant(classes) if classes else "zgemm"
-    tuned = autotune.tune(ctxs[0], shapes, top=args.autotune_top or 64)
-    tune_s = time.perf_counter() - t0
-    print(f"bench: autotuned {len(tuned)} GEMM shapes in {tune_s:.1f} s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    for c in ctxs:
-        c.reset_stats()
-        c.set_profile_filter(dom)
-        c.set_profile_sampling(PROFILE_EVERY)
-        c.set_profiling(True)
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        batched(everyone)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
+    dom, tuned, tune_s = None, [], 0.0
     kd = {"ms": 0.0, "flops": 0.0, "bytes": 0.0, "launches": 0}
-    for c in ctxs:
-        st = c.stats(dom)
-        for k in kd:
-            kd[k] += st[k]
-        c.set_profiling(False)
-        c.set_profile_filter(None)
-        c.set_profile_sampling(1)
-    print("bench: batched steps done", file=sys.stderr, flush=True)
-    # the same instances one after another, each alone on its context
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        for i in everyone:
-            batched([i])
-    torch.cuda.synchronize()
-    ts = time.perf_counter() - t0
-    print("bench: sequential steps done", file=sys.stderr, flush=True)
+    wave_s, seq_s = [], {}
+    for wi, wave in enumerate(waves):
+        objs = {i: build(i) for i in wave}
+        for w in range(args.warmup):
+            step(objs, wave)
+        if dom is None:
+            # the roofline kernel: the class with the most time in one batched
+            # step of the first wave; tiles from the autotuner for its GEMM
+            # shapes (untimed set-up)
+            from paper_2403_04946_amd import autotune
+
+            t0 = time.perf_counter()
+            for c, _, _ in objs.values():
+                c.reset_stats()
+                c.set_profiling(True, shapes=True)
+            step(objs, wave)
+            shapes, classes = {}, {}
+            for c, _, _ in objs.values():
+                st = c.dump_stats()
+                autotune.gemm_shapes(st, shapes)
+                for k, v in st.items():
+                    if k in KERNEL_BOUND:
+                        classes.setdefault(k, {"ms": 0.0})["ms"] += v["ms"]
+                c.set_profiling(False)
+            dom = dominant(classes) if classes else "zgemm"
+            if args.autotune:
+                tuned = autotune.tune(objs[wave[0]][0], shapes, top=args.autotune_top or 64)
+            tune_s = time.perf_counter() - t0
+        for c, _, _ in objs.values():
+            c.reset_stats()
+            c.set_profile_filter(dom)
+            c.set_profile_sampling(PROFILE_EVERY)
+            c.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in range(args.steps):
+            step(objs, wave)
+        torch.cuda.synchronize()
+        wave_s.append(time.perf_counter() - t0)
+        for c, _, _ in objs.values():
+            st = c.stats(dom)
+            for k in kd:
+                kd[k] += st[k]
+            c.set_profiling(False)
+            c.set_profile_filter(None)
+            c.set_profile_sampling(1)
+        if wi in (0, len(waves) - 1) and not args.no_sequential:
+            t0 = time.perf_counter()
+            for s_ in range(args.steps):
+                for i in wave:
+                    step(objs, [i])
+            torch.cuda.synchronize()
+            seq_s[wi] = time.perf_counter() - t0
+        release(objs)
+        print(f"bench: wave {wi + 1}/{len(waves)} ({len(wave)} instances) {wave_s[-1]:.1f} s", file=sys.stderr,
+              flush=True)
+    tb = sum(wave_s)
     stages = 4 * n * args.steps
+    seq = {f"wave {wi + 1}": {"instances": len(waves[wi]), "batched_s": wave_s[wi], "sequential_s": t,
+                              "speedup": t / wave_s[wi]} for wi, t in seq_s.items()}
     result = {
         "metric": "instance RK stages/sec, batched form",
         "value": stages / tb,
@@ -373,13 +399,14 @@ def main_batched(args):
         "data": "synthetic",
         "config": {
             "workload": ("uneven independent Burgers-Hopf instances: d 8..64, n in {32,64,128}, nu 1e-3..1e-1, "
-                         "caps 16..96, saturated ranks, split-FP16x3 sketch contractions"),
-            "instances": n, "contexts": nctx, "dt": DT, "eps": EPS,
+                         "caps 16..96, saturated ranks, split-FP16x3 sketch pass"),
+            "instances": n, "dt": DT, "eps": EPS, "sketch_power": args.sketch_power,
+            "waves": [len(w) for w in waves], "wave_limit": args.wave, "wave_gb": args.wave_gb,
             "instance_shapes": [[sp["d"], sp["n"], sp["cap"]] for sp in specs],
         },
+        "wave_seconds": wave_s,
         "gemm_autotune": {"shapes_tuned": len(tuned), "seconds": tune_s},
-        "sequential_reference": {"value": stages / ts, "unit": "instance-stages/s", "seconds": ts},
-        "speedup_over_sequential": ts / tb,
+        "sequential_reference": seq,
         # launches of the class from all instances overlap in time: the
         # figure is per launch (summed durations), not the chip's aggregate
         "roofline": roofline(dom, kd, with_traffic=False) if kd["launches"] else None,
@@ -800,6 +827,10 @@ def main():
                          "has |phi| <= 1; the grid L2 norm itself grows as the distribution concentrates)")
     ap.add_argument("--max-seconds", type=float, default=240.0, help="trajectory: wall-clock limit")
     ap.add_argument("--instances", type=int, default=16)
+    ap.add_argument("--wave", type=int, default=16, help="batched: instances per wave at most")
+    ap.add_argument("--wave-gb", type=float, default=200.0,
+                    help="batched: estimated temporaries per wave at most (GB)")
+    ap.add_argument("--no-sequential", action="store_true", help="batched: skip the one-after-another reference")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the GEMM launch-shape rule (by default the shapes of one step of each timed form "
                          "are tuned before timing)")
