@@ -291,3 +291,31 @@ def test_viscous_only_from_tridiagonal_ic_matches_exponential(ctx):
     assert err < 1e-10, err
     f.close()
     op.close()
+
+
+def test_step_temporaries_follow_the_operator_ranks(ctx):
+    """The step's cached temporaries are keyed by the operator's bond ranks:
+    stepping with the viscous-only operator (ranks 2) and then, on the same
+    context and shape, with the full operator (ranks up to 2d + 2) in exact
+    mode works, and matches the same full step on a fresh context."""
+    d, n, length, nu, dt, cap = 5, 16, 4.0, 0.05, 1e-3, 8
+    mu, sig = inputs.ic_params(d, 2)
+    visc = tt.Operator(ctx, d, n, length, nu, advection=0.0)
+    full_op = tt.Operator(ctx, d, n, length, nu)
+    a = tt.Tensor(ctx, d, n, cap)
+    a.set_gaussian(mu, sig, length)
+    tt.tt_step(ctx, visc, a, dt, cap, 1e-12, tt.TT_APPLY_EXACT)
+    b = tt.Tensor(ctx, d, n, cap)
+    b.set_gaussian(mu, sig, length)
+    tt.tt_step(ctx, full_op, b, dt, cap, 1e-12, tt.TT_APPLY_EXACT)
+    fresh = make_ctx()
+    op2 = tt.Operator(fresh, d, n, length, nu)
+    c = tt.Tensor(fresh, d, n, cap)
+    c.set_gaussian(mu, sig, length)
+    tt.tt_step(fresh, op2, c, dt, cap, 1e-12, tt.TT_APPLY_EXACT)
+    assert b.ranks() == c.ranks()
+    assert tt_ref.tt_diff_norm(b.get_cores(), c.get_cores()) <= 1e-13 * tt_ref.tt_norm(c.get_cores())
+    for t in (a, b, visc, full_op, c, op2):
+        t.close()
+    fresh.sync()
+    fresh.close()
