@@ -807,6 +807,9 @@ def main():
     ap.add_argument("--sketch-power", type=int, default=1,
                     help="subspace-iteration passes of every sketched apply (0 = the plain range finder)")
     ap.add_argument("--precision", choices=sorted(PRECISIONS), default="fp16x3")
+    ap.add_argument("--mixed-passes", type=int, choices=(0, 1), default=1,
+                    help="1: the reduced precision in every pass of the sketched apply but the last (0: in the "
+                         "Gaussian sketch pass only)")
     ap.add_argument("--error-steps", type=int, default=2,
                     help="trajectory steps from the initial condition in the error report")
     ap.add_argument("--no-fp64-reference", action="store_true")
@@ -871,6 +874,7 @@ def main():
 
     torch.cuda.init()
     ctx = tt.Context(0)
+    ctx.set_option(tt.TT_OPT_SKETCH_MIXED_PASSES, args.mixed_passes)
     op = tt.Operator(ctx, D, N, LEN, NU)
     prec = PRECISIONS[args.precision]
     f0 = tt.Tensor(ctx, D, N, CAP)

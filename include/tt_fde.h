@@ -174,14 +174,19 @@ int tt_ctx_reset_stats(tt_ctx* ctx);
  * TT_ENOCONV (0 forces that path for tests).  TT_OPT_QR_WIDE_PANELS (0 or
  * 1, default 0): the Cholesky form of the orthogonalisations takes panels
  * of 64 columns (1: the factor and its inverse formed once per pass, then
- * a triangular update) or 32 (0); results agree to rounding.  TT_EINVAL for an
+ * a triangular update) or 32 (0); results agree to rounding.
+ * TT_OPT_SKETCH_MIXED_PASSES (0 or 1, default 1): with power passes, the
+ * reduced precision of a sketched apply covers the Gaussian sketch pass
+ * only (0) or every pass but the last (1); the last pass, the projection
+ * whose result is truncated, is FP64.  TT_EINVAL for an
  * unknown option or a value out of range. */
 enum {
   TT_OPT_JACOBI_MAX_SWEEPS = 1,
   TT_OPT_QR_MIN_LEVEL = 2,
   TT_OPT_JACOBI_FUSED = 3,
   TT_OPT_JACOBI_WAIT_LIMIT = 4,
-  TT_OPT_QR_WIDE_PANELS = 5
+  TT_OPT_QR_WIDE_PANELS = 5,
+  TT_OPT_SKETCH_MIXED_PASSES = 6
 };
 int tt_ctx_set_option(tt_ctx* ctx, int option, long long value);
 int tt_ctx_get_stats(tt_ctx* ctx, const char* kernel, double* total_ms,

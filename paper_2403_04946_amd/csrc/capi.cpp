@@ -555,12 +555,11 @@ void apply_exact(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y)
 void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y, int l, uint64_t seed,
                   int precision, const int* widths = nullptr, int power = 0) {
   // the sketch contractions in plain FP64 or a split 16-bit form (mixed).
-  // With power passes only the Gaussian sketch pass takes `precision`: its
-  // arithmetic error only changes the random start of the subspace
-  // iteration, while in the later passes it perturbs the bases found and
-  // the projection itself, which at cap-limited cuts the truncation
-  // amplifies (split-FP16x3 there puts stage outputs 2e-5 from FP64 at
-  // d = 50; in the sketch pass alone, 4e-6)
+  // With power passes the last pass, the projection whose result the
+  // truncation takes, is FP64: its arithmetic error enters the projection
+  // itself, which cap-limited cuts amplify (split-FP16x3 there puts stage
+  // outputs 2e-5 from FP64 at d = 50), while the earlier passes only find
+  // the bases (with them in split-FP16x3, 4e-8)
   int prec = precision;
   auto gemm = [ctx, &prec](tt_ctx*, int opA, int opB, int M, int N, int K, zc alpha, const zc* A, long lda, long sA,
                            const zc* B, long ldb, long sB, zc beta, zc* C, long ldc, long sC, int batch) {
@@ -737,8 +736,12 @@ void apply_sketch(tt_ctx* ctx, const tt_op* op, const tt_tensor* x, tt_tensor* y
       right_sketch_pass();
     else
       sketch_pass();
-    prec = power > 0 ? TT_PREC_FP64 : precision;
     for (int p = 0; p <= power; ++p) {
+      // reduced precision in the Gaussian pass, and with
+      // TT_OPT_SKETCH_MIXED_PASSES 1 in every power pass but the last; the
+      // last pass (the projection itself) always in the requested
+      // precision when there are no power passes, else FP64
+      prec = (power == 0 || (ctx->sketch_mixed_passes && p < power)) ? precision : TT_PREC_FP64;
       if (((p & 1) != 0) != from_right)
         left_to_right();
       else
@@ -1186,6 +1189,11 @@ int tt_ctx_set_option(tt_ctx* ctx, int option, long long value) {
   if (option == TT_OPT_JACOBI_MAX_SWEEPS) {
     require(value >= 1 && value <= 60, TT_EINVAL, "tt_ctx_set_option: Jacobi sweep limit must be 1..60");
     ctx->jacobi_max_sweeps = (int)value;
+    return TT_OK;
+  }
+  if (option == TT_OPT_SKETCH_MIXED_PASSES) {
+    require(value == 0 || value == 1, TT_EINVAL, "tt_ctx_set_option: the mixed-passes switch is 0 or 1");
+    ctx->sketch_mixed_passes = (int)value;
     return TT_OK;
   }
   if (option == TT_OPT_QR_WIDE_PANELS) {

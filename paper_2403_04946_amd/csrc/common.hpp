@@ -123,6 +123,7 @@ struct tt_ctx {
   std::map<std::pair<int, int>, int> jacobi_sweeps_seen;
   int jacobi_max_sweeps = 60;   // sweep limit of every Jacobi SVD (tt_ctx_set_option)
   int qr_min_level = 0;         // most economical QR form allowed (tt_ctx_set_option)
+  int sketch_mixed_passes = 1;  // reduced precision in the power passes but the last (tt_ctx_set_option)
   int qr_wide = 0;              // 64-column panels in the fast QR form (tt_ctx_set_option)
   int jacobi_fused = 1;         // sweeps of a Jacobi SVD in one launch per batch (tt_ctx_set_option)
   long jacobi_wait_limit = 1L << 20;  // polls of a fused-sweep barrier before it gives up

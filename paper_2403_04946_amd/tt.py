@@ -36,6 +36,7 @@ TT_OPT_QR_MIN_LEVEL = 2
 TT_OPT_JACOBI_FUSED = 3
 TT_OPT_JACOBI_WAIT_LIMIT = 4
 TT_OPT_QR_WIDE_PANELS = 5
+TT_OPT_SKETCH_MIXED_PASSES = 6
 ORTH = {0: "none", 1: "right", 2: "left"}
 ERRORS = {
     -1: "TT_EINVAL",
