@@ -196,3 +196,38 @@ def test_mixed_precision_is_rejected_when_unknown(ctx):
     for t in (x, y, f):
         t.close()
     op.close()
+
+
+@pytest.mark.parametrize("mixed_passes", [1, 0])
+def test_mixed_power_pass_stage_within_gate(ctx, op, mixed_passes):
+    """The plain form's sketched apply has one power pass; in the mixed form
+    the split-FP16x3 products cover the Gaussian sketch pass and (option 1,
+    the default) the power pass, the last pass being FP64.  One stage from
+    the saturated input at d=50 (derivative rounded, combination rounded)
+    against the FP64 form from the same input and seeds: within the gate."""
+    x = tt.Tensor(ctx, D, N, CAP)
+    x.set_cores(inputs.random_tt(D, N, CAP, 0))
+    ctx.set_option(tt.TT_OPT_SKETCH_MIXED_PASSES, mixed_passes)
+    outs = {}
+    try:
+        for prec in (tt.TT_PREC_FP64, tt.TT_PREC_FP16X3):
+            k = tt.Tensor(ctx, D, N, max(ELL, CAP))
+            tt.tt_apply(ctx, op, x, k, tt.TT_APPLY_SKETCH, ELL, 5, precision=prec, power=1)
+            tt.tt_round(ctx, k, EPS, CAP, report=False)
+            y = tt.Tensor(ctx, D, N, 2 * CAP)
+            tt.tt_axpy(ctx, 1.0, x, 0.5 * DT, k, y)
+            tt.tt_round(ctx, y, EPS, CAP, report=False)
+            outs[prec] = (k, y)
+    finally:
+        ctx.set_option(tt.TT_OPT_SKETCH_MIXED_PASSES, 1)
+    ek = _rel_tt(ctx, outs[tt.TT_PREC_FP16X3][0], outs[tt.TT_PREC_FP64][0])
+    ey = _rel_tt(ctx, outs[tt.TT_PREC_FP16X3][1], outs[tt.TT_PREC_FP64][1])
+    print(f"mixed passes {mixed_passes}: derivative {ek:.2e}, stage output {ey:.2e}")
+    assert ey < GATE
+    assert ek < 1e-3
+    for pair in outs.values():
+        for t in pair:
+            t.close()
+    x.close()
+    with pytest.raises(tt.TTError):
+        ctx.set_option(tt.TT_OPT_SKETCH_MIXED_PASSES, 2)
