@@ -319,10 +319,9 @@ typedef struct {
                             the sketch contractions in that split 16-bit
                             form (mixed form; the exact product and
                             everything else stay FP64).  With power > 0
-                            only the Gaussian sketch sweep uses it (its
-                            error just changes the random start); the
-                            subspace-iteration and projection sweeps are
-                            FP64 */
+                            the last sweep (the projection) is FP64 and
+                            the earlier ones use it, or only the Gaussian
+                            sketch sweep with TT_OPT_SKETCH_MIXED_PASSES 0 */
   uint64_t seed;         /* counter-based RNG key for the Gaussian sketch */
   int power;             /* SKETCH: subspace-iteration passes after the
                             first sweep, 0..8 */
@@ -335,9 +334,10 @@ typedef struct {
  * l: left Gaussian TT sketches of L x, then a right-to-left sweep of LQ
  * factorisations giving right-orthonormal cores; each of `power` further
  * sweeps runs the other way with the previous sweep's interface chains in
- * place of the sketch (a subspace-iteration step per bond), so y is
- * right-orthonormal after an even number of them and left-orthonormal after
- * an odd one.  Ranks <= l (bounded by n^k and n^(d-k)); exact whenever l
+ * place of the sketch (a subspace-iteration step per bond).  For an odd
+ * `power` the Gaussian sketches are drawn from the right and the first
+ * sweep runs left to right, so the last sweep always runs right to left
+ * and y is right-orthonormal.  Ranks <= l (bounded by n^k and n^(d-k)); exact whenever l
  * reaches the ranks of L x.  The projection of L x onto a truncation of
  * it is, at Sec. 4.1's truncation T, an approximation of T[L x]: its error
  * against the exact T[L x] falls with l and with the passes. */
