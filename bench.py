@@ -657,6 +657,8 @@ def main_trajectory(args):
 
     torch.cuda.init()
     d, n, length, nu, cap, eps, dt, ell = TRAJECTORIES[args.trajectory]
+    if args.dt:
+        dt = args.dt
     prec = PRECISIONS[args.precision]
     ctx = tt.Context(0)
     op = tt.Operator(ctx, d, n, length, nu)
@@ -822,6 +824,7 @@ def main():
                          "condition (each its own JSON line)")
     ap.add_argument("--trajectory", choices=sorted(TRAJECTORIES), default="d20")
     ap.add_argument("--ic", choices=["gaussian", "tridiag"], default="gaussian")
+    ap.add_argument("--dt", type=float, default=None, help="trajectory: time step (default: the workload's)")
     ap.add_argument("--log", default=None, help="trajectory: per-step JSON lines to this file")
     ap.add_argument("--growth", type=float, default=1e3,
                     help="trajectory: stop when ||phi|| exceeds this multiple of its initial value")
