@@ -147,7 +147,6 @@ namespace {
   }
 
 inline zc Z(double re, double im = 0.0) { return make_double2(re, im); }
-constexpr double U_ROUND = 1.1102230246251565e-16;  // 2^-53
 
 void require(bool c, int code, const char* msg) {
   if (!c) fail(code, msg);
@@ -1606,6 +1605,10 @@ int tt_round(tt_ctx* ctx, tt_tensor* x, double eps_rel, const int* rmax, tt_roun
   ABI_CATCH(ctx)
 }
 
+}  // extern "C"
+
+namespace {
+
 // <x, y> = sum conj(x) y by left-to-right contraction:
 // W_{k+1} = V(X_k)^H (W_k H(Y_k)), W_0 = 1 (App. A.1 arithmetic)
 zc dot_tensors(tt_ctx* ctx, const tt_tensor* x, const tt_tensor* y) {
@@ -1853,6 +1856,10 @@ void check_solve_opts(const tt_solve_opts& o) {
 void randomized_into(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y);
 double sketch_rel_error(tt_ctx* ctx, int npieces, const zc* coef, const tt_tensor* const* pieces,
                         const tt_tensor* y, uint64_t seed);
+
+}  // namespace
+
+extern "C" {
 
 int tt_step(tt_ctx* ctx, const tt_op* op, tt_tensor* f, double dt, const tt_step_opts* opts, tt_step_report* rep) {
   if (!ctx || !op || !f || !opts) return TT_EINVAL;
@@ -2219,6 +2226,10 @@ int tt_step_batch(int count, tt_ctx* const* ctxs, const tt_op* const* ops, tt_te
   return TT_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
 const tt_op* identity_op(tt_ctx* ctx, int d, int n) {
   std::lock_guard<std::mutex> lock(cache_mutex());
   tt_op*& op = identity_ops()[{ctx, d, n}];
@@ -2314,6 +2325,10 @@ double round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint
   return sketch_rel_error(ctx, 1, &one, &px, y, seed);
 }
 
+}  // namespace
+
+extern "C" {
+
 int tt_round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint64_t seed, tt_tensor* y,
                         double* rel_err) {
   if (!ctx || !x || !y || !widths) return TT_EINVAL;
@@ -2377,6 +2392,8 @@ int tt_zgemm_mixed(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, i
   ABI_CATCH(ctx)
 }
 
+}  // extern "C"
+
 // ------------------------------------------------------------ autotuner
 namespace {
 // the launch shapes a GEMM of this form may take (tile codes as in GemmChoice)
@@ -2394,6 +2411,9 @@ struct ForceGuard {
   ~ForceGuard() { ttf::gemm_force(nullptr); }
 };
 }  // namespace
+
+extern "C" {
+
 
 int tt_gemm_autotune(tt_ctx* ctx, int precision, int opA, int opB, int M, int N, int K, int batch, int* choice,
                      double* best_us) {
