@@ -96,6 +96,32 @@ def test_mlp_forward_and_gradients_match_the_oracle(ctx):
     net.close()
 
 
+@pytest.mark.parametrize("n_in,width,bsz", [(5, 24, 37), (3, 16, 1), (20, 33, 50)])
+def test_mlp_ragged_tiles_match_the_oracle(ctx, n_in, width, bsz):
+    """The matrix-core products at sizes that leave partial 16 x 16 tiles
+    and partial k steps (n_in, width and the batch not multiples of 16 or
+    4, a batch of one), against the oracle's FP64 network."""
+    import torch
+
+    from oracle import mlp as omlp
+
+    rng = np.random.default_rng(6 + n_in)
+    net = tt.MLP(ctx, n_in, width, 64)
+    net.set_params(omlp.init(n_in, width, 2) + 0.05 * rng.standard_normal(omlp.count(n_in, width)))
+    used = net.get_params(as_used=True).astype(np.float64)
+    x = rng.standard_normal((bsz, n_in)).astype(np.float32)
+    t = rng.standard_normal(bsz).astype(np.float32)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    y = net.forward(xd).cpu().numpy()
+    yref, _ = omlp.forward(used, x.astype(np.float64), n_in, width)
+    assert np.abs(y - yref).max() <= 1e-5 * (np.abs(yref).max() + 1)
+    loss, g = net.gradients(xd, td)
+    gref = omlp.gradients(used, x.astype(np.float64), t.astype(np.float64), n_in, width)
+    assert np.all(np.isfinite(g))
+    assert np.linalg.norm(g - gref) <= 1e-4 * np.linalg.norm(gref)
+    net.close()
+
+
 def test_mlp_training_is_deterministic_and_learns(ctx):
     import torch
 
