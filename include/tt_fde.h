@@ -595,8 +595,9 @@ int tt_round_randomized(tt_ctx* ctx, const tt_tensor* x, const int* widths, uint
 
 /* ---------------------------------------------------- rank predictor MLP */
 /* The learned form's per-bond rank predictor: n_in -> width -> width -> 1
- * with ReLU hidden layers, FP16 parameters with FP32 accumulation on the
- * device, FP32 master parameters and Adam (beta 0.9, 0.999, eps 1e-8) for
+ * with ReLU hidden layers, FP16 parameters widened to FP32 for products
+ * on the FP32 matrix cores with FP32 activations, deltas and sums, FP32
+ * master parameters and Adam (beta 0.9, 0.999, eps 1e-8) for
  * training on the loss L = (1 / 2B) sum_b (y_b - t_b)^2.  Parameter vector
  * (host float32, tt_mlp_param_count of them): W1 (width x n_in, row-major),
  * b1 (width), W2 (width x width), b2 (width), W3 (1 x width), b3 (1).
