@@ -1,4 +1,6 @@
 """Pins for oracle.fullgrid and oracle.closed_forms."""
+import itertools
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -275,6 +277,55 @@ def test_deterministic_state_pins_advective_term():
     assert e33 < 6e-3 and 3.4 < e17 / e33 < 4.6, (e17, e33)
     # a sign error in the advective term is far outside that tolerance
     assert _deterministic_error(33, sign=-1.0) > 20 * e33
+
+
+def _average_over_gaussian_states(mu, sig, b, dm, nu, t, n, length, q=8):
+    """E[exp(i a . u(t))] over initial states u(0) ~ N(mu, diag(sig^2)), by
+    tensor Gauss-Hermite quadrature (q nodes per mode) over u(0), each node
+    carried to time t by the Galerkin ODE.  The PDE is linear in phi, and
+    from a deterministic state its solution is exp(i a . u(t)); averaged
+    over the Gaussian it is the solution from the Gaussian characteristic
+    function (the Monte-Carlo check of the nonlinear part, with quadrature
+    in place of sampling, so without sampling noise)."""
+    x, w = np.polynomial.hermite_e.hermegauss(q)
+    w = w / w.sum()
+    out = np.zeros((n,) * len(mu), dtype=np.complex128)
+    for idx in itertools.product(range(q), repeat=len(mu)):
+        u = closed_forms.galerkin_trajectory(mu + sig * x[list(idx)], b, dm, nu, t)
+        out += np.prod(w[list(idx)]) * closed_forms.deterministic_phi(u, n, length)
+    return out
+
+
+def test_gaussian_state_is_the_average_of_galerkin_trajectories():
+    """From a Gaussian initial condition the full-grid RK4 solution converges
+    at second order in h to the quadrature average of exp(i a . u(t)) over
+    Galerkin trajectories (d = 3: the first mode triad, so B != 0; at d = 2
+    B vanishes).  A wrong sign, swapped first two indices, a doubled factor
+    or a missing advective term each miss by far more than the grid error."""
+    d, length, nu, tend, steps = 3, 4.0, 0.05, 0.3, 60
+    b, dm = galerkin.coefficient_B(d), galerkin.coefficient_D(d)
+    assert np.count_nonzero(b) > 0
+    mu, sig = np.array([0.9, -0.7, 0.6]), np.array([0.35, 0.25, 0.3])
+
+    def error(n, bgrid, ref):
+        prob = fullgrid.Problem(bgrid, dm, nu, n, length)
+        f = fullgrid.gaussian_ic(mu, sig, n, length)
+        for _ in range(steps):
+            f = fullgrid.rk4_step(f, tend / steps, prob.apply)
+        inner = np.abs(fd.grid(n, length)) <= length / 2  # away from the one-sided closures
+        return float(np.abs(f - ref)[np.ix_(inner, inner, inner)].max())
+
+    ref17 = _average_over_gaussian_states(mu, sig, b, dm, nu, tend, 17, length)
+    ref33 = _average_over_gaussian_states(mu, sig, b, dm, nu, tend, 33, length)
+    # the quadrature has converged where the grids are compared: 6 nodes per
+    # mode agree with 8 there far below the grid error
+    inner17 = np.abs(fd.grid(17, length)) <= length / 2
+    q6 = _average_over_gaussian_states(mu, sig, b, dm, nu, tend, 17, length, q=6)
+    assert np.abs(q6 - ref17)[np.ix_(inner17, inner17, inner17)].max() < 1e-6
+    e17, e33 = error(17, b, ref17), error(33, b, ref33)
+    assert e33 < 6e-3 and 3.4 < e17 / e33 < 4.6, (e17, e33)
+    for wrong in (-b, b.transpose(1, 0, 2), 2.0 * b, 0.0 * b):
+        assert error(33, wrong, ref33) > 20 * e33
 
 
 def _run(d, n, length, nu, steps, dt, seed):
