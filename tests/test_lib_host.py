@@ -28,6 +28,17 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(tt.exported_symbols())
 
 
+def test_binding_constants_match_the_header():
+    """Every TT_* constant of the Python binding has the value the header's
+    enums give it (the binding restates them for ctypes)."""
+    text = open(HEADER).read()
+    header = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(TT_[A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+    names = [k for k in vars(tt) if re.fullmatch(r"TT_[A-Z0-9_]+", k)]
+    assert len(names) >= 20
+    wrong = {k: (getattr(tt, k), header.get(k)) for k in names if header.get(k) != getattr(tt, k)}
+    assert not wrong, wrong
+
+
 @pytest.mark.parametrize("d", [4, 7, 20])
 def test_coefficients_match_oracle(d):
     op = tt.Operator(None, d, 8, 4.0, 0.05)
