@@ -4,6 +4,8 @@ builder agrees with the oracle."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -37,6 +39,48 @@ def test_binding_constants_match_the_header():
     assert len(names) >= 20
     wrong = {k: (getattr(tt, k), header.get(k)) for k in names if header.get(k) != getattr(tt, k)}
     assert not wrong, wrong
+
+
+# header struct -> the binding's ctypes restatement of it
+STRUCTS = {
+    "tt_allocator": tt.AllocatorStruct,
+    "tt_op_opts": tt.OpOpts,
+    "tt_cdf_opts": tt.CdfOpts,
+    "tt_apply_opts": tt.ApplyOpts,
+    "tt_round_report": tt.RoundReport,
+    "tt_step_opts": tt.StepOpts,
+    "tt_step_report": tt.StepReport,
+    "tt_solve_opts": tt.SolveOpts,
+    "tt_solve_report": tt.SolveReport,
+}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The header compiles as plain C11, and every struct the binding passes
+    through ctypes has the header's size and field offsets (printed by a
+    C program built against the header with gcc)."""
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tt_fde.h"', "int main(void) {"]
+    for cname, cls in STRUCTS.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src, exe = tmp_path / "layout.c", tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run([gcc, "-std=c11", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, cls in STRUCTS.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
 
 
 @pytest.mark.parametrize("d", [4, 7, 20])
