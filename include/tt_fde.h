@@ -28,6 +28,11 @@
  *   - Every call returns TT_OK (0) or a negative TT_E* code; no exception
  *     crosses the ABI.  tt_last_error() gives a text for the last failure on
  *     that context.  After TT_EHIP the context should be destroyed.
+ *   - A null context, tensor, operator or network handle (the destroy calls
+ *     included) or a null required output pointer gives TT_EINVAL before any
+ *     HIP call.  Exceptions: tt_last_error(NULL) returns "null context",
+ *     tt_ctx_stream(NULL) returns NULL, and tt_step_batch with count 0 is
+ *     an empty batch (TT_OK).
  *   - Tensors own cap-sized device buffers allocated at creation; no call in
  *     the stepping path allocates tensor storage.  Contexts own workspaces,
  *     grown on first use to the largest size a call needs.

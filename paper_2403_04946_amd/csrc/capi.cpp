@@ -2653,6 +2653,7 @@ int tt_mlp_create(tt_ctx* ctx, int n_in, int width, int max_batch, tt_mlp** out)
 }
 
 int tt_mlp_destroy(tt_mlp* m) {
+  if (!m) return TT_EINVAL;
   mlp_free(m);
   return TT_OK;
 }

@@ -41,6 +41,35 @@ def test_binding_constants_match_the_header():
     assert not wrong, wrong
 
 
+def _zero_argument(argtype):
+    if argtype in (ctypes.c_double, ctypes.c_float):
+        return 0.0
+    if argtype in (ctypes.c_int, ctypes.c_long, ctypes.c_longlong, ctypes.c_ulong, ctypes.c_ulonglong):
+        return 0
+    return None  # every pointer argument null
+
+
+def test_null_handles_are_rejected_before_any_hip_call():
+    """Every entry point that takes a handle returns TT_EINVAL when it and
+    every other pointer argument are null and every number is zero (host
+    checks only: no GPU is needed or touched)."""
+    h = tt.lib()
+    no_handle = {"tt_gemm_table_count", "tt_gemm_table_clear"}
+    special = {"tt_last_error", "tt_ctx_stream", "tt_step_batch"}
+    checked = 0
+    for name in tt.exported_symbols():
+        if name in no_handle or name in special:
+            continue
+        f = getattr(h, name)
+        assert f(*[_zero_argument(a) for a in f.argtypes]) == -1, name
+        checked += 1
+    assert checked >= 50
+    assert h.tt_last_error(None) == b"null context"
+    assert h.tt_ctx_stream(None) is None
+    f = h.tt_step_batch
+    assert f(*[_zero_argument(a) for a in f.argtypes]) == 0  # count 0: an empty batch
+
+
 # header struct -> the binding's ctypes restatement of it
 STRUCTS = {
     "tt_allocator": tt.AllocatorStruct,
