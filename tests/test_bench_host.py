@@ -75,3 +75,29 @@ def test_traffic_records_name_their_summaries():
         got = bench.traffic_per_launch(name)
         assert got is None or got == rec["bytes_per_launch"]
     assert bench.traffic_per_launch("no_such_kernel") is None
+
+
+def test_profile_commands_run_committed_files_only():
+    """Every command quoted in a profile summary (indented lines starting
+    with rocprofv3 or python3) runs scripts, modules and test files of this
+    repository that exist, and gives the summary's output directory under
+    gpurun_out/ rather than a path outside the repository."""
+    import glob
+    import re
+
+    pdir = os.path.join(ROOT, "profiles")
+    summaries = sorted(glob.glob(os.path.join(pdir, "*.md")))
+    assert summaries
+    for path in summaries:
+        commands = 0
+        with open(path) as fh:
+            for line in fh:
+                if not re.match(r"^    (rocprofv3|python3?) ", line):
+                    continue
+                commands += 1
+                for mod in re.findall(r"-m (paper_2403_04946_amd\.[a-z_0-9]+)", line):
+                    assert os.path.exists(os.path.join(ROOT, *mod.split(".")) + ".py"), (path, mod)
+                for script in re.findall(r"(?<![\w/.-])([\w/]+\.py)\b", line):
+                    assert os.path.exists(os.path.join(ROOT, script)), (path, script)
+                assert "/root/" not in line and "_work/" not in line, (path, line)
+        assert commands >= 1, f"{path} quotes no command that made it"
