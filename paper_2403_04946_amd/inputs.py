@@ -37,8 +37,9 @@ def random_tt(d, n, rank, seed, scale=None):
 
     ``rank`` is an int (all interior ranks) or a list of d+1 ranks.  Cores
     are numpy arrays of shape (r_{k-1}, n, r_k).  ``scale`` multiplies each
-    core (default 1/sqrt(n * r_k), which keeps entries of the full tensor of
-    order one).
+    core (default 1/sqrt(2 n r_{k-1}): each core then preserves the expected
+    squared norm of what it is contracted with, so the full tensor has
+    expected squared Frobenius norm one).
     """
     rng = np.random.default_rng(seed)
     if np.isscalar(rank):
